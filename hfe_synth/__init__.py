@@ -1,0 +1,143 @@
+"""Seeded synthetic iris templates for the encrypted 1:N matching workloads.
+
+This module produces raw template bits only: iris codes, masks, the cyclic
+shift offsets applied to query eyes, and planted near-copies of database rows
+(so that match decisions are exercised).  It holds none of the encryption,
+encoding or matching arithmetic; both the HIP library's callers and the CPU
+oracle take their inputs from here.
+
+Template model (Section 2.1 of the paper: code c and mask m are bit vectors of
+the same length):
+  * code bits   ~ i.i.d. Bernoulli(p_code)   (0.5 by default)
+  * mask bits   ~ i.i.d. Bernoulli(p_mask)   (0.9 by default)
+  * a planted query eye is a database row whose code bits are flipped with
+    probability `flip`, then cyclically rotated by -r* so that the query column
+    with shift r* realigns it with the database row.
+
+Every array is numpy uint8 holding 0/1, row-major (one template per row).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+BASE_SEED = 260117561
+
+
+def _rng(seed: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([int(seed), int(stream)]))
+
+
+def db_templates(seed: int, d1: int, d2: int, p_code: float = 0.5,
+                 p_mask: float = 0.9) -> Tuple[np.ndarray, np.ndarray]:
+    """Return (codes, masks), each uint8 of shape (d1, d2) with 0/1 entries."""
+    g = _rng(seed, 1)
+    codes = (g.random((d1, d2)) < p_code).astype(np.uint8)
+    masks = (g.random((d1, d2)) < p_mask).astype(np.uint8)
+    return codes, masks
+
+
+@dataclasses.dataclass(frozen=True)
+class Planted:
+    eye: int        # query eye index
+    db_row: int     # database row it is a noisy copy of
+    shift: int      # r*: the query column with this shift realigns the copy
+    flip: float     # probability of flipping each code bit
+
+
+def query_eyes(seed: int, n_eyes: int, d2: int, db_codes: np.ndarray,
+               db_masks: np.ndarray, planted: Sequence[Planted] = (),
+               p_code: float = 0.5, p_mask: float = 0.9
+               ) -> Tuple[np.ndarray, np.ndarray]:
+    """Return (codes, masks) of shape (n_eyes, d2) for the query eyes.
+
+    Eyes not listed in `planted` are fresh random templates.  A planted eye is
+    roll(noisy copy of db row, -shift) for code and mask alike (rotation moves
+    code and mask together, Section 2.1.2 of the paper).
+    """
+    g = _rng(seed, 2)
+    codes = (g.random((n_eyes, d2)) < p_code).astype(np.uint8)
+    masks = (g.random((n_eyes, d2)) < p_mask).astype(np.uint8)
+    for pl in planted:
+        gp = _rng(seed, 1000 + pl.eye)
+        flips = (gp.random(d2) < pl.flip).astype(np.uint8)
+        c = db_codes[pl.db_row] ^ flips
+        m = db_masks[pl.db_row].copy()
+        codes[pl.eye] = np.roll(c, -pl.shift)
+        masks[pl.eye] = np.roll(m, -pl.shift)
+    return codes, masks
+
+
+def default_shifts(n_shifts: int) -> np.ndarray:
+    """Shift offsets r for the query columns: {-n/2, ..., n/2-1}; [0] if n == 1."""
+    if n_shifts == 1:
+        return np.zeros(1, dtype=np.int32)
+    return np.arange(-(n_shifts // 2), n_shifts - n_shifts // 2, dtype=np.int32)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """Shapes of one synthetic workload (ring degrees, primes, template sizes)."""
+    name: str
+    log_n_db: int
+    log_n_q: int
+    n_q_primes: int        # query primes the database carries
+    level: int             # query primes used by the query (l_Q)
+    d1: int                # database codes
+    d2: int                # code length in bits
+    eyes: int              # query eyes
+    n_shifts: int          # cyclic shifts per eye (query columns = eyes * n_shifts)
+    planted: Tuple[Planted, ...] = ()
+    seed: int = BASE_SEED
+
+    @property
+    def d3(self) -> int:
+        return self.eyes * self.n_shifts
+
+
+def _planted(eyes: int, d1: int, n_shifts: int, count: int, seed: int) -> Tuple[Planted, ...]:
+    g = _rng(seed, 3)
+    out = []
+    sh = default_shifts(n_shifts)
+    eye_ids = g.choice(eyes, size=min(count, eyes), replace=False)
+    for e in sorted(int(x) for x in eye_ids):
+        out.append(Planted(eye=e, db_row=int(g.integers(0, d1)),
+                           shift=int(sh[int(g.integers(0, len(sh)))]), flip=0.1))
+    return tuple(out)
+
+
+# Tiny plain workload: N = 2^12 for both layers, one query prime plus the
+# special prime, 4 query codes against 256 database codes of 1024 bits; query 0
+# is a planted copy of database row 17.
+TINY = Workload("tiny_n4096_d1_256_d2_1024_q4", 12, 12, 1, 1, 256, 1024, 4, 1,
+                planted=(Planted(0, 17, 0, 0.1),), seed=BASE_SEED + 1)
+
+# Small multi-chunk workload: several secrets per layer (k = 2, k' = 2).
+TINY_MULTI = Workload("tinymulti_ndb128_nq512_d1_256_d2_1024_q4", 7, 9, 2, 2, 256, 1024, 2, 2,
+                      planted=(Planted(1, 200, -1, 0.1),), seed=BASE_SEED + 11)
+
+# One GPU's share at paper scale: N_DB = 2^14, N_Q = 2^13, three query primes
+# plus the special prime, 32 eyes x 16 shifts = 512 query columns against
+# 14,336 database codes of 12,800 bits.
+PAPER_SHARE = Workload("share_ndb16384_nq8192_L3p_d1_14336_d2_12800_q512", 14, 13, 3, 3,
+                       14336, 12800, 32, 16, seed=BASE_SEED + 2)
+
+WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, PAPER_SHARE)}
+
+
+def planted_for(w: Workload, count: int = 4) -> Tuple[Planted, ...]:
+    """Planted eyes for a workload: its own list if given, else `count` random ones."""
+    if w.planted:
+        return w.planted
+    return _planted(w.eyes, w.d1, w.n_shifts, count, w.seed)
+
+
+def make_inputs(w: Workload, n_planted: int = 4) -> Dict[str, np.ndarray]:
+    """All template bits of a workload: db codes/masks, eye codes/masks, shifts."""
+    dbc, dbm = db_templates(w.seed, w.d1, w.d2)
+    pl = planted_for(w, n_planted)
+    qc, qm = query_eyes(w.seed, w.eyes, w.d2, dbc, dbm, pl)
+    return dict(db_codes=dbc, db_masks=dbm, q_codes=qc, q_masks=qm,
+                shifts=default_shifts(w.n_shifts), planted=pl)

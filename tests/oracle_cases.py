@@ -1,0 +1,63 @@
+"""Oracle results for the test workloads, computed once per test session.
+
+Each case runs the CPU oracle end to end on a seeded synthetic workload:
+keys, database and query encryption, CCMM, decryption, plus the popcount truth.
+GPU parity tests compare the HIP library against these values.
+"""
+import dataclasses
+import functools
+from typing import Dict
+
+import numpy as np
+
+import hfe_synth as S
+from oracle import ckks as OC
+from oracle import iris as OI
+from oracle import params as OP
+
+KEY_SEED = 101
+DB_SEED = 202
+Q_SEED = 303
+
+
+@dataclasses.dataclass
+class Case:
+    w: S.Workload
+    P: OP.Params
+    keys: OC.Keys
+    inputs: Dict
+    m_db: np.ndarray
+    q_codes: np.ndarray       # shifted query columns (d3 x d2)
+    q_masks: np.ndarray
+    m_q: np.ndarray
+    D: Dict[int, np.ndarray]
+    XT: Dict[int, np.ndarray]
+    row0: int
+    rows: int
+    out: Dict[int, np.ndarray]
+    v: list
+    ip: np.ndarray
+    ip_true: np.ndarray
+    overlap: np.ndarray
+
+
+def params_for(w: S.Workload) -> OP.Params:
+    return OP.make_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
+
+
+@functools.lru_cache(maxsize=None)
+def case(name: str, row0: int = 0, rows: int = -1) -> Case:
+    w = S.WORKLOADS[name]
+    P = params_for(w)
+    inp = S.make_inputs(w)
+    keys = OC.keygen(P, KEY_SEED)
+    m_db = OI.ternary(inp["db_codes"], inp["db_masks"])
+    qc, qm = OI.shifted_queries(inp["q_codes"], inp["q_masks"], inp["shifts"])
+    m_q = OI.ternary(qc, qm)
+    D = OC.encrypt_db(keys, m_db, DB_SEED)
+    XT = OC.encrypt_query(keys, m_q, w.level, Q_SEED)
+    rows = w.d1 - row0 if rows < 0 else rows
+    out = OC.ccmm(P, D, XT, w.level, row0, rows)
+    v, ip = OC.decrypt(keys, out, w.level, row0, rows)
+    ip_true, ov = OI.truth(qc, qm, inp["db_codes"][row0:row0 + rows], inp["db_masks"][row0:row0 + rows])
+    return Case(w, P, keys, inp, m_db, qc, qm, m_q, D, XT, row0, rows, out, v, ip, ip_true, ov)

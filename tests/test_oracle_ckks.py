@@ -1,0 +1,145 @@
+"""Pins of the oracle's encryption and CCMM against invariants the paper fixes.
+
+* Dec(a, b) = a*sk + b recovers scale*m up to the sampled error (Section 2.2.2),
+  with the secret products taken by a route independent of the oracle's
+  Neg-matrix (numpy.polymul folded mod X^n + 1, and the conjugate-secret form
+  of M_DB S_Q).
+* The CCMM result decrypts to the masked inner products of Section 2.1.3,
+  computed by brute-force popcount, within 0.25 on every pair, and the
+  threshold decisions agree.
+* Special cases: unit-vector query columns return database columns; an
+  all-zero query decrypts to zero.
+"""
+import numpy as np
+import pytest
+
+import hfe_synth as S
+from oracle import ckks as OC
+from oracle import iris as OI
+from oracle import prng
+
+from oracle_cases import DB_SEED, KEY_SEED, Q_SEED, case, params_for
+
+
+def _fold(s, a):
+    n = len(s)
+    full = np.polymul(np.asarray(s, dtype=object)[::-1], np.asarray(a, dtype=object)[::-1])[::-1]
+    full = list(full) + [0] * (2 * n - len(full))
+    return np.array([int(full[t]) - int(full[t + n]) for t in range(n)], dtype=object)
+
+
+def _centered(x, q):
+    x = int(x) % q
+    return x - q if x > q // 2 else x
+
+
+@pytest.mark.parametrize("name", [S.TINY_MULTI.name])
+def test_query_encryption_decrypts_to_delta_m_plus_small_error(name):
+    c = case(name)
+    P = c.P
+    delta = P.delta(c.w.level)
+    for i in range(c.w.level):
+        qi = P.q[i]
+        for col in range(c.m_q.shape[0]):
+            b = c.XT[i][col, :P.d2]
+            a = c.XT[i][col, P.d2:]
+            for j in range(P.k):
+                sa = _fold(c.keys.s[j], a)
+                lo, hi = j * P.n_q, min((j + 1) * P.n_q, P.d2)
+                for t in range(lo, hi):
+                    e = _centered(int(b[t]) + int(sa[t - lo]) - delta * int(c.m_q[col, t]), qi)
+                    assert -19 <= e <= 19
+
+
+@pytest.mark.parametrize("name", [S.TINY_MULTI.name])
+def test_db_encryption_decrypts_to_p_times_plaintext(name):
+    c = case(name)
+    P = c.P
+    n = P.n_q
+    # T = M_DB S_Q through the conjugate secret s~(X) = s(X^-1): row i of T is the sum over
+    # chunks j of s~_j * (chunk j of row i).
+    T = np.zeros((c.m_db.shape[0], n), dtype=object)
+    for j in range(P.k):
+        s = c.keys.s[j]
+        st = np.array([s[0]] + [-s[n - k] for k in range(1, n)])
+        lo, hi = j * n, min((j + 1) * n, P.d2)
+        for i in range(c.m_db.shape[0]):
+            chunk = np.zeros(n, dtype=np.int64)
+            chunk[:hi - lo] = c.m_db[i, lo:hi]
+            T[i] += _fold(st, chunk)
+    plain = np.concatenate([c.m_db.astype(object), T], axis=1)
+    rng = np.random.default_rng(0)
+    cols = sorted(rng.choice(P.K, 12, replace=False).tolist()) + [0, P.d2 - 1, P.d2, P.K - 1]
+    for pid, prime in OC.prime_ids(P, len(P.q)):
+        D = c.D[pid]
+        for col in cols:
+            a = D[:P.n_db, col]
+            for j in range(P.k_db):
+                sa = _fold(c.keys.s_db[j], a)
+                for i in range(j * P.n_db, min((j + 1) * P.n_db, c.m_db.shape[0])):
+                    e = _centered(int(D[P.n_db + i, col]) + int(sa[i - j * P.n_db])
+                                  - P.p * int(plain[i, col]), prime)
+                    assert -19 <= e <= 19
+
+
+@pytest.mark.parametrize("name", [S.TINY.name, S.TINY_MULTI.name])
+def test_ccmm_decrypts_to_popcount_inner_products(name):
+    c = case(name)
+    assert np.array_equal(c.ip, c.ip_true)
+    err = max(abs(float(c.v[a][b]) - int(c.ip_true[a, b]))
+              for a in range(len(c.v)) for b in range(c.rows))
+    assert err <= 0.25
+    dec = OI.decide(c.ip, c.overlap)
+    assert np.array_equal(dec, OI.decide(c.ip_true, c.overlap))
+    for pl in S.planted_for(c.w):
+        col = pl.eye * c.w.n_shifts + list(S.default_shifts(c.w.n_shifts)).index(pl.shift)
+        assert dec[col, pl.db_row - c.row0]
+
+
+def test_ccmm_on_a_row_shard_matches_the_full_result():
+    full = case(S.TINY_MULTI.name)
+    part = case(S.TINY_MULTI.name, 100, 60)
+    n = full.P.n_db
+    for i in range(full.w.level):
+        assert np.array_equal(part.out[i][:, :n], full.out[i][:, :n])
+        assert np.array_equal(part.out[i][:, n:], full.out[i][:, n + 100:n + 160])
+    assert np.array_equal(part.ip, full.ip[:, 100:160])
+
+
+def test_unit_vector_and_zero_queries():
+    w = S.TINY_MULTI
+    P = params_for(w)
+    c = case(w.name)
+    d2 = P.d2
+    ks = [0, 5, 511, 512, 1023]
+    mq = np.zeros((len(ks) + 1, d2), dtype=np.int8)
+    for r, k in enumerate(ks):
+        mq[r, k] = 1 if r % 2 == 0 else -1
+    XT = OC.encrypt_query(c.keys, mq, w.level, Q_SEED + 1)
+    out = OC.ccmm(P, c.D, XT, w.level, 0, w.d1)
+    v, ip = OC.decrypt(c.keys, out, w.level, 0, w.d1)
+    for r, k in enumerate(ks):
+        sign = 1 if r % 2 == 0 else -1
+        assert np.array_equal(ip[r], sign * c.m_db[:, k].astype(np.int64))
+    assert np.all(ip[len(ks)] == 0)
+
+
+def test_ccmm_invariant_before_rescale():
+    """B_pre + S_DB A_pre = p Delta M_DB M_Q + small (mod Q p), on the big integers."""
+    c = case(S.TINY_MULTI.name)
+    P = c.P
+    lvl = c.w.level
+    C = OC.ccmm_pre_rescale(P, c.D, c.XT, lvl, 0, c.w.d1)
+    ids = OC.prime_ids(P, lvl)
+    moduli = [m for _, m in ids]
+    Qp = P.Q(lvl) * P.p
+    delta = P.delta(lvl)
+    big = {(r, col): OC.crt([int(C[pid][r, col]) for pid, _ in ids], moduli)
+           for r in range(P.n_db + c.w.d1) for col in range(c.m_q.shape[0])}
+    S_rows = OC.s_db_rows(c.keys, range(c.w.d1))
+    for col in range(c.m_q.shape[0]):
+        a_pre = [big[(v, col)] for v in range(P.n_db)]
+        for i in range(0, c.w.d1, 17):
+            y = big[(P.n_db + i, col)] + sum(int(S_rows[i, v]) * a_pre[v] for v in range(P.n_db))
+            noise = OC.centered(y - P.p * delta * int(c.ip_true[col, i]), Qp)
+            assert abs(noise) < P.p * delta // 8
