@@ -1,0 +1,173 @@
+/*
+ * hfe.h -- C ABI of the MI355X encrypted-CCMM library for private 1:N iris matching.
+ *
+ * The library implements the hot path of the paper "Private Iris Recognition with
+ * High-Performance FHE" (arXiv 2601.17561): the RGSW-style encrypted matrix product
+ * (CCMM, Section 2.3; database representation, Section 6.3) between an encrypted database
+ * of masked ternary iris codes and a batch of encrypted query codes, with the key
+ * generation, encryption, rescale (Section 2.2.4), decryption (Section 2.2.2) and
+ * plaintext decision (equation (2), Section 2.1.3) around it.
+ *
+ * Conventions
+ *  - Every function returns hfe_status (0 = HFE_OK, negative = error) and never throws or
+ *    aborts.  After an error, hfe_last_error() returns a message (per thread).
+ *  - Array arguments are DEVICE pointers (GPU memory of the current HIP device) unless the
+ *    comment says "host".  Input arrays are borrowed: they must stay valid until the work
+ *    enqueued on `stream` has passed the call.  Outputs are written by work enqueued on
+ *    `stream`; synchronise the stream before reading them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All GPU work of a
+ *    call is enqueued on that stream; validation errors return before anything is enqueued.
+ *  - Handles (hfe_keys, hfe_db, hfe_qct, hfe_rct) are owned by the library and released with
+ *    hfe_free().  A database or query handle refers to its keys: keep the keys alive while
+ *    they are used.  Keys and databases are immutable once built and may be shared across
+ *    threads; query and result handles are single-owner.
+ *  - Device memory comes from the allocator installed with hfe_set_allocator(), else from
+ *    hipMalloc / hipFree.
+ *
+ * Layouts (row-major unless stated; "residue" = uint64 in [0, prime))
+ *  - Ternary matrices: int8 in {-1, 0, 1}.  M_DB: d1 x d2, one database code per row.
+ *    M_Q: d3 x d2, one query vector per row (the paper's M_Q is its transpose).
+ *  - Primes: the database carries query primes q_0..q_{L-1} and one special prime p.
+ *    A query of level l uses q_0..q_{l-1}; its scaling factor is
+ *    Delta_l = 2^(floor(log2(q_0 ... q_{l-1})) - gap_bits).
+ */
+#ifndef HFE_H
+#define HFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hfe_status;
+enum {
+  HFE_OK = 0,
+  HFE_EINVAL = -1,     /* invalid argument or parameter (e.g. a prime != 1 mod 2N)      */
+  HFE_ESHAPE = -2,     /* inconsistent sizes or row ranges                               */
+  HFE_ELEVEL = -3,     /* level above the primes the database carries                    */
+  HFE_ENOMEM = -4,     /* device allocation failed                                       */
+  HFE_EDEVICE = -5,    /* HIP runtime error                                              */
+  HFE_EBUSY = -6,      /* resource temporarily unavailable                               */
+  HFE_EOVERFLOW = -7,  /* a bound needed for exact arithmetic does not hold              */
+  HFE_EINTERNAL = -8
+};
+
+/* Contraction forms of hfe_ccmm (Section 6.3: the products mod Q reduced to small-integer
+ * matrix products).  PLAIN_U64: 36-bit residues multiplied on the vector ALU with 128-bit
+ * accumulation.  I8_MFMA: each centered residue split into 5 signed 8-bit digits, 25
+ * digit-pair int8 MFMA products with int32 accumulation, exact recombination mod prime. */
+typedef enum { HFE_FORM_PLAIN_U64 = 1, HFE_FORM_I8_MFMA = 2 } hfe_form;
+
+#define HFE_MAX_QPRIMES 8
+
+typedef struct {
+  uint32_t log_n_db;              /* N_DB = 2^log_n_db, database ring degree, 1..16      */
+  uint32_t log_n_q;               /* N_Q = 2^log_n_q, query ring degree, 1..16           */
+  uint32_t n_q_primes;            /* L, query primes carried by the database, 1..8       */
+  uint64_t q[HFE_MAX_QPRIMES];    /* q_0..q_{L-1}: distinct primes < 2^36, = 1 mod 2N    */
+  uint64_t p;                     /* special prime < 2^36, = 1 mod 2N, distinct from q_i */
+  uint32_t gap_bits;              /* Delta_l = 2^(floor(log2 Q_l) - gap_bits)            */
+  uint32_t d2;                    /* code length (columns of M_DB)                       */
+  uint32_t max_db_rows;           /* largest d1 the keys cover: ceil(max/N_DB) secrets   */
+  uint32_t t_num, t_den;          /* match threshold t = t_num / t_den, 0 < t < 1/2      */
+} hfe_params;
+
+typedef struct hfe_keys hfe_keys;  /* secrets and per-prime NTT tables                   */
+typedef struct hfe_db hfe_db;      /* encrypted database, resident on the device         */
+typedef struct hfe_qct hfe_qct;    /* encrypted query batch                              */
+typedef struct hfe_rct hfe_rct;    /* encrypted CCMM result                              */
+
+/* Device allocator hook: alloc(bytes, stream, ctx) returns device memory usable in stream
+ * order on `stream` (NULL on failure); dealloc(ptr, stream, ctx) releases it in stream order.
+ * Passing NULL functions restores hipMalloc / hipFree. */
+typedef void* (*hfe_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*hfe_dealloc_fn)(void* ptr, void* stream, void* ctx);
+hfe_status hfe_set_allocator(hfe_alloc_fn alloc, hfe_dealloc_fn dealloc, void* ctx);
+
+/* Fill *out (host) with default parameters: the largest primes < 2^36 that are = 1 mod 2^17
+ * (the first is p, the next n_q_primes are q_0..), gap 20, threshold 3/8. */
+hfe_status hfe_default_params(uint32_t log_n_db, uint32_t log_n_q, uint32_t n_q_primes,
+                              uint32_t d2, uint32_t max_db_rows, hfe_params* out);
+
+/* Key generation (Section 2.2.2, single key holder): ternary query secrets s_j in R_{N_Q},
+ * j < ceil(d2/N_Q), and database secrets s'_j in R_{N_DB}, j < ceil(max_db_rows/N_DB),
+ * drawn from the Philox4x64-10 streams keyed by `seed`.  Synchronous. */
+hfe_status hfe_keygen(const hfe_params* params, uint64_t seed, hfe_keys** out);
+
+/* Masked ternary encoding (Section 2.1.3) with cyclic shifts (Section 2.1.2):
+ * out[(e * n_shifts + s) * d2 + t] = m' - 2 (c' AND m') with c' = code row e and m' = mask
+ * row e, both rolled by shifts[s] (rolled[t] = x[(t - shifts[s]) mod d2]).
+ * codes, masks: n x d2 uint8 in {0,1}; shifts: host array of n_shifts int32;
+ * out: (n * n_shifts) x d2 int8. */
+hfe_status hfe_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int32_t d2,
+                      const int32_t* shifts, int32_t n_shifts, int8_t* out, void* stream);
+
+/* Database encryption in the RGSW/MSRLWE form of Sections 2.3 and 6.3: T = M_DB S_Q, and per
+ * prime of Q_L p: A = [A1 | A2] uniform (N_DB x (d2 + N_Q)), B = -S_DB A + p [M_DB | T] + E.
+ * m_db: d1 x d2 ternary (device).  forms: bitmask of hfe_form the database is prepared for.
+ * The result stays resident on the device. */
+hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, uint64_t seed,
+                          uint32_t forms, void* stream, hfe_db** out);
+
+/* Query encryption in MSRLWE form (Section 2.3): per column c and query prime,
+ * a_c uniform in R_{N_Q}, b_c = -S_Q a_c + Delta_level m_c + e_c (chunks of N_Q rows share
+ * a_c, each under its own secret).  m_q: d3 x d2 ternary (device); 1 <= level <= L. */
+hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint32_t level,
+                       uint64_t seed, void* stream, hfe_qct** out);
+
+/* The encrypted matrix product (Section 2.3, the four plaintext products written as one
+ * product per prime; Section 6.3): lift the query residues from Q to Q p (centered),
+ * C = D X mod prime for the level's primes and p, then rescale by p
+ * (Section 2.2.4, RS_p(x) = floor(x/p + 1/2) mod Q).  The database rows used are the
+ * N_DB A-part rows and the database codes [row0, row0 + rows).  form: hfe_form. */
+hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
+                    void* stream, hfe_rct** out);
+
+/* Decryption and coefficient decoding (Sections 2.2.1, 2.2.2): for column c and code r,
+ * y = B_out + (s'_j * A_out)[r mod N_DB] mod Q (CRT over the level's primes, centered),
+ * v[c * rows + r] = y / Delta (double) and ip[c * rows + r] = floor(y / Delta + 1/2).
+ * v may be NULL.  v, ip: d3 x rows (device). */
+hfe_status hfe_decrypt(const hfe_keys* keys, const hfe_rct* r, double* v, int32_t* ip,
+                       void* stream);
+
+/* Plaintext decision (equation (2)): score = ip / popcount(m_q AND m_db) > 1 - 2t, decided in
+ * integers as ip * t_den > (t_den - 2 t_num) * overlap (no match without overlap).
+ * ip: d3 x rows int32 (d3 = n_eyes * n_shifts, eye-major as produced by hfe_encode);
+ * q_masks: n_eyes x d2 uint8 (unshifted); db_masks: rows x d2 uint8 (the rows ip covers);
+ * shifts: host, n_shifts int32.  Outputs: decision d3 x rows uint8 (may be NULL),
+ * eye_match n_eyes uint8 = OR over the eye's shifts and all rows. */
+hfe_status hfe_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eyes,
+                     const int32_t* shifts, int32_t n_shifts, const uint8_t* db_masks,
+                     int64_t rows, int32_t d2, uint32_t t_num, uint32_t t_den,
+                     uint8_t* decision, uint8_t* eye_match, void* stream);
+
+/* Export residues to host memory for parity checks (synchronous; waits for the handle's
+ * producing work).  `which` selects an array; the canonical orders are
+ *   keys  0: query secrets    k  x N_Q  (int64 two's complement in uint64)
+ *         1: database secrets k' x N_DB
+ *   db    0: D per prime      [prime (q_0..q_{L-1}, p)][row < N_DB + d1][col < d2 + N_Q]
+ *   qct   0: query            [prime < level][column < d3][b_c (d2) | a_c (N_Q)]
+ *   rct   0: result           [prime < level][column < d3][A_out (N_DB) | B_out (rows)]
+ * If dst is NULL, *count receives the number of elements; otherwise n must equal it. */
+hfe_status hfe_export(const void* handle, int32_t which, uint64_t* dst, size_t n, size_t* count);
+
+/* Shape queries of a handle (host): dims[0..3] = {level or L, d3 or d1, rows, K}. */
+hfe_status hfe_shape(const void* handle, int64_t* dims);
+
+/* Release any handle (NULL-safe).  Waits for work that uses it on its stream. */
+void hfe_free(void* handle);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* hfe_last_error(void);
+
+/* The library's discrete-Gaussian table T[j] = floor(2^64 P(|e| <= j)), j < 19, computed on
+ * the host in quad precision (sigma = 3.2, tail 19).  dst: host, 19 entries. */
+hfe_status hfe_cdt_table(uint64_t* dst);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFE_H */

@@ -1,0 +1,300 @@
+"""Python binding of libhfe, the MI355X encrypted-CCMM library (argument marshalling only).
+
+Every function below has the name of the C entry point it calls (include/hfe.h) and does
+nothing but convert arguments: torch tensors on the GPU become device pointers, the current
+torch stream becomes the hipStream_t, handles are wrapped so that they are released with
+hfe_free, and a negative status raises HfeError with hfe_last_error().  All arithmetic of
+the encrypted matching runs in the HIP kernels of the library.
+
+PyTorch provides device memory and streams: on import the binding installs torch's caching
+allocator as the library's allocator (hfe_set_allocator), so the library's buffers are
+stream-ordered blocks of torch's pool.
+
+The library must have been built (paper_2601_17561_amd/build.py); importing this package
+without it raises ImportError.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfe.so")
+
+HFE_FORM_PLAIN_U64 = 1
+HFE_FORM_I8_MFMA = 2
+HFE_MAX_QPRIMES = 8
+
+STATUS_NAMES = {0: "HFE_OK", -1: "HFE_EINVAL", -2: "HFE_ESHAPE", -3: "HFE_ELEVEL", -4: "HFE_ENOMEM",
+                -5: "HFE_EDEVICE", -6: "HFE_EBUSY", -7: "HFE_EOVERFLOW", -8: "HFE_EINTERNAL"}
+
+EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode", "hfe_encrypt_db",
+            "hfe_encrypt", "hfe_ccmm", "hfe_decrypt", "hfe_match", "hfe_export", "hfe_shape", "hfe_free",
+            "hfe_last_error", "hfe_cdt_table")
+
+
+class HfeError(RuntimeError):
+    def __init__(self, status: int, fn: str, msg: str):
+        super().__init__(f"{fn}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hfe_params(ctypes.Structure):
+    _fields_ = [("log_n_db", ctypes.c_uint32), ("log_n_q", ctypes.c_uint32), ("n_q_primes", ctypes.c_uint32),
+                ("q", ctypes.c_uint64 * HFE_MAX_QPRIMES), ("p", ctypes.c_uint64), ("gap_bits", ctypes.c_uint32),
+                ("d2", ctypes.c_uint32), ("max_db_rows", ctypes.c_uint32), ("t_num", ctypes.c_uint32),
+                ("t_den", ctypes.c_uint32)]
+
+    def primes(self):
+        return [int(self.q[i]) for i in range(self.n_q_primes)], int(self.p)
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2601_17561_amd/build.py` "
+                      "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i32, _i64, _u32, _u64, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                    ctypes.c_uint64, ctypes.c_size_t)
+_ALLOC_FN = ctypes.CFUNCTYPE(_vp, _sz, _vp, _vp)
+_DEALLOC_FN = ctypes.CFUNCTYPE(None, _vp, _vp, _vp)
+
+_SIGS = {
+    "hfe_set_allocator": [_ALLOC_FN, _DEALLOC_FN, _vp],
+    "hfe_default_params": [_u32, _u32, _u32, _u32, _u32, ctypes.POINTER(hfe_params)],
+    "hfe_keygen": [ctypes.POINTER(hfe_params), _u64, ctypes.POINTER(_vp)],
+    "hfe_encode": [_vp, _vp, _i64, _i32, ctypes.POINTER(_i32), _i32, _vp, _vp],
+    "hfe_encrypt_db": [_vp, _vp, _i64, _u64, _u32, _vp, ctypes.POINTER(_vp)],
+    "hfe_encrypt": [_vp, _vp, _i64, _u32, _u64, _vp, ctypes.POINTER(_vp)],
+    "hfe_ccmm": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_vp)],
+    "hfe_decrypt": [_vp, _vp, _vp, _vp, _vp],
+    "hfe_match": [_vp, _vp, _i64, ctypes.POINTER(_i32), _i32, _vp, _i64, _i32, _u32, _u32, _vp, _vp, _vp],
+    "hfe_export": [_vp, _i32, _vp, _sz, ctypes.POINTER(_sz)],
+    "hfe_shape": [_vp, ctypes.POINTER(_i64)],
+    "hfe_cdt_table": [_vp],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _i32
+_lib.hfe_free.argtypes = [_vp]
+_lib.hfe_free.restype = None
+_lib.hfe_last_error.argtypes = []
+_lib.hfe_last_error.restype = ctypes.c_char_p
+
+
+def hfe_last_error() -> str:
+    return _lib.hfe_last_error().decode()
+
+
+def _check(status: int, fn: str) -> None:
+    if status != 0:
+        raise HfeError(status, fn, hfe_last_error())
+
+
+# ------------------------------------------------------------------ torch plumbing
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, dtype) -> int:
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch tensor on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+_allocator_refs = []
+
+
+def hfe_set_allocator(alloc=None, dealloc=None, ctx=None) -> None:
+    """Install Python callables alloc(bytes, stream) -> int and dealloc(ptr, stream)."""
+    if alloc is None:
+        _check(_lib.hfe_set_allocator(_ALLOC_FN(), _DEALLOC_FN(), None), "hfe_set_allocator")
+        _allocator_refs.clear()
+        return
+
+    def _a(nbytes, stream, _ctx):
+        try:
+            return alloc(int(nbytes), int(stream or 0))
+        except Exception:  # allocation failure is reported as NULL -> HFE_ENOMEM
+            return None
+
+    def _d(ptr, stream, _ctx):
+        try:
+            dealloc(int(ptr), int(stream or 0))
+        except Exception:
+            pass
+
+    a, d = _ALLOC_FN(_a), _DEALLOC_FN(_d)
+    _allocator_refs[:] = [a, d]
+    _check(_lib.hfe_set_allocator(a, d, None), "hfe_set_allocator")
+
+
+def use_torch_allocator() -> None:
+    """Route the library's device memory through torch's caching allocator."""
+    torch = _torch()
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+
+    def dealloc(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hfe_set_allocator(alloc, dealloc)
+
+
+# ------------------------------------------------------------------ handles
+
+class Handle:
+    """Owner of a library handle; released with hfe_free when collected or on free()."""
+
+    def __init__(self, ptr: int, parents=()):
+        self.ptr = ptr
+        self._parents = tuple(parents)
+
+    def free(self) -> None:
+        if self.ptr:
+            _lib.hfe_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    @property
+    def as_parameter(self):
+        return self.ptr
+
+
+def hfe_shape(h: Handle):
+    dims = (_i64 * 4)()
+    _check(_lib.hfe_shape(h.ptr, dims), "hfe_shape")
+    return tuple(int(x) for x in dims)
+
+
+def hfe_free(h: Handle) -> None:
+    h.free()
+
+
+# ------------------------------------------------------------------ entry points
+
+def hfe_default_params(log_n_db: int, log_n_q: int, n_q_primes: int, d2: int, max_db_rows: int) -> hfe_params:
+    P = hfe_params()
+    _check(_lib.hfe_default_params(log_n_db, log_n_q, n_q_primes, d2, max_db_rows, ctypes.byref(P)),
+           "hfe_default_params")
+    return P
+
+
+def hfe_keygen(params: hfe_params, seed: int) -> Handle:
+    out = _vp()
+    _check(_lib.hfe_keygen(ctypes.byref(params), seed, ctypes.byref(out)), "hfe_keygen")
+    return Handle(out.value)
+
+
+def hfe_encode(codes, masks, shifts: Sequence[int], out=None, stream=None):
+    """codes, masks: uint8 (n x d2) GPU tensors; returns int8 ((n * len(shifts)) x d2)."""
+    torch = _torch()
+    n, d2 = codes.shape
+    sh = (_i32 * len(shifts))(*[int(s) for s in shifts])
+    if out is None:
+        out = torch.empty((n * len(shifts), d2), dtype=torch.int8, device=codes.device)
+    _check(_lib.hfe_encode(_dev_ptr(codes, torch.uint8), _dev_ptr(masks, torch.uint8), n, d2, sh, len(shifts),
+                           _dev_ptr(out, torch.int8), _stream(stream)), "hfe_encode")
+    return out
+
+
+def hfe_encrypt_db(keys: Handle, m_db, seed: int, forms: int = HFE_FORM_PLAIN_U64 | HFE_FORM_I8_MFMA,
+                   stream=None) -> Handle:
+    torch = _torch()
+    d1 = m_db.shape[0]
+    out = _vp()
+    _check(_lib.hfe_encrypt_db(keys.ptr, _dev_ptr(m_db, torch.int8), d1, seed, forms, _stream(stream),
+                               ctypes.byref(out)), "hfe_encrypt_db")
+    return Handle(out.value, (keys,))
+
+
+def hfe_encrypt(keys: Handle, m_q, level: int, seed: int, stream=None) -> Handle:
+    torch = _torch()
+    out = _vp()
+    _check(_lib.hfe_encrypt(keys.ptr, _dev_ptr(m_q, torch.int8), m_q.shape[0], level, seed, _stream(stream),
+                            ctypes.byref(out)), "hfe_encrypt")
+    return Handle(out.value, (keys,))
+
+
+def hfe_ccmm(db: Handle, q: Handle, row0: int, rows: int, form: int, stream=None) -> Handle:
+    out = _vp()
+    _check(_lib.hfe_ccmm(db.ptr, q.ptr, row0, rows, form, _stream(stream), ctypes.byref(out)), "hfe_ccmm")
+    return Handle(out.value, (db, q))
+
+
+def hfe_decrypt(keys: Handle, r: Handle, v=None, ip=None, stream=None):
+    """Returns (v float64 or None, ip int32), both (d3 x rows) GPU tensors."""
+    torch = _torch()
+    _, d3, rows, _ = hfe_shape(r)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if ip is None:
+        ip = torch.empty((d3, rows), dtype=torch.int32, device=dev)
+    vp = None if v is False else (v if v is not None else torch.empty((d3, rows), dtype=torch.float64, device=dev))
+    _check(_lib.hfe_decrypt(keys.ptr, r.ptr, _dev_ptr(vp, torch.float64) if vp is not None else None,
+                            _dev_ptr(ip, torch.int32), _stream(stream)), "hfe_decrypt")
+    return vp, ip
+
+
+def hfe_match(ip, q_masks, shifts: Sequence[int], db_masks, t_num: int = 3, t_den: int = 8,
+              decision=None, eye_match=None, want_decision: bool = True, stream=None):
+    """Returns (decision uint8 (d3 x rows) or None, eye_match uint8 (n_eyes,))."""
+    torch = _torch()
+    n_eyes, d2 = q_masks.shape
+    rows = db_masks.shape[0]
+    sh = (_i32 * len(shifts))(*[int(s) for s in shifts])
+    if want_decision and decision is None:
+        decision = torch.empty((n_eyes * len(shifts), rows), dtype=torch.uint8, device=ip.device)
+    if eye_match is None:
+        eye_match = torch.empty((n_eyes,), dtype=torch.uint8, device=ip.device)
+    _check(_lib.hfe_match(_dev_ptr(ip, torch.int32), _dev_ptr(q_masks, torch.uint8), n_eyes, sh, len(shifts),
+                          _dev_ptr(db_masks, torch.uint8), rows, d2, t_num, t_den,
+                          _dev_ptr(decision, torch.uint8) if decision is not None else None,
+                          _dev_ptr(eye_match, torch.uint8), _stream(stream)), "hfe_match")
+    return decision, eye_match
+
+
+def hfe_export(h: Handle, which: int = 0) -> np.ndarray:
+    n = _sz()
+    _check(_lib.hfe_export(h.ptr, which, None, 0, ctypes.byref(n)), "hfe_export")
+    out = np.empty(n.value, dtype=np.uint64)
+    _check(_lib.hfe_export(h.ptr, which, out.ctypes.data, n.value, None), "hfe_export")
+    return out
+
+
+def hfe_cdt_table() -> list:
+    out = (_u64 * 19)()
+    _check(_lib.hfe_cdt_table(out), "hfe_cdt_table")
+    return [int(x) for x in out]
+
+
+try:  # torch's caching allocator serves the library's device memory when a GPU is present
+    if _torch().cuda.is_available():
+        use_torch_allocator()
+except Exception:  # pragma: no cover - torch without GPU support
+    pass

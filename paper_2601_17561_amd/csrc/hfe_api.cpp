@@ -1,0 +1,769 @@
+// The extern "C" API of the encrypted-CCMM library: validation, handle management, device
+// memory and the enqueueing of the kernels for key generation, encryption, the CCMM,
+// decryption and the match decision.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hfe_internal.h"
+
+namespace hfe {
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_err;
+}
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+hfe_status fail(hfe_status code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+static hfe_status hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();
+  return fail(e == hipErrorOutOfMemory ? HFE_ENOMEM : HFE_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HFE_LAUNCH(expr)                              \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return hip_fail(_e, #expr); \
+  } while (0)
+
+// ------------------------------------------------------------------ allocator
+namespace {
+std::mutex g_alloc_mu;
+hfe_alloc_fn g_alloc = nullptr;
+hfe_dealloc_fn g_dealloc = nullptr;
+void* g_alloc_ctx = nullptr;
+}  // namespace
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 256;
+  hfe_alloc_fn a;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> l(g_alloc_mu);
+    a = g_alloc;
+    ctx = g_alloc_ctx;
+  }
+  if (a) return a(bytes, (void*)s, ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(void* p, hipStream_t s) {
+  if (!p) return;
+  hfe_dealloc_fn d;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> l(g_alloc_mu);
+    d = g_dealloc;
+    ctx = g_alloc_ctx;
+  }
+  if (d) {
+    d(p, (void*)s, ctx);
+    return;
+  }
+  (void)hipFree(p);
+}
+
+hfe_status DevBuf::alloc(size_t n, hipStream_t s) {
+  reset();
+  ptr = dev_alloc(n, s);
+  if (!ptr) return fail(HFE_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed");
+  bytes = n;
+  stream = s;
+  return HFE_OK;
+}
+
+void DevBuf::reset() {
+  if (ptr) dev_free(ptr, stream);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+// ------------------------------------------------------------------ small big-integer helpers
+namespace {
+using u128 = unsigned __int128;
+
+struct Big {  // little-endian 64-bit words
+  std::vector<uint64_t> w;
+  explicit Big(uint64_t v = 0) : w{v} {}
+  void mul(uint64_t m) {
+    uint64_t carry = 0;
+    for (auto& x : w) {
+      u128 t = (u128)x * m + carry;
+      x = (uint64_t)t;
+      carry = (uint64_t)(t >> 64);
+    }
+    if (carry) w.push_back(carry);
+  }
+  int bit_length() const {
+    for (int i = (int)w.size() - 1; i >= 0; --i)
+      if (w[i]) return i * 64 + 64 - __builtin_clzll(w[i]);
+    return 0;
+  }
+};
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+
+// floor(log2(q_0 ... q_{l-1})) - gap
+int delta_log(const hfe_keys* k, int level) {
+  Big Q(1);
+  for (int i = 0; i < level; ++i) Q.mul(k->primes[i]);
+  return Q.bit_length() - 1 - (int)k->P.gap_bits;
+}
+
+void garner_consts(const hfe_keys* k, int level, uint64_t garner[HFE_MAX_QPRIMES][HFE_MAX_QPRIMES],
+                   uint64_t* half_digits) {
+  for (int i = 0; i < level; ++i) {
+    const uint64_t qi = k->primes[i];
+    uint64_t prod = 1 % qi;
+    for (int j = 0; j < i; ++j) {
+      garner[i][j] = prod;  // q_0..q_{j-1} mod q_i
+      prod = mulmod(prod, k->primes[j] % qi, qi);
+    }
+    garner[i][i] = inv_mod(prod, qi);
+  }
+  // mixed-radix digits of (Q - 1) / 2: halve (q_0 - 1, ..., q_{l-1} - 1) from the top digit
+  uint64_t carry = 0;
+  for (int i = level - 1; i >= 0; --i) {
+    const u128 cur = (u128)(k->primes[i] - 1) + (u128)carry * k->primes[i];
+    half_digits[i] = (uint64_t)(cur / 2);
+    carry = (uint64_t)(cur % 2);
+  }
+}
+}  // namespace
+
+// ------------------------------------------------------------------ validation
+static hfe_status check_params(const hfe_params* P) {
+  if (!P) return fail(HFE_EINVAL, "params is NULL");
+  if (P->log_n_db < 1 || P->log_n_db > (uint32_t)kMaxLogN || P->log_n_q < 1 ||
+      P->log_n_q > (uint32_t)kMaxLogN)
+    return fail(HFE_EINVAL, "ring degrees must be 2^1 .. 2^14");
+  if (P->n_q_primes < 1 || P->n_q_primes > HFE_MAX_QPRIMES)
+    return fail(HFE_EINVAL, "n_q_primes must be 1..8");
+  if (P->d2 < 1 || P->d2 > (1u << 20)) return fail(HFE_EINVAL, "d2 must be 1 .. 2^20");
+  if (P->max_db_rows < 1 || P->max_db_rows > (1u << 24)) return fail(HFE_EINVAL, "max_db_rows out of range");
+  if (P->t_den == 0 || 2ull * P->t_num >= P->t_den) return fail(HFE_EINVAL, "threshold must satisfy 0 <= t < 1/2");
+  const int logmax = (int)std::max(P->log_n_db, P->log_n_q);
+  std::vector<uint64_t> all(P->q, P->q + P->n_q_primes);
+  all.push_back(P->p);
+  for (size_t i = 0; i < all.size(); ++i) {
+    const uint64_t q = all[i];
+    if (q < (1ull << 20) || q >= (1ull << 36)) return fail(HFE_EINVAL, "primes must lie in [2^20, 2^36)");
+    if (!is_prime_u64(q)) return fail(HFE_EINVAL, "modulus " + std::to_string(q) + " is not prime");
+    if ((q - 1) % (2ull << logmax) != 0)
+      return fail(HFE_EINVAL, "prime " + std::to_string(q) + " is not 1 mod 2N");
+    for (size_t j = 0; j < i; ++j)
+      if (all[j] == q) return fail(HFE_EINVAL, "primes must be distinct");
+  }
+  // Delta >= 1 for level 1 and headroom for the largest inner product: d2 * Delta < Q / 2^(gap-1)
+  Big q0(P->q[0]);
+  if ((int)P->gap_bits < 2 || q0.bit_length() - 1 <= (int)P->gap_bits)
+    return fail(HFE_EINVAL, "gap_bits must be >= 2 and below log2 q_0");
+  if ((uint64_t)P->d2 >= (1ull << (P->gap_bits - 1)))
+    return fail(HFE_EOVERFLOW, "d2 * Delta would not fit below Q/2: raise gap_bits");
+  return HFE_OK;
+}
+
+template <class T>
+static T* as_handle(const void* h, uint32_t kind) {
+  if (!h) return nullptr;
+  const HandleBase* b = static_cast<const HandleBase*>(h);
+  return b->kind == kind ? static_cast<T*>(const_cast<void*>(h)) : nullptr;
+}
+
+}  // namespace hfe
+
+using namespace hfe;
+
+extern "C" {
+
+const char* hfe_last_error(void) { return get_error(); }
+
+hfe_status hfe_set_allocator(hfe_alloc_fn alloc, hfe_dealloc_fn dealloc, void* ctx) {
+  if ((alloc == nullptr) != (dealloc == nullptr))
+    return fail(HFE_EINVAL, "alloc and dealloc must both be set or both be NULL");
+  std::lock_guard<std::mutex> l(g_alloc_mu);
+  g_alloc = alloc;
+  g_dealloc = dealloc;
+  g_alloc_ctx = ctx;
+  return HFE_OK;
+}
+
+hfe_status hfe_cdt_table(uint64_t* dst) {
+  if (!dst) return fail(HFE_EINVAL, "dst is NULL");
+  if (cdt_table_quad_impl(dst) != 0) return fail(HFE_EINTERNAL, "CDT table out of range");
+  return HFE_OK;
+}
+
+hfe_status hfe_default_params(uint32_t log_n_db, uint32_t log_n_q, uint32_t n_q_primes, uint32_t d2,
+                              uint32_t max_db_rows, hfe_params* out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  if (n_q_primes < 1 || n_q_primes > HFE_MAX_QPRIMES) return fail(HFE_EINVAL, "n_q_primes must be 1..8");
+  hfe_params P;
+  std::memset(&P, 0, sizeof(P));
+  P.log_n_db = log_n_db;
+  P.log_n_q = log_n_q;
+  P.n_q_primes = n_q_primes;
+  P.gap_bits = 20;
+  P.d2 = d2;
+  P.max_db_rows = max_db_rows;
+  P.t_num = 3;
+  P.t_den = 8;
+  const uint64_t step = 1ull << 17;
+  uint64_t c = ((1ull << 36) - 1) / step * step + 1;
+  std::vector<uint64_t> primes;
+  while (primes.size() < n_q_primes + 1) {
+    if (is_prime_u64(c)) primes.push_back(c);
+    c -= step;
+  }
+  P.p = primes[0];
+  for (uint32_t i = 0; i < n_q_primes; ++i) P.q[i] = primes[i + 1];
+  HFE_TRY(check_params(&P));
+  *out = P;
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ keygen
+static hfe_status upload(DevBuf& b, const void* host, size_t bytes) {
+  HFE_TRY(b.alloc(bytes, nullptr));
+  HFE_LAUNCH(hipMemcpy(b.ptr, host, bytes, hipMemcpyHostToDevice));
+  return HFE_OK;
+}
+
+static hfe_status keygen_impl(const hfe_params* params, uint64_t seed, hfe_keys* K) {
+  K->kind = kKeys;
+  K->stream = nullptr;
+  K->P = *params;
+  const hfe_params& P = K->P;
+  K->L = (int)P.n_q_primes;
+  K->n_primes = K->L + 1;
+  for (int i = 0; i < K->L; ++i) {
+    K->primes[i] = P.q[i];
+    K->prime_id[i] = (uint32_t)i;
+  }
+  K->primes[K->L] = P.p;
+  K->prime_id[K->L] = kPrimeIdP;
+  for (int i = 0; i < K->n_primes; ++i) K->mods[i] = make_mod(K->primes[i]);
+  const int nq = 1 << P.log_n_q, ndb = 1 << P.log_n_db;
+  K->k = (int)((P.d2 + nq - 1) / nq);
+  K->k_db = (int)((P.max_db_rows + ndb - 1) / ndb);
+
+  // ternary secrets (streams QSEC / DBSEC, element (t, 0)), value = (uniform mod 3) - 1
+  const Mod m3 = make_mod(3);
+  K->s_host.resize((size_t)K->k * nq);
+  for (int j = 0; j < K->k; ++j)
+    for (int t = 0; t < nq; ++t)
+      K->s_host[(size_t)j * nq + t] = (int8_t)((int)uniform_at(seed, stream_tag(kQSec, j), t, 0, m3) - 1);
+  K->sdb_host.resize((size_t)K->k_db * ndb);
+  for (int j = 0; j < K->k_db; ++j)
+    for (int t = 0; t < ndb; ++t)
+      K->sdb_host[(size_t)j * ndb + t] = (int8_t)((int)uniform_at(seed, stream_tag(kDbSec, j), t, 0, m3) - 1);
+
+  // twiddle tables
+  std::vector<uint64_t> tab;
+  for (int z = 0; z < K->n_primes; ++z) {
+    const uint64_t q = K->primes[z];
+    for (int which = 0; which < 2; ++which) {
+      const int logn = which == 0 ? (int)P.log_n_db : (int)P.log_n_q;
+      NttTabOwner& o = which == 0 ? K->tab_db[z] : K->tab_q[z];
+      ntt_tables_host(q, logn, tab);
+      HFE_TRY(upload(o.buf, tab.data(), tab.size() * sizeof(uint64_t)));
+      const size_t n = (size_t)1 << logn;
+      const uint64_t* base = o.buf.as<uint64_t>();
+      o.tab.psi = base;
+      o.tab.psi_sh = base + n;
+      o.tab.ipsi = base + 2 * n;
+      o.tab.ipsi_sh = base + 3 * n;
+      o.tab.q = q;
+      o.tab.mu = K->mods[z].mu;
+      o.tab.n_inv = inv_mod(n % q, q);
+      o.tab.n_inv_sh = shoup(o.tab.n_inv, q);
+      o.tab.logn = logn;
+    }
+  }
+
+  // NTT-domain secrets with Shoup companions: blocks of [n values | n companions]
+  auto residue = [](int v, uint64_t q) -> uint64_t { return v >= 0 ? (uint64_t)v : q - (uint64_t)(-v); };
+  {
+    std::vector<uint64_t> h((size_t)K->n_primes * K->k * 2 * nq, 0);
+    for (int z = 0; z < K->n_primes; ++z)
+      for (int j = 0; j < K->k; ++j)
+        for (int t = 0; t < nq; ++t)
+          h[(((size_t)z * K->k + j) * 2) * nq + t] = residue(K->s_host[(size_t)j * nq + t], K->primes[z]);
+    HFE_TRY(upload(K->s_hat, h.data(), h.size() * 8));
+    for (int z = 0; z < K->n_primes; ++z)
+      HFE_LAUNCH(launch_ntt_fwd(K->s_hat.as<uint64_t>() + (size_t)z * K->k * 2 * nq, K->k, 2 * nq,
+                                K->tab_q[z].tab, true, nullptr));
+  }
+  {
+    // s~_j(X) = s_j(1/X) = s_0 - sum_{t>=1} s_{n-t} X^t, mod q_0 (T = M_DB S_Q is exact there)
+    std::vector<uint64_t> h((size_t)K->k * 2 * nq, 0);
+    for (int j = 0; j < K->k; ++j)
+      for (int t = 0; t < nq; ++t) {
+        const int v = t == 0 ? K->s_host[(size_t)j * nq] : -K->s_host[(size_t)j * nq + nq - t];
+        h[(size_t)j * 2 * nq + t] = residue(v, K->primes[0]);
+      }
+    HFE_TRY(upload(K->sconj_hat, h.data(), h.size() * 8));
+    HFE_LAUNCH(launch_ntt_fwd(K->sconj_hat.as<uint64_t>(), K->k, 2 * nq, K->tab_q[0].tab, true, nullptr));
+  }
+  {
+    std::vector<uint64_t> h((size_t)K->n_primes * K->k_db * 2 * ndb, 0);
+    for (int z = 0; z < K->n_primes; ++z)
+      for (int j = 0; j < K->k_db; ++j)
+        for (int t = 0; t < ndb; ++t)
+          h[(((size_t)z * K->k_db + j) * 2) * ndb + t] =
+              residue(K->sdb_host[(size_t)j * ndb + t], K->primes[z]);
+    HFE_TRY(upload(K->sdb_hat, h.data(), h.size() * 8));
+    for (int z = 0; z < K->n_primes; ++z)
+      HFE_LAUNCH(launch_ntt_fwd(K->sdb_hat.as<uint64_t>() + (size_t)z * K->k_db * 2 * ndb, K->k_db,
+                                2 * ndb, K->tab_db[z].tab, true, nullptr));
+  }
+  if (cdt_table_quad_impl(K->cdt_host) != 0) return fail(HFE_EINTERNAL, "CDT table out of range");
+  HFE_TRY(upload(K->cdt, K->cdt_host, sizeof(K->cdt_host)));
+  HFE_LAUNCH(hipDeviceSynchronize());
+  return HFE_OK;
+}
+
+hfe_status hfe_keygen(const hfe_params* params, uint64_t seed, hfe_keys** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  HFE_TRY(check_params(params));
+  hfe_keys* K = new (std::nothrow) hfe_keys();
+  if (!K) return fail(HFE_ENOMEM, "host allocation failed");
+  hfe_status st = keygen_impl(params, seed, K);
+  if (st != HFE_OK) {
+    delete K;
+    return st;
+  }
+  *out = K;
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ encode
+hfe_status hfe_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int32_t d2,
+                      const int32_t* shifts, int32_t n_shifts, int8_t* out, void* stream) {
+  if (!codes || !masks || !shifts || !out) return fail(HFE_EINVAL, "NULL argument");
+  if (n < 0 || d2 < 1) return fail(HFE_ESHAPE, "bad sizes");
+  if (n_shifts < 1 || n_shifts > 64) return fail(HFE_EINVAL, "n_shifts must be 1..64");
+  HFE_LAUNCH(launch_encode(codes, masks, n, d2, shifts, n_shifts, out, (hipStream_t)stream));
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ database encryption
+static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t d1, uint64_t seed,
+                                  uint32_t forms, hipStream_t s, hfe_db* D) {
+  const hfe_params& P = K->P;
+  const int64_t ndb = 1ll << P.log_n_db, nq = 1ll << P.log_n_q;
+  D->kind = kDb;
+  D->stream = s;
+  D->keys = K;
+  D->d1 = d1;
+  D->R = ndb + d1;
+  D->K = (int64_t)P.d2 + nq;
+  D->KB = (D->K + kKB - 1) / kKB;
+  D->R_pad = (D->R + 63) / 64 * 64 + kRowPad;
+  D->forms = forms;
+  const int np = K->n_primes;
+
+  DevBuf MT, Trow, Tt;
+  HFE_TRY(MT.alloc((size_t)P.d2 * d1, s));
+  HFE_TRY(Trow.alloc(sizeof(int32_t) * (size_t)nq * d1, s));
+  HFE_TRY(Tt.alloc(sizeof(int32_t) * (size_t)nq * d1, s));
+  HFE_LAUNCH(launch_transpose_i8(m_db, d1, P.d2, MT.as<int8_t>(), s));
+  HFE_LAUNCH(launch_db_T(m_db, d1, (int32_t)P.d2, K->sconj_hat.as<uint64_t>(), K->k, K->tab_q[0].tab,
+                         Trow.as<int32_t>(), Tt.as<int32_t>(), s));
+  HFE_TRY(D->Dt.alloc(sizeof(uint64_t) * (size_t)np * D->K * D->R, s));
+  DbEncArgs a;
+  a.seed = seed;
+  a.MT = MT.as<int8_t>();
+  a.Tt = Tt.as<int32_t>();
+  a.cdt = K->cdt.as<uint64_t>();
+  a.d1 = d1;
+  a.d2 = P.d2;
+  a.K = D->K;
+  a.R = D->R;
+  a.k_db = K->k_db;
+  a.p = P.p;
+  for (int z = 0; z < np; ++z)
+    HFE_LAUNCH(launch_db_encrypt(a, D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, K->prime_id[z],
+                                 K->mods[z], K->tab_db[z].tab,
+                                 K->sdb_hat.as<uint64_t>() + (size_t)z * K->k_db * 2 * ndb, s));
+  if (forms & HFE_FORM_I8_MFMA) {
+    const size_t plane = (size_t)D->KB * D->R_pad * kKB;
+    HFE_TRY(D->digits.alloc((size_t)np * kDigits * plane, s));
+    for (int z = 0; z < np; ++z)
+      HFE_LAUNCH(launch_split_db(D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, D->K, D->R, D->KB, D->R_pad,
+                                 K->primes[z], D->digits.as<int8_t>() + (size_t)z * kDigits * plane, s));
+  }
+  if (!(forms & HFE_FORM_PLAIN_U64)) D->Dt.reset();
+  return HFE_OK;
+}
+
+hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, uint64_t seed, uint32_t forms,
+                          void* stream, hfe_db** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const hfe_keys* K = as_handle<hfe_keys>(keys, kKeys);
+  if (!K || !m_db) return fail(HFE_EINVAL, "invalid keys or m_db");
+  if (d1 < 1 || d1 > (int64_t)K->P.max_db_rows)
+    return fail(HFE_ESHAPE, "d1 must be 1 .. max_db_rows");
+  if (forms == 0 || (forms & ~3u)) return fail(HFE_EINVAL, "forms must be a non-empty set of hfe_form");
+  hfe_db* D = new (std::nothrow) hfe_db();
+  if (!D) return fail(HFE_ENOMEM, "host allocation failed");
+  hfe_status st = encrypt_db_impl(K, m_db, d1, seed, forms, (hipStream_t)stream, D);
+  if (st != HFE_OK) {
+    delete D;
+    return st;
+  }
+  *out = D;
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ query encryption
+hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint32_t level, uint64_t seed,
+                       void* stream, hfe_qct** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const hfe_keys* K = as_handle<hfe_keys>(keys, kKeys);
+  if (!K || !m_q) return fail(HFE_EINVAL, "invalid keys or m_q");
+  if (d3 < 1 || d3 > (1 << 20)) return fail(HFE_ESHAPE, "d3 must be 1 .. 2^20");
+  if (level < 1 || (int)level > K->L) return fail(HFE_ELEVEL, "level must be 1 .. n_q_primes");
+  hipStream_t s = (hipStream_t)stream;
+  const hfe_params& P = K->P;
+  const int64_t nq = 1ll << P.log_n_q;
+  hfe_qct* Q = new (std::nothrow) hfe_qct();
+  if (!Q) return fail(HFE_ENOMEM, "host allocation failed");
+  Q->kind = kQct;
+  Q->stream = s;
+  Q->keys = K;
+  Q->level = (int)level;
+  Q->d3 = d3;
+  Q->K = (int64_t)P.d2 + nq;
+  hfe_status st = Q->XT.alloc(sizeof(uint64_t) * (size_t)level * d3 * Q->K, s);
+  if (st != HFE_OK) {
+    delete Q;
+    return st;
+  }
+  QEncArgs a;
+  a.seed = seed;
+  a.m_q = m_q;
+  a.cdt = K->cdt.as<uint64_t>();
+  a.d3 = d3;
+  a.d2 = P.d2;
+  a.K = Q->K;
+  a.k = K->k;
+  const int dl = delta_log(K, (int)level);
+  for (uint32_t i = 0; i < level; ++i) {
+    const uint64_t delta_mod = pow_mod(2, (uint64_t)dl, K->primes[i]);
+    hipError_t e = launch_q_encrypt(a, Q->XT.as<uint64_t>() + (size_t)i * d3 * Q->K, K->prime_id[i], K->mods[i],
+                                    delta_mod, K->tab_q[i].tab,
+                                    K->s_hat.as<uint64_t>() + (size_t)i * K->k * 2 * nq, s);
+    if (e != hipSuccess) {
+      delete Q;
+      return hip_fail(e, "launch_q_encrypt");
+    }
+  }
+  *out = Q;
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ CCMM
+static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, int64_t rows, int32_t form,
+                            hipStream_t s, hfe_rct* R) {
+  const hfe_keys* K = D->keys;
+  const hfe_params& P = K->P;
+  const int level = Qc->level;
+  const int64_t ndb = 1ll << P.log_n_db;
+  const int64_t d3 = Qc->d3;
+  const int64_t R_out = ndb + rows;
+  R->kind = kRct;
+  R->stream = s;
+  R->keys = K;
+  R->level = level;
+  R->d3 = d3;
+  R->row0 = row0;
+  R->rows = rows;
+  R->R_out = R_out;
+
+  LiftArgs la;
+  std::memset(&la, 0, sizeof(la));
+  la.level = level;
+  for (int i = 0; i < level; ++i) {
+    la.q[i] = K->primes[i];
+    la.mu[i] = K->mods[i].mu;
+  }
+  la.p = P.p;
+  la.mu_p = K->mods[K->L].mu;
+  garner_consts(K, level, la.garner, la.half_digits);
+  uint64_t prod = 1;
+  for (int i = 0; i < level; ++i) {
+    la.mprod_p[i] = prod;
+    prod = mulmod(prod, K->primes[i] % P.p, P.p);
+  }
+  la.mprod_p[level] = prod;
+  la.Q_mod_p = prod;
+
+  const int nz = level + 1;
+  auto slot = [&](int z) { return z < level ? z : K->L; };
+  DevBuf C, Xp, Xd;
+  HFE_TRY(C.alloc(sizeof(uint64_t) * (size_t)nz * d3 * R_out, s));
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.nz = nz;
+  g.K = D->K;
+  g.KB = D->KB;
+  g.R_db = D->R;
+  g.R_pad = D->R_pad;
+  g.n_db = ndb;
+  g.row0 = row0;
+  g.rows = rows;
+  g.R_out = R_out;
+  g.d3 = d3;
+  g.d3_pad = (d3 + 63) / 64 * 64;
+  for (int z = 0; z < nz; ++z) {
+    g.C[z] = C.as<uint64_t>() + (size_t)z * d3 * R_out;
+    g.mod[z] = K->mods[slot(z)];
+  }
+  if (form == HFE_FORM_PLAIN_U64) {
+    HFE_TRY(Xp.alloc(sizeof(uint64_t) * (size_t)d3 * D->K, s));
+    HFE_LAUNCH(launch_lift(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, g.d3_pad, la, Xp.as<uint64_t>(), nullptr, s));
+    for (int z = 0; z < nz; ++z) {
+      g.Dt[z] = D->Dt.as<uint64_t>() + (size_t)slot(z) * D->K * D->R;
+      g.X[z] = z < level ? Qc->XT.as<uint64_t>() + (size_t)z * d3 * D->K : Xp.as<uint64_t>();
+    }
+    HFE_LAUNCH(launch_gemm_plain(g, s));
+  } else {
+    const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
+    const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
+    HFE_TRY(Xd.alloc((size_t)nz * kDigits * planeX, s));
+    HFE_LAUNCH(launch_lift(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, g.d3_pad, la, nullptr, Xd.as<int8_t>(), s));
+    for (int z = 0; z < nz; ++z) {
+      g.Dd[z] = D->digits.as<int8_t>() + (size_t)slot(z) * kDigits * planeD;
+      g.Xd[z] = Xd.as<int8_t>() + (size_t)z * kDigits * planeX;
+    }
+    HFE_LAUNCH(launch_gemm_i8(g, s));
+  }
+  RescaleArgs ra;
+  std::memset(&ra, 0, sizeof(ra));
+  ra.level = level;
+  ra.p = P.p;
+  for (int i = 0; i < level; ++i) {
+    ra.mod[i] = K->mods[i];
+    ra.pinv[i] = inv_mod(P.p % K->primes[i], K->primes[i]);
+    ra.pinv_sh[i] = shoup(ra.pinv[i], K->primes[i]);
+  }
+  HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
+  HFE_LAUNCH(launch_rescale(C.as<uint64_t>(), C.as<uint64_t>() + (size_t)level * d3 * R_out, d3 * R_out, ra,
+                            R->out.as<uint64_t>(), s));
+  return HFE_OK;
+}
+
+hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form, void* stream,
+                    hfe_rct** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  const hfe_qct* Qc = as_handle<hfe_qct>(q, kQct);
+  if (!D || !Qc) return fail(HFE_EINVAL, "invalid database or query handle");
+  if (Qc->keys != D->keys) return fail(HFE_EINVAL, "database and query use different keys");
+  if (Qc->K != D->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
+  if (Qc->level > D->keys->L) return fail(HFE_ELEVEL, "query level above the database primes");
+  if (row0 < 0 || rows < 1 || row0 + rows > D->d1) return fail(HFE_ESHAPE, "row range outside the database");
+  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA) return fail(HFE_EINVAL, "unknown form");
+  if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
+  hfe_rct* R = new (std::nothrow) hfe_rct();
+  if (!R) return fail(HFE_ENOMEM, "host allocation failed");
+  hfe_status st = ccmm_impl(D, Qc, row0, rows, form, (hipStream_t)stream, R);
+  if (st != HFE_OK) {
+    delete R;
+    return st;
+  }
+  *out = R;
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ decryption
+hfe_status hfe_decrypt(const hfe_keys* keys, const hfe_rct* r, double* v, int32_t* ip, void* stream) {
+  const hfe_keys* K = as_handle<hfe_keys>(keys, kKeys);
+  const hfe_rct* R = as_handle<hfe_rct>(r, kRct);
+  if (!K || !R || !ip) return fail(HFE_EINVAL, "invalid keys, result or ip");
+  if (R->keys != K) return fail(HFE_EINVAL, "result was not produced under these keys");
+  hipStream_t s = (hipStream_t)stream;
+  const hfe_params& P = K->P;
+  const int64_t ndb = 1ll << P.log_n_db;
+  const int level = R->level;
+  if ((R->row0 + R->rows - 1) / ndb >= K->k_db) return fail(HFE_ESHAPE, "rows beyond the database secrets");
+  DevBuf y;
+  HFE_TRY(y.alloc(sizeof(uint64_t) * (size_t)level * R->d3 * R->rows, s));
+  for (int i = 0; i < level; ++i)
+    HFE_LAUNCH(launch_dec_products(R->out.as<uint64_t>() + (size_t)i * R->d3 * R->R_out, R->d3, R->R_out, R->row0,
+                                   R->rows, (int)P.log_n_db, K->tab_db[i].tab,
+                                   K->sdb_hat.as<uint64_t>() + (size_t)i * K->k_db * 2 * ndb, K->k_db,
+                                   y.as<uint64_t>() + (size_t)i * R->d3 * R->rows, s));
+  DecodeArgs da;
+  std::memset(&da, 0, sizeof(da));
+  da.level = level;
+  for (int i = 0; i < level; ++i) {
+    da.q[i] = K->primes[i];
+    da.mu[i] = K->mods[i].mu;
+  }
+  garner_consts(K, level, da.garner, da.half_digits);
+  Big Q(1);
+  for (int i = 0; i < level; ++i) Q.mul(K->primes[i]);
+  for (size_t j = 0; j < 5 && j < Q.w.size(); ++j) da.Qw[j] = Q.w[j];
+  da.delta_log = delta_log(K, level);
+  HFE_LAUNCH(launch_decode(y.as<uint64_t>(), R->d3 * R->rows, da, v, ip, s));
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ match
+hfe_status hfe_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eyes, const int32_t* shifts,
+                     int32_t n_shifts, const uint8_t* db_masks, int64_t rows, int32_t d2, uint32_t t_num,
+                     uint32_t t_den, uint8_t* decision, uint8_t* eye_match, void* stream) {
+  if (!ip || !q_masks || !shifts || !db_masks || !eye_match) return fail(HFE_EINVAL, "NULL argument");
+  if (n_eyes < 1 || rows < 1 || d2 < 1) return fail(HFE_ESHAPE, "bad sizes");
+  if (n_shifts < 1 || n_shifts > 64) return fail(HFE_EINVAL, "n_shifts must be 1..64");
+  if (t_den == 0 || 2ull * t_num >= t_den) return fail(HFE_EINVAL, "threshold must satisfy 0 <= t < 1/2");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t W = (d2 + 63) / 64, d3 = n_eyes * n_shifts, nb = (rows + 255) / 256;
+  DevBuf qw, dbw, part;
+  HFE_TRY(qw.alloc(sizeof(uint64_t) * (size_t)W * d3, s));
+  HFE_TRY(dbw.alloc(sizeof(uint64_t) * (size_t)W * rows, s));
+  HFE_TRY(part.alloc((size_t)d3 * nb, s));
+  HFE_LAUNCH(launch_match(ip, q_masks, n_eyes, shifts, n_shifts, db_masks, rows, d2, t_num, t_den,
+                          qw.as<uint64_t>(), dbw.as<uint64_t>(), decision, part.as<uint8_t>(), eye_match, s));
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ export / shape / free
+static hfe_status copy_out(const void* dev, void* dst, size_t bytes) {
+  HFE_LAUNCH(hipDeviceSynchronize());
+  HFE_LAUNCH(hipMemcpy(dst, dev, bytes, hipMemcpyDeviceToHost));
+  return HFE_OK;
+}
+
+hfe_status hfe_export(const void* handle, int32_t which, uint64_t* dst, size_t n, size_t* count) {
+  if (!handle) return fail(HFE_EINVAL, "handle is NULL");
+  const uint32_t kind = static_cast<const HandleBase*>(handle)->kind;
+  size_t need = 0;
+  if (kind == kKeys) {
+    const hfe_keys* K = static_cast<const hfe_keys*>(handle);
+    const std::vector<int8_t>& src = which == 0 ? K->s_host : K->sdb_host;
+    if (which != 0 && which != 1) return fail(HFE_EINVAL, "keys export: which must be 0 or 1");
+    need = src.size();
+    if (count) *count = need;
+    if (!dst) return HFE_OK;
+    if (n != need) return fail(HFE_ESHAPE, "export size mismatch");
+    for (size_t i = 0; i < need; ++i) dst[i] = (uint64_t)(int64_t)src[i];
+    return HFE_OK;
+  }
+  if (kind == kDb) {
+    const hfe_db* D = static_cast<const hfe_db*>(handle);
+    if (which != 0) return fail(HFE_EINVAL, "db export: which must be 0");
+    const int np = D->keys->n_primes;
+    need = (size_t)np * D->R * D->K;
+    if (count) *count = need;
+    if (!dst) return HFE_OK;
+    if (n != need) return fail(HFE_ESHAPE, "export size mismatch");
+    if (!D->Dt.ptr) return fail(HFE_EINVAL, "database kept no uint64 residues (plain form not requested)");
+    std::vector<uint64_t> tmp(need);
+    HFE_TRY(copy_out(D->Dt.ptr, tmp.data(), need * 8));
+    for (int z = 0; z < np; ++z)
+      for (int64_t c = 0; c < D->K; ++c)
+        for (int64_t r = 0; r < D->R; ++r)
+          dst[((size_t)z * D->R + r) * D->K + c] = tmp[((size_t)z * D->K + c) * D->R + r];
+    return HFE_OK;
+  }
+  if (kind == kQct) {
+    const hfe_qct* Q = static_cast<const hfe_qct*>(handle);
+    if (which != 0) return fail(HFE_EINVAL, "qct export: which must be 0");
+    need = (size_t)Q->level * Q->d3 * Q->K;
+    if (count) *count = need;
+    if (!dst) return HFE_OK;
+    if (n != need) return fail(HFE_ESHAPE, "export size mismatch");
+    return copy_out(Q->XT.ptr, dst, need * 8);
+  }
+  if (kind == kRct) {
+    const hfe_rct* R = static_cast<const hfe_rct*>(handle);
+    if (which != 0) return fail(HFE_EINVAL, "rct export: which must be 0");
+    need = (size_t)R->level * R->d3 * R->R_out;
+    if (count) *count = need;
+    if (!dst) return HFE_OK;
+    if (n != need) return fail(HFE_ESHAPE, "export size mismatch");
+    return copy_out(R->out.ptr, dst, need * 8);
+  }
+  return fail(HFE_EINVAL, "unknown handle");
+}
+
+hfe_status hfe_shape(const void* handle, int64_t* dims) {
+  if (!handle || !dims) return fail(HFE_EINVAL, "NULL argument");
+  const uint32_t kind = static_cast<const HandleBase*>(handle)->kind;
+  if (kind == kKeys) {
+    const hfe_keys* K = static_cast<const hfe_keys*>(handle);
+    dims[0] = K->L;
+    dims[1] = K->k;
+    dims[2] = K->k_db;
+    dims[3] = (int64_t)K->P.d2 + (1ll << K->P.log_n_q);
+  } else if (kind == kDb) {
+    const hfe_db* D = static_cast<const hfe_db*>(handle);
+    dims[0] = D->keys->L;
+    dims[1] = D->d1;
+    dims[2] = D->R;
+    dims[3] = D->K;
+  } else if (kind == kQct) {
+    const hfe_qct* Q = static_cast<const hfe_qct*>(handle);
+    dims[0] = Q->level;
+    dims[1] = Q->d3;
+    dims[2] = 0;
+    dims[3] = Q->K;
+  } else if (kind == kRct) {
+    const hfe_rct* R = static_cast<const hfe_rct*>(handle);
+    dims[0] = R->level;
+    dims[1] = R->d3;
+    dims[2] = R->rows;
+    dims[3] = R->R_out;
+  } else {
+    return fail(HFE_EINVAL, "unknown handle");
+  }
+  return HFE_OK;
+}
+
+void hfe_free(void* handle) {
+  if (!handle) return;
+  HandleBase* b = static_cast<HandleBase*>(handle);
+  switch (b->kind) {
+    case kKeys:
+      b->kind = 0;
+      delete static_cast<hfe_keys*>(handle);
+      break;
+    case kDb:
+      b->kind = 0;
+      delete static_cast<hfe_db*>(handle);
+      break;
+    case kQct:
+      b->kind = 0;
+      delete static_cast<hfe_qct*>(handle);
+      break;
+    case kRct:
+      b->kind = 0;
+      delete static_cast<hfe_rct*>(handle);
+      break;
+    default:
+      break;
+  }
+}
+
+}  // extern "C"

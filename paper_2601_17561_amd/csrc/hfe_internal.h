@@ -1,0 +1,274 @@
+// Internal declarations of the encrypted-CCMM library: handle structs, device buffers,
+// error reporting and the kernel launchers implemented in the .hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hfe.h"
+#include "hfe_math.h"
+
+namespace hfe {
+
+constexpr int kMaxPrimes = HFE_MAX_QPRIMES + 1;  // q_0..q_{L-1} and p
+constexpr int kDigits = 5;                       // balanced base-256 digits per 36-bit residue
+constexpr int kKB = 64;                          // K bytes per digit block
+constexpr int kRowPad = 256;                     // extra zero rows after the digit planes
+constexpr int kMaxLogN = 14;                     // ring degrees handled by the LDS-resident NTT
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+const char* get_error();
+
+struct Status {
+  hfe_status code;
+};
+
+#define HFE_CHECK_HIP(expr)                                                        \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      ::hfe::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));         \
+      return HFE_EDEVICE;                                                          \
+    }                                                                              \
+  } while (0)
+
+#define HFE_TRY(expr)                  \
+  do {                                 \
+    hfe_status _s = (expr);            \
+    if (_s != HFE_OK) return _s;       \
+  } while (0)
+
+hfe_status fail(hfe_status code, const std::string& msg);
+
+// ------------------------------------------------------------------ device memory
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// Owning device buffer (released in stream order on the stream it was allocated on).
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    reset();
+    ptr = o.ptr;
+    bytes = o.bytes;
+    stream = o.stream;
+    o.ptr = nullptr;
+    o.bytes = 0;
+    return *this;
+  }
+  ~DevBuf() { reset(); }
+  hfe_status alloc(size_t n, hipStream_t s);
+  void reset();
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+};
+
+// ------------------------------------------------------------------ NTT tables
+// Forward: Cooley-Tukey with psi^brv(i) twiddles (bit-reversed output); inverse:
+// Gentleman-Sande with psi^-brv(i) twiddles and the 1/n scale (natural-order output).
+struct NttTab {
+  const uint64_t* psi;
+  const uint64_t* psi_sh;
+  const uint64_t* ipsi;
+  const uint64_t* ipsi_sh;
+  uint64_t q, mu, n_inv, n_inv_sh;
+  int logn;
+};
+
+struct NttTabOwner {
+  DevBuf buf;  // psi | psi_sh | ipsi | ipsi_sh, n entries each
+  NttTab tab{};
+};
+
+// ------------------------------------------------------------------ handles
+enum Kind : uint32_t { kKeys = 0x4b455953, kDb = 0x44422020, kQct = 0x51435420, kRct = 0x52435420 };
+
+struct HandleBase {
+  uint32_t kind;
+  hipStream_t stream;  // stream of the work that produced the handle
+};
+
+}  // namespace hfe
+
+struct hfe_keys : hfe::HandleBase {
+  hfe_params P;
+  int L;                                   // query primes carried (n_q_primes)
+  int n_primes;                            // L + 1
+  uint64_t primes[hfe::kMaxPrimes];        // q_0..q_{L-1}, p (index L)
+  uint32_t prime_id[hfe::kMaxPrimes];      // random-stream ids (i, or 16 for p)
+  hfe::Mod mods[hfe::kMaxPrimes];
+  int k, k_db;
+  std::vector<int8_t> s_host;              // k x N_Q
+  std::vector<int8_t> sdb_host;            // k_db x N_DB
+  hfe::NttTabOwner tab_db[hfe::kMaxPrimes];   // ring N_DB
+  hfe::NttTabOwner tab_q[hfe::kMaxPrimes];    // ring N_Q
+  hfe::DevBuf s_hat;                       // [prime][k][N_Q]: NTT(s_j), then Shoup companions
+  hfe::DevBuf sconj_hat;                   // [k][N_Q] mod q_0: NTT of s~_j(X) = s_j(1/X), + Shoup
+  hfe::DevBuf sdb_hat;                     // [prime][k_db][N_DB]: NTT(s'_j), + Shoup
+  hfe::DevBuf cdt;                         // 19 uint64
+  uint64_t cdt_host[19];
+};
+
+struct hfe_db : hfe::HandleBase {
+  const hfe_keys* keys;
+  int64_t d1, R, K;                        // R = N_DB + d1 rows, K = d2 + N_Q columns
+  int64_t KB;                              // ceil(K / 64) digit blocks
+  int64_t R_pad;                           // rows of a digit plane (R + padding)
+  uint32_t forms;
+  hfe::DevBuf Dt;                          // [prime][K][R] uint64 (column-major D), plain form
+  hfe::DevBuf digits;                      // [prime][5][KB][R_pad][64] int8, i8 form
+};
+
+struct hfe_qct : hfe::HandleBase {
+  const hfe_keys* keys;
+  int level;
+  int64_t d3, K;
+  hfe::DevBuf XT;                          // [level][d3][K] uint64: row c = [b_c | a_c]
+};
+
+struct hfe_rct : hfe::HandleBase {
+  const hfe_keys* keys;
+  int level;
+  int64_t d3, row0, rows, R_out;           // R_out = N_DB + rows
+  hfe::DevBuf out;                         // [level][d3][R_out] uint64
+};
+
+namespace hfe {
+
+// ------------------------------------------------------------------ host math (hfe_host.cpp)
+bool is_prime_u64(uint64_t n);
+uint64_t pow_mod(uint64_t a, uint64_t e, uint64_t q);
+uint64_t inv_mod(uint64_t a, uint64_t q);
+Mod make_mod(uint64_t q);
+uint64_t shoup(uint64_t w, uint64_t q);
+// psi = primitive 2n-th root of unity (g^((q-1)/2n), g the smallest generator)
+uint64_t primitive_2n_root(uint64_t q, int logn);
+// host tables (psi_rev, psi_rev_sh, ipsi_rev, ipsi_rev_sh) for one prime and ring degree
+void ntt_tables_host(uint64_t q, int logn, std::vector<uint64_t>& out);
+int cdt_table_quad_impl(uint64_t* dst);  // hfe_cdt.cpp (quad precision), 0 on success
+
+// ------------------------------------------------------------------ launchers (.hip files)
+// All launchers enqueue on `s` and return hipGetLastError() of the launch.
+// Negacyclic forward NTT in place of `count` polynomials of length n = 2^tab.logn starting at
+// a + i * stride; with_shoup also writes the Shoup companions at a + i * stride + n.
+hipError_t launch_ntt_fwd(uint64_t* a, int64_t count, int64_t stride, NttTab tab, bool with_shoup,
+                          hipStream_t s);
+
+// T = M_DB S_Q mod q_0, centered to int32 (row-major in Trow, d1 x N_Q scratch) and
+// transposed into Tt[v][i] (N_Q x d1).
+hipError_t launch_db_T(const int8_t* m_db, int64_t d1, int32_t d2, const uint64_t* sconj_hat,
+                       int k, NttTab tab_q0, int32_t* Trow, int32_t* Tt, hipStream_t s);
+
+// Transposes: in (rows x cols) int8 -> out (cols x rows).
+hipError_t launch_transpose_i8(const int8_t* in, int64_t rows, int64_t cols, int8_t* out,
+                               hipStream_t s);
+
+struct DbEncArgs {
+  uint64_t seed;
+  const int8_t* MT;         // d2 x d1 (transposed M_DB)
+  const int32_t* Tt;        // N_Q x d1
+  const uint64_t* cdt;
+  int64_t d1, d2, K, R;
+  int k_db;
+  uint64_t p;
+};
+// Per prime: columns of D (Dt rows): [a_c (N_DB) | B[:, c] (d1)].
+hipError_t launch_db_encrypt(const DbEncArgs& a, uint64_t* Dt_prime, uint32_t prime_id,
+                             const Mod& m, NttTab tab_db, const uint64_t* sdb_hat_prime,
+                             hipStream_t s);
+
+struct QEncArgs {
+  uint64_t seed;
+  const int8_t* m_q;        // d3 x d2
+  const uint64_t* cdt;
+  int64_t d3, d2, K;
+  int k;
+};
+hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prime_id,
+                            const Mod& m, uint64_t delta_mod, NttTab tab_q,
+                            const uint64_t* s_hat_prime, hipStream_t s);
+
+// Digit split of the database: Dt [K][R] residues mod q -> digits [5][KB][R_pad][64].
+hipError_t launch_split_db(const uint64_t* Dt_prime, int64_t K, int64_t R, int64_t KB,
+                           int64_t R_pad, uint64_t q, int8_t* dig_prime, hipStream_t s);
+
+// Centered CRT lift of the query from Q_level to p, plus the int8 digit planes of every
+// prime of the level and p.  XT: [level][d3][K].  Outputs: Xp [d3][K] (lift mod p, may be
+// null) and Xd [level+1][5][KB][d3_pad][64] (may be null).
+struct LiftArgs {
+  int level;
+  uint64_t q[HFE_MAX_QPRIMES];
+  uint64_t mu[HFE_MAX_QPRIMES];                       // floor(2^64 / q_i)
+  uint64_t p, mu_p;
+  uint64_t garner[HFE_MAX_QPRIMES][HFE_MAX_QPRIMES];  // [i][j<i]: q_0..q_{j-1} mod q_i; [i][i]: inverse
+  uint64_t mprod_p[HFE_MAX_QPRIMES + 1];              // q_0..q_{i-1} mod p
+  uint64_t half_digits[HFE_MAX_QPRIMES];              // mixed-radix digits of (Q-1)/2
+  uint64_t Q_mod_p;
+};
+hipError_t launch_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
+                       const LiftArgs& la, uint64_t* Xp, int8_t* Xd, hipStream_t s);
+
+// Plain uint64 contraction.  For each prime slot z < nz: C[z][c][r] = sum_k Dt[z][k][src(r)] *
+// X[z][c][k] mod prime, rows r < R_out mapped to source rows (A-part then the shard).
+struct GemmArgs {
+  int nz;
+  const uint64_t* Dt[kMaxPrimes];
+  const int8_t* Dd[kMaxPrimes];
+  const uint64_t* X[kMaxPrimes];
+  const int8_t* Xd[kMaxPrimes];
+  uint64_t* C[kMaxPrimes];
+  Mod mod[kMaxPrimes];
+  int64_t K, KB, R_db, R_pad, n_db, row0, rows, R_out, d3, d3_pad;
+};
+hipError_t launch_gemm_plain(const GemmArgs& g, hipStream_t s);
+hipError_t launch_gemm_i8(const GemmArgs& g, hipStream_t s);
+
+// Rescale by p: out[i][c][r] = (C[i][c][r] - centered(C_p[c][r])) * p^-1 mod q_i.
+struct RescaleArgs {
+  int level;
+  Mod mod[HFE_MAX_QPRIMES];
+  uint64_t pinv[HFE_MAX_QPRIMES], pinv_sh[HFE_MAX_QPRIMES];
+  uint64_t p;
+};
+hipError_t launch_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, const RescaleArgs& ra,
+                          uint64_t* out, hipStream_t s);
+
+// Decryption: y[i][c][r] = B_out + (s'_j * A_out)[(row0 + r) mod N_DB] mod q_i.
+hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,
+                               int64_t rows, int n_db_log, NttTab tab, const uint64_t* sdb_hat_prime,
+                               int k_db, uint64_t* y_prime, hipStream_t s);
+
+struct DecodeArgs {
+  int level;
+  uint64_t q[HFE_MAX_QPRIMES];
+  uint64_t mu[HFE_MAX_QPRIMES];
+  uint64_t garner[HFE_MAX_QPRIMES][HFE_MAX_QPRIMES];
+  uint64_t half_digits[HFE_MAX_QPRIMES];
+  uint64_t Qw[5];           // Q as 64-bit words
+  int delta_log;
+};
+hipError_t launch_decode(const uint64_t* y, int64_t n, const DecodeArgs& da, double* v, int32_t* ip,
+                         hipStream_t s);
+
+hipError_t launch_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int32_t d2,
+                         const int32_t* shifts_dev, int32_t n_shifts, int8_t* out, hipStream_t s);
+
+hipError_t launch_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eyes,
+                        const int32_t* shifts_dev, int32_t n_shifts, const uint8_t* db_masks,
+                        int64_t rows, int32_t d2, uint32_t t_num, uint32_t t_den,
+                        uint64_t* qwords, uint64_t* dbwords, uint8_t* decision, uint8_t* col_any,
+                        uint8_t* eye_match, hipStream_t s);
+
+}  // namespace hfe

@@ -1,0 +1,399 @@
+// Elementwise and layout kernels around the contraction: masked ternary encoding, int8
+// transpose, digit split of the database, centered CRT lift of the query with its digit
+// split, rescale by the special prime, CRT decode, and the plaintext match decision.
+#include "hfe_internal.h"
+
+namespace hfe {
+
+constexpr int kMaxShifts = 64;
+struct Shifts {
+  int32_t r[kMaxShifts];
+};
+
+// ------------------------------------------------------------------ encode (Section 2.1.3)
+// out[(e * S + s) * d2 + t] = m' - 2 (c' AND m'), c' and m' = row e rolled by shifts[s].
+__global__ void k_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int32_t d2,
+                         Shifts sh, int32_t n_shifts, int8_t* out) {
+  const int64_t row = blockIdx.y;               // e * S + s
+  const int64_t e = row / n_shifts;
+  const int32_t r = sh.r[row % n_shifts];
+  const uint8_t* c = codes + e * d2;
+  const uint8_t* m = masks + e * d2;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < d2;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t src = (t - r) % d2;
+    if (src < 0) src += d2;
+    const int cm = c[src] & m[src] & 1;
+    out[row * d2 + t] = (int8_t)((m[src] & 1) - 2 * cm);
+  }
+}
+
+hipError_t launch_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int32_t d2,
+                         const int32_t* shifts, int32_t n_shifts, int8_t* out, hipStream_t s) {
+  if (n <= 0 || d2 <= 0) return hipSuccess;
+  if (n_shifts < 1 || n_shifts > kMaxShifts) return hipErrorInvalidValue;
+  Shifts sh{};
+  for (int i = 0; i < n_shifts; ++i) sh.r[i] = shifts[i];
+  dim3 grid((unsigned)((d2 + 255) / 256), (unsigned)(n * n_shifts));
+  hipLaunchKernelGGL(k_encode, grid, dim3(256), 0, s, codes, masks, n, d2, sh, n_shifts, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ int8 transpose
+__global__ void k_transpose_i8(const int8_t* in, int64_t rows, int64_t cols, int8_t* out) {
+  __shared__ int8_t tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  for (int y = threadIdx.y; y < 64; y += blockDim.y) {
+    const int64_t r = r0 + y, c = c0 + threadIdx.x;
+    if (r < rows && c < cols) tile[y][threadIdx.x] = in[r * cols + c];
+  }
+  __syncthreads();
+  for (int y = threadIdx.y; y < 64; y += blockDim.y) {
+    const int64_t c = c0 + y, r = r0 + threadIdx.x;
+    if (r < rows && c < cols) out[c * rows + r] = tile[threadIdx.x][y];
+  }
+}
+
+hipError_t launch_transpose_i8(const int8_t* in, int64_t rows, int64_t cols, int8_t* out,
+                               hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+  hipLaunchKernelGGL(k_transpose_i8, grid, dim3(64, 4), 0, s, in, rows, cols, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ digit split
+// Centered residue x in (-q/2, q/2) -> 5 balanced base-256 digits d_t in [-128, 127]
+// (|d_4| <= 8), x = sum_t d_t 256^t.
+__device__ __forceinline__ void split5(int64_t x, int32_t d[kDigits]) {
+#pragma unroll
+  for (int t = 0; t < kDigits - 1; ++t) {
+    const int32_t lo = (int32_t)((x + 128) & 255) - 128;
+    d[t] = lo;
+    x = (x - lo) >> 8;
+  }
+  d[kDigits - 1] = (int32_t)x;
+}
+
+// Thread (row r, block kb): 64 residues Dt[kb*64 + kk][r] -> 64 bytes of each digit plane.
+__global__ void __launch_bounds__(256) k_split_db(const uint64_t* Dt, int64_t K, int64_t R, int64_t KB,
+                                                  int64_t R_pad, uint64_t q, int8_t* dig) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t kb = blockIdx.y;
+  if (r >= R_pad) return;
+  uint32_t w[kDigits][kKB / 4];
+#pragma unroll
+  for (int t = 0; t < kDigits; ++t)
+#pragma unroll
+    for (int i = 0; i < kKB / 4; ++i) w[t][i] = 0;
+#pragma unroll
+  for (int kk = 0; kk < kKB; ++kk) {
+    const int64_t k = kb * kKB + kk;
+    int64_t x = 0;
+    if (r < R && k < K) x = centered(Dt[k * R + r], q);
+    int32_t d[kDigits];
+    split5(x, d);
+#pragma unroll
+    for (int t = 0; t < kDigits; ++t) w[t][kk >> 2] |= ((uint32_t)(d[t] & 255)) << (8 * (kk & 3));
+  }
+#pragma unroll
+  for (int t = 0; t < kDigits; ++t) {
+    uint4* dst = reinterpret_cast<uint4*>(dig + (((int64_t)t * KB + kb) * R_pad + r) * kKB);
+#pragma unroll
+    for (int i = 0; i < kKB / 16; ++i)
+      dst[i] = make_uint4(w[t][4 * i], w[t][4 * i + 1], w[t][4 * i + 2], w[t][4 * i + 3]);
+  }
+}
+
+hipError_t launch_split_db(const uint64_t* Dt_prime, int64_t K, int64_t R, int64_t KB, int64_t R_pad,
+                           uint64_t q, int8_t* dig_prime, hipStream_t s) {
+  dim3 grid((unsigned)((R_pad + 255) / 256), (unsigned)KB);
+  hipLaunchKernelGGL(k_split_db, grid, dim3(256), 0, s, Dt_prime, K, R, KB, R_pad, q, dig_prime);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Garner mixed radix
+// Residues y_i mod q_i -> digits v_i with Y = v_0 + v_1 q_0 + v_2 q_0 q_1 + ..., computed as
+// v_i = (y_i - sum_{j<i} v_j (q_0..q_{j-1} mod q_i)) * (q_0..q_{i-1})^-1 mod q_i.
+// garner[i][j] = q_0..q_{j-1} mod q_i for j < i, garner[i][i] = (q_0..q_{i-1})^-1 mod q_i.
+__device__ __forceinline__ void garner_digits(const uint64_t* y, int level,
+                                              const uint64_t (*garner)[HFE_MAX_QPRIMES],
+                                              const uint64_t* q, const uint64_t* mus, uint64_t* v) {
+  for (int i = 0; i < level; ++i) {
+    const uint64_t qi = q[i];
+    const uint64_t mu = mus[i];
+    uint64_t s = 0;
+    for (int j = 0; j < i; ++j)
+      s = add_mod(s, mul_mod(barrett64(v[j], qi, mu), garner[i][j], qi, mu), qi);
+    v[i] = i == 0 ? y[0] : mul_mod(sub_mod(y[i], s, qi), garner[i][i], qi, mu);
+  }
+}
+
+// Y > (Q - 1)/2, compared on mixed-radix digits from the most significant one.
+__device__ __forceinline__ bool above_half(const uint64_t* v, const uint64_t* half, int level) {
+  for (int i = level - 1; i >= 0; --i) {
+    if (v[i] != half[i]) return v[i] > half[i];
+  }
+  return false;
+}
+
+// ------------------------------------------------------------------ query lift + digit split
+// Element (c, k): residues XT[i][c][k] of L(x) mod q_i; the lift L(x) = centered CRT value in
+// (-Q/2, Q/2); L mod p.  Writes Xp[c][k] = L mod p (plain form) and, for every prime of the
+// level and p, the 5 digit planes of the centered residue (i8 form), zero in the padding.
+__global__ void __launch_bounds__(256) k_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
+                                              int64_t d3_pad, LiftArgs la, uint64_t* Xp, int8_t* Xd) {
+  const int64_t kpad = KB * kKB;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (k >= kpad) return;
+  const bool valid = c < d3 && k < K;
+  uint64_t y[HFE_MAX_QPRIMES] = {};
+  uint64_t lp = 0;
+  if (valid) {
+    for (int i = 0; i < la.level; ++i) y[i] = XT[((int64_t)i * d3 + c) * K + k];
+    uint64_t v[HFE_MAX_QPRIMES];
+    garner_digits(y, la.level, la.garner, la.q, la.mu, v);
+    const uint64_t p = la.p;
+    const uint64_t mup = la.mu_p;
+    for (int i = 0; i < la.level; ++i)
+      lp = add_mod(lp, mul_mod(barrett64(v[i], p, mup), la.mprod_p[i], p, mup), p);
+    if (above_half(v, la.half_digits, la.level)) lp = sub_mod(lp, la.Q_mod_p, p);
+    if (Xp) Xp[c * K + k] = lp;
+  }
+  if (!Xd) return;
+  const int64_t kb = k / kKB, kk = k % kKB;
+  for (int z = 0; z <= la.level; ++z) {
+    int64_t x = 0;
+    if (valid) x = z < la.level ? centered(y[z], la.q[z]) : centered(lp, la.p);
+    int32_t d[kDigits];
+    split5(x, d);
+#pragma unroll
+    for (int t = 0; t < kDigits; ++t)
+      Xd[((((int64_t)z * kDigits + t) * KB + kb) * d3_pad + c) * kKB + kk] = (int8_t)d[t];
+  }
+}
+
+hipError_t launch_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
+                       const LiftArgs& la, uint64_t* Xp, int8_t* Xd, hipStream_t s) {
+  const int64_t kpad = KB * kKB;
+  const int64_t cols = Xd ? d3_pad : d3;
+  dim3 grid((unsigned)((kpad + 255) / 256), (unsigned)cols);
+  hipLaunchKernelGGL(k_lift, grid, dim3(256), 0, s, XT, d3, K, KB, d3_pad, la, Xp, Xd);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ rescale by p
+// out[i][e] = (C[i][e] - centered(Cp[e]) mod q_i) * p^-1 mod q_i = RS_p of the CRT value.
+__global__ void k_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, RescaleArgs ra,
+                          uint64_t* out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cp = centered(Cp[e], ra.p);
+    for (int i = 0; i < ra.level; ++i) {
+      const Mod& m = ra.mod[i];
+      const uint64_t r = from_signed(cp, m.q, m.mu);
+      const uint64_t d = sub_mod(C[(int64_t)i * n + e], r, m.q);
+      out[(int64_t)i * n + e] = mul_shoup(d, ra.pinv[i], ra.pinv_sh[i], m.q);
+    }
+  }
+}
+
+hipError_t launch_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, const RescaleArgs& ra,
+                          uint64_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_rescale, dim3((unsigned)blocks), dim3(256), 0, s, C, Cp, n, ra, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ CRT decode
+// y residues [level][n] -> Y centered in (-Q/2, Q/2) as a 320-bit two's complement integer,
+// ip = floor(Y / 2^s + 1/2) and v = Y / 2^s.
+__global__ void k_decode(const uint64_t* y, int64_t n, DecodeArgs da, double* v, int32_t* ip) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t r[HFE_MAX_QPRIMES], g[HFE_MAX_QPRIMES];
+    for (int i = 0; i < da.level; ++i) r[i] = y[(int64_t)i * n + e];
+    garner_digits(r, da.level, da.garner, da.q, da.mu, g);
+    // Horner: Y = g_{l-1}; Y = Y * q_i + g_i for i = l-2 .. 0 (5 words, little endian)
+    uint64_t w[5] = {g[da.level - 1], 0, 0, 0, 0};
+    for (int i = da.level - 2; i >= 0; --i) {
+      uint64_t carry = g[i];
+      for (int j = 0; j < 5; ++j) {
+        const uint64_t lo = w[j] * da.q[i];
+        const uint64_t hi = mulhi64(w[j], da.q[i]);
+        const uint64_t s = lo + carry;
+        carry = hi + (s < lo ? 1 : 0);
+        w[j] = s;
+      }
+    }
+    if (above_half(g, da.half_digits, da.level)) {  // Y -= Q
+      uint64_t borrow = 0;
+      for (int j = 0; j < 5; ++j) {
+        const uint64_t a = w[j], b = da.Qw[j];
+        const uint64_t d = a - b - borrow;
+        borrow = (a < b || (a == b && borrow)) ? 1 : 0;
+        w[j] = d;
+      }
+    }
+    const bool neg = (int64_t)w[4] < 0;
+    // v = Y / 2^s
+    uint64_t m[5];
+    if (neg) {
+      uint64_t carry = 1;
+      for (int j = 0; j < 5; ++j) {
+        m[j] = ~w[j] + carry;
+        carry = (carry && m[j] == 0) ? 1 : 0;
+      }
+    } else {
+      for (int j = 0; j < 5; ++j) m[j] = w[j];
+    }
+    double mag = 0.0;
+    for (int j = 4; j >= 0; --j) mag = mag * 18446744073709551616.0 + (double)m[j];
+    if (v) v[e] = ldexp(neg ? -mag : mag, -da.delta_log);
+    // ip = (Y + 2^(s-1)) >> s, arithmetic
+    const int s = da.delta_log;
+    uint64_t add[5] = {0, 0, 0, 0, 0};
+    if (s > 0) add[(s - 1) >> 6] = 1ull << ((s - 1) & 63);
+    uint64_t carry = 0;
+    for (int j = 0; j < 5; ++j) {
+      const uint64_t a = w[j] + add[j];
+      const uint64_t c1 = a < w[j] ? 1 : 0;
+      const uint64_t b = a + carry;
+      const uint64_t c2 = b < a ? 1 : 0;
+      w[j] = b;
+      carry = c1 | c2;
+    }
+    const int wi = s >> 6, bi = s & 63;
+    uint64_t lo = w[wi] >> bi;
+    if (bi && wi + 1 < 5) lo |= w[wi + 1] << (64 - bi);
+    ip[e] = (int32_t)(uint32_t)lo;
+  }
+}
+
+hipError_t launch_decode(const uint64_t* y, int64_t n, const DecodeArgs& da, double* v, int32_t* ip,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(256), 0, s, y, n, da, v, ip);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ match decision
+// Masks packed into 64-bit words, words-major ([word][row]) so that a row block reads
+// contiguous words.  Query masks are rolled by their shifts while packing.
+__global__ void k_pack_masks(const uint8_t* masks, int64_t n, int32_t d2, Shifts sh, int32_t n_shifts,
+                             int32_t W, uint64_t* out) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // e * S + s
+  const int32_t w = blockIdx.y;
+  if (row >= n * n_shifts) return;
+  const int64_t e = row / n_shifts;
+  const int32_t r = sh.r[row % n_shifts];
+  const uint8_t* m = masks + e * d2;
+  uint64_t word = 0;
+  for (int b = 0; b < 64; ++b) {
+    const int64_t t = (int64_t)w * 64 + b;
+    if (t < d2) {
+      int64_t src = (t - r) % d2;
+      if (src < 0) src += d2;
+      word |= (uint64_t)(m[src] & 1) << b;
+    }
+  }
+  out[(int64_t)w * (n * n_shifts) + row] = word;
+}
+
+constexpr int kMatchCols = 16;
+
+// Block (column group g, row block): thread = one database row, kMatchCols query columns.
+__global__ void __launch_bounds__(256)
+k_match(const int32_t* ip, const uint64_t* qwords, const uint64_t* dbwords, int64_t d3, int64_t rows,
+        int32_t W, uint32_t t_num, uint32_t t_den, uint8_t* decision, uint8_t* part) {
+  extern __shared__ uint64_t qw[];  // [kMatchCols][W]
+  __shared__ int any_flag[kMatchCols];
+  const int64_t c0 = (int64_t)blockIdx.y * kMatchCols;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int i = threadIdx.x; i < kMatchCols * W; i += blockDim.x) {
+    const int cc = i / W, w = i % W;
+    qw[i] = (c0 + cc < d3) ? qwords[(int64_t)w * d3 + c0 + cc] : 0ull;
+  }
+  if (threadIdx.x < kMatchCols) any_flag[threadIdx.x] = 0;
+  __syncthreads();
+  int ov[kMatchCols];
+#pragma unroll
+  for (int cc = 0; cc < kMatchCols; ++cc) ov[cc] = 0;
+  if (r < rows) {
+    for (int w = 0; w < W; ++w) {
+      const uint64_t dw = dbwords[(int64_t)w * rows + r];
+#pragma unroll
+      for (int cc = 0; cc < kMatchCols; ++cc) ov[cc] += __popcll(qw[cc * W + w] & dw);
+    }
+  }
+  const int64_t lhs_scale = t_den, rhs_scale = (int64_t)t_den - 2 * (int64_t)t_num;
+#pragma unroll
+  for (int cc = 0; cc < kMatchCols; ++cc) {
+    const int64_t c = c0 + cc;
+    if (r < rows && c < d3) {
+      const int64_t x = ip[c * rows + r];
+      const bool dec = ov[cc] > 0 && x * lhs_scale > rhs_scale * ov[cc];
+      if (decision) decision[c * rows + r] = dec ? 1 : 0;
+      if (dec) any_flag[cc] = 1;  // benign race: every writer stores 1
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kMatchCols && c0 + threadIdx.x < d3)
+    part[(c0 + threadIdx.x) * gridDim.x + blockIdx.x] = (uint8_t)any_flag[threadIdx.x];
+}
+
+// eye_match[e] = OR of part[c][b] over its columns c and row blocks b.
+__global__ void k_eye_any(const uint8_t* part, int64_t n_eyes, int32_t n_shifts, int32_t nb,
+                          uint8_t* eye_match) {
+  const int64_t e = blockIdx.x;
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  const int64_t total = (int64_t)n_shifts * nb;
+  int mine = 0;
+  for (int64_t i = threadIdx.x; i < total; i += blockDim.x) mine |= part[e * total + i];
+  if (mine) flag = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) eye_match[e] = (uint8_t)flag;
+}
+
+hipError_t launch_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eyes,
+                        const int32_t* shifts, int32_t n_shifts, const uint8_t* db_masks,
+                        int64_t rows, int32_t d2, uint32_t t_num, uint32_t t_den, uint64_t* qwords,
+                        uint64_t* dbwords, uint8_t* decision, uint8_t* part, uint8_t* eye_match,
+                        hipStream_t s) {
+  if (n_shifts < 1 || n_shifts > kMaxShifts) return hipErrorInvalidValue;
+  const int32_t W = (d2 + 63) / 64;
+  const int64_t d3 = n_eyes * n_shifts;
+  Shifts sh{}, zero{};
+  for (int i = 0; i < n_shifts; ++i) sh.r[i] = shifts[i];
+  hipLaunchKernelGGL(k_pack_masks, dim3((unsigned)((d3 + 255) / 256), (unsigned)W), dim3(256), 0, s,
+                     q_masks, n_eyes, d2, sh, n_shifts, W, qwords);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pack_masks, dim3((unsigned)((rows + 255) / 256), (unsigned)W), dim3(256), 0, s,
+                     db_masks, rows, d2, zero, 1, W, dbwords);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned nb = (unsigned)((rows + 255) / 256);
+  const size_t lds = sizeof(uint64_t) * kMatchCols * W;
+  if (lds > 65536) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_match),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_match, dim3(nb, (unsigned)((d3 + kMatchCols - 1) / kMatchCols)), dim3(256), lds, s,
+                     ip, qwords, dbwords, d3, rows, W, t_num, t_den, decision, part);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eye_any, dim3((unsigned)n_eyes), dim3(256), 0, s, part, n_eyes, n_shifts,
+                     (int32_t)nb, eye_match);
+  return hipGetLastError();
+}
+
+}  // namespace hfe

@@ -1,0 +1,348 @@
+// Negacyclic NTT (LDS-resident, ring degrees up to 2^14) and the kernels built on it:
+// secret-key transforms, T = M_DB S_Q, database and query encryption, decryption products.
+//
+// Products in R_n = Z[X]/(X^n + 1) mod a 36-bit prime q (Section 2.2.1) are computed as
+// INTT(NTT(a) . NTT(s)) with the merged negacyclic transforms of Longa and Naehrig (2016):
+// forward Cooley-Tukey with twiddles psi^brv(i) (output in bit-reversed order), inverse
+// Gentleman-Sande with psi^-brv(i) and a final 1/n scale.  Twiddle products use Shoup's
+// precomputed quotients.  One workgroup transforms one polynomial held in LDS
+// (2^14 x 8 bytes = 128 KiB fits the 160 KiB LDS of a gfx950 CU).
+#include "hfe_internal.h"
+
+namespace hfe {
+
+constexpr int kNttThreads = 1024;
+
+__device__ __forceinline__ void ntt_fwd_lds(uint64_t* a, const NttTab& T) {
+  const int n = 1 << T.logn;
+  const uint64_t q = T.q;
+  for (int m = 1, logt = T.logn - 1; m < n; m <<= 1, --logt) {
+    const int t = 1 << logt;
+    for (int idx = threadIdx.x; idx < (n >> 1); idx += blockDim.x) {
+      const int i = idx >> logt;
+      const int j1 = (i << (logt + 1)) + (idx & (t - 1));
+      const uint64_t S = T.psi[m + i], Ssh = T.psi_sh[m + i];
+      const uint64_t U = a[j1];
+      const uint64_t V = mul_shoup(a[j1 + t], S, Ssh, q);
+      a[j1] = add_mod(U, V, q);
+      a[j1 + t] = sub_mod(U, V, q);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void ntt_inv_lds(uint64_t* a, const NttTab& T) {
+  const int n = 1 << T.logn;
+  const uint64_t q = T.q;
+  for (int m = n >> 1, logt = 0; m >= 1; m >>= 1, ++logt) {
+    const int t = 1 << logt;
+    for (int idx = threadIdx.x; idx < (n >> 1); idx += blockDim.x) {
+      const int i = idx >> logt;
+      const int j1 = (i << (logt + 1)) + (idx & (t - 1));
+      const uint64_t S = T.ipsi[m + i], Ssh = T.ipsi_sh[m + i];
+      const uint64_t U = a[j1], V = a[j1 + t];
+      a[j1] = add_mod(U, V, q);
+      a[j1 + t] = mul_shoup(sub_mod(U, V, q), S, Ssh, q);
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x)
+    a[idx] = mul_shoup(a[idx], T.n_inv, T.n_inv_sh, q);
+  __syncthreads();
+}
+
+// a <- a . w pointwise, w given with its Shoup companions w_sh (both n entries).
+__device__ __forceinline__ void pointwise_lds(uint64_t* a, const uint64_t* w, const uint64_t* w_sh,
+                                              int n, uint64_t q) {
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x)
+    a[idx] = mul_shoup(a[idx], w[idx], w_sh[idx], q);
+  __syncthreads();
+}
+
+static int ntt_block(int logn) {
+  int half = 1 << (logn > 0 ? logn - 1 : 0);
+  int b = half < 64 ? 64 : half;
+  return b > kNttThreads ? kNttThreads : b;
+}
+
+template <class K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// ------------------------------------------------------------------ batch forward NTT
+
+__global__ void __launch_bounds__(kNttThreads) k_ntt_fwd(uint64_t* a, int64_t stride, NttTab T,
+                                                          int with_shoup) {
+  extern __shared__ uint64_t lds[];
+  const int n = 1 << T.logn;
+  uint64_t* poly = a + (int64_t)blockIdx.x * stride;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = poly[i];
+  __syncthreads();
+  ntt_fwd_lds(lds, T);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint64_t v = lds[i];
+    poly[i] = v;
+    if (with_shoup) poly[n + i] = shoup_quot(v, T.q);
+  }
+}
+
+hipError_t launch_ntt_fwd(uint64_t* a, int64_t count, int64_t stride, NttTab tab, bool with_shoup,
+                          hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const size_t lds = sizeof(uint64_t) << tab.logn;
+  hipError_t e = allow_lds(k_ntt_fwd, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ntt_fwd, dim3((unsigned)count), dim3(ntt_block(tab.logn)), lds, s, a, stride, tab,
+                     with_shoup ? 1 : 0);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ T = M_DB S_Q
+// Row i of T is sum_j s~_j * m_i^(j) in R_{N_Q} (s~_j(X) = s_j(1/X), m_i^(j) = chunk j of
+// row i).  Exact integers with |T| <= d2 < q_0 / 2, so one prime suffices; the sum is
+// accumulated in the NTT domain in registers.  Output row-major T[i][v] (int32).
+
+constexpr int kTAccMax = 16;  // (2^14 / 1024) NTT-domain coefficients per thread
+
+__global__ void __launch_bounds__(kNttThreads)
+k_db_T(const int8_t* m_db, int32_t d2, const uint64_t* sconj_hat, int k, NttTab T, int32_t* Trow) {
+  extern __shared__ uint64_t lds[];
+  const int n = 1 << T.logn;
+  const int64_t i = blockIdx.x;
+  const uint64_t q = T.q;
+  uint64_t acc[kTAccMax];
+#pragma unroll
+  for (int r = 0; r < kTAccMax; ++r) acc[r] = 0;
+  for (int j = 0; j < k; ++j) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      const int64_t col = (int64_t)j * n + t;
+      const int8_t m = col < d2 ? m_db[i * d2 + col] : (int8_t)0;
+      lds[t] = m == 1 ? 1 : (m == -1 ? q - 1 : 0);
+    }
+    __syncthreads();
+    ntt_fwd_lds(lds, T);
+    const uint64_t* w = sconj_hat + (int64_t)j * 2 * n;
+    const uint64_t* wsh = w + n;
+#pragma unroll
+    for (int r = 0; r < kTAccMax; ++r) {
+      const int t = threadIdx.x + r * blockDim.x;
+      if (t < n) acc[r] = add_mod(acc[r], mul_shoup(lds[t], w[t], wsh[t], q), q);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kTAccMax; ++r) {
+    const int t = threadIdx.x + r * blockDim.x;
+    if (t < n) lds[t] = acc[r];
+  }
+  __syncthreads();
+  ntt_inv_lds(lds, T);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) Trow[i * n + t] = (int32_t)centered(lds[t], q);
+}
+
+__global__ void k_transpose_i32(const int32_t* in, int64_t rows, int64_t cols, int32_t* out) {
+  __shared__ int32_t tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+    const int64_t r = r0 + y, c = c0 + threadIdx.x;
+    if (r < rows && c < cols) tile[y][threadIdx.x] = in[r * cols + c];
+  }
+  __syncthreads();
+  for (int y = threadIdx.y; y < 32; y += blockDim.y) {
+    const int64_t c = c0 + y, r = r0 + threadIdx.x;
+    if (r < rows && c < cols) out[c * rows + r] = tile[threadIdx.x][y];
+  }
+}
+
+hipError_t launch_db_T(const int8_t* m_db, int64_t d1, int32_t d2, const uint64_t* sconj_hat, int k,
+                       NttTab tab_q0, int32_t* Trow, int32_t* Tt, hipStream_t s) {
+  if (d1 <= 0) return hipSuccess;
+  const int n = 1 << tab_q0.logn;
+  const size_t lds = sizeof(uint64_t) * n;
+  hipError_t e = allow_lds(k_db_T, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_db_T, dim3((unsigned)d1), dim3(ntt_block(tab_q0.logn)), lds, s, m_db, d2,
+                     sconj_hat, k, tab_q0, Trow);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)((n + 31) / 32), (unsigned)((d1 + 31) / 32));
+  hipLaunchKernelGGL(k_transpose_i32, grid, dim3(32, 8), 0, s, Trow, d1, (int64_t)n, Tt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ database encryption
+// One workgroup per column c of D (one a-polynomial): a_c uniform (stream DBA, element
+// (v, c)), then for each database chunk j the product s'_j * a_c, and for database rows i of
+// chunk j: B[i][c] = -(s'_j a_c)[i - j N_DB] + p * plain[i][c] + e(i, c) (stream DBE).
+// plain = M_DB for c < d2, T for c >= d2.  Column c of D is stored contiguously: Dt[c][row].
+
+__global__ void __launch_bounds__(kNttThreads)
+k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, const uint64_t* sdb_hat) {
+  extern __shared__ uint64_t lds[];
+  const int n = 1 << T.logn;
+  const int64_t c = blockIdx.x;
+  const uint64_t q = M.q;
+  uint64_t* col = Dt + c * A.R;
+  const uint64_t key_a = stream_tag(kDbA, prime_id);
+  for (int v4 = threadIdx.x; v4 < (n + 3) / 4; v4 += blockDim.x) {
+    const Philox4 b = philox4x64_10(A.seed, key_a, (uint64_t)v4, (uint64_t)c, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int v = 4 * v4 + j;
+      if (v < n) {
+        const uint64_t w = b.v[j];
+        const uint64_t x = w < M.bound ? barrett64(w, q, M.mu)
+                                       : uniform_at(A.seed, key_a, (uint64_t)v, (uint64_t)c, M);
+        lds[v] = x;
+        col[v] = x;
+      }
+    }
+  }
+  __syncthreads();
+  const uint64_t pm = barrett64(A.p, q, M.mu);
+  const uint64_t key_e = stream_tag(kDbE, 0);
+  const int chunks = (int)((A.d1 + n - 1) / n);
+  for (int j = 0; j < chunks; ++j) {
+    if (j) {
+      for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = col[v];
+      __syncthreads();
+    }
+    ntt_fwd_lds(lds, T);
+    pointwise_lds(lds, sdb_hat + (int64_t)j * 2 * n, sdb_hat + (int64_t)j * 2 * n + n, n, q);
+    ntt_inv_lds(lds, T);
+    const int64_t lo = (int64_t)j * n;
+    const int64_t hi = lo + n < A.d1 ? lo + n : A.d1;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const int32_t pl = c < A.d2 ? (int32_t)A.MT[c * A.d1 + i] : A.Tt[(c - A.d2) * A.d1 + i];
+      const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)i, (uint64_t)c, A.cdt);
+      const uint64_t ppl = pl >= 0 ? barrett64(pm * (uint64_t)pl, q, M.mu)
+                                   : sub_mod(0, barrett64(pm * (uint64_t)(-pl), q, M.mu), q);
+      uint64_t val = sub_mod(ppl, lds[i - lo], q);
+      val = add_mod(val, from_signed(e, q, M.mu), q);
+      col[n + i] = val;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_db_encrypt(const DbEncArgs& a, uint64_t* Dt_prime, uint32_t prime_id, const Mod& m,
+                             NttTab tab_db, const uint64_t* sdb_hat_prime, hipStream_t s) {
+  if (a.K <= 0) return hipSuccess;
+  const size_t lds = sizeof(uint64_t) << tab_db.logn;
+  hipError_t e = allow_lds(k_db_encrypt, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_db_encrypt, dim3((unsigned)a.K), dim3(ntt_block(tab_db.logn)), lds, s, a,
+                     Dt_prime, prime_id, m, tab_db, sdb_hat_prime);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ query encryption
+// One workgroup per query column c: a_c uniform in R_{N_Q} (stream QA, element (t, c)), and
+// for each chunk j of N_Q code rows b[t] = -(s_j a_c)[t - j N_Q] + Delta m[c][t] + e(t, c).
+// Output row c of XT: [b_c (d2) | a_c (N_Q)].
+
+__global__ void __launch_bounds__(kNttThreads)
+k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, NttTab T,
+            const uint64_t* s_hat) {
+  extern __shared__ uint64_t lds[];
+  const int n = 1 << T.logn;
+  const int64_t c = blockIdx.x;
+  const uint64_t q = M.q;
+  uint64_t* row = XT + c * A.K;
+  uint64_t* arow = row + A.d2;
+  const uint64_t key_a = stream_tag(kQA, prime_id);
+  for (int t4 = threadIdx.x; t4 < (n + 3) / 4; t4 += blockDim.x) {
+    const Philox4 b = philox4x64_10(A.seed, key_a, (uint64_t)t4, (uint64_t)c, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = 4 * t4 + j;
+      if (t < n) {
+        const uint64_t w = b.v[j];
+        const uint64_t x = w < M.bound ? barrett64(w, q, M.mu)
+                                       : uniform_at(A.seed, key_a, (uint64_t)t, (uint64_t)c, M);
+        lds[t] = x;
+        arow[t] = x;
+      }
+    }
+  }
+  __syncthreads();
+  const uint64_t key_e = stream_tag(kQE, 0);
+  const int8_t* m = A.m_q + c * A.d2;
+  for (int j = 0; j < A.k; ++j) {
+    if (j) {
+      for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = arow[t];
+      __syncthreads();
+    }
+    ntt_fwd_lds(lds, T);
+    pointwise_lds(lds, s_hat + (int64_t)j * 2 * n, s_hat + (int64_t)j * 2 * n + n, n, q);
+    ntt_inv_lds(lds, T);
+    const int64_t lo = (int64_t)j * n;
+    const int64_t hi = lo + n < A.d2 ? lo + n : A.d2;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+      const int8_t mv = m[t];
+      const uint64_t dm = mv == 1 ? delta : (mv == -1 ? (delta ? q - delta : 0) : 0);
+      const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)t, (uint64_t)c, A.cdt);
+      uint64_t val = sub_mod(dm, lds[t - lo], q);
+      val = add_mod(val, from_signed(e, q, M.mu), q);
+      row[t] = val;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prime_id, const Mod& m,
+                            uint64_t delta_mod, NttTab tab_q, const uint64_t* s_hat_prime,
+                            hipStream_t s) {
+  if (a.d3 <= 0) return hipSuccess;
+  const size_t lds = sizeof(uint64_t) << tab_q.logn;
+  hipError_t e = allow_lds(k_q_encrypt, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_q_encrypt, dim3((unsigned)a.d3), dim3(ntt_block(tab_q.logn)), lds, s, a,
+                     XT_prime, prime_id, m, delta_mod, tab_q, s_hat_prime);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ decryption products
+// Workgroup (c, j): y[c][r] = B_out[c][r] + (s'_j * A_out[c])[(row0 + r) - j N_DB] for the
+// selected rows r whose database row row0 + r lies in chunk j.
+
+__global__ void __launch_bounds__(kNttThreads)
+k_dec_products(const uint64_t* out, int64_t R_out, int64_t row0, int64_t rows, NttTab T,
+               const uint64_t* sdb_hat, int j0, uint64_t* y) {
+  extern __shared__ uint64_t lds[];
+  const int n = 1 << T.logn;
+  const int64_t c = blockIdx.x;
+  const int j = j0 + (int)blockIdx.y;
+  const uint64_t q = T.q;
+  const uint64_t* ocol = out + c * R_out;
+  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = ocol[v];
+  __syncthreads();
+  ntt_fwd_lds(lds, T);
+  pointwise_lds(lds, sdb_hat + (int64_t)j * 2 * n, sdb_hat + (int64_t)j * 2 * n + n, n, q);
+  ntt_inv_lds(lds, T);
+  int64_t lo = (int64_t)j * n - row0, hi = lo + n;
+  if (lo < 0) lo = 0;
+  if (hi > rows) hi = rows;
+  for (int64_t r = lo + threadIdx.x; r < hi; r += blockDim.x)
+    y[c * rows + r] = add_mod(ocol[n + r], lds[row0 + r - (int64_t)j * n], q);
+}
+
+hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,
+                               int64_t rows, int n_db_log, NttTab tab, const uint64_t* sdb_hat_prime,
+                               int k_db, uint64_t* y_prime, hipStream_t s) {
+  if (d3 <= 0 || rows <= 0) return hipSuccess;
+  const int64_t n = 1ll << n_db_log;
+  const int j0 = (int)(row0 / n), j1 = (int)((row0 + rows - 1) / n);
+  if (j1 >= k_db) return hipErrorInvalidValue;
+  const size_t lds = sizeof(uint64_t) << tab.logn;
+  hipError_t e = allow_lds(k_dec_products, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dec_products, dim3((unsigned)d3, (unsigned)(j1 - j0 + 1)), dim3(ntt_block(tab.logn)),
+                     lds, s, out_prime, R_out, row0, rows, tab, sdb_hat_prime, j0, y_prime);
+  return hipGetLastError();
+}
+
+}  // namespace hfe
