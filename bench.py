@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Encrypted 1:N iris matching on one MI355X: code comparisons per second.
+
+One step is one pass of the hot path over a batch of 32 query eyes x 16 cyclic shifts
+(512 query columns) against the resident encrypted database of 14,336 codes of 12,800 bits
+(N_DB = 2^14, N_Q = 2^13, three query primes plus the special prime):
+
+    masked ternary encoding of the shifted query templates -> query encryption ->
+    CCMM (centered lift + digit split, int8-MFMA contraction, rescale) -> decryption and
+    decoding -> threshold decision per pair and match per eye.
+
+The database is encrypted once before timing and stays in HBM.  Inputs (template bits) are
+resident in HBM before the timed region.  The metric counts query columns x database codes
+(every shift is one comparison).  The same step with the plain uint64 contraction is timed
+for comparison, and the contraction kernel is timed with HIP events on its stream inside
+every timed step for the roofline figure.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import hfe_synth as S  # noqa: E402
+
+PEAK_I8_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
+KEY_SEED, DB_SEED, Q_SEED = 11, 22, 33
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_work(w: S.Workload):
+    n_db, n_q = 1 << w.log_n_db, 1 << w.log_n_q
+    R_out = n_db + w.d1
+    K = w.d2 + n_q
+    W = R_out * K * w.d3 * (w.level + 1)          # residue multiply-adds per CCMM
+    return dict(R_out=R_out, K=K, residue_macs=W, i8_ops=2 * 25 * W)
+
+
+def cpu_baseline(w: S.Workload, inp, rows_sample: int, cols_sample: int):
+    """The oracle's CCMM (lift, exact contraction, CRT rescale) on a slice of the workload."""
+    import torch
+    from oracle import ckks as OC
+    from oracle import iris as OI
+    from oracle import params as OP
+    from oracle import prng
+
+    P = OP.make_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
+    keys = OC.keygen(P, KEY_SEED)
+    qc, qm = OI.shifted_queries(inp["q_codes"][:1], inp["q_masks"][:1], inp["shifts"][:cols_sample])
+    mq = OI.ternary(qc, qm)
+    XT = OC.encrypt_query(keys, mq, w.level, Q_SEED)
+    # database rows of the sample: the first rows of D (A-part), drawn from the database stream
+    log_rows = int(np.log2(rows_sample))
+    Ps = OP.Params(log_n_db=log_rows, log_n_q=P.log_n_q, q=P.q, p=P.p, d2=P.d2, max_db_rows=P.max_db_rows)
+    D = {pid: prng.uniform_matrix(DB_SEED, prng.DBA, pid, rows_sample, P.K, prime)
+         for pid, prime in OC.prime_ids(P, len(P.q))}
+    t0 = time.perf_counter()
+    OC.ccmm(Ps, D, XT, w.level, 0, 0)
+    dt = time.perf_counter() - t0
+    work = algorithmic_work(w)
+    # the full step needs R_out x d3 output residues per prime for d1 x d3 comparisons
+    cmp_per_s = w.d1 * rows_sample * cols_sample / (dt * work["R_out"])
+    return dict(value=cmp_per_s, unit="comparisons/s", cores=1, kind="oracle",
+                sample=(f"oracle CCMM (centered CRT lift, exact int64-limb contraction, CRT rescale) of "
+                        f"{rows_sample} database rows x {cols_sample} query columns x full K={P.K} x "
+                        f"{w.level + 1} primes in {dt:.1f} s, scaled by rows {rows_sample}/{work['R_out']}; "
+                        f"encryption and decryption not included; numpy int64 products, 1 thread "
+                        f"(torch threads available: {torch.get_num_threads()})"),
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--workload", default=S.PAPER_SHARE.name, choices=sorted(S.WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=1024)
+    ap.add_argument("--cpu-cols", type=int, default=32)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU layout "
+                                   "(database-row shards with a broadcast of the A-part result) is not built"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2601_17561_amd as H
+
+    w = S.WORKLOADS[args.workload]
+    work = algorithmic_work(w)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    log(f"workload {w.name}: d1={w.d1} d2={w.d2} d3={w.d3} N_DB=2^{w.log_n_db} N_Q=2^{w.log_n_q} "
+        f"primes={w.level}+p")
+    inp = S.make_inputs(w)
+    P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
+    keys = H.hfe_keygen(P, KEY_SEED)
+    db_codes = torch.from_numpy(inp["db_codes"]).to(dev)
+    db_masks = torch.from_numpy(inp["db_masks"]).to(dev)
+    q_codes = torch.from_numpy(inp["q_codes"]).to(dev)
+    q_masks = torch.from_numpy(inp["q_masks"]).to(dev)
+    shifts = [int(s) for s in inp["shifts"]]
+    log("encrypting the database (both forms)")
+    t0 = time.perf_counter()
+    m_db = H.hfe_encode(db_codes, db_masks, [0])
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA)
+    torch.cuda.synchronize()
+    t_db = time.perf_counter() - t0
+    del m_db
+    log(f"database encrypted in {t_db:.2f} s")
+
+    def step(form, profile_out=None):
+        m_q = H.hfe_encode(q_codes, q_masks, shifts)
+        qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+        r = H.hfe_ccmm(db, qct, 0, w.d1, form)
+        _, ip = H.hfe_decrypt(keys, r, v=False)
+        _, eye = H.hfe_match(ip, q_masks, shifts, db_masks, want_decision=False)
+        if profile_out is not None:
+            profile_out.append(r)
+        else:
+            r.free()
+        qct.free()
+        return ip, eye
+
+    results = {}
+    for name, form, steps, warm in (("i8", H.HFE_FORM_I8_MFMA, args.steps, args.warmup),
+                                    ("plain", H.HFE_FORM_PLAIN_U64, args.plain_steps, 1)):
+        for _ in range(warm):
+            step(form)
+        torch.cuda.synchronize()
+        H.hfe_profile(True)
+        prof = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ip, eye = step(form, prof)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        H.hfe_profile(False)
+        stages = np.array([H.hfe_profile_ms(r, 3) for r in prof])
+        for r in prof:
+            r.free()
+        ms = dt * 1e3 / steps
+        results[name] = dict(ms_per_step=ms, comparisons_per_s=w.d1 * w.d3 / (dt / steps),
+                             lift_ms=float(stages[:, 0].mean()), contraction_ms=float(stages[:, 1].mean()),
+                             rescale_ms=float(stages[:, 2].mean()), ip=ip, eye=eye)
+        log(f"{name}: {ms:.2f} ms/step, contraction {results[name]['contraction_ms']:.2f} ms "
+            f"(lift {results[name]['lift_ms']:.2f}, rescale {results[name]['rescale_ms']:.2f})")
+
+    same = bool(torch.equal(results["i8"]["ip"], results["plain"]["ip"]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample")
+        cpu = cpu_baseline(w, inp, args.cpu_rows, args.cpu_cols)
+        cpu.pop("seconds")
+
+    i8 = results["i8"]
+    achieved = work["i8_ops"] / (i8["contraction_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": "encrypted query x db code comparisons/sec on 1 MI355X, int8-MFMA vs plain",
+        "value": i8["comparisons_per_s"],
+        "unit": "comparisons/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": i8["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_db": 1 << w.log_n_db, "n_q": 1 << w.log_n_q,
+                   "query_primes": w.level, "special_primes": 1, "prime_bits": 36, "d1": w.d1, "d2": w.d2,
+                   "eyes": w.eyes, "shifts": w.n_shifts, "d3": w.d3, "form": "i8_mfma",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_I8_TOPS, "unit": "TOP/s",
+                     "frac": achieved / PEAK_I8_TOPS, "traffic": None,
+                     "kernel": "k_gemm_i8", "ops_per_launch": work["i8_ops"],
+                     "kernel_ms": i8["contraction_ms"]},
+        "plain": {"ms_per_step": results["plain"]["ms_per_step"],
+                  "comparisons_per_s": results["plain"]["comparisons_per_s"],
+                  "contraction_ms": results["plain"]["contraction_ms"],
+                  "residue_macs_per_s": work["residue_macs"] / (results["plain"]["contraction_ms"] * 1e-3)},
+        "i8_over_plain_step": results["plain"]["ms_per_step"] / i8["ms_per_step"],
+        "stages_ms": {"lift_split": i8["lift_ms"], "contraction": i8["contraction_ms"], "rescale": i8["rescale_ms"]},
+        "i8_equals_plain_ip": same,
+        "db_encrypt_s": t_db,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,18 +143,29 @@ hfe_status hfe_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eyes,
                      int64_t rows, int32_t d2, uint32_t t_num, uint32_t t_den,
                      uint8_t* decision, uint8_t* eye_match, void* stream);
 
-/* Export residues to host memory for parity checks (synchronous; waits for the handle's
- * producing work).  `which` selects an array; the canonical orders are
- *   keys  0: query secrets    k  x N_Q  (int64 two's complement in uint64)
- *         1: database secrets k' x N_DB
- *   db    0: D per prime      [prime (q_0..q_{L-1}, p)][row < N_DB + d1][col < d2 + N_Q]
+/* Export residues to host memory for parity checks (synchronous: waits for the device).
+ * `which` selects an array; elements [offset, offset + n) of its canonical order are copied
+ * to the host array dst.  Canonical orders:
+ *   keys  0: query secrets    [j < k][t < N_Q]      (int64 two's complement in uint64)
+ *         1: database secrets [j < k'][t < N_DB]
+ *   db    0: D per prime, column-major: [prime (q_0..q_{L-1}, p)][col < d2 + N_Q][row < N_DB + d1]
+ *            (available when the database was prepared for HFE_FORM_PLAIN_U64)
  *   qct   0: query            [prime < level][column < d3][b_c (d2) | a_c (N_Q)]
  *   rct   0: result           [prime < level][column < d3][A_out (N_DB) | B_out (rows)]
- * If dst is NULL, *count receives the number of elements; otherwise n must equal it. */
-hfe_status hfe_export(const void* handle, int32_t which, uint64_t* dst, size_t n, size_t* count);
+ * If dst is NULL, *count receives the total number of elements and nothing is copied. */
+hfe_status hfe_export(const void* handle, int32_t which, size_t offset, uint64_t* dst, size_t n,
+                      size_t* count);
 
 /* Shape queries of a handle (host): dims[0..3] = {level or L, d3 or d1, rows, K}. */
 hfe_status hfe_shape(const void* handle, int64_t* dims);
+
+/* Stage timing for measurement.  hfe_profile(1) makes later hfe_ccmm calls record HIP events on
+ * their stream around each stage (0: lift and digit split, 1: contraction kernel, 2: rescale);
+ * hfe_profile_ms(result, ms, n) waits for those events and writes the first n (<= 3) stage
+ * durations in milliseconds to host array ms.  HFE_EINVAL if the result was made without
+ * profiling. */
+hfe_status hfe_profile(int32_t enable);
+hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n);
 
 /* Release any handle (NULL-safe).  Waits for work that uses it on its stream. */
 void hfe_free(void* handle);

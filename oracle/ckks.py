@@ -223,3 +223,81 @@ def decrypt(keys: Keys, out: Dict[int, np.ndarray], level: int, row0: int, rows:
             v[c][r] = Fraction(yc, delta)
             ip[c, r] = (2 * yc + delta) // (2 * delta)
     return v, ip
+
+
+# ---------------------------------------------------------------- single entries (large sizes)
+# The functions below evaluate the same definitions one entry or one column at a time, for
+# workloads too large to materialise (checks on sampled entries).
+
+def negmul_vec(s: np.ndarray, a: np.ndarray) -> np.ndarray:
+    """Schoolbook s * a in Z[X]/(X^n + 1): sum over u of s_u X^u a, where X^u a shifts a up by
+    u places and negates the u coefficients that wrap past degree n - 1."""
+    n = len(a)
+    a = np.asarray(a, dtype=np.int64)
+    out = np.zeros(n, dtype=np.int64)
+    for u in np.nonzero(s)[0]:
+        shifted = np.roll(a, u)
+        shifted[:u] = -shifted[:u]
+        out += int(s[u]) * shifted
+    return out
+
+
+def s_q_column(keys: Keys, v: int) -> np.ndarray:
+    """Column v of S_Q (d2 entries): rows of chunk j are Neg(s_j)[t][v]."""
+    P = keys.params
+    n = P.n_q
+    t = np.arange(P.d2)
+    j, tt = t // n, t % n
+    d = tt - v
+    s = keys.s[j, d % n]
+    return np.where(d >= 0, s, -s).astype(np.int64)
+
+
+def db_entry(keys: Keys, m_db: np.ndarray, seed: int, pid: int, prime: int, r: int, c: int) -> int:
+    """D[r][c] mod prime of the database ciphertext (r < N_DB: A-part, else code row r - N_DB)."""
+    P = keys.params
+    if r < P.n_db:
+        return int(prng.uniform_mod(seed, prng.DBA, pid, [r], [c], prime)[0])
+    i = r - P.n_db
+    a_c = prng.uniform_mod(seed, prng.DBA, pid, np.arange(P.n_db), c, prime)
+    sa = int(imatmul(s_db_rows(keys, [i]), a_c.reshape(-1, 1))[0, 0])
+    if c < P.d2:
+        plain = int(m_db[i, c])
+    else:
+        plain = int(imatmul(m_db[i].astype(np.int64).reshape(1, -1),
+                            s_q_column(keys, c - P.d2).reshape(-1, 1))[0, 0])
+    e = int(prng.gaussian(seed, prng.DBE, 0, [i], [c])[0])
+    return (-sa + P.p * plain + e) % prime
+
+
+def query_column(keys: Keys, m_q_row: np.ndarray, level: int, seed: int, c: int) -> Dict[int, np.ndarray]:
+    """Row c of XT per query prime i: [b_c | a_c] of query column c (m_q_row = its d2 entries)."""
+    P = keys.params
+    n = P.n_q
+    delta = P.delta(level)
+    e = prng.gaussian(seed, prng.QE, 0, np.arange(P.d2), c)
+    out = {}
+    for i in range(level):
+        qi = P.q[i]
+        a = prng.uniform_mod(seed, prng.QA, i, np.arange(n), c, qi)
+        b = np.empty(P.d2, dtype=np.int64)
+        for j in range(P.k):
+            lo, hi = j * n, min((j + 1) * n, P.d2)
+            sa = negmul_vec(keys.s[j], a)
+            b[lo:hi] = (-sa[:hi - lo] + (delta % qi) * m_q_row[lo:hi].astype(np.int64) + e[lo:hi]) % qi
+        out[i] = np.concatenate([b, a])
+    return out
+
+
+def ccmm_entry(P: Params, d_row: Dict[int, List[int]], xt_col: Dict[int, np.ndarray], level: int) -> List[int]:
+    """Result residues (per query prime) of one output entry: RS_p of sum_k D[r][k] L(x)[k],
+    given row r of D per prime stream id and the query column's residues."""
+    moduli = [P.q[i] for i in range(level)]
+    Q = P.Q(level)
+    K = len(xt_col[0])
+    L = [centered(crt([int(xt_col[i][k]) for i in range(level)], moduli), Q) for k in range(K)]
+    ids = prime_ids(P, level)
+    res = [sum(int(d_row[pid][k]) * (L[k] % prime) for k in range(K)) % prime for pid, prime in ids]
+    x = crt(res, [m for _, m in ids])
+    y = rescale_p(x, P.p, Q)
+    return [y % qi for qi in moduli]

@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "HFE_OK", -1: "HFE_EINVAL", -2: "HFE_ESHAPE", -3: "HFE_ELEVEL
 
 EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode", "hfe_encrypt_db",
             "hfe_encrypt", "hfe_ccmm", "hfe_decrypt", "hfe_match", "hfe_export", "hfe_shape", "hfe_free",
-            "hfe_last_error", "hfe_cdt_table")
+            "hfe_last_error", "hfe_cdt_table", "hfe_profile", "hfe_profile_ms")
 
 
 class HfeError(RuntimeError):
@@ -72,9 +72,11 @@ _SIGS = {
     "hfe_ccmm": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_vp)],
     "hfe_decrypt": [_vp, _vp, _vp, _vp, _vp],
     "hfe_match": [_vp, _vp, _i64, ctypes.POINTER(_i32), _i32, _vp, _i64, _i32, _u32, _u32, _vp, _vp, _vp],
-    "hfe_export": [_vp, _i32, _vp, _sz, ctypes.POINTER(_sz)],
+    "hfe_export": [_vp, _i32, _sz, _vp, _sz, ctypes.POINTER(_sz)],
     "hfe_shape": [_vp, ctypes.POINTER(_i64)],
     "hfe_cdt_table": [_vp],
+    "hfe_profile": [_i32],
+    "hfe_profile_ms": [_vp, _vp, _i32],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -279,12 +281,25 @@ def hfe_match(ip, q_masks, shifts: Sequence[int], db_masks, t_num: int = 3, t_de
     return decision, eye_match
 
 
-def hfe_export(h: Handle, which: int = 0) -> np.ndarray:
-    n = _sz()
-    _check(_lib.hfe_export(h.ptr, which, None, 0, ctypes.byref(n)), "hfe_export")
-    out = np.empty(n.value, dtype=np.uint64)
-    _check(_lib.hfe_export(h.ptr, which, out.ctypes.data, n.value, None), "hfe_export")
+def hfe_export(h: Handle, which: int = 0, offset: int = 0, n: Optional[int] = None) -> np.ndarray:
+    """Elements [offset, offset + n) of the handle's canonical residue order (all by default)."""
+    total = _sz()
+    _check(_lib.hfe_export(h.ptr, which, 0, None, 0, ctypes.byref(total)), "hfe_export")
+    n = total.value - offset if n is None else n
+    out = np.empty(n, dtype=np.uint64)
+    _check(_lib.hfe_export(h.ptr, which, offset, out.ctypes.data, n, None), "hfe_export")
     return out
+
+
+def hfe_profile(enable: bool) -> None:
+    _check(_lib.hfe_profile(1 if enable else 0), "hfe_profile")
+
+
+def hfe_profile_ms(r: Handle, n: int = 3) -> list:
+    """Stage durations (ms) of a profiled hfe_ccmm: [lift + split, contraction, rescale][:n]."""
+    out = (ctypes.c_float * 3)()
+    _check(_lib.hfe_profile_ms(r.ptr, out, n), "hfe_profile_ms")
+    return [float(out[i]) for i in range(n)]
 
 
 def hfe_cdt_table() -> list:

@@ -2,6 +2,7 @@
 // memory and the enqueueing of the kernels for key generation, encryption, the CCMM,
 // decryption and the match decision.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -37,6 +38,7 @@ static hfe_status hip_fail(hipError_t e, const char* what) {
 
 // ------------------------------------------------------------------ allocator
 namespace {
+std::atomic<int> g_profile{0};
 std::mutex g_alloc_mu;
 hfe_alloc_fn g_alloc = nullptr;
 hfe_dealloc_fn g_dealloc = nullptr;
@@ -518,6 +520,11 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
 
   const int nz = level + 1;
   auto slot = [&](int z) { return z < level ? z : K->L; };
+  const bool prof = g_profile.load() != 0;
+  if (prof)
+    for (auto& e : R->ev) HFE_LAUNCH(hipEventCreate(&e));
+  auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(R->ev[i], s) : hipSuccess; };
+  HFE_LAUNCH(mark(0));
   DevBuf C, Xp, Xd;
   HFE_TRY(C.alloc(sizeof(uint64_t) * (size_t)nz * d3 * R_out, s));
   GemmArgs g;
@@ -544,6 +551,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
       g.Dt[z] = D->Dt.as<uint64_t>() + (size_t)slot(z) * D->K * D->R;
       g.X[z] = z < level ? Qc->XT.as<uint64_t>() + (size_t)z * d3 * D->K : Xp.as<uint64_t>();
     }
+    HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_plain(g, s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
@@ -554,8 +562,10 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
       g.Dd[z] = D->digits.as<int8_t>() + (size_t)slot(z) * kDigits * planeD;
       g.Xd[z] = Xd.as<int8_t>() + (size_t)z * kDigits * planeX;
     }
+    HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_i8(g, s));
   }
+  HFE_LAUNCH(mark(2));
   RescaleArgs ra;
   std::memset(&ra, 0, sizeof(ra));
   ra.level = level;
@@ -568,6 +578,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
   HFE_LAUNCH(launch_rescale(C.as<uint64_t>(), C.as<uint64_t>() + (size_t)level * d3 * R_out, d3 * R_out, ra,
                             R->out.as<uint64_t>(), s));
+  HFE_LAUNCH(mark(3));
   return HFE_OK;
 }
 
@@ -592,6 +603,22 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
     return st;
   }
   *out = R;
+  return HFE_OK;
+}
+
+hfe_status hfe_profile(int32_t enable) {
+  g_profile.store(enable ? 1 : 0);
+  return HFE_OK;
+}
+
+hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n) {
+  const hfe_rct* R = as_handle<hfe_rct>(r, kRct);
+  if (!R || !ms || n < 0 || n > 3) return fail(HFE_EINVAL, "invalid result handle or count");
+  if (!R->ev[0]) return fail(HFE_EINVAL, "result was produced without profiling");
+  for (int i = 0; i < n; ++i) {
+    HFE_LAUNCH(hipEventSynchronize(R->ev[i + 1]));
+    HFE_LAUNCH(hipEventElapsedTime(&ms[i], R->ev[i], R->ev[i + 1]));
+  }
   return HFE_OK;
 }
 
@@ -655,57 +682,46 @@ static hfe_status copy_out(const void* dev, void* dst, size_t bytes) {
   return HFE_OK;
 }
 
-hfe_status hfe_export(const void* handle, int32_t which, uint64_t* dst, size_t n, size_t* count) {
+hfe_status hfe_export(const void* handle, int32_t which, size_t offset, uint64_t* dst, size_t n,
+                      size_t* count) {
   if (!handle) return fail(HFE_EINVAL, "handle is NULL");
   const uint32_t kind = static_cast<const HandleBase*>(handle)->kind;
-  size_t need = 0;
+  size_t total = 0;
+  const void* dev = nullptr;
+  const int8_t* host8 = nullptr;
   if (kind == kKeys) {
     const hfe_keys* K = static_cast<const hfe_keys*>(handle);
-    const std::vector<int8_t>& src = which == 0 ? K->s_host : K->sdb_host;
     if (which != 0 && which != 1) return fail(HFE_EINVAL, "keys export: which must be 0 or 1");
-    need = src.size();
-    if (count) *count = need;
-    if (!dst) return HFE_OK;
-    if (n != need) return fail(HFE_ESHAPE, "export size mismatch");
-    for (size_t i = 0; i < need; ++i) dst[i] = (uint64_t)(int64_t)src[i];
-    return HFE_OK;
-  }
-  if (kind == kDb) {
+    const std::vector<int8_t>& src = which == 0 ? K->s_host : K->sdb_host;
+    total = src.size();
+    host8 = src.data();
+  } else if (kind == kDb) {
     const hfe_db* D = static_cast<const hfe_db*>(handle);
     if (which != 0) return fail(HFE_EINVAL, "db export: which must be 0");
-    const int np = D->keys->n_primes;
-    need = (size_t)np * D->R * D->K;
-    if (count) *count = need;
-    if (!dst) return HFE_OK;
-    if (n != need) return fail(HFE_ESHAPE, "export size mismatch");
-    if (!D->Dt.ptr) return fail(HFE_EINVAL, "database kept no uint64 residues (plain form not requested)");
-    std::vector<uint64_t> tmp(need);
-    HFE_TRY(copy_out(D->Dt.ptr, tmp.data(), need * 8));
-    for (int z = 0; z < np; ++z)
-      for (int64_t c = 0; c < D->K; ++c)
-        for (int64_t r = 0; r < D->R; ++r)
-          dst[((size_t)z * D->R + r) * D->K + c] = tmp[((size_t)z * D->K + c) * D->R + r];
-    return HFE_OK;
-  }
-  if (kind == kQct) {
+    total = (size_t)D->keys->n_primes * D->R * D->K;
+    dev = D->Dt.ptr;
+    if (dst && !dev) return fail(HFE_EINVAL, "database kept no uint64 residues (plain form not requested)");
+  } else if (kind == kQct) {
     const hfe_qct* Q = static_cast<const hfe_qct*>(handle);
     if (which != 0) return fail(HFE_EINVAL, "qct export: which must be 0");
-    need = (size_t)Q->level * Q->d3 * Q->K;
-    if (count) *count = need;
-    if (!dst) return HFE_OK;
-    if (n != need) return fail(HFE_ESHAPE, "export size mismatch");
-    return copy_out(Q->XT.ptr, dst, need * 8);
-  }
-  if (kind == kRct) {
+    total = (size_t)Q->level * Q->d3 * Q->K;
+    dev = Q->XT.ptr;
+  } else if (kind == kRct) {
     const hfe_rct* R = static_cast<const hfe_rct*>(handle);
     if (which != 0) return fail(HFE_EINVAL, "rct export: which must be 0");
-    need = (size_t)R->level * R->d3 * R->R_out;
-    if (count) *count = need;
-    if (!dst) return HFE_OK;
-    if (n != need) return fail(HFE_ESHAPE, "export size mismatch");
-    return copy_out(R->out.ptr, dst, need * 8);
+    total = (size_t)R->level * R->d3 * R->R_out;
+    dev = R->out.ptr;
+  } else {
+    return fail(HFE_EINVAL, "unknown handle");
   }
-  return fail(HFE_EINVAL, "unknown handle");
+  if (count) *count = total;
+  if (!dst) return HFE_OK;
+  if (offset > total || n > total - offset) return fail(HFE_ESHAPE, "export range outside the array");
+  if (host8) {
+    for (size_t i = 0; i < n; ++i) dst[i] = (uint64_t)(int64_t)host8[offset + i];
+    return HFE_OK;
+  }
+  return copy_out(static_cast<const uint64_t*>(dev) + offset, dst, n * sizeof(uint64_t));
 }
 
 hfe_status hfe_shape(const void* handle, int64_t* dims) {

@@ -143,6 +143,11 @@ struct hfe_rct : hfe::HandleBase {
   int level;
   int64_t d3, row0, rows, R_out;           // R_out = N_DB + rows
   hfe::DevBuf out;                         // [level][d3][R_out] uint64
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // stage boundaries when profiling
+  ~hfe_rct() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace hfe {

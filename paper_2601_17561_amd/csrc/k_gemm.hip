@@ -121,13 +121,23 @@ __device__ __forceinline__ uint64_t horner9(const int32_t a[9], uint64_t q, uint
   return r;
 }
 
+// Tile schedule: the workgroups of one launch are dealt round-robin to the 8 XCDs (each with its
+// own L2).  Workgroup i runs on XCD i % 8; its tile is chosen so that one XCD receives all
+// query-column tiles of a database-row tile back to back, hence the database digits of that
+// tile are fetched from HBM once into that XCD's L2 and shared by its query-column tiles.
+constexpr int kXcds = 8;
+
 __global__ void __launch_bounds__(256) k_gemm_i8(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) int8_t sA[kDigits][kIQ][kLdsRow];  // query digits
-  __shared__ __attribute__((aligned(16))) int8_t sB[kDigits][kIR][kLdsRow];  // database digits
+  __shared__ __attribute__((aligned(16))) int8_t sA[2][kDigits][kIQ][kLdsRow];  // query digits
+  __shared__ __attribute__((aligned(16))) int8_t sB[2][kDigits][kIR][kLdsRow];  // database digits
   const int z = blockIdx.z;
+  const int64_t n_ct = (g.d3 + kIQ - 1) / kIQ, n_rt = (g.R_out + kIR - 1) / kIR;
+  const int64_t wg = blockIdx.x, xcd = wg % kXcds, j = wg / kXcds;
+  const int64_t rt = (j / n_ct) * kXcds + xcd, ct = j % n_ct;
+  if (rt >= n_rt) return;
   const int8_t* __restrict__ Xd = g.Xd[z];
   const int8_t* __restrict__ Dd = g.Dd[z];
-  const int64_t r0 = (int64_t)blockIdx.x * kIR, c0 = (int64_t)blockIdx.y * kIQ;
+  const int64_t r0 = rt * kIR, c0 = ct * kIQ;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wq = wave & 1, wr = wave >> 1;
   // global -> LDS: thread loads 16 bytes (chunk tid & 3) of row (tid >> 2) of each digit plane
@@ -155,14 +165,16 @@ __global__ void __launch_bounds__(256) k_gemm_i8(GemmArgs g) {
       pa[t] = *reinterpret_cast<const v4i*>(gA + t * planeA + kb0 * stepA);
       pb[t] = *reinterpret_cast<const v4i*>(gB + t * planeB + kb0 * stepB);
     }
-    for (int64_t kb = kb0; kb < kb1; ++kb) {
 #pragma unroll
-      for (int t = 0; t < kDigits; ++t) {
-        *reinterpret_cast<v4i*>(&sA[t][ld_row][ld_chunk * 16]) = pa[t];
-        *reinterpret_cast<v4i*>(&sB[t][ld_row][ld_chunk * 16]) = pb[t];
-      }
-      __syncthreads();
-      if (kb + 1 < kb1) {
+    for (int t = 0; t < kDigits; ++t) {
+      *reinterpret_cast<v4i*>(&sA[kb0 & 1][t][ld_row][ld_chunk * 16]) = pa[t];
+      *reinterpret_cast<v4i*>(&sB[kb0 & 1][t][ld_row][ld_chunk * 16]) = pb[t];
+    }
+    __syncthreads();
+    for (int64_t kb = kb0; kb < kb1; ++kb) {
+      const int cur = (int)(kb & 1);
+      const bool more = kb + 1 < kb1;
+      if (more) {
         const size_t offA = (size_t)(kb + 1) * stepA, offB = (size_t)(kb + 1) * stepB;
 #pragma unroll
         for (int t = 0; t < kDigits; ++t) {
@@ -176,13 +188,20 @@ __global__ void __launch_bounds__(256) k_gemm_i8(GemmArgs g) {
         v4i a[kDigits];
 #pragma unroll
         for (int t = 0; t < kDigits; ++t)
-          a[t] = *reinterpret_cast<const v4i*>(&sA[t][wq * 32 + (lane & 31)][koff]);
+          a[t] = *reinterpret_cast<const v4i*>(&sA[cur][t][wq * 32 + (lane & 31)][koff]);
 #pragma unroll
         for (int s = 0; s < kDigits; ++s) {
-          const v4i b = *reinterpret_cast<const v4i*>(&sB[s][wr * 32 + (lane & 31)][koff]);
+          const v4i b = *reinterpret_cast<const v4i*>(&sB[cur][s][wr * 32 + (lane & 31)][koff]);
 #pragma unroll
           for (int t = 0; t < kDigits; ++t)
             acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[t], b, acc[s + t], 0, 0, 0);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int t = 0; t < kDigits; ++t) {
+          *reinterpret_cast<v4i*>(&sA[cur ^ 1][t][ld_row][ld_chunk * 16]) = pa[t];
+          *reinterpret_cast<v4i*>(&sB[cur ^ 1][t][ld_row][ld_chunk * 16]) = pb[t];
         }
       }
       __syncthreads();
@@ -190,12 +209,12 @@ __global__ void __launch_bounds__(256) k_gemm_i8(GemmArgs g) {
     // Recombine this K-chunk and accumulate it into the output (first chunk stores).
     if (out_r < g.R_out) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int64_t c = c0 + wq * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+      for (int jj = 0; jj < 16; ++jj) {
+        const int64_t c = c0 + wq * 32 + 8 * (jj >> 2) + 4 * (lane >> 5) + (jj & 3);
         if (c >= g.d3) continue;
         int32_t a9[9];
 #pragma unroll
-        for (int u = 0; u < 9; ++u) a9[u] = acc[u][j];
+        for (int u = 0; u < 9; ++u) a9[u] = acc[u][jj];
         uint64_t v = horner9(a9, m.q, m.mu);
         uint64_t* dst = C + c * g.R_out + out_r;
         if (kb0) v = add_mod(v, *dst, m.q);
@@ -207,7 +226,9 @@ __global__ void __launch_bounds__(256) k_gemm_i8(GemmArgs g) {
 
 hipError_t launch_gemm_i8(const GemmArgs& g, hipStream_t s) {
   if (g.R_out <= 0 || g.d3 <= 0) return hipSuccess;
-  dim3 grid((unsigned)((g.R_out + kIR - 1) / kIR), (unsigned)((g.d3 + kIQ - 1) / kIQ), (unsigned)g.nz);
+  const int64_t n_ct = (g.d3 + kIQ - 1) / kIQ, n_rt = (g.R_out + kIR - 1) / kIR;
+  const int64_t n_rt8 = (n_rt + kXcds - 1) / kXcds * kXcds;
+  dim3 grid((unsigned)(n_rt8 * n_ct), 1, (unsigned)g.nz);
   hipLaunchKernelGGL(k_gemm_i8, grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }

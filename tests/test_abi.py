@@ -99,9 +99,9 @@ def test_duplicate_primes_rejected():
 
 def test_null_arguments_rejected():
     lib = ctypes.CDLL(H.LIB_PATH)
-    lib.hfe_export.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
-                               ctypes.c_void_p]
-    assert lib.hfe_export(None, 0, None, 0, None) == -1
+    lib.hfe_export.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.c_void_p,
+                               ctypes.c_size_t, ctypes.c_void_p]
+    assert lib.hfe_export(None, 0, 0, None, 0, None) == -1
     lib.hfe_encode.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.hfe_encode(None, None, 1, 8, None, 1, None, None) == -1

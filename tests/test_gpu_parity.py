@@ -99,9 +99,9 @@ def test_db_ciphertext_bit_exact(name, row0, rows):
     g = run_for(name, row0, rows)
     c = g.c
     P = c.P
-    D = H.hfe_export(g.db, 0).reshape(len(P.q) + 1, P.n_db + c.w.d1, P.K).astype(np.int64)
+    D = H.hfe_export(g.db, 0).reshape(len(P.q) + 1, P.K, P.n_db + c.w.d1).astype(np.int64)
     for z, (pid, _) in enumerate(OC.prime_ids(P, len(P.q))):
-        bad = np.argwhere(D[z] != c.D[pid])
+        bad = np.argwhere(D[z].T != c.D[pid])
         assert bad.size == 0, f"prime slot {z}: {len(bad)} mismatches, first {bad[:3].tolist()}"
 
 

@@ -143,3 +143,24 @@ def test_ccmm_invariant_before_rescale():
             y = big[(P.n_db + i, col)] + sum(int(S_rows[i, v]) * a_pre[v] for v in range(P.n_db))
             noise = OC.centered(y - P.p * delta * int(c.ip_true[col, i]), Qp)
             assert abs(noise) < P.p * delta // 8
+
+
+def test_single_entry_functions_match_the_full_oracle():
+    """The sampled-entry evaluations used at large sizes agree with the full-matrix oracle."""
+    c = case(S.TINY_MULTI.name)
+    P = c.P
+    for pid, prime in OC.prime_ids(P, len(P.q)):
+        for r, col in [(0, 0), (5, 1000), (P.n_db, 3), (P.n_db + 255, P.K - 1), (P.n_db + 130, P.d2 + 7)]:
+            assert OC.db_entry(c.keys, c.m_db, DB_SEED, pid, prime, r, col) == c.D[pid][r, col]
+    for col in (0, 3):
+        qc = OC.query_column(c.keys, c.m_q[col], c.w.level, Q_SEED, col)
+        for i in range(c.w.level):
+            assert np.array_equal(qc[i], c.XT[i][col])
+    for r, col in [(3, 0), (P.n_db + 17, 1), (P.n_db + 255, 3)]:
+        drow = {pid: c.D[pid][r] for pid, _ in OC.prime_ids(P, c.w.level)}
+        xc = {i: c.XT[i][col] for i in range(c.w.level)}
+        assert OC.ccmm_entry(P, drow, xc, c.w.level) == [c.out[i][col, r] for i in range(c.w.level)]
+    s = c.keys.s[0]
+    a = np.arange(P.n_q) * 7919 % 1000
+    from oracle.ring import neg_matrix
+    assert np.array_equal(OC.negmul_vec(s, a), neg_matrix(s) @ a)
