@@ -89,6 +89,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024)
     ap.add_argument("--cpu-cols", type=int, default=32)
+    ap.add_argument("--sweep", action="store_true", help="time every int8 tile configuration and exit")
+    ap.add_argument("--variant", type=int, default=-1, help="int8 tile configuration (-1: default)")
+    ap.add_argument("--ccmm-only", type=int, default=0, help="run N int8 CCMMs after setup and exit (profiling)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="with --ccmm-only: also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU layout "
@@ -134,6 +139,43 @@ def main():
             r.free()
         qct.free()
         return ip, eye
+
+    H.hfe_set_i8_variant(args.variant)
+    if args.ccmm_only:
+        m_q = H.hfe_encode(q_codes, q_masks, shifts)
+        qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+        for _ in range(args.ccmm_only):
+            H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_I8_MFMA).free()
+        torch.cuda.synchronize()
+        log(f"ran {args.ccmm_only} int8 CCMMs")
+        if args.copy_mib:
+            src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"copied {args.copy_mib} MiB")
+        return
+
+    if args.sweep:
+        m_q = H.hfe_encode(q_codes, q_masks, shifts)
+        qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+        ref = None
+        for v in range(H.hfe_i8_variants()):
+            H.hfe_set_i8_variant(v)
+            H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_I8_MFMA).free()
+            H.hfe_profile(True)
+            rs = [H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_I8_MFMA) for _ in range(3)]
+            H.hfe_profile(False)
+            ms = [H.hfe_profile_ms(r, 3)[1] for r in rs]
+            out = H.hfe_export(rs[0], 0, 0, 1 << 20)
+            ref = out if ref is None else ref
+            ok = bool(np.array_equal(out, ref))
+            print(json.dumps({"variant": H.hfe_i8_variant_name(v), "contraction_ms": min(ms),
+                              "frac_of_peak": work["i8_ops"] / (min(ms) * 1e-3) / 1e12 / PEAK_I8_TOPS,
+                              "same_residues": ok}), flush=True)
+            for r in rs:
+                r.free()
+        return
 
     results = {}
     for name, form, steps, warm in (("i8", H.HFE_FORM_I8_MFMA, args.steps, args.warmup),

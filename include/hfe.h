@@ -167,6 +167,15 @@ hfe_status hfe_shape(const void* handle, int64_t* dims);
 hfe_status hfe_profile(int32_t enable);
 hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n);
 
+/* Tile configurations of the int8-MFMA contraction kernel.  hfe_i8_variants() returns their
+ * number; hfe_i8_variant_name(v) names one as "r<waves along database rows>q<waves along query
+ * columns>b<LDS stages>w<waves per SIMD>" (NULL if v is out of range); hfe_set_i8_variant(v)
+ * selects the configuration later hfe_ccmm calls use (-1 restores the default).  Every
+ * configuration computes the same residues. */
+int32_t hfe_i8_variants(void);
+const char* hfe_i8_variant_name(int32_t v);
+hfe_status hfe_set_i8_variant(int32_t v);
+
 /* Release any handle (NULL-safe).  Waits for work that uses it on its stream. */
 void hfe_free(void* handle);
 

@@ -33,7 +33,8 @@ STATUS_NAMES = {0: "HFE_OK", -1: "HFE_EINVAL", -2: "HFE_ESHAPE", -3: "HFE_ELEVEL
 
 EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode", "hfe_encrypt_db",
             "hfe_encrypt", "hfe_ccmm", "hfe_decrypt", "hfe_match", "hfe_export", "hfe_shape", "hfe_free",
-            "hfe_last_error", "hfe_cdt_table", "hfe_profile", "hfe_profile_ms")
+            "hfe_last_error", "hfe_cdt_table", "hfe_profile", "hfe_profile_ms", "hfe_i8_variants",
+            "hfe_i8_variant_name", "hfe_set_i8_variant")
 
 
 class HfeError(RuntimeError):
@@ -77,6 +78,7 @@ _SIGS = {
     "hfe_cdt_table": [_vp],
     "hfe_profile": [_i32],
     "hfe_profile_ms": [_vp, _vp, _i32],
+    "hfe_set_i8_variant": [_i32],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -84,6 +86,10 @@ for _name, _args in _SIGS.items():
     _f.restype = _i32
 _lib.hfe_free.argtypes = [_vp]
 _lib.hfe_free.restype = None
+_lib.hfe_i8_variants.argtypes = []
+_lib.hfe_i8_variants.restype = _i32
+_lib.hfe_i8_variant_name.argtypes = [_i32]
+_lib.hfe_i8_variant_name.restype = ctypes.c_char_p
 _lib.hfe_last_error.argtypes = []
 _lib.hfe_last_error.restype = ctypes.c_char_p
 
@@ -300,6 +306,19 @@ def hfe_profile_ms(r: Handle, n: int = 3) -> list:
     out = (ctypes.c_float * 3)()
     _check(_lib.hfe_profile_ms(r.ptr, out, n), "hfe_profile_ms")
     return [float(out[i]) for i in range(n)]
+
+
+def hfe_i8_variants() -> int:
+    return int(_lib.hfe_i8_variants())
+
+
+def hfe_i8_variant_name(v: int) -> Optional[str]:
+    name = _lib.hfe_i8_variant_name(v)
+    return name.decode() if name is not None else None
+
+
+def hfe_set_i8_variant(v: int) -> None:
+    _check(_lib.hfe_set_i8_variant(v), "hfe_set_i8_variant")
 
 
 def hfe_cdt_table() -> list:

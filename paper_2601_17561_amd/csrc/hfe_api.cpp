@@ -39,6 +39,8 @@ static hfe_status hip_fail(hipError_t e, const char* what) {
 // ------------------------------------------------------------------ allocator
 namespace {
 std::atomic<int> g_profile{0};
+std::atomic<int> g_i8_variant{-1};
+constexpr int kDefaultI8Variant = 0;
 std::mutex g_alloc_mu;
 hfe_alloc_fn g_alloc = nullptr;
 hfe_dealloc_fn g_dealloc = nullptr;
@@ -539,7 +541,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   g.rows = rows;
   g.R_out = R_out;
   g.d3 = d3;
-  g.d3_pad = (d3 + 63) / 64 * 64;
+  g.d3_pad = (d3 + kQueryPad - 1) / kQueryPad * kQueryPad;
   for (int z = 0; z < nz; ++z) {
     g.C[z] = C.as<uint64_t>() + (size_t)z * d3 * R_out;
     g.mod[z] = K->mods[slot(z)];
@@ -563,7 +565,8 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
       g.Xd[z] = Xd.as<int8_t>() + (size_t)z * kDigits * planeX;
     }
     HFE_LAUNCH(mark(1));
-    HFE_LAUNCH(launch_gemm_i8(g, s));
+    const int v = g_i8_variant.load();
+    HFE_LAUNCH(launch_gemm_i8(g, v < 0 ? kDefaultI8Variant : v, s));
   }
   HFE_LAUNCH(mark(2));
   RescaleArgs ra;
@@ -603,6 +606,16 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
     return st;
   }
   *out = R;
+  return HFE_OK;
+}
+
+int32_t hfe_i8_variants(void) { return i8_variant_count(); }
+
+const char* hfe_i8_variant_name(int32_t v) { return i8_variant_name(v); }
+
+hfe_status hfe_set_i8_variant(int32_t v) {
+  if (v < -1 || v >= i8_variant_count()) return fail(HFE_EINVAL, "no such i8 variant");
+  g_i8_variant.store(v);
   return HFE_OK;
 }
 

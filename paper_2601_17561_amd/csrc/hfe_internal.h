@@ -238,7 +238,10 @@ struct GemmArgs {
   int64_t K, KB, R_db, R_pad, n_db, row0, rows, R_out, d3, d3_pad;
 };
 hipError_t launch_gemm_plain(const GemmArgs& g, hipStream_t s);
-hipError_t launch_gemm_i8(const GemmArgs& g, hipStream_t s);
+hipError_t launch_gemm_i8(const GemmArgs& g, int variant, hipStream_t s);
+int i8_variant_count();
+const char* i8_variant_name(int v);
+constexpr int kQueryPad = 128;                   // query columns padded to the widest i8 tile
 
 // Rescale by p: out[i][c][r] = (C[i][c][r] - centered(C_p[c][r])) * p^-1 mod q_i.
 struct RescaleArgs {

@@ -127,61 +127,101 @@ __device__ __forceinline__ uint64_t horner9(const int32_t a[9], uint64_t q, uint
 // tile are fetched from HBM once into that XCD's L2 and shared by its query-column tiles.
 constexpr int kXcds = 8;
 
-__global__ void __launch_bounds__(256) k_gemm_i8(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) int8_t sA[2][kDigits][kIQ][kLdsRow];  // query digits
-  __shared__ __attribute__((aligned(16))) int8_t sB[2][kDigits][kIR][kLdsRow];  // database digits
+// Workgroup tile: WR x WQ waves, each owning a 32 (query) x 32 (database row) block of the
+// output; NBUF LDS stages (1: load, barrier, compute, barrier; 2: compute one stage while the
+// next is written); WPE = waves per SIMD the register budget is sized for.
+template <int WR, int WQ, int NBUF, int WPE>
+__global__ void __launch_bounds__(64 * WR * WQ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_gemm_i8(GemmArgs g) {
+  constexpr int T = 64 * WR * WQ;
+  constexpr int BR = 32 * WR, BQ = 32 * WQ;
+  constexpr int LA = (BQ * 4 + T - 1) / T;  // 16-byte loads per thread per query digit plane
+  constexpr int LB = (BR * 4 + T - 1) / T;  // ... per database digit plane
+  __shared__ __attribute__((aligned(16))) int8_t sA[NBUF][kDigits][BQ][kLdsRow];
+  __shared__ __attribute__((aligned(16))) int8_t sB[NBUF][kDigits][BR][kLdsRow];
   const int z = blockIdx.z;
-  const int64_t n_ct = (g.d3 + kIQ - 1) / kIQ, n_rt = (g.R_out + kIR - 1) / kIR;
+  const int64_t n_ct = (g.d3 + BQ - 1) / BQ, n_rt = (g.R_out + BR - 1) / BR;
   const int64_t wg = blockIdx.x, xcd = wg % kXcds, j = wg / kXcds;
   const int64_t rt = (j / n_ct) * kXcds + xcd, ct = j % n_ct;
   if (rt >= n_rt) return;
   const int8_t* __restrict__ Xd = g.Xd[z];
   const int8_t* __restrict__ Dd = g.Dd[z];
-  const int64_t r0 = rt * kIR, c0 = ct * kIQ;
+  const int64_t r0 = rt * BR, c0 = ct * BQ;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wq = wave & 1, wr = wave >> 1;
-  // global -> LDS: thread loads 16 bytes (chunk tid & 3) of row (tid >> 2) of each digit plane
-  const int ld_row = tid >> 2, ld_chunk = tid & 3;
-  const int64_t db_row = src_row(r0 + ld_row, g.n_db, g.row0);  // < R_pad for every tile (padding)
-  const int64_t q_col = c0 + ld_row;                            // < d3_pad
+  const int wq = wave % WQ, wr = wave / WQ;
   const size_t planeB = (size_t)g.KB * g.R_pad * kKB, planeA = (size_t)g.KB * g.d3_pad * kKB;
   const size_t stepB = (size_t)g.R_pad * kKB, stepA = (size_t)g.d3_pad * kKB;
-  const int8_t* gB = Dd + (size_t)db_row * kKB + ld_chunk * 16;
-  const int8_t* gA = Xd + (size_t)q_col * kKB + ld_chunk * 16;
+  // global -> LDS: load i of a plane covers 16 bytes (chunk idx & 3) of tile row idx >> 2,
+  // idx = tid + i T.  Database rows map to source rows (< R_pad, zero padding); query columns
+  // stay below d3_pad.
+  const int8_t* gA[LA];
+  const int8_t* gB[LB];
+  bool okA[LA], okB[LB];
+  int offA[LA], offB[LB];
+#pragma unroll
+  for (int i = 0; i < LA; ++i) {
+    const int idx = tid + i * T;
+    okA[i] = idx < BQ * 4;
+    const int row = okA[i] ? idx >> 2 : 0, ch = idx & 3;
+    gA[i] = Xd + (size_t)(c0 + row) * kKB + ch * 16;
+    offA[i] = row * kLdsRow + ch * 16;
+  }
+#pragma unroll
+  for (int i = 0; i < LB; ++i) {
+    const int idx = tid + i * T;
+    okB[i] = idx < BR * 4;
+    const int row = okB[i] ? idx >> 2 : 0, ch = idx & 3;
+    gB[i] = Dd + (size_t)src_row(r0 + row, g.n_db, g.row0) * kKB + ch * 16;
+    offB[i] = row * kLdsRow + ch * 16;
+  }
   const Mod m = g.mod[z];
   // 32x32 MFMA result layout: lane l, element j holds row (M = query) 8 (j / 4) + 4 (l / 32)
   // + j % 4 and column (N = database row) l % 32.
   const int64_t out_r = r0 + wr * 32 + (lane & 31);
   uint64_t* C = g.C[z];
 
+  v4i pa[kDigits][LA], pb[kDigits][LB];
+  auto fetch = [&](int64_t kb) {
+#pragma unroll
+    for (int t = 0; t < kDigits; ++t) {
+#pragma unroll
+      for (int i = 0; i < LA; ++i)
+        if (okA[i]) pa[t][i] = *reinterpret_cast<const v4i*>(gA[i] + t * planeA + kb * stepA);
+#pragma unroll
+      for (int i = 0; i < LB; ++i)
+        if (okB[i]) pb[t][i] = *reinterpret_cast<const v4i*>(gB[i] + t * planeB + kb * stepB);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < kDigits; ++t) {
+#pragma unroll
+      for (int i = 0; i < LA; ++i)
+        if (okA[i]) *reinterpret_cast<v4i*>(&sA[buf][t][0][0] + offA[i]) = pa[t][i];
+#pragma unroll
+      for (int i = 0; i < LB; ++i)
+        if (okB[i]) *reinterpret_cast<v4i*>(&sB[buf][t][0][0] + offB[i]) = pb[t][i];
+    }
+  };
+
   for (int64_t kb0 = 0; kb0 < g.KB; kb0 += kChunkKB) {
     const int64_t kb1 = kb0 + kChunkKB < g.KB ? kb0 + kChunkKB : g.KB;
     v16i acc[9];
 #pragma unroll
     for (int u = 0; u < 9; ++u) acc[u] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    v4i pa[kDigits], pb[kDigits];
-#pragma unroll
-    for (int t = 0; t < kDigits; ++t) {
-      pa[t] = *reinterpret_cast<const v4i*>(gA + t * planeA + kb0 * stepA);
-      pb[t] = *reinterpret_cast<const v4i*>(gB + t * planeB + kb0 * stepB);
+    fetch(kb0);
+    if (NBUF == 2) {
+      stash(0);
+      __syncthreads();
     }
-#pragma unroll
-    for (int t = 0; t < kDigits; ++t) {
-      *reinterpret_cast<v4i*>(&sA[kb0 & 1][t][ld_row][ld_chunk * 16]) = pa[t];
-      *reinterpret_cast<v4i*>(&sB[kb0 & 1][t][ld_row][ld_chunk * 16]) = pb[t];
-    }
-    __syncthreads();
     for (int64_t kb = kb0; kb < kb1; ++kb) {
-      const int cur = (int)(kb & 1);
+      const int cur = NBUF == 2 ? (int)((kb - kb0) & 1) : 0;
       const bool more = kb + 1 < kb1;
-      if (more) {
-        const size_t offA = (size_t)(kb + 1) * stepA, offB = (size_t)(kb + 1) * stepB;
-#pragma unroll
-        for (int t = 0; t < kDigits; ++t) {
-          pa[t] = *reinterpret_cast<const v4i*>(gA + t * planeA + offA);
-          pb[t] = *reinterpret_cast<const v4i*>(gB + t * planeB + offB);
-        }
+      if (NBUF == 1) {
+        stash(0);
+        __syncthreads();
       }
+      if (more) fetch(kb + 1);
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
         const int koff = half * 32 + (lane >> 5) * 16;
@@ -197,13 +237,7 @@ __global__ void __launch_bounds__(256) k_gemm_i8(GemmArgs g) {
             acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[t], b, acc[s + t], 0, 0, 0);
         }
       }
-      if (more) {
-#pragma unroll
-        for (int t = 0; t < kDigits; ++t) {
-          *reinterpret_cast<v4i*>(&sA[cur ^ 1][t][ld_row][ld_chunk * 16]) = pa[t];
-          *reinterpret_cast<v4i*>(&sB[cur ^ 1][t][ld_row][ld_chunk * 16]) = pb[t];
-        }
-      }
+      if (NBUF == 2 && more) stash(cur ^ 1);
       __syncthreads();
     }
     // Recombine this K-chunk and accumulate it into the output (first chunk stores).
@@ -224,12 +258,144 @@ __global__ void __launch_bounds__(256) k_gemm_i8(GemmArgs g) {
   }
 }
 
-hipError_t launch_gemm_i8(const GemmArgs& g, hipStream_t s) {
+// Software-pipelined form of the same contraction (2 x 2 waves, 64 x 64 tile): two register
+// sets carry K-blocks i + 1 and i + 2 while block i is multiplied from LDS, and the LDS
+// stores of block i + 1 are issued between the MFMAs of block i, so that stores, global
+// loads and the one barrier per block overlap the matrix pipe.
+template <int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_gemm_i8_pipe(GemmArgs g) {
+  constexpr int BR = 64, BQ = 64;
+  __shared__ __attribute__((aligned(16))) int8_t sA[2][kDigits][BQ][kLdsRow];
+  __shared__ __attribute__((aligned(16))) int8_t sB[2][kDigits][BR][kLdsRow];
+  const int z = blockIdx.z;
+  const int64_t n_ct = (g.d3 + BQ - 1) / BQ, n_rt = (g.R_out + BR - 1) / BR;
+  const int64_t wg = blockIdx.x, xcd = wg % kXcds, j = wg / kXcds;
+  const int64_t rt = (j / n_ct) * kXcds + xcd, ct = j % n_ct;
+  if (rt >= n_rt) return;
+  const int64_t r0 = rt * BR, c0 = ct * BQ;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wq = wave & 1, wr = wave >> 1;
+  const size_t planeB = (size_t)g.KB * g.R_pad * kKB, planeA = (size_t)g.KB * g.d3_pad * kKB;
+  const size_t stepB = (size_t)g.R_pad * kKB, stepA = (size_t)g.d3_pad * kKB;
+  const int ld_row = tid >> 2, ld_ch = tid & 3;
+  const int8_t* gA = g.Xd[z] + (size_t)(c0 + ld_row) * kKB + ld_ch * 16;
+  const int8_t* gB = g.Dd[z] + (size_t)src_row(r0 + ld_row, g.n_db, g.row0) * kKB + ld_ch * 16;
+  const int st_off = ld_row * kLdsRow + ld_ch * 16;
+  const int rd_a = (wq * 32 + (lane & 31)) * kLdsRow, rd_b = (wr * 32 + (lane & 31)) * kLdsRow;
+  const Mod m = g.mod[z];
+  const int64_t out_r = r0 + wr * 32 + (lane & 31);
+  uint64_t* C = g.C[z];
+
+  v4i p0[2 * kDigits], p1[2 * kDigits];  // [A digits 0..4, B digits 0..4] of one K-block
+  auto fetch = [&](v4i* p, int64_t kb) {
+#pragma unroll
+    for (int t = 0; t < kDigits; ++t) {
+      p[t] = *reinterpret_cast<const v4i*>(gA + t * planeA + kb * stepA);
+      p[kDigits + t] = *reinterpret_cast<const v4i*>(gB + t * planeB + kb * stepB);
+    }
+  };
+  auto put = [&](const v4i* p, int buf, int i) {  // i-th of the 10 16-byte stores of a block
+    if (i < kDigits)
+      *reinterpret_cast<v4i*>(&sA[buf][i][0][0] + st_off) = p[i];
+    else
+      *reinterpret_cast<v4i*>(&sB[buf][i - kDigits][0][0] + st_off) = p[i];
+  };
+
+  for (int64_t kb0 = 0; kb0 < g.KB; kb0 += kChunkKB) {
+    const int64_t kb_end = kb0 + kChunkKB < g.KB ? kb0 + kChunkKB : g.KB;
+    const int64_t n = kb_end - kb0;
+    v16i acc[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) acc[u] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    fetch(p0, kb0);
+#pragma unroll
+    for (int i = 0; i < 2 * kDigits; ++i) put(p0, 0, i);
+    fetch(p1, n > 1 ? kb0 + 1 : kb0);
+    __syncthreads();
+    // One K-block: multiply LDS stage `cur`; store the next block (register set `nx`) into the
+    // other stage between the MFMAs (a store past the last block is harmless: that stage is
+    // not read again); the block after next is loaded into set `ld` first (clamped to the last
+    // block, so every load is in range and the code has no data-dependent branches).
+    // Fragments are read one step ahead so LDS latency overlaps the MFMAs.
+    auto block = [&](int cur, v4i* nx, v4i* ld, int64_t i) {
+      fetch(ld, kb0 + i + 2 < kb_end ? kb0 + i + 2 : kb_end - 1);
+      __builtin_amdgcn_sched_barrier(0);  // keep the global loads at the head of the block
+      const int8_t* A = &sA[cur][0][0][0] + rd_a;
+      const int8_t* B = &sB[cur][0][0][0] + rd_b;
+      constexpr int planeA_l = BQ * kLdsRow, planeB_l = BR * kLdsRow;
+      const int k0 = (lane >> 5) * 16, k1 = 32 + (lane >> 5) * 16;
+      v4i a0[kDigits], a1[kDigits], b_cur, b_nxt;
+#pragma unroll
+      for (int t = 0; t < kDigits; ++t) a0[t] = *reinterpret_cast<const v4i*>(A + t * planeA_l + k0);
+      b_cur = *reinterpret_cast<const v4i*>(B + k0);
+#pragma unroll
+      for (int step = 0; step < 2 * kDigits; ++step) {
+        const int half = step / kDigits, s = step % kDigits;
+        if (step + 1 < 2 * kDigits) {
+          const int hs = (step + 1) / kDigits, ss = (step + 1) % kDigits;
+          b_nxt = *reinterpret_cast<const v4i*>(B + ss * planeB_l + (hs ? k1 : k0));
+        }
+        if (step >= 2 && step < 2 + kDigits)
+          a1[step - 2] = *reinterpret_cast<const v4i*>(A + (step - 2) * planeA_l + k1);
+        put(nx, cur ^ 1, step);
+#pragma unroll
+        for (int t = 0; t < kDigits; ++t)
+          acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(half ? a1[t] : a0[t], b_cur, acc[s + t], 0, 0, 0);
+        b_cur = b_nxt;
+      }
+      __syncthreads();
+    };
+    for (int64_t i = 0; i < n; i += 2) {
+      block(0, p1, p0, i);
+      if (i + 1 < n) block(1, p0, p1, i + 1);
+    }
+    if (out_r < g.R_out) {
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int64_t c = c0 + wq * 32 + 8 * (jj >> 2) + 4 * (lane >> 5) + (jj & 3);
+        if (c >= g.d3) continue;
+        int32_t a9[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) a9[u] = acc[u][jj];
+        uint64_t v = horner9(a9, m.q, m.mu);
+        uint64_t* dst = C + c * g.R_out + out_r;
+        if (kb0) v = add_mod(v, *dst, m.q);
+        *dst = v;
+      }
+    }
+  }
+}
+
+struct I8Variant {
+  const char* name;
+  void (*kernel)(GemmArgs);
+  int br, bq, threads;
+};
+
+#define HFE_I8_VARIANT(WR, WQ, NB, WPE) \
+  { "r" #WR "q" #WQ "b" #NB "w" #WPE, k_gemm_i8<WR, WQ, NB, WPE>, 32 * (WR), 32 * (WQ), 64 * (WR) * (WQ) }
+
+static const I8Variant kI8Variants[] = {
+    {"pipe_w1", k_gemm_i8_pipe<1>, 64, 64, 256},
+    HFE_I8_VARIANT(2, 2, 1, 1), HFE_I8_VARIANT(2, 2, 2, 1), HFE_I8_VARIANT(2, 2, 1, 2),
+    HFE_I8_VARIANT(4, 2, 1, 2), HFE_I8_VARIANT(2, 4, 1, 2), HFE_I8_VARIANT(4, 2, 2, 2),
+    HFE_I8_VARIANT(2, 4, 2, 2),
+};
+constexpr int kNumI8Variants = sizeof(kI8Variants) / sizeof(kI8Variants[0]);
+
+int i8_variant_count() { return kNumI8Variants; }
+const char* i8_variant_name(int v) { return (v >= 0 && v < kNumI8Variants) ? kI8Variants[v].name : nullptr; }
+
+hipError_t launch_gemm_i8(const GemmArgs& g, int variant, hipStream_t s) {
   if (g.R_out <= 0 || g.d3 <= 0) return hipSuccess;
-  const int64_t n_ct = (g.d3 + kIQ - 1) / kIQ, n_rt = (g.R_out + kIR - 1) / kIR;
+  if (variant < 0 || variant >= kNumI8Variants) return hipErrorInvalidValue;
+  const I8Variant& v = kI8Variants[variant];
+  if (g.d3_pad % v.bq != 0) return hipErrorInvalidValue;  // query padding must cover the tile
+  const int64_t n_ct = (g.d3 + v.bq - 1) / v.bq, n_rt = (g.R_out + v.br - 1) / v.br;
   const int64_t n_rt8 = (n_rt + kXcds - 1) / kXcds * kXcds;
   dim3 grid((unsigned)(n_rt8 * n_ct), 1, (unsigned)g.nz);
-  hipLaunchKernelGGL(k_gemm_i8, grid, dim3(256), 0, s, g);
+  hipLaunchKernelGGL(v.kernel, grid, dim3(v.threads), 0, s, g);
   return hipGetLastError();
 }
 
