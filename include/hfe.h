@@ -125,6 +125,75 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
 hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
                     void* stream, hfe_rct** out);
 
+/* Batched CCMM: item i is its own CCMM of items[i].q (any level, any column count) against the
+ * database codes [items[i].row0, items[i].row0 + items[i].rows), all against one database.
+ * int8 form: one grouped launch lifts and digit-splits every item's query, ONE persistent launch
+ * computes the tiles of every item and prime (workgroups loop over a device-resident tile
+ * table), one grouped launch rescales; plain form: one hfe_ccmm per item.  outs[i] receives
+ * item i's result handle (release each with hfe_free).  1 <= n <= 256. */
+typedef struct {
+  const hfe_qct* q;
+  int64_t row0, rows;
+} hfe_batch_item;
+hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32_t n, int32_t form,
+                            void* stream, hfe_rct** outs);
+
+/* Reusable batched int8 CCMM for repeated batches (e.g. serving steps): the workspace for up to
+ * max_items items, max_cols query columns in total and levels up to max_level is allocated once;
+ * hfe_plan_run writes the batch's descriptor tables (a host-to-device copy on `stream`) and
+ * enqueues the three grouped launches, captured on the first use_graph run into a hipGraph that
+ * later runs replay (any later stream is fine; the graph is launched on it).  hfe_plan_result
+ * returns item i's result of the last run as a view owned by the plan: valid until the next
+ * hfe_plan_run or hfe_free(plan); hfe_free on the view does nothing.  Runs on one plan must not
+ * overlap; the plan's database must outlive it. */
+typedef struct hfe_plan hfe_plan;
+hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols, uint32_t max_level,
+                           hfe_plan** out);
+hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, int32_t use_graph,
+                        void* stream);
+hfe_status hfe_plan_result(const hfe_plan* plan, int32_t i, const hfe_rct** view);
+
+/* Autotuner of the int8 contraction tiles: times every tile configuration (see hfe_i8_variants)
+ * on this problem (reps timed runs each, after one untimed), records the fastest for the
+ * problem's (level, query-column bucket) so that later hfe_ccmm / batched calls of that shape
+ * use it, and returns it in *best.  The table can be saved and loaded as text
+ * ("<level> <column bucket> <configuration name>" per line). */
+hfe_status hfe_autotune(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t reps,
+                        void* stream, int32_t* best);
+hfe_status hfe_autotune_save(const char* path);
+hfe_status hfe_autotune_load(const char* path);
+
+/* Continuous-batching server over a resident database (int8 form).  A worker thread keeps
+ * n_slots steps in flight on their own streams; each step admits queued requests in arrival
+ * order while their columns fit the step (at most max_cols_per_step columns, at most
+ * max_items_per_step requests, and the memory budget: mem_budget bytes of workspace split over
+ * the slots, allocated at creation), runs them as one batched CCMM (captured hipGraph) and
+ * decrypts every request into its own output.  Requests that arrive while steps run are
+ * admitted by the next free slot, so their work overlaps on the device.  A request larger than
+ * one step is rejected (HFE_EBUSY).  All device memory is allocated by hfe_server_create; the
+ * worker allocates nothing.
+ *   hfe_server_submit: q (its keys must be the server's; level <= max_level) stays borrowed
+ *     until the ticket completes; ip_out: device int32 d3 x d1 (query-major) receives the
+ *     decrypted inner products against every database code.
+ *   hfe_server_poll: *state = 0 queued, 1 running, 2 done, or a negative status (rejected).
+ *   hfe_server_wait: blocks until the ticket completes (HFE_EBUSY after timeout_ms, < 0: none).
+ *   hfe_server_stats: counts and latencies (arrival -> result ready; admission -> ready) of the
+ *     requests completed since creation or the last reset. */
+typedef struct hfe_server hfe_server;
+typedef struct {
+  int64_t submitted, completed, rejected, steps, max_queue;
+  double p50_ms, p99_ms, service_p50_ms, service_p99_ms, mean_ms;
+  double req_per_s, cmp_per_s, mean_cols_per_step, elapsed_s;
+} hfe_server_report;
+hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_cols_per_step,
+                             int32_t max_items_per_step, int32_t n_slots, uint32_t max_level,
+                             hfe_server** out);
+hfe_status hfe_server_submit(hfe_server* srv, const hfe_qct* q, int32_t* ip_out, uint64_t* ticket);
+hfe_status hfe_server_poll(hfe_server* srv, uint64_t ticket, int32_t* state);
+hfe_status hfe_server_wait(hfe_server* srv, uint64_t ticket, int64_t timeout_ms);
+hfe_status hfe_server_stats(hfe_server* srv, hfe_server_report* out);
+hfe_status hfe_server_reset_stats(hfe_server* srv);
+
 /* Decryption and coefficient decoding (Sections 2.2.1, 2.2.2): for column c and code r,
  * y = B_out + (s'_j * A_out)[r mod N_DB] mod Q (CRT over the level's primes, centered),
  * v[c * rows + r] = y / Delta (double) and ip[c * rows + r] = floor(y / Delta + 1/2).

@@ -34,7 +34,9 @@ STATUS_NAMES = {0: "HFE_OK", -1: "HFE_EINVAL", -2: "HFE_ESHAPE", -3: "HFE_ELEVEL
 EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode", "hfe_encrypt_db",
             "hfe_encrypt", "hfe_ccmm", "hfe_decrypt", "hfe_match", "hfe_export", "hfe_shape", "hfe_free",
             "hfe_last_error", "hfe_cdt_table", "hfe_profile", "hfe_profile_ms", "hfe_i8_variants",
-            "hfe_i8_variant_name", "hfe_set_i8_variant")
+            "hfe_i8_variant_name", "hfe_set_i8_variant", "hfe_ccmm_batched", "hfe_plan_create", "hfe_plan_run",
+            "hfe_plan_result", "hfe_autotune", "hfe_autotune_save", "hfe_autotune_load", "hfe_server_create",
+            "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_stats", "hfe_server_reset_stats")
 
 
 class HfeError(RuntimeError):
@@ -51,6 +53,16 @@ class hfe_params(ctypes.Structure):
 
     def primes(self):
         return [int(self.q[i]) for i in range(self.n_q_primes)], int(self.p)
+
+
+class hfe_batch_item(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_void_p), ("row0", ctypes.c_int64), ("rows", ctypes.c_int64)]
+
+
+class hfe_server_report(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "steps", "max_queue")] + \
+               [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "service_p50_ms", "service_p99_ms", "mean_ms",
+                                               "req_per_s", "cmp_per_s", "mean_cols_per_step", "elapsed_s")]
 
 
 if not os.path.exists(LIB_PATH):
@@ -79,6 +91,19 @@ _SIGS = {
     "hfe_profile": [_i32],
     "hfe_profile_ms": [_vp, _vp, _i32],
     "hfe_set_i8_variant": [_i32],
+    "hfe_ccmm_batched": [_vp, ctypes.POINTER(hfe_batch_item), _i32, _i32, _vp, ctypes.POINTER(_vp)],
+    "hfe_plan_create": [_vp, _i32, _i64, _u32, ctypes.POINTER(_vp)],
+    "hfe_plan_run": [_vp, ctypes.POINTER(hfe_batch_item), _i32, _i32, _vp],
+    "hfe_plan_result": [_vp, _i32, ctypes.POINTER(_vp)],
+    "hfe_autotune": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_i32)],
+    "hfe_autotune_save": [ctypes.c_char_p],
+    "hfe_autotune_load": [ctypes.c_char_p],
+    "hfe_server_create": [_vp, _sz, _i64, _i32, _i32, _u32, ctypes.POINTER(_vp)],
+    "hfe_server_submit": [_vp, _vp, _vp, ctypes.POINTER(_u64)],
+    "hfe_server_poll": [_vp, _u64, ctypes.POINTER(_i32)],
+    "hfe_server_wait": [_vp, _u64, _i64],
+    "hfe_server_stats": [_vp, ctypes.POINTER(hfe_server_report)],
+    "hfe_server_reset_stats": [_vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -319,6 +344,114 @@ def hfe_i8_variant_name(v: int) -> Optional[str]:
 
 def hfe_set_i8_variant(v: int) -> None:
     _check(_lib.hfe_set_i8_variant(v), "hfe_set_i8_variant")
+
+
+class View(Handle):
+    """A result owned by a plan (valid until the plan's next run); never released here."""
+
+    def free(self) -> None:
+        self.ptr = None
+
+
+def _items(items):
+    arr = (hfe_batch_item * len(items))()
+    for i, (q, row0, rows) in enumerate(items):
+        arr[i].q = q.ptr
+        arr[i].row0 = row0
+        arr[i].rows = rows
+    return arr
+
+
+def hfe_ccmm_batched(db: Handle, items, form: int, stream=None):
+    """items: sequence of (query Handle, row0, rows); returns one result Handle per item."""
+    arr = _items(items)
+    outs = (_vp * len(items))()
+    _check(_lib.hfe_ccmm_batched(db.ptr, arr, len(items), form, _stream(stream), outs), "hfe_ccmm_batched")
+    return [Handle(outs[i], (db, items[i][0])) for i in range(len(items))]
+
+
+def hfe_plan_create(db: Handle, max_items: int, max_cols: int, max_level: int) -> Handle:
+    out = _vp()
+    _check(_lib.hfe_plan_create(db.ptr, max_items, max_cols, max_level, ctypes.byref(out)), "hfe_plan_create")
+    return Handle(out.value, (db,))
+
+
+def hfe_plan_run(plan: Handle, items, use_graph: bool = True, stream=None) -> None:
+    arr = _items(items)
+    plan._run_items = list(items)  # keep the queries alive while the run may still read them
+    _check(_lib.hfe_plan_run(plan.ptr, arr, len(items), 1 if use_graph else 0, _stream(stream)), "hfe_plan_run")
+
+
+def hfe_plan_result(plan: Handle, i: int) -> View:
+    out = _vp()
+    _check(_lib.hfe_plan_result(plan.ptr, i, ctypes.byref(out)), "hfe_plan_result")
+    return View(out.value, (plan,))
+
+
+def hfe_autotune(db: Handle, q: Handle, row0: int, rows: int, reps: int = 2, stream=None) -> int:
+    best = _i32()
+    _check(_lib.hfe_autotune(db.ptr, q.ptr, row0, rows, reps, _stream(stream), ctypes.byref(best)), "hfe_autotune")
+    return int(best.value)
+
+
+def hfe_autotune_save(path: str) -> None:
+    _check(_lib.hfe_autotune_save(path.encode()), "hfe_autotune_save")
+
+
+def hfe_autotune_load(path: str) -> None:
+    _check(_lib.hfe_autotune_load(path.encode()), "hfe_autotune_load")
+
+
+class Server(Handle):
+    """A serving loop; keeps each in-flight request's query and output alive until it completes."""
+
+    def __init__(self, ptr, parents=()):
+        super().__init__(ptr, parents)
+        self._live = {}
+
+
+def hfe_server_create(db: Handle, mem_budget: int, max_cols_per_step: int, max_items_per_step: int = 64,
+                      n_slots: int = 2, max_level: int = 1) -> Server:
+    out = _vp()
+    _check(_lib.hfe_server_create(db.ptr, mem_budget, max_cols_per_step, max_items_per_step, n_slots, max_level,
+                                  ctypes.byref(out)), "hfe_server_create")
+    return Server(out.value, (db,))
+
+
+def hfe_server_submit(srv: Server, q: Handle, ip_out) -> int:
+    """ip_out: int32 GPU tensor (d3 x d1) receiving the request's decrypted inner products."""
+    torch = _torch()
+    t = _u64()
+    _check(_lib.hfe_server_submit(srv.ptr, q.ptr, _dev_ptr(ip_out, torch.int32), ctypes.byref(t)), "hfe_server_submit")
+    srv._live[int(t.value)] = (q, ip_out)
+    return int(t.value)
+
+
+def hfe_server_poll(srv: Server, ticket: int) -> int:
+    st = _i32()
+    _check(_lib.hfe_server_poll(srv.ptr, ticket, ctypes.byref(st)), "hfe_server_poll")
+    if st.value == 2 or st.value < 0:
+        srv._live.pop(ticket, None)
+    return int(st.value)
+
+
+def hfe_server_wait(srv: Server, ticket: int, timeout_ms: int = -1) -> None:
+    try:
+        _check(_lib.hfe_server_wait(srv.ptr, ticket, timeout_ms), "hfe_server_wait")
+    finally:
+        st = _i32()
+        if _lib.hfe_server_poll(srv.ptr, ticket, ctypes.byref(st)) == 0 and (st.value == 2 or st.value < 0):
+            srv._live.pop(ticket, None)
+
+
+def hfe_server_stats(srv: Server) -> dict:
+    r = hfe_server_report()
+    _check(_lib.hfe_server_stats(srv.ptr, ctypes.byref(r)), "hfe_server_stats")
+    return {name: getattr(r, name) for name, _ in hfe_server_report._fields_}
+
+
+def hfe_server_reset_stats(srv: Server) -> None:
+    _check(_lib.hfe_server_reset_stats(srv.ptr), "hfe_server_reset_stats")
 
 
 def hfe_cdt_table() -> list:

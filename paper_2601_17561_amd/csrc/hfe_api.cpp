@@ -2,6 +2,8 @@
 // memory and the enqueueing of the kernels for key generation, encryption, the CCMM,
 // decryption and the match decision.
 #include <algorithm>
+#include <cstdio>
+#include <map>
 #include <atomic>
 #include <cstring>
 #include <mutex>
@@ -485,12 +487,61 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
 }
 
 // ------------------------------------------------------------------ CCMM
+static LiftArgs make_lift_args(const hfe_keys* K, int level) {
+  LiftArgs la;
+  std::memset(&la, 0, sizeof(la));
+  la.level = level;
+  for (int i = 0; i < level; ++i) {
+    la.q[i] = K->primes[i];
+    la.mu[i] = K->mods[i].mu;
+  }
+  la.p = K->P.p;
+  la.mu_p = K->mods[K->L].mu;
+  garner_consts(K, level, la.garner, la.half_digits);
+  uint64_t prod = 1;
+  for (int i = 0; i < level; ++i) {
+    la.mprod_p[i] = prod;
+    prod = mulmod(prod, K->primes[i] % K->P.p, K->P.p);
+  }
+  la.mprod_p[level] = prod;
+  la.Q_mod_p = prod;
+  return la;
+}
+
+static RescaleArgs make_rescale_args(const hfe_keys* K, int level) {
+  RescaleArgs ra;
+  std::memset(&ra, 0, sizeof(ra));
+  ra.level = level;
+  ra.p = K->P.p;
+  for (int i = 0; i < level; ++i) {
+    ra.mod[i] = K->mods[i];
+    ra.pinv[i] = inv_mod(K->P.p % K->primes[i], K->primes[i]);
+    ra.pinv_sh[i] = shoup(ra.pinv[i], K->primes[i]);
+  }
+  return ra;
+}
+
+// Autotuned tile configurations: (level, d3 bucket) -> variant.
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int64_t>, int> g_tuned;
+static int64_t d3_bucket(int64_t d3) {
+  int64_t b = 64;
+  while (b < d3) b <<= 1;
+  return b;
+}
+static int pick_i8_variant(int level, int64_t d3) {
+  const int forced = g_i8_variant.load();
+  if (forced >= 0) return forced;
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  auto it = g_tuned.find({level, d3_bucket(d3)});
+  return it == g_tuned.end() ? kDefaultI8Variant : it->second;
+}
+
 static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, int64_t rows, int32_t form,
                             hipStream_t s, hfe_rct* R) {
   const hfe_keys* K = D->keys;
-  const hfe_params& P = K->P;
   const int level = Qc->level;
-  const int64_t ndb = 1ll << P.log_n_db;
+  const int64_t ndb = 1ll << K->P.log_n_db;
   const int64_t d3 = Qc->d3;
   const int64_t R_out = ndb + rows;
   R->kind = kRct;
@@ -502,24 +553,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   R->rows = rows;
   R->R_out = R_out;
 
-  LiftArgs la;
-  std::memset(&la, 0, sizeof(la));
-  la.level = level;
-  for (int i = 0; i < level; ++i) {
-    la.q[i] = K->primes[i];
-    la.mu[i] = K->mods[i].mu;
-  }
-  la.p = P.p;
-  la.mu_p = K->mods[K->L].mu;
-  garner_consts(K, level, la.garner, la.half_digits);
-  uint64_t prod = 1;
-  for (int i = 0; i < level; ++i) {
-    la.mprod_p[i] = prod;
-    prod = mulmod(prod, K->primes[i] % P.p, P.p);
-  }
-  la.mprod_p[level] = prod;
-  la.Q_mod_p = prod;
-
+  const LiftArgs la = make_lift_args(K, level);
   const int nz = level + 1;
   auto slot = [&](int z) { return z < level ? z : K->L; };
   const bool prof = g_profile.load() != 0;
@@ -565,22 +599,14 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
       g.Xd[z] = Xd.as<int8_t>() + (size_t)z * kDigits * planeX;
     }
     HFE_LAUNCH(mark(1));
-    const int v = g_i8_variant.load();
-    HFE_LAUNCH(launch_gemm_i8(g, v < 0 ? kDefaultI8Variant : v, s));
+    HFE_LAUNCH(launch_gemm_i8(g, pick_i8_variant(level, d3), s));
   }
   HFE_LAUNCH(mark(2));
-  RescaleArgs ra;
-  std::memset(&ra, 0, sizeof(ra));
-  ra.level = level;
-  ra.p = P.p;
-  for (int i = 0; i < level; ++i) {
-    ra.mod[i] = K->mods[i];
-    ra.pinv[i] = inv_mod(P.p % K->primes[i], K->primes[i]);
-    ra.pinv_sh[i] = shoup(ra.pinv[i], K->primes[i]);
-  }
+  const RescaleArgs ra = make_rescale_args(K, level);
   HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
+  R->outp = R->out.as<uint64_t>();
   HFE_LAUNCH(launch_rescale(C.as<uint64_t>(), C.as<uint64_t>() + (size_t)level * d3 * R_out, d3 * R_out, ra,
-                            R->out.as<uint64_t>(), s));
+                            R->outp, s));
   HFE_LAUNCH(mark(3));
   return HFE_OK;
 }
@@ -635,24 +661,453 @@ hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n) {
   return HFE_OK;
 }
 
-// ------------------------------------------------------------------ decryption
-hfe_status hfe_decrypt(const hfe_keys* keys, const hfe_rct* r, double* v, int32_t* ip, void* stream) {
-  const hfe_keys* K = as_handle<hfe_keys>(keys, kKeys);
-  const hfe_rct* R = as_handle<hfe_rct>(r, kRct);
-  if (!K || !R || !ip) return fail(HFE_EINVAL, "invalid keys, result or ip");
-  if (R->keys != K) return fail(HFE_EINVAL, "result was not produced under these keys");
+// ------------------------------------------------------------------ batched CCMM
+}  // extern "C"
+
+namespace {
+// Byte layout of the descriptor tables of a batch of up to `cap` items (256-byte aligned parts).
+struct BlobLayout {
+  size_t gh, gd, lh, ld, rh, rd, bytes;
+  explicit BlobLayout(int cap) {
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    gh = 0;
+    gd = al(gh + sizeof(BatchHeader));
+    lh = al(gd + sizeof(BatchDesc) * cap);
+    ld = al(lh + sizeof(BatchElemHeader));
+    rh = al(ld + sizeof(BatchLiftDesc) * cap);
+    rd = al(rh + sizeof(BatchElemHeader));
+    bytes = al(rd + sizeof(BatchRescaleDesc) * cap);
+  }
+};
+
+struct BatchSizes {
+  size_t xd_bytes = 0, c_elems = 0, out_elems = 0;
+  int64_t cols = 0;
+  int max_level = 0;
+};
+
+hfe_status check_item(const hfe_db* D, const hfe_batch_item& it) {
+  const hfe_qct* Qc = as_handle<hfe_qct>(it.q, kQct);
+  if (!Qc) return fail(HFE_EINVAL, "invalid query handle in batch");
+  if (Qc->keys != D->keys) return fail(HFE_EINVAL, "database and query use different keys");
+  if (Qc->K != D->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
+  if (Qc->level > D->keys->L) return fail(HFE_ELEVEL, "query level above the database primes");
+  if (it.row0 < 0 || it.rows < 1 || it.row0 + it.rows > D->d1) return fail(HFE_ESHAPE, "row range outside the database");
+  return HFE_OK;
+}
+
+// Sizes of a batch, and (when blob != nullptr) its descriptor tables pointing into the given
+// workspace (xd_base, c_base) and result arrays (outs[i]).
+BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int variant, int8_t* xd_base,
+                      uint64_t* c_base, uint64_t* const* outs, uint8_t* blob, const BlobLayout& L) {
+  const hfe_keys* K = D->keys;
+  const int64_t ndb = 1ll << K->P.log_n_db;
+  BatchSizes z;
+  int64_t tiles = 0, lift_e = 0, resc_e = 0;
+  for (int i = 0; i < n; ++i) {
+    const hfe_qct* Qc = static_cast<const hfe_qct*>(items[i].q);
+    const int level = Qc->level, nz = level + 1;
+    const int64_t d3 = Qc->d3, d3_pad = (d3 + kQueryPad - 1) / kQueryPad * kQueryPad;
+    const int64_t R_out = ndb + items[i].rows;
+    const size_t xd_i = (size_t)nz * kDigits * D->KB * d3_pad * kKB;
+    const size_t c_i = (size_t)nz * d3 * R_out;
+    if (blob) {
+      BatchDesc& g = reinterpret_cast<BatchDesc*>(blob + L.gd)[i];
+      std::memset(&g, 0, sizeof(g));
+      g.Xd = xd_base + z.xd_bytes;
+      g.C = c_base + z.c_elems;
+      g.row0 = items[i].row0;
+      g.R_out = R_out;
+      g.d3 = d3;
+      g.d3_pad = d3_pad;
+      g.tile_begin = tiles;
+      g.nz = nz;
+      for (int zz = 0; zz < nz; ++zz) {
+        g.slot[zz] = zz < level ? zz : K->L;
+        g.mod[zz] = K->mods[g.slot[zz]];
+      }
+      BatchLiftDesc& l = reinterpret_cast<BatchLiftDesc*>(blob + L.ld)[i];
+      std::memset(&l, 0, sizeof(l));
+      l.XT = Qc->XT.as<uint64_t>();
+      l.Xd = xd_base + z.xd_bytes;
+      l.d3 = d3;
+      l.d3_pad = d3_pad;
+      l.elem_begin = lift_e;
+      l.la = make_lift_args(K, level);
+      BatchRescaleDesc& r = reinterpret_cast<BatchRescaleDesc*>(blob + L.rd)[i];
+      std::memset(&r, 0, sizeof(r));
+      r.C = g.C;
+      r.out = outs[i];
+      r.n = d3 * R_out;
+      r.elem_begin = resc_e;
+      r.ra = make_rescale_args(K, level);
+    }
+    tiles += i8_batched_tiles(variant, d3, R_out, nz);
+    lift_e += d3_pad * D->KB * kKB;
+    resc_e += (d3 * R_out + 255) / 256 * 256;
+    z.xd_bytes += xd_i;
+    z.c_elems += c_i;
+    z.out_elems += (size_t)level * d3 * R_out;
+    z.cols += d3;
+    z.max_level = std::max(z.max_level, level);
+  }
+  if (blob) {
+    BatchHeader* gh = reinterpret_cast<BatchHeader*>(blob + L.gh);
+    gh->total_tiles = tiles;
+    gh->n = n;
+    BatchElemHeader* lh = reinterpret_cast<BatchElemHeader*>(blob + L.lh);
+    lh->total = lift_e;
+    lh->n = n;
+    BatchElemHeader* rh = reinterpret_cast<BatchElemHeader*>(blob + L.rh);
+    rh->total = resc_e;
+    rh->n = n;
+  }
+  return z;
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      cus = prop.multiProcessorCount;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout& L, int variant, int gemm_grid,
+                         int elem_grid, hipStream_t s) {
+  HFE_LAUNCH(launch_lift_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.lh),
+                                 reinterpret_cast<const BatchLiftDesc*>(dblob + L.ld), D->K, D->KB, elem_grid, s));
+  BatchGemmArgs a;
+  a.hdr = reinterpret_cast<const BatchHeader*>(dblob + L.gh);
+  a.desc = reinterpret_cast<const BatchDesc*>(dblob + L.gd);
+  a.Dd = D->digits.as<int8_t>();
+  a.KB = D->KB;
+  a.R_pad = D->R_pad;
+  a.n_db = 1ll << D->keys->P.log_n_db;
+  HFE_LAUNCH(launch_gemm_i8_batched(a, variant, gemm_grid, s));
+  HFE_LAUNCH(launch_rescale_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.rh),
+                                    reinterpret_cast<const BatchRescaleDesc*>(dblob + L.rd), elem_grid, s));
+  return HFE_OK;
+}
+
+int gemm_grid_for(int variant) {
+  const int g = device_cus() * i8_variant_wgs_per_cu(variant);
+  return (g + kXcds - 1) / kXcds * kXcds;
+}
+constexpr int kElemGrid = 4096;
+}  // namespace
+
+extern "C" {
+
+hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32_t n, int32_t form, void* stream,
+                            hfe_rct** outs) {
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  if (!D || !items || !outs) return fail(HFE_EINVAL, "invalid database, items or outs");
+  if (n < 1 || n > kMaxBatch) return fail(HFE_EINVAL, "batch size must be 1 .. 256");
+  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA) return fail(HFE_EINVAL, "unknown form");
+  if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
+  for (int i = 0; i < n; ++i) {
+    outs[i] = nullptr;
+    HFE_TRY(check_item(D, items[i]));
+  }
   hipStream_t s = (hipStream_t)stream;
+  if (form == HFE_FORM_PLAIN_U64) {
+    for (int i = 0; i < n; ++i) {
+      hfe_status st = hfe_ccmm(db, items[i].q, items[i].row0, items[i].rows, form, stream, &outs[i]);
+      if (st != HFE_OK) {
+        for (int j = 0; j < i; ++j) hfe_free(outs[j]);
+        return st;
+      }
+    }
+    return HFE_OK;
+  }
+  // all items of one batch use one tile configuration: the tuned one for the largest level and
+  // the mean column count
+  const BlobLayout L(n);
+  const BatchSizes sz0 = batch_fill(D, items, n, 0, nullptr, nullptr, nullptr, nullptr, L);
+  const int variant = pick_i8_variant(sz0.max_level, sz0.cols / n);
+  const hfe_keys* K = D->keys;
+  const int64_t ndb = 1ll << K->P.log_n_db;
+  std::vector<hfe_rct*> R(n, nullptr);
+  auto cleanup = [&]() {
+    for (auto* r : R) delete r;
+  };
+  std::vector<uint64_t*> outp(n);
+  for (int i = 0; i < n; ++i) {
+    const hfe_qct* Qc = static_cast<const hfe_qct*>(items[i].q);
+    hfe_rct* r = new (std::nothrow) hfe_rct();
+    if (!r) {
+      cleanup();
+      return fail(HFE_ENOMEM, "host allocation failed");
+    }
+    R[i] = r;
+    r->kind = kRct;
+    r->stream = s;
+    r->keys = K;
+    r->level = Qc->level;
+    r->d3 = Qc->d3;
+    r->row0 = items[i].row0;
+    r->rows = items[i].rows;
+    r->R_out = ndb + items[i].rows;
+    hfe_status st = r->out.alloc(sizeof(uint64_t) * (size_t)r->level * r->d3 * r->R_out, s);
+    if (st != HFE_OK) {
+      cleanup();
+      return st;
+    }
+    r->outp = r->out.as<uint64_t>();
+    outp[i] = r->outp;
+  }
+  DevBuf Xd, C, blob;
+  hfe_status st = Xd.alloc(sz0.xd_bytes, s);
+  if (st == HFE_OK) st = C.alloc(sizeof(uint64_t) * sz0.c_elems, s);
+  if (st == HFE_OK) st = blob.alloc(L.bytes, s);
+  if (st != HFE_OK) {
+    cleanup();
+    return st;
+  }
+  std::vector<uint8_t> host(L.bytes, 0);
+  batch_fill(D, items, n, variant, Xd.as<int8_t>(), C.as<uint64_t>(), outp.data(), host.data(), L);
+  hipError_t e = hipMemcpyAsync(blob.ptr, host.data(), L.bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // the pageable staging is freed on return
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "descriptor upload");
+  }
+  st = batch_enqueue(D, blob.as<uint8_t>(), L, variant, gemm_grid_for(variant), kElemGrid, s);
+  if (st != HFE_OK) {
+    cleanup();
+    return st;
+  }
+  for (int i = 0; i < n; ++i) outs[i] = R[i];
+  return HFE_OK;
+}
+
+hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols, uint32_t max_level,
+                           hfe_plan** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  if (!D) return fail(HFE_EINVAL, "invalid database handle");
+  if (!(D->forms & HFE_FORM_I8_MFMA)) return fail(HFE_EINVAL, "database not prepared for the int8 form");
+  if (max_items < 1 || max_items > kMaxBatch) return fail(HFE_EINVAL, "max_items must be 1 .. 256");
+  if (max_cols < 1 || max_level < 1 || (int)max_level > D->keys->L) return fail(HFE_EINVAL, "bad capacity");
+  hfe_plan* P = new (std::nothrow) hfe_plan();
+  if (!P) return fail(HFE_ENOMEM, "host allocation failed");
+  P->kind = kPlan;
+  P->stream = nullptr;
+  P->db = D;
+  P->max_items = max_items;
+  P->max_cols = max_cols;
+  P->max_level = (int)max_level;
+  P->variant = pick_i8_variant((int)max_level, max_cols / max_items);
+  const int64_t ndb = 1ll << D->keys->P.log_n_db;
+  const int64_t R_max = ndb + D->d1;
+  const int64_t cols_pad = max_cols + (int64_t)max_items * (kQueryPad - 1);
+  P->xd_cap = (size_t)(max_level + 1) * kDigits * D->KB * cols_pad * kKB;
+  P->c_cap = (size_t)(max_level + 1) * max_cols * R_max;
+  P->out_cap = (size_t)max_level * max_cols * R_max;
+  const BlobLayout L(max_items);
+  P->blob_bytes = L.bytes;
+  hfe_status st = P->ws_xd.alloc(P->xd_cap, nullptr);
+  if (st == HFE_OK) st = P->ws_c.alloc(sizeof(uint64_t) * P->c_cap, nullptr);
+  if (st == HFE_OK) st = P->ws_out.alloc(sizeof(uint64_t) * P->out_cap, nullptr);
+  if (st == HFE_OK) st = P->desc.alloc(L.bytes, nullptr);
+  hipError_t e = hipSuccess;
+  if (st == HFE_OK) e = hipHostMalloc(&P->host_blob, L.bytes, hipHostMallocDefault);
+  if (st == HFE_OK && e == hipSuccess) e = hipEventCreateWithFlags(&P->copied, hipEventDisableTiming);
+  if (st == HFE_OK && e != hipSuccess) st = hip_fail(e, "plan staging");
+  if (st != HFE_OK) {
+    delete P;
+    return st;
+  }
+  P->gemm_grid = gemm_grid_for(P->variant);
+  P->elem_grid = kElemGrid;
+  for (int i = 0; i < max_items; ++i) {
+    hfe_rct* v = new (std::nothrow) hfe_rct();
+    if (!v) {
+      delete P;
+      return fail(HFE_ENOMEM, "host allocation failed");
+    }
+    v->kind = kRct;
+    v->is_view = true;
+    v->keys = D->keys;
+    P->views.push_back(v);
+  }
+  *out = P;
+  return HFE_OK;
+}
+
+hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, int32_t use_graph, void* stream) {
+  hfe_plan* P = as_handle<hfe_plan>(plan, kPlan);
+  if (!P || !items) return fail(HFE_EINVAL, "invalid plan or items");
+  if (n < 1 || n > P->max_items) return fail(HFE_EINVAL, "batch larger than the plan");
+  const hfe_db* D = P->db;
+  for (int i = 0; i < n; ++i) {
+    HFE_TRY(check_item(D, items[i]));
+    if (static_cast<const hfe_qct*>(items[i].q)->level > P->max_level)
+      return fail(HFE_ELEVEL, "item level above the plan's maximum");
+  }
+  const BlobLayout L(P->max_items);
+  const BatchSizes sz = batch_fill(D, items, n, P->variant, nullptr, nullptr, nullptr, nullptr, L);
+  if (sz.cols > P->max_cols || sz.xd_bytes > P->xd_cap || sz.c_elems > P->c_cap || sz.out_elems > P->out_cap)
+    return fail(HFE_ESHAPE, "batch exceeds the plan's workspace");
+  hipStream_t s = (hipStream_t)stream;
+  // result views: consecutive slices of the output workspace
+  const int64_t ndb = 1ll << D->keys->P.log_n_db;
+  std::vector<uint64_t*> outp(n);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    const hfe_qct* Qc = static_cast<const hfe_qct*>(items[i].q);
+    hfe_rct* v = P->views[i];
+    v->stream = s;
+    v->level = Qc->level;
+    v->d3 = Qc->d3;
+    v->row0 = items[i].row0;
+    v->rows = items[i].rows;
+    v->R_out = ndb + items[i].rows;
+    v->outp = P->ws_out.as<uint64_t>() + off;
+    outp[i] = v->outp;
+    off += (size_t)v->level * v->d3 * v->R_out;
+  }
+  // the pinned staging may still feed the previous run's upload
+  HFE_LAUNCH(hipEventSynchronize(P->copied));
+  uint8_t* host = static_cast<uint8_t*>(P->host_blob);
+  std::memset(host, 0, P->blob_bytes);
+  batch_fill(D, items, n, P->variant, P->ws_xd.as<int8_t>(), P->ws_c.as<uint64_t>(), outp.data(), host, L);
+  HFE_LAUNCH(hipMemcpyAsync(P->desc.ptr, host, P->blob_bytes, hipMemcpyHostToDevice, s));
+  HFE_LAUNCH(hipEventRecord(P->copied, s));
+  if (!use_graph) {
+    HFE_TRY(batch_enqueue(D, P->desc.as<uint8_t>(), L, P->variant, P->gemm_grid, P->elem_grid, s));
+  } else {
+    if (!P->exec) {
+      // capture on a private stream that joins the caller's stream through events
+      hipStream_t cap;
+      HFE_LAUNCH(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hfe_status st = HFE_OK;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) st = batch_enqueue(D, P->desc.as<uint8_t>(), L, P->variant, P->gemm_grid, P->elem_grid, cap);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(cap, &g);
+      (void)hipStreamDestroy(cap);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+      }
+      if (st != HFE_OK) {
+        (void)hipGraphDestroy(g);
+        return st;
+      }
+      P->graph = g;
+      HFE_LAUNCH(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0));
+    }
+    HFE_LAUNCH(hipGraphLaunch(P->exec, s));
+  }
+  P->n_last = n;
+  return HFE_OK;
+}
+
+hfe_status hfe_plan_result(const hfe_plan* plan, int32_t i, const hfe_rct** view) {
+  const hfe_plan* P = as_handle<hfe_plan>(plan, kPlan);
+  if (!P || !view) return fail(HFE_EINVAL, "invalid plan or view");
+  if (i < 0 || i >= P->n_last) return fail(HFE_EINVAL, "no such item in the last run");
+  *view = P->views[i];
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+hfe_status hfe_autotune(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t reps, void* stream,
+                        int32_t* best) {
+  const hfe_qct* Qc = as_handle<hfe_qct>(q, kQct);
+  if (!Qc || !best || reps < 1) return fail(HFE_EINVAL, "invalid query, best or reps");
+  const int saved_variant = g_i8_variant.load();
+  const int saved_profile = g_profile.load();
+  float best_ms = 1e30f;
+  int best_v = -1;
+  hfe_status st = HFE_OK;
+  for (int v = 0; v < i8_variant_count() && st == HFE_OK; ++v) {
+    g_i8_variant.store(v);
+    float vbest = 1e30f;
+    for (int r = 0; r <= reps && st == HFE_OK; ++r) {
+      g_profile.store(r > 0 ? 1 : 0);
+      hfe_rct* res = nullptr;
+      st = hfe_ccmm(db, q, row0, rows, HFE_FORM_I8_MFMA, stream, &res);
+      if (st == HFE_OK && r > 0) {
+        float ms[2];
+        st = hfe_profile_ms(res, ms, 2);
+        if (st == HFE_OK) vbest = std::min(vbest, ms[1]);
+      }
+      hfe_free(res);
+    }
+    if (vbest < best_ms) {
+      best_ms = vbest;
+      best_v = v;
+    }
+  }
+  g_i8_variant.store(saved_variant);
+  g_profile.store(saved_profile);
+  if (st != HFE_OK) return st;
+  {
+    std::lock_guard<std::mutex> l(g_tune_mu);
+    g_tuned[{Qc->level, d3_bucket(Qc->d3)}] = best_v;
+  }
+  *best = best_v;
+  return HFE_OK;
+}
+
+hfe_status hfe_autotune_save(const char* path) {
+  if (!path) return fail(HFE_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(HFE_EINVAL, std::string("cannot write ") + path);
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  for (const auto& kv : g_tuned)
+    std::fprintf(f, "%d %lld %s\n", kv.first.first, (long long)kv.first.second, i8_variant_name(kv.second));
+  std::fclose(f);
+  return HFE_OK;
+}
+
+hfe_status hfe_autotune_load(const char* path) {
+  if (!path) return fail(HFE_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(HFE_EINVAL, std::string("cannot read ") + path);
+  int level;
+  long long bucket;
+  char name[64];
+  std::map<std::pair<int, int64_t>, int> table;
+  while (std::fscanf(f, "%d %lld %63s", &level, &bucket, name) == 3) {
+    int v = -1;
+    for (int i = 0; i < i8_variant_count(); ++i)
+      if (std::string(i8_variant_name(i)) == name) v = i;
+    if (v < 0) {
+      std::fclose(f);
+      return fail(HFE_EINVAL, std::string("unknown tile configuration ") + name);
+    }
+    table[{level, (int64_t)bucket}] = v;
+  }
+  std::fclose(f);
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  for (const auto& kv : table) g_tuned[kv.first] = kv.second;
+  return HFE_OK;
+}
+
+// ------------------------------------------------------------------ decryption
+}  // extern "C"
+
+// Decryption into caller-provided scratch y ([level][d3][rows] uint64); no allocation.
+hfe_status hfe::decrypt_impl(const hfe_keys* K, const hfe_rct* R, double* v, int32_t* ip, uint64_t* y,
+                               hipStream_t s) {
   const hfe_params& P = K->P;
   const int64_t ndb = 1ll << P.log_n_db;
   const int level = R->level;
-  if ((R->row0 + R->rows - 1) / ndb >= K->k_db) return fail(HFE_ESHAPE, "rows beyond the database secrets");
-  DevBuf y;
-  HFE_TRY(y.alloc(sizeof(uint64_t) * (size_t)level * R->d3 * R->rows, s));
   for (int i = 0; i < level; ++i)
-    HFE_LAUNCH(launch_dec_products(R->out.as<uint64_t>() + (size_t)i * R->d3 * R->R_out, R->d3, R->R_out, R->row0,
-                                   R->rows, (int)P.log_n_db, K->tab_db[i].tab,
+    HFE_LAUNCH(launch_dec_products(R->outp + (size_t)i * R->d3 * R->R_out, R->d3, R->R_out, R->row0, R->rows,
+                                   (int)P.log_n_db, K->tab_db[i].tab,
                                    K->sdb_hat.as<uint64_t>() + (size_t)i * K->k_db * 2 * ndb, K->k_db,
-                                   y.as<uint64_t>() + (size_t)i * R->d3 * R->rows, s));
+                                   y + (size_t)i * R->d3 * R->rows, s));
   DecodeArgs da;
   std::memset(&da, 0, sizeof(da));
   da.level = level;
@@ -665,8 +1120,23 @@ hfe_status hfe_decrypt(const hfe_keys* keys, const hfe_rct* r, double* v, int32_
   for (int i = 0; i < level; ++i) Q.mul(K->primes[i]);
   for (size_t j = 0; j < 5 && j < Q.w.size(); ++j) da.Qw[j] = Q.w[j];
   da.delta_log = delta_log(K, level);
-  HFE_LAUNCH(launch_decode(y.as<uint64_t>(), R->d3 * R->rows, da, v, ip, s));
+  HFE_LAUNCH(launch_decode(y, R->d3 * R->rows, da, v, ip, s));
   return HFE_OK;
+}
+
+extern "C" {
+
+hfe_status hfe_decrypt(const hfe_keys* keys, const hfe_rct* r, double* v, int32_t* ip, void* stream) {
+  const hfe_keys* K = as_handle<hfe_keys>(keys, kKeys);
+  const hfe_rct* R = as_handle<hfe_rct>(r, kRct);
+  if (!K || !R || !ip) return fail(HFE_EINVAL, "invalid keys, result or ip");
+  if (R->keys != K) return fail(HFE_EINVAL, "result was not produced under these keys");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ndb = 1ll << K->P.log_n_db;
+  if ((R->row0 + R->rows - 1) / ndb >= K->k_db) return fail(HFE_ESHAPE, "rows beyond the database secrets");
+  DevBuf y;
+  HFE_TRY(y.alloc(sizeof(uint64_t) * (size_t)R->level * R->d3 * R->rows, s));
+  return decrypt_impl(K, R, v, ip, y.as<uint64_t>(), s);
 }
 
 // ------------------------------------------------------------------ match
@@ -723,7 +1193,7 @@ hfe_status hfe_export(const void* handle, int32_t which, size_t offset, uint64_t
     const hfe_rct* R = static_cast<const hfe_rct*>(handle);
     if (which != 0) return fail(HFE_EINVAL, "rct export: which must be 0");
     total = (size_t)R->level * R->d3 * R->R_out;
-    dev = R->out.ptr;
+    dev = R->outp;
   } else {
     return fail(HFE_EINVAL, "unknown handle");
   }
@@ -787,8 +1257,16 @@ void hfe_free(void* handle) {
       delete static_cast<hfe_qct*>(handle);
       break;
     case kRct:
+      if (static_cast<hfe_rct*>(handle)->is_view) break;  // owned by its plan
       b->kind = 0;
       delete static_cast<hfe_rct*>(handle);
+      break;
+    case kPlan:
+      b->kind = 0;
+      delete static_cast<hfe_plan*>(handle);
+      break;
+    case kServer:
+      destroy_server(handle);
       break;
     default:
       break;

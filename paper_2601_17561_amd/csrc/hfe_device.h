@@ -1,0 +1,94 @@
+// Device-side element operations shared by the per-call and the grouped (batched) kernels:
+// balanced int8 digit split, Garner mixed-radix reconstruction, the centered CRT lift of one
+// query residue vector with its digit split, and the rescale of one output entry.
+#pragma once
+
+#include "hfe_internal.h"
+
+namespace hfe {
+
+// ------------------------------------------------------------------ digit split
+// Centered residue x in (-q/2, q/2) -> 5 balanced base-256 digits d_t in [-128, 127]
+// (|d_4| <= 8), x = sum_t d_t 256^t.
+__device__ __forceinline__ void split5(int64_t x, int32_t d[kDigits]) {
+#pragma unroll
+  for (int t = 0; t < kDigits - 1; ++t) {
+    const int32_t lo = (int32_t)((x + 128) & 255) - 128;
+    d[t] = lo;
+    x = (x - lo) >> 8;
+  }
+  d[kDigits - 1] = (int32_t)x;
+}
+
+// ------------------------------------------------------------------ Garner mixed radix
+// Residues y_i mod q_i -> digits v_i with Y = v_0 + v_1 q_0 + v_2 q_0 q_1 + ..., computed as
+// v_i = (y_i - sum_{j<i} v_j (q_0..q_{j-1} mod q_i)) * (q_0..q_{i-1})^-1 mod q_i.
+// garner[i][j] = q_0..q_{j-1} mod q_i for j < i, garner[i][i] = (q_0..q_{i-1})^-1 mod q_i.
+__device__ __forceinline__ void garner_digits(const uint64_t* y, int level,
+                                              const uint64_t (*garner)[HFE_MAX_QPRIMES],
+                                              const uint64_t* q, const uint64_t* mus, uint64_t* v) {
+  for (int i = 0; i < level; ++i) {
+    const uint64_t qi = q[i];
+    const uint64_t mu = mus[i];
+    uint64_t s = 0;
+    for (int j = 0; j < i; ++j)
+      s = add_mod(s, mul_mod(barrett64(v[j], qi, mu), garner[i][j], qi, mu), qi);
+    v[i] = i == 0 ? y[0] : mul_mod(sub_mod(y[i], s, qi), garner[i][i], qi, mu);
+  }
+}
+
+// Y > (Q - 1)/2, compared on mixed-radix digits from the most significant one.
+__device__ __forceinline__ bool above_half(const uint64_t* v, const uint64_t* half, int level) {
+  for (int i = level - 1; i >= 0; --i) {
+    if (v[i] != half[i]) return v[i] > half[i];
+  }
+  return false;
+}
+
+// Query element (c, k) of XT ([level][d3][K]): the lift L(x) = centered CRT value of the
+// residues y_i in (-Q/2, Q/2), reduced mod p; writes Xp[c][k] = L mod p (if Xp) and the 5
+// digit planes of every prime of the level and p (if Xd), zero for padding positions.
+__device__ __forceinline__ void lift_element(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
+                                             int64_t d3_pad, const LiftArgs& la, uint64_t* Xp, int8_t* Xd,
+                                             int64_t c, int64_t k) {
+  const bool valid = c < d3 && k < K;
+  uint64_t y[HFE_MAX_QPRIMES] = {};
+  uint64_t lp = 0;
+  if (valid) {
+    for (int i = 0; i < la.level; ++i) y[i] = XT[((int64_t)i * d3 + c) * K + k];
+    uint64_t v[HFE_MAX_QPRIMES];
+    garner_digits(y, la.level, la.garner, la.q, la.mu, v);
+    const uint64_t p = la.p;
+    const uint64_t mup = la.mu_p;
+    for (int i = 0; i < la.level; ++i)
+      lp = add_mod(lp, mul_mod(barrett64(v[i], p, mup), la.mprod_p[i], p, mup), p);
+    if (above_half(v, la.half_digits, la.level)) lp = sub_mod(lp, la.Q_mod_p, p);
+    if (Xp) Xp[c * K + k] = lp;
+  }
+  if (!Xd) return;
+  const int64_t kb = k / kKB, kk = k % kKB;
+  for (int z = 0; z <= la.level; ++z) {
+    int64_t x = 0;
+    if (valid) x = z < la.level ? centered(y[z], la.q[z]) : centered(lp, la.p);
+    int32_t d[kDigits];
+    split5(x, d);
+#pragma unroll
+    for (int t = 0; t < kDigits; ++t)
+      Xd[((((int64_t)z * kDigits + t) * KB + kb) * d3_pad + c) * kKB + kk] = (int8_t)d[t];
+  }
+}
+
+// Output entry e of a contraction (C[i] = residues mod q_i, Cp = residues mod p, n entries per
+// prime): out[i][e] = (C[i][e] - centered(Cp[e]) mod q_i) * p^-1 mod q_i = RS_p of the CRT value.
+__device__ __forceinline__ void rescale_element(const uint64_t* C, const uint64_t* Cp, int64_t n,
+                                                const RescaleArgs& ra, uint64_t* out, int64_t e) {
+  const int64_t cp = centered(Cp[e], ra.p);
+  for (int i = 0; i < ra.level; ++i) {
+    const Mod& m = ra.mod[i];
+    const uint64_t r = from_signed(cp, m.q, m.mu);
+    const uint64_t d = sub_mod(C[(int64_t)i * n + e], r, m.q);
+    out[(int64_t)i * n + e] = mul_shoup(d, ra.pinv[i], ra.pinv_sh[i], m.q);
+  }
+}
+
+}  // namespace hfe

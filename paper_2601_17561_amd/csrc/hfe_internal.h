@@ -18,6 +18,7 @@ constexpr int kDigits = 5;                       // balanced base-256 digits per
 constexpr int kKB = 64;                          // K bytes per digit block
 constexpr int kRowPad = 256;                     // extra zero rows after the digit planes
 constexpr int kMaxLogN = 14;                     // ring degrees handled by the LDS-resident NTT
+constexpr int kXcds = 8;                         // accelerator complex dies (one L2 each) of an MI355X
 
 // ------------------------------------------------------------------ errors
 void set_error(const std::string& msg);
@@ -93,7 +94,9 @@ struct NttTabOwner {
 };
 
 // ------------------------------------------------------------------ handles
-enum Kind : uint32_t { kKeys = 0x4b455953, kDb = 0x44422020, kQct = 0x51435420, kRct = 0x52435420 };
+enum Kind : uint32_t {
+  kKeys = 0x4b455953, kDb = 0x44422020, kQct = 0x51435420, kRct = 0x52435420, kPlan = 0x504c414e, kServer = 0x53525652
+};
 
 struct HandleBase {
   uint32_t kind;
@@ -142,7 +145,9 @@ struct hfe_rct : hfe::HandleBase {
   const hfe_keys* keys;
   int level;
   int64_t d3, row0, rows, R_out;           // R_out = N_DB + rows
-  hfe::DevBuf out;                         // [level][d3][R_out] uint64
+  hfe::DevBuf out;                         // owned storage (empty for a view into a plan)
+  uint64_t* outp = nullptr;                // [level][d3][R_out] uint64 residues
+  bool is_view = false;                    // owned by an hfe_plan; hfe_free ignores it
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // stage boundaries when profiling
   ~hfe_rct() {
     for (auto& e : ev)
@@ -241,6 +246,34 @@ hipError_t launch_gemm_plain(const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_i8(const GemmArgs& g, int variant, hipStream_t s);
 int i8_variant_count();
 const char* i8_variant_name(int v);
+int i8_variant_tile_rows(int v);
+int i8_variant_tile_cols(int v);
+int i8_variant_wgs_per_cu(int v);  // resident workgroups per CU the configuration is sized for
+
+// Batched contraction: a device-resident table of problems sharing one database.
+struct BatchDesc {
+  const int8_t* Xd;               // [nz][5][KB][d3_pad][64] query digits of this problem
+  uint64_t* C;                    // [nz][d3][R_out] contraction output
+  int64_t row0, R_out, d3, d3_pad;
+  int64_t tile_begin;             // first tile of this problem in the launch (multiple of 8)
+  int32_t nz, pad_;
+  int32_t slot[kMaxPrimes];       // database prime slot of each z
+  Mod mod[kMaxPrimes];
+};
+struct BatchHeader {
+  int64_t total_tiles;
+  int32_t n, pad_;
+};
+struct BatchGemmArgs {
+  const BatchHeader* hdr;         // device
+  const BatchDesc* desc;          // device, hdr->n entries
+  const int8_t* Dd;               // database digits, all slots
+  int64_t KB, R_pad, n_db;
+};
+int64_t i8_batched_tiles(int variant, int64_t d3, int64_t R_out, int nz);
+
+
+hipError_t launch_gemm_i8_batched(const BatchGemmArgs& a, int variant, int grid, hipStream_t s);
 constexpr int kQueryPad = 128;                   // query columns padded to the widest i8 tile
 
 // Rescale by p: out[i][c][r] = (C[i][c][r] - centered(C_p[c][r])) * p^-1 mod q_i.
@@ -279,4 +312,55 @@ hipError_t launch_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eye
                         uint64_t* qwords, uint64_t* dbwords, uint8_t* decision, uint8_t* col_any,
                         uint8_t* eye_match, hipStream_t s);
 
+constexpr int kMaxBatch = 256;                   // problems per batched launch
+struct BatchElemHeader {
+  int64_t total;                  // elements of the launch (chunks of 256 per problem start)
+  int32_t n, pad_;
+};
+struct BatchLiftDesc {
+  const uint64_t* XT;             // [level][d3][K] query ciphertext
+  int8_t* Xd;                     // [level + 1][5][KB][d3_pad][64]
+  int64_t d3, d3_pad, elem_begin; // elements: d3_pad x KB*64
+  LiftArgs la;
+};
+struct BatchRescaleDesc {
+  const uint64_t* C;              // [level + 1][n]
+  uint64_t* out;                  // [level][n]
+  int64_t n, elem_begin;          // n = d3 x R_out
+  RescaleArgs ra;
+};
+hipError_t launch_lift_batched(const BatchElemHeader* hdr, const BatchLiftDesc* d, int64_t K, int64_t KB,
+                               int grid, hipStream_t s);
+hipError_t launch_rescale_batched(const BatchElemHeader* hdr, const BatchRescaleDesc* d, int grid, hipStream_t s);
+
+}  // namespace hfe
+
+// A reusable batched contraction: fixed workspace and descriptor tables, so that the grouped
+// launches can be captured once in a hipGraph and replayed for any batch that fits.
+struct hfe_plan : hfe::HandleBase {
+  const hfe_db* db = nullptr;
+  int max_items = 0, max_level = 0, variant = 0;
+  int64_t max_cols = 0;
+  size_t xd_cap = 0, c_cap = 0, out_cap = 0;          // workspace capacities (bytes, elements)
+  hfe::DevBuf ws_xd, ws_c, ws_out, desc;               // device workspace and descriptor tables
+  void* host_blob = nullptr;                           // pinned staging of the descriptor tables
+  size_t blob_bytes = 0;
+  hipEvent_t copied = nullptr;                         // staging may be rewritten after this
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int gemm_grid = 0, elem_grid = 0, n_last = 0;
+  std::vector<hfe_rct*> views;
+  ~hfe_plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (copied) (void)hipEventDestroy(copied);
+    if (host_blob) (void)hipHostFree(host_blob);
+    for (auto* v : views) delete v;
+  }
+};
+
+namespace hfe {
+// Decryption of a result into caller-provided scratch y ([level][d3][rows] uint64).
+hfe_status decrypt_impl(const hfe_keys* K, const hfe_rct* R, double* v, int32_t* ip, uint64_t* y, hipStream_t s);
+void destroy_server(void* handle);  // hfe_server.cpp
 }  // namespace hfe

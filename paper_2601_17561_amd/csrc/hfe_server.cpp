@@ -1,0 +1,354 @@
+// Continuous-batching server: a worker thread admits queued requests into steps (batched int8
+// CCMM + per-request decryption) on a ring of preallocated slots, each with its own stream,
+// workspace (an hfe_plan) and decryption scratch.  Completion is signalled by a host function
+// enqueued behind each step, which timestamps the requests and frees the slot.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "hfe_internal.h"
+
+namespace hfe {
+namespace {
+double now_s() {
+  using clk = std::chrono::steady_clock;
+  return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+struct Request {
+  const hfe_qct* q = nullptr;
+  int32_t* ip_out = nullptr;
+  int64_t d3 = 0;
+  int level = 0;
+  int state = 0;  // 0 queued, 1 running, 2 done, < 0 rejected
+  double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+struct Slot;
+struct StepDone {
+  hfe_server* srv;
+  int slot;
+  std::vector<uint64_t> tickets;
+};
+
+struct Slot {
+  hfe_plan* plan = nullptr;
+  hipStream_t stream = nullptr;
+  DevBuf y;
+  bool busy = false;
+  StepDone done;
+};
+
+double pct(std::vector<double> v, double p) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const size_t i = std::min(v.size() - 1, (size_t)(p * (v.size() - 1) + 0.5));
+  return v[i];
+}
+}  // namespace
+}  // namespace hfe
+
+struct hfe_server : hfe::HandleBase {
+  const hfe_db* db = nullptr;
+  int device = 0;
+  int64_t max_cols = 0;
+  int max_items = 0, max_level = 0;
+  std::vector<std::unique_ptr<hfe::Slot>> slots;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, hfe::Request> reqs;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  // statistics since creation / reset
+  std::vector<double> lat, svc;
+  int64_t submitted = 0, completed = 0, rejected = 0, steps = 0, max_queue = 0, cols_steps = 0;
+  double t_first = -1, t_last = 0, cmp = 0;
+
+  void finish_step(int si);
+  void run();
+};
+
+using namespace hfe;
+
+static void on_step_done(void* p) {
+  StepDone* d = static_cast<StepDone*>(p);
+  d->srv->finish_step(d->slot);
+}
+
+void hfe_server::finish_step(int si) {
+  std::lock_guard<std::mutex> l(mu);
+  Slot& sl = *slots[si];
+  const double t = now_s();
+  for (uint64_t tk : sl.done.tickets) {
+    auto it = reqs.find(tk);
+    if (it == reqs.end()) continue;
+    Request& r = it->second;
+    r.state = 2;
+    r.t_done = t;
+    lat.push_back((t - r.t_submit) * 1e3);
+    svc.push_back((t - r.t_admit) * 1e3);
+    ++completed;
+    cmp += (double)r.d3 * db->d1;
+    t_last = t;
+  }
+  sl.busy = false;
+  cv.notify_all();
+}
+
+void hfe_server::run() {
+  (void)hipSetDevice(device);
+  const int64_t d1 = db->d1;
+  for (;;) {
+    int si = -1;
+    std::vector<hfe_batch_item> items;
+    std::vector<uint64_t> tickets;
+    {
+      std::unique_lock<std::mutex> l(mu);
+      cv.wait(l, [&] {
+        if (stop) return true;
+        if (queue.empty()) return false;
+        for (auto& s : slots)
+          if (!s->busy) return true;
+        return false;
+      });
+      if (stop) {
+        cv.wait(l, [&] {
+          for (auto& s : slots)
+            if (s->busy) return false;
+          return true;
+        });
+        for (uint64_t tk : queue) reqs[tk].state = HFE_EBUSY;
+        queue.clear();
+        return;
+      }
+      for (size_t i = 0; i < slots.size(); ++i)
+        if (!slots[i]->busy) {
+          si = (int)i;
+          break;
+        }
+      // admission in arrival order: columns, request count and workspace of one step
+      int64_t cols = 0;
+      const double t = now_s();
+      while (!queue.empty() && (int)items.size() < max_items) {
+        Request& r = reqs[queue.front()];
+        if (r.d3 > max_cols) {
+          r.state = HFE_EBUSY;
+          r.t_done = t;
+          ++rejected;
+          queue.pop_front();
+          continue;
+        }
+        if (cols + r.d3 > max_cols) break;
+        cols += r.d3;
+        r.state = 1;
+        r.t_admit = t;
+        items.push_back({r.q, 0, d1});
+        tickets.push_back(queue.front());
+        queue.pop_front();
+      }
+      if (items.empty()) continue;
+      slots[si]->busy = true;
+      ++steps;
+      cols_steps += cols;
+    }
+    Slot& sl = *slots[si];
+    hfe_status st = hfe_plan_run(sl.plan, items.data(), (int32_t)items.size(), 1, sl.stream);
+    size_t off = 0;
+    for (size_t i = 0; st == HFE_OK && i < items.size(); ++i) {
+      const hfe_rct* view = nullptr;
+      st = hfe_plan_result(sl.plan, (int32_t)i, &view);
+      int32_t* ip_out = nullptr;
+      {
+        std::lock_guard<std::mutex> l(mu);
+        ip_out = reqs[tickets[i]].ip_out;
+      }
+      if (st == HFE_OK) st = decrypt_impl(db->keys, view, nullptr, ip_out, sl.y.as<uint64_t>() + off, sl.stream);
+      off += (size_t)view->level * view->d3 * view->rows;
+    }
+    sl.done.srv = this;
+    sl.done.slot = si;
+    sl.done.tickets = tickets;
+    hipError_t e = hipSuccess;
+    if (st == HFE_OK) e = hipLaunchHostFunc(sl.stream, on_step_done, &sl.done);
+    if (st != HFE_OK || e != hipSuccess) {
+      std::lock_guard<std::mutex> l(mu);
+      for (uint64_t tk : tickets) reqs[tk].state = st != HFE_OK ? st : HFE_EDEVICE;
+      sl.busy = false;
+      cv.notify_all();
+    }
+  }
+}
+
+namespace hfe {
+void destroy_server(void* handle) {
+  hfe_server* S = static_cast<hfe_server*>(handle);
+  {
+    std::lock_guard<std::mutex> l(S->mu);
+    S->stop = true;
+  }
+  S->cv.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  for (auto& sl : S->slots) {
+    if (sl->stream) (void)hipStreamSynchronize(sl->stream);
+    hfe_free(sl->plan);
+    sl->y.reset();
+    if (sl->stream) (void)hipStreamDestroy(sl->stream);
+  }
+  S->kind = 0;
+  delete S;
+}
+}  // namespace hfe
+
+extern "C" {
+
+hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_cols_per_step, int32_t max_items_per_step,
+                             int32_t n_slots, uint32_t max_level, hfe_server** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(db));
+  if (!db || hb->kind != kDb) return fail(HFE_EINVAL, "invalid database handle");
+  if (!(db->forms & HFE_FORM_I8_MFMA)) return fail(HFE_EINVAL, "database not prepared for the int8 form");
+  if (n_slots < 1 || n_slots > 8 || max_items_per_step < 1 || max_items_per_step > kMaxBatch ||
+      max_cols_per_step < 1 || max_level < 1 || (int)max_level > db->keys->L)
+    return fail(HFE_EINVAL, "bad server configuration");
+  // workspace per query column of one step: query digits, contraction output, result,
+  // decryption scratch (plus the column padding of each request)
+  const int64_t ndb = 1ll << db->keys->P.log_n_db, R_max = ndb + db->d1;
+  const size_t per_col = (size_t)(max_level + 1) * kDigits * db->KB * kKB + (size_t)(max_level + 1) * R_max * 8 +
+                         (size_t)max_level * R_max * 8 + (size_t)max_level * db->d1 * 8;
+  const size_t pad = (size_t)max_items_per_step * (kQueryPad - 1) * (max_level + 1) * kDigits * db->KB * kKB;
+  const size_t per_slot = mem_budget / (size_t)n_slots;
+  if (per_slot <= pad + per_col) return fail(HFE_ENOMEM, "memory budget below one column per slot");
+  const int64_t cols = std::min<int64_t>(max_cols_per_step, (int64_t)((per_slot - pad) / per_col));
+  hfe_server* S = new (std::nothrow) hfe_server();
+  if (!S) return fail(HFE_ENOMEM, "host allocation failed");
+  S->kind = kServer;
+  S->stream = nullptr;
+  S->db = db;
+  S->max_cols = cols;
+  S->max_items = max_items_per_step;
+  S->max_level = (int)max_level;
+  (void)hipGetDevice(&S->device);
+  for (int i = 0; i < n_slots; ++i) {
+    auto sl = std::make_unique<Slot>();
+    hfe_status st = hfe_plan_create(db, max_items_per_step, cols, max_level, &sl->plan);
+    if (st == HFE_OK) st = sl->y.alloc(sizeof(uint64_t) * (size_t)max_level * cols * db->d1, nullptr);
+    if (st == HFE_OK && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess)
+      st = fail(HFE_EDEVICE, "stream creation failed");
+    S->slots.push_back(std::move(sl));
+    if (st != HFE_OK) {
+      destroy_server(S);
+      return st;
+    }
+  }
+  S->worker = std::thread([S] { S->run(); });
+  *out = S;
+  return HFE_OK;
+}
+
+static hfe_server* as_server(hfe_server* s) {
+  return (s && static_cast<HandleBase*>(static_cast<void*>(s))->kind == kServer) ? s : nullptr;
+}
+
+hfe_status hfe_server_submit(hfe_server* srv, const hfe_qct* q, int32_t* ip_out, uint64_t* ticket) {
+  hfe_server* S = as_server(srv);
+  const HandleBase* qb = static_cast<const HandleBase*>(static_cast<const void*>(q));
+  if (!S || !q || qb->kind != kQct || !ip_out || !ticket) return fail(HFE_EINVAL, "invalid server, query, output or ticket");
+  if (q->keys != S->db->keys) return fail(HFE_EINVAL, "query encrypted under other keys");
+  if (q->K != S->db->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
+  if (q->level > S->max_level) return fail(HFE_ELEVEL, "query level above the server's maximum");
+  std::lock_guard<std::mutex> l(S->mu);
+  const uint64_t tk = S->next_ticket++;
+  Request& r = S->reqs[tk];
+  r.q = q;
+  r.ip_out = ip_out;
+  r.d3 = q->d3;
+  r.level = q->level;
+  r.t_submit = now_s();
+  if (S->t_first < 0) S->t_first = r.t_submit;
+  S->queue.push_back(tk);
+  ++S->submitted;
+  S->max_queue = std::max<int64_t>(S->max_queue, (int64_t)S->queue.size());
+  S->cv.notify_all();
+  *ticket = tk;
+  return HFE_OK;
+}
+
+hfe_status hfe_server_poll(hfe_server* srv, uint64_t ticket, int32_t* state) {
+  hfe_server* S = as_server(srv);
+  if (!S || !state) return fail(HFE_EINVAL, "invalid server or state");
+  std::lock_guard<std::mutex> l(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(HFE_EINVAL, "unknown ticket");
+  *state = it->second.state;
+  return HFE_OK;
+}
+
+hfe_status hfe_server_wait(hfe_server* srv, uint64_t ticket, int64_t timeout_ms) {
+  hfe_server* S = as_server(srv);
+  if (!S) return fail(HFE_EINVAL, "invalid server");
+  std::unique_lock<std::mutex> l(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(HFE_EINVAL, "unknown ticket");
+  auto ready = [&] { return it->second.state == 2 || it->second.state < 0; };
+  if (timeout_ms < 0)
+    S->cv.wait(l, ready);
+  else if (!S->cv.wait_for(l, std::chrono::milliseconds(timeout_ms), ready))
+    return fail(HFE_EBUSY, "timed out");
+  if (it->second.state < 0) return fail(it->second.state, "request rejected: larger than one step");
+  return HFE_OK;
+}
+
+hfe_status hfe_server_stats(hfe_server* srv, hfe_server_report* out) {
+  hfe_server* S = as_server(srv);
+  if (!S || !out) return fail(HFE_EINVAL, "invalid server or out");
+  std::lock_guard<std::mutex> l(S->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = S->submitted;
+  out->completed = S->completed;
+  out->rejected = S->rejected;
+  out->steps = S->steps;
+  out->max_queue = S->max_queue;
+  out->p50_ms = pct(S->lat, 0.50);
+  out->p99_ms = pct(S->lat, 0.99);
+  out->service_p50_ms = pct(S->svc, 0.50);
+  out->service_p99_ms = pct(S->svc, 0.99);
+  double sum = 0;
+  for (double x : S->lat) sum += x;
+  out->mean_ms = S->lat.empty() ? 0.0 : sum / S->lat.size();
+  out->elapsed_s = S->t_first < 0 ? 0.0 : S->t_last - S->t_first;
+  out->req_per_s = out->elapsed_s > 0 ? S->completed / out->elapsed_s : 0.0;
+  out->cmp_per_s = out->elapsed_s > 0 ? S->cmp / out->elapsed_s : 0.0;
+  out->mean_cols_per_step = S->steps ? (double)S->cols_steps / S->steps : 0.0;
+  return HFE_OK;
+}
+
+hfe_status hfe_server_reset_stats(hfe_server* srv) {
+  hfe_server* S = as_server(srv);
+  if (!S) return fail(HFE_EINVAL, "invalid server");
+  std::lock_guard<std::mutex> l(S->mu);
+  S->lat.clear();
+  S->svc.clear();
+  S->submitted = S->completed = S->rejected = S->steps = S->max_queue = S->cols_steps = 0;
+  S->t_first = -1;
+  S->t_last = 0;
+  S->cmp = 0;
+  for (auto it = S->reqs.begin(); it != S->reqs.end();) {
+    if (it->second.state == 2 || it->second.state < 0)
+      it = S->reqs.erase(it);
+    else
+      ++it;
+  }
+  return HFE_OK;
+}
+
+}  // extern "C"

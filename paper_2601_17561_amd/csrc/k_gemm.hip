@@ -122,37 +122,68 @@ __device__ __forceinline__ uint64_t horner9(const int32_t a[9], uint64_t q, uint
 }
 
 // Tile schedule: the workgroups of one launch are dealt round-robin to the 8 XCDs (each with its
-// own L2).  Workgroup i runs on XCD i % 8; its tile is chosen so that one XCD receives all
+// own L2).  Workgroup i runs on XCD i % 8; tiles are numbered so that one XCD receives all
 // query-column tiles of a database-row tile back to back, hence the database digits of that
 // tile are fetched from HBM once into that XCD's L2 and shared by its query-column tiles.
-constexpr int kXcds = 8;
+
+// One output tile of one prime of one contraction problem.
+struct I8Tile {
+  const int8_t* Xd;   // query digits of this prime: [5][KB][d3_pad][64]
+  const int8_t* Dd;   // database digits of this prime: [5][KB][R_pad][64]
+  uint64_t* C;        // output of this prime: [d3][R_out]
+  Mod m;
+  int64_t KB, R_pad, d3_pad, n_db, row0, R_out, d3;
+  int64_t r0, c0;     // tile origin: output row, query column
+};
+
+// Tile index within one prime of a problem -> (row tile, column tile), XCD-aware: tile index l
+// runs on XCD l % 8 when the launch grid is a multiple of 8 and the problem starts at a
+// multiple of 8.  Returns false for the padding tiles (row tile beyond the last one).
+__device__ __forceinline__ bool tile_coords(int64_t l, int64_t n_rt, int64_t n_ct, int64_t& rt, int64_t& ct) {
+  const int64_t xcd = l % kXcds, j = l / kXcds;
+  rt = (j / n_ct) * kXcds + xcd;
+  ct = j % n_ct;
+  return rt < n_rt;
+}
+
+__device__ __forceinline__ void store_tile(const I8Tile& T, const v16i* acc, int wq, int wr, int lane, bool accumulate) {
+  // 32x32 MFMA result layout: lane l, element j holds row (M = query) 8 (j / 4) + 4 (l / 32)
+  // + j % 4 and column (N = database row) l % 32.
+  const int64_t out_r = T.r0 + wr * 32 + (lane & 31);
+  if (out_r >= T.R_out) return;
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    const int64_t c = T.c0 + wq * 32 + 8 * (jj >> 2) + 4 * (lane >> 5) + (jj & 3);
+    if (c >= T.d3) continue;
+    int32_t a9[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) a9[u] = acc[u][jj];
+    uint64_t v = horner9(a9, T.m.q, T.m.mu);
+    uint64_t* dst = T.C + c * T.R_out + out_r;
+    if (accumulate) v = add_mod(v, *dst, T.m.q);
+    *dst = v;
+  }
+}
 
 // Workgroup tile: WR x WQ waves, each owning a 32 (query) x 32 (database row) block of the
 // output; NBUF LDS stages (1: load, barrier, compute, barrier; 2: compute one stage while the
-// next is written); WPE = waves per SIMD the register budget is sized for.
-template <int WR, int WQ, int NBUF, int WPE>
-__global__ void __launch_bounds__(64 * WR * WQ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-k_gemm_i8(GemmArgs g) {
-  constexpr int T = 64 * WR * WQ;
+// next is written).  lds: NBUF * 5 * (32 WQ + 32 WR) * kLdsRow bytes.
+template <int WR, int WQ, int NBUF>
+__device__ __forceinline__ void tile_basic(const I8Tile& T, int8_t* lds) {
+  constexpr int NT = 64 * WR * WQ;
   constexpr int BR = 32 * WR, BQ = 32 * WQ;
-  constexpr int LA = (BQ * 4 + T - 1) / T;  // 16-byte loads per thread per query digit plane
-  constexpr int LB = (BR * 4 + T - 1) / T;  // ... per database digit plane
-  __shared__ __attribute__((aligned(16))) int8_t sA[NBUF][kDigits][BQ][kLdsRow];
-  __shared__ __attribute__((aligned(16))) int8_t sB[NBUF][kDigits][BR][kLdsRow];
-  const int z = blockIdx.z;
-  const int64_t n_ct = (g.d3 + BQ - 1) / BQ, n_rt = (g.R_out + BR - 1) / BR;
-  const int64_t wg = blockIdx.x, xcd = wg % kXcds, j = wg / kXcds;
-  const int64_t rt = (j / n_ct) * kXcds + xcd, ct = j % n_ct;
-  if (rt >= n_rt) return;
-  const int8_t* __restrict__ Xd = g.Xd[z];
-  const int8_t* __restrict__ Dd = g.Dd[z];
-  const int64_t r0 = rt * BR, c0 = ct * BQ;
+  constexpr int LA = (BQ * 4 + NT - 1) / NT;  // 16-byte loads per thread per query digit plane
+  constexpr int LB = (BR * 4 + NT - 1) / NT;  // ... per database digit plane
+  auto sA = [&](int buf, int t) { return lds + ((size_t)(buf * kDigits + t) * BQ) * kLdsRow; };
+  auto sB = [&](int buf, int t) {
+    return lds + (size_t)NBUF * kDigits * BQ * kLdsRow + ((size_t)(buf * kDigits + t) * BR) * kLdsRow;
+  };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wq = wave % WQ, wr = wave / WQ;
-  const size_t planeB = (size_t)g.KB * g.R_pad * kKB, planeA = (size_t)g.KB * g.d3_pad * kKB;
-  const size_t stepB = (size_t)g.R_pad * kKB, stepA = (size_t)g.d3_pad * kKB;
+  const size_t planeB = (size_t)T.KB * T.R_pad * kKB, planeA = (size_t)T.KB * T.d3_pad * kKB;
+  const size_t stepB = (size_t)T.R_pad * kKB, stepA = (size_t)T.d3_pad * kKB;
   // global -> LDS: load i of a plane covers 16 bytes (chunk idx & 3) of tile row idx >> 2,
-  // idx = tid + i T.  Database rows map to source rows (< R_pad, zero padding); query columns
+  // idx = tid + i NT.  Database rows map to source rows (< R_pad, zero padding); query columns
   // stay below d3_pad.
   const int8_t* gA[LA];
   const int8_t* gB[LB];
@@ -160,26 +191,20 @@ k_gemm_i8(GemmArgs g) {
   int offA[LA], offB[LB];
 #pragma unroll
   for (int i = 0; i < LA; ++i) {
-    const int idx = tid + i * T;
+    const int idx = tid + i * NT;
     okA[i] = idx < BQ * 4;
     const int row = okA[i] ? idx >> 2 : 0, ch = idx & 3;
-    gA[i] = Xd + (size_t)(c0 + row) * kKB + ch * 16;
+    gA[i] = T.Xd + (size_t)(T.c0 + row) * kKB + ch * 16;
     offA[i] = row * kLdsRow + ch * 16;
   }
 #pragma unroll
   for (int i = 0; i < LB; ++i) {
-    const int idx = tid + i * T;
+    const int idx = tid + i * NT;
     okB[i] = idx < BR * 4;
     const int row = okB[i] ? idx >> 2 : 0, ch = idx & 3;
-    gB[i] = Dd + (size_t)src_row(r0 + row, g.n_db, g.row0) * kKB + ch * 16;
+    gB[i] = T.Dd + (size_t)src_row(T.r0 + row, T.n_db, T.row0) * kKB + ch * 16;
     offB[i] = row * kLdsRow + ch * 16;
   }
-  const Mod m = g.mod[z];
-  // 32x32 MFMA result layout: lane l, element j holds row (M = query) 8 (j / 4) + 4 (l / 32)
-  // + j % 4 and column (N = database row) l % 32.
-  const int64_t out_r = r0 + wr * 32 + (lane & 31);
-  uint64_t* C = g.C[z];
-
   v4i pa[kDigits][LA], pb[kDigits][LB];
   auto fetch = [&](int64_t kb) {
 #pragma unroll
@@ -197,15 +222,14 @@ k_gemm_i8(GemmArgs g) {
     for (int t = 0; t < kDigits; ++t) {
 #pragma unroll
       for (int i = 0; i < LA; ++i)
-        if (okA[i]) *reinterpret_cast<v4i*>(&sA[buf][t][0][0] + offA[i]) = pa[t][i];
+        if (okA[i]) *reinterpret_cast<v4i*>(sA(buf, t) + offA[i]) = pa[t][i];
 #pragma unroll
       for (int i = 0; i < LB; ++i)
-        if (okB[i]) *reinterpret_cast<v4i*>(&sB[buf][t][0][0] + offB[i]) = pb[t][i];
+        if (okB[i]) *reinterpret_cast<v4i*>(sB(buf, t) + offB[i]) = pb[t][i];
     }
   };
-
-  for (int64_t kb0 = 0; kb0 < g.KB; kb0 += kChunkKB) {
-    const int64_t kb1 = kb0 + kChunkKB < g.KB ? kb0 + kChunkKB : g.KB;
+  for (int64_t kb0 = 0; kb0 < T.KB; kb0 += kChunkKB) {
+    const int64_t kb1 = kb0 + kChunkKB < T.KB ? kb0 + kChunkKB : T.KB;
     v16i acc[9];
 #pragma unroll
     for (int u = 0; u < 9; ++u) acc[u] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -228,10 +252,10 @@ k_gemm_i8(GemmArgs g) {
         v4i a[kDigits];
 #pragma unroll
         for (int t = 0; t < kDigits; ++t)
-          a[t] = *reinterpret_cast<const v4i*>(&sA[cur][t][wq * 32 + (lane & 31)][koff]);
+          a[t] = *reinterpret_cast<const v4i*>(sA(cur, t) + (wq * 32 + (lane & 31)) * kLdsRow + koff);
 #pragma unroll
         for (int s = 0; s < kDigits; ++s) {
-          const v4i b = *reinterpret_cast<const v4i*>(&sB[cur][s][wr * 32 + (lane & 31)][koff]);
+          const v4i b = *reinterpret_cast<const v4i*>(sB(cur, s) + (wr * 32 + (lane & 31)) * kLdsRow + koff);
 #pragma unroll
           for (int t = 0; t < kDigits; ++t)
             acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[t], b, acc[s + t], 0, 0, 0);
@@ -240,52 +264,30 @@ k_gemm_i8(GemmArgs g) {
       if (NBUF == 2 && more) stash(cur ^ 1);
       __syncthreads();
     }
-    // Recombine this K-chunk and accumulate it into the output (first chunk stores).
-    if (out_r < g.R_out) {
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        const int64_t c = c0 + wq * 32 + 8 * (jj >> 2) + 4 * (lane >> 5) + (jj & 3);
-        if (c >= g.d3) continue;
-        int32_t a9[9];
-#pragma unroll
-        for (int u = 0; u < 9; ++u) a9[u] = acc[u][jj];
-        uint64_t v = horner9(a9, m.q, m.mu);
-        uint64_t* dst = C + c * g.R_out + out_r;
-        if (kb0) v = add_mod(v, *dst, m.q);
-        *dst = v;
-      }
-    }
+    store_tile(T, acc, wq, wr, lane, kb0 != 0);
   }
 }
 
-// Software-pipelined form of the same contraction (2 x 2 waves, 64 x 64 tile): two register
-// sets carry K-blocks i + 1 and i + 2 while block i is multiplied from LDS, and the LDS
-// stores of block i + 1 are issued between the MFMAs of block i, so that stores, global
-// loads and the one barrier per block overlap the matrix pipe.
-template <int WPE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
-k_gemm_i8_pipe(GemmArgs g) {
+// Software-pipelined tile (2 x 2 waves, 64 x 64): two register sets carry K-blocks i + 1 and
+// i + 2 while block i is multiplied from LDS, and the LDS stores of block i + 1 are issued
+// between the MFMAs of block i, so that stores, global loads and the one barrier per block
+// overlap the matrix pipe.  lds: 2 * 5 * 128 * kLdsRow bytes.
+__device__ __forceinline__ void tile_pipe(const I8Tile& T, int8_t* lds) {
   constexpr int BR = 64, BQ = 64;
-  __shared__ __attribute__((aligned(16))) int8_t sA[2][kDigits][BQ][kLdsRow];
-  __shared__ __attribute__((aligned(16))) int8_t sB[2][kDigits][BR][kLdsRow];
-  const int z = blockIdx.z;
-  const int64_t n_ct = (g.d3 + BQ - 1) / BQ, n_rt = (g.R_out + BR - 1) / BR;
-  const int64_t wg = blockIdx.x, xcd = wg % kXcds, j = wg / kXcds;
-  const int64_t rt = (j / n_ct) * kXcds + xcd, ct = j % n_ct;
-  if (rt >= n_rt) return;
-  const int64_t r0 = rt * BR, c0 = ct * BQ;
+  constexpr int planeA_l = BQ * kLdsRow, planeB_l = BR * kLdsRow;
+  auto sA = [&](int buf, int t) { return lds + ((size_t)(buf * kDigits + t) * BQ) * kLdsRow; };
+  auto sB = [&](int buf, int t) {
+    return lds + (size_t)2 * kDigits * BQ * kLdsRow + ((size_t)(buf * kDigits + t) * BR) * kLdsRow;
+  };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wq = wave & 1, wr = wave >> 1;
-  const size_t planeB = (size_t)g.KB * g.R_pad * kKB, planeA = (size_t)g.KB * g.d3_pad * kKB;
-  const size_t stepB = (size_t)g.R_pad * kKB, stepA = (size_t)g.d3_pad * kKB;
+  const size_t planeB = (size_t)T.KB * T.R_pad * kKB, planeA = (size_t)T.KB * T.d3_pad * kKB;
+  const size_t stepB = (size_t)T.R_pad * kKB, stepA = (size_t)T.d3_pad * kKB;
   const int ld_row = tid >> 2, ld_ch = tid & 3;
-  const int8_t* gA = g.Xd[z] + (size_t)(c0 + ld_row) * kKB + ld_ch * 16;
-  const int8_t* gB = g.Dd[z] + (size_t)src_row(r0 + ld_row, g.n_db, g.row0) * kKB + ld_ch * 16;
+  const int8_t* gA = T.Xd + (size_t)(T.c0 + ld_row) * kKB + ld_ch * 16;
+  const int8_t* gB = T.Dd + (size_t)src_row(T.r0 + ld_row, T.n_db, T.row0) * kKB + ld_ch * 16;
   const int st_off = ld_row * kLdsRow + ld_ch * 16;
   const int rd_a = (wq * 32 + (lane & 31)) * kLdsRow, rd_b = (wr * 32 + (lane & 31)) * kLdsRow;
-  const Mod m = g.mod[z];
-  const int64_t out_r = r0 + wr * 32 + (lane & 31);
-  uint64_t* C = g.C[z];
 
   v4i p0[2 * kDigits], p1[2 * kDigits];  // [A digits 0..4, B digits 0..4] of one K-block
   auto fetch = [&](v4i* p, int64_t kb) {
@@ -297,13 +299,13 @@ k_gemm_i8_pipe(GemmArgs g) {
   };
   auto put = [&](const v4i* p, int buf, int i) {  // i-th of the 10 16-byte stores of a block
     if (i < kDigits)
-      *reinterpret_cast<v4i*>(&sA[buf][i][0][0] + st_off) = p[i];
+      *reinterpret_cast<v4i*>(sA(buf, i) + st_off) = p[i];
     else
-      *reinterpret_cast<v4i*>(&sB[buf][i - kDigits][0][0] + st_off) = p[i];
+      *reinterpret_cast<v4i*>(sB(buf, i - kDigits) + st_off) = p[i];
   };
 
-  for (int64_t kb0 = 0; kb0 < g.KB; kb0 += kChunkKB) {
-    const int64_t kb_end = kb0 + kChunkKB < g.KB ? kb0 + kChunkKB : g.KB;
+  for (int64_t kb0 = 0; kb0 < T.KB; kb0 += kChunkKB) {
+    const int64_t kb_end = kb0 + kChunkKB < T.KB ? kb0 + kChunkKB : T.KB;
     const int64_t n = kb_end - kb0;
     v16i acc[9];
 #pragma unroll
@@ -321,9 +323,8 @@ k_gemm_i8_pipe(GemmArgs g) {
     auto block = [&](int cur, v4i* nx, v4i* ld, int64_t i) {
       fetch(ld, kb0 + i + 2 < kb_end ? kb0 + i + 2 : kb_end - 1);
       __builtin_amdgcn_sched_barrier(0);  // keep the global loads at the head of the block
-      const int8_t* A = &sA[cur][0][0][0] + rd_a;
-      const int8_t* B = &sB[cur][0][0][0] + rd_b;
-      constexpr int planeA_l = BQ * kLdsRow, planeB_l = BR * kLdsRow;
+      const int8_t* A = sA(cur, 0) + rd_a;
+      const int8_t* B = sB(cur, 0) + rd_b;
       const int k0 = (lane >> 5) * 16, k1 = 32 + (lane >> 5) * 16;
       v4i a0[kDigits], a1[kDigits], b_cur, b_nxt;
 #pragma unroll
@@ -336,8 +337,7 @@ k_gemm_i8_pipe(GemmArgs g) {
           const int hs = (step + 1) / kDigits, ss = (step + 1) % kDigits;
           b_nxt = *reinterpret_cast<const v4i*>(B + ss * planeB_l + (hs ? k1 : k0));
         }
-        if (step >= 2 && step < 2 + kDigits)
-          a1[step - 2] = *reinterpret_cast<const v4i*>(A + (step - 2) * planeA_l + k1);
+        if (step < kDigits) a1[step] = *reinterpret_cast<const v4i*>(A + step * planeA_l + k1);
         put(nx, cur ^ 1, step);
 #pragma unroll
         for (int t = 0; t < kDigits; ++t)
@@ -350,42 +350,84 @@ k_gemm_i8_pipe(GemmArgs g) {
       block(0, p1, p0, i);
       if (i + 1 < n) block(1, p0, p1, i + 1);
     }
-    if (out_r < g.R_out) {
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        const int64_t c = c0 + wq * 32 + 8 * (jj >> 2) + 4 * (lane >> 5) + (jj & 3);
-        if (c >= g.d3) continue;
-        int32_t a9[9];
-#pragma unroll
-        for (int u = 0; u < 9; ++u) a9[u] = acc[u][jj];
-        uint64_t v = horner9(a9, m.q, m.mu);
-        uint64_t* dst = C + c * g.R_out + out_r;
-        if (kb0) v = add_mod(v, *dst, m.q);
-        *dst = v;
-      }
-    }
+    store_tile(T, acc, wq, wr, lane, kb0 != 0);
+  }
+}
+
+// Grid launch: blockIdx.z = prime slot, blockIdx.x = XCD-ordered tile.
+template <int WR, int WQ, int NBUF, int WPE, bool PIPE>
+__global__ void __launch_bounds__(64 * WR * WQ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_gemm_i8(GemmArgs g) {
+  constexpr int BR = 32 * WR, BQ = 32 * WQ;
+  __shared__ __attribute__((aligned(16))) int8_t lds[NBUF * kDigits * (BQ + BR) * kLdsRow];
+  const int z = blockIdx.z;
+  const int64_t n_ct = (g.d3 + BQ - 1) / BQ, n_rt = (g.R_out + BR - 1) / BR;
+  int64_t rt, ct;
+  if (!tile_coords(blockIdx.x, n_rt, n_ct, rt, ct)) return;
+  I8Tile T{g.Xd[z], g.Dd[z], g.C[z], g.mod[z], g.KB, g.R_pad, g.d3_pad, g.n_db, g.row0, g.R_out, g.d3,
+           rt * BR, ct * BQ};
+  if (PIPE)
+    tile_pipe(T, lds);
+  else
+    tile_basic<WR, WQ, NBUF>(T, lds);
+}
+
+// Persistent grouped launch over a table of problems (batched CCMM): workgroup w processes
+// tiles w, w + G, w + 2G, ... of the concatenated tile list (G = grid size, a multiple of 8,
+// and every problem starts at a multiple of 8, so tile t always runs on XCD t % 8).
+template <int WR, int WQ, int NBUF, int WPE, bool PIPE>
+__global__ void __launch_bounds__(64 * WR * WQ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+k_gemm_i8_batched(BatchGemmArgs a) {
+  constexpr int BR = 32 * WR, BQ = 32 * WQ;
+  __shared__ __attribute__((aligned(16))) int8_t lds[NBUF * kDigits * (BQ + BR) * kLdsRow];
+  const int64_t total = a.hdr->total_tiles;
+  const int n = a.hdr->n;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int b = 0;
+    while (b + 1 < n && a.desc[b + 1].tile_begin <= t) ++b;
+    const BatchDesc& d = a.desc[b];
+    const int64_t n_ct = (d.d3 + BQ - 1) / BQ, n_rt = (d.R_out + BR - 1) / BR;
+    const int64_t per_prime = (n_rt + kXcds - 1) / kXcds * kXcds * n_ct;
+    const int64_t local = t - d.tile_begin;
+    const int z = (int)(local / per_prime);
+    int64_t rt, ct;
+    if (!tile_coords(local % per_prime, n_rt, n_ct, rt, ct)) continue;
+    const size_t planeX = (size_t)a.KB * d.d3_pad * kKB * kDigits;
+    const size_t planeD = (size_t)a.KB * a.R_pad * kKB * kDigits;
+    I8Tile T{d.Xd + z * planeX, a.Dd + d.slot[z] * planeD, d.C + (size_t)z * d.d3 * d.R_out, d.mod[z], a.KB,
+             a.R_pad, d.d3_pad, a.n_db, d.row0, d.R_out, d.d3, rt * BR, ct * BQ};
+    if (PIPE)
+      tile_pipe(T, lds);
+    else
+      tile_basic<WR, WQ, NBUF>(T, lds);
   }
 }
 
 struct I8Variant {
   const char* name;
-  void (*kernel)(GemmArgs);
-  int br, bq, threads;
+  void (*grid)(GemmArgs);
+  void (*batched)(BatchGemmArgs);
+  int br, bq, threads, waves_per_simd;
 };
 
-#define HFE_I8_VARIANT(WR, WQ, NB, WPE) \
-  { "r" #WR "q" #WQ "b" #NB "w" #WPE, k_gemm_i8<WR, WQ, NB, WPE>, 32 * (WR), 32 * (WQ), 64 * (WR) * (WQ) }
+#define HFE_I8_VARIANT(NAME, WR, WQ, NB, WPE, PIPE)                                                          \
+  {                                                                                                          \
+    NAME, k_gemm_i8<WR, WQ, NB, WPE, PIPE>, k_gemm_i8_batched<WR, WQ, NB, WPE, PIPE>, 32 * (WR), 32 * (WQ), \
+        64 * (WR) * (WQ), (WPE)                                                                              \
+  }
 
 static const I8Variant kI8Variants[] = {
-    {"pipe_w1", k_gemm_i8_pipe<1>, 64, 64, 256},
-    HFE_I8_VARIANT(2, 2, 1, 1), HFE_I8_VARIANT(2, 2, 2, 1), HFE_I8_VARIANT(2, 2, 1, 2),
-    HFE_I8_VARIANT(4, 2, 1, 2), HFE_I8_VARIANT(2, 4, 1, 2), HFE_I8_VARIANT(4, 2, 2, 2),
-    HFE_I8_VARIANT(2, 4, 2, 2),
+    HFE_I8_VARIANT("pipe_w1", 2, 2, 2, 1, true),     HFE_I8_VARIANT("r2q2b1w1", 2, 2, 1, 1, false),
+    HFE_I8_VARIANT("r2q2b2w1", 2, 2, 2, 1, false),   HFE_I8_VARIANT("r2q2b1w2", 2, 2, 1, 2, false),
+    HFE_I8_VARIANT("r4q2b1w2", 4, 2, 1, 2, false),   HFE_I8_VARIANT("r2q4b1w2", 2, 4, 1, 2, false),
 };
 constexpr int kNumI8Variants = sizeof(kI8Variants) / sizeof(kI8Variants[0]);
 
 int i8_variant_count() { return kNumI8Variants; }
 const char* i8_variant_name(int v) { return (v >= 0 && v < kNumI8Variants) ? kI8Variants[v].name : nullptr; }
+int i8_variant_tile_rows(int v) { return kI8Variants[v].br; }
+int i8_variant_tile_cols(int v) { return kI8Variants[v].bq; }
+int i8_variant_wgs_per_cu(int v) { return kI8Variants[v].waves_per_simd * 4 * 64 / kI8Variants[v].threads; }
 
 hipError_t launch_gemm_i8(const GemmArgs& g, int variant, hipStream_t s) {
   if (g.R_out <= 0 || g.d3 <= 0) return hipSuccess;
@@ -395,7 +437,20 @@ hipError_t launch_gemm_i8(const GemmArgs& g, int variant, hipStream_t s) {
   const int64_t n_ct = (g.d3 + v.bq - 1) / v.bq, n_rt = (g.R_out + v.br - 1) / v.br;
   const int64_t n_rt8 = (n_rt + kXcds - 1) / kXcds * kXcds;
   dim3 grid((unsigned)(n_rt8 * n_ct), 1, (unsigned)g.nz);
-  hipLaunchKernelGGL(v.kernel, grid, dim3(v.threads), 0, s, g);
+  hipLaunchKernelGGL(v.grid, grid, dim3(v.threads), 0, s, g);
+  return hipGetLastError();
+}
+
+int64_t i8_batched_tiles(int variant, int64_t d3, int64_t R_out, int nz) {
+  const I8Variant& v = kI8Variants[variant];
+  const int64_t n_ct = (d3 + v.bq - 1) / v.bq, n_rt = (R_out + v.br - 1) / v.br;
+  return (n_rt + kXcds - 1) / kXcds * kXcds * n_ct * nz;
+}
+
+hipError_t launch_gemm_i8_batched(const BatchGemmArgs& a, int variant, int grid, hipStream_t s) {
+  if (variant < 0 || variant >= kNumI8Variants) return hipErrorInvalidValue;
+  const I8Variant& v = kI8Variants[variant];
+  hipLaunchKernelGGL(v.batched, dim3((unsigned)grid), dim3(v.threads), 0, s, a);
   return hipGetLastError();
 }
 

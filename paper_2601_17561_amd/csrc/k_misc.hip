@@ -1,7 +1,7 @@
 // Elementwise and layout kernels around the contraction: masked ternary encoding, int8
 // transpose, digit split of the database, centered CRT lift of the query with its digit
 // split, rescale by the special prime, CRT decode, and the plaintext match decision.
-#include "hfe_internal.h"
+#include "hfe_device.h"
 
 namespace hfe {
 
@@ -62,19 +62,6 @@ hipError_t launch_transpose_i8(const int8_t* in, int64_t rows, int64_t cols, int
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ digit split
-// Centered residue x in (-q/2, q/2) -> 5 balanced base-256 digits d_t in [-128, 127]
-// (|d_4| <= 8), x = sum_t d_t 256^t.
-__device__ __forceinline__ void split5(int64_t x, int32_t d[kDigits]) {
-#pragma unroll
-  for (int t = 0; t < kDigits - 1; ++t) {
-    const int32_t lo = (int32_t)((x + 128) & 255) - 128;
-    d[t] = lo;
-    x = (x - lo) >> 8;
-  }
-  d[kDigits - 1] = (int32_t)x;
-}
-
 // Thread (row r, block kb): 64 residues Dt[kb*64 + kk][r] -> 64 bytes of each digit plane.
 __global__ void __launch_bounds__(256) k_split_db(const uint64_t* Dt, int64_t K, int64_t R, int64_t KB,
                                                   int64_t R_pad, uint64_t q, int8_t* dig) {
@@ -112,66 +99,15 @@ hipError_t launch_split_db(const uint64_t* Dt_prime, int64_t K, int64_t R, int64
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ Garner mixed radix
-// Residues y_i mod q_i -> digits v_i with Y = v_0 + v_1 q_0 + v_2 q_0 q_1 + ..., computed as
-// v_i = (y_i - sum_{j<i} v_j (q_0..q_{j-1} mod q_i)) * (q_0..q_{i-1})^-1 mod q_i.
-// garner[i][j] = q_0..q_{j-1} mod q_i for j < i, garner[i][i] = (q_0..q_{i-1})^-1 mod q_i.
-__device__ __forceinline__ void garner_digits(const uint64_t* y, int level,
-                                              const uint64_t (*garner)[HFE_MAX_QPRIMES],
-                                              const uint64_t* q, const uint64_t* mus, uint64_t* v) {
-  for (int i = 0; i < level; ++i) {
-    const uint64_t qi = q[i];
-    const uint64_t mu = mus[i];
-    uint64_t s = 0;
-    for (int j = 0; j < i; ++j)
-      s = add_mod(s, mul_mod(barrett64(v[j], qi, mu), garner[i][j], qi, mu), qi);
-    v[i] = i == 0 ? y[0] : mul_mod(sub_mod(y[i], s, qi), garner[i][i], qi, mu);
-  }
-}
-
-// Y > (Q - 1)/2, compared on mixed-radix digits from the most significant one.
-__device__ __forceinline__ bool above_half(const uint64_t* v, const uint64_t* half, int level) {
-  for (int i = level - 1; i >= 0; --i) {
-    if (v[i] != half[i]) return v[i] > half[i];
-  }
-  return false;
-}
-
 // ------------------------------------------------------------------ query lift + digit split
 // Element (c, k): residues XT[i][c][k] of L(x) mod q_i; the lift L(x) = centered CRT value in
 // (-Q/2, Q/2); L mod p.  Writes Xp[c][k] = L mod p (plain form) and, for every prime of the
 // level and p, the 5 digit planes of the centered residue (i8 form), zero in the padding.
 __global__ void __launch_bounds__(256) k_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
                                               int64_t d3_pad, LiftArgs la, uint64_t* Xp, int8_t* Xd) {
-  const int64_t kpad = KB * kKB;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = blockIdx.y;
-  if (k >= kpad) return;
-  const bool valid = c < d3 && k < K;
-  uint64_t y[HFE_MAX_QPRIMES] = {};
-  uint64_t lp = 0;
-  if (valid) {
-    for (int i = 0; i < la.level; ++i) y[i] = XT[((int64_t)i * d3 + c) * K + k];
-    uint64_t v[HFE_MAX_QPRIMES];
-    garner_digits(y, la.level, la.garner, la.q, la.mu, v);
-    const uint64_t p = la.p;
-    const uint64_t mup = la.mu_p;
-    for (int i = 0; i < la.level; ++i)
-      lp = add_mod(lp, mul_mod(barrett64(v[i], p, mup), la.mprod_p[i], p, mup), p);
-    if (above_half(v, la.half_digits, la.level)) lp = sub_mod(lp, la.Q_mod_p, p);
-    if (Xp) Xp[c * K + k] = lp;
-  }
-  if (!Xd) return;
-  const int64_t kb = k / kKB, kk = k % kKB;
-  for (int z = 0; z <= la.level; ++z) {
-    int64_t x = 0;
-    if (valid) x = z < la.level ? centered(y[z], la.q[z]) : centered(lp, la.p);
-    int32_t d[kDigits];
-    split5(x, d);
-#pragma unroll
-    for (int t = 0; t < kDigits; ++t)
-      Xd[((((int64_t)z * kDigits + t) * KB + kb) * d3_pad + c) * kKB + kk] = (int8_t)d[t];
-  }
+  if (k >= KB * kKB) return;
+  lift_element(XT, d3, K, KB, d3_pad, la, Xp, Xd, blockIdx.y, k);
 }
 
 hipError_t launch_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
@@ -188,15 +124,8 @@ hipError_t launch_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, in
 __global__ void k_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, RescaleArgs ra,
                           uint64_t* out) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cp = centered(Cp[e], ra.p);
-    for (int i = 0; i < ra.level; ++i) {
-      const Mod& m = ra.mod[i];
-      const uint64_t r = from_signed(cp, m.q, m.mu);
-      const uint64_t d = sub_mod(C[(int64_t)i * n + e], r, m.q);
-      out[(int64_t)i * n + e] = mul_shoup(d, ra.pinv[i], ra.pinv_sh[i], m.q);
-    }
-  }
+       e += (int64_t)gridDim.x * blockDim.x)
+    rescale_element(C, Cp, n, ra, out, e);
 }
 
 hipError_t launch_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, const RescaleArgs& ra,
