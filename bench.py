@@ -79,6 +79,121 @@ def cpu_baseline(w: S.Workload, inp, rows_sample: int, cols_sample: int):
                 seconds=dt)
 
 
+def encrypt_database(H, torch, w, forms):
+    inp_db = S.db_templates(w.seed, w.d1, w.d2)
+    P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
+    keys = H.hfe_keygen(P, KEY_SEED)
+    dev = torch.device("cuda", 0)
+    m_db = H.hfe_encode(torch.from_numpy(inp_db[0]).to(dev), torch.from_numpy(inp_db[1]).to(dev), [0])
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, forms)
+    torch.cuda.synchronize()
+    return keys, db
+
+
+def encrypt_eyes(H, torch, keys, w, stream_id, eyes, level, shifts):
+    dev = torch.device("cuda", 0)
+    codes, masks = S.random_eyes(w.seed, stream_id, eyes, w.d2)
+    m_q = H.hfe_encode(torch.from_numpy(codes).to(dev), torch.from_numpy(masks).to(dev), shifts)
+    return H.hfe_encrypt(keys, m_q, level, Q_SEED + stream_id)
+
+
+def run_batched(args, H, torch):
+    """Uneven batch: items of 1-64 eyes x 16 shifts at levels 1-5 (2-6 primes with p) against
+    database shards of 2,048-14,336 codes, as one reusable plan (three grouped launches captured
+    in a hipGraph), against the same items as one hfe_ccmm call each."""
+    w = S.PAPER_SHARE_L5
+    n_db, K = 1 << w.log_n_db, w.d2 + (1 << w.log_n_q)
+    mix = S.batched_mix(w.seed, args.batch_items, w.d1, 64, w.n_q_primes, 2048)
+    shifts = [int(x) for x in S.default_shifts(16)]
+    log(f"batched: encrypting the {w.d1}-code database with {w.n_q_primes} query primes + p (int8 form)")
+    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA)
+    items = []
+    for i, it in enumerate(mix):
+        items.append((encrypt_eyes(H, torch, keys, w, i, it.eyes, it.level, shifts), it.row0, it.rows))
+    torch.cuda.synchronize()
+    cols = sum(it.eyes * 16 for it in mix)
+    ops = sum(50 * (n_db + it.rows) * K * it.eyes * 16 * (it.level + 1) for it in mix)
+    comparisons = sum(it.rows * it.eyes * 16 for it in mix)
+    log(f"batched: {len(mix)} items, {cols} query columns, {ops / 1e15:.2f} P int8 ops; autotuning")
+    big = max(range(len(mix)), key=lambda i: mix[i].eyes * mix[i].level)
+    tuned = H.hfe_autotune(db, items[big][0], items[big][1], items[big][2], reps=1)
+    plan = H.hfe_plan_create(db, len(items), cols, w.n_q_primes)
+    H.hfe_plan_run(plan, items, use_graph=True)       # captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        H.hfe_plan_run(plan, items, use_graph=True)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    same = all(np.array_equal(H.hfe_export(H.hfe_plan_result(plan, i), 0, 0, 1 << 16),
+                              H.hfe_export(H.hfe_ccmm(db, q, r0, nr, H.HFE_FORM_I8_MFMA), 0, 0, 1 << 16))
+               for i, (q, r0, nr) in list(enumerate(items))[:4])
+    plan.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, r0, nr in items:
+        H.hfe_ccmm(db, q, r0, nr, H.HFE_FORM_I8_MFMA).free()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    tops = ops / (plan_ms * 1e-3) / 1e12
+    line = {"metric": "batched encrypted CCMM, int8 ops/s (one persistent launch per stage, hipGraph)",
+            "value": tops, "unit": "TOP/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
+            "ms_per_batch": plan_ms, "comparisons_per_s": comparisons / (plan_ms * 1e-3),
+            "frac_of_peak": tops / PEAK_I8_TOPS, "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / plan_ms,
+            "same_residues_as_single_calls": bool(same), "tile": H.hfe_i8_variant_name(tuned), "dtype": "i8",
+            "data": "synthetic",
+            "config": {"workload": "batched_" + w.name, "items": len(mix), "eyes": "1-64", "shifts": 16,
+                       "levels": "1-5 query primes + p", "rows": "2048-14336", "columns": cols}}
+    print(json.dumps(line), flush=True)
+
+
+def run_serving(args, H, torch):
+    """Poisson arrivals of 1-32 eyes x 16 shifts against the resident share database, through
+    the continuous-batching server; throughput and arrival-to-result latency percentiles."""
+    w = S.PAPER_SHARE
+    shifts = [int(x) for x in S.default_shifts(16)]
+    log(f"serving: encrypting the {w.d1}-code database (int8 form)")
+    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA)
+    dev = torch.device("cuda", 0)
+    lines = []
+    for rate in args.rates:
+        n = max(8, int(rate * args.serve_seconds))
+        t_arr, eyes = S.poisson_arrivals(w.seed + int(rate), n, rate, 32)
+        log(f"serving: {n} requests at {rate} req/s, encrypting them client-side")
+        reqs = [encrypt_eyes(H, torch, keys, w, 1000 + i, int(e), w.level, shifts) for i, e in enumerate(eyes)]
+        outs = [torch.empty((int(e) * 16, w.d1), dtype=torch.int32, device=dev) for e in eyes]
+        torch.cuda.synchronize()
+        srv = H.hfe_server_create(db, args.serve_budget_gib << 30, args.serve_cols, 64, 2, w.level)
+        tickets = []
+        t0 = time.perf_counter()
+        for i in range(n):
+            wait = t0 + t_arr[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            tickets.append(H.hfe_server_submit(srv, reqs[i], outs[i]))
+        for t in tickets:
+            H.hfe_server_wait(srv, t, 600000)
+        dt = time.perf_counter() - t0
+        st = H.hfe_server_stats(srv)
+        srv.free()
+        cmp = int(eyes.sum()) * 16 * w.d1
+        line = {"metric": "encrypted 1:N serving, comparisons/s with continuous batching",
+                "value": cmp / dt, "unit": "comparisons/s", "n_gpus": 1, "higher_is_better": True,
+                "offered_req_per_s": rate, "requests": n, "served_req_per_s": n / dt,
+                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "service_p50_ms": st["service_p50_ms"],
+                "service_p99_ms": st["service_p99_ms"], "steps": st["steps"],
+                "mean_cols_per_step": st["mean_cols_per_step"], "max_queue": st["max_queue"],
+                "rejected": st["rejected"], "dtype": "i8", "data": "synthetic",
+                "config": {"workload": "serving_" + w.name, "eyes": "1-32", "shifts": 16,
+                           "arrivals": f"poisson {rate}/s", "max_cols_per_step": args.serve_cols,
+                           "slots": 2, "mem_budget_gib": args.serve_budget_gib}}
+        print(json.dumps(line), flush=True)
+        lines.append(line)
+        del reqs, outs
+        torch.cuda.synchronize()
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +207,14 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time every int8 tile configuration and exit")
     ap.add_argument("--variant", type=int, default=-1, help="int8 tile configuration (-1: default)")
     ap.add_argument("--ccmm-only", type=int, default=0, help="run N int8 CCMMs after setup and exit (profiling)")
+    ap.add_argument("--mode", choices=("step", "batched", "serving"), default="step",
+                    help="step: the hot-path step (default); batched: 64 uneven items as one plan; "
+                         "serving: Poisson arrivals through the server")
+    ap.add_argument("--batch-items", type=int, default=64)
+    ap.add_argument("--rates", type=float, nargs="+", default=[200.0, 40.0], help="serving arrival rates, req/s")
+    ap.add_argument("--serve-seconds", type=float, default=1.5, help="serving: seconds of arrivals per rate")
+    ap.add_argument("--serve-cols", type=int, default=1024, help="serving: query columns per step")
+    ap.add_argument("--serve-budget-gib", type=int, default=16, help="serving: workspace memory budget")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="with --ccmm-only: also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -103,6 +226,10 @@ def main():
     import torch
     import paper_2601_17561_amd as H
 
+    if args.mode == "batched":
+        return run_batched(args, H, torch)
+    if args.mode == "serving":
+        return run_serving(args, H, torch)
     w = S.WORKLOADS[args.workload]
     work = algorithmic_work(w)
     dev = torch.device("cuda", 0)

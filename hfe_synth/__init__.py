@@ -124,7 +124,51 @@ TINY_MULTI = Workload("tinymulti_ndb128_nq512_d1_256_d2_1024_q4", 7, 9, 2, 2, 25
 PAPER_SHARE = Workload("share_ndb16384_nq8192_L3p_d1_14336_d2_12800_q512", 14, 13, 3, 3,
                        14336, 12800, 32, 16, seed=BASE_SEED + 2)
 
-WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, PAPER_SHARE)}
+
+
+# Database of the batched workload: the share's shapes with five query primes, so that batch
+# items can run at levels 1..5 (2..6 primes with the special prime).
+PAPER_SHARE_L5 = dataclasses.replace(PAPER_SHARE, name="share_ndb16384_nq8192_L5p_d1_14336_d2_12800",
+                                     n_q_primes=5, level=5)
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchItemSpec:
+    eyes: int       # query eyes of the item (columns = eyes * shifts)
+    level: int      # query primes used
+    row0: int       # first database code of the item's shard
+    rows: int       # codes in the shard
+
+
+def batched_mix(seed: int, n_items: int, d1: int, max_eyes: int, max_level: int,
+                min_rows: int) -> Tuple[BatchItemSpec, ...]:
+    """Uneven batch items: eyes ~ U{1..max_eyes}, level ~ U{1..max_level}, shard size
+    ~ U{min_rows..d1} codes at a uniform offset."""
+    g = _rng(seed, 4)
+    out = []
+    for _ in range(n_items):
+        rows = int(g.integers(min_rows, d1 + 1))
+        out.append(BatchItemSpec(eyes=int(g.integers(1, max_eyes + 1)), level=int(g.integers(1, max_level + 1)),
+                                 row0=int(g.integers(0, d1 - rows + 1)), rows=rows))
+    return tuple(out)
+
+
+def poisson_arrivals(seed: int, n: int, rate: float, max_eyes: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Arrival times (seconds from 0; exponential gaps of mean 1/rate) and eyes ~ U{1..max_eyes}."""
+    g = _rng(seed, 5)
+    t = np.cumsum(g.exponential(1.0 / rate, n))
+    return t - t[0], g.integers(1, max_eyes + 1, n)
+
+
+def random_eyes(seed: int, stream: int, n_eyes: int, d2: int, p_code: float = 0.5,
+                p_mask: float = 0.9) -> Tuple[np.ndarray, np.ndarray]:
+    """Fresh query eyes (codes, masks), uint8 0/1 of shape (n_eyes, d2)."""
+    g = _rng(seed, 100 + stream)
+    return ((g.random((n_eyes, d2)) < p_code).astype(np.uint8),
+            (g.random((n_eyes, d2)) < p_mask).astype(np.uint8))
+
+
+WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, PAPER_SHARE, PAPER_SHARE_L5)}
 
 
 def planted_for(w: Workload, count: int = 4) -> Tuple[Planted, ...]:

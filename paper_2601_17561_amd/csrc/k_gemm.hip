@@ -354,32 +354,132 @@ __device__ __forceinline__ void tile_pipe(const I8Tile& T, int8_t* lds) {
   }
 }
 
+// Tile fed by direct global-to-LDS loads (global_load_lds_dwordx4: each lane's 16 bytes land
+// at M0 + 16 * lane), three LDS stages, so block i + 2 is in flight while block i is
+// multiplied and no registers stage the data.  Rows are 64 bytes without padding; the 16-byte
+// chunk c of row r sits at chunk position c ^ ((r >> 2) & 3), which makes the b128 fragment
+// reads of 16 consecutive rows hit 64 distinct banks.  Wait counts are managed here: each
+// thread issues 10 loads per block (5 query planes, 5 database planes) and waits until only
+// the two younger blocks are outstanding before the barrier that publishes a stage.
+// lds: 3 stages x 2 operands x 5 planes x 64 rows x 64 bytes = 122,880 bytes.
+constexpr int kDmaStages = 3;
+constexpr int kDmaPlane = 64 * kKB;  // one digit plane of a 64-row tile
+
+__device__ __forceinline__ void dma16(const int8_t* g, uint32_t lds_addr) {
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+               :
+               : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
+               : "memory", "m0");
+}
+
+__device__ __forceinline__ void tile_dma(const I8Tile& T, int8_t* lds) {
+  constexpr int BR = 64, BQ = 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wq = wave & 1, wr = wave >> 1;
+  const size_t planeB = (size_t)T.KB * T.R_pad * kKB, planeA = (size_t)T.KB * T.d3_pad * kKB;
+  const size_t stepB = (size_t)T.R_pad * kKB, stepA = (size_t)T.d3_pad * kKB;
+  // loads: wave w fills rows 16 w .. 16 w + 15 of every plane; lane l -> row 16 w + l / 4,
+  // stored chunk l % 4, which holds logical chunk (l % 4) ^ ((row >> 2) & 3)
+  const int ld_row = 16 * wave + (lane >> 2);
+  const int ld_chunk = (lane & 3) ^ ((ld_row >> 2) & 3);
+  const int8_t* gA = T.Xd + (size_t)(T.c0 + ld_row) * kKB + ld_chunk * 16;
+  const int8_t* gB = T.Dd + (size_t)src_row(T.r0 + ld_row, T.n_db, T.row0) * kKB + ld_chunk * 16;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)lds + wave * 1024;
+  auto plane_off = [](int stage, int opnd, int t) { return ((stage * 2 + opnd) * kDigits + t) * kDmaPlane; };
+  auto issue = [&](int stage, int64_t kb) {
+#pragma unroll
+    for (int t = 0; t < kDigits; ++t) {
+      dma16(gA + t * planeA + kb * stepA, lds0 + plane_off(stage, 0, t));
+      dma16(gB + t * planeB + kb * stepB, lds0 + plane_off(stage, 1, t));
+    }
+  };
+  // fragment reads: row r, logical chunk c -> byte r * 64 + ((c ^ ((r >> 2) & 3)) * 16)
+  const int ra = wq * 32 + (lane & 31), rb = wr * 32 + (lane & 31);
+  const int swa = (ra >> 2) & 3, swb = (rb >> 2) & 3;
+  const int c0 = lane >> 5;  // logical chunk of the first half; the second half adds 2
+
+  for (int64_t kb0 = 0; kb0 < T.KB; kb0 += kChunkKB) {
+    const int64_t kb_end = kb0 + kChunkKB < T.KB ? kb0 + kChunkKB : T.KB;
+    const int64_t n = kb_end - kb0;
+    auto clamp = [&](int64_t i) { return kb0 + (i < n ? i : n - 1); };
+    v16i acc[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) acc[u] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    issue(0, clamp(0));
+    issue(1, clamp(1));
+    for (int64_t i = 0; i < n; ++i) {
+      const int st = (int)(i % kDmaStages);
+      // block i complete for this wave (blocks i + 1 may still fly), then for all waves; all
+      // waves are also done reading the stage that block i + 2 overwrites
+      asm volatile("s_waitcnt vmcnt(10) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      issue((int)((i + 2) % kDmaStages), clamp(i + 2));
+      const int8_t* A = lds + plane_off(st, 0, 0) + ra * kKB;
+      const int8_t* B = lds + plane_off(st, 1, 0) + rb * kKB;
+      auto fa = [&](int t, int c) {
+        return *reinterpret_cast<const v4i*>(A + t * kDmaPlane + ((c ^ swa) << 4));
+      };
+      auto fb = [&](int t, int c) {
+        return *reinterpret_cast<const v4i*>(B + t * kDmaPlane + ((c ^ swb) << 4));
+      };
+      v4i a0[kDigits], a1[kDigits], b_cur, b_nxt;
+#pragma unroll
+      for (int t = 0; t < kDigits; ++t) a0[t] = fa(t, c0);
+      b_cur = fb(0, c0);
+#pragma unroll
+      for (int step = 0; step < 2 * kDigits; ++step) {
+        const int half = step / kDigits, s = step % kDigits;
+        if (step + 1 < 2 * kDigits) b_nxt = fb((step + 1) % kDigits, c0 + 2 * ((step + 1) / kDigits));
+        if (step < kDigits) a1[step] = fa(step, c0 + 2);
+#pragma unroll
+        for (int t = 0; t < kDigits; ++t)
+          acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(half ? a1[t] : a0[t], b_cur, acc[s + t], 0, 0, 0);
+        b_cur = b_nxt;
+      }
+    }
+    // drain the clamped loads still in flight before the stages are reused
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    store_tile(T, acc, wq, wr, lane, kb0 != 0);
+  }
+}
+
 // Grid launch: blockIdx.z = prime slot, blockIdx.x = XCD-ordered tile.
-template <int WR, int WQ, int NBUF, int WPE, bool PIPE>
+template <int WR, int WQ, int NBUF, int WPE, int MODE>
+constexpr int lds_bytes() {
+  return MODE == 2 ? kDmaStages * 2 * kDigits * kDmaPlane : NBUF * kDigits * (32 * WQ + 32 * WR) * kLdsRow;
+}
+
+template <int WR, int WQ, int NBUF, int WPE, int MODE>
+__device__ __forceinline__ void run_tile(const I8Tile& T, int8_t* lds) {
+  if constexpr (MODE == 2)
+    tile_dma(T, lds);
+  else if constexpr (MODE == 1)
+    tile_pipe(T, lds);
+  else
+    tile_basic<WR, WQ, NBUF>(T, lds);
+}
+
+template <int WR, int WQ, int NBUF, int WPE, int MODE>
 __global__ void __launch_bounds__(64 * WR * WQ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_gemm_i8(GemmArgs g) {
   constexpr int BR = 32 * WR, BQ = 32 * WQ;
-  __shared__ __attribute__((aligned(16))) int8_t lds[NBUF * kDigits * (BQ + BR) * kLdsRow];
+  __shared__ __attribute__((aligned(16))) int8_t lds[lds_bytes<WR, WQ, NBUF, WPE, MODE>()];
   const int z = blockIdx.z;
   const int64_t n_ct = (g.d3 + BQ - 1) / BQ, n_rt = (g.R_out + BR - 1) / BR;
   int64_t rt, ct;
   if (!tile_coords(blockIdx.x, n_rt, n_ct, rt, ct)) return;
   I8Tile T{g.Xd[z], g.Dd[z], g.C[z], g.mod[z], g.KB, g.R_pad, g.d3_pad, g.n_db, g.row0, g.R_out, g.d3,
            rt * BR, ct * BQ};
-  if (PIPE)
-    tile_pipe(T, lds);
-  else
-    tile_basic<WR, WQ, NBUF>(T, lds);
+  run_tile<WR, WQ, NBUF, WPE, MODE>(T, lds);
 }
 
 // Persistent grouped launch over a table of problems (batched CCMM): workgroup w processes
 // tiles w, w + G, w + 2G, ... of the concatenated tile list (G = grid size, a multiple of 8,
 // and every problem starts at a multiple of 8, so tile t always runs on XCD t % 8).
-template <int WR, int WQ, int NBUF, int WPE, bool PIPE>
+template <int WR, int WQ, int NBUF, int WPE, int MODE>
 __global__ void __launch_bounds__(64 * WR * WQ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_gemm_i8_batched(BatchGemmArgs a) {
   constexpr int BR = 32 * WR, BQ = 32 * WQ;
-  __shared__ __attribute__((aligned(16))) int8_t lds[NBUF * kDigits * (BQ + BR) * kLdsRow];
+  __shared__ __attribute__((aligned(16))) int8_t lds[lds_bytes<WR, WQ, NBUF, WPE, MODE>()];
   const int64_t total = a.hdr->total_tiles;
   const int n = a.hdr->n;
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
@@ -396,10 +496,7 @@ k_gemm_i8_batched(BatchGemmArgs a) {
     const size_t planeD = (size_t)a.KB * a.R_pad * kKB * kDigits;
     I8Tile T{d.Xd + z * planeX, a.Dd + d.slot[z] * planeD, d.C + (size_t)z * d.d3 * d.R_out, d.mod[z], a.KB,
              a.R_pad, d.d3_pad, a.n_db, d.row0, d.R_out, d.d3, rt * BR, ct * BQ};
-    if (PIPE)
-      tile_pipe(T, lds);
-    else
-      tile_basic<WR, WQ, NBUF>(T, lds);
+    run_tile<WR, WQ, NBUF, WPE, MODE>(T, lds);
   }
 }
 
@@ -410,16 +507,18 @@ struct I8Variant {
   int br, bq, threads, waves_per_simd;
 };
 
-#define HFE_I8_VARIANT(NAME, WR, WQ, NB, WPE, PIPE)                                                          \
+#define HFE_I8_VARIANT(NAME, WR, WQ, NB, WPE, MODE)                                                          \
   {                                                                                                          \
-    NAME, k_gemm_i8<WR, WQ, NB, WPE, PIPE>, k_gemm_i8_batched<WR, WQ, NB, WPE, PIPE>, 32 * (WR), 32 * (WQ), \
+    NAME, k_gemm_i8<WR, WQ, NB, WPE, MODE>, k_gemm_i8_batched<WR, WQ, NB, WPE, MODE>, 32 * (WR), 32 * (WQ), \
         64 * (WR) * (WQ), (WPE)                                                                              \
   }
 
+// MODE 0: tile_basic, 1: tile_pipe, 2: tile_dma.  The first entry is the default.
 static const I8Variant kI8Variants[] = {
-    HFE_I8_VARIANT("pipe_w1", 2, 2, 2, 1, true),     HFE_I8_VARIANT("r2q2b1w1", 2, 2, 1, 1, false),
-    HFE_I8_VARIANT("r2q2b2w1", 2, 2, 2, 1, false),   HFE_I8_VARIANT("r2q2b1w2", 2, 2, 1, 2, false),
-    HFE_I8_VARIANT("r4q2b1w2", 4, 2, 1, 2, false),   HFE_I8_VARIANT("r2q4b1w2", 2, 4, 1, 2, false),
+    HFE_I8_VARIANT("pipe_w1", 2, 2, 2, 1, 1),     HFE_I8_VARIANT("dma3_w1", 2, 2, 3, 1, 2),
+    HFE_I8_VARIANT("r2q2b1w1", 2, 2, 1, 1, 0),    HFE_I8_VARIANT("r2q2b2w1", 2, 2, 2, 1, 0),
+    HFE_I8_VARIANT("r2q2b1w2", 2, 2, 1, 2, 0),    HFE_I8_VARIANT("r4q2b1w2", 4, 2, 1, 2, 0),
+    HFE_I8_VARIANT("r2q4b1w2", 2, 4, 1, 2, 0),
 };
 constexpr int kNumI8Variants = sizeof(kI8Variants) / sizeof(kI8Variants[0]);
 

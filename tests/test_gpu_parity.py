@@ -126,6 +126,24 @@ def test_ccmm_result_bit_exact(name, row0, rows, form):
         assert bad.size == 0, f"{form} prime {i}: {len(bad)} mismatches, first {bad[:3].tolist()}"
 
 
+@pytest.mark.parametrize("name,row0,rows", CASES, ids=IDS)
+def test_every_i8_tile_configuration_bit_exact(name, row0, rows):
+    """Each int8 tile configuration (register-staged, pipelined, LDS-DMA) gives the oracle's residues."""
+    g = run_for(name, row0, rows)
+    c = g.c
+    try:
+        for v in range(H.hfe_i8_variants()):
+            H.hfe_set_i8_variant(v)
+            _say(f"[gpu] {c.w.name}: ccmm i8 tile {H.hfe_i8_variant_name(v)}")
+            r = g.ccmm("i8")
+            out = H.hfe_export(r, 0).reshape(c.w.level, c.m_q.shape[0], c.P.n_db + c.rows).astype(np.int64)
+            for i in range(c.w.level):
+                bad = np.argwhere(out[i] != c.out[i])
+                assert bad.size == 0, f"{H.hfe_i8_variant_name(v)} prime {i}: {len(bad)} mismatches"
+    finally:
+        H.hfe_set_i8_variant(-1)
+
+
 @pytest.mark.parametrize("form", ["plain", "i8"])
 @pytest.mark.parametrize("name,row0,rows", CASES, ids=IDS)
 def test_decrypt_and_match_equal_popcount_truth(name, row0, rows, form):
