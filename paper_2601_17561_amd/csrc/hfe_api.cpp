@@ -784,6 +784,7 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
                                  reinterpret_cast<const BatchLiftDesc*>(dblob + L.ld), D->K, D->KB, elem_grid, s));
   BatchGemmArgs a;
   a.hdr = reinterpret_cast<const BatchHeader*>(dblob + L.gh);
+  a.next = const_cast<uint32_t*>(a.hdr->next);
   a.desc = reinterpret_cast<const BatchDesc*>(dblob + L.gd);
   a.Dd = D->digits.as<int8_t>();
   a.KB = D->KB;

@@ -261,11 +261,13 @@ struct BatchDesc {
   Mod mod[kMaxPrimes];
 };
 struct BatchHeader {
-  int64_t total_tiles;
+  int64_t total_tiles;            // multiple of kXcds
   int32_t n, pad_;
+  uint32_t next[kXcds];           // tiles claimed per XCD; zero in every uploaded table
 };
 struct BatchGemmArgs {
   const BatchHeader* hdr;         // device
+  uint32_t* next;                 // device, hdr->next
   const BatchDesc* desc;          // device, hdr->n entries
   const int8_t* Dd;               // database digits, all slots
   int64_t KB, R_pad, n_db;

@@ -355,15 +355,15 @@ __device__ __forceinline__ void tile_pipe(const I8Tile& T, int8_t* lds) {
 }
 
 // Tile fed by direct global-to-LDS loads (global_load_lds_dwordx4: each lane's 16 bytes land
-// at M0 + 16 * lane), three LDS stages, so block i + 2 is in flight while block i is
-// multiplied and no registers stage the data.  Rows are 64 bytes without padding; the 16-byte
-// chunk c of row r sits at chunk position c ^ ((r >> 2) & 3), which makes the b128 fragment
-// reads of 16 consecutive rows hit 64 distinct banks.  Wait counts are managed here: each
-// thread issues 10 loads per block (5 query planes, 5 database planes) and waits until only
-// the two younger blocks are outstanding before the barrier that publishes a stage.
-// lds: 3 stages x 2 operands x 5 planes x 64 rows x 64 bytes = 122,880 bytes.
-constexpr int kDmaStages = 3;
-constexpr int kDmaPlane = 64 * kKB;  // one digit plane of a 64-row tile
+// at M0 + 16 * lane, so one instruction of a wave fills 16 rows of 64 bytes), STAGES LDS stages,
+// so later K-blocks are in flight while block i is multiplied and no registers stage the data.
+// WR x WQ waves, each owning a 32 (query) x 32 (database row) output block.  Rows are 64 bytes
+// without padding; the 16-byte chunk c of row r sits at chunk position c ^ ((r >> 2) & 3), which
+// makes the b128 fragment reads of 16 consecutive rows hit 64 distinct banks.  Wait counts are
+// managed here: with three stages every wave issues the same number of loads per block and waits
+// until only the next block's are outstanding, with two stages it waits for all.
+// lds: STAGES x 5 x (32 WQ + 32 WR) rows x 64 bytes.
+constexpr int kDmaRow = kKB;  // LDS bytes per tile row
 
 __device__ __forceinline__ void dma16(const int8_t* g, uint32_t lds_addr) {
   asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
@@ -372,31 +372,48 @@ __device__ __forceinline__ void dma16(const int8_t* g, uint32_t lds_addr) {
                : "memory", "m0");
 }
 
+template <int WR, int WQ, int STAGES>
 __device__ __forceinline__ void tile_dma(const I8Tile& T, int8_t* lds) {
-  constexpr int BR = 64, BQ = 64;
+  constexpr int NW = WR * WQ, BR = 32 * WR, BQ = 32 * WQ;
+  constexpr int kPA = BQ * kDmaRow, kPB = BR * kDmaRow, kStage = kDigits * (kPA + kPB);
+  constexpr int LA = (BQ / 16 + NW - 1) / NW, LB = (BR / 16 + NW - 1) / NW;  // loads per wave per plane
+  static_assert(STAGES == 2 || (STAGES == 3 && BQ / 16 % NW == 0 && BR / 16 % NW == 0),
+                "three stages need the same load count on every wave");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wq = wave & 1, wr = wave >> 1;
+  const int wq = wave % WQ, wr = wave / WQ;
   const size_t planeB = (size_t)T.KB * T.R_pad * kKB, planeA = (size_t)T.KB * T.d3_pad * kKB;
   const size_t stepB = (size_t)T.R_pad * kKB, stepA = (size_t)T.d3_pad * kKB;
-  // loads: wave w fills rows 16 w .. 16 w + 15 of every plane; lane l -> row 16 w + l / 4,
-  // stored chunk l % 4, which holds logical chunk (l % 4) ^ ((row >> 2) & 3)
+  // load j of a wave fills plane rows 16 (wave + NW j) .. + 15: lane l -> row + l / 4, stored
+  // chunk l % 4, which holds logical chunk (l % 4) ^ ((row >> 2) & 3) (the same for every j,
+  // since 16 NW j is a multiple of 16)
   const int ld_row = 16 * wave + (lane >> 2);
-  const int ld_chunk = (lane & 3) ^ ((ld_row >> 2) & 3);
-  const int8_t* gA = T.Xd + (size_t)(T.c0 + ld_row) * kKB + ld_chunk * 16;
-  const int8_t* gB = T.Dd + (size_t)src_row(T.r0 + ld_row, T.n_db, T.row0) * kKB + ld_chunk * 16;
-  const uint32_t lds0 = (uint32_t)(uintptr_t)lds + wave * 1024;
-  auto plane_off = [](int stage, int opnd, int t) { return ((stage * 2 + opnd) * kDigits + t) * kDmaPlane; };
+  const int ld_chunk = ((lane & 3) ^ ((ld_row >> 2) & 3)) * 16;
+  const int8_t* gA[LA];
+  const int8_t* gB[LB];
+#pragma unroll
+  for (int j = 0; j < LA; ++j) gA[j] = T.Xd + (size_t)(T.c0 + ld_row + 16 * NW * j) * kKB + ld_chunk;
+#pragma unroll
+  for (int j = 0; j < LB; ++j)
+    gB[j] = T.Dd + (size_t)src_row(T.r0 + ld_row + 16 * NW * j, T.n_db, T.row0) * kKB + ld_chunk;
+  const uint32_t lds0 = (uint32_t)(uintptr_t)lds + wave * 16 * kDmaRow;
   auto issue = [&](int stage, int64_t kb) {
+    const uint32_t base = lds0 + stage * kStage;
 #pragma unroll
     for (int t = 0; t < kDigits; ++t) {
-      dma16(gA + t * planeA + kb * stepA, lds0 + plane_off(stage, 0, t));
-      dma16(gB + t * planeB + kb * stepB, lds0 + plane_off(stage, 1, t));
+#pragma unroll
+      for (int j = 0; j < LA; ++j)
+        if (16 * (wave + NW * j) < BQ) dma16(gA[j] + t * planeA + kb * stepA, base + t * kPA + 16 * NW * j * kDmaRow);
+#pragma unroll
+      for (int j = 0; j < LB; ++j)
+        if (16 * (wave + NW * j) < BR)
+          dma16(gB[j] + t * planeB + kb * stepB, base + kDigits * kPA + t * kPB + 16 * NW * j * kDmaRow);
     }
   };
-  // fragment reads: row r, logical chunk c -> byte r * 64 + ((c ^ ((r >> 2) & 3)) * 16)
-  const int ra = wq * 32 + (lane & 31), rb = wr * 32 + (lane & 31);
-  const int swa = (ra >> 2) & 3, swb = (rb >> 2) & 3;
-  const int c0 = lane >> 5;  // logical chunk of the first half; the second half adds 2
+  // fragment reads: row r, logical chunk c -> byte r * 64 + ((c ^ ((r >> 2) & 3)) * 16); the
+  // query row wq 32 + l % 32 and database row wr 32 + l % 32 share the swizzle
+  const int sw = ((lane & 31) >> 2) & 3;
+  const int offA = (wq * 32 + (lane & 31)) * kDmaRow, offB = kDigits * kPA + (wr * 32 + (lane & 31)) * kDmaRow;
+  const int c0 = lane >> 5;  // logical chunk of the first K-half; the second half adds 2
 
   for (int64_t kb0 = 0; kb0 < T.KB; kb0 += kChunkKB) {
     const int64_t kb_end = kb0 + kChunkKB < T.KB ? kb0 + kChunkKB : T.KB;
@@ -405,22 +422,22 @@ __device__ __forceinline__ void tile_dma(const I8Tile& T, int8_t* lds) {
     v16i acc[9];
 #pragma unroll
     for (int u = 0; u < 9; ++u) acc[u] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    issue(0, clamp(0));
-    issue(1, clamp(1));
+#pragma unroll
+    for (int j = 0; j < STAGES - 1; ++j) issue(j, clamp(j));
     for (int64_t i = 0; i < n; ++i) {
-      const int st = (int)(i % kDmaStages);
-      // block i complete for this wave (blocks i + 1 may still fly), then for all waves; all
-      // waves are also done reading the stage that block i + 2 overwrites
-      asm volatile("s_waitcnt vmcnt(10) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-      issue((int)((i + 2) % kDmaStages), clamp(i + 2));
-      const int8_t* A = lds + plane_off(st, 0, 0) + ra * kKB;
-      const int8_t* B = lds + plane_off(st, 1, 0) + rb * kKB;
-      auto fa = [&](int t, int c) {
-        return *reinterpret_cast<const v4i*>(A + t * kDmaPlane + ((c ^ swa) << 4));
-      };
-      auto fb = [&](int t, int c) {
-        return *reinterpret_cast<const v4i*>(B + t * kDmaPlane + ((c ^ swb) << 4));
-      };
+      const int st = (int)(i % STAGES);
+      // block i complete for this wave (with three stages block i + 1 may still fly), then for
+      // all waves; all waves are also done reading the stage that block i + STAGES - 1 overwrites
+      if constexpr (STAGES == 3) {
+        static_assert(kDigits * (BQ / 16 / NW + BR / 16 / NW) == 10, "vmcnt below assumes 10 loads per block");
+        asm volatile("s_waitcnt vmcnt(10) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      } else {
+        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      }
+      issue((int)((i + STAGES - 1) % STAGES), clamp(i + STAGES - 1));
+      const int8_t* S = lds + st * kStage;
+      auto fa = [&](int t, int c) { return *reinterpret_cast<const v4i*>(S + offA + t * kPA + ((c ^ sw) << 4)); };
+      auto fb = [&](int t, int c) { return *reinterpret_cast<const v4i*>(S + offB + t * kPB + ((c ^ sw) << 4)); };
       v4i a0[kDigits], a1[kDigits], b_cur, b_nxt;
 #pragma unroll
       for (int t = 0; t < kDigits; ++t) a0[t] = fa(t, c0);
@@ -445,13 +462,13 @@ __device__ __forceinline__ void tile_dma(const I8Tile& T, int8_t* lds) {
 // Grid launch: blockIdx.z = prime slot, blockIdx.x = XCD-ordered tile.
 template <int WR, int WQ, int NBUF, int WPE, int MODE>
 constexpr int lds_bytes() {
-  return MODE == 2 ? kDmaStages * 2 * kDigits * kDmaPlane : NBUF * kDigits * (32 * WQ + 32 * WR) * kLdsRow;
+  return NBUF * kDigits * (32 * WQ + 32 * WR) * (MODE == 2 ? kDmaRow : kLdsRow);
 }
 
 template <int WR, int WQ, int NBUF, int WPE, int MODE>
 __device__ __forceinline__ void run_tile(const I8Tile& T, int8_t* lds) {
   if constexpr (MODE == 2)
-    tile_dma(T, lds);
+    tile_dma<WR, WQ, NBUF>(T, lds);
   else if constexpr (MODE == 1)
     tile_pipe(T, lds);
   else
@@ -479,13 +496,29 @@ template <int WR, int WQ, int NBUF, int WPE, int MODE>
 __global__ void __launch_bounds__(64 * WR * WQ) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 k_gemm_i8_batched(BatchGemmArgs a) {
   constexpr int BR = 32 * WR, BQ = 32 * WQ;
+  // no other LDS than the tile's, so that the tile's occupancy holds
   __shared__ __attribute__((aligned(16))) int8_t lds[lds_bytes<WR, WQ, NBUF, WPE, MODE>()];
-  const int64_t total = a.hdr->total_tiles;
   const int n = a.hdr->n;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    int b = 0;
-    while (b + 1 < n && a.desc[b + 1].tile_begin <= t) ++b;
-    const BatchDesc& d = a.desc[b];
+  // Tiles are claimed in order from one counter per XCD (workgroup b runs on XCD b mod 8), so
+  // the workgroups of an XCD always work on a contiguous window of tiles that share database
+  // and query blocks in L2, however unevenly tiles finish; tile t = 8 j + xcd.  The claim is
+  // passed to the workgroup through the first LDS word, which no tile uses between tiles.
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = a.hdr->total_tiles / kXcds;
+  for (;;) {
+    __syncthreads();  // the previous tile is done with LDS
+    if (threadIdx.x == 0) *reinterpret_cast<uint32_t*>(lds) = atomicAdd(a.next + xcd, 1u);
+    __syncthreads();
+    const int64_t j = *reinterpret_cast<const uint32_t*>(lds);
+    __syncthreads();  // every thread has read the claim before the tile overwrites LDS
+    if (j >= per_xcd) break;
+    const int64_t t = j * kXcds + xcd;
+    int lo = 0, hi = n - 1;  // last problem whose first tile is <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.desc[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const BatchDesc& d = a.desc[lo];
     const int64_t n_ct = (d.d3 + BQ - 1) / BQ, n_rt = (d.R_out + BR - 1) / BR;
     const int64_t per_prime = (n_rt + kXcds - 1) / kXcds * kXcds * n_ct;
     const int64_t local = t - d.tile_begin;
@@ -513,9 +546,12 @@ struct I8Variant {
         64 * (WR) * (WQ), (WPE)                                                                              \
   }
 
-// MODE 0: tile_basic, 1: tile_pipe, 2: tile_dma.  The first entry is the default.
+// MODE 0: tile_basic, 1: tile_pipe, 2: tile_dma (NB = LDS stages).  The first entry is the
+// default.
 static const I8Variant kI8Variants[] = {
-    HFE_I8_VARIANT("pipe_w1", 2, 2, 2, 1, 1),     HFE_I8_VARIANT("dma3_w1", 2, 2, 3, 1, 2),
+    HFE_I8_VARIANT("dma2_w2", 2, 2, 2, 2, 2),     HFE_I8_VARIANT("dma3_w1", 2, 2, 3, 1, 2),
+    HFE_I8_VARIANT("dma_q128_w2", 2, 4, 2, 2, 2), HFE_I8_VARIANT("dma_r128_w2", 4, 2, 2, 2, 2),
+    HFE_I8_VARIANT("pipe_w1", 2, 2, 2, 1, 1),
     HFE_I8_VARIANT("r2q2b1w1", 2, 2, 1, 1, 0),    HFE_I8_VARIANT("r2q2b2w1", 2, 2, 2, 1, 0),
     HFE_I8_VARIANT("r2q2b1w2", 2, 2, 1, 2, 0),    HFE_I8_VARIANT("r4q2b1w2", 4, 2, 1, 2, 0),
     HFE_I8_VARIANT("r2q4b1w2", 2, 4, 1, 2, 0),
