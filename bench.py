@@ -115,8 +115,10 @@ def run_batched(args, H, torch):
     ops = sum(50 * (n_db + it.rows) * K * it.eyes * 16 * (it.level + 1) for it in mix)
     comparisons = sum(it.rows * it.eyes * 16 for it in mix)
     log(f"batched: {len(mix)} items, {cols} query columns, {ops / 1e15:.2f} P int8 ops; autotuning")
-    big = max(range(len(mix)), key=lambda i: mix[i].eyes * mix[i].level)
-    tuned = H.hfe_autotune(db, items[big][0], items[big][1], items[big][2], reps=1)
+    # the plan looks the autotuner's table up by its largest level and mean column count
+    tq = encrypt_eyes(H, torch, keys, w, 999, 32, w.n_q_primes, shifts)
+    tuned = H.hfe_autotune(db, tq, 0, w.d1, reps=1)
+    tq.free()
     plan = H.hfe_plan_create(db, len(items), cols, w.n_q_primes)
     H.hfe_plan_run(plan, items, use_graph=True)       # captures the graph
     torch.cuda.synchronize()
@@ -275,6 +277,16 @@ def main():
         return ip, eye
 
     H.hfe_set_i8_variant(args.variant)
+    tile = None
+    if args.variant < 0 and not args.sweep and not args.ccmm_only:
+        # the autotuner picks the int8 tile for this shape (setup, not timed)
+        m_q = H.hfe_encode(q_codes, q_masks, shifts)
+        qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+        tile = H.hfe_i8_variant_name(H.hfe_autotune(db, qct, 0, w.d1, reps=2))
+        qct.free()
+        log(f"autotuned int8 tile: {tile}")
+    elif args.variant >= 0:
+        tile = H.hfe_i8_variant_name(args.variant)
     if args.ccmm_only:
         m_q = H.hfe_encode(q_codes, q_masks, shifts)
         qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
@@ -364,7 +376,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_I8_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_I8_TOPS, "traffic": None,
-                     "kernel": "k_gemm_i8", "ops_per_launch": work["i8_ops"],
+                     "kernel": f"k_gemm_i8 ({tile})", "ops_per_launch": work["i8_ops"],
                      "kernel_ms": i8["contraction_ms"]},
         "plain": {"ms_per_step": results["plain"]["ms_per_step"],
                   "comparisons_per_s": results["plain"]["comparisons_per_s"],

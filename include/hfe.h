@@ -155,9 +155,11 @@ hfe_status hfe_plan_result(const hfe_plan* plan, int32_t i, const hfe_rct** view
 
 /* Autotuner of the int8 contraction tiles: times every tile configuration (see hfe_i8_variants)
  * on this problem (reps timed runs each, after one untimed), records the fastest for the
- * problem's (level, query-column bucket) so that later hfe_ccmm / batched calls of that shape
- * use it, and returns it in *best.  The table can be saved and loaded as text
- * ("<level> <column bucket> <configuration name>" per line). */
+ * problem's (level, query-column bucket; buckets are powers of two from 64) and returns it in
+ * *best.  Later hfe_ccmm calls, batches (by their largest level and mean column count) and plans
+ * (at creation) use the entry of their level with the nearest bucket, else the default.  The
+ * table can be saved and loaded as text ("<level> <column bucket> <configuration name>" per
+ * line). */
 hfe_status hfe_autotune(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t reps,
                         void* stream, int32_t* best);
 hfe_status hfe_autotune_save(const char* path);
@@ -237,10 +239,12 @@ hfe_status hfe_profile(int32_t enable);
 hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n);
 
 /* Tile configurations of the int8-MFMA contraction kernel.  hfe_i8_variants() returns their
- * number; hfe_i8_variant_name(v) names one as "r<waves along database rows>q<waves along query
- * columns>b<LDS stages>w<waves per SIMD>" (NULL if v is out of range); hfe_set_i8_variant(v)
- * selects the configuration later hfe_ccmm calls use (-1 restores the default).  Every
- * configuration computes the same residues. */
+ * number (configuration 0 is the default); hfe_i8_variant_name(v) names one (NULL if v is out of
+ * range): "dma*" configurations load the digit planes straight into LDS ("q128" / "r128": 128
+ * query columns / database rows per workgroup, "w<n>": waves per SIMD), "pipe_w1" prefetches
+ * through registers, "r<a>q<b>b<c>w<d>" are register-staged tiles of a x b waves with c LDS
+ * buffers.  hfe_set_i8_variant(v) forces the configuration of later calls, overriding the
+ * autotuner (-1 restores the default choice).  Every configuration computes the same residues. */
 int32_t hfe_i8_variants(void);
 const char* hfe_i8_variant_name(int32_t v);
 hfe_status hfe_set_i8_variant(int32_t v);

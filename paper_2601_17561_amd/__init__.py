@@ -69,6 +69,13 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2601_17561_amd/build.py` "
                       "(there is no CPU fallback)")
 
+# torch ships its own HIP and HSA runtimes under the same sonames as ROCm's.  Importing it first
+# lets libhfe.so bind to those already loaded; loaded the other way round, a process would hold
+# two HIP runtimes, and the library's would find no device next to torch's.
+try:
+    import torch as _torch_first  # noqa: F401
+except ImportError:  # host-only use of the library (no device work)
+    pass
 _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i32, _i64, _u32, _u64, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                     ctypes.c_uint64, ctypes.c_size_t)

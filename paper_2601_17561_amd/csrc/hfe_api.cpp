@@ -529,12 +529,24 @@ static int64_t d3_bucket(int64_t d3) {
   while (b < d3) b <<= 1;
   return b;
 }
+// The forced variant if one is set; else the tuned entry of this level with the nearest column
+// bucket; else the default.
 static int pick_i8_variant(int level, int64_t d3) {
   const int forced = g_i8_variant.load();
   if (forced >= 0) return forced;
   std::lock_guard<std::mutex> l(g_tune_mu);
-  auto it = g_tuned.find({level, d3_bucket(d3)});
-  return it == g_tuned.end() ? kDefaultI8Variant : it->second;
+  const int64_t b = d3_bucket(d3);
+  int best = kDefaultI8Variant;
+  int64_t best_dist = -1;
+  for (const auto& kv : g_tuned) {
+    if (kv.first.first != level) continue;
+    const int64_t dist = kv.first.second > b ? kv.first.second / b : b / kv.first.second;
+    if (best_dist < 0 || dist < best_dist) {
+      best_dist = dist;
+      best = kv.second;
+    }
+  }
+  return best;
 }
 
 static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, int64_t rows, int32_t form,

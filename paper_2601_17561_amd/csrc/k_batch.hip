@@ -10,10 +10,15 @@ namespace hfe {
 
 constexpr int kChunk = 256;
 
+// The problem a chunk starting at element e belongs to.  e is uniform over the block, so the
+// result is too; readfirstlane lets the compiler read the problem's descriptor with scalar loads.
 __device__ __forceinline__ int find_problem(const int64_t* begins, int n, int64_t e) {
-  int b = 0;
-  while (b + 1 < n && begins[b + 1] <= e) ++b;
-  return b;
+  int lo = 0, hi = n - 1;  // last problem whose first element is <= e
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begins[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
 }
 
 __global__ void __launch_bounds__(kChunk) k_lift_batched(const BatchElemHeader* hdr, const BatchLiftDesc* d,

@@ -509,7 +509,9 @@ k_gemm_i8_batched(BatchGemmArgs a) {
     __syncthreads();  // the previous tile is done with LDS
     if (threadIdx.x == 0) *reinterpret_cast<uint32_t*>(lds) = atomicAdd(a.next + xcd, 1u);
     __syncthreads();
-    const int64_t j = *reinterpret_cast<const uint32_t*>(lds);
+    // uniform by construction; readfirstlane tells the compiler, so that the descriptor and
+    // tile coordinates below live in scalar registers as kernel arguments do
+    const int64_t j = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t*>(lds));
     __syncthreads();  // every thread has read the claim before the tile overwrites LDS
     if (j >= per_xcd) break;
     const int64_t t = j * kXcds + xcd;
@@ -549,8 +551,8 @@ struct I8Variant {
 // MODE 0: tile_basic, 1: tile_pipe, 2: tile_dma (NB = LDS stages).  The first entry is the
 // default.
 static const I8Variant kI8Variants[] = {
+    HFE_I8_VARIANT("dma_r128_w2", 4, 2, 2, 2, 2), HFE_I8_VARIANT("dma_q128_w2", 2, 4, 2, 2, 2),
     HFE_I8_VARIANT("dma2_w2", 2, 2, 2, 2, 2),     HFE_I8_VARIANT("dma3_w1", 2, 2, 3, 1, 2),
-    HFE_I8_VARIANT("dma_q128_w2", 2, 4, 2, 2, 2), HFE_I8_VARIANT("dma_r128_w2", 4, 2, 2, 2, 2),
     HFE_I8_VARIANT("pipe_w1", 2, 2, 2, 1, 1),
     HFE_I8_VARIANT("r2q2b1w1", 2, 2, 1, 1, 0),    HFE_I8_VARIANT("r2q2b2w1", 2, 2, 2, 1, 0),
     HFE_I8_VARIANT("r2q2b1w2", 2, 2, 1, 2, 0),    HFE_I8_VARIANT("r4q2b1w2", 4, 2, 1, 2, 0),

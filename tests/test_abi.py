@@ -109,3 +109,17 @@ def test_null_arguments_rejected():
     lib.hfe_free(None)                       # NULL-safe
     lib.hfe_cdt_table.argtypes = [ctypes.c_void_p]
     assert lib.hfe_cdt_table(None) == -1
+
+
+def test_one_hip_runtime_when_the_package_is_imported_before_torch():
+    """Importing the package first must not load a second HIP runtime beside torch's."""
+    import subprocess
+    import sys
+    code = ("import paper_2601_17561_amd, torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l or 'libhsa-runtime64' in l}\n"
+            "print(len([x for x in libs if 'amdhip' in x]), len([x for x in libs if 'hsa-runtime' in x]))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["1", "1"], out.stdout
+
