@@ -31,6 +31,10 @@ import numpy as np  # noqa: E402
 import hfe_synth as S  # noqa: E402
 
 PEAK_I8_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
+# Bytes beyond L2 per launch of the contraction on the share workload (d3 = 512), from rocprofv3
+# FETCH_SIZE + WRITE_SIZE scaled by a 1 GiB copy (profiles/pmc_k_gemm_i8_dma_q128_r128_share_q512.md);
+# reported only for the kernels they were taken on.
+MEASURED_TRAFFIC_GB = {"dma_q128_w2": 28.3, "dma_r128_w2": 30.4}
 KEY_SEED, DB_SEED, Q_SEED = 11, 22, 33
 
 
@@ -375,7 +379,9 @@ def main():
                    "eyes": w.eyes, "shifts": w.n_shifts, "d3": w.d3, "form": "i8_mfma",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_I8_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_I8_TOPS, "traffic": None,
+                     "frac": achieved / PEAK_I8_TOPS,
+                     "traffic": (MEASURED_TRAFFIC_GB.get(tile) if w.name == S.PAPER_SHARE.name else None),
+                     "traffic_unit": "GB per launch (HBM side of L2, rocprofv3 counters)",
                      "kernel": f"k_gemm_i8 ({tile})", "ops_per_launch": work["i8_ops"],
                      "kernel_ms": i8["contraction_ms"]},
         "plain": {"ms_per_step": results["plain"]["ms_per_step"],
