@@ -128,9 +128,11 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
 /* Batched CCMM: item i is its own CCMM of items[i].q (any level, any column count) against the
  * database codes [items[i].row0, items[i].row0 + items[i].rows), all against one database.
  * int8 form: one grouped launch lifts and digit-splits every item's query, ONE persistent launch
- * computes the tiles of every item and prime (workgroups loop over a device-resident tile
- * table), one grouped launch rescales; plain form: one hfe_ccmm per item.  outs[i] receives
- * item i's result handle (release each with hfe_free).  1 <= n <= 256. */
+ * computes the tiles of every item and prime (workgroups claim tiles of a device-resident tile
+ * table in order), one grouped launch rescales; all items share one tile configuration (the
+ * forced one, else of the tuned and the default configuration the one that pads the items
+ * least); plain form: one hfe_ccmm per item.  outs[i] receives item i's result handle (release
+ * each with hfe_free).  1 <= n <= 256. */
 typedef struct {
   const hfe_qct* q;
   int64_t row0, rows;
@@ -141,8 +143,9 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
 /* Reusable batched int8 CCMM for repeated batches (e.g. serving steps): the workspace for up to
  * max_items items, max_cols query columns in total and levels up to max_level is allocated once;
  * hfe_plan_run writes the batch's descriptor tables (a host-to-device copy on `stream`) and
- * enqueues the three grouped launches, captured on the first use_graph run into a hipGraph that
- * later runs replay (any later stream is fine; the graph is launched on it).  hfe_plan_result
+ * enqueues the three grouped launches; with use_graph they are captured, on the first run that
+ * uses a tile configuration, into a hipGraph that later runs with that configuration replay (any
+ * later stream is fine; the graph is launched on it).  hfe_plan_result
  * returns item i's result of the last run as a view owned by the plan: valid until the next
  * hfe_plan_run or hfe_free(plan); hfe_free on the view does nothing.  Runs on one plan must not
  * overlap; the plan's database must outlive it. */

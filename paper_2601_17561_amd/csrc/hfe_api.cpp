@@ -813,6 +813,27 @@ int gemm_grid_for(int variant) {
   return (g + kXcds - 1) / kXcds * kXcds;
 }
 constexpr int kElemGrid = 4096;
+
+// Tile configuration of a batch: the forced one if set; else, of the configuration tuned for the
+// batch's largest level and mean column count and the default one, the one whose tiles pad the
+// batch's problems least (MFMA work including padded rows and columns); ties go to the tuned one.
+int choose_batch_variant(const hfe_db* D, const hfe_batch_item* items, int n, int max_level, int64_t mean_cols) {
+  if (g_i8_variant.load() >= 0) return g_i8_variant.load();
+  const int tuned = pick_i8_variant(max_level, mean_cols);
+  if (tuned == kDefaultI8Variant) return tuned;
+  const int64_t ndb = 1ll << D->keys->P.log_n_db;
+  auto padded = [&](int v) {
+    const int64_t br = i8_variant_tile_rows(v), bq = i8_variant_tile_cols(v);
+    double w = 0;
+    for (int i = 0; i < n; ++i) {
+      const hfe_qct* Qc = static_cast<const hfe_qct*>(items[i].q);
+      const int64_t R = ndb + items[i].rows;
+      w += (double)(Qc->level + 1) * ((Qc->d3 + bq - 1) / bq * bq) * ((R + br - 1) / br * br);
+    }
+    return w;
+  };
+  return padded(kDefaultI8Variant) < padded(tuned) ? kDefaultI8Variant : tuned;
+}
 }  // namespace
 
 extern "C" {
@@ -839,11 +860,10 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
     }
     return HFE_OK;
   }
-  // all items of one batch use one tile configuration: the tuned one for the largest level and
-  // the mean column count
+  // all items of one batch use one tile configuration
   const BlobLayout L(n);
   const BatchSizes sz0 = batch_fill(D, items, n, 0, nullptr, nullptr, nullptr, nullptr, L);
-  const int variant = pick_i8_variant(sz0.max_level, sz0.cols / n);
+  const int variant = choose_batch_variant(D, items, n, sz0.max_level, sz0.cols / n);
   const hfe_keys* K = D->keys;
   const int64_t ndb = 1ll << K->P.log_n_db;
   std::vector<hfe_rct*> R(n, nullptr);
@@ -917,7 +937,6 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   P->max_items = max_items;
   P->max_cols = max_cols;
   P->max_level = (int)max_level;
-  P->variant = pick_i8_variant((int)max_level, max_cols / max_items);
   const int64_t ndb = 1ll << D->keys->P.log_n_db;
   const int64_t R_max = ndb + D->d1;
   const int64_t cols_pad = max_cols + (int64_t)max_items * (kQueryPad - 1);
@@ -938,7 +957,6 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
     delete P;
     return st;
   }
-  P->gemm_grid = gemm_grid_for(P->variant);
   P->elem_grid = kElemGrid;
   for (int i = 0; i < max_items; ++i) {
     hfe_rct* v = new (std::nothrow) hfe_rct();
@@ -966,7 +984,9 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
       return fail(HFE_ELEVEL, "item level above the plan's maximum");
   }
   const BlobLayout L(P->max_items);
-  const BatchSizes sz = batch_fill(D, items, n, P->variant, nullptr, nullptr, nullptr, nullptr, L);
+  const BatchSizes sz = batch_fill(D, items, n, 0, nullptr, nullptr, nullptr, nullptr, L);
+  const int variant = choose_batch_variant(D, items, n, sz.max_level, sz.cols / n);
+  const int gemm_grid = gemm_grid_for(variant);
   if (sz.cols > P->max_cols || sz.xd_bytes > P->xd_cap || sz.c_elems > P->c_cap || sz.out_elems > P->out_cap)
     return fail(HFE_ESHAPE, "batch exceeds the plan's workspace");
   hipStream_t s = (hipStream_t)stream;
@@ -991,19 +1011,19 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
   HFE_LAUNCH(hipEventSynchronize(P->copied));
   uint8_t* host = static_cast<uint8_t*>(P->host_blob);
   std::memset(host, 0, P->blob_bytes);
-  batch_fill(D, items, n, P->variant, P->ws_xd.as<int8_t>(), P->ws_c.as<uint64_t>(), outp.data(), host, L);
+  batch_fill(D, items, n, variant, P->ws_xd.as<int8_t>(), P->ws_c.as<uint64_t>(), outp.data(), host, L);
   HFE_LAUNCH(hipMemcpyAsync(P->desc.ptr, host, P->blob_bytes, hipMemcpyHostToDevice, s));
   HFE_LAUNCH(hipEventRecord(P->copied, s));
   if (!use_graph) {
-    HFE_TRY(batch_enqueue(D, P->desc.as<uint8_t>(), L, P->variant, P->gemm_grid, P->elem_grid, s));
+    HFE_TRY(batch_enqueue(D, P->desc.as<uint8_t>(), L, variant, gemm_grid, P->elem_grid, s));
   } else {
-    if (!P->exec) {
+    if (!P->exec[variant]) {
       // capture on a private stream that joins the caller's stream through events
       hipStream_t cap;
       HFE_LAUNCH(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
       hfe_status st = HFE_OK;
       hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) st = batch_enqueue(D, P->desc.as<uint8_t>(), L, P->variant, P->gemm_grid, P->elem_grid, cap);
+      if (e == hipSuccess) st = batch_enqueue(D, P->desc.as<uint8_t>(), L, variant, gemm_grid, P->elem_grid, cap);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(cap, &g);
       (void)hipStreamDestroy(cap);
@@ -1015,10 +1035,10 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
         (void)hipGraphDestroy(g);
         return st;
       }
-      P->graph = g;
-      HFE_LAUNCH(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0));
+      P->graph[variant] = g;
+      HFE_LAUNCH(hipGraphInstantiate(&P->exec[variant], g, nullptr, nullptr, 0));
     }
-    HFE_LAUNCH(hipGraphLaunch(P->exec, s));
+    HFE_LAUNCH(hipGraphLaunch(P->exec[variant], s));
   }
   P->n_last = n;
   return HFE_OK;

@@ -244,6 +244,7 @@ struct GemmArgs {
 };
 hipError_t launch_gemm_plain(const GemmArgs& g, hipStream_t s);
 hipError_t launch_gemm_i8(const GemmArgs& g, int variant, hipStream_t s);
+constexpr int kMaxI8Variants = 16;  // upper bound of i8_variant_count()
 int i8_variant_count();
 const char* i8_variant_name(int v);
 int i8_variant_tile_rows(int v);
@@ -348,13 +349,17 @@ struct hfe_plan : hfe::HandleBase {
   void* host_blob = nullptr;                           // pinned staging of the descriptor tables
   size_t blob_bytes = 0;
   hipEvent_t copied = nullptr;                         // staging may be rewritten after this
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int gemm_grid = 0, elem_grid = 0, n_last = 0;
+  // one captured graph per tile configuration a run has used (the configuration is chosen per
+  // batch, see choose_batch_variant)
+  hipGraph_t graph[hfe::kMaxI8Variants] = {};
+  hipGraphExec_t exec[hfe::kMaxI8Variants] = {};
+  int elem_grid = 0, n_last = 0;
   std::vector<hfe_rct*> views;
   ~hfe_plan() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (int v = 0; v < hfe::kMaxI8Variants; ++v) {
+      if (exec[v]) (void)hipGraphExecDestroy(exec[v]);
+      if (graph[v]) (void)hipGraphDestroy(graph[v]);
+    }
     if (copied) (void)hipEventDestroy(copied);
     if (host_blob) (void)hipHostFree(host_blob);
     for (auto* v : views) delete v;

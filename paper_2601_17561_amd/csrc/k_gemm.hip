@@ -559,6 +559,7 @@ static const I8Variant kI8Variants[] = {
     HFE_I8_VARIANT("r2q4b1w2", 2, 4, 1, 2, 0),
 };
 constexpr int kNumI8Variants = sizeof(kI8Variants) / sizeof(kI8Variants[0]);
+static_assert(kNumI8Variants <= kMaxI8Variants, "raise kMaxI8Variants");
 
 int i8_variant_count() { return kNumI8Variants; }
 const char* i8_variant_name(int v) { return (v >= 0 && v < kNumI8Variants) ? kI8Variants[v].name : nullptr; }
