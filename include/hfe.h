@@ -57,8 +57,14 @@ enum {
 /* Contraction forms of hfe_ccmm (Section 6.3: the products mod Q reduced to small-integer
  * matrix products).  PLAIN_U64: 36-bit residues multiplied on the vector ALU with 128-bit
  * accumulation.  I8_MFMA: each centered residue split into 5 signed 8-bit digits, 25
- * digit-pair int8 MFMA products with int32 accumulation, exact recombination mod prime. */
-typedef enum { HFE_FORM_PLAIN_U64 = 1, HFE_FORM_I8_MFMA = 2 } hfe_form;
+ * digit-pair int8 MFMA products with int32 accumulation, exact recombination mod prime.
+ * RNS_I8: the RNS technique of Section 6.3 applied per prime: each centered residue kept as its
+ * balanced residues modulo n pairwise coprime moduli <= 256 (n = 11 for 36-bit primes and K up
+ * to about 67,000; the product of the moduli exceeds twice the largest exact sum), one int8
+ * MFMA product per modulus with int32 accumulation (K < 2^17), then the Chinese remainder
+ * reconstruction of the exact sum and its reduction mod the prime.  All forms give the same
+ * residues.  The database stores 8, 5 and n bytes per entry and prime for the three forms. */
+typedef enum { HFE_FORM_PLAIN_U64 = 1, HFE_FORM_I8_MFMA = 2, HFE_FORM_RNS_I8 = 4 } hfe_form;
 
 #define HFE_MAX_QPRIMES 8
 
@@ -106,8 +112,9 @@ hfe_status hfe_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int
 
 /* Database encryption in the RGSW/MSRLWE form of Sections 2.3 and 6.3: T = M_DB S_Q, and per
  * prime of Q_L p: A = [A1 | A2] uniform (N_DB x (d2 + N_Q)), B = -S_DB A + p [M_DB | T] + E.
- * m_db: d1 x d2 ternary (device).  forms: bitmask of hfe_form the database is prepared for.
- * The result stays resident on the device. */
+ * m_db: d1 x d2 ternary (device).  forms: bitmask of hfe_form the database is prepared for
+ * (HFE_FORM_RNS_I8 needs d2 + N_Q < 2^17, else HFE_ESHAPE).  The result stays resident on the
+ * device. */
 hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, uint64_t seed,
                           uint32_t forms, void* stream, hfe_db** out);
 

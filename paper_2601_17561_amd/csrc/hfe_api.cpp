@@ -369,6 +369,65 @@ hfe_status hfe_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int
 }
 
 // ------------------------------------------------------------------ database encryption
+// Small moduli of the RNS form for contraction length K: the shortest prefix of kRnsMods whose
+// product M exceeds 2 K h^2 (h = (q - 1) / 2 for the largest prime of the basis), so that the
+// centered sum S of K products of centered residues is determined by S mod M; K < 2^17 keeps
+// every int32 accumulation of int8 products exact.
+static hfe_status rns_moduli_for(const hfe_keys* K, int64_t Klen, int* n_out) {
+  if (Klen >= (1 << 17)) return fail(HFE_ESHAPE, "RNS form: contraction length must be below 2^17");
+  uint64_t qmax = 0;
+  for (int z = 0; z < K->n_primes; ++z) qmax = std::max(qmax, K->primes[z]);
+  const unsigned __int128 h = (qmax - 1) / 2;
+  const unsigned __int128 bound = (unsigned __int128)2 * (uint64_t)Klen * h * h + 1;
+  unsigned __int128 M = 1;
+  for (int n = 1; n <= kRnsMaxMods; ++n) {
+    M *= (uint64_t)kRnsMods[n - 1];
+    if (M >= bound) {
+      *n_out = n;
+      return HFE_OK;
+    }
+  }
+  return fail(HFE_ESHAPE, "RNS form: contraction too long for the small moduli");
+}
+
+// a^-1 mod m for gcd(a, m) = 1 (extended Euclid; m need not be prime).
+static int64_t inv_mod_any(int64_t a, int64_t m) {
+  int64_t r0 = m, r1 = ((a % m) + m) % m, t0 = 0, t1 = 1;
+  while (r1 != 0) {
+    const int64_t qt = r0 / r1;
+    const int64_t r2 = r0 - qt * r1, t2 = t0 - qt * t1;
+    r0 = r1;
+    r1 = r2;
+    t0 = t1;
+    t1 = t2;
+  }
+  return ((t0 % m) + m) % m;  // r0 == 1 for coprime inputs
+}
+
+// Garner and sign constants of the RNS form, and M mod the prime of each slot of a level.
+static RnsCrtArgs make_rns_crt_args(const hfe_keys* K, int level, int n) {
+  RnsCrtArgs ra;
+  std::memset(&ra, 0, sizeof(ra));
+  ra.n = n;
+  for (int i = 0; i < n; ++i) ra.m[i] = kRnsMods[i];
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < i; ++k) ra.inv[i][k] = (int32_t)inv_mod_any(ra.m[k], ra.m[i]);
+  // mixed-radix digits of H = (M - 1) / 2: H = sum_i c_i m_0 .. m_{i-1}
+  unsigned __int128 M = 1;
+  for (int i = 0; i < n; ++i) M *= (uint64_t)ra.m[i];
+  unsigned __int128 H = (M - 1) / 2;
+  for (int i = 0; i < n; ++i) {
+    ra.half[i] = (int32_t)(H % (uint64_t)ra.m[i]);
+    H /= (uint64_t)ra.m[i];
+  }
+  for (int z = 0; z <= level; ++z) {
+    const int slot = z < level ? z : K->L;
+    ra.mod[z] = K->mods[slot];
+    ra.M_mod_q[z] = (uint64_t)(M % K->primes[slot]);
+  }
+  return ra;
+}
+
 static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t d1, uint64_t seed,
                                   uint32_t forms, hipStream_t s, hfe_db* D) {
   const hfe_params& P = K->P;
@@ -414,6 +473,16 @@ static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t
       HFE_LAUNCH(launch_split_db(D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, D->K, D->R, D->KB, D->R_pad,
                                  K->primes[z], D->digits.as<int8_t>() + (size_t)z * kDigits * plane, s));
   }
+  if (forms & HFE_FORM_RNS_I8) {
+    int n = 0;
+    HFE_TRY(rns_moduli_for(K, D->K, &n));
+    D->n_rns = n;
+    const size_t plane = (size_t)D->KB * D->R_pad * kKB;
+    HFE_TRY(D->rns.alloc((size_t)np * n * plane, s));
+    for (int z = 0; z < np; ++z)
+      HFE_LAUNCH(launch_split_db_rns(D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, D->K, D->R, D->KB, D->R_pad,
+                                     K->primes[z], n, D->rns.as<int8_t>() + (size_t)z * n * plane, s));
+  }
   if (!(forms & HFE_FORM_PLAIN_U64)) D->Dt.reset();
   return HFE_OK;
 }
@@ -426,7 +495,7 @@ hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, 
   if (!K || !m_db) return fail(HFE_EINVAL, "invalid keys or m_db");
   if (d1 < 1 || d1 > (int64_t)K->P.max_db_rows)
     return fail(HFE_ESHAPE, "d1 must be 1 .. max_db_rows");
-  if (forms == 0 || (forms & ~3u)) return fail(HFE_EINVAL, "forms must be a non-empty set of hfe_form");
+  if (forms == 0 || (forms & ~7u)) return fail(HFE_EINVAL, "forms must be a non-empty set of hfe_form");
   hfe_db* D = new (std::nothrow) hfe_db();
   if (!D) return fail(HFE_ENOMEM, "host allocation failed");
   hfe_status st = encrypt_db_impl(K, m_db, d1, seed, forms, (hipStream_t)stream, D);
@@ -601,6 +670,34 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     }
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_plain(g, s));
+  } else if (form == HFE_FORM_RNS_I8) {
+    const int n = D->n_rns;
+    const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
+    const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
+    HFE_TRY(Xd.alloc((size_t)nz * n * planeX, s));
+    HFE_LAUNCH(launch_lift_rns(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, g.d3_pad, la, n, Xd.as<int8_t>(), s));
+    DevBuf res;
+    HFE_TRY(res.alloc(sizeof(uint16_t) * (size_t)nz * n * d3 * R_out, s));
+    RnsGemmArgs rg;
+    std::memset(&rg, 0, sizeof(rg));
+    rg.nz = nz;
+    rg.n_mod = n;
+    for (int z = 0; z < nz; ++z) {
+      rg.Dr[z] = D->rns.as<int8_t>() + (size_t)slot(z) * n * planeD;
+      rg.Xr[z] = Xd.as<int8_t>() + (size_t)z * n * planeX;
+    }
+    for (int j = 0; j < n; ++j) rg.m[j] = kRnsMods[j];
+    rg.res = res.as<uint16_t>();
+    rg.KB = D->KB;
+    rg.R_pad = D->R_pad;
+    rg.n_db = ndb;
+    rg.row0 = row0;
+    rg.R_out = R_out;
+    rg.d3 = d3;
+    rg.d3_pad = g.d3_pad;
+    HFE_LAUNCH(mark(1));
+    HFE_LAUNCH(launch_gemm_rns(rg, s));
+    HFE_LAUNCH(launch_crt_rns(res.as<uint16_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), C.as<uint64_t>(), s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
@@ -634,7 +731,8 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
   if (Qc->K != D->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
   if (Qc->level > D->keys->L) return fail(HFE_ELEVEL, "query level above the database primes");
   if (row0 < 0 || rows < 1 || row0 + rows > D->d1) return fail(HFE_ESHAPE, "row range outside the database");
-  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA) return fail(HFE_EINVAL, "unknown form");
+  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
+    return fail(HFE_EINVAL, "unknown form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   hfe_rct* R = new (std::nothrow) hfe_rct();
   if (!R) return fail(HFE_ENOMEM, "host allocation failed");
@@ -843,14 +941,15 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
   const hfe_db* D = as_handle<hfe_db>(db, kDb);
   if (!D || !items || !outs) return fail(HFE_EINVAL, "invalid database, items or outs");
   if (n < 1 || n > kMaxBatch) return fail(HFE_EINVAL, "batch size must be 1 .. 256");
-  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA) return fail(HFE_EINVAL, "unknown form");
+  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
+    return fail(HFE_EINVAL, "unknown form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   for (int i = 0; i < n; ++i) {
     outs[i] = nullptr;
     HFE_TRY(check_item(D, items[i]));
   }
   hipStream_t s = (hipStream_t)stream;
-  if (form == HFE_FORM_PLAIN_U64) {
+  if (form != HFE_FORM_I8_MFMA) {  // plain and RNS forms: one call per item
     for (int i = 0; i < n; ++i) {
       hfe_status st = hfe_ccmm(db, items[i].q, items[i].row0, items[i].rows, form, stream, &outs[i]);
       if (st != HFE_OK) {

@@ -7,6 +7,15 @@
 
 namespace hfe {
 
+// MFMA operand and result vectors: 16 int8 per lane (as 4 ints), 16 int32 per lane.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// Contraction row r (0 .. N_DB + rows) -> database row: the A-part rows, then the shard's rows.
+__device__ __forceinline__ int64_t src_row(int64_t r, int64_t n_db, int64_t row0) {
+  return r < n_db ? r : r + row0;
+}
+
 // ------------------------------------------------------------------ digit split
 // Centered residue x in (-q/2, q/2) -> 5 balanced base-256 digits d_t in [-128, 127]
 // (|d_4| <= 8), x = sum_t d_t 256^t.
@@ -45,26 +54,33 @@ __device__ __forceinline__ bool above_half(const uint64_t* v, const uint64_t* ha
   return false;
 }
 
-// Query element (c, k) of XT ([level][d3][K]): the lift L(x) = centered CRT value of the
-// residues y_i in (-Q/2, Q/2), reduced mod p; writes Xp[c][k] = L mod p (if Xp) and the 5
-// digit planes of every prime of the level and p (if Xd), zero for padding positions.
+// Query element (c, k) of XT ([level][d3][K]): the residues y_i of the lift L(x) = centered
+// CRT value in (-Q/2, Q/2), and lp = L mod p.  Returns false for padding positions (c >= d3 or
+// k >= K), where the lifted value is 0.
+__device__ __forceinline__ bool lift_residues(const uint64_t* XT, int64_t d3, int64_t K, const LiftArgs& la,
+                                              int64_t c, int64_t k, uint64_t* y, uint64_t& lp) {
+  lp = 0;
+  if (c >= d3 || k >= K) return false;
+  for (int i = 0; i < la.level; ++i) y[i] = XT[((int64_t)i * d3 + c) * K + k];
+  uint64_t v[HFE_MAX_QPRIMES];
+  garner_digits(y, la.level, la.garner, la.q, la.mu, v);
+  const uint64_t p = la.p;
+  const uint64_t mup = la.mu_p;
+  for (int i = 0; i < la.level; ++i)
+    lp = add_mod(lp, mul_mod(barrett64(v[i], p, mup), la.mprod_p[i], p, mup), p);
+  if (above_half(v, la.half_digits, la.level)) lp = sub_mod(lp, la.Q_mod_p, p);
+  return true;
+}
+
+// Query element (c, k): writes Xp[c][k] = L mod p (if Xp) and the 5 digit planes of every prime
+// of the level and p (if Xd), zero for padding positions.
 __device__ __forceinline__ void lift_element(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
                                              int64_t d3_pad, const LiftArgs& la, uint64_t* Xp, int8_t* Xd,
                                              int64_t c, int64_t k) {
-  const bool valid = c < d3 && k < K;
   uint64_t y[HFE_MAX_QPRIMES] = {};
-  uint64_t lp = 0;
-  if (valid) {
-    for (int i = 0; i < la.level; ++i) y[i] = XT[((int64_t)i * d3 + c) * K + k];
-    uint64_t v[HFE_MAX_QPRIMES];
-    garner_digits(y, la.level, la.garner, la.q, la.mu, v);
-    const uint64_t p = la.p;
-    const uint64_t mup = la.mu_p;
-    for (int i = 0; i < la.level; ++i)
-      lp = add_mod(lp, mul_mod(barrett64(v[i], p, mup), la.mprod_p[i], p, mup), p);
-    if (above_half(v, la.half_digits, la.level)) lp = sub_mod(lp, la.Q_mod_p, p);
-    if (Xp) Xp[c * K + k] = lp;
-  }
+  uint64_t lp;
+  const bool valid = lift_residues(XT, d3, K, la, c, k, y, lp);
+  if (valid && Xp) Xp[c * K + k] = lp;
   if (!Xd) return;
   const int64_t kb = k / kKB, kk = k % kKB;
   for (int z = 0; z <= la.level; ++z) {

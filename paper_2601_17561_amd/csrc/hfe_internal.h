@@ -124,6 +124,16 @@ struct hfe_keys : hfe::HandleBase {
   uint64_t cdt_host[19];
 };
 
+namespace hfe {
+// ------------------------------------------------------------------ small-modulus (RNS) form
+// Pairwise coprime moduli <= 256 (balanced residues fit int8), largest product first: 2^8,
+// 3*5*17, 11*23, 251, 13*19, then primes.  A database uses the shortest prefix whose product
+// exceeds twice the largest exact contraction sum (Section 6.3, RNS over small moduli).
+constexpr int kRnsMaxMods = 16;
+constexpr int32_t kRnsMods[kRnsMaxMods] = {256, 255, 253, 251, 247, 241, 239, 233,
+                                           229, 227, 223, 211, 199, 197, 193, 191};
+}  // namespace hfe
+
 struct hfe_db : hfe::HandleBase {
   const hfe_keys* keys;
   int64_t d1, R, K;                        // R = N_DB + d1 rows, K = d2 + N_Q columns
@@ -132,6 +142,8 @@ struct hfe_db : hfe::HandleBase {
   uint32_t forms;
   hfe::DevBuf Dt;                          // [prime][K][R] uint64 (column-major D), plain form
   hfe::DevBuf digits;                      // [prime][5][KB][R_pad][64] int8, i8 form
+  int n_rns = 0;                           // small moduli in use (RNS form)
+  hfe::DevBuf rns;                         // [prime][n_rns][KB][R_pad][64] int8, RNS form
 };
 
 struct hfe_qct : hfe::HandleBase {
@@ -229,6 +241,35 @@ struct LiftArgs {
 };
 hipError_t launch_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
                        const LiftArgs& la, uint64_t* Xp, int8_t* Xd, hipStream_t s);
+
+// Small-modulus (RNS) form: the database and the lifted query as one balanced int8 plane per
+// modulus (layouts as the digit planes); one int8 product per (prime, modulus) reduced mod the
+// modulus into res[z][j][c][r] (uint16); the CRT of the n residues gives the exact centered
+// integer sum, reduced mod the prime into C[z][c][r].
+hipError_t launch_split_db_rns(const uint64_t* Dt_prime, int64_t K, int64_t R, int64_t KB, int64_t R_pad,
+                               uint64_t q, int n_mod, int8_t* dig_prime, hipStream_t s);
+hipError_t launch_lift_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
+                           const LiftArgs& la, int n_mod, int8_t* Xr, hipStream_t s);
+struct RnsGemmArgs {
+  int nz, n_mod;
+  const int8_t* Dr[kMaxPrimes];                // [n_mod][KB][R_pad][64] per prime slot
+  const int8_t* Xr[kMaxPrimes];                // [n_mod][KB][d3_pad][64]
+  int32_t m[kRnsMaxMods];
+  uint16_t* res;                               // [nz][n_mod][d3][R_out]
+  int64_t KB, R_pad, n_db, row0, R_out, d3, d3_pad;
+};
+hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s);
+struct RnsCrtArgs {
+  int n;                                       // moduli in use
+  int32_t m[kRnsMaxMods];
+  int32_t inv[kRnsMaxMods][kRnsMaxMods];       // [i][k < i]: m_k^-1 mod m_i
+  int32_t half[kRnsMaxMods];                   // mixed-radix digits of (M - 1) / 2, M = prod m
+  Mod mod[kMaxPrimes];                         // prime of each slot
+  uint64_t M_mod_q[kMaxPrimes];                // M mod that prime
+};
+hipError_t launch_crt_rns(const uint16_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
+                          hipStream_t s);
+constexpr int kRnsTileR = 256, kRnsTileQ = 128;  // workgroup tile of the RNS contraction
 
 // Plain uint64 contraction.  For each prime slot z < nz: C[z][c][r] = sum_k Dt[z][k][src(r)] *
 // X[z][c][k] mod prime, rows r < R_out mapped to source rows (A-part then the shard).

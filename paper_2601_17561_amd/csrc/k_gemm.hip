@@ -15,13 +15,9 @@
 //    one int32 accumulator (9 accumulators), exact because a K-chunk of at most 32,704
 //    keeps every partial sum below 2^31; recombination by Horner's rule in 64-bit integers
 //    with a Barrett reduction at each step.
-#include "hfe_internal.h"
+#include "hfe_device.h"
 
 namespace hfe {
-
-__device__ __forceinline__ int64_t src_row(int64_t r, int64_t n_db, int64_t row0) {
-  return r < n_db ? r : r + row0;
-}
 
 // ------------------------------------------------------------------ plain form
 constexpr int kPR = 64;   // output rows per workgroup (one per lane)
@@ -100,9 +96,6 @@ hipError_t launch_gemm_plain(const GemmArgs& g, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ int8 MFMA form
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
-
 constexpr int kIQ = 64;           // query columns per workgroup (2 waves x 32)
 constexpr int kIR = 64;           // output rows per workgroup (2 waves x 32)
 constexpr int kLdsRow = 80;       // bytes per LDS row: 64 digits + 16 pad (conflict-free b128 reads)
