@@ -50,6 +50,19 @@ def algorithmic_work(w: S.Workload):
     return dict(R_out=R_out, K=K, residue_macs=W, i8_ops=2 * 25 * W)
 
 
+def rns_moduli(w: S.Workload, qmax: int) -> int:
+    """Small moduli the RNS form uses for this shape (the library's rule): the shortest prefix
+    of its coprime list whose product exceeds 2 K ((q - 1) / 2)^2 for the largest prime q."""
+    import math
+    mods = (256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191)
+    K = w.d2 + (1 << w.log_n_q)
+    bound = 2 * K * ((qmax - 1) // 2) ** 2 + 1
+    for n in range(1, len(mods) + 1):
+        if math.prod(mods[:n]) >= bound:
+            return n
+    raise ValueError("contraction too long for the small moduli")
+
+
 def cpu_baseline(w: S.Workload, inp, rows_sample: int, cols_sample: int):
     """The oracle's CCMM (lift, exact contraction, CRT rescale) on a slice of the workload."""
     import torch
@@ -261,7 +274,7 @@ def main():
     log("encrypting the database (both forms)")
     t0 = time.perf_counter()
     m_db = H.hfe_encode(db_codes, db_masks, [0])
-    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA)
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
     torch.cuda.synchronize()
     t_db = time.perf_counter() - t0
     del m_db
@@ -329,6 +342,7 @@ def main():
 
     results = {}
     for name, form, steps, warm in (("i8", H.HFE_FORM_I8_MFMA, args.steps, args.warmup),
+                                    ("rns", H.HFE_FORM_RNS_I8, args.steps, args.warmup),
                                     ("plain", H.HFE_FORM_PLAIN_U64, args.plain_steps, 1)):
         for _ in range(warm):
             step(form)
@@ -353,6 +367,11 @@ def main():
             f"(lift {results[name]['lift_ms']:.2f}, rescale {results[name]['rescale_ms']:.2f})")
 
     same = bool(torch.equal(results["i8"]["ip"], results["plain"]["ip"]))
+    same_rns = bool(torch.equal(results["rns"]["ip"], results["i8"]["ip"]))
+    rns = results["rns"]
+    qs, p_special = P.primes()
+    n_mod = rns_moduli(w, max(list(qs) + [p_special]))
+    rns_ops = 2 * n_mod * work["residue_macs"]
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
@@ -388,6 +407,12 @@ def main():
                   "comparisons_per_s": results["plain"]["comparisons_per_s"],
                   "contraction_ms": results["plain"]["contraction_ms"],
                   "residue_macs_per_s": work["residue_macs"] / (results["plain"]["contraction_ms"] * 1e-3)},
+        "rns": {"form": f"small-modulus RNS, {n_mod} moduli per prime", "ms_per_step": rns["ms_per_step"],
+                "comparisons_per_s": rns["comparisons_per_s"], "contraction_ms": rns["contraction_ms"],
+                "lift_ms": rns["lift_ms"], "crt_rescale_ms": rns["rescale_ms"],
+                "int8_ops_per_launch": rns_ops,
+                "frac_of_peak": rns_ops / (rns["contraction_ms"] * 1e-3) / 1e12 / PEAK_I8_TOPS,
+                "over_i8_step": i8["ms_per_step"] / rns["ms_per_step"], "equals_i8_ip": same_rns},
         "i8_over_plain_step": results["plain"]["ms_per_step"] / i8["ms_per_step"],
         "stages_ms": {"lift_split": i8["lift_ms"], "contraction": i8["contraction_ms"], "rescale": i8["rescale_ms"]},
         "i8_equals_plain_ip": same,

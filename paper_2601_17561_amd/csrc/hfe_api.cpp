@@ -409,7 +409,10 @@ static RnsCrtArgs make_rns_crt_args(const hfe_keys* K, int level, int n) {
   RnsCrtArgs ra;
   std::memset(&ra, 0, sizeof(ra));
   ra.n = n;
-  for (int i = 0; i < n; ++i) ra.m[i] = kRnsMods[i];
+  for (int i = 0; i < n; ++i) {
+    ra.m[i] = kRnsMods[i];
+    ra.magic[i] = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)kRnsMods[i] - 1) / (uint64_t)kRnsMods[i]);
+  }
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < i; ++k) ra.inv[i][k] = (int32_t)inv_mod_any(ra.m[k], ra.m[i]);
   // mixed-radix digits of H = (M - 1) / 2: H = sum_i c_i m_0 .. m_{i-1}
@@ -686,7 +689,10 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
       rg.Dr[z] = D->rns.as<int8_t>() + (size_t)slot(z) * n * planeD;
       rg.Xr[z] = Xd.as<int8_t>() + (size_t)z * n * planeX;
     }
-    for (int j = 0; j < n; ++j) rg.m[j] = kRnsMods[j];
+    for (int j = 0; j < n; ++j) {
+      rg.m[j] = kRnsMods[j];
+      rg.magic[j] = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)kRnsMods[j] - 1) / (uint64_t)kRnsMods[j]);
+    }
     rg.res = res.as<uint16_t>();
     rg.KB = D->KB;
     rg.R_pad = D->R_pad;

@@ -255,6 +255,7 @@ struct RnsGemmArgs {
   const int8_t* Dr[kMaxPrimes];                // [n_mod][KB][R_pad][64] per prime slot
   const int8_t* Xr[kMaxPrimes];                // [n_mod][KB][d3_pad][64]
   int32_t m[kRnsMaxMods];
+  uint32_t magic[kRnsMaxMods];                 // ceil(2^32 / m): x mod m by multiply-high, x < 2^24
   uint16_t* res;                               // [nz][n_mod][d3][R_out]
   int64_t KB, R_pad, n_db, row0, R_out, d3, d3_pad;
 };
@@ -262,6 +263,7 @@ hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s);
 struct RnsCrtArgs {
   int n;                                       // moduli in use
   int32_t m[kRnsMaxMods];
+  uint32_t magic[kRnsMaxMods];                 // ceil(2^32 / m)
   int32_t inv[kRnsMaxMods][kRnsMaxMods];       // [i][k < i]: m_k^-1 mod m_i
   int32_t half[kRnsMaxMods];                   // mixed-radix digits of (M - 1) / 2, M = prod m
   Mod mod[kMaxPrimes];                         // prime of each slot

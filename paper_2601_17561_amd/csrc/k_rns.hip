@@ -20,6 +20,12 @@ __device__ __forceinline__ int32_t balanced_mod(int64_t x, int32_t m) {
   return (int32_t)r >= (m + 1) / 2 ? (int32_t)r - m : (int32_t)r;
 }
 
+// x mod m for x < 2^24 and 2 <= m <= 256 with magic = ceil(2^32 / m): the quotient
+// floor(x magic / 2^32) is exact because x (magic - 2^32 / m) / 2^32 < 2^-8 <= 1 / m.
+__device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t m, uint32_t magic) {
+  return x - __umulhi(x, magic) * m;
+}
+
 // ------------------------------------------------------------------ database split
 // Thread (row r, K-block kb): the 64 centered residues of D[k][r] -> one 64-byte row per modulus.
 __global__ void __launch_bounds__(256) k_split_db_rns(const uint64_t* Dt, int64_t K, int64_t R, int64_t KB,
@@ -172,6 +178,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   // epilogue: S mod m_j in [0, m_j) -> res[z][j][c][r]; 32 x 32 result layout as in the digit
   // form (lane l, element e: query column 8 (e / 4) + 4 (l / 32) + e % 4, row l % 32)
   const int32_t m = g.m[j];
+  const uint32_t magic = g.magic[j];
+  // |acc| < 2^31: u = acc + 2^31 = hi 2^17 + lo (hi < 2^15), and
+  // acc mod m = (hi (2^17 mod m) + lo + (m - 2^31 mod m)) mod m with the argument below 2^24
+  const uint32_t t16 = mod_small(1u << 16, (uint32_t)m, magic), t17 = mod_small(1u << 17, (uint32_t)m, magic);
+  const uint32_t off = (uint32_t)m - mod_small(mod_small(1u << 15, (uint32_t)m, magic) * t16, (uint32_t)m, magic);
   uint16_t* res = g.res + ((size_t)z * g.n_mod + j) * g.d3 * g.R_out;
 #pragma unroll
   for (int b = 0; b < kRnsWRB; ++b) {
@@ -183,8 +194,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       for (int e = 0; e < 16; ++e) {
         const int64_t c = c0 + wq * 32 * kRnsWQB + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         if (c >= g.d3) continue;
-        int32_t v = acc[a][b][e] % m;
-        if (v < 0) v += m;
+        const uint32_t u = (uint32_t)acc[a][b][e] + 0x80000000u;  // acc + 2^31 >= 0
+        const uint32_t v = mod_small((u >> 17) * t17 + (u & 0x1FFFF) + off, (uint32_t)m, magic);
         res[c * g.R_out + r] = (uint16_t)v;
       }
   }
@@ -214,10 +225,11 @@ __global__ void __launch_bounds__(256) k_crt_rns(const uint16_t* res, int nz, in
     for (int i = 0; i < ra.n; ++i) {
       int32_t v = r[(size_t)i * n];
       const int32_t mi = ra.m[i];
+      const uint32_t mg = ra.magic[i];
       for (int k = 0; k < i; ++k) {
-        v -= c[k] % mi;  // c_k < m_k may exceed m_i
+        v -= (int32_t)mod_small((uint32_t)c[k], (uint32_t)mi, mg);  // c_k < m_k may exceed m_i
         if (v < 0) v += mi;
-        v = (v * ra.inv[i][k]) % mi;
+        v = (int32_t)mod_small((uint32_t)(v * ra.inv[i][k]), (uint32_t)mi, mg);
       }
       c[i] = v;
     }
