@@ -52,11 +52,11 @@ def algorithmic_work(w: S.Workload):
 
 def rns_moduli(w: S.Workload, qmax: int) -> int:
     """Small moduli the RNS form uses for this shape (the library's rule): the shortest prefix
-    of its coprime list whose product exceeds 2 K ((q - 1) / 2)^2 for the largest prime q."""
+    of its coprime list whose product is at least 4 K ((q - 1) / 2)^2 for the largest prime q."""
     import math
     mods = (256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191)
     K = w.d2 + (1 << w.log_n_q)
-    bound = 2 * K * ((qmax - 1) // 2) ** 2 + 1
+    bound = 4 * K * ((qmax - 1) // 2) ** 2
     for n in range(1, len(mods) + 1):
         if math.prod(mods[:n]) >= bound:
             return n

@@ -60,7 +60,7 @@ enum {
  * digit-pair int8 MFMA products with int32 accumulation, exact recombination mod prime.
  * RNS_I8: the RNS technique of Section 6.3 applied per prime: each centered residue kept as its
  * balanced residues modulo n pairwise coprime moduli <= 256 (n = 11 for 36-bit primes and K up
- * to about 67,000; the product of the moduli exceeds twice the largest exact sum), one int8
+ * to about 33,000; the product of the moduli is at least four times the largest exact sum), one int8
  * MFMA product per modulus with int32 accumulation (K < 2^17), then the Chinese remainder
  * reconstruction of the exact sum and its reduction mod the prime.  All forms give the same
  * residues.  The database stores 8, 5 and n bytes per entry and prime for the three forms. */

@@ -370,15 +370,16 @@ hfe_status hfe_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int
 
 // ------------------------------------------------------------------ database encryption
 // Small moduli of the RNS form for contraction length K: the shortest prefix of kRnsMods whose
-// product M exceeds 2 K h^2 (h = (q - 1) / 2 for the largest prime of the basis), so that the
-// centered sum S of K products of centered residues is determined by S mod M; K < 2^17 keeps
-// every int32 accumulation of int8 products exact.
+// product M is at least 4 K h^2 (h = (q - 1) / 2 for the largest prime of the basis): the
+// centered sum S of K products of centered residues is determined by S mod M, with |S| <= M / 4
+// so that the CRT can round its multiple of M from a single-precision sum.  K < 2^17 keeps every
+// int32 accumulation of int8 products exact.
 static hfe_status rns_moduli_for(const hfe_keys* K, int64_t Klen, int* n_out) {
   if (Klen >= (1 << 17)) return fail(HFE_ESHAPE, "RNS form: contraction length must be below 2^17");
   uint64_t qmax = 0;
   for (int z = 0; z < K->n_primes; ++z) qmax = std::max(qmax, K->primes[z]);
   const unsigned __int128 h = (qmax - 1) / 2;
-  const unsigned __int128 bound = (unsigned __int128)2 * (uint64_t)Klen * h * h + 1;
+  const unsigned __int128 bound = (unsigned __int128)4 * (uint64_t)Klen * h * h;
   unsigned __int128 M = 1;
   for (int n = 1; n <= kRnsMaxMods; ++n) {
     M *= (uint64_t)kRnsMods[n - 1];
@@ -404,29 +405,28 @@ static int64_t inv_mod_any(int64_t a, int64_t m) {
   return ((t0 % m) + m) % m;  // r0 == 1 for coprime inputs
 }
 
-// Garner and sign constants of the RNS form, and M mod the prime of each slot of a level.
+// CRT constants of the RNS form: (M/m_j)^-1 mod m_j, 1/m_j, and (M/m_j), M mod the prime of each
+// slot of a level.
 static RnsCrtArgs make_rns_crt_args(const hfe_keys* K, int level, int n) {
   RnsCrtArgs ra;
   std::memset(&ra, 0, sizeof(ra));
   ra.n = n;
-  for (int i = 0; i < n; ++i) {
-    ra.m[i] = kRnsMods[i];
-    ra.magic[i] = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)kRnsMods[i] - 1) / (uint64_t)kRnsMods[i]);
-  }
-  for (int i = 0; i < n; ++i)
-    for (int k = 0; k < i; ++k) ra.inv[i][k] = (int32_t)inv_mod_any(ra.m[k], ra.m[i]);
-  // mixed-radix digits of H = (M - 1) / 2: H = sum_i c_i m_0 .. m_{i-1}
   unsigned __int128 M = 1;
-  for (int i = 0; i < n; ++i) M *= (uint64_t)ra.m[i];
-  unsigned __int128 H = (M - 1) / 2;
-  for (int i = 0; i < n; ++i) {
-    ra.half[i] = (int32_t)(H % (uint64_t)ra.m[i]);
-    H /= (uint64_t)ra.m[i];
+  for (int i = 0; i < n; ++i) M *= (uint64_t)kRnsMods[i];
+  for (int j = 0; j < n; ++j) {
+    const int64_t m = kRnsMods[j];
+    ra.m[j] = (int32_t)m;
+    ra.magic[j] = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)m - 1) / (uint64_t)m);
+    const unsigned __int128 Mj = M / (uint64_t)m;
+    ra.inv[j] = (int32_t)inv_mod_any((int64_t)(Mj % (uint64_t)m), m);
+    ra.rcp[j] = 1.0f / (float)m;
   }
   for (int z = 0; z <= level; ++z) {
     const int slot = z < level ? z : K->L;
+    const uint64_t q = K->primes[slot];
     ra.mod[z] = K->mods[slot];
-    ra.M_mod_q[z] = (uint64_t)(M % K->primes[slot]);
+    ra.M_mod_q[z] = (uint64_t)(M % q);
+    for (int j = 0; j < n; ++j) ra.Mj_mod_q[z][j] = (uint64_t)((M / (uint64_t)kRnsMods[j]) % q);
   }
   return ra;
 }
@@ -675,10 +675,11 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(launch_gemm_plain(g, s));
   } else if (form == HFE_FORM_RNS_I8) {
     const int n = D->n_rns;
-    const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
+    const int64_t d3_pad = (d3 + kRnsTileQ - 1) / kRnsTileQ * kRnsTileQ;  // whole query tiles
+    const size_t planeX = (size_t)D->KB * d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
     HFE_TRY(Xd.alloc((size_t)nz * n * planeX, s));
-    HFE_LAUNCH(launch_lift_rns(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, g.d3_pad, la, n, Xd.as<int8_t>(), s));
+    HFE_LAUNCH(launch_lift_rns(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd.as<int8_t>(), s));
     DevBuf res;
     HFE_TRY(res.alloc(sizeof(uint16_t) * (size_t)nz * n * d3 * R_out, s));
     RnsGemmArgs rg;
@@ -700,7 +701,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     rg.row0 = row0;
     rg.R_out = R_out;
     rg.d3 = d3;
-    rg.d3_pad = g.d3_pad;
+    rg.d3_pad = d3_pad;
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_rns(rg, s));
     HFE_LAUNCH(launch_crt_rns(res.as<uint16_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), C.as<uint64_t>(), s));

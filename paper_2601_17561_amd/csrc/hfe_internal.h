@@ -264,14 +264,15 @@ struct RnsCrtArgs {
   int n;                                       // moduli in use
   int32_t m[kRnsMaxMods];
   uint32_t magic[kRnsMaxMods];                 // ceil(2^32 / m)
-  int32_t inv[kRnsMaxMods][kRnsMaxMods];       // [i][k < i]: m_k^-1 mod m_i
-  int32_t half[kRnsMaxMods];                   // mixed-radix digits of (M - 1) / 2, M = prod m
+  int32_t inv[kRnsMaxMods];                    // (M / m_j)^-1 mod m_j, M = prod m
+  float rcp[kRnsMaxMods];                      // 1 / m_j
   Mod mod[kMaxPrimes];                         // prime of each slot
+  uint64_t Mj_mod_q[kMaxPrimes][kRnsMaxMods];  // (M / m_j) mod that prime
   uint64_t M_mod_q[kMaxPrimes];                // M mod that prime
 };
 hipError_t launch_crt_rns(const uint16_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
                           hipStream_t s);
-constexpr int kRnsTileR = 256, kRnsTileQ = 128;  // workgroup tile of the RNS contraction
+constexpr int kRnsTileR = 256, kRnsTileQ = 256;  // workgroup tile of the RNS contraction
 
 // Plain uint64 contraction.  For each prime slot z < nz: C[z][c][r] = sum_k Dt[z][k][src(r)] *
 // X[z][c][k] mod prime, rows r < R_out mapped to source rows (A-part then the shard).

@@ -8,22 +8,30 @@
 
 namespace hfe {
 
-// ------------------------------------------------------------------ balanced residues
-// x (|x| < 2^40) -> r_j = x mod m_j in [-floor(m_j/2), ceil(m_j/2) - 1], j < n.
-__device__ __forceinline__ int32_t balanced_mod(int64_t x, int32_t m) {
-  const uint64_t a = (uint64_t)(x < 0 ? -x : x);
-  // a = hi 2^24 + lo with hi < 2^16: a mod m = (hi (2^24 mod m) + lo) mod m in 32-bit
-  const uint32_t hi = (uint32_t)(a >> 24), lo = (uint32_t)(a & 0xFFFFFF);
-  const uint32_t t24 = (1u << 24) % (uint32_t)m;
-  uint32_t r = (uint32_t)(((uint64_t)hi * t24 + lo) % (uint32_t)m);
-  if (x < 0 && r) r = (uint32_t)m - r;
-  return (int32_t)r >= (m + 1) / 2 ? (int32_t)r - m : (int32_t)r;
-}
-
 // x mod m for x < 2^24 and 2 <= m <= 256 with magic = ceil(2^32 / m): the quotient
 // floor(x magic / 2^32) is exact because x (magic - 2^32 / m) / 2^32 < 2^-8 <= 1 / m.
 __device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t m, uint32_t magic) {
   return x - __umulhi(x, magic) * m;
+}
+
+// ------------------------------------------------------------------ balanced residues
+// ceil(2^32 / m) for the moduli of kRnsMods.
+__constant__ uint32_t kRnsMagic[kRnsMaxMods] = {
+    16777216u, 16843010u, 16976156u, 17111424u, 17388532u, 17821442u, 17970575u, 18433337u,
+    18755316u, 18920561u, 19259944u, 20355296u, 21582751u, 21801865u, 22253717u, 22486740u};
+
+// x (|x| < 2^40) -> x mod m_j in [-floor(m_j/2), ceil(m_j/2) - 1] for the modulus kRnsMods[j]:
+// |x| = hi 2^24 + lo (hi < 2^16), |x| mod m = (hi (2^24 mod m) + lo) mod m with the argument
+// split once more below 2^24.
+__device__ __forceinline__ int32_t balanced_mod(int64_t x, int j) {
+  const uint32_t m = (uint32_t)kRnsMods[j], mg = kRnsMagic[j];
+  const uint64_t a = (uint64_t)(x < 0 ? -x : x);
+  const uint32_t hi = (uint32_t)(a >> 24), lo = (uint32_t)(a & 0xFFFFFF);
+  const uint32_t t24 = mod_small(mod_small(1u << 12, m, mg) * mod_small(1u << 12, m, mg), m, mg);
+  const uint32_t hm = mod_small(mod_small(hi >> 8, m, mg) * mod_small(1u << 8, m, mg) + (hi & 255), m, mg);
+  uint32_t r = mod_small(mod_small(hm * t24, m, mg) + mod_small(lo, m, mg), m, mg);
+  if (x < 0 && r) r = m - r;
+  return (int32_t)r >= ((int32_t)m + 1) / 2 ? (int32_t)r - (int32_t)m : (int32_t)r;
 }
 
 // ------------------------------------------------------------------ database split
@@ -40,13 +48,12 @@ __global__ void __launch_bounds__(256) k_split_db_rns(const uint64_t* Dt, int64_
     x[kk] = (r < R && k < K) ? centered(Dt[k * R + r], q) : 0;
   }
   for (int j = 0; j < n_mod; ++j) {
-    const int32_t m = kRnsMods[j];
     uint32_t w[kKB / 4];
 #pragma unroll
     for (int i = 0; i < kKB / 4; ++i) {
       uint32_t v = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) v |= ((uint32_t)(balanced_mod(x[4 * i + b], m) & 255)) << (8 * b);
+      for (int b = 0; b < 4; ++b) v |= ((uint32_t)(balanced_mod(x[4 * i + b], j) & 255)) << (8 * b);
       w[i] = v;
     }
     uint4* dst = reinterpret_cast<uint4*>(dig + (((int64_t)j * KB + kb) * R_pad + r) * kKB);
@@ -79,7 +86,7 @@ __global__ void __launch_bounds__(256) k_lift_rns(const uint64_t* XT, int64_t d3
     int64_t x = 0;
     if (valid) x = z < la.level ? centered(y[z], la.q[z]) : centered(lp, la.p);
     for (int j = 0; j < n_mod; ++j)
-      Xr[((((int64_t)z * n_mod + j) * KB + kb) * d3_pad + c) * kKB + kk] = (int8_t)balanced_mod(x, kRnsMods[j]);
+      Xr[((((int64_t)z * n_mod + j) * KB + kb) * d3_pad + c) * kKB + kk] = (int8_t)balanced_mod(x, j);
   }
 }
 
@@ -91,16 +98,17 @@ hipError_t launch_lift_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB
 }
 
 // ------------------------------------------------------------------ contraction per modulus
-// Workgroup: 2 x 2 waves on 256 database rows x 128 query columns of one (prime, modulus); wave
-// (wq, wr) owns 64 query columns x 128 rows as 2 x 4 blocks of 32 x 32 with one int32
-// accumulator each (v_mfma_i32_32x32x32_i8), so each fragment read from LDS feeds 2 or 4 MFMAs.
-// One 64-byte K-block of both operands per LDS stage (24 KiB), three stages fed by direct
+// Workgroup: 4 x 2 waves (two per SIMD) on 256 database rows x 256 query columns of one (prime,
+// modulus); wave (wq, wr) owns 64 query columns x 128 rows as 2 x 4 blocks of 32 x 32 with one
+// int32 accumulator each (v_mfma_i32_32x32x32_i8), so each fragment read from LDS feeds 2 or 4
+// MFMAs.  One 64-byte K-block of both operands per LDS stage (32 KiB), three stages fed by direct
 // global-to-LDS loads (same row swizzle as the digit form's DMA tiles), so two K-blocks are in
 // flight while one is multiplied.  Exactness: |S| over the K-range <= K * 128 * 128 < 2^31 for
 // K < 2^17 (checked by the host).
-constexpr int kRnsWQB = 2, kRnsWRB = 4, kRnsNW = 4, kRnsStages = 3;
+constexpr int kRnsWQB = 2, kRnsWRB = 4, kRnsNQ = kRnsTileQ / 64, kRnsNR = kRnsTileR / 128;
+constexpr int kRnsNW = kRnsNQ * kRnsNR, kRnsStages = 3;
 constexpr int kRnsPA = kRnsTileQ * kKB, kRnsPB = kRnsTileR * kKB, kRnsStage = kRnsPA + kRnsPB;
-constexpr int kRnsLA = kRnsTileQ / 16 / kRnsNW, kRnsLB = kRnsTileR / 16 / kRnsNW;  // 2 + 4 loads per wave
+constexpr int kRnsLA = kRnsTileQ / 16 / kRnsNW, kRnsLB = kRnsTileR / 16 / kRnsNW;  // 2 + 2 loads per wave
 
 __device__ __forceinline__ void dma16_rns(const int8_t* g, uint32_t lds_addr) {
   asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
@@ -109,8 +117,8 @@ __device__ __forceinline__ void dma16_rns(const int8_t* g, uint32_t lds_addr) {
                : "memory", "m0");
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_gemm_rns(RnsGemmArgs g) {
-  static_assert(kRnsLA + kRnsLB == 6, "the vmcnt below assumes 6 loads per wave per K-block");
+__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_gemm_rns(RnsGemmArgs g) {
+  static_assert(kRnsNW == 8 && kRnsLA + kRnsLB == 4, "the vmcnt below assumes 4 loads per wave per K-block");
   __shared__ __attribute__((aligned(16))) int8_t lds[kRnsStages * kRnsStage];
   const int j = blockIdx.y, z = blockIdx.z;
   const int64_t n_ct = (g.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (g.R_out + kRnsTileR - 1) / kRnsTileR;
@@ -119,7 +127,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   if (rt >= n_rt) return;
   const int64_t r0 = rt * kRnsTileR, c0 = ct * kRnsTileQ;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wq = wave & 1, wr = wave >> 1;
+  const int wq = wave % kRnsNQ, wr = wave / kRnsNQ;
   const int8_t* X = g.Xr[z] + (size_t)j * g.KB * g.d3_pad * kKB;
   const int8_t* D = g.Dr[z] + (size_t)j * g.KB * g.R_pad * kKB;
   const size_t stepA = (size_t)g.d3_pad * kKB, stepB = (size_t)g.R_pad * kKB;
@@ -157,7 +165,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   for (int64_t i = 0; i < KB; ++i) {
     // block i complete for this wave (block i + 1 may still fly), then for all waves; all waves
     // are done reading the stage that block i + 2 overwrites
-    asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
     issue((int)((i + 2) % kRnsStages), clamp(i + 2));
     const int8_t* S = lds + (int)(i % kRnsStages) * kRnsStage;
 #pragma unroll
@@ -207,44 +215,35 @@ hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s) {
   const int64_t n_ct = (g.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (g.R_out + kRnsTileR - 1) / kRnsTileR;
   const int64_t n_rt8 = (n_rt + kXcds - 1) / kXcds * kXcds;
   dim3 grid((unsigned)(n_rt8 * n_ct), (unsigned)g.n_mod, (unsigned)g.nz);
-  hipLaunchKernelGGL(k_gemm_rns, grid, dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_gemm_rns, grid, dim3(64 * kRnsNW), 0, s, g);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ CRT back to the prime
-// Entry e of prime slot z: residues s_j = S mod m_j -> mixed-radix digits c_j of the value X in
-// [0, M) (Garner: c_i = (...((s_i - c_0) m_0^-1 - c_1) m_1^-1 ... - c_{i-1}) m_{i-1}^-1 mod m_i),
-// S = X if X <= (M - 1) / 2 else X - M, and C = S mod q by Horner over the digits.
+// Entry e of prime slot z: residues s_j = S mod m_j.  With y_j = s_j (M/m_j)^-1 mod m_j,
+// S = sum_j y_j (M/m_j) - a M with a = round(sum_j y_j / m_j), since sum_j y_j (M/m_j) = S
+// (mod M) and |S| <= M / 4 (the host chooses M >= 4 max |S|), so the fraction sum_j y_j / m_j
+// - floor(...) = (S mod M) / M lies at least 1/4 away from 1/2 and single precision (error
+// below 2^-19 over 16 terms) decides a exactly; then
+// C = sum_j y_j ((M/m_j) mod q) - a (M mod q) mod q.
 __global__ void __launch_bounds__(256) k_crt_rns(const uint16_t* res, int nz, int64_t n, RnsCrtArgs ra, uint64_t* C) {
   const int64_t total = (int64_t)nz * n;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int z = (int)(t / n);
     const int64_t e = t - (int64_t)z * n;
     const uint16_t* r = res + (size_t)z * ra.n * n + e;
-    int32_t c[kRnsMaxMods];
-    for (int i = 0; i < ra.n; ++i) {
-      int32_t v = r[(size_t)i * n];
-      const int32_t mi = ra.m[i];
-      const uint32_t mg = ra.magic[i];
-      for (int k = 0; k < i; ++k) {
-        v -= (int32_t)mod_small((uint32_t)c[k], (uint32_t)mi, mg);  // c_k < m_k may exceed m_i
-        if (v < 0) v += mi;
-        v = (int32_t)mod_small((uint32_t)(v * ra.inv[i][k]), (uint32_t)mi, mg);
-      }
-      c[i] = v;
+    float frac = 0.f;
+    uint64_t acc = 0;  // sum of y_j ((M/m_j) mod q) < 16 * 2^8 * 2^36
+    for (int j = 0; j < ra.n; ++j) {
+      const uint32_t y = mod_small((uint32_t)r[(size_t)j * n] * (uint32_t)ra.inv[j], (uint32_t)ra.m[j], ra.magic[j]);
+      frac = fmaf((float)y, ra.rcp[j], frac);
+      acc += (uint64_t)y * ra.Mj_mod_q[z][j];
     }
-    bool neg = false;
-    for (int i = ra.n - 1; i >= 0; --i) {
-      if (c[i] != ra.half[i]) {
-        neg = c[i] > ra.half[i];
-        break;
-      }
-    }
+    const uint64_t a = (uint64_t)(frac + 0.5f);
     const Mod md = ra.mod[z];
-    uint64_t acc = (uint64_t)c[ra.n - 1];
-    for (int i = ra.n - 2; i >= 0; --i) acc = barrett64(acc * (uint64_t)ra.m[i] + (uint64_t)c[i], md.q, md.mu);
-    if (neg) acc = sub_mod(acc, ra.M_mod_q[z], md.q);
-    C[(size_t)z * n + e] = acc;
+    uint64_t v = barrett64(acc, md.q, md.mu);
+    v = sub_mod(v, barrett64(a * ra.M_mod_q[z], md.q, md.mu), md.q);
+    C[(size_t)z * n + e] = v;
   }
 }
 
