@@ -214,24 +214,44 @@ hipError_t launch_decode(const uint64_t* y, int64_t n, const DecodeArgs& da, dou
 // ------------------------------------------------------------------ match decision
 // Masks packed into 64-bit words, words-major ([word][row]) so that a row block reads
 // contiguous words.  Query masks are rolled by their shifts while packing.
+// Thread (word w, row): out[w][row] = bits t = 64 w .. 64 w + 63 of the row rolled by its shift
+// (bit b = mask[(t - r) mod d2] & 1, zero beyond d2).  Lanes take consecutive rows of one word,
+// so the word-major writes are coalesced; an unshifted row whose 64 bytes lie inside the mask row
+// is read as four 16-byte loads (one aligned 64-byte line when d2 is a multiple of 64).
 __global__ void k_pack_masks(const uint8_t* masks, int64_t n, int32_t d2, Shifts sh, int32_t n_shifts,
                              int32_t W, uint64_t* out) {
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // e * S + s
-  const int32_t w = blockIdx.y;
-  if (row >= n * n_shifts) return;
+  const int64_t rows = n * n_shifts;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * W) return;
+  const int32_t w = (int32_t)(idx / rows);
+  const int64_t row = idx - (int64_t)w * rows;  // e * S + s
   const int64_t e = row / n_shifts;
   const int32_t r = sh.r[row % n_shifts];
   const uint8_t* m = masks + e * d2;
+  const int64_t t0 = (int64_t)w * 64;
   uint64_t word = 0;
-  for (int b = 0; b < 64; ++b) {
-    const int64_t t = (int64_t)w * 64 + b;
-    if (t < d2) {
-      int64_t src = (t - r) % d2;
-      if (src < 0) src += d2;
-      word |= (uint64_t)(m[src] & 1) << b;
+  if (r == 0 && t0 + 64 <= d2 && (((uintptr_t)(m + t0)) & 15) == 0) {
+    const uint4* p = reinterpret_cast<const uint4*>(m + t0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint4 v = p[i];
+      const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) word |= (uint64_t)((d[k] >> (8 * b)) & 1u) << (16 * i + 4 * k + b);
+    }
+  } else {
+    for (int b = 0; b < 64; ++b) {
+      const int64_t t = t0 + b;
+      if (t < d2) {
+        int64_t src = (t - r) % d2;
+        if (src < 0) src += d2;
+        word |= (uint64_t)(m[src] & 1) << b;
+      }
     }
   }
-  out[(int64_t)w * (n * n_shifts) + row] = word;
+  out[(int64_t)w * rows + row] = word;
 }
 
 constexpr int kMatchCols = 16;
@@ -301,11 +321,11 @@ hipError_t launch_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eye
   const int64_t d3 = n_eyes * n_shifts;
   Shifts sh{}, zero{};
   for (int i = 0; i < n_shifts; ++i) sh.r[i] = shifts[i];
-  hipLaunchKernelGGL(k_pack_masks, dim3((unsigned)((d3 + 255) / 256), (unsigned)W), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_pack_masks, dim3((unsigned)((d3 * W + 255) / 256)), dim3(256), 0, s,
                      q_masks, n_eyes, d2, sh, n_shifts, W, qwords);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pack_masks, dim3((unsigned)((rows + 255) / 256), (unsigned)W), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_pack_masks, dim3((unsigned)((rows * W + 255) / 256)), dim3(256), 0, s,
                      db_masks, rows, d2, zero, 1, W, dbwords);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
