@@ -232,6 +232,7 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time every int8 tile configuration and exit")
     ap.add_argument("--variant", type=int, default=-1, help="int8 tile configuration (-1: default)")
     ap.add_argument("--ccmm-only", type=int, default=0, help="run N int8 CCMMs after setup and exit (profiling)")
+    ap.add_argument("--form", choices=("i8", "rns"), default="i8", help="with --ccmm-only: the int8 form to run")
     ap.add_argument("--mode", choices=("step", "batched", "serving"), default="step",
                     help="step: the hot-path step (default); batched: 64 uneven items as one plan; "
                          "serving: Poisson arrivals through the server")
@@ -271,7 +272,7 @@ def main():
     q_codes = torch.from_numpy(inp["q_codes"]).to(dev)
     q_masks = torch.from_numpy(inp["q_masks"]).to(dev)
     shifts = [int(s) for s in inp["shifts"]]
-    log("encrypting the database (both forms)")
+    log("encrypting the database (plain, digit and RNS forms)")
     t0 = time.perf_counter()
     m_db = H.hfe_encode(db_codes, db_masks, [0])
     db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
@@ -307,8 +308,9 @@ def main():
     if args.ccmm_only:
         m_q = H.hfe_encode(q_codes, q_masks, shifts)
         qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+        form = H.HFE_FORM_RNS_I8 if args.form == "rns" else H.HFE_FORM_I8_MFMA
         for _ in range(args.ccmm_only):
-            H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_I8_MFMA).free()
+            H.hfe_ccmm(db, qct, 0, w.d1, form).free()
         torch.cuda.synchronize()
         log(f"ran {args.ccmm_only} int8 CCMMs")
         if args.copy_mib:
