@@ -134,12 +134,15 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
 
 /* Batched CCMM: item i is its own CCMM of items[i].q (any level, any column count) against the
  * database codes [items[i].row0, items[i].row0 + items[i].rows), all against one database.
- * int8 form: one grouped launch lifts and digit-splits every item's query, ONE persistent launch
- * computes the tiles of every item and prime (workgroups claim tiles of a device-resident tile
- * table in order), one grouped launch rescales; all items share one tile configuration (the
- * forced one, else of the tuned and the default configuration the one that pads the items
- * least); plain form: one hfe_ccmm per item.  outs[i] receives item i's result handle (release
- * each with hfe_free).  1 <= n <= 256. */
+ * Items with the same level and row range form one problem, their query columns side by side (so
+ * only a problem pads its columns to whole tiles).  int8 forms (HFE_FORM_I8_MFMA, HFE_FORM_RNS_I8):
+ * one grouped launch lifts and splits every item's query, ONE persistent launch computes the tiles
+ * of every problem, prime (and small modulus) (workgroups claim tiles of a device-resident tile
+ * table in order), for the RNS form one grouped launch reconstructs the residues mod each prime,
+ * and one grouped launch rescales every item; the digit form's problems share one tile
+ * configuration (the forced one, else of the tuned and the default configuration the one that pads
+ * the problems least); plain form: one hfe_ccmm per item.  outs[i] receives item i's result handle
+ * (release each with hfe_free).  1 <= n <= 256. */
 typedef struct {
   const hfe_qct* q;
   int64_t row0, rows;
@@ -147,18 +150,19 @@ typedef struct {
 hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32_t n, int32_t form,
                             void* stream, hfe_rct** outs);
 
-/* Reusable batched int8 CCMM for repeated batches (e.g. serving steps): the workspace for up to
+/* Reusable batched int8 CCMM for repeated batches (e.g. serving steps), in the int8 form `form`
+ * (HFE_FORM_I8_MFMA or HFE_FORM_RNS_I8, prepared in the database): the workspace for up to
  * max_items items, max_cols query columns in total and levels up to max_level is allocated once;
  * hfe_plan_run writes the batch's descriptor tables (a host-to-device copy on `stream`) and
- * enqueues the three grouped launches; with use_graph they are captured, on the first run that
- * uses a tile configuration, into a hipGraph that later runs with that configuration replay (any
- * later stream is fine; the graph is launched on it).  hfe_plan_result
+ * enqueues the grouped launches; with use_graph they are captured, on the first run that uses a
+ * tile configuration, into a hipGraph that later runs with that configuration replay (any later
+ * stream is fine; the graph is launched on it).  hfe_plan_result
  * returns item i's result of the last run as a view owned by the plan: valid until the next
  * hfe_plan_run or hfe_free(plan); hfe_free on the view does nothing.  Runs on one plan must not
  * overlap; the plan's database must outlive it. */
 typedef struct hfe_plan hfe_plan;
 hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols, uint32_t max_level,
-                           hfe_plan** out);
+                           int32_t form, hfe_plan** out);
 hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, int32_t use_graph,
                         void* stream);
 hfe_status hfe_plan_result(const hfe_plan* plan, int32_t i, const hfe_rct** view);
@@ -175,7 +179,8 @@ hfe_status hfe_autotune(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_
 hfe_status hfe_autotune_save(const char* path);
 hfe_status hfe_autotune_load(const char* path);
 
-/* Continuous-batching server over a resident database (int8 form).  A worker thread keeps
+/* Continuous-batching server over a resident database, in the int8 form `form` (HFE_FORM_I8_MFMA
+ * or HFE_FORM_RNS_I8, prepared in the database).  A worker thread keeps
  * n_slots steps in flight on their own streams; each step admits queued requests in arrival
  * order while their columns fit the step (at most max_cols_per_step columns, at most
  * max_items_per_step requests, and the memory budget: mem_budget bytes of workspace split over
@@ -198,7 +203,7 @@ typedef struct {
   double req_per_s, cmp_per_s, mean_cols_per_step, elapsed_s;
 } hfe_server_report;
 hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_cols_per_step,
-                             int32_t max_items_per_step, int32_t n_slots, uint32_t max_level,
+                             int32_t max_items_per_step, int32_t n_slots, uint32_t max_level, int32_t form,
                              hfe_server** out);
 hfe_status hfe_server_submit(hfe_server* srv, const hfe_qct* q, int32_t* ip_out, uint64_t* ticket);
 hfe_status hfe_server_poll(hfe_server* srv, uint64_t ticket, int32_t* state);

@@ -100,13 +100,13 @@ _SIGS = {
     "hfe_profile_ms": [_vp, _vp, _i32],
     "hfe_set_i8_variant": [_i32],
     "hfe_ccmm_batched": [_vp, ctypes.POINTER(hfe_batch_item), _i32, _i32, _vp, ctypes.POINTER(_vp)],
-    "hfe_plan_create": [_vp, _i32, _i64, _u32, ctypes.POINTER(_vp)],
+    "hfe_plan_create": [_vp, _i32, _i64, _u32, _i32, ctypes.POINTER(_vp)],
     "hfe_plan_run": [_vp, ctypes.POINTER(hfe_batch_item), _i32, _i32, _vp],
     "hfe_plan_result": [_vp, _i32, ctypes.POINTER(_vp)],
     "hfe_autotune": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_i32)],
     "hfe_autotune_save": [ctypes.c_char_p],
     "hfe_autotune_load": [ctypes.c_char_p],
-    "hfe_server_create": [_vp, _sz, _i64, _i32, _i32, _u32, ctypes.POINTER(_vp)],
+    "hfe_server_create": [_vp, _sz, _i64, _i32, _i32, _u32, _i32, ctypes.POINTER(_vp)],
     "hfe_server_submit": [_vp, _vp, _vp, ctypes.POINTER(_u64)],
     "hfe_server_poll": [_vp, _u64, ctypes.POINTER(_i32)],
     "hfe_server_wait": [_vp, _u64, _i64],
@@ -378,9 +378,10 @@ def hfe_ccmm_batched(db: Handle, items, form: int, stream=None):
     return [Handle(outs[i], (db, items[i][0])) for i in range(len(items))]
 
 
-def hfe_plan_create(db: Handle, max_items: int, max_cols: int, max_level: int) -> Handle:
+def hfe_plan_create(db: Handle, max_items: int, max_cols: int, max_level: int,
+                    form: int = HFE_FORM_I8_MFMA) -> Handle:
     out = _vp()
-    _check(_lib.hfe_plan_create(db.ptr, max_items, max_cols, max_level, ctypes.byref(out)), "hfe_plan_create")
+    _check(_lib.hfe_plan_create(db.ptr, max_items, max_cols, max_level, form, ctypes.byref(out)), "hfe_plan_create")
     return Handle(out.value, (db,))
 
 
@@ -419,10 +420,10 @@ class Server(Handle):
 
 
 def hfe_server_create(db: Handle, mem_budget: int, max_cols_per_step: int, max_items_per_step: int = 64,
-                      n_slots: int = 2, max_level: int = 1) -> Server:
+                      n_slots: int = 2, max_level: int = 1, form: int = HFE_FORM_I8_MFMA) -> Server:
     out = _vp()
     _check(_lib.hfe_server_create(db.ptr, mem_budget, max_cols_per_step, max_items_per_step, n_slots, max_level,
-                                  ctypes.byref(out)), "hfe_server_create")
+                                  form, ctypes.byref(out)), "hfe_server_create")
     return Server(out.value, (db,))
 
 

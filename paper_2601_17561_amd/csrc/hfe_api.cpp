@@ -782,9 +782,10 @@ hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n) {
 }  // extern "C"
 
 namespace {
-// Byte layout of the descriptor tables of a batch of up to `cap` items (256-byte aligned parts).
+// Byte layout of the descriptor tables of a batch of up to `cap` items (256-byte aligned parts):
+// contraction (per problem), lift (per item), rescale (per item), RNS reconstruction (per problem).
 struct BlobLayout {
-  size_t gh, gd, lh, ld, rh, rd, bytes;
+  size_t gh, gd, lh, ld, rh, rd, ch, cd, bytes;
   explicit BlobLayout(int cap) {
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     gh = 0;
@@ -793,14 +794,16 @@ struct BlobLayout {
     ld = al(lh + sizeof(BatchElemHeader));
     rh = al(ld + sizeof(BatchLiftDesc) * cap);
     rd = al(rh + sizeof(BatchElemHeader));
-    bytes = al(rd + sizeof(BatchRescaleDesc) * cap);
+    ch = al(rd + sizeof(BatchRescaleDesc) * cap);
+    cd = al(ch + sizeof(BatchElemHeader));
+    bytes = al(cd + sizeof(BatchCrtDesc) * cap);
   }
 };
 
 struct BatchSizes {
-  size_t xd_bytes = 0, c_elems = 0, out_elems = 0;
+  size_t xd_bytes = 0, c_elems = 0, res_elems = 0, out_elems = 0;
   int64_t cols = 0;
-  int max_level = 0;
+  int max_level = 0, problems = 0;
 };
 
 hfe_status check_item(const hfe_db* D, const hfe_batch_item& it) {
@@ -813,71 +816,150 @@ hfe_status check_item(const hfe_db* D, const hfe_batch_item& it) {
   return HFE_OK;
 }
 
-// Sizes of a batch, and (when blob != nullptr) its descriptor tables pointing into the given
-// workspace (xd_base, c_base) and result arrays (outs[i]).
-BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int variant, int8_t* xd_base,
-                      uint64_t* c_base, uint64_t* const* outs, uint8_t* blob, const BlobLayout& L) {
+// Problems of a batch: the items with the same level and row range, in order of first appearance;
+// an item's query columns follow those of the problem's earlier items.
+struct Grouping {
+  std::vector<int> prob;                   // problem of each item
+  std::vector<int64_t> c0;                 // first column of each item in its problem
+  std::vector<int> last;                   // last item of each problem
+  std::vector<int> first;                  // first item of each problem
+  std::vector<int64_t> d3;                 // columns of each problem
+};
+
+Grouping group_items(const hfe_batch_item* items, int n) {
+  Grouping g;
+  g.prob.resize(n);
+  g.c0.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const hfe_qct* Qi = static_cast<const hfe_qct*>(items[i].q);
+    int b = -1;
+    for (size_t k = 0; k < g.first.size(); ++k) {
+      const hfe_batch_item& f = items[g.first[k]];
+      if (static_cast<const hfe_qct*>(f.q)->level == Qi->level && f.row0 == items[i].row0 && f.rows == items[i].rows) {
+        b = (int)k;
+        break;
+      }
+    }
+    if (b < 0) {
+      b = (int)g.first.size();
+      g.first.push_back(i);
+      g.last.push_back(i);
+      g.d3.push_back(0);
+    }
+    g.prob[i] = b;
+    g.c0[i] = g.d3[b];
+    g.d3[b] += Qi->d3;
+    g.last[b] = i;
+  }
+  return g;
+}
+
+// Sizes of a batch for a form (HFE_FORM_I8_MFMA with the digit tile `variant`, or HFE_FORM_RNS_I8),
+// and (when blob != nullptr) its descriptor tables pointing into the given workspace (xd_base,
+// c_base, res_base) and result arrays (outs[i]).
+BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int form, int variant, int8_t* xd_base,
+                      uint64_t* c_base, uint16_t* res_base, uint64_t* const* outs, uint8_t* blob,
+                      const BlobLayout& L) {
   const hfe_keys* K = D->keys;
   const int64_t ndb = 1ll << K->P.log_n_db;
+  const bool rns = form == HFE_FORM_RNS_I8;
+  const int planes = rns ? D->n_rns : kDigits;
+  const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
+  const Grouping gr = group_items(items, n);
+  const int np = (int)gr.first.size();
   BatchSizes z;
-  int64_t tiles = 0, lift_e = 0, resc_e = 0;
-  for (int i = 0; i < n; ++i) {
-    const hfe_qct* Qc = static_cast<const hfe_qct*>(items[i].q);
-    const int level = Qc->level, nz = level + 1;
-    const int64_t d3 = Qc->d3, d3_pad = (d3 + kQueryPad - 1) / kQueryPad * kQueryPad;
-    const int64_t R_out = ndb + items[i].rows;
-    const size_t xd_i = (size_t)nz * kDigits * D->KB * d3_pad * kKB;
-    const size_t c_i = (size_t)nz * d3 * R_out;
+  z.problems = np;
+  std::vector<size_t> xd_off(np), c_off(np), res_off(np);
+  std::vector<int64_t> d3_pad(np), R_out(np);
+  int64_t tiles = 0, crt_e = 0;
+  for (int b = 0; b < np; ++b) {
+    const hfe_batch_item& f = items[gr.first[b]];
+    const int level = static_cast<const hfe_qct*>(f.q)->level, nz = level + 1;
+    const int64_t d3 = gr.d3[b];
+    d3_pad[b] = (d3 + qpad - 1) / qpad * qpad;
+    R_out[b] = ndb + f.rows;
+    xd_off[b] = z.xd_bytes;
+    c_off[b] = z.c_elems;
+    res_off[b] = z.res_elems;
     if (blob) {
-      BatchDesc& g = reinterpret_cast<BatchDesc*>(blob + L.gd)[i];
+      BatchDesc& g = reinterpret_cast<BatchDesc*>(blob + L.gd)[b];
       std::memset(&g, 0, sizeof(g));
-      g.Xd = xd_base + z.xd_bytes;
-      g.C = c_base + z.c_elems;
-      g.row0 = items[i].row0;
-      g.R_out = R_out;
+      g.Xd = xd_base + xd_off[b];
+      g.C = c_base + c_off[b];
+      g.res = rns ? res_base + res_off[b] : nullptr;
+      g.row0 = f.row0;
+      g.R_out = R_out[b];
       g.d3 = d3;
-      g.d3_pad = d3_pad;
+      g.d3_pad = d3_pad[b];
       g.tile_begin = tiles;
       g.nz = nz;
       for (int zz = 0; zz < nz; ++zz) {
         g.slot[zz] = zz < level ? zz : K->L;
         g.mod[zz] = K->mods[g.slot[zz]];
       }
+      if (rns) {
+        BatchCrtDesc& c = reinterpret_cast<BatchCrtDesc*>(blob + L.cd)[b];
+        std::memset(&c, 0, sizeof(c));
+        c.res = g.res;
+        c.C = g.C;
+        c.n = d3 * R_out[b];
+        c.elem_begin = crt_e;
+        c.nz = nz;
+        c.level = level;
+        c.pslot = K->L;
+      }
+    }
+    tiles += rns ? rns_batched_tiles(d3, R_out[b], nz, planes) : i8_batched_tiles(variant, d3, R_out[b], nz);
+    crt_e += ((int64_t)nz * d3 * R_out[b] + 255) / 256 * 256;
+    z.xd_bytes += (size_t)nz * planes * D->KB * d3_pad[b] * kKB;
+    z.c_elems += (size_t)nz * d3 * R_out[b];
+    if (rns) z.res_elems += (size_t)nz * planes * d3 * R_out[b];
+    z.max_level = std::max(z.max_level, level);
+  }
+  int64_t lift_e = 0, resc_e = 0;
+  for (int i = 0; i < n; ++i) {
+    const hfe_qct* Qc = static_cast<const hfe_qct*>(items[i].q);
+    const int b = gr.prob[i], level = Qc->level;
+    const int64_t d3 = Qc->d3;
+    const int64_t cols = d3 + (gr.last[b] == i ? d3_pad[b] - gr.d3[b] : 0);  // the last item writes the padding
+    if (blob) {
       BatchLiftDesc& l = reinterpret_cast<BatchLiftDesc*>(blob + L.ld)[i];
       std::memset(&l, 0, sizeof(l));
       l.XT = Qc->XT.as<uint64_t>();
-      l.Xd = xd_base + z.xd_bytes;
+      l.Xd = xd_base + xd_off[b];
       l.d3 = d3;
-      l.d3_pad = d3_pad;
+      l.c0 = gr.c0[i];
+      l.cols = cols;
+      l.d3_pad = d3_pad[b];
       l.elem_begin = lift_e;
       l.la = make_lift_args(K, level);
       BatchRescaleDesc& r = reinterpret_cast<BatchRescaleDesc*>(blob + L.rd)[i];
       std::memset(&r, 0, sizeof(r));
-      r.C = g.C;
+      r.C = c_base + c_off[b] + gr.c0[i] * R_out[b];
+      r.zstride = gr.d3[b] * R_out[b];
       r.out = outs[i];
-      r.n = d3 * R_out;
+      r.n = d3 * R_out[b];
       r.elem_begin = resc_e;
       r.ra = make_rescale_args(K, level);
     }
-    tiles += i8_batched_tiles(variant, d3, R_out, nz);
-    lift_e += d3_pad * D->KB * kKB;
-    resc_e += (d3 * R_out + 255) / 256 * 256;
-    z.xd_bytes += xd_i;
-    z.c_elems += c_i;
-    z.out_elems += (size_t)level * d3 * R_out;
+    lift_e += (cols * D->KB * kKB + 255) / 256 * 256;
+    resc_e += (d3 * R_out[b] + 255) / 256 * 256;
+    z.out_elems += (size_t)level * d3 * R_out[b];
     z.cols += d3;
-    z.max_level = std::max(z.max_level, level);
   }
   if (blob) {
     BatchHeader* gh = reinterpret_cast<BatchHeader*>(blob + L.gh);
     gh->total_tiles = tiles;
-    gh->n = n;
+    gh->n = np;
     BatchElemHeader* lh = reinterpret_cast<BatchElemHeader*>(blob + L.lh);
     lh->total = lift_e;
     lh->n = n;
     BatchElemHeader* rh = reinterpret_cast<BatchElemHeader*>(blob + L.rh);
     rh->total = resc_e;
     rh->n = n;
+    BatchElemHeader* ch = reinterpret_cast<BatchElemHeader*>(blob + L.ch);
+    ch->total = rns ? crt_e : 0;
+    ch->n = rns ? np : 0;
   }
   return z;
 }
@@ -895,45 +977,73 @@ int device_cus() {
   return cus;
 }
 
-hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout& L, int variant, int gemm_grid,
+int gemm_grid_for(int form, int variant) {
+  const int g = device_cus() * (form == HFE_FORM_RNS_I8 ? rns_wgs_per_cu() : i8_variant_wgs_per_cu(variant));
+  return (g + kXcds - 1) / kXcds * kXcds;
+}
+constexpr int kElemGrid = 4096;
+
+hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout& L, int form, int variant,
                          int elem_grid, hipStream_t s) {
+  const bool rns = form == HFE_FORM_RNS_I8;
   HFE_LAUNCH(launch_lift_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.lh),
-                                 reinterpret_cast<const BatchLiftDesc*>(dblob + L.ld), D->K, D->KB, elem_grid, s));
-  BatchGemmArgs a;
-  a.hdr = reinterpret_cast<const BatchHeader*>(dblob + L.gh);
-  a.next = const_cast<uint32_t*>(a.hdr->next);
-  a.desc = reinterpret_cast<const BatchDesc*>(dblob + L.gd);
-  a.Dd = D->digits.as<int8_t>();
-  a.KB = D->KB;
-  a.R_pad = D->R_pad;
-  a.n_db = 1ll << D->keys->P.log_n_db;
-  HFE_LAUNCH(launch_gemm_i8_batched(a, variant, gemm_grid, s));
+                                 reinterpret_cast<const BatchLiftDesc*>(dblob + L.ld), D->K, D->KB,
+                                 rns ? D->n_rns : 0, elem_grid, s));
+  const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(dblob + L.gh);
+  const int64_t ndb = 1ll << D->keys->P.log_n_db;
+  if (rns) {
+    RnsBatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.hdr = hdr;
+    a.next = const_cast<uint32_t*>(hdr->next);
+    a.desc = reinterpret_cast<const BatchDesc*>(dblob + L.gd);
+    a.Dr = D->rns.as<int8_t>();
+    a.n_mod = D->n_rns;
+    for (int j = 0; j < D->n_rns; ++j) {
+      a.m[j] = kRnsMods[j];
+      a.magic[j] = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)kRnsMods[j] - 1) / (uint64_t)kRnsMods[j]);
+    }
+    a.KB = D->KB;
+    a.R_pad = D->R_pad;
+    a.n_db = ndb;
+    HFE_LAUNCH(launch_gemm_rns_batched(a, gemm_grid_for(form, 0), s));
+    // by-slot constants: level L makes z index the database slot
+    HFE_LAUNCH(launch_crt_rns_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.ch),
+                                      reinterpret_cast<const BatchCrtDesc*>(dblob + L.cd),
+                                      make_rns_crt_args(D->keys, D->keys->L, D->n_rns), elem_grid, s));
+  } else {
+    BatchGemmArgs a;
+    a.hdr = hdr;
+    a.next = const_cast<uint32_t*>(hdr->next);
+    a.desc = reinterpret_cast<const BatchDesc*>(dblob + L.gd);
+    a.Dd = D->digits.as<int8_t>();
+    a.KB = D->KB;
+    a.R_pad = D->R_pad;
+    a.n_db = ndb;
+    HFE_LAUNCH(launch_gemm_i8_batched(a, variant, gemm_grid_for(form, variant), s));
+  }
   HFE_LAUNCH(launch_rescale_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.rh),
                                     reinterpret_cast<const BatchRescaleDesc*>(dblob + L.rd), elem_grid, s));
   return HFE_OK;
 }
 
-int gemm_grid_for(int variant) {
-  const int g = device_cus() * i8_variant_wgs_per_cu(variant);
-  return (g + kXcds - 1) / kXcds * kXcds;
-}
-constexpr int kElemGrid = 4096;
-
-// Tile configuration of a batch: the forced one if set; else, of the configuration tuned for the
-// batch's largest level and mean column count and the default one, the one whose tiles pad the
+// Digit tile configuration of a batch: the forced one if set; else, of the configuration tuned for
+// the batch's largest level and mean column count and the default one, the one whose tiles pad the
 // batch's problems least (MFMA work including padded rows and columns); ties go to the tuned one.
 int choose_batch_variant(const hfe_db* D, const hfe_batch_item* items, int n, int max_level, int64_t mean_cols) {
   if (g_i8_variant.load() >= 0) return g_i8_variant.load();
   const int tuned = pick_i8_variant(max_level, mean_cols);
   if (tuned == kDefaultI8Variant) return tuned;
   const int64_t ndb = 1ll << D->keys->P.log_n_db;
+  const Grouping gr = group_items(items, n);
   auto padded = [&](int v) {
     const int64_t br = i8_variant_tile_rows(v), bq = i8_variant_tile_cols(v);
     double w = 0;
-    for (int i = 0; i < n; ++i) {
-      const hfe_qct* Qc = static_cast<const hfe_qct*>(items[i].q);
-      const int64_t R = ndb + items[i].rows;
-      w += (double)(Qc->level + 1) * ((Qc->d3 + bq - 1) / bq * bq) * ((R + br - 1) / br * br);
+    for (size_t b = 0; b < gr.first.size(); ++b) {
+      const hfe_batch_item& f = items[gr.first[b]];
+      const int64_t R = ndb + f.rows;
+      w += (double)(static_cast<const hfe_qct*>(f.q)->level + 1) * ((gr.d3[b] + bq - 1) / bq * bq) *
+           ((R + br - 1) / br * br);
     }
     return w;
   };
@@ -956,7 +1066,7 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
     HFE_TRY(check_item(D, items[i]));
   }
   hipStream_t s = (hipStream_t)stream;
-  if (form != HFE_FORM_I8_MFMA) {  // plain and RNS forms: one call per item
+  if (form == HFE_FORM_PLAIN_U64) {  // one call per item
     for (int i = 0; i < n; ++i) {
       hfe_status st = hfe_ccmm(db, items[i].q, items[i].row0, items[i].rows, form, stream, &outs[i]);
       if (st != HFE_OK) {
@@ -966,10 +1076,10 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
     }
     return HFE_OK;
   }
-  // all items of one batch use one tile configuration
+  // all problems of one batch use one tile configuration
   const BlobLayout L(n);
-  const BatchSizes sz0 = batch_fill(D, items, n, 0, nullptr, nullptr, nullptr, nullptr, L);
-  const int variant = choose_batch_variant(D, items, n, sz0.max_level, sz0.cols / n);
+  const BatchSizes sz0 = batch_fill(D, items, n, form, 0, nullptr, nullptr, nullptr, nullptr, nullptr, L);
+  const int variant = form == HFE_FORM_I8_MFMA ? choose_batch_variant(D, items, n, sz0.max_level, sz0.cols / n) : 0;
   const hfe_keys* K = D->keys;
   const int64_t ndb = 1ll << K->P.log_n_db;
   std::vector<hfe_rct*> R(n, nullptr);
@@ -1001,23 +1111,25 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
     r->outp = r->out.as<uint64_t>();
     outp[i] = r->outp;
   }
-  DevBuf Xd, C, blob;
+  DevBuf Xd, C, res, blob;
   hfe_status st = Xd.alloc(sz0.xd_bytes, s);
   if (st == HFE_OK) st = C.alloc(sizeof(uint64_t) * sz0.c_elems, s);
+  if (st == HFE_OK && sz0.res_elems) st = res.alloc(sizeof(uint16_t) * sz0.res_elems, s);
   if (st == HFE_OK) st = blob.alloc(L.bytes, s);
   if (st != HFE_OK) {
     cleanup();
     return st;
   }
   std::vector<uint8_t> host(L.bytes, 0);
-  batch_fill(D, items, n, variant, Xd.as<int8_t>(), C.as<uint64_t>(), outp.data(), host.data(), L);
+  batch_fill(D, items, n, form, variant, Xd.as<int8_t>(), C.as<uint64_t>(), res.as<uint16_t>(), outp.data(),
+             host.data(), L);
   hipError_t e = hipMemcpyAsync(blob.ptr, host.data(), L.bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // the pageable staging is freed on return
   if (e != hipSuccess) {
     cleanup();
     return hip_fail(e, "descriptor upload");
   }
-  st = batch_enqueue(D, blob.as<uint8_t>(), L, variant, gemm_grid_for(variant), kElemGrid, s);
+  st = batch_enqueue(D, blob.as<uint8_t>(), L, form, variant, kElemGrid, s);
   if (st != HFE_OK) {
     cleanup();
     return st;
@@ -1026,13 +1138,14 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
   return HFE_OK;
 }
 
-hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols, uint32_t max_level,
+hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols, uint32_t max_level, int32_t form,
                            hfe_plan** out) {
   if (!out) return fail(HFE_EINVAL, "out is NULL");
   *out = nullptr;
   const hfe_db* D = as_handle<hfe_db>(db, kDb);
   if (!D) return fail(HFE_EINVAL, "invalid database handle");
-  if (!(D->forms & HFE_FORM_I8_MFMA)) return fail(HFE_EINVAL, "database not prepared for the int8 form");
+  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8) return fail(HFE_EINVAL, "plans run an int8 form");
+  if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   if (max_items < 1 || max_items > kMaxBatch) return fail(HFE_EINVAL, "max_items must be 1 .. 256");
   if (max_cols < 1 || max_level < 1 || (int)max_level > D->keys->L) return fail(HFE_EINVAL, "bad capacity");
   hfe_plan* P = new (std::nothrow) hfe_plan();
@@ -1040,19 +1153,25 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   P->kind = kPlan;
   P->stream = nullptr;
   P->db = D;
+  P->form = form;
   P->max_items = max_items;
   P->max_cols = max_cols;
   P->max_level = (int)max_level;
+  const bool rns = form == HFE_FORM_RNS_I8;
+  const int planes = rns ? D->n_rns : kDigits;
+  const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
   const int64_t ndb = 1ll << D->keys->P.log_n_db;
   const int64_t R_max = ndb + D->d1;
-  const int64_t cols_pad = max_cols + (int64_t)max_items * (kQueryPad - 1);
-  P->xd_cap = (size_t)(max_level + 1) * kDigits * D->KB * cols_pad * kKB;
+  const int64_t cols_pad = max_cols + (int64_t)max_items * (qpad - 1);  // every item its own problem
+  P->xd_cap = (size_t)(max_level + 1) * planes * D->KB * cols_pad * kKB;
   P->c_cap = (size_t)(max_level + 1) * max_cols * R_max;
+  P->res_cap = rns ? (size_t)(max_level + 1) * planes * max_cols * R_max : 0;
   P->out_cap = (size_t)max_level * max_cols * R_max;
   const BlobLayout L(max_items);
   P->blob_bytes = L.bytes;
   hfe_status st = P->ws_xd.alloc(P->xd_cap, nullptr);
   if (st == HFE_OK) st = P->ws_c.alloc(sizeof(uint64_t) * P->c_cap, nullptr);
+  if (st == HFE_OK && rns) st = P->ws_res.alloc(sizeof(uint16_t) * P->res_cap, nullptr);
   if (st == HFE_OK) st = P->ws_out.alloc(sizeof(uint64_t) * P->out_cap, nullptr);
   if (st == HFE_OK) st = P->desc.alloc(L.bytes, nullptr);
   hipError_t e = hipSuccess;
@@ -1090,10 +1209,11 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
       return fail(HFE_ELEVEL, "item level above the plan's maximum");
   }
   const BlobLayout L(P->max_items);
-  const BatchSizes sz = batch_fill(D, items, n, 0, nullptr, nullptr, nullptr, nullptr, L);
-  const int variant = choose_batch_variant(D, items, n, sz.max_level, sz.cols / n);
-  const int gemm_grid = gemm_grid_for(variant);
-  if (sz.cols > P->max_cols || sz.xd_bytes > P->xd_cap || sz.c_elems > P->c_cap || sz.out_elems > P->out_cap)
+  const BatchSizes sz = batch_fill(D, items, n, P->form, 0, nullptr, nullptr, nullptr, nullptr, nullptr, L);
+  const int variant =
+      P->form == HFE_FORM_I8_MFMA ? choose_batch_variant(D, items, n, sz.max_level, sz.cols / n) : 0;
+  if (sz.cols > P->max_cols || sz.xd_bytes > P->xd_cap || sz.c_elems > P->c_cap || sz.res_elems > P->res_cap ||
+      sz.out_elems > P->out_cap)
     return fail(HFE_ESHAPE, "batch exceeds the plan's workspace");
   hipStream_t s = (hipStream_t)stream;
   // result views: consecutive slices of the output workspace
@@ -1117,11 +1237,12 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
   HFE_LAUNCH(hipEventSynchronize(P->copied));
   uint8_t* host = static_cast<uint8_t*>(P->host_blob);
   std::memset(host, 0, P->blob_bytes);
-  batch_fill(D, items, n, variant, P->ws_xd.as<int8_t>(), P->ws_c.as<uint64_t>(), outp.data(), host, L);
+  batch_fill(D, items, n, P->form, variant, P->ws_xd.as<int8_t>(), P->ws_c.as<uint64_t>(),
+             P->ws_res.as<uint16_t>(), outp.data(), host, L);
   HFE_LAUNCH(hipMemcpyAsync(P->desc.ptr, host, P->blob_bytes, hipMemcpyHostToDevice, s));
   HFE_LAUNCH(hipEventRecord(P->copied, s));
   if (!use_graph) {
-    HFE_TRY(batch_enqueue(D, P->desc.as<uint8_t>(), L, variant, gemm_grid, P->elem_grid, s));
+    HFE_TRY(batch_enqueue(D, P->desc.as<uint8_t>(), L, P->form, variant, P->elem_grid, s));
   } else {
     if (!P->exec[variant]) {
       // capture on a private stream that joins the caller's stream through events
@@ -1129,7 +1250,7 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
       HFE_LAUNCH(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
       hfe_status st = HFE_OK;
       hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) st = batch_enqueue(D, P->desc.as<uint8_t>(), L, variant, gemm_grid, P->elem_grid, cap);
+      if (e == hipSuccess) st = batch_enqueue(D, P->desc.as<uint8_t>(), L, P->form, variant, P->elem_grid, cap);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(cap, &g);
       (void)hipStreamDestroy(cap);

@@ -273,6 +273,28 @@ struct RnsCrtArgs {
 hipError_t launch_crt_rns(const uint16_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
                           hipStream_t s);
 constexpr int kRnsTileR = 256, kRnsTileQ = 256;  // workgroup tile of the RNS contraction
+struct BatchDesc;
+struct BatchHeader;
+struct BatchElemHeader;
+struct BatchCrtDesc;
+// Batched RNS contraction: problem b's tiles are [tile_begin, tile_begin + rns_batched_tiles(...)),
+// ordered (z, modulus, XCD-ordered tile); workgroups claim tiles per XCD as the digit form's.
+struct RnsBatchArgs {
+  const BatchHeader* hdr;
+  uint32_t* next;
+  const BatchDesc* desc;
+  const int8_t* Dr;                            // database planes, all slots: [slot][n_mod][KB][R_pad][64]
+  int32_t n_mod, pad_;
+  int32_t m[kRnsMaxMods];
+  uint32_t magic[kRnsMaxMods];
+  int64_t KB, R_pad, n_db;
+};
+int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod);
+hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, hipStream_t s);
+// ra indexed by database slot (mod, Mj_mod_q, M_mod_q of slot z at [z])
+hipError_t launch_crt_rns_batched(const BatchElemHeader* hdr, const BatchCrtDesc* d, const RnsCrtArgs& ra,
+                                  int grid, hipStream_t s);
+int rns_wgs_per_cu();
 
 // Plain uint64 contraction.  For each prime slot z < nz: C[z][c][r] = sum_k Dt[z][k][src(r)] *
 // X[z][c][k] mod prime, rows r < R_out mapped to source rows (A-part then the shard).
@@ -296,9 +318,13 @@ int i8_variant_tile_cols(int v);
 int i8_variant_wgs_per_cu(int v);  // resident workgroups per CU the configuration is sized for
 
 // Batched contraction: a device-resident table of problems sharing one database.
+// A batch's problems: items with the same level and database row range are merged into one
+// problem (their query columns side by side), so that only a problem, not every item, pads its
+// columns to whole tiles.
 struct BatchDesc {
-  const int8_t* Xd;               // [nz][5][KB][d3_pad][64] query digits of this problem
+  const int8_t* Xd;               // [nz][planes][KB][d3_pad][64] query planes of this problem
   uint64_t* C;                    // [nz][d3][R_out] contraction output
+  uint16_t* res;                  // RNS form: [nz][n_mod][d3][R_out] residues by small modulus
   int64_t row0, R_out, d3, d3_pad;
   int64_t tile_begin;             // first tile of this problem in the launch (multiple of 8)
   int32_t nz, pad_;
@@ -364,20 +390,29 @@ struct BatchElemHeader {
   int64_t total;                  // elements of the launch (chunks of 256 per problem start)
   int32_t n, pad_;
 };
-struct BatchLiftDesc {
-  const uint64_t* XT;             // [level][d3][K] query ciphertext
-  int8_t* Xd;                     // [level + 1][5][KB][d3_pad][64]
-  int64_t d3, d3_pad, elem_begin; // elements: d3_pad x KB*64
+struct BatchLiftDesc {               // one per item
+  const uint64_t* XT;             // [level][d3][K] query ciphertext of the item
+  int8_t* Xd;                     // its problem's [level + 1][planes][KB][d3_pad][64]
+  int64_t d3, c0, cols;           // item columns, first column in the problem, columns written
+                                  // (d3, plus the problem's padding for its last item)
+  int64_t d3_pad, elem_begin;     // elements: cols x KB*64
   LiftArgs la;
 };
-struct BatchRescaleDesc {
-  const uint64_t* C;              // [level + 1][n]
+struct BatchRescaleDesc {            // one per item
+  const uint64_t* C;              // its problem's C + c0 R_out: prime z at C + z zstride
   uint64_t* out;                  // [level][n]
-  int64_t n, elem_begin;          // n = d3 x R_out
+  int64_t n, zstride, elem_begin; // n = d3 x R_out of the item
   RescaleArgs ra;
 };
+struct BatchCrtDesc {                // RNS form, one per problem
+  const uint16_t* res;            // [nz][n_mod][n]
+  uint64_t* C;                    // [nz][n]
+  int64_t n, elem_begin;          // n = d3 x R_out of the problem; elements nz x n
+  int32_t nz, level, pslot, pad_; // database slot of z: z < level ? z : pslot (the special prime)
+};
+// form: 0 = the 5-digit planes, n > 0 = the RNS form with n small moduli
 hipError_t launch_lift_batched(const BatchElemHeader* hdr, const BatchLiftDesc* d, int64_t K, int64_t KB,
-                               int grid, hipStream_t s);
+                               int form, int grid, hipStream_t s);
 hipError_t launch_rescale_batched(const BatchElemHeader* hdr, const BatchRescaleDesc* d, int grid, hipStream_t s);
 
 }  // namespace hfe
@@ -386,15 +421,16 @@ hipError_t launch_rescale_batched(const BatchElemHeader* hdr, const BatchRescale
 // launches can be captured once in a hipGraph and replayed for any batch that fits.
 struct hfe_plan : hfe::HandleBase {
   const hfe_db* db = nullptr;
-  int max_items = 0, max_level = 0, variant = 0;
+  int form = HFE_FORM_I8_MFMA;                         // int8 form of the plan's contraction
+  int max_items = 0, max_level = 0;
   int64_t max_cols = 0;
-  size_t xd_cap = 0, c_cap = 0, out_cap = 0;          // workspace capacities (bytes, elements)
-  hfe::DevBuf ws_xd, ws_c, ws_out, desc;               // device workspace and descriptor tables
+  size_t xd_cap = 0, c_cap = 0, res_cap = 0, out_cap = 0;  // workspace capacities (bytes, elements)
+  hfe::DevBuf ws_xd, ws_c, ws_res, ws_out, desc;       // device workspace and descriptor tables
   void* host_blob = nullptr;                           // pinned staging of the descriptor tables
   size_t blob_bytes = 0;
   hipEvent_t copied = nullptr;                         // staging may be rewritten after this
-  // one captured graph per tile configuration a run has used (the configuration is chosen per
-  // batch, see choose_batch_variant)
+  // one captured graph per digit tile configuration a run has used (chosen per batch; the RNS
+  // form has one configuration, index 0)
   hipGraph_t graph[hfe::kMaxI8Variants] = {};
   hipGraphExec_t exec[hfe::kMaxI8Variants] = {};
   int elem_grid = 0, n_last = 0;

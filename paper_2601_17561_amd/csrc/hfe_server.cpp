@@ -211,21 +211,27 @@ void destroy_server(void* handle) {
 extern "C" {
 
 hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_cols_per_step, int32_t max_items_per_step,
-                             int32_t n_slots, uint32_t max_level, hfe_server** out) {
+                             int32_t n_slots, uint32_t max_level, int32_t form, hfe_server** out) {
   if (!out) return fail(HFE_EINVAL, "out is NULL");
   *out = nullptr;
   const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(db));
   if (!db || hb->kind != kDb) return fail(HFE_EINVAL, "invalid database handle");
-  if (!(db->forms & HFE_FORM_I8_MFMA)) return fail(HFE_EINVAL, "database not prepared for the int8 form");
+  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8) return fail(HFE_EINVAL, "the server runs an int8 form");
+  if (!(db->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   if (n_slots < 1 || n_slots > 8 || max_items_per_step < 1 || max_items_per_step > kMaxBatch ||
       max_cols_per_step < 1 || max_level < 1 || (int)max_level > db->keys->L)
     return fail(HFE_EINVAL, "bad server configuration");
-  // workspace per query column of one step: query digits, contraction output, result,
-  // decryption scratch (plus the column padding of each request)
+  // workspace per query column of one step: query planes, RNS residues, contraction output,
+  // result, decryption scratch (plus the column padding of each request)
+  const bool rns = form == HFE_FORM_RNS_I8;
+  const int planes = rns ? db->n_rns : kDigits;
+  const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
   const int64_t ndb = 1ll << db->keys->P.log_n_db, R_max = ndb + db->d1;
-  const size_t per_col = (size_t)(max_level + 1) * kDigits * db->KB * kKB + (size_t)(max_level + 1) * R_max * 8 +
-                         (size_t)max_level * R_max * 8 + (size_t)max_level * db->d1 * 8;
-  const size_t pad = (size_t)max_items_per_step * (kQueryPad - 1) * (max_level + 1) * kDigits * db->KB * kKB;
+  const size_t per_col = (size_t)(max_level + 1) * planes * db->KB * kKB +
+                         (rns ? (size_t)(max_level + 1) * planes * R_max * 2 : 0) +
+                         (size_t)(max_level + 1) * R_max * 8 + (size_t)max_level * R_max * 8 +
+                         (size_t)max_level * db->d1 * 8;
+  const size_t pad = (size_t)max_items_per_step * (qpad - 1) * (max_level + 1) * planes * db->KB * kKB;
   const size_t per_slot = mem_budget / (size_t)n_slots;
   if (per_slot <= pad + per_col) return fail(HFE_ENOMEM, "memory budget below one column per slot");
   const int64_t cols = std::min<int64_t>(max_cols_per_step, (int64_t)((per_slot - pad) / per_col));
@@ -240,7 +246,7 @@ hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_co
   (void)hipGetDevice(&S->device);
   for (int i = 0; i < n_slots; ++i) {
     auto sl = std::make_unique<Slot>();
-    hfe_status st = hfe_plan_create(db, max_items_per_step, cols, max_level, &sl->plan);
+    hfe_status st = hfe_plan_create(db, max_items_per_step, cols, max_level, form, &sl->plan);
     if (st == HFE_OK) st = sl->y.alloc(sizeof(uint64_t) * (size_t)max_level * cols * db->d1, nullptr);
     if (st == HFE_OK && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess)
       st = fail(HFE_EDEVICE, "stream creation failed");

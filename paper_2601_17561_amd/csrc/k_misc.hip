@@ -125,7 +125,7 @@ __global__ void k_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, Resc
                           uint64_t* out) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x)
-    rescale_element(C, Cp, n, ra, out, e);
+    rescale_element(C, Cp, n, ra, out, e, n);
 }
 
 hipError_t launch_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, const RescaleArgs& ra,

@@ -8,32 +8,6 @@
 
 namespace hfe {
 
-// x mod m for x < 2^24 and 2 <= m <= 256 with magic = ceil(2^32 / m): the quotient
-// floor(x magic / 2^32) is exact because x (magic - 2^32 / m) / 2^32 < 2^-8 <= 1 / m.
-__device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t m, uint32_t magic) {
-  return x - __umulhi(x, magic) * m;
-}
-
-// ------------------------------------------------------------------ balanced residues
-// ceil(2^32 / m) for the moduli of kRnsMods.
-__constant__ uint32_t kRnsMagic[kRnsMaxMods] = {
-    16777216u, 16843010u, 16976156u, 17111424u, 17388532u, 17821442u, 17970575u, 18433337u,
-    18755316u, 18920561u, 19259944u, 20355296u, 21582751u, 21801865u, 22253717u, 22486740u};
-
-// x (|x| < 2^40) -> x mod m_j in [-floor(m_j/2), ceil(m_j/2) - 1] for the modulus kRnsMods[j]:
-// |x| = hi 2^24 + lo (hi < 2^16), |x| mod m = (hi (2^24 mod m) + lo) mod m with the argument
-// split once more below 2^24.
-__device__ __forceinline__ int32_t balanced_mod(int64_t x, int j) {
-  const uint32_t m = (uint32_t)kRnsMods[j], mg = kRnsMagic[j];
-  const uint64_t a = (uint64_t)(x < 0 ? -x : x);
-  const uint32_t hi = (uint32_t)(a >> 24), lo = (uint32_t)(a & 0xFFFFFF);
-  const uint32_t t24 = mod_small(mod_small(1u << 12, m, mg) * mod_small(1u << 12, m, mg), m, mg);
-  const uint32_t hm = mod_small(mod_small(hi >> 8, m, mg) * mod_small(1u << 8, m, mg) + (hi & 255), m, mg);
-  uint32_t r = mod_small(mod_small(hm * t24, m, mg) + mod_small(lo, m, mg), m, mg);
-  if (x < 0 && r) r = m - r;
-  return (int32_t)r >= ((int32_t)m + 1) / 2 ? (int32_t)r - (int32_t)m : (int32_t)r;
-}
-
 // ------------------------------------------------------------------ database split
 // Thread (row r, K-block kb): the 64 centered residues of D[k][r] -> one 64-byte row per modulus.
 __global__ void __launch_bounds__(256) k_split_db_rns(const uint64_t* Dt, int64_t K, int64_t R, int64_t KB,
@@ -76,18 +50,8 @@ hipError_t launch_split_db_rns(const uint64_t* Dt_prime, int64_t K, int64_t R, i
 __global__ void __launch_bounds__(256) k_lift_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
                                                   int64_t d3_pad, LiftArgs la, int n_mod, int8_t* Xr) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = blockIdx.y;
   if (k >= KB * kKB) return;
-  uint64_t y[HFE_MAX_QPRIMES] = {};
-  uint64_t lp;
-  const bool valid = lift_residues(XT, d3, K, la, c, k, y, lp);
-  const int64_t kb = k / kKB, kk = k % kKB;
-  for (int z = 0; z <= la.level; ++z) {
-    int64_t x = 0;
-    if (valid) x = z < la.level ? centered(y[z], la.q[z]) : centered(lp, la.p);
-    for (int j = 0; j < n_mod; ++j)
-      Xr[((((int64_t)z * n_mod + j) * KB + kb) * d3_pad + c) * kKB + kk] = (int8_t)balanced_mod(x, j);
-  }
+  lift_element_rns(XT, d3, K, KB, d3_pad, la, n_mod, Xr, blockIdx.y, k);
 }
 
 hipError_t launch_lift_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
@@ -117,19 +81,24 @@ __device__ __forceinline__ void dma16_rns(const int8_t* g, uint32_t lds_addr) {
                : "memory", "m0");
 }
 
-__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_gemm_rns(RnsGemmArgs g) {
+// One output tile (rows r0.., query columns c0..) of one (prime, modulus) product: X and D are that
+// modulus' query and database planes, res its residue plane [d3][R_out].
+struct RnsTile {
+  const int8_t* X;
+  const int8_t* D;
+  uint16_t* res;
+  int32_t m;
+  uint32_t magic;
+  int64_t KB, R_pad, d3_pad, n_db, row0, R_out, d3, r0, c0;
+};
+
+__device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
   static_assert(kRnsNW == 8 && kRnsLA + kRnsLB == 4, "the vmcnt below assumes 4 loads per wave per K-block");
-  __shared__ __attribute__((aligned(16))) int8_t lds[kRnsStages * kRnsStage];
-  const int j = blockIdx.y, z = blockIdx.z;
-  const int64_t n_ct = (g.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (g.R_out + kRnsTileR - 1) / kRnsTileR;
-  const int64_t l = blockIdx.x, xcd = l % kXcds, jj = l / kXcds;
-  const int64_t rt = (jj / n_ct) * kXcds + xcd, ct = jj % n_ct;
-  if (rt >= n_rt) return;
-  const int64_t r0 = rt * kRnsTileR, c0 = ct * kRnsTileQ;
+  const int64_t r0 = g.r0, c0 = g.c0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wq = wave % kRnsNQ, wr = wave / kRnsNQ;
-  const int8_t* X = g.Xr[z] + (size_t)j * g.KB * g.d3_pad * kKB;
-  const int8_t* D = g.Dr[z] + (size_t)j * g.KB * g.R_pad * kKB;
+  const int8_t* X = g.X;
+  const int8_t* D = g.D;
   const size_t stepA = (size_t)g.d3_pad * kKB, stepB = (size_t)g.R_pad * kKB;
   // load i of a wave fills tile rows 16 (wave + 4 i) .. + 15 (lane l: row + l / 4, stored chunk
   // l % 4 holding logical chunk (l % 4) ^ ((row >> 2) & 3))
@@ -185,13 +154,13 @@ __global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_e
   asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   // epilogue: S mod m_j in [0, m_j) -> res[z][j][c][r]; 32 x 32 result layout as in the digit
   // form (lane l, element e: query column 8 (e / 4) + 4 (l / 32) + e % 4, row l % 32)
-  const int32_t m = g.m[j];
-  const uint32_t magic = g.magic[j];
+  const int32_t m = g.m;
+  const uint32_t magic = g.magic;
   // |acc| < 2^31: u = acc + 2^31 = hi 2^17 + lo (hi < 2^15), and
   // acc mod m = (hi (2^17 mod m) + lo + (m - 2^31 mod m)) mod m with the argument below 2^24
   const uint32_t t16 = mod_small(1u << 16, (uint32_t)m, magic), t17 = mod_small(1u << 17, (uint32_t)m, magic);
   const uint32_t off = (uint32_t)m - mod_small(mod_small(1u << 15, (uint32_t)m, magic) * t16, (uint32_t)m, magic);
-  uint16_t* res = g.res + ((size_t)z * g.n_mod + j) * g.d3 * g.R_out;
+  uint16_t* res = g.res;
 #pragma unroll
   for (int b = 0; b < kRnsWRB; ++b) {
     const int64_t r = r0 + wr * 32 * kRnsWRB + b * 32 + (lane & 31);
@@ -208,6 +177,69 @@ __global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_e
       }
   }
 }
+
+__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_gemm_rns(RnsGemmArgs g) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[kRnsStages * kRnsStage];
+  const int j = blockIdx.y, z = blockIdx.z;
+  const int64_t n_ct = (g.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (g.R_out + kRnsTileR - 1) / kRnsTileR;
+  const int64_t l = blockIdx.x, xcd = l % kXcds, jj = l / kXcds;
+  const int64_t rt = (jj / n_ct) * kXcds + xcd, ct = jj % n_ct;
+  if (rt >= n_rt) return;
+  RnsTile t{g.Xr[z] + (size_t)j * g.KB * g.d3_pad * kKB, g.Dr[z] + (size_t)j * g.KB * g.R_pad * kKB,
+            g.res + ((size_t)z * g.n_mod + j) * g.d3 * g.R_out, g.m[j], g.magic[j], g.KB, g.R_pad, g.d3_pad, g.n_db,
+            g.row0, g.R_out, g.d3, rt * kRnsTileR, ct * kRnsTileQ};
+  rns_tile(t, lds);
+}
+
+// Persistent batched form: problem b's tiles are ordered (z, modulus, XCD-ordered tile), starting at
+// its tile_begin; workgroups claim tiles in order from one counter per XCD (tile t = 8 j + xcd), as
+// the digit form's batched kernel.
+__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_gemm_rns_batched(RnsBatchArgs a) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[kRnsStages * kRnsStage];
+  const int n = a.hdr->n;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = a.hdr->total_tiles / kXcds;
+  for (;;) {
+    __syncthreads();  // the previous tile is done with LDS
+    if (threadIdx.x == 0) *reinterpret_cast<uint32_t*>(lds) = atomicAdd(a.next + xcd, 1u);
+    __syncthreads();
+    const int64_t jc = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t*>(lds));
+    __syncthreads();  // every thread has read the claim before the tile overwrites LDS
+    if (jc >= per_xcd) break;
+    const int64_t t = jc * kXcds + xcd;
+    int lo = 0, hi = n - 1;  // last problem whose first tile is <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.desc[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const BatchDesc& d = a.desc[lo];
+    const int64_t n_ct = (d.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (d.R_out + kRnsTileR - 1) / kRnsTileR;
+    const int64_t per_mod = (n_rt + kXcds - 1) / kXcds * kXcds * n_ct;
+    const int64_t local = t - d.tile_begin;
+    const int zj = (int)(local / per_mod);
+    const int z = zj / a.n_mod, j = zj % a.n_mod;
+    const int64_t l = local % per_mod, lj = l / kXcds;
+    const int64_t rt = (lj / n_ct) * kXcds + l % kXcds, ct = lj % n_ct;
+    if (rt >= n_rt) continue;
+    RnsTile tl{d.Xd + ((size_t)z * a.n_mod + j) * a.KB * d.d3_pad * kKB,
+               a.Dr + ((size_t)d.slot[z] * a.n_mod + j) * a.KB * a.R_pad * kKB,
+               d.res + ((size_t)z * a.n_mod + j) * d.d3 * d.R_out, a.m[j], a.magic[j], a.KB, a.R_pad, d.d3_pad,
+               a.n_db, d.row0, d.R_out, d.d3, rt * kRnsTileR, ct * kRnsTileQ};
+    rns_tile(tl, lds);
+  }
+}
+
+int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod) {
+  const int64_t n_ct = (d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (R_out + kRnsTileR - 1) / kRnsTileR;
+  return (n_rt + kXcds - 1) / kXcds * kXcds * n_ct * nz * n_mod;
+}
+
+hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_rns_batched, dim3((unsigned)grid), dim3(64 * kRnsNW), 0, s, a);
+  return hipGetLastError();
+}
+
+int rns_wgs_per_cu() { return 1; }  // 96 KiB of LDS per workgroup
 
 hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s) {
   if (g.R_out <= 0 || g.d3 <= 0) return hipSuccess;
@@ -231,19 +263,7 @@ __global__ void __launch_bounds__(256) k_crt_rns(const uint16_t* res, int nz, in
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int z = (int)(t / n);
     const int64_t e = t - (int64_t)z * n;
-    const uint16_t* r = res + (size_t)z * ra.n * n + e;
-    float frac = 0.f;
-    uint64_t acc = 0;  // sum of y_j ((M/m_j) mod q) < 16 * 2^8 * 2^36
-    for (int j = 0; j < ra.n; ++j) {
-      const uint32_t y = mod_small((uint32_t)r[(size_t)j * n] * (uint32_t)ra.inv[j], (uint32_t)ra.m[j], ra.magic[j]);
-      frac = fmaf((float)y, ra.rcp[j], frac);
-      acc += (uint64_t)y * ra.Mj_mod_q[z][j];
-    }
-    const uint64_t a = (uint64_t)(frac + 0.5f);
-    const Mod md = ra.mod[z];
-    uint64_t v = barrett64(acc, md.q, md.mu);
-    v = sub_mod(v, barrett64(a * ra.M_mod_q[z], md.q, md.mu), md.q);
-    C[(size_t)z * n + e] = v;
+    C[(size_t)z * n + e] = crt_entry(res + (size_t)z * ra.n * n + e, n, ra, z);
   }
 }
 

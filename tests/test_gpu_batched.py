@@ -1,11 +1,12 @@
 """Batched CCMM (one persistent grouped launch), the reusable plan with its captured hipGraph,
-and the tile autotuner.
+and the tile autotuner, for both int8 forms (digits, small-modulus RNS).
 
-Every item of a batch is its own CCMM (own level, column count and database row range).
-Each item's residues must equal the oracle's (for the oracle-computed case) and the
-single-call result bit for bit, and its decrypted inner products must equal the exact
-plaintext products M_DB M_Q computed by the oracle.  Graph replays are checked after eager
-work in between, on every replay.
+Every item of a batch is its own CCMM (own level, column count and database row range); items
+with the same level and row range share one problem (columns side by side), which the batch
+below exercises with groups of two and three items.  Each item's residues must equal the
+oracle's (for the oracle-computed case) and the single-call result bit for bit, and its
+decrypted inner products must equal the exact plaintext products M_DB M_Q computed by the
+oracle.  Graph replays are checked after eager work in between, on every replay.
 """
 import os
 import sys
@@ -41,12 +42,13 @@ def env():
     P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
     keys = H.hfe_keygen(P, KEY_SEED)
     m_db = torch.from_numpy(c.m_db).to(dev)
-    db = H.hfe_encrypt_db(keys, m_db, DB_SEED)
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
     rng = np.random.default_rng(7)
     # items: (m_q rows, level, row0, rows); the first is the oracle case itself
     specs = [(c.m_q, 2, 0, w.d1, Q_SEED), (rng.integers(-1, 2, (3, w.d2)), 1, 10, 100, 501),
              (rng.integers(-1, 2, (130, w.d2)), 2, 0, 256, 502), (rng.integers(-1, 2, (1, w.d2)), 1, 255, 1, 503),
-             (rng.integers(-1, 2, (64, w.d2)), 2, 128, 128, 504)]
+             (rng.integers(-1, 2, (64, w.d2)), 2, 128, 128, 504), (rng.integers(-1, 2, (5, w.d2)), 1, 10, 100, 505),
+             (rng.integers(-1, 2, (2, w.d2)), 2, 0, w.d1, 506)]
     items, mqs = [], []
     for mq, level, row0, rows, seed in specs:
         mq = np.ascontiguousarray(mq.astype(np.int8))
@@ -66,12 +68,15 @@ def _plain_product(env, i):
     return OR.imatmul(env["c"].m_db[row0:row0 + rows].astype(np.int64), env["mqs"][i].astype(np.int64).T).T
 
 
+_singles = {}
+
+
 def _check_results(env, results, tag):
     c = env["c"]
-    singles = []
-    for i, (q, row0, rows) in enumerate(env["items"]):
-        r1 = H.hfe_ccmm(env["db"], q, row0, rows, H.HFE_FORM_I8_MFMA)
-        singles.append(_residues(r1))
+    if not _singles:
+        for i, (q, row0, rows) in enumerate(env["items"]):
+            _singles[i] = _residues(H.hfe_ccmm(env["db"], q, row0, rows, H.HFE_FORM_I8_MFMA))
+    singles = [_singles[i] for i in range(len(results))]
     for i, r in enumerate(results):
         got = _residues(r)
         assert np.array_equal(got, singles[i]), f"{tag}: item {i} differs from the single call"
@@ -95,6 +100,13 @@ def test_batched_i8_equals_single_calls_and_oracle(env, variant):
         H.hfe_set_i8_variant(-1)
 
 
+def test_batched_rns_equals_single_calls_and_oracle(env):
+    _say("[gpu-batched] hfe_ccmm_batched rns")
+    res = H.hfe_ccmm_batched(env["db"], env["items"], H.HFE_FORM_RNS_I8)
+    torch.cuda.synchronize()
+    _check_results(env, res, "batched rns")
+
+
 def test_batched_plain_equals_i8(env):
     _say("[gpu-batched] hfe_ccmm_batched plain")
     a = H.hfe_ccmm_batched(env["db"], env["items"], H.HFE_FORM_PLAIN_U64)
@@ -103,10 +115,11 @@ def test_batched_plain_equals_i8(env):
         assert np.array_equal(_residues(x), _residues(y))
 
 
-def test_plan_graph_replays(env):
+@pytest.mark.parametrize("form", ["i8", "rns"])
+def test_plan_graph_replays(env, form):
     items = env["items"]
-    _say("[gpu-batched] plan: eager run, graph capture, replays with eager work between")
-    plan = H.hfe_plan_create(env["db"], 8, 512, 2)
+    _say(f"[gpu-batched] plan ({form}): eager run, graph capture, replays with eager work between")
+    plan = H.hfe_plan_create(env["db"], 8, 512, 2, H.HFE_FORM_I8_MFMA if form == "i8" else H.HFE_FORM_RNS_I8)
     H.hfe_plan_run(plan, items, use_graph=False)
     torch.cuda.synchronize()
     _check_results(env, [H.hfe_plan_result(plan, i) for i in range(len(items))], "plan eager")
@@ -127,6 +140,7 @@ def test_plan_graph_replays(env):
     with pytest.raises(H.HfeError):
         H.hfe_plan_result(plan, 2)                                   # only 2 items in the last run
     big = [(items[2][0], 0, 256)] * 5                                # 650 columns > capacity 512
+    assert len(items) <= 8
     with pytest.raises(H.HfeError) as e:
         H.hfe_plan_run(plan, big)
     assert e.value.status == -2

@@ -36,7 +36,7 @@ def env():
     _say("[gpu-serving] tinymulti: keygen / encrypt database")
     P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
     keys = H.hfe_keygen(P, KEY_SEED)
-    db = H.hfe_encrypt_db(keys, torch.from_numpy(c.m_db).to(dev), DB_SEED, H.HFE_FORM_I8_MFMA)
+    db = H.hfe_encrypt_db(keys, torch.from_numpy(c.m_db).to(dev), DB_SEED, H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
     rng = np.random.default_rng(11)
     reqs = []
     for i, d3 in enumerate([1, 7, 16, 33, 2, 40, 16, 5, 24, 3, 12, 9]):
@@ -63,9 +63,13 @@ def _run(srv, env, idx, burst):
     return {i: o.cpu().numpy() for i, o in outs.items()}
 
 
-def test_same_result_alone_and_in_the_mix(env):
-    _say("[gpu-serving] server: requests alone, then in a burst")
-    srv = H.hfe_server_create(env["db"], 1 << 30, 64, 8, 2, 2)
+FORMS = {"i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8}
+
+
+@pytest.mark.parametrize("form", ["i8", "rns"])
+def test_same_result_alone_and_in_the_mix(env, form):
+    _say(f"[gpu-serving] server ({form}): requests alone, then in a burst")
+    srv = H.hfe_server_create(env["db"], 2 << 30, 64, 8, 2, 2, FORMS[form])
     idx = list(range(len(env["reqs"])))
     alone = _run(srv, env, idx, burst=False)
     st_alone = H.hfe_server_stats(srv)
