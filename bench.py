@@ -116,54 +116,58 @@ def encrypt_eyes(H, torch, keys, w, stream_id, eyes, level, shifts):
 
 def run_batched(args, H, torch):
     """Uneven batch: items of 1-64 eyes x 16 shifts at levels 1-5 (2-6 primes with p) against
-    database shards of 2,048-14,336 codes, as one reusable plan (three grouped launches captured
-    in a hipGraph), against the same items as one hfe_ccmm call each."""
+    database shards of 2,048-14,336 codes, as one batched call (grouped persistent launches; the
+    workspace sized to the batch, which a plan would size for its worst case), against the same
+    items as one hfe_ccmm call each, for both int8 forms."""
     w = S.PAPER_SHARE_L5
     n_db, K = 1 << w.log_n_db, w.d2 + (1 << w.log_n_q)
     mix = S.batched_mix(w.seed, args.batch_items, w.d1, 64, w.n_q_primes, 2048)
     shifts = [int(x) for x in S.default_shifts(16)]
-    log(f"batched: encrypting the {w.d1}-code database with {w.n_q_primes} query primes + p (int8 form)")
-    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA)
+    log(f"batched: encrypting the {w.d1}-code database with {w.n_q_primes} query primes + p (int8 forms)")
+    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
     items = []
     for i, it in enumerate(mix):
         items.append((encrypt_eyes(H, torch, keys, w, i, it.eyes, it.level, shifts), it.row0, it.rows))
     torch.cuda.synchronize()
     cols = sum(it.eyes * 16 for it in mix)
-    ops = sum(50 * (n_db + it.rows) * K * it.eyes * 16 * (it.level + 1) for it in mix)
+    macs = sum((n_db + it.rows) * K * it.eyes * 16 * (it.level + 1) for it in mix)
     comparisons = sum(it.rows * it.eyes * 16 for it in mix)
-    log(f"batched: {len(mix)} items, {cols} query columns, {ops / 1e15:.2f} P int8 ops; autotuning")
+    log(f"batched: {len(mix)} items, {cols} query columns; autotuning the digit tile")
     # the plan looks the autotuner's table up by its largest level and mean column count
     tq = encrypt_eyes(H, torch, keys, w, 999, 32, w.n_q_primes, shifts)
     tuned = H.hfe_autotune(db, tq, 0, w.d1, reps=1)
     tq.free()
-    plan = H.hfe_plan_create(db, len(items), cols, w.n_q_primes)
-    H.hfe_plan_run(plan, items, use_graph=True)       # captures the graph
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        H.hfe_plan_run(plan, items, use_graph=True)
-    torch.cuda.synchronize()
-    plan_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    same = all(np.array_equal(H.hfe_export(H.hfe_plan_result(plan, i), 0, 0, 1 << 16),
-                              H.hfe_export(H.hfe_ccmm(db, q, r0, nr, H.HFE_FORM_I8_MFMA), 0, 0, 1 << 16))
-               for i, (q, r0, nr) in list(enumerate(items))[:4])
-    plan.free()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for q, r0, nr in items:
-        H.hfe_ccmm(db, q, r0, nr, H.HFE_FORM_I8_MFMA).free()
-    torch.cuda.synchronize()
-    seq_ms = (time.perf_counter() - t0) * 1e3
-    tops = ops / (plan_ms * 1e-3) / 1e12
-    line = {"metric": "batched encrypted CCMM, int8 ops/s (one persistent launch per stage, hipGraph)",
-            "value": tops, "unit": "TOP/s", "n_gpus": 1, "steps": args.steps, "higher_is_better": True,
-            "ms_per_batch": plan_ms, "comparisons_per_s": comparisons / (plan_ms * 1e-3),
-            "frac_of_peak": tops / PEAK_I8_TOPS, "sequential_ms": seq_ms, "speedup_vs_sequential": seq_ms / plan_ms,
-            "same_residues_as_single_calls": bool(same), "tile": H.hfe_i8_variant_name(tuned), "dtype": "i8",
-            "data": "synthetic",
-            "config": {"workload": "batched_" + w.name, "items": len(mix), "eyes": "1-64", "shifts": 16,
-                       "levels": "1-5 query primes + p", "rows": "2048-14336", "columns": cols}}
-    print(json.dumps(line), flush=True)
+    qs, p_special = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1).primes()
+    n_mod = rns_moduli(w, max(list(qs) + [p_special]))
+    for name, form, per_mac in (("i8", H.HFE_FORM_I8_MFMA, 50), ("rns", H.HFE_FORM_RNS_I8, 2 * n_mod)):
+        res = H.hfe_ccmm_batched(db, items, form)           # warm-up (workspace into torch's cache)
+        same = all(np.array_equal(H.hfe_export(res[i], 0, 0, 1 << 16),
+                                  H.hfe_export(H.hfe_ccmm(db, q, r0, nr, form), 0, 0, 1 << 16))
+                   for i, (q, r0, nr) in list(enumerate(items))[:4])
+        del res
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for r in H.hfe_ccmm_batched(db, items, form):
+                r.free()
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        t0 = time.perf_counter()
+        for q, r0, nr in items:
+            H.hfe_ccmm(db, q, r0, nr, form).free()
+        torch.cuda.synchronize()
+        seq_ms = (time.perf_counter() - t0) * 1e3
+        tops = per_mac * macs / (plan_ms * 1e-3) / 1e12
+        line = {"metric": "batched encrypted CCMM, comparisons/s (grouped persistent launches)",
+                "value": comparisons / (plan_ms * 1e-3), "unit": "comparisons/s", "n_gpus": 1, "steps": args.steps,
+                "higher_is_better": True, "form": name, "ms_per_batch": plan_ms, "int8_tops": tops,
+                "frac_of_peak": tops / PEAK_I8_TOPS, "sequential_ms": seq_ms,
+                "speedup_vs_sequential": seq_ms / plan_ms, "same_residues_as_single_calls": bool(same),
+                "tile": H.hfe_i8_variant_name(tuned) if name == "i8" else f"rns 256x256, {n_mod} moduli",
+                "dtype": "i8", "data": "synthetic",
+                "config": {"workload": "batched_" + w.name, "items": len(mix), "eyes": "1-64", "shifts": 16,
+                           "levels": "1-5 query primes + p", "rows": "2048-14336", "columns": cols}}
+        print(json.dumps(line), flush=True)
 
 
 def run_serving(args, H, torch):
@@ -176,17 +180,18 @@ def run_serving(args, H, torch):
     w = S.PAPER_SHARE
     shifts = [int(x) for x in S.default_shifts(16)]
     log(f"serving: encrypting the {w.d1}-code database (int8 form)")
-    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA)
+    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
     dev = torch.device("cuda", 0)
     pool = {e: encrypt_eyes(H, torch, keys, w, 1000 + e, e, w.level, shifts) for e in range(1, 33)}
     torch.cuda.synchronize()
     lines = []
+    form = H.HFE_FORM_RNS_I8 if args.serve_form == "rns" else H.HFE_FORM_I8_MFMA
     for rate in args.rates:
         n = max(8, int(rate * args.serve_seconds))
         t_arr, eyes = S.poisson_arrivals(w.seed + int(rate), n, rate, 32)
         log(f"serving: {n} requests at {rate} req/s over {t_arr[-1]:.1f} s")
         outs = [torch.empty((int(e) * 16, w.d1), dtype=torch.int32, device=dev) for e in eyes]
-        srv = H.hfe_server_create(db, args.serve_budget_gib << 30, args.serve_cols, 64, 2, w.level)
+        srv = H.hfe_server_create(db, args.serve_budget_gib << 30, args.serve_cols, 64, 2, w.level, form)
         tickets = []
         t0 = time.perf_counter()
         for i in range(n):
@@ -207,7 +212,7 @@ def run_serving(args, H, torch):
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "service_p50_ms": st["service_p50_ms"],
                 "service_p99_ms": st["service_p99_ms"], "steps": st["steps"],
                 "mean_cols_per_step": st["mean_cols_per_step"], "max_queue": st["max_queue"],
-                "rejected": st["rejected"], "dtype": "i8", "data": "synthetic",
+                "rejected": st["rejected"], "form": args.serve_form, "dtype": "i8", "data": "synthetic",
                 "config": {"workload": "serving_" + w.name, "eyes": "1-32", "shifts": 16,
                            "arrivals": f"poisson {rate}/s", "window_s": args.serve_seconds,
                            "max_cols_per_step": args.serve_cols, "slots": 2,
@@ -242,6 +247,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving: seconds of arrivals per rate")
     ap.add_argument("--serve-cols", type=int, default=2048, help="serving: query columns per step")
     ap.add_argument("--serve-budget-gib", type=int, default=64, help="serving: workspace memory budget")
+    ap.add_argument("--serve-form", choices=("i8", "rns"), default="rns", help="serving: int8 form of the server")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="with --ccmm-only: also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

@@ -681,7 +681,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_TRY(Xd.alloc((size_t)nz * n * planeX, s));
     HFE_LAUNCH(launch_lift_rns(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd.as<int8_t>(), s));
     DevBuf res;
-    HFE_TRY(res.alloc(sizeof(uint16_t) * (size_t)nz * n * d3 * R_out, s));
+    HFE_TRY(res.alloc((size_t)nz * n * d3 * R_out, s));
     RnsGemmArgs rg;
     std::memset(&rg, 0, sizeof(rg));
     rg.nz = nz;
@@ -694,7 +694,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
       rg.m[j] = kRnsMods[j];
       rg.magic[j] = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)kRnsMods[j] - 1) / (uint64_t)kRnsMods[j]);
     }
-    rg.res = res.as<uint16_t>();
+    rg.res = res.as<uint8_t>();
     rg.KB = D->KB;
     rg.R_pad = D->R_pad;
     rg.n_db = ndb;
@@ -704,7 +704,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     rg.d3_pad = d3_pad;
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_rns(rg, s));
-    HFE_LAUNCH(launch_crt_rns(res.as<uint16_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), C.as<uint64_t>(), s));
+    HFE_LAUNCH(launch_crt_rns(res.as<uint8_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), C.as<uint64_t>(), s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
@@ -858,7 +858,7 @@ Grouping group_items(const hfe_batch_item* items, int n) {
 // and (when blob != nullptr) its descriptor tables pointing into the given workspace (xd_base,
 // c_base, res_base) and result arrays (outs[i]).
 BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int form, int variant, int8_t* xd_base,
-                      uint64_t* c_base, uint16_t* res_base, uint64_t* const* outs, uint8_t* blob,
+                      uint64_t* c_base, uint8_t* res_base, uint64_t* const* outs, uint8_t* blob,
                       const BlobLayout& L) {
   const hfe_keys* K = D->keys;
   const int64_t ndb = 1ll << K->P.log_n_db;
@@ -1114,14 +1114,14 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
   DevBuf Xd, C, res, blob;
   hfe_status st = Xd.alloc(sz0.xd_bytes, s);
   if (st == HFE_OK) st = C.alloc(sizeof(uint64_t) * sz0.c_elems, s);
-  if (st == HFE_OK && sz0.res_elems) st = res.alloc(sizeof(uint16_t) * sz0.res_elems, s);
+  if (st == HFE_OK && sz0.res_elems) st = res.alloc(sz0.res_elems, s);
   if (st == HFE_OK) st = blob.alloc(L.bytes, s);
   if (st != HFE_OK) {
     cleanup();
     return st;
   }
   std::vector<uint8_t> host(L.bytes, 0);
-  batch_fill(D, items, n, form, variant, Xd.as<int8_t>(), C.as<uint64_t>(), res.as<uint16_t>(), outp.data(),
+  batch_fill(D, items, n, form, variant, Xd.as<int8_t>(), C.as<uint64_t>(), res.as<uint8_t>(), outp.data(),
              host.data(), L);
   hipError_t e = hipMemcpyAsync(blob.ptr, host.data(), L.bytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // the pageable staging is freed on return
@@ -1171,7 +1171,7 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   P->blob_bytes = L.bytes;
   hfe_status st = P->ws_xd.alloc(P->xd_cap, nullptr);
   if (st == HFE_OK) st = P->ws_c.alloc(sizeof(uint64_t) * P->c_cap, nullptr);
-  if (st == HFE_OK && rns) st = P->ws_res.alloc(sizeof(uint16_t) * P->res_cap, nullptr);
+  if (st == HFE_OK && rns) st = P->ws_res.alloc(P->res_cap, nullptr);
   if (st == HFE_OK) st = P->ws_out.alloc(sizeof(uint64_t) * P->out_cap, nullptr);
   if (st == HFE_OK) st = P->desc.alloc(L.bytes, nullptr);
   hipError_t e = hipSuccess;
@@ -1238,7 +1238,7 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
   uint8_t* host = static_cast<uint8_t*>(P->host_blob);
   std::memset(host, 0, P->blob_bytes);
   batch_fill(D, items, n, P->form, variant, P->ws_xd.as<int8_t>(), P->ws_c.as<uint64_t>(),
-             P->ws_res.as<uint16_t>(), outp.data(), host, L);
+             P->ws_res.as<uint8_t>(), outp.data(), host, L);
   HFE_LAUNCH(hipMemcpyAsync(P->desc.ptr, host, P->blob_bytes, hipMemcpyHostToDevice, s));
   HFE_LAUNCH(hipEventRecord(P->copied, s));
   if (!use_graph) {

@@ -140,7 +140,7 @@ __device__ __forceinline__ void lift_element_rns(const uint64_t* XT, int64_t d3,
 
 // CRT of one entry (see k_crt_rns): residues r[j n] mod m_j -> the exact centered sum mod the prime
 // of database slot `slot`.
-__device__ __forceinline__ uint64_t crt_entry(const uint16_t* r, int64_t n, const RnsCrtArgs& ra, int slot) {
+__device__ __forceinline__ uint64_t crt_entry(const uint8_t* r, int64_t n, const RnsCrtArgs& ra, int slot) {
   float frac = 0.f;
   uint64_t acc = 0;  // sum of y_j ((M/m_j) mod q) < 16 * 2^8 * 2^36
   for (int j = 0; j < ra.n; ++j) {

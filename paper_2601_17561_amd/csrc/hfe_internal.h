@@ -244,7 +244,7 @@ hipError_t launch_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, in
 
 // Small-modulus (RNS) form: the database and the lifted query as one balanced int8 plane per
 // modulus (layouts as the digit planes); one int8 product per (prime, modulus) reduced mod the
-// modulus into res[z][j][c][r] (uint16); the CRT of the n residues gives the exact centered
+// modulus into res[z][j][c][r] (one byte); the CRT of the n residues gives the exact centered
 // integer sum, reduced mod the prime into C[z][c][r].
 hipError_t launch_split_db_rns(const uint64_t* Dt_prime, int64_t K, int64_t R, int64_t KB, int64_t R_pad,
                                uint64_t q, int n_mod, int8_t* dig_prime, hipStream_t s);
@@ -256,7 +256,7 @@ struct RnsGemmArgs {
   const int8_t* Xr[kMaxPrimes];                // [n_mod][KB][d3_pad][64]
   int32_t m[kRnsMaxMods];
   uint32_t magic[kRnsMaxMods];                 // ceil(2^32 / m): x mod m by multiply-high, x < 2^24
-  uint16_t* res;                               // [nz][n_mod][d3][R_out]
+  uint8_t* res;                                // [nz][n_mod][d3][R_out], residues < m_j <= 256
   int64_t KB, R_pad, n_db, row0, R_out, d3, d3_pad;
 };
 hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s);
@@ -270,7 +270,7 @@ struct RnsCrtArgs {
   uint64_t Mj_mod_q[kMaxPrimes][kRnsMaxMods];  // (M / m_j) mod that prime
   uint64_t M_mod_q[kMaxPrimes];                // M mod that prime
 };
-hipError_t launch_crt_rns(const uint16_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
+hipError_t launch_crt_rns(const uint8_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
                           hipStream_t s);
 constexpr int kRnsTileR = 256, kRnsTileQ = 256;  // workgroup tile of the RNS contraction
 struct BatchDesc;
@@ -324,7 +324,7 @@ int i8_variant_wgs_per_cu(int v);  // resident workgroups per CU the configurati
 struct BatchDesc {
   const int8_t* Xd;               // [nz][planes][KB][d3_pad][64] query planes of this problem
   uint64_t* C;                    // [nz][d3][R_out] contraction output
-  uint16_t* res;                  // RNS form: [nz][n_mod][d3][R_out] residues by small modulus
+  uint8_t* res;                   // RNS form: [nz][n_mod][d3][R_out] residues by small modulus
   int64_t row0, R_out, d3, d3_pad;
   int64_t tile_begin;             // first tile of this problem in the launch (multiple of 8)
   int32_t nz, pad_;
@@ -405,7 +405,7 @@ struct BatchRescaleDesc {            // one per item
   RescaleArgs ra;
 };
 struct BatchCrtDesc {                // RNS form, one per problem
-  const uint16_t* res;            // [nz][n_mod][n]
+  const uint8_t* res;             // [nz][n_mod][n]
   uint64_t* C;                    // [nz][n]
   int64_t n, elem_begin;          // n = d3 x R_out of the problem; elements nz x n
   int32_t nz, level, pslot, pad_; // database slot of z: z < level ? z : pslot (the special prime)

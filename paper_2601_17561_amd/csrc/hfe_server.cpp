@@ -228,7 +228,7 @@ hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_co
   const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
   const int64_t ndb = 1ll << db->keys->P.log_n_db, R_max = ndb + db->d1;
   const size_t per_col = (size_t)(max_level + 1) * planes * db->KB * kKB +
-                         (rns ? (size_t)(max_level + 1) * planes * R_max * 2 : 0) +
+                         (rns ? (size_t)(max_level + 1) * planes * R_max : 0) +
                          (size_t)(max_level + 1) * R_max * 8 + (size_t)max_level * R_max * 8 +
                          (size_t)max_level * db->d1 * 8;
   const size_t pad = (size_t)max_items_per_step * (qpad - 1) * (max_level + 1) * planes * db->KB * kKB;

@@ -86,7 +86,7 @@ __device__ __forceinline__ void dma16_rns(const int8_t* g, uint32_t lds_addr) {
 struct RnsTile {
   const int8_t* X;
   const int8_t* D;
-  uint16_t* res;
+  uint8_t* res;
   int32_t m;
   uint32_t magic;
   int64_t KB, R_pad, d3_pad, n_db, row0, R_out, d3, r0, c0;
@@ -160,7 +160,7 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
   // acc mod m = (hi (2^17 mod m) + lo + (m - 2^31 mod m)) mod m with the argument below 2^24
   const uint32_t t16 = mod_small(1u << 16, (uint32_t)m, magic), t17 = mod_small(1u << 17, (uint32_t)m, magic);
   const uint32_t off = (uint32_t)m - mod_small(mod_small(1u << 15, (uint32_t)m, magic) * t16, (uint32_t)m, magic);
-  uint16_t* res = g.res;
+  uint8_t* res = g.res;
 #pragma unroll
   for (int b = 0; b < kRnsWRB; ++b) {
     const int64_t r = r0 + wr * 32 * kRnsWRB + b * 32 + (lane & 31);
@@ -173,7 +173,7 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
         if (c >= g.d3) continue;
         const uint32_t u = (uint32_t)acc[a][b][e] + 0x80000000u;  // acc + 2^31 >= 0
         const uint32_t v = mod_small((u >> 17) * t17 + (u & 0x1FFFF) + off, (uint32_t)m, magic);
-        res[c * g.R_out + r] = (uint16_t)v;
+        res[c * g.R_out + r] = (uint8_t)v;
       }
   }
 }
@@ -258,7 +258,7 @@ hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s) {
 // - floor(...) = (S mod M) / M lies at least 1/4 away from 1/2 and single precision (error
 // below 2^-19 over 16 terms) decides a exactly; then
 // C = sum_j y_j ((M/m_j) mod q) - a (M mod q) mod q.
-__global__ void __launch_bounds__(256) k_crt_rns(const uint16_t* res, int nz, int64_t n, RnsCrtArgs ra, uint64_t* C) {
+__global__ void __launch_bounds__(256) k_crt_rns(const uint8_t* res, int nz, int64_t n, RnsCrtArgs ra, uint64_t* C) {
   const int64_t total = (int64_t)nz * n;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
     const int z = (int)(t / n);
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(256) k_crt_rns(const uint16_t* res, int nz, in
   }
 }
 
-hipError_t launch_crt_rns(const uint16_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
+hipError_t launch_crt_rns(const uint8_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
                           hipStream_t s) {
   const int64_t total = (int64_t)nz * n;
   if (total <= 0) return hipSuccess;
