@@ -287,12 +287,21 @@ def main():
     del m_db
     log(f"database encrypted in {t_db:.2f} s")
 
-    def step(form, profile_out=None):
+    def step(form, profile_out=None, marks=None):
+        # marks: 6 events recorded on the stream the library runs on (torch's current stream)
+        # around encode, encrypt, CCMM, decrypt and match
+        mark = (lambda i: marks[i].record()) if marks is not None else (lambda i: None)
+        mark(0)
         m_q = H.hfe_encode(q_codes, q_masks, shifts)
+        mark(1)
         qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+        mark(2)
         r = H.hfe_ccmm(db, qct, 0, w.d1, form)
+        mark(3)
         _, ip = H.hfe_decrypt(keys, r, v=False)
+        mark(4)
         _, eye = H.hfe_match(ip, q_masks, shifts, db_masks, want_decision=False)
+        mark(5)
         if profile_out is not None:
             profile_out.append(r)
         else:
@@ -352,29 +361,38 @@ def main():
     for name, form, steps, warm in (("i8", H.HFE_FORM_I8_MFMA, args.steps, args.warmup),
                                     ("rns", H.HFE_FORM_RNS_I8, args.steps, args.warmup),
                                     ("plain", H.HFE_FORM_PLAIN_U64, args.plain_steps, 1)):
+        if steps <= 0:
+            continue
         for _ in range(warm):
             step(form)
         torch.cuda.synchronize()
         H.hfe_profile(True)
         prof = []
+        marks = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            ip, eye = step(form, prof)
+        for i in range(steps):
+            ip, eye = step(form, prof, marks[i])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         H.hfe_profile(False)
         stages = np.array([H.hfe_profile_ms(r, 3) for r in prof])
+        phases = np.array([[m[k].elapsed_time(m[k + 1]) for k in range(5)] for m in marks])
         for r in prof:
             r.free()
         ms = dt * 1e3 / steps
         results[name] = dict(ms_per_step=ms, comparisons_per_s=w.d1 * w.d3 / (dt / steps),
                              lift_ms=float(stages[:, 0].mean()), contraction_ms=float(stages[:, 1].mean()),
-                             rescale_ms=float(stages[:, 2].mean()), ip=ip, eye=eye)
+                             contraction_median_ms=float(np.median(stages[:, 1])),
+                             rescale_ms=float(stages[:, 2].mean()), ip=ip, eye=eye,
+                             phases_ms={k: float(v) for k, v in zip(
+                                 ("encode", "encrypt", "ccmm", "decrypt", "match"), phases.mean(axis=0))})
         log(f"{name}: {ms:.2f} ms/step, contraction {results[name]['contraction_ms']:.2f} ms "
-            f"(lift {results[name]['lift_ms']:.2f}, rescale {results[name]['rescale_ms']:.2f})")
+            f"(lift {results[name]['lift_ms']:.2f}, rescale {results[name]['rescale_ms']:.2f}); phases "
+            + " ".join(f"{k} {v:.3f}" for k, v in results[name]["phases_ms"].items()))
 
-    same = bool(torch.equal(results["i8"]["ip"], results["plain"]["ip"]))
+    plain = results.get("plain")
+    same = bool(torch.equal(results["i8"]["ip"], plain["ip"])) if plain else None
     same_rns = bool(torch.equal(results["rns"]["ip"], results["i8"]["ip"]))
     rns = results["rns"]
     qs, p_special = P.primes()
@@ -411,18 +429,22 @@ def main():
                      "traffic_unit": "GB per launch (HBM side of L2, rocprofv3 counters)",
                      "kernel": f"k_gemm_i8 ({tile})", "ops_per_launch": work["i8_ops"],
                      "kernel_ms": i8["contraction_ms"]},
-        "plain": {"ms_per_step": results["plain"]["ms_per_step"],
-                  "comparisons_per_s": results["plain"]["comparisons_per_s"],
-                  "contraction_ms": results["plain"]["contraction_ms"],
-                  "residue_macs_per_s": work["residue_macs"] / (results["plain"]["contraction_ms"] * 1e-3)},
+        "plain": ({"ms_per_step": plain["ms_per_step"],
+                   "comparisons_per_s": plain["comparisons_per_s"],
+                   "contraction_ms": plain["contraction_ms"],
+                   "residue_macs_per_s": work["residue_macs"] / (plain["contraction_ms"] * 1e-3)}
+                  if plain else None),
         "rns": {"form": f"small-modulus RNS, {n_mod} moduli per prime", "ms_per_step": rns["ms_per_step"],
                 "comparisons_per_s": rns["comparisons_per_s"], "contraction_ms": rns["contraction_ms"],
                 "lift_ms": rns["lift_ms"], "crt_rescale_ms": rns["rescale_ms"],
                 "int8_ops_per_launch": rns_ops,
                 "frac_of_peak": rns_ops / (rns["contraction_ms"] * 1e-3) / 1e12 / PEAK_I8_TOPS,
-                "over_i8_step": i8["ms_per_step"] / rns["ms_per_step"], "equals_i8_ip": same_rns},
-        "i8_over_plain_step": results["plain"]["ms_per_step"] / i8["ms_per_step"],
-        "stages_ms": {"lift_split": i8["lift_ms"], "contraction": i8["contraction_ms"], "rescale": i8["rescale_ms"]},
+                "over_i8_step": i8["ms_per_step"] / rns["ms_per_step"], "equals_i8_ip": same_rns,
+                "phases_ms": rns["phases_ms"]},
+        "i8_over_plain_step": plain["ms_per_step"] / i8["ms_per_step"] if plain else None,
+        "stages_ms": {"lift_split": i8["lift_ms"], "contraction": i8["contraction_ms"],
+                      "contraction_median": i8["contraction_median_ms"], "rescale": i8["rescale_ms"]},
+        "phases_ms": i8["phases_ms"],
         "i8_equals_plain_ip": same,
         "db_encrypt_s": t_db,
         "cpu_baseline": cpu,

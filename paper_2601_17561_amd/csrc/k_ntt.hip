@@ -13,42 +13,121 @@ namespace hfe {
 
 constexpr int kNttThreads = 1024;
 
+// Both transforms run in rounds of up to three butterfly stages: a thread loads a group of 2^S
+// coefficients into registers, applies S stages there and stores them back, so a transform of
+// degree 2^logn takes ceil(logn / 3) LDS passes and barriers instead of logn.
+//
+// Forward (Cooley-Tukey) round with first half-size t: group g holds a[base + k stride], k < 2^S,
+// stride = t / 2^(S-1), base = B 2t + r (B = g / stride, r = g mod stride).  Stage s (half-size
+// t / 2^s, m = n / (2t) 2^s blocks) pairs k and k + 2^(S-1-s); the pair lies in block
+// B 2^s + (k >> (S - s)), whose twiddle is psi[m + block].
+template <int S>
+__device__ __forceinline__ void fwd_round(uint64_t* a, const NttTab& T, int n, int t) {
+  constexpr int G = 1 << S;
+  const uint64_t q = T.q;
+  const int stride = t >> (S - 1), m1 = n / (2 * t);
+  for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
+    const int B = g / stride, r = g - B * stride;
+    const int base = B * 2 * t + r;
+    uint64_t x[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) x[k] = a[base + k * stride];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int h = 1 << (S - 1 - s);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        if (k & h) continue;
+        const int w = (m1 << s) + (B << s) + (k >> (S - s));
+        const uint64_t U = x[k];
+        const uint64_t V = mul_shoup(x[k + h], T.psi[w], T.psi_sh[w], q);
+        x[k] = add_mod(U, V, q);
+        x[k + h] = sub_mod(U, V, q);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) a[base + k * stride] = x[k];
+  }
+  __syncthreads();
+}
+
+// Inverse (Gentleman-Sande) round with first half-size t: group g holds a[base + k t], k < 2^S,
+// base = B 2^S t + r (B = g / t, r = g mod t).  Stage s (half-size 2^s t, m = n / (2^(s+1) t)
+// blocks) pairs k and k + 2^s; the pair lies in block B 2^(S-1-s) + (k >> (s + 1)), twiddle
+// ipsi[m + block].  With scale, the round ends with the 1/n factor.
+template <int S>
+__device__ __forceinline__ void inv_round(uint64_t* a, const NttTab& T, int n, int t, bool scale) {
+  constexpr int G = 1 << S;
+  const uint64_t q = T.q;
+  for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
+    const int B = g / t, r = g - B * t;
+    const int base = B * G * t + r;
+    uint64_t x[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) x[k] = a[base + k * t];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int h = 1 << s;
+      const int m = n / (2 * h * t);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        if (k & h) continue;
+        const int w = m + (B << (S - 1 - s)) + (k >> (s + 1));
+        const uint64_t U = x[k], V = x[k + h];
+        x[k] = add_mod(U, V, q);
+        x[k + h] = mul_shoup(sub_mod(U, V, q), T.ipsi[w], T.ipsi_sh[w], q);
+      }
+    }
+    if (scale) {
+#pragma unroll
+      for (int k = 0; k < G; ++k) x[k] = mul_shoup(x[k], T.n_inv, T.n_inv_sh, q);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) a[base + k * t] = x[k];
+  }
+  __syncthreads();
+}
+
+// Forward negacyclic NTT in place (output in bit-reversed order).
 __device__ __forceinline__ void ntt_fwd_lds(uint64_t* a, const NttTab& T) {
   const int n = 1 << T.logn;
-  const uint64_t q = T.q;
-  for (int m = 1, logt = T.logn - 1; m < n; m <<= 1, --logt) {
-    const int t = 1 << logt;
-    for (int idx = threadIdx.x; idx < (n >> 1); idx += blockDim.x) {
-      const int i = idx >> logt;
-      const int j1 = (i << (logt + 1)) + (idx & (t - 1));
-      const uint64_t S = T.psi[m + i], Ssh = T.psi_sh[m + i];
-      const uint64_t U = a[j1];
-      const uint64_t V = mul_shoup(a[j1 + t], S, Ssh, q);
-      a[j1] = add_mod(U, V, q);
-      a[j1 + t] = sub_mod(U, V, q);
+  int t = n >> 1, left = T.logn;
+  while (left > 0) {
+    if (left >= 3) {
+      fwd_round<3>(a, T, n, t);
+      t >>= 3;
+      left -= 3;
+    } else if (left == 2) {
+      fwd_round<2>(a, T, n, t);
+      t >>= 2;
+      left -= 2;
+    } else {
+      fwd_round<1>(a, T, n, t);
+      t >>= 1;
+      left -= 1;
     }
-    __syncthreads();
   }
 }
 
+// Inverse negacyclic NTT in place (input in bit-reversed order), including the 1/n factor.
 __device__ __forceinline__ void ntt_inv_lds(uint64_t* a, const NttTab& T) {
   const int n = 1 << T.logn;
-  const uint64_t q = T.q;
-  for (int m = n >> 1, logt = 0; m >= 1; m >>= 1, ++logt) {
-    const int t = 1 << logt;
-    for (int idx = threadIdx.x; idx < (n >> 1); idx += blockDim.x) {
-      const int i = idx >> logt;
-      const int j1 = (i << (logt + 1)) + (idx & (t - 1));
-      const uint64_t S = T.ipsi[m + i], Ssh = T.ipsi_sh[m + i];
-      const uint64_t U = a[j1], V = a[j1 + t];
-      a[j1] = add_mod(U, V, q);
-      a[j1 + t] = mul_shoup(sub_mod(U, V, q), S, Ssh, q);
+  int t = 1, left = T.logn;
+  while (left > 0) {
+    if (left >= 3) {
+      inv_round<3>(a, T, n, t, left == 3);
+      t <<= 3;
+      left -= 3;
+    } else if (left == 2) {
+      inv_round<2>(a, T, n, t, true);
+      t <<= 2;
+      left -= 2;
+    } else {
+      inv_round<1>(a, T, n, t, true);
+      t <<= 1;
+      left -= 1;
     }
-    __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < n; idx += blockDim.x)
-    a[idx] = mul_shoup(a[idx], T.n_inv, T.n_inv_sh, q);
-  __syncthreads();
 }
 
 // a <- a . w pointwise, w given with its Shoup companions w_sh (both n entries).
@@ -202,16 +281,26 @@ k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, cons
     }
   }
   __syncthreads();
+  // NTT(a_c) once, kept in registers for all chunks.
+  ntt_fwd_lds(lds, T);
+  uint64_t ahat[kTAccMax];
+#pragma unroll
+  for (int r = 0; r < kTAccMax; ++r) {
+    const int v = threadIdx.x + r * blockDim.x;
+    ahat[r] = v < n ? lds[v] : 0;
+  }
   const uint64_t pm = barrett64(A.p, q, M.mu);
   const uint64_t key_e = stream_tag(kDbE, 0);
   const int chunks = (int)((A.d1 + n - 1) / n);
   for (int j = 0; j < chunks; ++j) {
-    if (j) {
-      for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = col[v];
-      __syncthreads();
+    const uint64_t* w = sdb_hat + (int64_t)j * 2 * n;
+    const uint64_t* wsh = w + n;
+#pragma unroll
+    for (int r = 0; r < kTAccMax; ++r) {
+      const int v = threadIdx.x + r * blockDim.x;
+      if (v < n) lds[v] = mul_shoup(ahat[r], w[v], wsh[v], q);
     }
-    ntt_fwd_lds(lds, T);
-    pointwise_lds(lds, sdb_hat + (int64_t)j * 2 * n, sdb_hat + (int64_t)j * 2 * n + n, n, q);
+    __syncthreads();
     ntt_inv_lds(lds, T);
     const int64_t lo = (int64_t)j * n;
     const int64_t hi = lo + n < A.d1 ? lo + n : A.d1;
@@ -269,15 +358,25 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
     }
   }
   __syncthreads();
+  // NTT(a_c) once, kept in registers (n / blockDim <= kTAccMax values per thread) for all chunks.
+  ntt_fwd_lds(lds, T);
+  uint64_t ahat[kTAccMax];
+#pragma unroll
+  for (int r = 0; r < kTAccMax; ++r) {
+    const int t = threadIdx.x + r * blockDim.x;
+    ahat[r] = t < n ? lds[t] : 0;
+  }
   const uint64_t key_e = stream_tag(kQE, 0);
   const int8_t* m = A.m_q + c * A.d2;
   for (int j = 0; j < A.k; ++j) {
-    if (j) {
-      for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = arow[t];
-      __syncthreads();
+    const uint64_t* w = s_hat + (int64_t)j * 2 * n;
+    const uint64_t* wsh = w + n;
+#pragma unroll
+    for (int r = 0; r < kTAccMax; ++r) {
+      const int t = threadIdx.x + r * blockDim.x;
+      if (t < n) lds[t] = mul_shoup(ahat[r], w[t], wsh[t], q);
     }
-    ntt_fwd_lds(lds, T);
-    pointwise_lds(lds, s_hat + (int64_t)j * 2 * n, s_hat + (int64_t)j * 2 * n + n, n, q);
+    __syncthreads();
     ntt_inv_lds(lds, T);
     const int64_t lo = (int64_t)j * n;
     const int64_t hi = lo + n < A.d2 ? lo + n : A.d2;
