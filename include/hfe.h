@@ -86,8 +86,10 @@ typedef struct hfe_qct hfe_qct;    /* encrypted query batch                     
 typedef struct hfe_rct hfe_rct;    /* encrypted CCMM result                              */
 
 /* Device allocator hook: alloc(bytes, stream, ctx) returns device memory usable in stream
- * order on `stream` (NULL on failure); dealloc(ptr, stream, ctx) releases it in stream order.
- * Passing NULL functions restores hipMalloc / hipFree. */
+ * order on `stream` (NULL on failure), aligned to at least 256 bytes as hipMalloc's is (the
+ * kernels read and write 16-byte vectors at offsets that are multiples of 16 from the start);
+ * dealloc(ptr, stream, ctx) releases it in stream order.  Passing NULL functions restores
+ * hipMalloc / hipFree. */
 typedef void* (*hfe_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*hfe_dealloc_fn)(void* ptr, void* stream, void* ctx);
 hfe_status hfe_set_allocator(hfe_alloc_fn alloc, hfe_dealloc_fn dealloc, void* ctx);

@@ -72,8 +72,12 @@ __global__ void __launch_bounds__(kChunk) k_crt_rns_batched(const BatchElemHeade
     const BatchCrtDesc& p = d[b];
     const int64_t e = base + threadIdx.x - p.elem_begin;
     if (e >= (int64_t)p.nz * p.n) continue;
-    const int z = (int)(e / p.n);
-    const int64_t i = e - (int64_t)z * p.n;
+    int z = 0;
+    int64_t i = e;
+    while (i >= p.n) {  // nz is at most the number of primes
+      i -= p.n;
+      ++z;
+    }
     const int slot = z < p.level ? z : p.pslot;
     p.C[(size_t)z * p.n + i] = crt_entry(p.res + (size_t)z * ra.n * p.n + i, p.n, ra, slot);
   }
