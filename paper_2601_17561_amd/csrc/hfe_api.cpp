@@ -910,10 +910,12 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
       }
     }
     tiles += rns ? rns_batched_tiles(d3, R_out[b], nz, planes) : i8_batched_tiles(variant, d3, R_out[b], nz);
-    crt_e += ((int64_t)nz * d3 * R_out[b] + 255) / 256 * 256;
+    crt_e += ((int64_t)nz * ((d3 * R_out[b] + 3) / 4) + 255) / 256 * 256;  // the CRT's unit: 4 entries
     z.xd_bytes += (size_t)nz * planes * D->KB * d3_pad[b] * kKB;
-    z.c_elems += (size_t)nz * d3 * R_out[b];
-    if (rns) z.res_elems += (size_t)nz * planes * d3 * R_out[b];
+    // each problem's C and residues start at a multiple of 4 entries (the CRT's word loads and
+    // 16-byte stores)
+    z.c_elems += ((size_t)nz * d3 * R_out[b] + 3) / 4 * 4;
+    if (rns) z.res_elems += ((size_t)nz * planes * d3 * R_out[b] + 3) / 4 * 4;
     z.max_level = std::max(z.max_level, level);
   }
   int64_t lift_e = 0, resc_e = 0;
@@ -1164,8 +1166,8 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   const int64_t R_max = ndb + D->d1;
   const int64_t cols_pad = max_cols + (int64_t)max_items * (qpad - 1);  // every item its own problem
   P->xd_cap = (size_t)(max_level + 1) * planes * D->KB * cols_pad * kKB;
-  P->c_cap = (size_t)(max_level + 1) * max_cols * R_max;
-  P->res_cap = rns ? (size_t)(max_level + 1) * planes * max_cols * R_max : 0;
+  P->c_cap = (size_t)(max_level + 1) * max_cols * R_max + 4 * (size_t)max_items;  // + alignment of each problem
+  P->res_cap = rns ? (size_t)(max_level + 1) * planes * max_cols * R_max + 4 * (size_t)max_items : 0;
   P->out_cap = (size_t)max_level * max_cols * R_max;
   const BlobLayout L(max_items);
   P->blob_bytes = L.bytes;

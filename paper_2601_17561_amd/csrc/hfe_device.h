@@ -36,10 +36,14 @@ __device__ __forceinline__ void split5(int64_t x, int32_t d[kDigits]) {
 __device__ __forceinline__ void garner_digits(const uint64_t* y, int level,
                                               const uint64_t (*garner)[HFE_MAX_QPRIMES],
                                               const uint64_t* q, const uint64_t* mus, uint64_t* v) {
-  for (int i = 0; i < level; ++i) {
+  // loops unrolled to the maximum level, so that y and v stay in registers
+#pragma unroll
+  for (int i = 0; i < HFE_MAX_QPRIMES; ++i) {
+    if (i >= level) break;
     const uint64_t qi = q[i];
     const uint64_t mu = mus[i];
     uint64_t s = 0;
+#pragma unroll
     for (int j = 0; j < i; ++j)
       s = add_mod(s, mul_mod(barrett64(v[j], qi, mu), garner[i][j], qi, mu), qi);
     v[i] = i == 0 ? y[0] : mul_mod(sub_mod(y[i], s, qi), garner[i][i], qi, mu);
@@ -48,10 +52,15 @@ __device__ __forceinline__ void garner_digits(const uint64_t* y, int level,
 
 // Y > (Q - 1)/2, compared on mixed-radix digits from the most significant one.
 __device__ __forceinline__ bool above_half(const uint64_t* v, const uint64_t* half, int level) {
-  for (int i = level - 1; i >= 0; --i) {
-    if (v[i] != half[i]) return v[i] > half[i];
+  bool gt = false, decided = false;
+#pragma unroll
+  for (int i = HFE_MAX_QPRIMES - 1; i >= 0; --i) {
+    if (i < level && !decided && v[i] != half[i]) {
+      gt = v[i] > half[i];
+      decided = true;
+    }
   }
-  return false;
+  return gt;
 }
 
 // Query element (c, k) of XT ([level][d3][K]): the residues y_i of the lift L(x) = centered
@@ -61,37 +70,18 @@ __device__ __forceinline__ bool lift_residues(const uint64_t* XT, int64_t d3, in
                                               int64_t c, int64_t k, uint64_t* y, uint64_t& lp) {
   lp = 0;
   if (c >= d3 || k >= K) return false;
-  for (int i = 0; i < la.level; ++i) y[i] = XT[((int64_t)i * d3 + c) * K + k];
-  uint64_t v[HFE_MAX_QPRIMES];
+#pragma unroll
+  for (int i = 0; i < HFE_MAX_QPRIMES; ++i)
+    if (i < la.level) y[i] = XT[((int64_t)i * d3 + c) * K + k];
+  uint64_t v[HFE_MAX_QPRIMES] = {};
   garner_digits(y, la.level, la.garner, la.q, la.mu, v);
   const uint64_t p = la.p;
   const uint64_t mup = la.mu_p;
-  for (int i = 0; i < la.level; ++i)
-    lp = add_mod(lp, mul_mod(barrett64(v[i], p, mup), la.mprod_p[i], p, mup), p);
+#pragma unroll
+  for (int i = 0; i < HFE_MAX_QPRIMES; ++i)
+    if (i < la.level) lp = add_mod(lp, mul_mod(barrett64(v[i], p, mup), la.mprod_p[i], p, mup), p);
   if (above_half(v, la.half_digits, la.level)) lp = sub_mod(lp, la.Q_mod_p, p);
   return true;
-}
-
-// Query element (c, k): writes Xp[c][k] = L mod p (if Xp) and the 5 digit planes of every prime
-// of the level and p (if Xd), zero for padding positions.
-__device__ __forceinline__ void lift_element(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
-                                             int64_t d3_pad, const LiftArgs& la, uint64_t* Xp, int8_t* Xd,
-                                             int64_t c, int64_t k) {
-  uint64_t y[HFE_MAX_QPRIMES] = {};
-  uint64_t lp;
-  const bool valid = lift_residues(XT, d3, K, la, c, k, y, lp);
-  if (valid && Xp) Xp[c * K + k] = lp;
-  if (!Xd) return;
-  const int64_t kb = k / kKB, kk = k % kKB;
-  for (int z = 0; z <= la.level; ++z) {
-    int64_t x = 0;
-    if (valid) x = z < la.level ? centered(y[z], la.q[z]) : centered(lp, la.p);
-    int32_t d[kDigits];
-    split5(x, d);
-#pragma unroll
-    for (int t = 0; t < kDigits; ++t)
-      Xd[((((int64_t)z * kDigits + t) * KB + kb) * d3_pad + c) * kKB + kk] = (int8_t)d[t];
-  }
 }
 
 // ------------------------------------------------------------------ RNS form: small moduli
@@ -102,41 +92,88 @@ __device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t m, uint32_t m
 }
 
 // ------------------------------------------------------------------ balanced residues
-// ceil(2^32 / m) for the moduli of kRnsMods.
-__constant__ static uint32_t kRnsMagic[kRnsMaxMods] = {
-    16777216u, 16843010u, 16976156u, 17111424u, 17388532u, 17821442u, 17970575u, 18433337u,
-    18755316u, 18920561u, 19259944u, 20355296u, 21582751u, 21801865u, 22253717u, 22486740u};
+// Per small modulus m_j of kRnsMods: m_j, ceil(2^32 / m_j) and 2^24 mod m_j, computed at compile time.
+struct RnsModConsts {
+  uint32_t m[kRnsMaxMods], magic[kRnsMaxMods], t24[kRnsMaxMods];
+};
+constexpr RnsModConsts make_rns_mod_consts() {
+  RnsModConsts c{};
+  for (int j = 0; j < kRnsMaxMods; ++j) {
+    const uint64_t m = (uint64_t)kRnsMods[j];
+    c.m[j] = (uint32_t)m;
+    c.magic[j] = (uint32_t)(((1ull << 32) + m - 1) / m);
+    c.t24[j] = (uint32_t)((1ull << 24) % m);
+  }
+  return c;
+}
+__constant__ static RnsModConsts kRnsC = make_rns_mod_consts();
 
 // x (|x| < 2^40) -> x mod m_j in [-floor(m_j/2), ceil(m_j/2) - 1] for the modulus kRnsMods[j]:
-// |x| = hi 2^24 + lo (hi < 2^16), |x| mod m = (hi (2^24 mod m) + lo) mod m with the argument
-// split once more below 2^24.
+// |x| = hi 2^24 + lo (hi < 2^16), and |x| mod m = (hi (2^24 mod m) + (lo mod m)) mod m, whose
+// argument is at most (2^16 - 1)(m - 1) + m - 1 < 2^24.
 __device__ __forceinline__ int32_t balanced_mod(int64_t x, int j) {
-  const uint32_t m = (uint32_t)kRnsMods[j], mg = kRnsMagic[j];
+  const uint32_t m = kRnsC.m[j], mg = kRnsC.magic[j];
   const uint64_t a = (uint64_t)(x < 0 ? -x : x);
   const uint32_t hi = (uint32_t)(a >> 24), lo = (uint32_t)(a & 0xFFFFFF);
-  const uint32_t t24 = mod_small(mod_small(1u << 12, m, mg) * mod_small(1u << 12, m, mg), m, mg);
-  const uint32_t hm = mod_small(mod_small(hi >> 8, m, mg) * mod_small(1u << 8, m, mg) + (hi & 255), m, mg);
-  uint32_t r = mod_small(mod_small(hm * t24, m, mg) + mod_small(lo, m, mg), m, mg);
+  uint32_t r = mod_small(hi * kRnsC.t24[j] + mod_small(lo, m, mg), m, mg);
   if (x < 0 && r) r = m - r;
   return (int32_t)r >= ((int32_t)m + 1) / 2 ? (int32_t)r - (int32_t)m : (int32_t)r;
 }
 
-// Query element (c, k) of the RNS form: for every prime of the level and p, the balanced residues
-// of the centered lifted value modulo each small modulus, Xr[z][j][kb][c][kk] (zero in padding).
-__device__ __forceinline__ void lift_element_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
-                                                 int64_t d3_pad, const LiftArgs& la, int n_mod, int8_t* Xr,
-                                                 int64_t c, int64_t k) {
+// The bytes b of the 4 lanes of a lane quad (lanes 4i .. 4i + 3, lane 4i + e holding byte e),
+// packed into one 32-bit word that every lane of the quad receives (two DPP quad permutations).
+// Every lane of the quad must be active.
+__device__ __forceinline__ uint32_t quad_word(uint32_t b) {
+  uint32_t v = (b & 255u) << (8 * (threadIdx.x & 3));
+  v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm(1, 0, 3, 2)
+  v |= (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm(2, 3, 0, 1)
+  return v;
+}
+
+// Query element (c, k), computed by lane k mod 4 of a lane quad whose 4 lanes hold k - k mod 4 ..
+// + 3 of the same column (whole quads active): the lift (as lift_residues; zero in the padding),
+// L mod p into Xp[c][k] when Xp is given, and, when X is given, for every prime of the level and p
+// the int8 planes of the centered residue, stored by the quad's first lane as one 4-byte word per
+// plane: form 0 the 5 balanced digits (X[z][t][kb][c][kk]), form n > 0 the balanced residues
+// modulo the first n small moduli (X[z][j][kb][c][kk]).
+__device__ __forceinline__ void lift_lane(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
+                                          const LiftArgs& la, int form, uint64_t* Xp, int8_t* X, int64_t c,
+                                          int64_t k) {
   uint64_t y[HFE_MAX_QPRIMES] = {};
   uint64_t lp;
   const bool valid = lift_residues(XT, d3, K, la, c, k, y, lp);
-  const int64_t kb = k / kKB, kk = k % kKB;
-  for (int z = 0; z <= la.level; ++z) {
-    int64_t x = 0;
-    if (valid) x = z < la.level ? centered(y[z], la.q[z]) : centered(lp, la.p);
-    for (int j = 0; j < n_mod; ++j)
-      Xr[((((int64_t)z * n_mod + j) * KB + kb) * d3_pad + c) * kKB + kk] = (int8_t)balanced_mod(x, j);
+  if (valid && Xp) Xp[c * K + k] = lp;
+  if (!X) return;
+  const bool writer = (threadIdx.x & 3) == 0;
+  const int64_t kb = k / kKB, kk = k % kKB - (k & 3);
+  const int planes = form == 0 ? kDigits : form;
+  const int64_t pstride = KB * d3_pad * kKB / 4;  // words between consecutive planes
+  // the planes of prime slot z (the level's primes, then p) for centered value x
+  auto emit = [&](int z, int64_t x) {
+    uint32_t* row = reinterpret_cast<uint32_t*>(X + (((int64_t)z * planes * KB + kb) * d3_pad + c) * kKB + kk);
+    if (form == 0) {
+      int32_t d[kDigits];
+      split5(x, d);
+#pragma unroll
+      for (int t = 0; t < kDigits; ++t) {
+        const uint32_t w = quad_word((uint32_t)d[t]);
+        if (writer) row[t * pstride] = w;
+      }
+    } else {
+      for (int j = 0; j < form; ++j) {
+        const uint32_t w = quad_word((uint32_t)balanced_mod(x, j));
+        if (writer) row[j * pstride] = w;
+      }
+    }
+  };
+#pragma unroll
+  for (int z = 0; z < HFE_MAX_QPRIMES; ++z) {
+    if (z >= la.level) break;
+    emit(z, valid ? centered(y[z], la.q[z]) : 0);
   }
+  emit(la.level, valid ? centered(lp, la.p) : 0);
 }
+
 
 // CRT of one entry (see k_crt_rns): residues r[j n] mod m_j -> the exact centered sum mod the prime
 // of database slot `slot`.
@@ -152,6 +189,40 @@ __device__ __forceinline__ uint64_t crt_entry(const uint8_t* r, int64_t n, const
   const Mod md = ra.mod[slot];
   const uint64_t v = barrett64(acc, md.q, md.mu);
   return sub_mod(v, barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
+}
+
+// Entries e0 .. e0 + 3 (those below n) of one prime slot: r = that slot's first residue plane
+// ([n_mod][n] bytes), out = its n results.  With n a multiple of 4 the residues of each modulus
+// are read as one 4-byte word and the results written as two 16-byte vectors.
+__device__ __forceinline__ void crt_quad(const uint8_t* r, int64_t n, const RnsCrtArgs& ra, int slot, uint64_t* out,
+                                         int64_t e0) {
+  if ((n & 3) != 0) {
+    for (int b = 0; b < 4 && e0 + b < n; ++b) out[e0 + b] = crt_entry(r + e0 + b, n, ra, slot);
+    return;
+  }
+  float frac[4] = {0.f, 0.f, 0.f, 0.f};
+  uint64_t acc[4] = {0, 0, 0, 0};
+  for (int j = 0; j < ra.n; ++j) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(r + (size_t)j * n + e0);
+    const uint32_t m = (uint32_t)ra.m[j], magic = ra.magic[j], inv = (uint32_t)ra.inv[j];
+    const uint64_t mj = ra.Mj_mod_q[slot][j];
+    const float rcp = ra.rcp[j];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t y = mod_small(((w >> (8 * b)) & 255u) * inv, m, magic);
+      frac[b] = fmaf((float)y, rcp, frac[b]);
+      acc[b] += (uint64_t)y * mj;
+    }
+  }
+  const Mod md = ra.mod[slot];
+  uint64_t v[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint64_t a = (uint64_t)(frac[b] + 0.5f);
+    v[b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
+  }
+  reinterpret_cast<ulonglong2*>(out + e0)[0] = make_ulonglong2(v[0], v[1]);
+  reinterpret_cast<ulonglong2*>(out + e0)[1] = make_ulonglong2(v[2], v[3]);
 }
 
 // Output entry e of a contraction (C[i] = residues mod q_i, Cp = residues mod p, n entries per

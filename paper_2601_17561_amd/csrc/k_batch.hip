@@ -3,8 +3,8 @@
 // another rescales every item's output, and for the RNS form a third reconstructs every problem's
 // residues mod its primes.  Each reads its work list from a device-resident descriptor table, so
 // the same launches (and a hipGraph that captured them) serve any batch that fits the workspace:
-// the host only rewrites the table.  Work is dealt in chunks of 256 elements; every list entry
-// starts at a multiple of 256, so one chunk never straddles two entries.
+// the host only rewrites the table.  Work is dealt in chunks of 256 units; every list entry starts
+// at a multiple of 256, so one chunk never straddles two entries.
 #include "hfe_device.h"
 
 namespace hfe {
@@ -34,13 +34,11 @@ __global__ void __launch_bounds__(kChunk) k_lift_batched(const BatchElemHeader* 
     const int b = find_problem(begins, n, base);
     const BatchLiftDesc& p = d[b];
     const int64_t e = base + threadIdx.x - p.elem_begin;
+    // whole lane quads pass (cols x kpad is a multiple of 4), as the lift's packing needs
     if (e >= p.cols * kpad) continue;
     // columns c >= p.d3 are the problem's padding: lift_residues reports them invalid (zero)
-    int8_t* X = p.Xd + p.c0 * kKB;
-    if (form == 0)
-      lift_element(p.XT, p.d3, K, KB, p.d3_pad, p.la, nullptr, X, e / kpad, e % kpad);
-    else
-      lift_element_rns(p.XT, p.d3, K, KB, p.d3_pad, p.la, form, X, e / kpad, e % kpad);
+    const int64_t c = e / kpad;
+    lift_lane(p.XT, p.d3, K, KB, p.d3_pad, p.la, form, nullptr, p.Xd + p.c0 * kKB, c, e - c * kpad);
   }
 }
 
@@ -70,16 +68,17 @@ __global__ void __launch_bounds__(kChunk) k_crt_rns_batched(const BatchElemHeade
   for (int64_t base = (int64_t)blockIdx.x * kChunk; base < total; base += (int64_t)gridDim.x * kChunk) {
     const int b = find_problem(begins, n, base);
     const BatchCrtDesc& p = d[b];
+    const int64_t nq = (p.n + 3) / 4;  // units: 4 consecutive entries of one prime slot
     const int64_t e = base + threadIdx.x - p.elem_begin;
-    if (e >= (int64_t)p.nz * p.n) continue;
+    if (e >= (int64_t)p.nz * nq) continue;
     int z = 0;
     int64_t i = e;
-    while (i >= p.n) {  // nz is at most the number of primes
-      i -= p.n;
+    while (i >= nq) {  // nz is at most the number of primes
+      i -= nq;
       ++z;
     }
     const int slot = z < p.level ? z : p.pslot;
-    p.C[(size_t)z * p.n + i] = crt_entry(p.res + (size_t)z * ra.n * p.n + i, p.n, ra, slot);
+    crt_quad(p.res + (size_t)z * ra.n * p.n, p.n, ra, slot, p.C + (size_t)z * p.n, 4 * i);
   }
 }
 

@@ -100,14 +100,15 @@ hipError_t launch_split_db(const uint64_t* Dt_prime, int64_t K, int64_t R, int64
 }
 
 // ------------------------------------------------------------------ query lift + digit split
-// Element (c, k): residues XT[i][c][k] of L(x) mod q_i; the lift L(x) = centered CRT value in
-// (-Q/2, Q/2); L mod p.  Writes Xp[c][k] = L mod p (plain form) and, for every prime of the
-// level and p, the 5 digit planes of the centered residue (i8 form), zero in the padding.
+// Element (c, k): residues XT[i][c][k] of L(x) mod q_i, where the lift L(x) is the centered CRT
+// value in (-Q/2, Q/2).  Writes Xp[c][k] = L mod p (plain form) and, for every prime of the level
+// and p, the 5 digit planes of the centered residue (i8 form), zero in the padding.  The K-range
+// KB * 64 is a multiple of the block, so lane quads are whole.
 __global__ void __launch_bounds__(256) k_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
                                               int64_t d3_pad, LiftArgs la, uint64_t* Xp, int8_t* Xd) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= KB * kKB) return;
-  lift_element(XT, d3, K, KB, d3_pad, la, Xp, Xd, blockIdx.y, k);
+  lift_lane(XT, d3, K, KB, d3_pad, la, 0, Xp, Xd, blockIdx.y, k);
 }
 
 hipError_t launch_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,

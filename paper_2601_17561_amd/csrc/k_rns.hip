@@ -44,14 +44,14 @@ hipError_t launch_split_db_rns(const uint64_t* Dt_prime, int64_t K, int64_t R, i
 }
 
 // ------------------------------------------------------------------ query lift
-// Element (c, k): the lift of the query residues (as for the digit form), then for every prime
-// of the level and p the balanced residues of the centered value modulo each small modulus:
+// Element (c, k): the lift of the query residues (as for the digit form), then for every prime of
+// the level and p the balanced residues of the centered value modulo each small modulus:
 // Xr[z][j][kb][c][kk], zero in the padding.
 __global__ void __launch_bounds__(256) k_lift_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
                                                   int64_t d3_pad, LiftArgs la, int n_mod, int8_t* Xr) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= KB * kKB) return;
-  lift_element_rns(XT, d3, K, KB, d3_pad, la, n_mod, Xr, blockIdx.y, k);
+  lift_lane(XT, d3, K, KB, d3_pad, la, n_mod, nullptr, Xr, blockIdx.y, k);
 }
 
 hipError_t launch_lift_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
@@ -290,41 +290,12 @@ hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s) {
 // - floor(...) = (S mod M) / M lies at least 1/4 away from 1/2 and single precision (error
 // below 2^-19 over 16 terms) decides a exactly; then
 // C = sum_j y_j ((M/m_j) mod q) - a (M mod q) mod q.
-// Thread: 4 consecutive entries of one prime slot (blockIdx.y), the residues of each modulus read
-// as one 4-byte word when the planes allow it.
+// Thread: 4 consecutive entries of one prime slot (blockIdx.y).
 __global__ void __launch_bounds__(256) k_crt_rns(const uint8_t* res, int64_t n, RnsCrtArgs ra, uint64_t* C) {
   const int z = blockIdx.y;
   const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
   if (e0 >= n) return;
-  const uint8_t* r = res + (size_t)z * ra.n * n + e0;
-  uint64_t* out = C + (size_t)z * n + e0;
-  if ((n & 3) == 0) {
-    float frac[4] = {0.f, 0.f, 0.f, 0.f};
-    uint64_t acc[4] = {0, 0, 0, 0};
-    for (int j = 0; j < ra.n; ++j) {
-      const uint32_t w = *reinterpret_cast<const uint32_t*>(r + (size_t)j * n);
-      const uint32_t m = (uint32_t)ra.m[j], magic = ra.magic[j], inv = (uint32_t)ra.inv[j];
-      const uint64_t mj = ra.Mj_mod_q[z][j];
-      const float rcp = ra.rcp[j];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const uint32_t y = mod_small(((w >> (8 * b)) & 255u) * inv, m, magic);
-        frac[b] = fmaf((float)y, rcp, frac[b]);
-        acc[b] += (uint64_t)y * mj;
-      }
-    }
-    const Mod md = ra.mod[z];
-    uint64_t v[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const uint64_t a = (uint64_t)(frac[b] + 0.5f);
-      v[b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[z], md.q, md.mu), md.q);
-    }
-    reinterpret_cast<ulonglong2*>(out)[0] = make_ulonglong2(v[0], v[1]);
-    reinterpret_cast<ulonglong2*>(out)[1] = make_ulonglong2(v[2], v[3]);
-  } else {
-    for (int b = 0; b < 4 && e0 + b < n; ++b) out[b] = crt_entry(r + b, n, ra, z);
-  }
+  crt_quad(res + (size_t)z * ra.n * n, n, ra, z, C + (size_t)z * n, e0);
 }
 
 hipError_t launch_crt_rns(const uint8_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
