@@ -107,6 +107,17 @@ def test_batched_rns_equals_single_calls_and_oracle(env):
     _check_results(env, res, "batched rns")
 
 
+def test_single_rns_calls_equal_digit_form_on_every_item(env):
+    # the items include d3 x R_out not divisible by 4 (1 column x 129 rows), where the CRT takes
+    # its entry-by-entry path, and divisible ones, where it reads 4-byte residue words
+    _say("[gpu-batched] single hfe_ccmm calls, rns form, every item")
+    res = [H.hfe_ccmm(env["db"], q, row0, rows, H.HFE_FORM_RNS_I8) for q, row0, rows in env["items"]]
+    torch.cuda.synchronize()
+    n_db = env["c"].P.n_db
+    assert any(mq.shape[0] * (n_db + it[2]) % 4 for mq, it in zip(env["mqs"], env["items"]))
+    _check_results(env, res, "single rns")
+
+
 def test_batched_plain_equals_i8(env):
     _say("[gpu-batched] hfe_ccmm_batched plain")
     a = H.hfe_ccmm_batched(env["db"], env["items"], H.HFE_FORM_PLAIN_U64)
