@@ -315,7 +315,7 @@ def main():
         # the autotuner picks the int8 tile for this shape (setup, not timed)
         m_q = H.hfe_encode(q_codes, q_masks, shifts)
         qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
-        tile = H.hfe_i8_variant_name(H.hfe_autotune(db, qct, 0, w.d1, reps=2))
+        tile = H.hfe_i8_variant_name(H.hfe_autotune(db, qct, 0, w.d1, reps=3))
         qct.free()
         log(f"autotuned int8 tile: {tile}")
     elif args.variant >= 0:

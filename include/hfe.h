@@ -170,7 +170,8 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
 hfe_status hfe_plan_result(const hfe_plan* plan, int32_t i, const hfe_rct** view);
 
 /* Autotuner of the int8 contraction tiles: times every tile configuration (see hfe_i8_variants)
- * on this problem (reps timed runs each, after one untimed), records the fastest for the
+ * on this problem (one untimed run each, then reps rounds that time every configuration once,
+ * keeping each configuration's best), records the fastest for the
  * problem's (level, query-column bucket; buckets are powers of two from 64) and returns it in
  * *best.  Later hfe_ccmm calls, batches (by their largest level and mean column count) and plans
  * (at creation) use the entry of their level with the nearest bucket, else the default.  The

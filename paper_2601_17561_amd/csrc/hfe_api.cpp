@@ -1288,28 +1288,28 @@ hfe_status hfe_autotune(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_
   if (!Qc || !best || reps < 1) return fail(HFE_EINVAL, "invalid query, best or reps");
   const int saved_variant = g_i8_variant.load();
   const int saved_profile = g_profile.load();
-  float best_ms = 1e30f;
-  int best_v = -1;
+  // one untimed run per configuration, then `reps` rounds that time every configuration once each
+  // (interleaved, so a drift of the clock over the tuning run favours none), keeping each one's best
+  const int nv = i8_variant_count();
+  std::vector<float> vbest(nv, 1e30f);
   hfe_status st = HFE_OK;
-  for (int v = 0; v < i8_variant_count() && st == HFE_OK; ++v) {
-    g_i8_variant.store(v);
-    float vbest = 1e30f;
-    for (int r = 0; r <= reps && st == HFE_OK; ++r) {
+  for (int r = 0; r <= reps && st == HFE_OK; ++r) {
+    for (int v = 0; v < nv && st == HFE_OK; ++v) {
+      g_i8_variant.store(v);
       g_profile.store(r > 0 ? 1 : 0);
       hfe_rct* res = nullptr;
       st = hfe_ccmm(db, q, row0, rows, HFE_FORM_I8_MFMA, stream, &res);
       if (st == HFE_OK && r > 0) {
         float ms[2];
         st = hfe_profile_ms(res, ms, 2);
-        if (st == HFE_OK) vbest = std::min(vbest, ms[1]);
+        if (st == HFE_OK) vbest[v] = std::min(vbest[v], ms[1]);
       }
       hfe_free(res);
     }
-    if (vbest < best_ms) {
-      best_ms = vbest;
-      best_v = v;
-    }
   }
+  int best_v = 0;
+  for (int v = 1; v < nv; ++v)
+    if (vbest[v] < vbest[best_v]) best_v = v;
   g_i8_variant.store(saved_variant);
   g_profile.store(saved_profile);
   if (st != HFE_OK) return st;
