@@ -69,11 +69,14 @@ hipError_t launch_lift_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB
 // global-to-LDS loads (same row swizzle as the digit form's DMA tiles), so up to three K-blocks
 // are in flight while one is multiplied (three stages measured 6% slower, five no faster).
 // Exactness: |S| over the K-range <= K * 128 * 128 < 2^31 for K < 2^17 (checked by the host).
-constexpr int kRnsWQB = 2, kRnsWRB = 4, kRnsNQ = kRnsTileQ / 64, kRnsNR = kRnsTileR / 128;
+constexpr int kRnsWQB = 2, kRnsWRB = 4, kRnsWPE = 2;  // 32 x 32 blocks per wave; waves per SIMD
+constexpr int kRnsNQ = kRnsTileQ / (32 * kRnsWQB), kRnsNR = kRnsTileR / (32 * kRnsWRB);
 constexpr int kRnsNW = kRnsNQ * kRnsNR, kRnsStages = 4;
 static_assert(kRnsStages >= 3 && kRnsStages <= 5, "the K-block wait handles three to five stages");
 constexpr int kRnsPA = kRnsTileQ * kKB, kRnsPB = kRnsTileR * kKB, kRnsStage = kRnsPA + kRnsPB;
-constexpr int kRnsLA = kRnsTileQ / 16 / kRnsNW, kRnsLB = kRnsTileR / 16 / kRnsNW;  // 2 + 2 loads per wave
+constexpr int kRnsLA = kRnsTileQ / 16 / kRnsNW, kRnsLB = kRnsTileR / 16 / kRnsNW;  // loads per wave per K-block
+constexpr int kRnsVm = (kRnsLA + kRnsLB) * (kRnsStages - 2);  // loads a wave may leave in flight at a K-block wait
+static_assert(kRnsTileQ % (16 * kRnsNW) == 0 && kRnsTileR % (16 * kRnsNW) == 0, "whole loads per wave");
 
 __device__ __forceinline__ void dma16_rns(const int8_t* g, uint32_t lds_addr) {
   asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
@@ -94,7 +97,6 @@ struct RnsTile {
 };
 
 __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
-  static_assert(kRnsNW == 8 && kRnsLA + kRnsLB == 4, "the vmcnt below assumes 4 loads per wave per K-block");
   const int64_t r0 = g.r0, c0 = g.c0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wq = wave % kRnsNQ, wr = wave / kRnsNQ;
@@ -148,12 +150,20 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
   // this wave's loads of the oldest outstanding K-block have landed (the S - 2 younger ones may
   // still fly) and its LDS reads are done; then the same for every wave
   auto wait_block = [] {
-    if constexpr (kRnsStages == 3)
+    static_assert(kRnsVm == 4 || kRnsVm == 6 || kRnsVm == 8 || kRnsVm == 12 || kRnsVm == 16 || kRnsVm == 24,
+                  "no K-block wait for this tile shape");
+    if constexpr (kRnsVm == 4)
       asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else if constexpr (kRnsStages == 4)
+    else if constexpr (kRnsVm == 6)
+      asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else if constexpr (kRnsVm == 8)
       asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else
+    else if constexpr (kRnsVm == 12)
       asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else if constexpr (kRnsVm == 16)
+      asm volatile("s_waitcnt vmcnt(16) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(24) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   };
   // Software pipeline: the fragments of half 0 of block i are in registers when iteration i
   // starts; half 1 is read while half 0 multiplies, and half 0 of block i + 1 while half 1
@@ -210,7 +220,7 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
   }
 }
 
-__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_gemm_rns(RnsGemmArgs g) {
+__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(kRnsWPE, kRnsWPE))) k_gemm_rns(RnsGemmArgs g) {
   __shared__ __attribute__((aligned(16))) int8_t lds[kRnsStages * kRnsStage];
   const int j = blockIdx.y, z = blockIdx.z;
   const int64_t n_ct = (g.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (g.R_out + kRnsTileR - 1) / kRnsTileR;
@@ -226,7 +236,7 @@ __global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_e
 // Persistent batched form: problem b's tiles are ordered (z, modulus, XCD-ordered tile), starting at
 // its tile_begin; workgroups claim tiles in order from one counter per XCD (tile t = 8 j + xcd), as
 // the digit form's batched kernel.
-__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_gemm_rns_batched(RnsBatchArgs a) {
+__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(kRnsWPE, kRnsWPE))) k_gemm_rns_batched(RnsBatchArgs a) {
   __shared__ __attribute__((aligned(16))) int8_t lds[kRnsStages * kRnsStage];
   const int n = a.hdr->n;
   const int xcd = blockIdx.x % kXcds;
@@ -271,7 +281,12 @@ hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, hipStream_t 
   return hipGetLastError();
 }
 
-int rns_wgs_per_cu() { return 1; }  // 96 KiB or more of LDS per workgroup
+// resident workgroups per CU: as many as the 160 KiB of LDS hold, at most the waves-per-SIMD target
+int rns_wgs_per_cu() {
+  const int by_lds = 160 * 1024 / (kRnsStages * kRnsStage), by_waves = kRnsWPE * 4 / kRnsNW;
+  const int w = by_lds < by_waves ? by_lds : by_waves;
+  return w > 0 ? w : 1;
+}
 
 hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s) {
   if (g.R_out <= 0 || g.d3 <= 0) return hipSuccess;
