@@ -69,8 +69,9 @@ typedef enum { HFE_FORM_PLAIN_U64 = 1, HFE_FORM_I8_MFMA = 2, HFE_FORM_RNS_I8 = 4
 #define HFE_MAX_QPRIMES 8
 
 typedef struct {
-  uint32_t log_n_db;              /* N_DB = 2^log_n_db, database ring degree, 1..16      */
-  uint32_t log_n_q;               /* N_Q = 2^log_n_q, query ring degree, 1..16           */
+  uint32_t log_n_db;              /* N_DB = 2^log_n_db, database ring degree, 1..14 (the */
+                                  /* transforms are LDS-resident: 2^14 x 8 B = 128 KiB)  */
+  uint32_t log_n_q;               /* N_Q = 2^log_n_q, query ring degree, 1..14           */
   uint32_t n_q_primes;            /* L, query primes carried by the database, 1..8       */
   uint64_t q[HFE_MAX_QPRIMES];    /* q_0..q_{L-1}: distinct primes < 2^36, = 1 mod 2N    */
   uint64_t p;                     /* special prime < 2^36, = 1 mod 2N, distinct from q_i */
