@@ -29,6 +29,22 @@ __device__ __forceinline__ void split5(int64_t x, int32_t d[kDigits]) {
   d[kDigits - 1] = (int32_t)x;
 }
 
+// ------------------------------------------------------------------ direct global-to-LDS load
+// global_load_lds_dwordx4: each lane's 16 bytes at g land in LDS at M0 + 16 * lane.  The load is
+// counted by vmcnt like any vector load; callers wait for it with explicit s_waitcnt.  M0 is
+// written and not restored: the compiler reserves M0 and sets it right before the few
+// instructions that read it, so no value of its own lives in M0 across this statement (the clobber
+// entry records the write; the compiler warns that it does not act on it).
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void dma16(const int8_t* g, uint32_t lds_addr) {
+  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+               :
+               : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
 // ------------------------------------------------------------------ Garner mixed radix
 // Residues y_i mod q_i -> digits v_i with Y = v_0 + v_1 q_0 + v_2 q_0 q_1 + ..., computed as
 // v_i = (y_i - sum_{j<i} v_j (q_0..q_{j-1} mod q_i)) * (q_0..q_{i-1})^-1 mod q_i.

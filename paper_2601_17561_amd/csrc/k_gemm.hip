@@ -96,8 +96,6 @@ hipError_t launch_gemm_plain(const GemmArgs& g, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ int8 MFMA form
-constexpr int kIQ = 64;           // query columns per workgroup (2 waves x 32)
-constexpr int kIR = 64;           // output rows per workgroup (2 waves x 32)
 constexpr int kLdsRow = 80;       // bytes per LDS row: 64 digits + 16 pad (conflict-free b128 reads)
 constexpr int kChunkKB = 511;     // K-blocks per exact int32 chunk: 511 * 64 * 4 * 2^14 < 2^31
 
@@ -358,12 +356,6 @@ __device__ __forceinline__ void tile_pipe(const I8Tile& T, int8_t* lds) {
 // lds: STAGES x 5 x (32 WQ + 32 WR) rows x 64 bytes.
 constexpr int kDmaRow = kKB;  // LDS bytes per tile row
 
-__device__ __forceinline__ void dma16(const int8_t* g, uint32_t lds_addr) {
-  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
-               :
-               : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
-               : "memory", "m0");
-}
 
 template <int WR, int WQ, int STAGES>
 __device__ __forceinline__ void tile_dma(const I8Tile& T, int8_t* lds) {

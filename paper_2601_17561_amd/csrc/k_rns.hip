@@ -78,12 +78,6 @@ constexpr int kRnsLA = kRnsTileQ / 16 / kRnsNW, kRnsLB = kRnsTileR / 16 / kRnsNW
 constexpr int kRnsVm = (kRnsLA + kRnsLB) * (kRnsStages - 2);  // loads a wave may leave in flight at a K-block wait
 static_assert(kRnsTileQ % (16 * kRnsNW) == 0 && kRnsTileR % (16 * kRnsNW) == 0, "whole loads per wave");
 
-__device__ __forceinline__ void dma16_rns(const int8_t* g, uint32_t lds_addr) {
-  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
-               :
-               : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
-               : "memory", "m0");
-}
 
 // One output tile (rows r0.., query columns c0..) of one (prime, modulus) product: X and D are that
 // modulus' query and database planes, res its residue plane [d3][R_out].
@@ -118,9 +112,9 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
   auto issue = [&](int stage, int64_t kb) {
     const uint32_t base = lds0 + stage * kRnsStage;
 #pragma unroll
-    for (int i = 0; i < kRnsLA; ++i) dma16_rns(gA[i] + kb * stepA, base + 16 * kRnsNW * i * kKB);
+    for (int i = 0; i < kRnsLA; ++i) dma16(gA[i] + kb * stepA, base + 16 * kRnsNW * i * kKB);
 #pragma unroll
-    for (int i = 0; i < kRnsLB; ++i) dma16_rns(gB[i] + kb * stepB, base + kRnsPA + 16 * kRnsNW * i * kKB);
+    for (int i = 0; i < kRnsLB; ++i) dma16(gB[i] + kb * stepB, base + kRnsPA + 16 * kRnsNW * i * kKB);
   };
   const int sw = ((lane & 31) >> 2) & 3, cl = lane >> 5;
   const int offA = (wq * 32 * kRnsWQB + (lane & 31)) * kKB;
