@@ -782,23 +782,26 @@ hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n) {
 }  // extern "C"
 
 namespace {
-// Byte layout of the descriptor tables of a batch of up to `cap` items (256-byte aligned parts):
-// contraction (per problem), lift (per item), rescale (per item), RNS reconstruction (per problem).
+// Byte layout of the descriptor tables of a batch of up to `items` items and `problems` problems
+// (256-byte aligned parts): contraction (per problem), lift (per item), rescale (per item), RNS
+// reconstruction (per problem).
 struct BlobLayout {
   size_t gh, gd, lh, ld, rh, rd, ch, cd, bytes;
-  explicit BlobLayout(int cap) {
+  BlobLayout(int items, int problems) {
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     gh = 0;
     gd = al(gh + sizeof(BatchHeader));
-    lh = al(gd + sizeof(BatchDesc) * cap);
+    lh = al(gd + sizeof(BatchDesc) * problems);
     ld = al(lh + sizeof(BatchElemHeader));
-    rh = al(ld + sizeof(BatchLiftDesc) * cap);
+    rh = al(ld + sizeof(BatchLiftDesc) * items);
     rd = al(rh + sizeof(BatchElemHeader));
-    ch = al(rd + sizeof(BatchRescaleDesc) * cap);
+    ch = al(rd + sizeof(BatchRescaleDesc) * items);
     cd = al(ch + sizeof(BatchElemHeader));
-    bytes = al(cd + sizeof(BatchCrtDesc) * cap);
+    bytes = al(cd + sizeof(BatchCrtDesc) * problems);
   }
 };
+// problems of a batch of n items: at most one more per level than items (see group_items)
+int max_problems(int n) { return n + kMaxPrimes; }
 
 struct BatchSizes {
   size_t xd_bytes = 0, c_elems = 0, res_elems = 0, out_elems = 0;
@@ -816,40 +819,89 @@ hfe_status check_item(const hfe_db* D, const hfe_batch_item& it) {
   return HFE_OK;
 }
 
-// Problems of a batch: the items with the same level and row range, in order of first appearance;
-// an item's query columns follow those of the problem's earlier items.
+// Problems of a batch.  Every item multiplies the database's N_DB A rows and its own range of B
+// rows.  The items of one level that share a row range form one problem (A rows and that range,
+// their query columns side by side).  A level whose items cover several row ranges is split:
+// one problem over the A rows for all of the level's columns, padded to whole tiles once, and one
+// problem per row range over just its B rows, which reads its columns from the A problem's query
+// planes (the level's columns are ordered by row range there, so each range's columns are
+// contiguous).  Every item's query planes are lifted once, into its owner problem.
+struct Problem {
+  int level = 0;
+  int64_t row0 = 0, rows = 0;  // B rows of the problem (rows = 0: A rows only)
+  bool a_rows = true;          // the problem includes the A rows
+  int64_t d3 = 0;              // query columns
+  int owner = 0;               // problem holding these columns' query planes (itself, or its A problem)
+  int64_t xc0 = 0;             // first column in the owner's planes
+  int last_item = -1;          // owners: the item whose columns come last (it also fills the padding)
+};
 struct Grouping {
-  std::vector<int> prob;                   // problem of each item
-  std::vector<int64_t> c0;                 // first column of each item in its problem
-  std::vector<int> last;                   // last item of each problem
-  std::vector<int> first;                  // first item of each problem
-  std::vector<int64_t> d3;                 // columns of each problem
+  std::vector<Problem> p;
+  std::vector<int> pa, pb;      // per item: problem of its A rows, of its B rows
+  std::vector<int64_t> ca, cb;  // per item: first column in those problems
 };
 
 Grouping group_items(const hfe_batch_item* items, int n) {
   Grouping g;
-  g.prob.resize(n);
-  g.c0.resize(n);
+  g.pa.resize(n);
+  g.pb.resize(n);
+  g.ca.resize(n);
+  g.cb.resize(n);
+  auto level_of = [&](int i) { return static_cast<const hfe_qct*>(items[i].q)->level; };
+  auto d3_of = [&](int i) { return static_cast<const hfe_qct*>(items[i].q)->d3; };
+  std::vector<int> levels;                       // in order of first appearance
+  std::vector<std::vector<std::vector<int>>> by;  // per level: per row range (first appearance): items
   for (int i = 0; i < n; ++i) {
-    const hfe_qct* Qi = static_cast<const hfe_qct*>(items[i].q);
-    int b = -1;
-    for (size_t k = 0; k < g.first.size(); ++k) {
-      const hfe_batch_item& f = items[g.first[k]];
-      if (static_cast<const hfe_qct*>(f.q)->level == Qi->level && f.row0 == items[i].row0 && f.rows == items[i].rows) {
-        b = (int)k;
-        break;
+    size_t l = 0;
+    while (l < levels.size() && levels[l] != level_of(i)) ++l;
+    if (l == levels.size()) {
+      levels.push_back(level_of(i));
+      by.emplace_back();
+    }
+    size_t r = 0;
+    while (r < by[l].size() &&
+           !(items[by[l][r][0]].row0 == items[i].row0 && items[by[l][r][0]].rows == items[i].rows))
+      ++r;
+    if (r == by[l].size()) by[l].emplace_back();
+    by[l][r].push_back(i);
+  }
+  for (size_t l = 0; l < levels.size(); ++l) {
+    const int A = (int)g.p.size();
+    Problem pa;
+    pa.level = levels[l];
+    pa.owner = A;
+    if (by[l].size() == 1) {  // one row range: one problem
+      pa.row0 = items[by[l][0][0]].row0;
+      pa.rows = items[by[l][0][0]].rows;
+    }
+    g.p.push_back(pa);
+    for (const auto& range : by[l]) {
+      int B = A;
+      if (by[l].size() > 1) {
+        B = (int)g.p.size();
+        Problem pb;
+        pb.level = levels[l];
+        pb.row0 = items[range[0]].row0;
+        pb.rows = items[range[0]].rows;
+        pb.a_rows = false;
+        pb.owner = A;
+        pb.xc0 = g.p[A].d3;
+        g.p.push_back(pb);
+      }
+      for (int i : range) {
+        g.pa[i] = A;
+        g.ca[i] = g.p[A].d3;
+        g.p[A].d3 += d3_of(i);
+        g.p[A].last_item = i;
+        g.pb[i] = B;
+        if (B != A) {
+          g.cb[i] = g.p[B].d3;
+          g.p[B].d3 += d3_of(i);
+        } else {
+          g.cb[i] = g.ca[i];
+        }
       }
     }
-    if (b < 0) {
-      b = (int)g.first.size();
-      g.first.push_back(i);
-      g.last.push_back(i);
-      g.d3.push_back(0);
-    }
-    g.prob[i] = b;
-    g.c0[i] = g.d3[b];
-    g.d3[b] += Qi->d3;
-    g.last[b] = i;
   }
   return g;
 }
@@ -866,31 +918,43 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
   const int planes = rns ? D->n_rns : kDigits;
   const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
   const Grouping gr = group_items(items, n);
-  const int np = (int)gr.first.size();
+  const int np = (int)gr.p.size();
   BatchSizes z;
   z.problems = np;
   std::vector<size_t> xd_off(np), c_off(np), res_off(np);
   std::vector<int64_t> d3_pad(np), R_out(np);
+  std::vector<char> feeds(np, 0);  // owners whose planes split problems also read
+  for (int b = 0; b < np; ++b)
+    if (gr.p[b].owner != b) feeds[gr.p[b].owner] = 1;
+  // query planes of the owners: whole tiles, and for an owner that feeds split problems room for
+  // their last tile, which may reach qpad - 1 columns past the owner's columns
+  for (int b = 0; b < np; ++b) {
+    const Problem& P = gr.p[b];
+    if (P.owner != b) continue;
+    d3_pad[b] = (P.d3 + (feeds[b] ? qpad - 1 : 0) + qpad - 1) / qpad * qpad;
+    xd_off[b] = z.xd_bytes;
+    z.xd_bytes += (size_t)(P.level + 1) * planes * D->KB * d3_pad[b] * kKB;
+  }
   int64_t tiles = 0, crt_e = 0;
   for (int b = 0; b < np; ++b) {
-    const hfe_batch_item& f = items[gr.first[b]];
-    const int level = static_cast<const hfe_qct*>(f.q)->level, nz = level + 1;
-    const int64_t d3 = gr.d3[b];
-    d3_pad[b] = (d3 + qpad - 1) / qpad * qpad;
-    R_out[b] = ndb + f.rows;
-    xd_off[b] = z.xd_bytes;
+    const Problem& P = gr.p[b];
+    const int level = P.level, nz = level + 1;
+    const int64_t d3 = P.d3;
+    R_out[b] = (P.a_rows ? ndb : 0) + P.rows;
     c_off[b] = z.c_elems;
     res_off[b] = z.res_elems;
     if (blob) {
       BatchDesc& g = reinterpret_cast<BatchDesc*>(blob + L.gd)[b];
       std::memset(&g, 0, sizeof(g));
-      g.Xd = xd_base + xd_off[b];
+      g.Xd = xd_base + xd_off[P.owner] + P.xc0 * kKB;
       g.C = c_base + c_off[b];
       g.res = rns ? res_base + res_off[b] : nullptr;
-      g.row0 = f.row0;
+      // output row r < n_db is database row r, row r >= n_db is row n_db + row0 + (r - n_db)
+      g.n_db = P.a_rows ? ndb : 0;
+      g.row0 = P.a_rows ? P.row0 : ndb + P.row0;
       g.R_out = R_out[b];
       g.d3 = d3;
-      g.d3_pad = d3_pad[b];
+      g.d3_pad = d3_pad[P.owner];
       g.tile_begin = tiles;
       g.nz = nz;
       for (int zz = 0; zz < nz; ++zz) {
@@ -911,7 +975,6 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
     }
     tiles += rns ? rns_batched_tiles(d3, R_out[b], nz, planes) : i8_batched_tiles(variant, d3, R_out[b], nz);
     crt_e += ((int64_t)nz * ((d3 * R_out[b] + 3) / 4) + 255) / 256 * 256;  // the CRT's unit: 4 entries
-    z.xd_bytes += (size_t)nz * planes * D->KB * d3_pad[b] * kKB;
     // each problem's C and residues start at a multiple of 4 entries (the CRT's word loads and
     // 16-byte stores)
     z.c_elems += ((size_t)nz * d3 * R_out[b] + 3) / 4 * 4;
@@ -921,32 +984,48 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
   int64_t lift_e = 0, resc_e = 0;
   for (int i = 0; i < n; ++i) {
     const hfe_qct* Qc = static_cast<const hfe_qct*>(items[i].q);
-    const int b = gr.prob[i], level = Qc->level;
+    const int level = Qc->level;
     const int64_t d3 = Qc->d3;
-    const int64_t cols = d3 + (gr.last[b] == i ? d3_pad[b] - gr.d3[b] : 0);  // the last item writes the padding
+    const int a = gr.pa[i], bb = gr.pb[i];  // the A problem is the owner of the item's planes
+    const int64_t R_item = ndb + items[i].rows;
+    // the owner's last item also writes the padding columns (zeros)
+    const int64_t cols = d3 + (gr.p[a].last_item == i ? d3_pad[a] - (gr.ca[i] + d3) : 0);
     if (blob) {
       BatchLiftDesc& l = reinterpret_cast<BatchLiftDesc*>(blob + L.ld)[i];
       std::memset(&l, 0, sizeof(l));
       l.XT = Qc->XT.as<uint64_t>();
-      l.Xd = xd_base + xd_off[b];
+      l.Xd = xd_base + xd_off[a];
       l.d3 = d3;
-      l.c0 = gr.c0[i];
+      l.c0 = gr.ca[i];
       l.cols = cols;
-      l.d3_pad = d3_pad[b];
+      l.d3_pad = d3_pad[a];
       l.elem_begin = lift_e;
       l.la = make_lift_args(K, level);
       BatchRescaleDesc& r = reinterpret_cast<BatchRescaleDesc*>(blob + L.rd)[i];
       std::memset(&r, 0, sizeof(r));
-      r.C = c_base + c_off[b] + gr.c0[i] * R_out[b];
-      r.zstride = gr.d3[b] * R_out[b];
+      r.C = c_base + c_off[a] + gr.ca[i] * R_out[a];
+      r.Ra = R_out[a];
+      r.zstride = gr.p[a].d3 * R_out[a];
+      if (bb == a) {  // every row in the one problem
+        r.Cb = r.C;
+        r.Rb = r.Ra;
+        r.zstride_b = r.zstride;
+        r.split = R_item;
+      } else {
+        r.Cb = c_base + c_off[bb] + gr.cb[i] * R_out[bb];
+        r.Rb = R_out[bb];
+        r.zstride_b = gr.p[bb].d3 * R_out[bb];
+        r.split = ndb;
+      }
+      r.R_out = R_item;
       r.out = outs[i];
-      r.n = d3 * R_out[b];
+      r.n = d3 * R_item;
       r.elem_begin = resc_e;
       r.ra = make_rescale_args(K, level);
     }
     lift_e += (cols * D->KB * kKB + 255) / 256 * 256;
-    resc_e += (d3 * R_out[b] + 255) / 256 * 256;
-    z.out_elems += (size_t)level * d3 * R_out[b];
+    resc_e += (d3 * R_item + 255) / 256 * 256;
+    z.out_elems += (size_t)level * d3 * R_item;
     z.cols += d3;
   }
   if (blob) {
@@ -1007,7 +1086,6 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
     }
     a.KB = D->KB;
     a.R_pad = D->R_pad;
-    a.n_db = ndb;
     HFE_LAUNCH(launch_gemm_rns_batched(a, gemm_grid_for(form, 0), s));
     // by-slot constants: level L makes z index the database slot
     HFE_LAUNCH(launch_crt_rns_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.ch),
@@ -1021,7 +1099,6 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
     a.Dd = D->digits.as<int8_t>();
     a.KB = D->KB;
     a.R_pad = D->R_pad;
-    a.n_db = ndb;
     HFE_LAUNCH(launch_gemm_i8_batched(a, variant, gemm_grid_for(form, variant), s));
   }
   HFE_LAUNCH(launch_rescale_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.rh),
@@ -1041,11 +1118,9 @@ int choose_batch_variant(const hfe_db* D, const hfe_batch_item* items, int n, in
   auto padded = [&](int v) {
     const int64_t br = i8_variant_tile_rows(v), bq = i8_variant_tile_cols(v);
     double w = 0;
-    for (size_t b = 0; b < gr.first.size(); ++b) {
-      const hfe_batch_item& f = items[gr.first[b]];
-      const int64_t R = ndb + f.rows;
-      w += (double)(static_cast<const hfe_qct*>(f.q)->level + 1) * ((gr.d3[b] + bq - 1) / bq * bq) *
-           ((R + br - 1) / br * br);
+    for (const Problem& P : gr.p) {
+      const int64_t R = (P.a_rows ? ndb : 0) + P.rows;
+      w += (double)(P.level + 1) * ((P.d3 + bq - 1) / bq * bq) * ((R + br - 1) / br * br);
     }
     return w;
   };
@@ -1079,7 +1154,7 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
     return HFE_OK;
   }
   // all problems of one batch use one tile configuration
-  const BlobLayout L(n);
+  const BlobLayout L(n, max_problems(n));
   const BatchSizes sz0 = batch_fill(D, items, n, form, 0, nullptr, nullptr, nullptr, nullptr, nullptr, L);
   const int variant = form == HFE_FORM_I8_MFMA ? choose_batch_variant(D, items, n, sz0.max_level, sz0.cols / n) : 0;
   const hfe_keys* K = D->keys;
@@ -1164,12 +1239,15 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
   const int64_t ndb = 1ll << D->keys->P.log_n_db;
   const int64_t R_max = ndb + D->d1;
-  const int64_t cols_pad = max_cols + (int64_t)max_items * (qpad - 1);  // every item its own problem
+  // an owner problem pads at most qpad - 1 columns per item (two items at least when it also feeds
+  // split problems, which need up to 2 (qpad - 1))
+  const int64_t cols_pad = max_cols + (int64_t)max_items * (qpad - 1);
   P->xd_cap = (size_t)(max_level + 1) * planes * D->KB * cols_pad * kKB;
-  P->c_cap = (size_t)(max_level + 1) * max_cols * R_max + 4 * (size_t)max_items;  // + alignment of each problem
-  P->res_cap = rns ? (size_t)(max_level + 1) * planes * max_cols * R_max + 4 * (size_t)max_items : 0;
+  // + the alignment of each problem's start
+  P->c_cap = (size_t)(max_level + 1) * max_cols * R_max + 4 * (size_t)max_problems(max_items);
+  P->res_cap = rns ? (size_t)(max_level + 1) * planes * max_cols * R_max + 4 * (size_t)max_problems(max_items) : 0;
   P->out_cap = (size_t)max_level * max_cols * R_max;
-  const BlobLayout L(max_items);
+  const BlobLayout L(max_items, max_problems(max_items));
   P->blob_bytes = L.bytes;
   hfe_status st = P->ws_xd.alloc(P->xd_cap, nullptr);
   if (st == HFE_OK) st = P->ws_c.alloc(sizeof(uint64_t) * P->c_cap, nullptr);
@@ -1210,7 +1288,7 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
     if (static_cast<const hfe_qct*>(items[i].q)->level > P->max_level)
       return fail(HFE_ELEVEL, "item level above the plan's maximum");
   }
-  const BlobLayout L(P->max_items);
+  const BlobLayout L(P->max_items, max_problems(P->max_items));
   const BatchSizes sz = batch_fill(D, items, n, P->form, 0, nullptr, nullptr, nullptr, nullptr, nullptr, L);
   const int variant =
       P->form == HFE_FORM_I8_MFMA ? choose_batch_variant(D, items, n, sz.max_level, sz.cols / n) : 0;

@@ -256,4 +256,10 @@ __device__ __forceinline__ void rescale_element(const uint64_t* C, const uint64_
   }
 }
 
+// The same for an entry whose residues sit at src + z zstride (z = 0 .. level, p last).
+__device__ __forceinline__ void rescale_from(const uint64_t* src, int64_t zstride, const RescaleArgs& ra,
+                                             uint64_t* out, int64_t n, int64_t e) {
+  rescale_element(src - e, src - e + (int64_t)ra.level * zstride, n, ra, out, e, zstride);
+}
+
 }  // namespace hfe

@@ -287,7 +287,7 @@ struct RnsBatchArgs {
   int32_t n_mod, pad_;
   int32_t m[kRnsMaxMods];
   uint32_t magic[kRnsMaxMods];
-  int64_t KB, R_pad, n_db;
+  int64_t KB, R_pad;
 };
 int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod);
 hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, hipStream_t s);
@@ -325,7 +325,8 @@ struct BatchDesc {
   const int8_t* Xd;               // [nz][planes][KB][d3_pad][64] query planes of this problem
   uint64_t* C;                    // [nz][d3][R_out] contraction output
   uint8_t* res;                   // RNS form: [nz][n_mod][d3][R_out] residues by small modulus
-  int64_t row0, R_out, d3, d3_pad;
+  int64_t n_db, row0, R_out, d3;  // output row r < n_db: database row r; r >= n_db: n_db + row0 + (r - n_db)
+  int64_t d3_pad;                 // columns of the query planes Xd points into (their row stride)
   int64_t tile_begin;             // first tile of this problem in the launch (multiple of 8)
   int32_t nz, pad_;
   int32_t slot[kMaxPrimes];       // database prime slot of each z
@@ -341,7 +342,7 @@ struct BatchGemmArgs {
   uint32_t* next;                 // device, hdr->next
   const BatchDesc* desc;          // device, hdr->n entries
   const int8_t* Dd;               // database digits, all slots
-  int64_t KB, R_pad, n_db;
+  int64_t KB, R_pad;
 };
 int64_t i8_batched_tiles(int variant, int64_t d3, int64_t R_out, int nz);
 
@@ -385,7 +386,7 @@ hipError_t launch_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eye
                         uint64_t* qwords, uint64_t* dbwords, uint8_t* decision, uint8_t* col_any,
                         uint8_t* eye_match, hipStream_t s);
 
-constexpr int kMaxBatch = 256;                   // problems per batched launch
+constexpr int kMaxBatch = 256;                   // items per batched launch
 struct BatchElemHeader {
   int64_t total;                  // elements of the launch (chunks of 256 per problem start)
   int32_t n, pad_;
@@ -399,9 +400,14 @@ struct BatchLiftDesc {               // one per item
   LiftArgs la;
 };
 struct BatchRescaleDesc {            // one per item
-  const uint64_t* C;              // its problem's C + c0 R_out: prime z at C + z zstride
+  // Output row r < split of column c: C + z zstride + c Ra + r (its A problem's output); rows
+  // r >= split: Cb + z zstride_b + c Rb + (r - split) (its B problem's output; split = R_out and
+  // Cb = C when one problem holds all its rows)
+  const uint64_t* C;
+  const uint64_t* Cb;
   uint64_t* out;                  // [level][n]
-  int64_t n, zstride, elem_begin; // n = d3 x R_out of the item
+  int64_t n, R_out, elem_begin;   // n = d3 x R_out of the item
+  int64_t split, Ra, Rb, zstride, zstride_b;
   RescaleArgs ra;
 };
 struct BatchCrtDesc {                // RNS form, one per problem

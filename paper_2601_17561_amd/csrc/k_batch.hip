@@ -53,14 +53,18 @@ __global__ void __launch_bounds__(kChunk) k_rescale_batched(const BatchElemHeade
     const BatchRescaleDesc& p = d[b];
     const int64_t e = base + threadIdx.x - p.elem_begin;
     if (e >= p.n) continue;
-    rescale_element(p.C, p.C + (int64_t)p.ra.level * p.zstride, p.n, p.ra, p.out, e, p.zstride);
+    const int64_t c = e / p.R_out, r = e - c * p.R_out;
+    if (r < p.split)
+      rescale_from(p.C + c * p.Ra + r, p.zstride, p.ra, p.out, p.n, e);
+    else
+      rescale_from(p.Cb + c * p.Rb + (r - p.split), p.zstride_b, p.ra, p.out, p.n, e);
   }
 }
 
 // ra is indexed by database slot.
 __global__ void __launch_bounds__(kChunk) k_crt_rns_batched(const BatchElemHeader* hdr, const BatchCrtDesc* d,
                                                             RnsCrtArgs ra) {
-  __shared__ int64_t begins[kMaxBatch];
+  __shared__ int64_t begins[kMaxBatch + kMaxPrimes];  // one entry per problem (items + split levels)
   const int n = hdr->n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) begins[i] = d[i].elem_begin;
   __syncthreads();

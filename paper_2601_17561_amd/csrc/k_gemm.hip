@@ -515,7 +515,7 @@ k_gemm_i8_batched(BatchGemmArgs a) {
     const size_t planeX = (size_t)a.KB * d.d3_pad * kKB * kDigits;
     const size_t planeD = (size_t)a.KB * a.R_pad * kKB * kDigits;
     I8Tile T{d.Xd + z * planeX, a.Dd + d.slot[z] * planeD, d.C + (size_t)z * d.d3 * d.R_out, d.mod[z], a.KB,
-             a.R_pad, d.d3_pad, a.n_db, d.row0, d.R_out, d.d3, rt * BR, ct * BQ};
+             a.R_pad, d.d3_pad, d.n_db, d.row0, d.R_out, d.d3, rt * BR, ct * BQ};
     run_tile<WR, WQ, NBUF, WPE, MODE>(T, lds);
   }
 }

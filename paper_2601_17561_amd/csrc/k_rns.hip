@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_e
     RnsTile tl{d.Xd + ((size_t)z * a.n_mod + j) * a.KB * d.d3_pad * kKB,
                a.Dr + ((size_t)d.slot[z] * a.n_mod + j) * a.KB * a.R_pad * kKB,
                d.res + ((size_t)z * a.n_mod + j) * d.d3 * d.R_out, a.m[j], a.magic[j], a.KB, a.R_pad, d.d3_pad,
-               a.n_db, d.row0, d.R_out, d.d3, rt * kRnsTileR, ct * kRnsTileQ};
+               d.n_db, d.row0, d.R_out, d.d3, rt * kRnsTileR, ct * kRnsTileQ};
     rns_tile(tl, lds);
   }
 }
