@@ -138,7 +138,9 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
 /* Batched CCMM: item i is its own CCMM of items[i].q (any level, any column count) against the
  * database codes [items[i].row0, items[i].row0 + items[i].rows), all against one database.
  * Items with the same level and row range form one problem, their query columns side by side (so
- * only a problem pads its columns to whole tiles).  int8 forms (HFE_FORM_I8_MFMA, HFE_FORM_RNS_I8):
+ * only a problem pads its columns to whole tiles); a level whose items cover several row ranges is
+ * split into one problem over the N_DB A rows for all its columns and one problem per row range
+ * over that range's rows.  int8 forms (HFE_FORM_I8_MFMA, HFE_FORM_RNS_I8):
  * one grouped launch lifts and splits every item's query, ONE persistent launch computes the tiles
  * of every problem, prime (and small modulus) (workgroups claim tiles of a device-resident tile
  * table in order), for the RNS form one grouped launch reconstructs the residues mod each prime,
