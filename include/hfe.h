@@ -198,10 +198,16 @@ hfe_status hfe_autotune_load(const char* path);
  *   hfe_server_submit: q (its keys must be the server's; level <= max_level) stays borrowed
  *     until the ticket completes; ip_out: device int32 d3 x d1 (query-major) receives the
  *     decrypted inner products against every database code.
- *   hfe_server_poll: *state = 0 queued, 1 running, 2 done, or a negative status (rejected).
- *   hfe_server_wait: blocks until the ticket completes (HFE_EBUSY after timeout_ms, < 0: none).
+ *   hfe_server_poll: *state = 0 queued, 1 running, 2 done, or a negative status: HFE_EBUSY
+ *     (rejected as larger than one step, or still queued when the server was freed), another
+ *     status (its step failed).
+ *   hfe_server_wait: blocks until the ticket is done (HFE_OK) or failed (its negative status),
+ *     at most timeout_ms (< 0: no limit; then HFE_EBUSY, and hfe_server_poll tells a timeout,
+ *     state 0 or 1, from a rejection).
  *   hfe_server_stats: counts and latencies (arrival -> result ready; admission -> ready) of the
- *     requests completed since creation or the last reset. */
+ *     requests completed since creation or the last reset.
+ *   hfe_server_reset_stats: clears the statistics and forgets finished requests (their tickets
+ *     become unknown); the server keeps every finished request until then. */
 typedef struct hfe_server hfe_server;
 typedef struct {
   int64_t submitted, completed, rejected, steps, max_queue;

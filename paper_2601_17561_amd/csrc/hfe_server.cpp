@@ -303,14 +303,21 @@ hfe_status hfe_server_wait(hfe_server* srv, uint64_t ticket, int64_t timeout_ms)
   hfe_server* S = as_server(srv);
   if (!S) return fail(HFE_EINVAL, "invalid server");
   std::unique_lock<std::mutex> l(S->mu);
-  auto it = S->reqs.find(ticket);
-  if (it == S->reqs.end()) return fail(HFE_EINVAL, "unknown ticket");
-  auto ready = [&] { return it->second.state == 2 || it->second.state < 0; };
+  if (S->reqs.find(ticket) == S->reqs.end()) return fail(HFE_EINVAL, "unknown ticket");
+  // looked up afresh on every wake-up: submissions may rehash the table while this thread waits,
+  // and hfe_server_reset_stats may drop finished requests
+  int state = 0;
+  auto ready = [&] {
+    auto it = S->reqs.find(ticket);
+    state = it == S->reqs.end() ? 2 : it->second.state;
+    return state == 2 || state < 0;
+  };
   if (timeout_ms < 0)
     S->cv.wait(l, ready);
   else if (!S->cv.wait_for(l, std::chrono::milliseconds(timeout_ms), ready))
     return fail(HFE_EBUSY, "timed out");
-  if (it->second.state < 0) return fail(it->second.state, "request rejected: larger than one step");
+  if (state == HFE_EBUSY) return fail(HFE_EBUSY, "request rejected: larger than one step, or the server stopped");
+  if (state < 0) return fail(state, "the request's step failed");
   return HFE_OK;
 }
 
