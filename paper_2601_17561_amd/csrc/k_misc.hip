@@ -142,29 +142,40 @@ hipError_t launch_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, cons
 // y residues [level][n] -> Y centered in (-Q/2, Q/2) as a 320-bit two's complement integer,
 // ip = floor(Y / 2^s + 1/2) and v = Y / 2^s.
 __global__ void k_decode(const uint64_t* y, int64_t n, DecodeArgs da, double* v, int32_t* ip) {
+  // every array below is indexed by compile-time constants (loops unrolled to the maximum level,
+  // guarded by the actual one), so it stays in registers
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t r[HFE_MAX_QPRIMES], g[HFE_MAX_QPRIMES];
-    for (int i = 0; i < da.level; ++i) r[i] = y[(int64_t)i * n + e];
+    uint64_t r[HFE_MAX_QPRIMES] = {}, g[HFE_MAX_QPRIMES] = {};
+#pragma unroll
+    for (int i = 0; i < HFE_MAX_QPRIMES; ++i)
+      if (i < da.level) r[i] = y[(int64_t)i * n + e];
     garner_digits(r, da.level, da.garner, da.q, da.mu, g);
     // Horner: Y = g_{l-1}; Y = Y * q_i + g_i for i = l-2 .. 0 (5 words, little endian)
-    uint64_t w[5] = {g[da.level - 1], 0, 0, 0, 0};
-    for (int i = da.level - 2; i >= 0; --i) {
+    uint64_t w[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < HFE_MAX_QPRIMES; ++i)
+      if (i == da.level - 1) w[0] = g[i];
+#pragma unroll
+    for (int i = HFE_MAX_QPRIMES - 2; i >= 0; --i) {
+      if (i > da.level - 2) continue;
       uint64_t carry = g[i];
+#pragma unroll
       for (int j = 0; j < 5; ++j) {
         const uint64_t lo = w[j] * da.q[i];
         const uint64_t hi = mulhi64(w[j], da.q[i]);
-        const uint64_t s = lo + carry;
-        carry = hi + (s < lo ? 1 : 0);
-        w[j] = s;
+        const uint64_t sm = lo + carry;
+        carry = hi + (sm < lo ? 1 : 0);
+        w[j] = sm;
       }
     }
     if (above_half(g, da.half_digits, da.level)) {  // Y -= Q
       uint64_t borrow = 0;
+#pragma unroll
       for (int j = 0; j < 5; ++j) {
-        const uint64_t a = w[j], b = da.Qw[j];
-        const uint64_t d = a - b - borrow;
-        borrow = (a < b || (a == b && borrow)) ? 1 : 0;
+        const uint64_t x = w[j], q = da.Qw[j];
+        const uint64_t d = x - q - borrow;
+        borrow = (x < q || (x == q && borrow)) ? 1 : 0;
         w[j] = d;
       }
     }
@@ -173,32 +184,40 @@ __global__ void k_decode(const uint64_t* y, int64_t n, DecodeArgs da, double* v,
     uint64_t m[5];
     if (neg) {
       uint64_t carry = 1;
+#pragma unroll
       for (int j = 0; j < 5; ++j) {
         m[j] = ~w[j] + carry;
         carry = (carry && m[j] == 0) ? 1 : 0;
       }
     } else {
+#pragma unroll
       for (int j = 0; j < 5; ++j) m[j] = w[j];
     }
     double mag = 0.0;
+#pragma unroll
     for (int j = 4; j >= 0; --j) mag = mag * 18446744073709551616.0 + (double)m[j];
     if (v) v[e] = ldexp(neg ? -mag : mag, -da.delta_log);
     // ip = (Y + 2^(s-1)) >> s, arithmetic
     const int s = da.delta_log;
-    uint64_t add[5] = {0, 0, 0, 0, 0};
-    if (s > 0) add[(s - 1) >> 6] = 1ull << ((s - 1) & 63);
+    const int aw = (s - 1) >> 6;
     uint64_t carry = 0;
+#pragma unroll
     for (int j = 0; j < 5; ++j) {
-      const uint64_t a = w[j] + add[j];
-      const uint64_t c1 = a < w[j] ? 1 : 0;
-      const uint64_t b = a + carry;
-      const uint64_t c2 = b < a ? 1 : 0;
-      w[j] = b;
+      const uint64_t add = (s > 0 && j == aw) ? 1ull << ((s - 1) & 63) : 0;
+      const uint64_t x = w[j] + add;
+      const uint64_t c1 = x < w[j] ? 1 : 0;
+      const uint64_t b2 = x + carry;
+      const uint64_t c2 = b2 < x ? 1 : 0;
+      w[j] = b2;
       carry = c1 | c2;
     }
     const int wi = s >> 6, bi = s & 63;
-    uint64_t lo = w[wi] >> bi;
-    if (bi && wi + 1 < 5) lo |= w[wi + 1] << (64 - bi);
+    uint64_t lo = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      if (j == wi) lo |= w[j] >> bi;
+      if (bi && j == wi + 1) lo |= w[j] << (64 - bi);
+    }
     ip[e] = (int32_t)(uint32_t)lo;
   }
 }
