@@ -32,9 +32,9 @@ import hfe_synth as S  # noqa: E402
 
 PEAK_I8_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 # Bytes beyond L2 per launch of the contraction on the share workload (d3 = 512), from rocprofv3
-# FETCH_SIZE + WRITE_SIZE scaled by a 1 GiB copy (profiles/pmc_k_gemm_i8_dma_q128_r128_share_q512.md);
-# reported only for the kernels they were taken on.
-MEASURED_TRAFFIC_GB = {"dma_q128_w2": 28.3, "dma_r128_w2": 30.4}
+# FETCH_SIZE + WRITE_SIZE scaled by a 1 GiB copy (profiles/pmc_k_gemm_i8_dma_q128_r128_share_q512.md,
+# profiles/pmc_k_gemm_i8_dma2_w2_share_q512.md); reported only for the kernels they were taken on.
+MEASURED_TRAFFIC_GB = {"dma_q128_w2": 28.3, "dma_r128_w2": 30.4, "dma2_w2": 90.1}
 KEY_SEED, DB_SEED, Q_SEED = 11, 22, 33
 
 
