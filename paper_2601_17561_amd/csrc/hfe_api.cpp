@@ -675,7 +675,8 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(launch_gemm_plain(g, s));
   } else if (form == HFE_FORM_RNS_I8) {
     const int n = D->n_rns;
-    const int64_t d3_pad = (d3 + kRnsTileQ - 1) / kRnsTileQ * kRnsTileQ;  // whole query tiles
+    const int tq = rns_tile_q(&d3, &R_out, &nz, 1);  // query tile width by padded work
+    const int64_t d3_pad = (d3 + tq - 1) / tq * tq;   // whole query tiles
     const size_t planeX = (size_t)D->KB * d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
     HFE_TRY(Xd.alloc((size_t)nz * n * planeX, s));
@@ -703,7 +704,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     rg.d3 = d3;
     rg.d3_pad = d3_pad;
     HFE_LAUNCH(mark(1));
-    HFE_LAUNCH(launch_gemm_rns(rg, s));
+    HFE_LAUNCH(launch_gemm_rns(rg, tq, s));
     HFE_LAUNCH(launch_crt_rns(res.as<uint8_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), C.as<uint64_t>(), s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
@@ -926,6 +927,18 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
   std::vector<char> feeds(np, 0);  // owners whose planes split problems also read
   for (int b = 0; b < np; ++b)
     if (gr.p[b].owner != b) feeds[gr.p[b].owner] = 1;
+  for (int b = 0; b < np; ++b) R_out[b] = (gr.p[b].a_rows ? ndb : 0) + gr.p[b].rows;
+  // RNS form: each problem's query tile width by its own padded work; the 256-column problems come
+  // first in the tables (one launch each width).  Owners' planes are padded for the widest tiles.
+  std::vector<int> tq(np, 0), ord(np);
+  for (int b = 0; b < np; ++b) {
+    ord[b] = b;
+    if (rns) {
+      const int nzb = gr.p[b].level + 1;
+      tq[b] = rns_tile_q(&gr.p[b].d3, &R_out[b], &nzb, 1);
+    }
+  }
+  if (rns) std::stable_partition(ord.begin(), ord.end(), [&](int b) { return tq[b] == 256; });
   // query planes of the owners: whole tiles, and for an owner that feeds split problems room for
   // their last tile, which may reach qpad - 1 columns past the owner's columns
   for (int b = 0; b < np; ++b) {
@@ -935,16 +948,17 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
     xd_off[b] = z.xd_bytes;
     z.xd_bytes += (size_t)(P.level + 1) * planes * D->KB * d3_pad[b] * kKB;
   }
-  int64_t tiles = 0, crt_e = 0;
-  for (int b = 0; b < np; ++b) {
+  int64_t tiles = 0, crt_e = 0, tiles_wide = 0;
+  int n_wide = 0;
+  for (int k = 0; k < np; ++k) {
+    const int b = ord[k];  // table position k
     const Problem& P = gr.p[b];
     const int level = P.level, nz = level + 1;
     const int64_t d3 = P.d3;
-    R_out[b] = (P.a_rows ? ndb : 0) + P.rows;
     c_off[b] = z.c_elems;
     res_off[b] = z.res_elems;
     if (blob) {
-      BatchDesc& g = reinterpret_cast<BatchDesc*>(blob + L.gd)[b];
+      BatchDesc& g = reinterpret_cast<BatchDesc*>(blob + L.gd)[k];
       std::memset(&g, 0, sizeof(g));
       g.Xd = xd_base + xd_off[P.owner] + P.xc0 * kKB;
       g.C = c_base + c_off[b];
@@ -962,7 +976,7 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
         g.mod[zz] = K->mods[g.slot[zz]];
       }
       if (rns) {
-        BatchCrtDesc& c = reinterpret_cast<BatchCrtDesc*>(blob + L.cd)[b];
+        BatchCrtDesc& c = reinterpret_cast<BatchCrtDesc*>(blob + L.cd)[k];
         std::memset(&c, 0, sizeof(c));
         c.res = g.res;
         c.C = g.C;
@@ -973,7 +987,11 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
         c.pslot = K->L;
       }
     }
-    tiles += rns ? rns_batched_tiles(d3, R_out[b], nz, planes) : i8_batched_tiles(variant, d3, R_out[b], nz);
+    tiles += rns ? rns_batched_tiles(d3, R_out[b], nz, planes, tq[b]) : i8_batched_tiles(variant, d3, R_out[b], nz);
+    if (rns && tq[b] == 256) {
+      tiles_wide = tiles;
+      n_wide = k + 1;
+    }
     crt_e += ((int64_t)nz * ((d3 * R_out[b] + 3) / 4) + 255) / 256 * 256;  // the CRT's unit: 4 entries
     // each problem's C and residues start at a multiple of 4 entries (the CRT's word loads and
     // 16-byte stores)
@@ -1032,6 +1050,8 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
     BatchHeader* gh = reinterpret_cast<BatchHeader*>(blob + L.gh);
     gh->total_tiles = tiles;
     gh->n = np;
+    gh->tiles_wide = rns ? tiles_wide : tiles;
+    gh->n_wide = rns ? n_wide : np;
     BatchElemHeader* lh = reinterpret_cast<BatchElemHeader*>(blob + L.lh);
     lh->total = lift_e;
     lh->n = n;
@@ -1059,7 +1079,8 @@ int device_cus() {
 }
 
 int gemm_grid_for(int form, int variant) {
-  const int g = device_cus() * (form == HFE_FORM_RNS_I8 ? rns_wgs_per_cu() : i8_variant_wgs_per_cu(variant));
+  // RNS form: variant is the query tile width (256 or 128)
+  const int g = device_cus() * (form == HFE_FORM_RNS_I8 ? rns_wgs_per_cu(variant) : i8_variant_wgs_per_cu(variant));
   return (g + kXcds - 1) / kXcds * kXcds;
 }
 constexpr int kElemGrid = 4096;
@@ -1077,6 +1098,7 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
     std::memset(&a, 0, sizeof(a));
     a.hdr = hdr;
     a.next = const_cast<uint32_t*>(hdr->next);
+    a.next_narrow = const_cast<uint32_t*>(hdr->next_narrow);
     a.desc = reinterpret_cast<const BatchDesc*>(dblob + L.gd);
     a.Dr = D->rns.as<int8_t>();
     a.n_mod = D->n_rns;
@@ -1086,7 +1108,9 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
     }
     a.KB = D->KB;
     a.R_pad = D->R_pad;
-    HFE_LAUNCH(launch_gemm_rns_batched(a, gemm_grid_for(form, 0), s));
+    // the 256-column problems, then the 128-column ones (either launch may find no tiles)
+    HFE_LAUNCH(launch_gemm_rns_batched(a, gemm_grid_for(form, 256), 256, s));
+    HFE_LAUNCH(launch_gemm_rns_batched(a, gemm_grid_for(form, 128), 128, s));
     // by-slot constants: level L makes z index the database slot
     HFE_LAUNCH(launch_crt_rns_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.ch),
                                       reinterpret_cast<const BatchCrtDesc*>(dblob + L.cd),
@@ -1126,6 +1150,7 @@ int choose_batch_variant(const hfe_db* D, const hfe_batch_item* items, int n, in
   };
   return padded(kDefaultI8Variant) < padded(tuned) ? kDefaultI8Variant : tuned;
 }
+
 }  // namespace
 
 extern "C" {

@@ -259,7 +259,10 @@ struct RnsGemmArgs {
   uint8_t* res;                                // [nz][n_mod][d3][R_out], residues < m_j <= 256
   int64_t KB, R_pad, n_db, row0, R_out, d3, d3_pad;
 };
-hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s);
+// tq: query columns of the workgroup tile, 128 or 256 (g.d3_pad a multiple of it)
+hipError_t launch_gemm_rns(const RnsGemmArgs& g, int tq, hipStream_t s);
+// the tile width with less padded work for problems of d3 columns, R_out rows and nz prime slots
+int rns_tile_q(const int64_t* d3, const int64_t* R_out, const int* nz, int n);
 struct RnsCrtArgs {
   int n;                                       // moduli in use
   int32_t m[kRnsMaxMods];
@@ -272,16 +275,18 @@ struct RnsCrtArgs {
 };
 hipError_t launch_crt_rns(const uint8_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
                           hipStream_t s);
-constexpr int kRnsTileR = 256, kRnsTileQ = 256;  // workgroup tile of the RNS contraction
+constexpr int kRnsTileR = 256, kRnsTileQ = 256;  // RNS workgroup tile: rows, widest query columns
 struct BatchDesc;
 struct BatchHeader;
 struct BatchElemHeader;
 struct BatchCrtDesc;
 // Batched RNS contraction: problem b's tiles are [tile_begin, tile_begin + rns_batched_tiles(...)),
-// ordered (z, modulus, XCD-ordered tile); workgroups claim tiles per XCD as the digit form's.
+// ordered (z, modulus, XCD-ordered tile); workgroups claim tiles per XCD as the digit form's.  The
+// launch with tq = 256 serves problems [0, hdr->n_wide), the one with tq = 128 the others.
 struct RnsBatchArgs {
   const BatchHeader* hdr;
-  uint32_t* next;
+  uint32_t* next;                              // hdr->next (256-column tiles)
+  uint32_t* next_narrow;                       // hdr->next_narrow (128-column tiles)
   const BatchDesc* desc;
   const int8_t* Dr;                            // database planes, all slots: [slot][n_mod][KB][R_pad][64]
   int32_t n_mod, pad_;
@@ -289,12 +294,12 @@ struct RnsBatchArgs {
   uint32_t magic[kRnsMaxMods];
   int64_t KB, R_pad;
 };
-int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod);
-hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, hipStream_t s);
+int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod, int tq);
+hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, int tq, hipStream_t s);
 // ra indexed by database slot (mod, Mj_mod_q, M_mod_q of slot z at [z])
 hipError_t launch_crt_rns_batched(const BatchElemHeader* hdr, const BatchCrtDesc* d, const RnsCrtArgs& ra,
                                   int grid, hipStream_t s);
-int rns_wgs_per_cu();
+int rns_wgs_per_cu(int tq);
 
 // Plain uint64 contraction.  For each prime slot z < nz: C[z][c][r] = sum_k Dt[z][k][src(r)] *
 // X[z][c][k] mod prime, rows r < R_out mapped to source rows (A-part then the shard).
@@ -336,6 +341,11 @@ struct BatchHeader {
   int64_t total_tiles;            // multiple of kXcds
   int32_t n, pad_;
   uint32_t next[kXcds];           // tiles claimed per XCD; zero in every uploaded table
+  // RNS form: problems [0, n_wide) use 256-column query tiles (tiles [0, tiles_wide)), the rest
+  // 128-column tiles, claimed by a second launch through next_narrow
+  uint32_t next_narrow[kXcds];
+  int64_t tiles_wide;
+  int32_t n_wide, pad2_;
 };
 struct BatchGemmArgs {
   const BatchHeader* hdr;         // device

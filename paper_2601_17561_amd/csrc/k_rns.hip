@@ -62,22 +62,31 @@ hipError_t launch_lift_rns(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB
 }
 
 // ------------------------------------------------------------------ contraction per modulus
-// Workgroup: 4 x 2 waves (two per SIMD) on 256 database rows x 256 query columns of one (prime,
-// modulus); wave (wq, wr) owns 64 query columns x 128 rows as 2 x 4 blocks of 32 x 32 with one
-// int32 accumulator each (v_mfma_i32_32x32x32_i8), so each fragment read from LDS feeds 2 or 4
-// MFMAs.  One 64-byte K-block of both operands per LDS stage (32 KiB), four stages fed by direct
-// global-to-LDS loads (same row swizzle as the digit form's DMA tiles), so up to three K-blocks
-// are in flight while one is multiplied (three stages measured 6% slower, five no faster).
+// Workgroup tile: 256 database rows x TQ query columns of one (prime, modulus).  Each wave owns 64
+// query columns x 128 rows as 2 x 4 blocks of 32 x 32 with one int32 accumulator each
+// (v_mfma_i32_32x32x32_i8), so each fragment read from LDS feeds 2 or 4 MFMAs.  One 64-byte K-block
+// of both operands per LDS stage, fed by direct global-to-LDS loads (same row swizzle as the digit
+// form's DMA tiles).
+//   TQ = 256: 4 x 2 waves (two per SIMD), four stages of 32 KiB, one workgroup per CU; up to three
+//     K-blocks are in flight while one is multiplied (three stages measured 6% slower, five no faster).
+//   TQ = 128: 2 x 2 waves, three stages of 24 KiB, two workgroups per CU.  About 9% slower per
+//     column than TQ = 256, but it pads query columns to 128 instead of 256; the host picks the
+//     width per call or batch by padded work.
 // Exactness: |S| over the K-range <= K * 128 * 128 < 2^31 for K < 2^17 (checked by the host).
-constexpr int kRnsWQB = 2, kRnsWRB = 4, kRnsWPE = 2;  // 32 x 32 blocks per wave; waves per SIMD
-constexpr int kRnsNQ = kRnsTileQ / (32 * kRnsWQB), kRnsNR = kRnsTileR / (32 * kRnsWRB);
-constexpr int kRnsNW = kRnsNQ * kRnsNR, kRnsStages = 4;
-static_assert(kRnsStages >= 3 && kRnsStages <= 5, "the K-block wait handles three to five stages");
-constexpr int kRnsPA = kRnsTileQ * kKB, kRnsPB = kRnsTileR * kKB, kRnsStage = kRnsPA + kRnsPB;
-constexpr int kRnsLA = kRnsTileQ / 16 / kRnsNW, kRnsLB = kRnsTileR / 16 / kRnsNW;  // loads per wave per K-block
-constexpr int kRnsVm = (kRnsLA + kRnsLB) * (kRnsStages - 2);  // loads a wave may leave in flight at a K-block wait
-static_assert(kRnsTileQ % (16 * kRnsNW) == 0 && kRnsTileR % (16 * kRnsNW) == 0, "whole loads per wave");
-
+template <int TQ>
+struct RnsCfg {
+  static_assert(TQ == 128 || TQ == 256, "query tile of 128 or 256 columns");
+  static constexpr int WQB = 2, WRB = 4, WPE = 2;  // 32 x 32 blocks per wave; waves per SIMD
+  static constexpr int TR = kRnsTileR;
+  static constexpr int NQ = TQ / (32 * WQB), NR = TR / (32 * WRB), NW = NQ * NR;
+  static constexpr int STAGES = TQ == 256 ? 4 : 3;
+  static constexpr int PA = TQ * kKB, PB = TR * kKB, STAGE = PA + PB;
+  static constexpr int LA = TQ / 16 / NW, LB = TR / 16 / NW;  // loads per wave per K-block
+  static constexpr int VM = (LA + LB) * (STAGES - 2);         // loads a wave may leave in flight at a wait
+  static constexpr int LDS = STAGES * STAGE;
+  static_assert(TQ % (16 * NW) == 0 && TR % (16 * NW) == 0, "whole loads per wave");
+  static_assert(STAGES >= 3, "the K-block wait leaves STAGES - 2 blocks in flight");
+};
 
 // One output tile (rows r0.., query columns c0..) of one (prime, modulus) product: X and D are that
 // modulus' query and database planes, res its residue plane [d3][R_out].
@@ -90,85 +99,84 @@ struct RnsTile {
   int64_t KB, R_pad, d3_pad, n_db, row0, R_out, d3, r0, c0;
 };
 
+// this wave's loads of the oldest outstanding K-block have landed (the younger ones may still fly)
+// and its LDS reads are done; then the same for every wave
+template <int VM>
+__device__ __forceinline__ void rns_wait_block() {
+  static_assert(VM == 4 || VM == 6 || VM == 8 || VM == 12, "no K-block wait for this tile shape");
+  if constexpr (VM == 4)
+    asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else if constexpr (VM == 6)
+    asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else if constexpr (VM == 8)
+    asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else
+    asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int TQ>
 __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
+  using C = RnsCfg<TQ>;
   const int64_t r0 = g.r0, c0 = g.c0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wq = wave % kRnsNQ, wr = wave / kRnsNQ;
+  const int wq = wave % C::NQ, wr = wave / C::NQ;
   const int8_t* X = g.X;
   const int8_t* D = g.D;
   const size_t stepA = (size_t)g.d3_pad * kKB, stepB = (size_t)g.R_pad * kKB;
-  // load i of a wave fills tile rows 16 (wave + 4 i) .. + 15 (lane l: row + l / 4, stored chunk
+  // load i of a wave fills tile rows 16 (wave + NW i) .. + 15 (lane l: row + l / 4, stored chunk
   // l % 4 holding logical chunk (l % 4) ^ ((row >> 2) & 3))
   const int ld_row = 16 * wave + (lane >> 2);
   const int ld_chunk = ((lane & 3) ^ ((ld_row >> 2) & 3)) * 16;
-  const int8_t* gA[kRnsLA];
-  const int8_t* gB[kRnsLB];
+  const int8_t* gA[C::LA];
+  const int8_t* gB[C::LB];
 #pragma unroll
-  for (int i = 0; i < kRnsLA; ++i) gA[i] = X + (size_t)(c0 + ld_row + 16 * kRnsNW * i) * kKB + ld_chunk;
+  for (int i = 0; i < C::LA; ++i) gA[i] = X + (size_t)(c0 + ld_row + 16 * C::NW * i) * kKB + ld_chunk;
 #pragma unroll
-  for (int i = 0; i < kRnsLB; ++i)
-    gB[i] = D + (size_t)src_row(r0 + ld_row + 16 * kRnsNW * i, g.n_db, g.row0) * kKB + ld_chunk;
+  for (int i = 0; i < C::LB; ++i)
+    gB[i] = D + (size_t)src_row(r0 + ld_row + 16 * C::NW * i, g.n_db, g.row0) * kKB + ld_chunk;
   const uint32_t lds0 = (uint32_t)(uintptr_t)lds + wave * 16 * kKB;
   auto issue = [&](int stage, int64_t kb) {
-    const uint32_t base = lds0 + stage * kRnsStage;
+    const uint32_t base = lds0 + stage * C::STAGE;
 #pragma unroll
-    for (int i = 0; i < kRnsLA; ++i) dma16(gA[i] + kb * stepA, base + 16 * kRnsNW * i * kKB);
+    for (int i = 0; i < C::LA; ++i) dma16(gA[i] + kb * stepA, base + 16 * C::NW * i * kKB);
 #pragma unroll
-    for (int i = 0; i < kRnsLB; ++i) dma16(gB[i] + kb * stepB, base + kRnsPA + 16 * kRnsNW * i * kKB);
+    for (int i = 0; i < C::LB; ++i) dma16(gB[i] + kb * stepB, base + C::PA + 16 * C::NW * i * kKB);
   };
   const int sw = ((lane & 31) >> 2) & 3, cl = lane >> 5;
-  const int offA = (wq * 32 * kRnsWQB + (lane & 31)) * kKB;
-  const int offB = kRnsPA + (wr * 32 * kRnsWRB + (lane & 31)) * kKB;
-  v16i acc[kRnsWQB][kRnsWRB];
+  const int offA = (wq * 32 * C::WQB + (lane & 31)) * kKB;
+  const int offB = C::PA + (wr * 32 * C::WRB + (lane & 31)) * kKB;
+  v16i acc[C::WQB][C::WRB];
 #pragma unroll
-  for (int a = 0; a < kRnsWQB; ++a)
+  for (int a = 0; a < C::WQB; ++a)
 #pragma unroll
-    for (int b = 0; b < kRnsWRB; ++b) acc[a][b] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < C::WRB; ++b) acc[a][b] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t KB = g.KB;
   auto clamp = [&](int64_t i) { return i < KB ? i : KB - 1; };
   // fragments of one half (32 bytes of K) of the K-block in stage st
-  auto read_half = [&](int st, int h, v4i (&fa)[kRnsWQB], v4i (&fb)[kRnsWRB]) {
-    const int8_t* S = lds + st * kRnsStage;
+  auto read_half = [&](int st, int h, v4i (&fa)[C::WQB], v4i (&fb)[C::WRB]) {
+    const int8_t* S = lds + st * C::STAGE;
     const int chunk = ((cl + 2 * h) ^ sw) << 4;
 #pragma unroll
-    for (int a = 0; a < kRnsWQB; ++a) fa[a] = *reinterpret_cast<const v4i*>(S + offA + a * 32 * kKB + chunk);
+    for (int a = 0; a < C::WQB; ++a) fa[a] = *reinterpret_cast<const v4i*>(S + offA + a * 32 * kKB + chunk);
 #pragma unroll
-    for (int b = 0; b < kRnsWRB; ++b) fb[b] = *reinterpret_cast<const v4i*>(S + offB + b * 32 * kKB + chunk);
+    for (int b = 0; b < C::WRB; ++b) fb[b] = *reinterpret_cast<const v4i*>(S + offB + b * 32 * kKB + chunk);
   };
-  auto mma = [&](const v4i (&fa)[kRnsWQB], const v4i (&fb)[kRnsWRB]) {
+  auto mma = [&](const v4i (&fa)[C::WQB], const v4i (&fb)[C::WRB]) {
 #pragma unroll
-    for (int a = 0; a < kRnsWQB; ++a)
+    for (int a = 0; a < C::WQB; ++a)
 #pragma unroll
-      for (int b = 0; b < kRnsWRB; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
-  };
-  // this wave's loads of the oldest outstanding K-block have landed (the S - 2 younger ones may
-  // still fly) and its LDS reads are done; then the same for every wave
-  auto wait_block = [] {
-    static_assert(kRnsVm == 4 || kRnsVm == 6 || kRnsVm == 8 || kRnsVm == 12 || kRnsVm == 16 || kRnsVm == 24,
-                  "no K-block wait for this tile shape");
-    if constexpr (kRnsVm == 4)
-      asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else if constexpr (kRnsVm == 6)
-      asm volatile("s_waitcnt vmcnt(6) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else if constexpr (kRnsVm == 8)
-      asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else if constexpr (kRnsVm == 12)
-      asm volatile("s_waitcnt vmcnt(12) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else if constexpr (kRnsVm == 16)
-      asm volatile("s_waitcnt vmcnt(16) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    else
-      asm volatile("s_waitcnt vmcnt(24) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      for (int b = 0; b < C::WRB; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
   };
   // Software pipeline: the fragments of half 0 of block i are in registers when iteration i
   // starts; half 1 is read while half 0 multiplies, and half 0 of block i + 1 while half 1
   // multiplies, so LDS latency hides behind the MFMAs.  The barrier sits between the halves:
   // after it block i + 1 is in LDS and no wave reads block i's stage any more, which then
-  // receives block i + S.
+  // receives block i + STAGES.
 #pragma unroll
-  for (int st = 0; st < kRnsStages - 1; ++st) issue(st, clamp(st));
-  wait_block();
-  issue(kRnsStages - 1, clamp(kRnsStages - 1));
-  v4i f0a[kRnsWQB], f0b[kRnsWRB], f1a[kRnsWQB], f1b[kRnsWRB];
+  for (int st = 0; st < C::STAGES - 1; ++st) issue(st, clamp(st));
+  rns_wait_block<C::VM>();
+  issue(C::STAGES - 1, clamp(C::STAGES - 1));
+  v4i f0a[C::WQB], f0b[C::WRB], f1a[C::WQB], f1b[C::WRB];
   read_half(0, 0, f0a, f0b);
   // settle every outstanding LDS and scalar load here, so that the compiler's wait analysis
   // enters the loop with LDS reads only and waits for the older half alone inside it
@@ -179,9 +187,9 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
     __builtin_amdgcn_sched_barrier(0);
     mma(f0a, f0b);
     __builtin_amdgcn_sched_barrier(0);
-    wait_block();
-    issue(cur, clamp(i + kRnsStages));
-    cur = cur + 1 == kRnsStages ? 0 : cur + 1;
+    rns_wait_block<C::VM>();
+    issue(cur, clamp(i + C::STAGES));
+    cur = cur + 1 == C::STAGES ? 0 : cur + 1;
     read_half(cur, 0, f0a, f0b);  // block i + 1 (a landed duplicate of the last block at the end)
     __builtin_amdgcn_sched_barrier(0);
     mma(f1a, f1b);
@@ -198,14 +206,14 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
   const uint32_t off = (uint32_t)m - mod_small(mod_small(1u << 15, (uint32_t)m, magic) * t16, (uint32_t)m, magic);
   uint8_t* res = g.res;
 #pragma unroll
-  for (int b = 0; b < kRnsWRB; ++b) {
-    const int64_t r = r0 + wr * 32 * kRnsWRB + b * 32 + (lane & 31);
+  for (int b = 0; b < C::WRB; ++b) {
+    const int64_t r = r0 + wr * 32 * C::WRB + b * 32 + (lane & 31);
     if (r >= g.R_out) continue;
 #pragma unroll
-    for (int a = 0; a < kRnsWQB; ++a)
+    for (int a = 0; a < C::WQB; ++a)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int64_t c = c0 + wq * 32 * kRnsWQB + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        const int64_t c = c0 + wq * 32 * C::WQB + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         if (c >= g.d3) continue;
         const uint32_t u = (uint32_t)acc[a][b][e] + 0x80000000u;  // acc + 2^31 >= 0
         const uint32_t v = mod_small((u >> 17) * t17 + (u & 0x1FFFF) + off, (uint32_t)m, magic);
@@ -214,42 +222,52 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
   }
 }
 
-__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(kRnsWPE, kRnsWPE))) k_gemm_rns(RnsGemmArgs g) {
-  __shared__ __attribute__((aligned(16))) int8_t lds[kRnsStages * kRnsStage];
+template <int TQ>
+__global__ void __launch_bounds__(64 * RnsCfg<TQ>::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_gemm_rns(RnsGemmArgs g) {
+  using C = RnsCfg<TQ>;
+  __shared__ __attribute__((aligned(16))) int8_t lds[C::LDS];
   const int j = blockIdx.y, z = blockIdx.z;
-  const int64_t n_ct = (g.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (g.R_out + kRnsTileR - 1) / kRnsTileR;
+  const int64_t n_ct = (g.d3 + TQ - 1) / TQ, n_rt = (g.R_out + C::TR - 1) / C::TR;
   const int64_t l = blockIdx.x, xcd = l % kXcds, jj = l / kXcds;
   const int64_t rt = (jj / n_ct) * kXcds + xcd, ct = jj % n_ct;
   if (rt >= n_rt) return;
   RnsTile t{g.Xr[z] + (size_t)j * g.KB * g.d3_pad * kKB, g.Dr[z] + (size_t)j * g.KB * g.R_pad * kKB,
             g.res + ((size_t)z * g.n_mod + j) * g.d3 * g.R_out, g.m[j], g.magic[j], g.KB, g.R_pad, g.d3_pad, g.n_db,
-            g.row0, g.R_out, g.d3, rt * kRnsTileR, ct * kRnsTileQ};
-  rns_tile(t, lds);
+            g.row0, g.R_out, g.d3, rt * C::TR, ct * TQ};
+  rns_tile<TQ>(t, lds);
 }
 
 // Persistent batched form: problem b's tiles are ordered (z, modulus, XCD-ordered tile), starting at
 // its tile_begin; workgroups claim tiles in order from one counter per XCD (tile t = 8 j + xcd), as
 // the digit form's batched kernel.
-__global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_eu(kRnsWPE, kRnsWPE))) k_gemm_rns_batched(RnsBatchArgs a) {
-  __shared__ __attribute__((aligned(16))) int8_t lds[kRnsStages * kRnsStage];
-  const int n = a.hdr->n;
+template <int TQ>
+__global__ void __launch_bounds__(64 * RnsCfg<TQ>::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_gemm_rns_batched(RnsBatchArgs a) {
+  using C = RnsCfg<TQ>;
+  __shared__ __attribute__((aligned(16))) int8_t lds[C::LDS];
+  // this launch's problems and tiles (read on the device, so that a captured graph serves any batch)
+  constexpr bool narrow = TQ == 128;
+  const int p_lo = narrow ? a.hdr->n_wide : 0, p_hi = narrow ? a.hdr->n : a.hdr->n_wide;
+  const int64_t t_lo = narrow ? a.hdr->tiles_wide : 0, t_hi = narrow ? a.hdr->total_tiles : a.hdr->tiles_wide;
+  uint32_t* next = narrow ? a.next_narrow : a.next;
   const int xcd = blockIdx.x % kXcds;
-  const int64_t per_xcd = a.hdr->total_tiles / kXcds;
+  const int64_t per_xcd = (t_hi - t_lo) / kXcds;
   for (;;) {
     __syncthreads();  // the previous tile is done with LDS
-    if (threadIdx.x == 0) *reinterpret_cast<uint32_t*>(lds) = atomicAdd(a.next + xcd, 1u);
+    if (threadIdx.x == 0) *reinterpret_cast<uint32_t*>(lds) = atomicAdd(next + xcd, 1u);
     __syncthreads();
     const int64_t jc = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t*>(lds));
     __syncthreads();  // every thread has read the claim before the tile overwrites LDS
     if (jc >= per_xcd) break;
-    const int64_t t = jc * kXcds + xcd;
-    int lo = 0, hi = n - 1;  // last problem whose first tile is <= t
+    const int64_t t = t_lo + jc * kXcds + xcd;
+    int lo = p_lo, hi = p_hi - 1;  // last problem of this launch whose first tile is <= t
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (a.desc[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
     }
     const BatchDesc& d = a.desc[lo];
-    const int64_t n_ct = (d.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (d.R_out + kRnsTileR - 1) / kRnsTileR;
+    const int64_t n_ct = (d.d3 + TQ - 1) / TQ, n_rt = (d.R_out + C::TR - 1) / C::TR;
     const int64_t per_mod = (n_rt + kXcds - 1) / kXcds * kXcds * n_ct;
     const int64_t local = t - d.tile_begin;
     const int zj = (int)(local / per_mod);
@@ -260,35 +278,58 @@ __global__ void __launch_bounds__(64 * kRnsNW) __attribute__((amdgpu_waves_per_e
     RnsTile tl{d.Xd + ((size_t)z * a.n_mod + j) * a.KB * d.d3_pad * kKB,
                a.Dr + ((size_t)d.slot[z] * a.n_mod + j) * a.KB * a.R_pad * kKB,
                d.res + ((size_t)z * a.n_mod + j) * d.d3 * d.R_out, a.m[j], a.magic[j], a.KB, a.R_pad, d.d3_pad,
-               d.n_db, d.row0, d.R_out, d.d3, rt * kRnsTileR, ct * kRnsTileQ};
-    rns_tile(tl, lds);
+               d.n_db, d.row0, d.R_out, d.d3, rt * C::TR, ct * TQ};
+    rns_tile<TQ>(tl, lds);
   }
 }
 
-int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod) {
-  const int64_t n_ct = (d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (R_out + kRnsTileR - 1) / kRnsTileR;
+int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod, int tq) {
+  const int64_t n_ct = (d3 + tq - 1) / tq, n_rt = (R_out + kRnsTileR - 1) / kRnsTileR;
   return (n_rt + kXcds - 1) / kXcds * kXcds * n_ct * nz * n_mod;
 }
 
-hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_gemm_rns_batched, dim3((unsigned)grid), dim3(64 * kRnsNW), 0, s, a);
+hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, int tq, hipStream_t s) {
+  if (tq == 128)
+    hipLaunchKernelGGL(k_gemm_rns_batched<128>, dim3((unsigned)grid), dim3(64 * RnsCfg<128>::NW), 0, s, a);
+  else if (tq == 256)
+    hipLaunchKernelGGL(k_gemm_rns_batched<256>, dim3((unsigned)grid), dim3(64 * RnsCfg<256>::NW), 0, s, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-// resident workgroups per CU: as many as the 160 KiB of LDS hold, at most the waves-per-SIMD target
-int rns_wgs_per_cu() {
-  const int by_lds = 160 * 1024 / (kRnsStages * kRnsStage), by_waves = kRnsWPE * 4 / kRnsNW;
+// resident workgroups per CU: as many as the 160 KiB of LDS hold, at most two waves per SIMD
+template <int TQ>
+static int wgs_per_cu() {
+  using C = RnsCfg<TQ>;
+  const int by_lds = 160 * 1024 / C::LDS, by_waves = C::WPE * 4 / C::NW;
   const int w = by_lds < by_waves ? by_lds : by_waves;
   return w > 0 ? w : 1;
 }
+int rns_wgs_per_cu(int tq) { return tq == 128 ? wgs_per_cu<128>() : wgs_per_cu<256>(); }
 
-hipError_t launch_gemm_rns(const RnsGemmArgs& g, hipStream_t s) {
+// Query tile of the RNS contraction for a set of problems (d3, R_out, slots): the width whose
+// padded work, weighted by its measured speed per column, is smaller (ties: 256).
+int rns_tile_q(const int64_t* d3, const int64_t* R_out, const int* nz, int n) {
+  double w128 = 0, w256 = 0;
+  for (int i = 0; i < n; ++i) {
+    const double rows = (double)((R_out[i] + kRnsTileR - 1) / kRnsTileR * kRnsTileR) * nz[i];
+    w128 += rows * ((d3[i] + 127) / 128 * 128) * 1.09;
+    w256 += rows * ((d3[i] + 255) / 256 * 256);
+  }
+  return w128 < w256 ? 128 : 256;
+}
+
+hipError_t launch_gemm_rns(const RnsGemmArgs& g, int tq, hipStream_t s) {
   if (g.R_out <= 0 || g.d3 <= 0) return hipSuccess;
-  if (g.d3_pad % kRnsTileQ != 0) return hipErrorInvalidValue;
-  const int64_t n_ct = (g.d3 + kRnsTileQ - 1) / kRnsTileQ, n_rt = (g.R_out + kRnsTileR - 1) / kRnsTileR;
+  if ((tq != 128 && tq != 256) || g.d3_pad % tq != 0) return hipErrorInvalidValue;
+  const int64_t n_ct = (g.d3 + tq - 1) / tq, n_rt = (g.R_out + kRnsTileR - 1) / kRnsTileR;
   const int64_t n_rt8 = (n_rt + kXcds - 1) / kXcds * kXcds;
   dim3 grid((unsigned)(n_rt8 * n_ct), (unsigned)g.n_mod, (unsigned)g.nz);
-  hipLaunchKernelGGL(k_gemm_rns, grid, dim3(64 * kRnsNW), 0, s, g);
+  if (tq == 128)
+    hipLaunchKernelGGL(k_gemm_rns<128>, grid, dim3(64 * RnsCfg<128>::NW), 0, s, g);
+  else
+    hipLaunchKernelGGL(k_gemm_rns<256>, grid, dim3(64 * RnsCfg<256>::NW), 0, s, g);
   return hipGetLastError();
 }
 
