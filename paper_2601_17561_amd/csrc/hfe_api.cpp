@@ -285,18 +285,22 @@ static hfe_status keygen_impl(const hfe_params* params, uint64_t seed, hfe_keys*
     for (int which = 0; which < 2; ++which) {
       const int logn = which == 0 ? (int)P.log_n_db : (int)P.log_n_q;
       NttTabOwner& o = which == 0 ? K->tab_db[z] : K->tab_q[z];
-      ntt_tables_host(q, logn, tab);
-      HFE_TRY(upload(o.buf, tab.data(), tab.size() * sizeof(uint64_t)));
+      ntt_tables_host(q, logn, tab);  // psi | psi_sh | ipsi | ipsi_sh
       const size_t n = (size_t)1 << logn;
-      const uint64_t* base = o.buf.as<uint64_t>();
-      o.tab.psi = base;
-      o.tab.psi_sh = base + n;
-      o.tab.ipsi = base + 2 * n;
-      o.tab.ipsi_sh = base + 3 * n;
+      // the transforms take the twiddles as doubles (exact: below 2^36)
+      std::vector<double> td(2 * n);
+      for (size_t i = 0; i < n; ++i) {
+        td[i] = (double)tab[i];
+        td[n + i] = (double)tab[2 * n + i];
+      }
+      HFE_TRY(upload(o.buf, td.data(), td.size() * sizeof(double)));
+      const double* base = o.buf.as<double>();
+      o.tab.psi_d = base;
+      o.tab.ipsi_d = base + n;
       o.tab.q = q;
-      o.tab.mu = K->mods[z].mu;
-      o.tab.n_inv = inv_mod(n % q, q);
-      o.tab.n_inv_sh = shoup(o.tab.n_inv, q);
+      o.tab.qd = (double)q;
+      o.tab.qinv = 1.0 / (double)q;  // correctly rounded
+      o.tab.n_inv_d = (double)inv_mod(n % q, q);
       o.tab.logn = logn;
     }
   }

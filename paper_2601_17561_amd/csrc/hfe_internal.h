@@ -80,16 +80,15 @@ struct DevBuf {
 // Forward: Cooley-Tukey with psi^brv(i) twiddles (bit-reversed output); inverse:
 // Gentleman-Sande with psi^-brv(i) twiddles and the 1/n scale (natural-order output).
 struct NttTab {
-  const uint64_t* psi;
-  const uint64_t* psi_sh;
-  const uint64_t* ipsi;
-  const uint64_t* ipsi_sh;
-  uint64_t q, mu, n_inv, n_inv_sh;
+  const double* psi_d;   // psi^brv(i) mod q, n entries (exact integers as doubles)
+  const double* ipsi_d;  // psi^-brv(i) mod q
+  uint64_t q;
+  double qd, qinv, n_inv_d;  // q, RN(1/q), n^-1 mod q
   int logn;
 };
 
 struct NttTabOwner {
-  DevBuf buf;  // psi | psi_sh | ipsi | ipsi_sh, n entries each
+  DevBuf buf;  // psi | ipsi as doubles, n entries each
   NttTab tab{};
 };
 

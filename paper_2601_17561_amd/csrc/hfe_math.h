@@ -140,8 +140,8 @@ HFE_HD uint64_t uniform_at(uint64_t seed, uint64_t key1, uint64_t i0, uint64_t i
 HFE_HD int32_t gaussian_at(uint64_t seed, uint64_t key1, uint64_t i0, uint64_t i1,
                            const uint64_t* cdt) {
   Philox4 b = philox4x64_10(seed, key1, i0 >> 1, i1, 0, 0);
-  int h = (int)(i0 & 1);
-  uint64_t w = b.v[2 * h], sw = b.v[2 * h + 1];
+  const bool h = (i0 & 1) != 0;  // words 2h, 2h + 1 of the block (selected, not indexed: registers)
+  const uint64_t w = h ? b.v[2] : b.v[0], sw = h ? b.v[3] : b.v[1];
   int32_t mag = 0;
 #pragma unroll
   for (int j = 0; j < 19; ++j) mag += (w >= cdt[j]) ? 1 : 0;

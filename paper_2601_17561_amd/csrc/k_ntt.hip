@@ -4,14 +4,45 @@
 // Products in R_n = Z[X]/(X^n + 1) mod a 36-bit prime q (Section 2.2.1) are computed as
 // INTT(NTT(a) . NTT(s)) with the merged negacyclic transforms of Longa and Naehrig (2016):
 // forward Cooley-Tukey with twiddles psi^brv(i) (output in bit-reversed order), inverse
-// Gentleman-Sande with psi^-brv(i) and a final 1/n scale.  Twiddle products use Shoup's
-// precomputed quotients.  One workgroup transforms one polynomial held in LDS
-// (2^14 x 8 bytes = 128 KiB fits the 160 KiB LDS of a gfx950 CU).
+// Gentleman-Sande with psi^-brv(i) and a final 1/n scale.  One workgroup transforms one
+// polynomial held in LDS (2^14 x 8 bytes = 128 KiB fits the 160 KiB LDS of a gfx950 CU).
+// Inside the transforms residues are held as doubles (exact integers below 2^36) and multiplied
+// mod q with an error-free fp64 product (see mulmod_d): about a third of the integer instructions
+// of a 64-bit Shoup product, at the same issue rate on this chip.
+#include <type_traits>
+
 #include "hfe_internal.h"
 
 namespace hfe {
 
 constexpr int kNttThreads = 1024;
+
+// ------------------------------------------------------------------ fp64 residue arithmetic
+// Residues mod q < 2^36 as doubles holding exact integers in [0, q).
+// a w mod q for a, w in [0, q): hi = RN(a w) is an integer and lo = a w - hi (|lo| <= 2^18) is
+// exact from one fused multiply-add; t = floor(hi / q) from the rounded reciprocal is within one of
+// floor(a w / q) (relative error below 3 2^-53 on a value below 2^36); hi - t q is an integer below
+// 2^38 in magnitude, so the second fused multiply-add is exact, and so is adding lo.  The result
+// lies in (-q, 2q) and one conditional correction each way brings it to [0, q).
+__device__ __forceinline__ double mulmod_d(double a, double w, double q, double qinv) {
+#pragma clang fp contract(off)
+  const double hi = a * w;
+  const double lo = __builtin_fma(a, w, -hi);
+  const double t = __builtin_floor(hi * qinv);
+  double r = __builtin_fma(-t, q, hi) + lo;
+  r = r < 0.0 ? r + q : r;
+  return r >= q ? r - q : r;
+}
+__device__ __forceinline__ double addmod_d(double a, double b, double q) {
+  const double s = a + b;  // exact below 2^37
+  return s >= q ? s - q : s;
+}
+__device__ __forceinline__ double submod_d(double a, double b, double q) {
+  const double d = a - b;
+  return d < 0.0 ? d + q : d;
+}
+__device__ __forceinline__ double to_d(uint64_t x) { return (double)x; }    // exact below 2^53
+__device__ __forceinline__ uint64_t to_u(double x) { return (uint64_t)x; }  // x an integer in [0, q)
 
 // Both transforms run in rounds of up to three butterfly stages: a thread loads a group of 2^S
 // coefficients into registers, applies S stages there and stores them back, so a transform of
@@ -22,14 +53,14 @@ constexpr int kNttThreads = 1024;
 // t / 2^s, m = n / (2t) 2^s blocks) pairs k and k + 2^(S-1-s); the pair lies in block
 // B 2^s + (k >> (S - s)), whose twiddle is psi[m + block].
 template <int S>
-__device__ __forceinline__ void fwd_round(uint64_t* a, const NttTab& T, int n, int t) {
+__device__ __forceinline__ void fwd_round(double* a, const NttTab& T, int n, int t) {
   constexpr int G = 1 << S;
-  const uint64_t q = T.q;
+  const double q = T.qd, qinv = T.qinv;
   const int stride = t >> (S - 1), m1 = n / (2 * t);
   for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
     const int B = g / stride, r = g - B * stride;
     const int base = B * 2 * t + r;
-    uint64_t x[G];
+    double x[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) x[k] = a[base + k * stride];
 #pragma unroll
@@ -39,10 +70,10 @@ __device__ __forceinline__ void fwd_round(uint64_t* a, const NttTab& T, int n, i
       for (int k = 0; k < G; ++k) {
         if (k & h) continue;
         const int w = (m1 << s) + (B << s) + (k >> (S - s));
-        const uint64_t U = x[k];
-        const uint64_t V = mul_shoup(x[k + h], T.psi[w], T.psi_sh[w], q);
-        x[k] = add_mod(U, V, q);
-        x[k + h] = sub_mod(U, V, q);
+        const double U = x[k];
+        const double V = mulmod_d(x[k + h], T.psi_d[w], q, qinv);
+        x[k] = addmod_d(U, V, q);
+        x[k + h] = submod_d(U, V, q);
       }
     }
 #pragma unroll
@@ -56,13 +87,13 @@ __device__ __forceinline__ void fwd_round(uint64_t* a, const NttTab& T, int n, i
 // blocks) pairs k and k + 2^s; the pair lies in block B 2^(S-1-s) + (k >> (s + 1)), twiddle
 // ipsi[m + block].  With scale, the round ends with the 1/n factor.
 template <int S>
-__device__ __forceinline__ void inv_round(uint64_t* a, const NttTab& T, int n, int t, bool scale) {
+__device__ __forceinline__ void inv_round(double* a, const NttTab& T, int n, int t, bool scale) {
   constexpr int G = 1 << S;
-  const uint64_t q = T.q;
+  const double q = T.qd, qinv = T.qinv;
   for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
     const int B = g / t, r = g - B * t;
     const int base = B * G * t + r;
-    uint64_t x[G];
+    double x[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) x[k] = a[base + k * t];
 #pragma unroll
@@ -73,14 +104,14 @@ __device__ __forceinline__ void inv_round(uint64_t* a, const NttTab& T, int n, i
       for (int k = 0; k < G; ++k) {
         if (k & h) continue;
         const int w = m + (B << (S - 1 - s)) + (k >> (s + 1));
-        const uint64_t U = x[k], V = x[k + h];
-        x[k] = add_mod(U, V, q);
-        x[k + h] = mul_shoup(sub_mod(U, V, q), T.ipsi[w], T.ipsi_sh[w], q);
+        const double U = x[k], V = x[k + h];
+        x[k] = addmod_d(U, V, q);
+        x[k + h] = mulmod_d(submod_d(U, V, q), T.ipsi_d[w], q, qinv);
       }
     }
     if (scale) {
 #pragma unroll
-      for (int k = 0; k < G; ++k) x[k] = mul_shoup(x[k], T.n_inv, T.n_inv_sh, q);
+      for (int k = 0; k < G; ++k) x[k] = mulmod_d(x[k], T.n_inv_d, q, qinv);
     }
 #pragma unroll
     for (int k = 0; k < G; ++k) a[base + k * t] = x[k];
@@ -89,7 +120,7 @@ __device__ __forceinline__ void inv_round(uint64_t* a, const NttTab& T, int n, i
 }
 
 // Forward negacyclic NTT in place (output in bit-reversed order).
-__device__ __forceinline__ void ntt_fwd_lds(uint64_t* a, const NttTab& T) {
+__device__ __forceinline__ void ntt_fwd_lds(double* a, const NttTab& T) {
   const int n = 1 << T.logn;
   int t = n >> 1, left = T.logn;
   while (left > 0) {
@@ -110,7 +141,7 @@ __device__ __forceinline__ void ntt_fwd_lds(uint64_t* a, const NttTab& T) {
 }
 
 // Inverse negacyclic NTT in place (input in bit-reversed order), including the 1/n factor.
-__device__ __forceinline__ void ntt_inv_lds(uint64_t* a, const NttTab& T) {
+__device__ __forceinline__ void ntt_inv_lds(double* a, const NttTab& T) {
   const int n = 1 << T.logn;
   int t = 1, left = T.logn;
   while (left > 0) {
@@ -130,14 +161,6 @@ __device__ __forceinline__ void ntt_inv_lds(uint64_t* a, const NttTab& T) {
   }
 }
 
-// a <- a . w pointwise, w given with its Shoup companions w_sh (both n entries).
-__device__ __forceinline__ void pointwise_lds(uint64_t* a, const uint64_t* w, const uint64_t* w_sh,
-                                              int n, uint64_t q) {
-  for (int idx = threadIdx.x; idx < n; idx += blockDim.x)
-    a[idx] = mul_shoup(a[idx], w[idx], w_sh[idx], q);
-  __syncthreads();
-}
-
 static int ntt_block(int logn) {
   int half = 1 << (logn > 0 ? logn - 1 : 0);
   int b = half < 64 ? 64 : half;
@@ -155,14 +178,14 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
 
 __global__ void __launch_bounds__(kNttThreads) k_ntt_fwd(uint64_t* a, int64_t stride, NttTab T,
                                                           int with_shoup) {
-  extern __shared__ uint64_t lds[];
+  extern __shared__ double lds[];
   const int n = 1 << T.logn;
   uint64_t* poly = a + (int64_t)blockIdx.x * stride;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = poly[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = to_d(poly[i]);
   __syncthreads();
   ntt_fwd_lds(lds, T);
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const uint64_t v = lds[i];
+    const uint64_t v = to_u(lds[i]);
     poly[i] = v;
     if (with_shoup) poly[n + i] = shoup_quot(v, T.q);
   }
@@ -171,7 +194,7 @@ __global__ void __launch_bounds__(kNttThreads) k_ntt_fwd(uint64_t* a, int64_t st
 hipError_t launch_ntt_fwd(uint64_t* a, int64_t count, int64_t stride, NttTab tab, bool with_shoup,
                           hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const size_t lds = sizeof(uint64_t) << tab.logn;
+  const size_t lds = sizeof(double) << tab.logn;
   hipError_t e = allow_lds(k_ntt_fwd, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_ntt_fwd, dim3((unsigned)count), dim3(ntt_block(tab.logn)), lds, s, a, stride, tab,
@@ -184,42 +207,59 @@ hipError_t launch_ntt_fwd(uint64_t* a, int64_t count, int64_t stride, NttTab tab
 // row i).  Exact integers with |T| <= d2 < q_0 / 2, so one prime suffices; the sum is
 // accumulated in the NTT domain in registers.  Output row-major T[i][v] (int32).
 
-constexpr int kTAccMax = 16;  // (2^14 / 1024) NTT-domain coefficients per thread
+// R: NTT-domain coefficients each thread keeps in registers, n / blockDim (1 .. 16 for n <= 2^14),
+// a template parameter so that the register arrays are no larger than the transform needs.
+static int regs_per_thread(int logn) {
+  const int r = (1 << logn) / ntt_block(logn);
+  return r < 1 ? 1 : r;
+}
+// f(std::integral_constant<int, R>{}) for the runtime count r
+template <class F>
+static hipError_t by_regs(int r, F f) {
+  switch (r) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    default: return hipErrorInvalidValue;
+  }
+}
 
+template <int R>
 __global__ void __launch_bounds__(kNttThreads)
 k_db_T(const int8_t* m_db, int32_t d2, const uint64_t* sconj_hat, int k, NttTab T, int32_t* Trow) {
-  extern __shared__ uint64_t lds[];
+  extern __shared__ double lds[];
   const int n = 1 << T.logn;
   const int64_t i = blockIdx.x;
-  const uint64_t q = T.q;
-  uint64_t acc[kTAccMax];
+  const double q = T.qd, qinv = T.qinv;
+  double acc[R];
 #pragma unroll
-  for (int r = 0; r < kTAccMax; ++r) acc[r] = 0;
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
   for (int j = 0; j < k; ++j) {
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
       const int64_t col = (int64_t)j * n + t;
       const int8_t m = col < d2 ? m_db[i * d2 + col] : (int8_t)0;
-      lds[t] = m == 1 ? 1 : (m == -1 ? q - 1 : 0);
+      lds[t] = m == 1 ? 1.0 : (m == -1 ? q - 1.0 : 0.0);
     }
     __syncthreads();
     ntt_fwd_lds(lds, T);
     const uint64_t* w = sconj_hat + (int64_t)j * 2 * n;
-    const uint64_t* wsh = w + n;
 #pragma unroll
-    for (int r = 0; r < kTAccMax; ++r) {
+    for (int r = 0; r < R; ++r) {
       const int t = threadIdx.x + r * blockDim.x;
-      if (t < n) acc[r] = add_mod(acc[r], mul_shoup(lds[t], w[t], wsh[t], q), q);
+      if (t < n) acc[r] = addmod_d(acc[r], mulmod_d(lds[t], to_d(w[t]), q, qinv), q);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < kTAccMax; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int t = threadIdx.x + r * blockDim.x;
     if (t < n) lds[t] = acc[r];
   }
   __syncthreads();
   ntt_inv_lds(lds, T);
-  for (int t = threadIdx.x; t < n; t += blockDim.x) Trow[i * n + t] = (int32_t)centered(lds[t], q);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) Trow[i * n + t] = (int32_t)centered(to_u(lds[t]), T.q);
 }
 
 __global__ void k_transpose_i32(const int32_t* in, int64_t rows, int64_t cols, int32_t* out) {
@@ -240,12 +280,15 @@ hipError_t launch_db_T(const int8_t* m_db, int64_t d1, int32_t d2, const uint64_
                        NttTab tab_q0, int32_t* Trow, int32_t* Tt, hipStream_t s) {
   if (d1 <= 0) return hipSuccess;
   const int n = 1 << tab_q0.logn;
-  const size_t lds = sizeof(uint64_t) * n;
-  hipError_t e = allow_lds(k_db_T, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_db_T, dim3((unsigned)d1), dim3(ntt_block(tab_q0.logn)), lds, s, m_db, d2,
-                     sconj_hat, k, tab_q0, Trow);
-  e = hipGetLastError();
+  const size_t lds = sizeof(double) * n;
+  hipError_t e = by_regs(regs_per_thread(tab_q0.logn), [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    hipError_t e2 = allow_lds(k_db_T<R>, lds);
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL(k_db_T<R>, dim3((unsigned)d1), dim3(ntt_block(tab_q0.logn)), lds, s, m_db, d2,
+                       sconj_hat, k, tab_q0, Trow);
+    return hipGetLastError();
+  });
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((n + 31) / 32), (unsigned)((d1 + 31) / 32));
   hipLaunchKernelGGL(k_transpose_i32, grid, dim3(32, 8), 0, s, Trow, d1, (int64_t)n, Tt);
@@ -258,9 +301,10 @@ hipError_t launch_db_T(const int8_t* m_db, int64_t d1, int32_t d2, const uint64_
 // chunk j: B[i][c] = -(s'_j a_c)[i - j N_DB] + p * plain[i][c] + e(i, c) (stream DBE).
 // plain = M_DB for c < d2, T for c >= d2.  Column c of D is stored contiguously: Dt[c][row].
 
+template <int R>
 __global__ void __launch_bounds__(kNttThreads)
 k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, const uint64_t* sdb_hat) {
-  extern __shared__ uint64_t lds[];
+  extern __shared__ double lds[];
   const int n = 1 << T.logn;
   const int64_t c = blockIdx.x;
   const uint64_t q = M.q;
@@ -275,7 +319,7 @@ k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, cons
         const uint64_t w = b.v[j];
         const uint64_t x = w < M.bound ? barrett64(w, q, M.mu)
                                        : uniform_at(A.seed, key_a, (uint64_t)v, (uint64_t)c, M);
-        lds[v] = x;
+        lds[v] = to_d(x);
         col[v] = x;
       }
     }
@@ -283,22 +327,21 @@ k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, cons
   __syncthreads();
   // NTT(a_c) once, kept in registers for all chunks.
   ntt_fwd_lds(lds, T);
-  uint64_t ahat[kTAccMax];
+  double ahat[R];
 #pragma unroll
-  for (int r = 0; r < kTAccMax; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int v = threadIdx.x + r * blockDim.x;
-    ahat[r] = v < n ? lds[v] : 0;
+    ahat[r] = v < n ? lds[v] : 0.0;
   }
   const uint64_t pm = barrett64(A.p, q, M.mu);
   const uint64_t key_e = stream_tag(kDbE, 0);
   const int chunks = (int)((A.d1 + n - 1) / n);
   for (int j = 0; j < chunks; ++j) {
     const uint64_t* w = sdb_hat + (int64_t)j * 2 * n;
-    const uint64_t* wsh = w + n;
 #pragma unroll
-    for (int r = 0; r < kTAccMax; ++r) {
+    for (int r = 0; r < R; ++r) {
       const int v = threadIdx.x + r * blockDim.x;
-      if (v < n) lds[v] = mul_shoup(ahat[r], w[v], wsh[v], q);
+      if (v < n) lds[v] = mulmod_d(ahat[r], to_d(w[v]), T.qd, T.qinv);
     }
     __syncthreads();
     ntt_inv_lds(lds, T);
@@ -309,7 +352,7 @@ k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, cons
       const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)i, (uint64_t)c, A.cdt);
       const uint64_t ppl = pl >= 0 ? barrett64(pm * (uint64_t)pl, q, M.mu)
                                    : sub_mod(0, barrett64(pm * (uint64_t)(-pl), q, M.mu), q);
-      uint64_t val = sub_mod(ppl, lds[i - lo], q);
+      uint64_t val = sub_mod(ppl, to_u(lds[i - lo]), q);
       val = add_mod(val, from_signed(e, q, M.mu), q);
       col[n + i] = val;
     }
@@ -320,12 +363,15 @@ k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, cons
 hipError_t launch_db_encrypt(const DbEncArgs& a, uint64_t* Dt_prime, uint32_t prime_id, const Mod& m,
                              NttTab tab_db, const uint64_t* sdb_hat_prime, hipStream_t s) {
   if (a.K <= 0) return hipSuccess;
-  const size_t lds = sizeof(uint64_t) << tab_db.logn;
-  hipError_t e = allow_lds(k_db_encrypt, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_db_encrypt, dim3((unsigned)a.K), dim3(ntt_block(tab_db.logn)), lds, s, a,
-                     Dt_prime, prime_id, m, tab_db, sdb_hat_prime);
-  return hipGetLastError();
+  const size_t lds = sizeof(double) << tab_db.logn;
+  return by_regs(regs_per_thread(tab_db.logn), [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    hipError_t e = allow_lds(k_db_encrypt<R>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_db_encrypt<R>, dim3((unsigned)a.K), dim3(ntt_block(tab_db.logn)), lds, s, a,
+                       Dt_prime, prime_id, m, tab_db, sdb_hat_prime);
+    return hipGetLastError();
+  });
 }
 
 // ------------------------------------------------------------------ query encryption
@@ -333,10 +379,11 @@ hipError_t launch_db_encrypt(const DbEncArgs& a, uint64_t* Dt_prime, uint32_t pr
 // for each chunk j of N_Q code rows b[t] = -(s_j a_c)[t - j N_Q] + Delta m[c][t] + e(t, c).
 // Output row c of XT: [b_c (d2) | a_c (N_Q)].
 
+template <int R>
 __global__ void __launch_bounds__(kNttThreads)
 k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, NttTab T,
             const uint64_t* s_hat) {
-  extern __shared__ uint64_t lds[];
+  extern __shared__ double lds[];
   const int n = 1 << T.logn;
   const int64_t c = blockIdx.x;
   const uint64_t q = M.q;
@@ -352,29 +399,28 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
         const uint64_t w = b.v[j];
         const uint64_t x = w < M.bound ? barrett64(w, q, M.mu)
                                        : uniform_at(A.seed, key_a, (uint64_t)t, (uint64_t)c, M);
-        lds[t] = x;
+        lds[t] = to_d(x);
         arow[t] = x;
       }
     }
   }
   __syncthreads();
-  // NTT(a_c) once, kept in registers (n / blockDim <= kTAccMax values per thread) for all chunks.
+  // NTT(a_c) once, kept in registers (n / blockDim = R values per thread) for all chunks.
   ntt_fwd_lds(lds, T);
-  uint64_t ahat[kTAccMax];
+  double ahat[R];
 #pragma unroll
-  for (int r = 0; r < kTAccMax; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int t = threadIdx.x + r * blockDim.x;
-    ahat[r] = t < n ? lds[t] : 0;
+    ahat[r] = t < n ? lds[t] : 0.0;
   }
   const uint64_t key_e = stream_tag(kQE, 0);
   const int8_t* m = A.m_q + c * A.d2;
   for (int j = 0; j < A.k; ++j) {
     const uint64_t* w = s_hat + (int64_t)j * 2 * n;
-    const uint64_t* wsh = w + n;
 #pragma unroll
-    for (int r = 0; r < kTAccMax; ++r) {
+    for (int r = 0; r < R; ++r) {
       const int t = threadIdx.x + r * blockDim.x;
-      if (t < n) lds[t] = mul_shoup(ahat[r], w[t], wsh[t], q);
+      if (t < n) lds[t] = mulmod_d(ahat[r], to_d(w[t]), T.qd, T.qinv);
     }
     __syncthreads();
     ntt_inv_lds(lds, T);
@@ -384,7 +430,7 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
       const int8_t mv = m[t];
       const uint64_t dm = mv == 1 ? delta : (mv == -1 ? (delta ? q - delta : 0) : 0);
       const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)t, (uint64_t)c, A.cdt);
-      uint64_t val = sub_mod(dm, lds[t - lo], q);
+      uint64_t val = sub_mod(dm, to_u(lds[t - lo]), q);
       val = add_mod(val, from_signed(e, q, M.mu), q);
       row[t] = val;
     }
@@ -396,12 +442,15 @@ hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prim
                             uint64_t delta_mod, NttTab tab_q, const uint64_t* s_hat_prime,
                             hipStream_t s) {
   if (a.d3 <= 0) return hipSuccess;
-  const size_t lds = sizeof(uint64_t) << tab_q.logn;
-  hipError_t e = allow_lds(k_q_encrypt, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_q_encrypt, dim3((unsigned)a.d3), dim3(ntt_block(tab_q.logn)), lds, s, a,
-                     XT_prime, prime_id, m, delta_mod, tab_q, s_hat_prime);
-  return hipGetLastError();
+  const size_t lds = sizeof(double) << tab_q.logn;
+  return by_regs(regs_per_thread(tab_q.logn), [&](auto rc) {
+    constexpr int R = decltype(rc)::value;
+    hipError_t e = allow_lds(k_q_encrypt<R>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_q_encrypt<R>, dim3((unsigned)a.d3), dim3(ntt_block(tab_q.logn)), lds, s, a,
+                       XT_prime, prime_id, m, delta_mod, tab_q, s_hat_prime);
+    return hipGetLastError();
+  });
 }
 
 // ------------------------------------------------------------------ decryption products
@@ -411,22 +460,24 @@ hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prim
 __global__ void __launch_bounds__(kNttThreads)
 k_dec_products(const uint64_t* out, int64_t R_out, int64_t row0, int64_t rows, NttTab T,
                const uint64_t* sdb_hat, int j0, uint64_t* y) {
-  extern __shared__ uint64_t lds[];
+  extern __shared__ double lds[];
   const int n = 1 << T.logn;
   const int64_t c = blockIdx.x;
   const int j = j0 + (int)blockIdx.y;
   const uint64_t q = T.q;
   const uint64_t* ocol = out + c * R_out;
-  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = ocol[v];
+  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = to_d(ocol[v]);
   __syncthreads();
   ntt_fwd_lds(lds, T);
-  pointwise_lds(lds, sdb_hat + (int64_t)j * 2 * n, sdb_hat + (int64_t)j * 2 * n + n, n, q);
+  const uint64_t* w = sdb_hat + (int64_t)j * 2 * n;
+  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = mulmod_d(lds[v], to_d(w[v]), T.qd, T.qinv);
+  __syncthreads();
   ntt_inv_lds(lds, T);
   int64_t lo = (int64_t)j * n - row0, hi = lo + n;
   if (lo < 0) lo = 0;
   if (hi > rows) hi = rows;
   for (int64_t r = lo + threadIdx.x; r < hi; r += blockDim.x)
-    y[c * rows + r] = add_mod(ocol[n + r], lds[row0 + r - (int64_t)j * n], q);
+    y[c * rows + r] = add_mod(ocol[n + r], to_u(lds[row0 + r - (int64_t)j * n]), q);
 }
 
 hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,
@@ -436,7 +487,7 @@ hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_
   const int64_t n = 1ll << n_db_log;
   const int j0 = (int)(row0 / n), j1 = (int)((row0 + rows - 1) / n);
   if (j1 >= k_db) return hipErrorInvalidValue;
-  const size_t lds = sizeof(uint64_t) << tab.logn;
+  const size_t lds = sizeof(double) << tab.logn;
   hipError_t e = allow_lds(k_dec_products, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dec_products, dim3((unsigned)d3, (unsigned)(j1 - j0 + 1)), dim3(ntt_block(tab.logn)),
