@@ -63,6 +63,19 @@ def rns_moduli(w: S.Workload, qmax: int) -> int:
     raise ValueError("contraction too long for the small moduli")
 
 
+def p2_bases(w: S.Workload, qmax: int) -> int:
+    """Bases n of the n^2 form for this shape (the library's rule): the shortest prefix of its
+    prime list whose squares' product is at least 4 K ((q - 1) / 2)^2 for the largest prime q."""
+    import math
+    bases = (251, 241, 239, 233, 229, 227, 223, 211)
+    K = w.d2 + (1 << w.log_n_q)
+    bound = 4 * K * ((qmax - 1) // 2) ** 2
+    for n in range(1, len(bases) + 1):
+        if math.prod(b * b for b in bases[:n]) >= bound:
+            return n
+    raise ValueError("contraction too long for the n^2 bases")
+
+
 def cpu_baseline(w: S.Workload, inp, rows_sample: int, cols_sample: int):
     """The oracle's CCMM (lift, exact contraction, CRT rescale) on a slice of the workload."""
     import torch
@@ -237,7 +250,7 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time every int8 tile configuration and exit")
     ap.add_argument("--variant", type=int, default=-1, help="int8 tile configuration (-1: default)")
     ap.add_argument("--ccmm-only", type=int, default=0, help="run N int8 CCMMs after setup and exit (profiling)")
-    ap.add_argument("--form", choices=("i8", "rns"), default="i8", help="with --ccmm-only: the int8 form to run")
+    ap.add_argument("--form", choices=("i8", "rns", "p2"), default="i8", help="with --ccmm-only: the int8 form to run")
     ap.add_argument("--mode", choices=("step", "batched", "serving"), default="step",
                     help="step: the hot-path step (default); batched: 64 uneven items as one plan; "
                          "serving: Poisson arrivals through the server")
@@ -278,10 +291,11 @@ def main():
     q_codes = torch.from_numpy(inp["q_codes"]).to(dev)
     q_masks = torch.from_numpy(inp["q_masks"]).to(dev)
     shifts = [int(s) for s in inp["shifts"]]
-    log("encrypting the database (plain, digit and RNS forms)")
+    log("encrypting the database (plain, digit, RNS and n^2 forms)")
     t0 = time.perf_counter()
     m_db = H.hfe_encode(db_codes, db_masks, [0])
-    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED,
+                          H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8 | H.HFE_FORM_P2_I8)
     torch.cuda.synchronize()
     t_db = time.perf_counter() - t0
     del m_db
@@ -323,7 +337,7 @@ def main():
     if args.ccmm_only:
         m_q = H.hfe_encode(q_codes, q_masks, shifts)
         qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
-        form = H.HFE_FORM_RNS_I8 if args.form == "rns" else H.HFE_FORM_I8_MFMA
+        form = {"rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}.get(args.form, H.HFE_FORM_I8_MFMA)
         for _ in range(args.ccmm_only):
             H.hfe_ccmm(db, qct, 0, w.d1, form).free()
         torch.cuda.synchronize()
@@ -360,6 +374,7 @@ def main():
     results = {}
     for name, form, steps, warm in (("i8", H.HFE_FORM_I8_MFMA, args.steps, args.warmup),
                                     ("rns", H.HFE_FORM_RNS_I8, args.steps, args.warmup),
+                                    ("p2", H.HFE_FORM_P2_I8, args.steps, args.warmup),
                                     ("plain", H.HFE_FORM_PLAIN_U64, args.plain_steps, 1)):
         if steps <= 0:
             continue
@@ -398,6 +413,10 @@ def main():
     qs, p_special = P.primes()
     n_mod = rns_moduli(w, max(list(qs) + [p_special]))
     rns_ops = 2 * n_mod * work["residue_macs"]
+    p2 = results["p2"]
+    n_b = p2_bases(w, max(list(qs) + [p_special]))
+    p2_ops = 2 * 3 * n_b * work["residue_macs"]
+    same_p2 = bool(torch.equal(p2["ip"], results["i8"]["ip"]))
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
@@ -441,6 +460,13 @@ def main():
                 "frac_of_peak": rns_ops / (rns["contraction_ms"] * 1e-3) / 1e12 / PEAK_I8_TOPS,
                 "over_i8_step": i8["ms_per_step"] / rns["ms_per_step"], "equals_i8_ip": same_rns,
                 "phases_ms": rns["phases_ms"]},
+        "p2": {"form": f"n^2 split M + n M', {n_b} bases, 3 int8 products each, per prime",
+               "ms_per_step": p2["ms_per_step"], "comparisons_per_s": p2["comparisons_per_s"],
+               "contraction_ms": p2["contraction_ms"], "lift_ms": p2["lift_ms"], "crt_rescale_ms": p2["rescale_ms"],
+               "int8_ops_per_launch": p2_ops,
+               "frac_of_peak": p2_ops / (p2["contraction_ms"] * 1e-3) / 1e12 / PEAK_I8_TOPS,
+               "over_i8_step": i8["ms_per_step"] / p2["ms_per_step"], "equals_i8_ip": same_p2,
+               "phases_ms": p2["phases_ms"]},
         "i8_over_plain_step": plain["ms_per_step"] / i8["ms_per_step"] if plain else None,
         "stages_ms": {"lift_split": i8["lift_ms"], "contraction": i8["contraction_ms"],
                       "contraction_median": i8["contraction_median_ms"], "rescale": i8["rescale_ms"]},

@@ -62,9 +62,17 @@ enum {
  * balanced residues modulo n pairwise coprime moduli <= 256 (n = 11 for 36-bit primes and K up
  * to about 33,000; the product of the moduli is at least four times the largest exact sum), one int8
  * MFMA product per modulus with int32 accumulation (K < 2^17), then the Chinese remainder
- * reconstruction of the exact sum and its reduction mod the prime.  All forms give the same
- * residues.  The database stores 8, 5 and n bytes per entry and prime for the three forms. */
-typedef enum { HFE_FORM_PLAIN_U64 = 1, HFE_FORM_I8_MFMA = 2, HFE_FORM_RNS_I8 = 4 } hfe_form;
+ * reconstruction of the exact sum and its reduction mod the prime.
+ * P2_I8: the n^2 technique of Section 6.3 applied per prime: for bases n_j among the primes
+ * 211 <= n <= 251 (6 for 36-bit primes and K up to about 65,000; the product of the n_j^2 is at
+ * least four times the largest exact sum), each centered residue's residue mod n_j^2 written as
+ * M + n_j M' with |M|, |M'| <= 125; per base the three int8 MFMA products M N, M N' and M' N with
+ * int32 accumulation (K <= 2^16) give the exact sum mod n_j^2, then the Chinese remainder
+ * reconstruction and the reduction mod the prime.  Single calls only (hfe_ccmm); batches, plans
+ * and servers run the other forms.
+ * All forms give the same residues.  The database stores 8, 5, n and 2 n bytes per entry and
+ * prime for the four forms. */
+typedef enum { HFE_FORM_PLAIN_U64 = 1, HFE_FORM_I8_MFMA = 2, HFE_FORM_RNS_I8 = 4, HFE_FORM_P2_I8 = 8 } hfe_form;
 
 #define HFE_MAX_QPRIMES 8
 
@@ -116,8 +124,8 @@ hfe_status hfe_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int
 /* Database encryption in the RGSW/MSRLWE form of Sections 2.3 and 6.3: T = M_DB S_Q, and per
  * prime of Q_L p: A = [A1 | A2] uniform (N_DB x (d2 + N_Q)), B = -S_DB A + p [M_DB | T] + E.
  * m_db: d1 x d2 ternary (device).  forms: bitmask of hfe_form the database is prepared for
- * (HFE_FORM_RNS_I8 needs d2 + N_Q < 2^17, else HFE_ESHAPE).  The result stays resident on the
- * device. */
+ * (HFE_FORM_RNS_I8 needs d2 + N_Q < 2^17 and HFE_FORM_P2_I8 d2 + N_Q <= 2^16, else HFE_ESHAPE).
+ * The result stays resident on the device. */
 hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, uint64_t seed,
                           uint32_t forms, void* stream, hfe_db** out);
 
@@ -147,7 +155,7 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
  * and one grouped launch rescales every item; the digit form's problems share one tile
  * configuration (the forced one, else of the tuned and the default configuration the one that pads
  * the problems least); plain form: one hfe_ccmm per item.  outs[i] receives item i's result handle
- * (release each with hfe_free).  1 <= n <= 256. */
+ * (release each with hfe_free).  1 <= n <= 256.  HFE_FORM_P2_I8: HFE_EINVAL. */
 typedef struct {
   const hfe_qct* q;
   int64_t row0, rows;

@@ -27,6 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libhfe.so")
 HFE_FORM_PLAIN_U64 = 1
 HFE_FORM_I8_MFMA = 2
 HFE_FORM_RNS_I8 = 4
+HFE_FORM_P2_I8 = 8
 HFE_MAX_QPRIMES = 8
 
 STATUS_NAMES = {0: "HFE_OK", -1: "HFE_EINVAL", -2: "HFE_ESHAPE", -3: "HFE_ELEVEL", -4: "HFE_ENOMEM",

@@ -435,6 +435,50 @@ static RnsCrtArgs make_rns_crt_args(const hfe_keys* K, int level, int n) {
   return ra;
 }
 
+// Bases of the n^2 form for contraction length K: the shortest prefix of kP2Bases whose squares'
+// product M is at least 4 K h^2 (as for the RNS form).  K <= 2^16 keeps the int32 accumulation of
+// the 2 K products of each G1 sum exact (|digits| <= 125).
+static hfe_status p2_bases_for(const hfe_keys* K, int64_t Klen, int* n_out) {
+  if (Klen > (1 << 16)) return fail(HFE_ESHAPE, "n^2 form: contraction length must be at most 2^16");
+  uint64_t qmax = 0;
+  for (int z = 0; z < K->n_primes; ++z) qmax = std::max(qmax, K->primes[z]);
+  const unsigned __int128 h = (qmax - 1) / 2;
+  const unsigned __int128 bound = (unsigned __int128)4 * (uint64_t)Klen * h * h;
+  unsigned __int128 M = 1;
+  for (int n = 1; n <= kP2MaxBases; ++n) {
+    M *= (uint64_t)kP2Bases[n - 1] * (uint64_t)kP2Bases[n - 1];
+    if (M >= bound) {
+      *n_out = n;
+      return HFE_OK;
+    }
+  }
+  return fail(HFE_ESHAPE, "n^2 form: contraction too long for the bases");
+}
+
+// CRT constants of the n^2 form (moduli m_j = n_j^2), as make_rns_crt_args.
+static P2CrtArgs make_p2_crt_args(const hfe_keys* K, int level, int n) {
+  P2CrtArgs ra;
+  std::memset(&ra, 0, sizeof(ra));
+  ra.n = n;
+  unsigned __int128 M = 1;
+  for (int i = 0; i < n; ++i) M *= (uint64_t)kP2Bases[i] * (uint64_t)kP2Bases[i];
+  for (int j = 0; j < n; ++j) {
+    const int64_t m = (int64_t)kP2Bases[j] * kP2Bases[j];
+    ra.m[j] = (int32_t)m;
+    const unsigned __int128 Mj = M / (uint64_t)m;
+    ra.inv[j] = (int32_t)inv_mod_any((int64_t)(Mj % (uint64_t)m), m);
+    ra.rcp[j] = 1.0f / (float)m;
+  }
+  for (int z = 0; z <= level; ++z) {
+    const int slot = z < level ? z : K->L;
+    const uint64_t q = K->primes[slot];
+    ra.mod[z] = K->mods[slot];
+    ra.M_mod_q[z] = (uint64_t)(M % q);
+    for (int j = 0; j < n; ++j) ra.Mj_mod_q[z][j] = (uint64_t)((M / (uint64_t)ra.m[j]) % q);
+  }
+  return ra;
+}
+
 static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t d1, uint64_t seed,
                                   uint32_t forms, hipStream_t s, hfe_db* D) {
   const hfe_params& P = K->P;
@@ -490,6 +534,16 @@ static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t
       HFE_LAUNCH(launch_split_db_rns(D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, D->K, D->R, D->KB, D->R_pad,
                                      K->primes[z], n, D->rns.as<int8_t>() + (size_t)z * n * plane, s));
   }
+  if (forms & HFE_FORM_P2_I8) {
+    int n = 0;
+    HFE_TRY(p2_bases_for(K, D->K, &n));
+    D->n_p2 = n;
+    const size_t plane = (size_t)D->KB * D->R_pad * kKB;
+    HFE_TRY(D->p2.alloc((size_t)np * 2 * n * plane, s));
+    for (int z = 0; z < np; ++z)
+      HFE_LAUNCH(launch_split_db_p2(D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, D->K, D->R, D->KB, D->R_pad,
+                                    K->primes[z], n, D->p2.as<int8_t>() + (size_t)z * 2 * n * plane, s));
+  }
   if (!(forms & HFE_FORM_PLAIN_U64)) D->Dt.reset();
   return HFE_OK;
 }
@@ -502,7 +556,7 @@ hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, 
   if (!K || !m_db) return fail(HFE_EINVAL, "invalid keys or m_db");
   if (d1 < 1 || d1 > (int64_t)K->P.max_db_rows)
     return fail(HFE_ESHAPE, "d1 must be 1 .. max_db_rows");
-  if (forms == 0 || (forms & ~7u)) return fail(HFE_EINVAL, "forms must be a non-empty set of hfe_form");
+  if (forms == 0 || (forms & ~15u)) return fail(HFE_EINVAL, "forms must be a non-empty set of hfe_form");
   hfe_db* D = new (std::nothrow) hfe_db();
   if (!D) return fail(HFE_ENOMEM, "host allocation failed");
   hfe_status st = encrypt_db_impl(K, m_db, d1, seed, forms, (hipStream_t)stream, D);
@@ -710,6 +764,35 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_rns(rg, tq, s));
     HFE_LAUNCH(launch_crt_rns(res.as<uint8_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), C.as<uint64_t>(), s));
+  } else if (form == HFE_FORM_P2_I8) {
+    const int n = D->n_p2;
+    const int64_t d3_pad = (d3 + kP2TileQ - 1) / kP2TileQ * kP2TileQ;
+    const size_t planeX = (size_t)D->KB * d3_pad * kKB;
+    const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
+    HFE_TRY(Xd.alloc((size_t)nz * 2 * n * planeX, s));
+    HFE_LAUNCH(launch_lift_p2(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd.as<int8_t>(), s));
+    DevBuf res;
+    HFE_TRY(res.alloc(sizeof(uint16_t) * (size_t)nz * n * d3 * R_out, s));
+    P2GemmArgs pg;
+    std::memset(&pg, 0, sizeof(pg));
+    pg.nz = nz;
+    pg.n_bases = n;
+    for (int z = 0; z < nz; ++z) {
+      pg.Dq[z] = D->p2.as<int8_t>() + (size_t)slot(z) * 2 * n * planeD;
+      pg.Xq[z] = Xd.as<int8_t>() + (size_t)z * 2 * n * planeX;
+    }
+    for (int j = 0; j < n; ++j) pg.n[j] = kP2Bases[j];
+    pg.res = res.as<uint16_t>();
+    pg.KB = D->KB;
+    pg.R_pad = D->R_pad;
+    pg.n_db = ndb;
+    pg.row0 = row0;
+    pg.R_out = R_out;
+    pg.d3 = d3;
+    pg.d3_pad = d3_pad;
+    HFE_LAUNCH(mark(1));
+    HFE_LAUNCH(launch_gemm_p2(pg, s));
+    HFE_LAUNCH(launch_crt_p2(res.as<uint16_t>(), nz, d3 * R_out, make_p2_crt_args(K, level, n), C.as<uint64_t>(), s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
@@ -743,7 +826,7 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
   if (Qc->K != D->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
   if (Qc->level > D->keys->L) return fail(HFE_ELEVEL, "query level above the database primes");
   if (row0 < 0 || rows < 1 || row0 + rows > D->d1) return fail(HFE_ESHAPE, "row range outside the database");
-  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
+  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
     return fail(HFE_EINVAL, "unknown form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   hfe_rct* R = new (std::nothrow) hfe_rct();
@@ -1164,6 +1247,7 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
   const hfe_db* D = as_handle<hfe_db>(db, kDb);
   if (!D || !items || !outs) return fail(HFE_EINVAL, "invalid database, items or outs");
   if (n < 1 || n > kMaxBatch) return fail(HFE_EINVAL, "batch size must be 1 .. 256");
+  if (form == HFE_FORM_P2_I8) return fail(HFE_EINVAL, "batched calls run the plain, digit or RNS form");
   if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
     return fail(HFE_EINVAL, "unknown form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
@@ -1250,7 +1334,8 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   *out = nullptr;
   const hfe_db* D = as_handle<hfe_db>(db, kDb);
   if (!D) return fail(HFE_EINVAL, "invalid database handle");
-  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8) return fail(HFE_EINVAL, "plans run an int8 form");
+  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
+    return fail(HFE_EINVAL, "plans run the digit or the RNS int8 form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   if (max_items < 1 || max_items > kMaxBatch) return fail(HFE_EINVAL, "max_items must be 1 .. 256");
   if (max_cols < 1 || max_level < 1 || (int)max_level > D->keys->L) return fail(HFE_EINVAL, "bad capacity");

@@ -136,6 +136,48 @@ __device__ __forceinline__ int32_t balanced_mod(int64_t x, int j) {
   return (int32_t)r >= ((int32_t)m + 1) / 2 ? (int32_t)r - (int32_t)m : (int32_t)r;
 }
 
+// ------------------------------------------------------------------ n^2 form: bases and digits
+// x mod m in [0, m) for |x| < 2^48 and 2 <= m < 2^24, rcp = 1 / m rounded to double: x rcp differs
+// from x / m by less than 2^-4, so floor(x rcp) is the quotient or one off, fixed by one step.
+__device__ __forceinline__ int64_t mod_f64(int64_t x, int64_t m, double rcp) {
+  int64_t r = x - (int64_t)floor((double)x * rcp) * m;
+  if (r < 0)
+    r += m;
+  else if (r >= m)
+    r -= m;
+  return r;
+}
+
+// Per base n_j of kP2Bases: n_j, n_j^2 and their reciprocals, computed at compile time.
+struct P2BaseConsts {
+  int32_t n[kP2MaxBases], m[kP2MaxBases];
+  double rcp_n[kP2MaxBases], rcp_m[kP2MaxBases];
+};
+constexpr P2BaseConsts make_p2_base_consts() {
+  P2BaseConsts c{};
+  for (int j = 0; j < kP2MaxBases; ++j) {
+    c.n[j] = kP2Bases[j];
+    c.m[j] = kP2Bases[j] * kP2Bases[j];
+    c.rcp_n[j] = 1.0 / (double)c.n[j];
+    c.rcp_m[j] = 1.0 / (double)c.m[j];
+  }
+  return c;
+}
+__constant__ static P2BaseConsts kP2C = make_p2_base_consts();
+
+// Centered x (|x| < 2^48) -> (M, M') with x = M + n M' (mod n^2) for n = kP2Bases[j], both in
+// [-(n-1)/2, (n-1)/2]: r = x mod n^2, M = the balanced residue of r mod n, M' = the balanced
+// residue of (r - M) / n (an integer in [0, n]) mod n.
+__device__ __forceinline__ void p2_digits(int64_t x, int j, int32_t& M, int32_t& Mp) {
+  const int32_t n = kP2C.n[j], h = (n - 1) / 2;
+  const int32_t r = (int32_t)mod_f64(x, kP2C.m[j], kP2C.rcp_m[j]);
+  M = (int32_t)mod_f64(r, n, kP2C.rcp_n[j]);
+  if (M > h) M -= n;
+  int32_t t = (int32_t)((double)(r - M) * kP2C.rcp_n[j] + 0.5);  // exact multiple of n: nearest is exact
+  if (t == n) t = 0;
+  Mp = t > h ? t - n : t;
+}
+
 // The bytes b of the 4 lanes of a lane quad (lanes 4i .. 4i + 3, lane 4i + e holding byte e),
 // packed into one 32-bit word that every lane of the quad receives (two DPP quad permutations).
 // Every lane of the quad must be active.
@@ -151,7 +193,8 @@ __device__ __forceinline__ uint32_t quad_word(uint32_t b) {
 // L mod p into Xp[c][k] when Xp is given, and, when X is given, for every prime of the level and p
 // the int8 planes of the centered residue, stored by the quad's first lane as one 4-byte word per
 // plane: form 0 the 5 balanced digits (X[z][t][kb][c][kk]), form n > 0 the balanced residues
-// modulo the first n small moduli (X[z][j][kb][c][kk]).
+// modulo the first n small moduli (X[z][j][kb][c][kk]), form -n < 0 the n^2-form digits M, M' of
+// the first n bases (X[z][2j + t][kb][c][kk]).
 __device__ __forceinline__ void lift_lane(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
                                           const LiftArgs& la, int form, uint64_t* Xp, int8_t* X, int64_t c,
                                           int64_t k) {
@@ -162,7 +205,7 @@ __device__ __forceinline__ void lift_lane(const uint64_t* XT, int64_t d3, int64_
   if (!X) return;
   const bool writer = (threadIdx.x & 3) == 0;
   const int64_t kb = k / kKB, kk = k % kKB - (k & 3);
-  const int planes = form == 0 ? kDigits : form;
+  const int planes = form == 0 ? kDigits : form > 0 ? form : -2 * form;
   const int64_t pstride = KB * d3_pad * kKB / 4;  // words between consecutive planes
   // the planes of prime slot z (the level's primes, then p) for centered value x
   auto emit = [&](int z, int64_t x) {
@@ -175,10 +218,20 @@ __device__ __forceinline__ void lift_lane(const uint64_t* XT, int64_t d3, int64_
         const uint32_t w = quad_word((uint32_t)d[t]);
         if (writer) row[t * pstride] = w;
       }
-    } else {
+    } else if (form > 0) {
       for (int j = 0; j < form; ++j) {
         const uint32_t w = quad_word((uint32_t)balanced_mod(x, j));
         if (writer) row[j * pstride] = w;
+      }
+    } else {
+      for (int j = 0; j < -form; ++j) {
+        int32_t M, Mp;
+        p2_digits(x, j, M, Mp);
+        const uint32_t w0 = quad_word((uint32_t)M), w1 = quad_word((uint32_t)Mp);
+        if (writer) {
+          row[2 * j * pstride] = w0;
+          row[(2 * j + 1) * pstride] = w1;
+        }
       }
     }
   };

@@ -131,6 +131,11 @@ namespace hfe {
 constexpr int kRnsMaxMods = 16;
 constexpr int32_t kRnsMods[kRnsMaxMods] = {256, 255, 253, 251, 247, 241, 239, 233,
                                            229, 227, 223, 211, 199, 197, 193, 191};
+// Bases n of the n^2 form (Section 6.3, a matrix modulo n^2 as M + n M'): primes 127 <= n <= 253,
+// largest first.  A database uses the shortest prefix whose squares' product is at least four
+// times the largest exact contraction sum; at most 8 (the product stays below 2^128).
+constexpr int kP2MaxBases = 8;
+constexpr int32_t kP2Bases[kP2MaxBases] = {251, 241, 239, 233, 229, 227, 223, 211};
 }  // namespace hfe
 
 struct hfe_db : hfe::HandleBase {
@@ -143,6 +148,8 @@ struct hfe_db : hfe::HandleBase {
   hfe::DevBuf digits;                      // [prime][5][KB][R_pad][64] int8, i8 form
   int n_rns = 0;                           // small moduli in use (RNS form)
   hfe::DevBuf rns;                         // [prime][n_rns][KB][R_pad][64] int8, RNS form
+  int n_p2 = 0;                            // bases n in use (n^2 form)
+  hfe::DevBuf p2;                          // [prime][2 n_p2][KB][R_pad][64] int8: M, M' per base
 };
 
 struct hfe_qct : hfe::HandleBase {
@@ -275,6 +282,36 @@ struct RnsCrtArgs {
 hipError_t launch_crt_rns(const uint8_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
                           hipStream_t s);
 constexpr int kRnsTileR = 256, kRnsTileQ = 256;  // RNS workgroup tile: rows, widest query columns
+// n^2 form: per base n_j the database and the lifted query as two balanced int8 planes, M and M'
+// with x = M + n_j M' (mod n_j^2) (planes 2j and 2j + 1, layouts as the digit planes); per (prime,
+// base) the products G0 = sum M N and G1 = sum (M N' + M' N) give S mod n_j^2 = G0 + n_j G1, stored
+// as res[z][j][c][r] (uint16); the CRT of those residues gives the exact centered sum, reduced mod
+// the prime into C[z][c][r].
+hipError_t launch_split_db_p2(const uint64_t* Dt_prime, int64_t K, int64_t R, int64_t KB, int64_t R_pad,
+                              uint64_t q, int n_bases, int8_t* planes_prime, hipStream_t s);
+hipError_t launch_lift_p2(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
+                          const LiftArgs& la, int n_bases, int8_t* Xq, hipStream_t s);
+constexpr int kP2TileR = 128, kP2TileQ = 256;  // n^2 workgroup tile: rows, query columns
+struct P2GemmArgs {
+  int nz, n_bases;
+  const int8_t* Dq[kMaxPrimes];                // [2 n_bases][KB][R_pad][64] per prime slot
+  const int8_t* Xq[kMaxPrimes];                // [2 n_bases][KB][d3_pad][64]
+  int32_t n[kP2MaxBases];                      // bases
+  uint16_t* res;                               // [nz][n_bases][d3][R_out], residues < n^2
+  int64_t KB, R_pad, n_db, row0, R_out, d3, d3_pad;  // d3_pad a multiple of kP2TileQ
+};
+hipError_t launch_gemm_p2(const P2GemmArgs& g, hipStream_t s);
+struct P2CrtArgs {
+  int n;                                       // bases in use
+  int32_t m[kP2MaxBases];                      // n_j^2
+  int32_t inv[kP2MaxBases];                    // (M / m_j)^-1 mod m_j, M = prod m
+  float rcp[kP2MaxBases];                      // 1 / m_j
+  Mod mod[kMaxPrimes];                         // prime of each slot
+  uint64_t Mj_mod_q[kMaxPrimes][kP2MaxBases];  // (M / m_j) mod that prime
+  uint64_t M_mod_q[kMaxPrimes];                // M mod that prime
+};
+hipError_t launch_crt_p2(const uint16_t* res, int nz, int64_t n, const P2CrtArgs& ra, uint64_t* C, hipStream_t s);
+
 struct BatchDesc;
 struct BatchHeader;
 struct BatchElemHeader;

@@ -216,7 +216,8 @@ hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_co
   *out = nullptr;
   const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(db));
   if (!db || hb->kind != kDb) return fail(HFE_EINVAL, "invalid database handle");
-  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8) return fail(HFE_EINVAL, "the server runs an int8 form");
+  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
+    return fail(HFE_EINVAL, "the server runs the digit or the RNS int8 form");
   if (!(db->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   if (n_slots < 1 || n_slots > 8 || max_items_per_step < 1 || max_items_per_step > kMaxBatch ||
       max_cols_per_step < 1 || max_level < 1 || (int)max_level > db->keys->L)

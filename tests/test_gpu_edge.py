@@ -22,7 +22,7 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("needs a GPU", allow_module_level=True)
 H = pytest.importorskip("paper_2601_17561_amd")
 
-FORMS = (H.HFE_FORM_PLAIN_U64, H.HFE_FORM_I8_MFMA, H.HFE_FORM_RNS_I8)
+FORMS = (H.HFE_FORM_PLAIN_U64, H.HFE_FORM_I8_MFMA, H.HFE_FORM_RNS_I8, H.HFE_FORM_P2_I8)
 
 
 def _say(msg):
@@ -30,11 +30,13 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("d2", [32768, 130048], ids=["k33280_two_digit_chunks", "k130560_near_rns_limit"])
+@pytest.mark.parametrize("d2", [32768, 65024, 130048],
+                         ids=["k33280_two_digit_chunks", "k65536_n2_limit", "k130560_near_rns_limit"])
 def test_long_k_all_forms_agree_and_decrypt_exactly(d2):
     log_n_db, log_n_q, d1, d3, level = 7, 9, 70, 5, 2
     K = d2 + (1 << log_n_q)
     assert K > 511 * 64 and K < 1 << 17
+    forms = FORMS if K <= 1 << 16 else FORMS[:3]  # the n^2 form needs K <= 2^16
     _say(f"[gpu-edge] K = {K}: keygen, encrypt")
     dev = torch.device("cuda", 0)
     P = H.hfe_default_params(log_n_db, log_n_q, level, d2, d1)
@@ -42,11 +44,14 @@ def test_long_k_all_forms_agree_and_decrypt_exactly(d2):
     rng = np.random.default_rng(d2)
     m_db = rng.integers(-1, 2, (d1, d2)).astype(np.int8)
     m_q = rng.integers(-1, 2, (d3, d2)).astype(np.int8)
-    db = H.hfe_encrypt_db(keys, torch.from_numpy(m_db).to(dev), 32, sum(FORMS))
+    if K > 1 << 16:
+        with pytest.raises(H.HfeError):
+            H.hfe_encrypt_db(keys, torch.from_numpy(m_db).to(dev), 32, H.HFE_FORM_P2_I8)
+    db = H.hfe_encrypt_db(keys, torch.from_numpy(m_db).to(dev), 32, sum(forms))
     q = H.hfe_encrypt(keys, torch.from_numpy(m_q).to(dev), level, 33)
     exact = (m_q.astype(np.int64) @ m_db.astype(np.int64).T)  # d3 x d1
     ref = None
-    for form in FORMS:
+    for form in forms:
         _say(f"[gpu-edge] K = {K}: ccmm form {form}")
         r = H.hfe_ccmm(db, q, 0, d1, form)
         out = H.hfe_export(r, 0)

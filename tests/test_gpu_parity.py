@@ -24,7 +24,7 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("needs a GPU", allow_module_level=True)
 H = pytest.importorskip("paper_2601_17561_amd")
 
-FORMS = {"plain": H.HFE_FORM_PLAIN_U64, "i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8}
+FORMS = {"plain": H.HFE_FORM_PLAIN_U64, "i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}
 
 
 def _say(msg):
@@ -35,7 +35,7 @@ def _say(msg):
 class GpuRun:
     """The hot path of one oracle case on the GPU."""
 
-    def __init__(self, c, forms=H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8):
+    def __init__(self, c, forms=H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8 | H.HFE_FORM_P2_I8):
         w = c.w
         _say(f"[gpu] {w.name}: keygen / encode / encrypt_db")
         self.c = c
@@ -114,7 +114,7 @@ def test_query_ciphertext_bit_exact(name, row0, rows):
         assert np.array_equal(XT[i], c.XT[i]), f"prime {i}"
 
 
-@pytest.mark.parametrize("form", ["plain", "i8", "rns"])
+@pytest.mark.parametrize("form", ["plain", "i8", "rns", "p2"])
 @pytest.mark.parametrize("name,row0,rows", CASES, ids=IDS)
 def test_ccmm_result_bit_exact(name, row0, rows, form):
     g = run_for(name, row0, rows)
@@ -144,7 +144,7 @@ def test_every_i8_tile_configuration_bit_exact(name, row0, rows):
         H.hfe_set_i8_variant(-1)
 
 
-@pytest.mark.parametrize("form", ["plain", "i8", "rns"])
+@pytest.mark.parametrize("form", ["plain", "i8", "rns", "p2"])
 @pytest.mark.parametrize("name,row0,rows", CASES, ids=IDS)
 def test_decrypt_and_match_equal_popcount_truth(name, row0, rows, form):
     g = run_for(name, row0, rows)
@@ -174,7 +174,7 @@ def test_level_below_database_primes():
     _, ip_o = OC.decrypt(c.keys, out, 1, 0, c.w.d1)
     _say("[gpu] tinymulti: level-1 query")
     qct = H.hfe_encrypt(g.keys, g.m_q, 1, Q_SEED + 7)
-    for form in ("plain", "i8", "rns"):
+    for form in ("plain", "i8", "rns", "p2"):
         r = H.hfe_ccmm(g.db, qct, 0, c.w.d1, FORMS[form])
         got = H.hfe_export(r, 0).reshape(1, c.m_q.shape[0], -1).astype(np.int64)
         assert np.array_equal(got[0], out[0]), form
@@ -194,3 +194,10 @@ def test_api_errors_on_device_handles():
     with pytest.raises(H.HfeError) as e:
         H.hfe_encrypt(g.keys, g.m_q, 3, 1)                          # level above L = 2
     assert e.value.status == -3
+    # the n^2 form runs in single calls only
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_ccmm_batched(g.db, [(g.qct, 0, 10)], H.HFE_FORM_P2_I8)
+    assert e.value.status == -1
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_plan_create(g.db, 2, 64, 2, H.HFE_FORM_P2_I8)
+    assert e.value.status == -1

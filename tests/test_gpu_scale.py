@@ -52,7 +52,8 @@ def run():
     q_masks = torch.from_numpy(inp["q_masks"]).to(dev)
     shifts = [int(s) for s in inp["shifts"]]
     m_db = H.hfe_encode(db_codes, db_masks, [0])
-    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED,
+                          H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8 | H.HFE_FORM_P2_I8)
     m_q = H.hfe_encode(torch.from_numpy(inp["q_codes"]).to(dev), q_masks, shifts)
     _say(f"[gpu-scale] {w.name}: encrypt query, ccmm i8 and plain")
     qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
@@ -60,6 +61,8 @@ def run():
     r_pl = H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_PLAIN_U64)
     _say(f"[gpu-scale] {w.name}: ccmm rns")
     r_rns = H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_RNS_I8)
+    _say(f"[gpu-scale] {w.name}: ccmm n^2")
+    r_p2 = H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_P2_I8)
     _say(f"[gpu-scale] {w.name}: decrypt and match")
     v, ip = H.hfe_decrypt(keys, r_i8)
     dec, eye = H.hfe_match(ip, q_masks, shifts, db_masks)
@@ -70,7 +73,7 @@ def run():
     m_db_o = iris.ternary(inp["db_codes"], inp["db_masks"])
     qc, qm = iris.shifted_queries(inp["q_codes"], inp["q_masks"], inp["shifts"])
     m_q_o = iris.ternary(qc, qm)
-    return dict(inp=inp, keys=keys, db=db, qct=qct, r_i8=r_i8, r_pl=r_pl, r_rns=r_rns, v=v, ip=ip, dec=dec, eye=eye,
+    return dict(inp=inp, keys=keys, db=db, qct=qct, r_i8=r_i8, r_pl=r_pl, r_rns=r_rns, r_p2=r_p2, v=v, ip=ip, dec=dec, eye=eye,
                 Po=Po, keys_o=keys_o, m_db_o=m_db_o, m_q_o=m_q_o, qc=qc, qm=qm, m_q=m_q)
 
 
@@ -122,7 +125,7 @@ def test_ccmm_sampled_a_part_entries(run):
     for r, c in ((0, 0), (Po.n_db - 1, 77), (5000, W.d3 - 1)):
         d_row = {pid: prng.uniform_mod(DB_SEED, prng.DBA, pid, np.full(Po.K, r), kk, prime) for pid, prime in ids}
         exp = OC.ccmm_entry(Po, d_row, _query_col(run, c), W.level)
-        for name in ("r_i8", "r_pl", "r_rns"):
+        for name in ("r_i8", "r_pl", "r_rns", "r_p2"):
             for i in range(W.level):
                 got = int(H.hfe_export(run[name], 0, (i * W.d3 + c) * R_out + r, 1)[0])
                 assert got == exp[i], (name, i, r, c)
@@ -136,6 +139,12 @@ def test_i8_equals_plain_on_every_residue(run):
 
 def test_rns_equals_i8_on_every_residue(run):
     a = H.hfe_export(run["r_rns"], 0)
+    b = H.hfe_export(run["r_i8"], 0)
+    assert a.shape == b.shape and np.array_equal(a, b)
+
+
+def test_n2_form_equals_i8_on_every_residue(run):
+    a = H.hfe_export(run["r_p2"], 0)
     b = H.hfe_export(run["r_i8"], 0)
     assert a.shape == b.shape and np.array_equal(a, b)
 
