@@ -68,8 +68,7 @@ enum {
  * least four times the largest exact sum), each centered residue's residue mod n_j^2 written as
  * M + n_j M' with |M|, |M'| <= 125; per base the three int8 MFMA products M N, M N' and M' N with
  * int32 accumulation (K <= 2^16) give the exact sum mod n_j^2, then the Chinese remainder
- * reconstruction and the reduction mod the prime.  Single calls only (hfe_ccmm); batches, plans
- * and servers run the other forms.
+ * reconstruction and the reduction mod the prime.
  * All forms give the same residues.  The database stores 8, 5, n and 2 n bytes per entry and
  * prime for the four forms. */
 typedef enum { HFE_FORM_PLAIN_U64 = 1, HFE_FORM_I8_MFMA = 2, HFE_FORM_RNS_I8 = 4, HFE_FORM_P2_I8 = 8 } hfe_form;
@@ -148,14 +147,15 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
  * Items with the same level and row range form one problem, their query columns side by side (so
  * only a problem pads its columns to whole tiles); a level whose items cover several row ranges is
  * split into one problem over the N_DB A rows for all its columns and one problem per row range
- * over that range's rows.  int8 forms (HFE_FORM_I8_MFMA, HFE_FORM_RNS_I8):
+ * over that range's rows.  int8 forms (HFE_FORM_I8_MFMA, HFE_FORM_RNS_I8, HFE_FORM_P2_I8):
  * one grouped launch lifts and splits every item's query, ONE persistent launch computes the tiles
- * of every problem, prime (and small modulus) (workgroups claim tiles of a device-resident tile
- * table in order), for the RNS form one grouped launch reconstructs the residues mod each prime,
+ * of every problem, prime (and small modulus or base) (workgroups claim tiles of a device-resident
+ * tile table in order), for the RNS and n^2 forms one grouped launch reconstructs the residues mod
+ * each prime,
  * and one grouped launch rescales every item; the digit form's problems share one tile
  * configuration (the forced one, else of the tuned and the default configuration the one that pads
  * the problems least); plain form: one hfe_ccmm per item.  outs[i] receives item i's result handle
- * (release each with hfe_free).  1 <= n <= 256.  HFE_FORM_P2_I8: HFE_EINVAL. */
+ * (release each with hfe_free).  1 <= n <= 256. */
 typedef struct {
   const hfe_qct* q;
   int64_t row0, rows;
@@ -164,8 +164,9 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
                             void* stream, hfe_rct** outs);
 
 /* Reusable batched int8 CCMM for repeated batches (e.g. serving steps), in the int8 form `form`
- * (HFE_FORM_I8_MFMA or HFE_FORM_RNS_I8, prepared in the database): the workspace for up to
- * max_items items, max_cols query columns in total and levels up to max_level is allocated once;
+ * (HFE_FORM_I8_MFMA, HFE_FORM_RNS_I8 or HFE_FORM_P2_I8, prepared in the database): the workspace
+ * for up to max_items items, max_cols query columns in total and levels up to max_level is
+ * allocated once;
  * hfe_plan_run writes the batch's descriptor tables (a host-to-device copy on `stream`) and
  * enqueues the grouped launches; with use_graph they are captured, on the first run that uses a
  * tile configuration, into a hipGraph that later runs with that configuration replay (any later
@@ -193,8 +194,8 @@ hfe_status hfe_autotune(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_
 hfe_status hfe_autotune_save(const char* path);
 hfe_status hfe_autotune_load(const char* path);
 
-/* Continuous-batching server over a resident database, in the int8 form `form` (HFE_FORM_I8_MFMA
- * or HFE_FORM_RNS_I8, prepared in the database).  A worker thread keeps
+/* Continuous-batching server over a resident database, in the int8 form `form` (HFE_FORM_I8_MFMA,
+ * HFE_FORM_RNS_I8 or HFE_FORM_P2_I8, prepared in the database).  A worker thread keeps
  * n_slots steps in flight on their own streams; each step admits queued requests in arrival
  * order while their columns fit the step (at most max_cols_per_step columns, at most
  * max_items_per_step requests, and the memory budget: mem_budget bytes of workspace split over

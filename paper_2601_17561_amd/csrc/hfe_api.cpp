@@ -869,6 +869,17 @@ hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n) {
 // ------------------------------------------------------------------ batched CCMM
 }  // extern "C"
 
+FormShape hfe::form_shape(const hfe_db* D, int form) {
+  FormShape f;
+  f.rns = form == HFE_FORM_RNS_I8;
+  f.p2 = form == HFE_FORM_P2_I8;
+  f.planes = f.rns ? D->n_rns : f.p2 ? 2 * D->n_p2 : kDigits;
+  f.qpad = f.rns ? kRnsTileQ : f.p2 ? kP2TileQ : kQueryPad;
+  f.res_bytes = f.rns ? 1 : f.p2 ? 2 : 0;
+  f.lift_form = f.rns ? D->n_rns : f.p2 ? -D->n_p2 : 0;
+  return f;
+}
+
 namespace {
 // Byte layout of the descriptor tables of a batch of up to `items` items and `problems` problems
 // (256-byte aligned parts): contraction (per problem), lift (per item), rescale (per item), RNS
@@ -994,7 +1005,8 @@ Grouping group_items(const hfe_batch_item* items, int n) {
   return g;
 }
 
-// Sizes of a batch for a form (HFE_FORM_I8_MFMA with the digit tile `variant`, or HFE_FORM_RNS_I8),
+// Sizes of a batch for a form (HFE_FORM_I8_MFMA with the digit tile `variant`, HFE_FORM_RNS_I8 or
+// HFE_FORM_P2_I8),
 // and (when blob != nullptr) its descriptor tables pointing into the given workspace (xd_base,
 // c_base, res_base) and result arrays (outs[i]).
 BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int form, int variant, int8_t* xd_base,
@@ -1002,9 +1014,10 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
                       const BlobLayout& L) {
   const hfe_keys* K = D->keys;
   const int64_t ndb = 1ll << K->P.log_n_db;
-  const bool rns = form == HFE_FORM_RNS_I8;
-  const int planes = rns ? D->n_rns : kDigits;
-  const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
+  const FormShape fs = form_shape(D, form);
+  const bool rns = fs.rns, small = fs.res_bytes > 0;
+  const int planes = fs.planes;
+  const int64_t qpad = fs.qpad;
   const Grouping gr = group_items(items, n);
   const int np = (int)gr.p.size();
   BatchSizes z;
@@ -1049,7 +1062,7 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
       std::memset(&g, 0, sizeof(g));
       g.Xd = xd_base + xd_off[P.owner] + P.xc0 * kKB;
       g.C = c_base + c_off[b];
-      g.res = rns ? res_base + res_off[b] : nullptr;
+      g.res = small ? res_base + res_off[b] : nullptr;
       // output row r < n_db is database row r, row r >= n_db is row n_db + row0 + (r - n_db)
       g.n_db = P.a_rows ? ndb : 0;
       g.row0 = P.a_rows ? P.row0 : ndb + P.row0;
@@ -1062,7 +1075,7 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
         g.slot[zz] = zz < level ? zz : K->L;
         g.mod[zz] = K->mods[g.slot[zz]];
       }
-      if (rns) {
+      if (small) {
         BatchCrtDesc& c = reinterpret_cast<BatchCrtDesc*>(blob + L.cd)[k];
         std::memset(&c, 0, sizeof(c));
         c.res = g.res;
@@ -1074,16 +1087,20 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
         c.pslot = K->L;
       }
     }
-    tiles += rns ? rns_batched_tiles(d3, R_out[b], nz, planes, tq[b]) : i8_batched_tiles(variant, d3, R_out[b], nz);
+    tiles += rns      ? rns_batched_tiles(d3, R_out[b], nz, planes, tq[b])
+             : fs.p2 ? p2_batched_tiles(d3, R_out[b], nz, D->n_p2)
+                     : i8_batched_tiles(variant, d3, R_out[b], nz);
     if (rns && tq[b] == 256) {
       tiles_wide = tiles;
       n_wide = k + 1;
     }
-    crt_e += ((int64_t)nz * ((d3 * R_out[b] + 3) / 4) + 255) / 256 * 256;  // the CRT's unit: 4 entries
-    // each problem's C and residues start at a multiple of 4 entries (the CRT's word loads and
-    // 16-byte stores)
+    // the CRT's unit: 4 entries (RNS form) or 2 (n^2 form) of one prime slot
+    const int64_t unit = fs.p2 ? 2 : 4;
+    crt_e += ((int64_t)nz * ((d3 * R_out[b] + unit - 1) / unit) + 255) / 256 * 256;
+    // each problem's C starts at a multiple of 4 entries and its residues at a multiple of 8 bytes
+    // (the CRT's word loads and 16-byte stores)
     z.c_elems += ((size_t)nz * d3 * R_out[b] + 3) / 4 * 4;
-    if (rns) z.res_elems += ((size_t)nz * planes * d3 * R_out[b] + 3) / 4 * 4;
+    if (small) z.res_elems += ((size_t)nz * (fs.p2 ? D->n_p2 : planes) * d3 * R_out[b] * fs.res_bytes + 7) / 8 * 8;
     z.max_level = std::max(z.max_level, level);
   }
   int64_t lift_e = 0, resc_e = 0;
@@ -1146,8 +1163,8 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
     rh->total = resc_e;
     rh->n = n;
     BatchElemHeader* ch = reinterpret_cast<BatchElemHeader*>(blob + L.ch);
-    ch->total = rns ? crt_e : 0;
-    ch->n = rns ? np : 0;
+    ch->total = small ? crt_e : 0;
+    ch->n = small ? np : 0;
   }
   return z;
 }
@@ -1166,8 +1183,10 @@ int device_cus() {
 }
 
 int gemm_grid_for(int form, int variant) {
-  // RNS form: variant is the query tile width (256 or 128)
-  const int g = device_cus() * (form == HFE_FORM_RNS_I8 ? rns_wgs_per_cu(variant) : i8_variant_wgs_per_cu(variant));
+  // RNS form: variant is the query tile width (256 or 128); n^2 form: one workgroup per CU
+  const int g = device_cus() * (form == HFE_FORM_RNS_I8  ? rns_wgs_per_cu(variant)
+                                : form == HFE_FORM_P2_I8 ? 1
+                                                         : i8_variant_wgs_per_cu(variant));
   return (g + kXcds - 1) / kXcds * kXcds;
 }
 constexpr int kElemGrid = 4096;
@@ -1177,7 +1196,7 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
   const bool rns = form == HFE_FORM_RNS_I8;
   HFE_LAUNCH(launch_lift_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.lh),
                                  reinterpret_cast<const BatchLiftDesc*>(dblob + L.ld), D->K, D->KB,
-                                 rns ? D->n_rns : 0, elem_grid, s));
+                                 form_shape(D, form).lift_form, elem_grid, s));
   const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(dblob + L.gh);
   const int64_t ndb = 1ll << D->keys->P.log_n_db;
   if (rns) {
@@ -1202,6 +1221,20 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
     HFE_LAUNCH(launch_crt_rns_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.ch),
                                       reinterpret_cast<const BatchCrtDesc*>(dblob + L.cd),
                                       make_rns_crt_args(D->keys, D->keys->L, D->n_rns), elem_grid, s));
+  } else if (form == HFE_FORM_P2_I8) {
+    P2BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.hdr = hdr;
+    a.next = const_cast<uint32_t*>(hdr->next);
+    a.desc = reinterpret_cast<const BatchDesc*>(dblob + L.gd);
+    a.Dq = D->p2.as<int8_t>();
+    a.n_bases = D->n_p2;
+    a.KB = D->KB;
+    a.R_pad = D->R_pad;
+    HFE_LAUNCH(launch_gemm_p2_batched(a, gemm_grid_for(form, 0), s));
+    HFE_LAUNCH(launch_crt_p2_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.ch),
+                                     reinterpret_cast<const BatchCrtDesc*>(dblob + L.cd),
+                                     make_p2_crt_args(D->keys, D->keys->L, D->n_p2), elem_grid, s));
   } else {
     BatchGemmArgs a;
     a.hdr = hdr;
@@ -1247,8 +1280,7 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
   const hfe_db* D = as_handle<hfe_db>(db, kDb);
   if (!D || !items || !outs) return fail(HFE_EINVAL, "invalid database, items or outs");
   if (n < 1 || n > kMaxBatch) return fail(HFE_EINVAL, "batch size must be 1 .. 256");
-  if (form == HFE_FORM_P2_I8) return fail(HFE_EINVAL, "batched calls run the plain, digit or RNS form");
-  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
+  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
     return fail(HFE_EINVAL, "unknown form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   for (int i = 0; i < n; ++i) {
@@ -1334,8 +1366,8 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   *out = nullptr;
   const hfe_db* D = as_handle<hfe_db>(db, kDb);
   if (!D) return fail(HFE_EINVAL, "invalid database handle");
-  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
-    return fail(HFE_EINVAL, "plans run the digit or the RNS int8 form");
+  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
+    return fail(HFE_EINVAL, "plans run an int8 form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   if (max_items < 1 || max_items > kMaxBatch) return fail(HFE_EINVAL, "max_items must be 1 .. 256");
   if (max_cols < 1 || max_level < 1 || (int)max_level > D->keys->L) return fail(HFE_EINVAL, "bad capacity");
@@ -1348,9 +1380,9 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   P->max_items = max_items;
   P->max_cols = max_cols;
   P->max_level = (int)max_level;
-  const bool rns = form == HFE_FORM_RNS_I8;
-  const int planes = rns ? D->n_rns : kDigits;
-  const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
+  const FormShape fs = form_shape(D, form);
+  const int planes = fs.planes;
+  const int64_t qpad = fs.qpad;
   const int64_t ndb = 1ll << D->keys->P.log_n_db;
   const int64_t R_max = ndb + D->d1;
   // an owner problem pads at most qpad - 1 columns per item (two items at least when it also feeds
@@ -1359,13 +1391,18 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   P->xd_cap = (size_t)(max_level + 1) * planes * D->KB * cols_pad * kKB;
   // + the alignment of each problem's start
   P->c_cap = (size_t)(max_level + 1) * max_cols * R_max + 4 * (size_t)max_problems(max_items);
-  P->res_cap = rns ? (size_t)(max_level + 1) * planes * max_cols * R_max + 4 * (size_t)max_problems(max_items) : 0;
+  // residues of the small-modulus forms (bytes; one per modulus or two per base), each problem's
+  // start aligned to 8 bytes
+  const int res_planes = fs.p2 ? D->n_p2 : fs.rns ? D->n_rns : 0;
+  P->res_cap = fs.res_bytes ? (size_t)(max_level + 1) * res_planes * max_cols * R_max * fs.res_bytes +
+                                  8 * (size_t)max_problems(max_items)
+                            : 0;
   P->out_cap = (size_t)max_level * max_cols * R_max;
   const BlobLayout L(max_items, max_problems(max_items));
   P->blob_bytes = L.bytes;
   hfe_status st = P->ws_xd.alloc(P->xd_cap, nullptr);
   if (st == HFE_OK) st = P->ws_c.alloc(sizeof(uint64_t) * P->c_cap, nullptr);
-  if (st == HFE_OK && rns) st = P->ws_res.alloc(P->res_cap, nullptr);
+  if (st == HFE_OK && fs.res_bytes) st = P->ws_res.alloc(P->res_cap, nullptr);
   if (st == HFE_OK) st = P->ws_out.alloc(sizeof(uint64_t) * P->out_cap, nullptr);
   if (st == HFE_OK) st = P->desc.alloc(L.bytes, nullptr);
   hipError_t e = hipSuccess;

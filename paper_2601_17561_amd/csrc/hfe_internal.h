@@ -332,6 +332,22 @@ struct RnsBatchArgs {
 };
 int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod, int tq);
 hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, int tq, hipStream_t s);
+// Batched n^2 contraction: problem b's tiles are [tile_begin, tile_begin + p2_batched_tiles(...)),
+// ordered (z, base, XCD-ordered tile); one persistent launch claims every problem's tiles through
+// hdr->next.  Residues (uint16) go to desc.res.
+struct P2BatchArgs {
+  const BatchHeader* hdr;
+  uint32_t* next;                              // hdr->next
+  const BatchDesc* desc;
+  const int8_t* Dq;                            // database planes, all slots: [slot][2 n_bases][KB][R_pad][64]
+  int32_t n_bases, pad_;
+  int64_t KB, R_pad;
+};
+int64_t p2_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_bases);
+hipError_t launch_gemm_p2_batched(const P2BatchArgs& a, int grid, hipStream_t s);
+// ra indexed by database slot; d[b].res points at uint16 residues
+hipError_t launch_crt_p2_batched(const BatchElemHeader* hdr, const BatchCrtDesc* d, const P2CrtArgs& ra, int grid,
+                                 hipStream_t s);
 // ra indexed by database slot (mod, Mj_mod_q, M_mod_q of slot z at [z])
 hipError_t launch_crt_rns_batched(const BatchElemHeader* hdr, const BatchCrtDesc* d, const RnsCrtArgs& ra,
                                   int grid, hipStream_t s);
@@ -456,13 +472,14 @@ struct BatchRescaleDesc {            // one per item
   int64_t split, Ra, Rb, zstride, zstride_b;
   RescaleArgs ra;
 };
-struct BatchCrtDesc {                // RNS form, one per problem
-  const uint8_t* res;             // [nz][n_mod][n]
+struct BatchCrtDesc {                // small-modulus forms, one per problem
+  const uint8_t* res;             // [nz][n_mod][n] bytes (RNS form) or uint16 (n^2 form)
   uint64_t* C;                    // [nz][n]
   int64_t n, elem_begin;          // n = d3 x R_out of the problem; elements nz x n
   int32_t nz, level, pslot, pad_; // database slot of z: z < level ? z : pslot (the special prime)
 };
-// form: 0 = the 5-digit planes, n > 0 = the RNS form with n small moduli
+// form: 0 = the 5-digit planes, n > 0 = the RNS form with n small moduli, -n < 0 = the n^2 form
+// with n bases
 hipError_t launch_lift_batched(const BatchElemHeader* hdr, const BatchLiftDesc* d, int64_t K, int64_t KB,
                                int form, int grid, hipStream_t s);
 hipError_t launch_rescale_batched(const BatchElemHeader* hdr, const BatchRescaleDesc* d, int grid, hipStream_t s);
@@ -499,6 +516,15 @@ struct hfe_plan : hfe::HandleBase {
 };
 
 namespace hfe {
+// Batch parameters of an int8 form of a database: int8 planes per prime slot, query column padding,
+// bytes per residue of the small-modulus contraction (0: the contraction writes C itself), and the
+// form code of the query lift (0 digits, n RNS moduli, -n n^2 bases).
+struct FormShape {
+  bool rns = false, p2 = false;
+  int planes = 0, res_bytes = 0, lift_form = 0;
+  int64_t qpad = 0;
+};
+FormShape form_shape(const hfe_db* D, int form);
 // Decryption of a result into caller-provided scratch y ([level][d3][rows] uint64).
 hfe_status decrypt_impl(const hfe_keys* K, const hfe_rct* R, double* v, int32_t* ip, uint64_t* y, hipStream_t s);
 void destroy_server(void* handle);  // hfe_server.cpp

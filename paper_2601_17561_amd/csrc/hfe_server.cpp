@@ -216,20 +216,21 @@ hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_co
   *out = nullptr;
   const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(db));
   if (!db || hb->kind != kDb) return fail(HFE_EINVAL, "invalid database handle");
-  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8)
-    return fail(HFE_EINVAL, "the server runs the digit or the RNS int8 form");
+  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
+    return fail(HFE_EINVAL, "the server runs an int8 form");
   if (!(db->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
   if (n_slots < 1 || n_slots > 8 || max_items_per_step < 1 || max_items_per_step > kMaxBatch ||
       max_cols_per_step < 1 || max_level < 1 || (int)max_level > db->keys->L)
     return fail(HFE_EINVAL, "bad server configuration");
-  // workspace per query column of one step: query planes, RNS residues, contraction output,
-  // result, decryption scratch (plus the column padding of each request)
-  const bool rns = form == HFE_FORM_RNS_I8;
-  const int planes = rns ? db->n_rns : kDigits;
-  const int64_t qpad = rns ? kRnsTileQ : kQueryPad;
+  // workspace per query column of one step: query planes, small-modulus residues, contraction
+  // output, result, decryption scratch (plus the column padding of each request)
+  const FormShape fs = form_shape(db, form);
+  const int planes = fs.planes;
+  const int64_t qpad = fs.qpad;
+  const int res_planes = fs.p2 ? db->n_p2 : fs.rns ? db->n_rns : 0;
   const int64_t ndb = 1ll << db->keys->P.log_n_db, R_max = ndb + db->d1;
   const size_t per_col = (size_t)(max_level + 1) * planes * db->KB * kKB +
-                         (rns ? (size_t)(max_level + 1) * planes * R_max : 0) +
+                         (size_t)(max_level + 1) * res_planes * R_max * fs.res_bytes +
                          (size_t)(max_level + 1) * R_max * 8 + (size_t)max_level * R_max * 8 +
                          (size_t)max_level * db->d1 * 8;
   const size_t pad = (size_t)max_items_per_step * (qpad - 1) * (max_level + 1) * planes * db->KB * kKB;

@@ -22,7 +22,8 @@ __device__ __forceinline__ int find_problem(const int64_t* begins, int n, int64_
   return __builtin_amdgcn_readfirstlane(lo);
 }
 
-// form 0: 5 digit planes per prime; form n > 0: the RNS form with n small moduli.
+// form 0: 5 digit planes per prime; form n > 0: the RNS form with n small moduli; form -n < 0: the
+// n^2 form with n bases (planes M, M' per base).
 __global__ void __launch_bounds__(kChunk) k_lift_batched(const BatchElemHeader* hdr, const BatchLiftDesc* d,
                                                          int64_t K, int64_t KB, int form) {
   __shared__ int64_t begins[kMaxBatch];

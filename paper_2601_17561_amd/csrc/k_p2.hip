@@ -97,20 +97,25 @@ struct P2Cfg {
   static_assert(TQ % (16 * NW) == 0 && TR % (16 * NW) == 0, "whole loads per wave and plane");
 };
 
-__global__ void __launch_bounds__(64 * P2Cfg::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_gemm_p2(P2GemmArgs g) {
+// One output tile (rows r0.., query columns c0..) of one (prime, base j) product: X and D are the
+// base's plane M of the query and of the database (M' follows one plane later), res its residue
+// plane [d3][R_out].
+struct P2Tile {
+  const int8_t* X;
+  const int8_t* D;
+  uint16_t* res;
+  int j;
+  int64_t KB, R_pad, d3_pad, n_db, row0, R_out, d3, r0, c0;
+};
+
+__device__ __forceinline__ void p2_tile(const P2Tile& g, int8_t* lds) {
   using C = P2Cfg;
-  __shared__ __attribute__((aligned(16))) int8_t lds[C::LDS];
-  const int j = blockIdx.y, z = blockIdx.z;
-  const int64_t n_ct = (g.d3 + C::TQ - 1) / C::TQ, n_rt = (g.R_out + C::TR - 1) / C::TR;
-  const int64_t l = blockIdx.x, xcd = l % kXcds, jj = l / kXcds;
-  const int64_t rt = (jj / n_ct) * kXcds + xcd, ct = jj % n_ct;
-  if (rt >= n_rt) return;
-  const int64_t r0 = rt * C::TR, c0 = ct * C::TQ;
+  const int j = g.j;
+  const int64_t r0 = g.r0, c0 = g.c0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wq = wave % C::NQ, wr = wave / C::NQ;
-  const int8_t* X = g.Xq[z] + (size_t)(2 * j) * g.KB * g.d3_pad * kKB;  // plane M of this base
-  const int8_t* D = g.Dq[z] + (size_t)(2 * j) * g.KB * g.R_pad * kKB;
+  const int8_t* X = g.X;
+  const int8_t* D = g.D;
   const size_t planeA = (size_t)g.KB * g.d3_pad * kKB, planeB = (size_t)g.KB * g.R_pad * kKB;
   const size_t stepA = (size_t)g.d3_pad * kKB, stepB = (size_t)g.R_pad * kKB;
   // Load i of a wave fills stage row u = 16 (wave + NW i) + lane / 4 of the stacked planes (u / T
@@ -212,7 +217,7 @@ k_gemm_p2(P2GemmArgs g) {
   // row l % 32)
   const int32_t n = kP2C.n[j], m = kP2C.m[j];
   const double rn = kP2C.rcp_n[j], rm = kP2C.rcp_m[j];
-  uint16_t* res = g.res + ((size_t)z * g.n_bases + j) * g.d3 * g.R_out;
+  uint16_t* res = g.res;
 #pragma unroll
   for (int b = 0; b < C::WRB; ++b) {
     const int64_t r = r0 + wr * 32 * C::WRB + b * 32 + (lane & 31);
@@ -228,6 +233,72 @@ k_gemm_p2(P2GemmArgs g) {
         res[c * g.R_out + r] = (uint16_t)v;
       }
   }
+}
+
+__global__ void __launch_bounds__(64 * P2Cfg::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_gemm_p2(P2GemmArgs g) {
+  using C = P2Cfg;
+  __shared__ __attribute__((aligned(16))) int8_t lds[C::LDS];
+  const int j = blockIdx.y, z = blockIdx.z;
+  const int64_t n_ct = (g.d3 + C::TQ - 1) / C::TQ, n_rt = (g.R_out + C::TR - 1) / C::TR;
+  const int64_t l = blockIdx.x, xcd = l % kXcds, jj = l / kXcds;
+  const int64_t rt = (jj / n_ct) * kXcds + xcd, ct = jj % n_ct;
+  if (rt >= n_rt) return;
+  P2Tile t{g.Xq[z] + (size_t)(2 * j) * g.KB * g.d3_pad * kKB, g.Dq[z] + (size_t)(2 * j) * g.KB * g.R_pad * kKB,
+           g.res + ((size_t)z * g.n_bases + j) * g.d3 * g.R_out, j, g.KB, g.R_pad, g.d3_pad, g.n_db, g.row0,
+           g.R_out, g.d3, rt * C::TR, ct * C::TQ};
+  p2_tile(t, lds);
+}
+
+// Persistent batched form: problem b's tiles are ordered (z, base, XCD-ordered tile), starting at its
+// tile_begin; workgroups claim tiles in order from one counter per XCD (tile t = 8 i + xcd), as the
+// digit form's batched kernel.
+__global__ void __launch_bounds__(64 * P2Cfg::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_gemm_p2_batched(P2BatchArgs a) {
+  using C = P2Cfg;
+  __shared__ __attribute__((aligned(16))) int8_t lds[C::LDS];
+  const int np = a.hdr->n;
+  const int64_t total = a.hdr->total_tiles;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = total / kXcds;
+  for (;;) {
+    __syncthreads();  // the previous tile is done with LDS
+    if (threadIdx.x == 0) *reinterpret_cast<uint32_t*>(lds) = atomicAdd(a.next + xcd, 1u);
+    __syncthreads();
+    const int64_t jc = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t*>(lds));
+    __syncthreads();  // every thread has read the claim before the tile overwrites LDS
+    if (jc >= per_xcd) break;
+    const int64_t t = jc * kXcds + xcd;
+    int lo = 0, hi = np - 1;  // last problem whose first tile is <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.desc[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    const BatchDesc& d = a.desc[lo];
+    const int64_t n_ct = (d.d3 + C::TQ - 1) / C::TQ, n_rt = (d.R_out + C::TR - 1) / C::TR;
+    const int64_t per_base = (n_rt + kXcds - 1) / kXcds * kXcds * n_ct;
+    const int64_t local = t - d.tile_begin;
+    const int zj = (int)(local / per_base);
+    const int z = zj / a.n_bases, j = zj % a.n_bases;
+    const int64_t l = local % per_base, lj = l / kXcds;
+    const int64_t rt = (lj / n_ct) * kXcds + l % kXcds, ct = lj % n_ct;
+    if (rt >= n_rt) continue;
+    P2Tile tl{d.Xd + (size_t)(z * a.n_bases + j) * 2 * a.KB * d.d3_pad * kKB,
+              a.Dq + (size_t)(d.slot[z] * a.n_bases + j) * 2 * a.KB * a.R_pad * kKB,
+              reinterpret_cast<uint16_t*>(d.res) + ((size_t)z * a.n_bases + j) * d.d3 * d.R_out, j, a.KB, a.R_pad,
+              d.d3_pad, d.n_db, d.row0, d.R_out, d.d3, rt * C::TR, ct * C::TQ};
+    p2_tile(tl, lds);
+  }
+}
+
+int64_t p2_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_bases) {
+  const int64_t n_ct = (d3 + kP2TileQ - 1) / kP2TileQ, n_rt = (R_out + kP2TileR - 1) / kP2TileR;
+  return (n_rt + kXcds - 1) / kXcds * kXcds * n_ct * nz * n_bases;
+}
+
+hipError_t launch_gemm_p2_batched(const P2BatchArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemm_p2_batched, dim3((unsigned)grid), dim3(64 * P2Cfg::NW), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm_p2(const P2GemmArgs& g, hipStream_t s) {
@@ -247,11 +318,10 @@ hipError_t launch_gemm_p2(const P2GemmArgs& g, hipStream_t s) {
 // float sum of at most 8 terms is off by less than 2^-20); then
 // C = sum_j y_j ((M/m_j) mod q) - a (M mod q) mod q, the sum below 8 * 2^16 * 2^36.
 // Thread: 2 consecutive entries of one prime slot (blockIdx.y), residues read as one 4-byte word.
-__global__ void __launch_bounds__(256) k_crt_p2(const uint16_t* res, int64_t n, P2CrtArgs ra, uint64_t* C) {
-  const int z = blockIdx.y;
-  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
-  if (e0 >= n) return;
-  const uint16_t* r = res + (size_t)z * ra.n * n;
+// Entries e0, e0 + 1 (those below n) of one prime slot: r = that slot's first residue plane
+// ([n_bases][n] uint16), out = its n results; ra indexed by `slot`.
+__device__ __forceinline__ void crt_pair(const uint16_t* r, int64_t n, const P2CrtArgs& ra, int slot, uint64_t* out,
+                                         int64_t e0) {
   const int cnt = e0 + 1 < n ? 2 : 1;
   float frac[2] = {0.f, 0.f};
   uint64_t acc[2] = {0, 0};
@@ -271,14 +341,55 @@ __global__ void __launch_bounds__(256) k_crt_p2(const uint16_t* res, int64_t n, 
     for (int b = 0; b < 2; ++b) {
       const uint32_t y = (uint32_t)mod_f64((int64_t)s2[b] * ra.inv[j], m, rcp);
       frac[b] = fmaf((float)y, ra.rcp[j], frac[b]);
-      acc[b] += (uint64_t)y * ra.Mj_mod_q[z][j];
+      acc[b] += (uint64_t)y * ra.Mj_mod_q[slot][j];
     }
   }
-  const Mod md = ra.mod[z];
+  const Mod md = ra.mod[slot];
   for (int b = 0; b < cnt; ++b) {
     const uint64_t a = (uint64_t)(frac[b] + 0.5f);
-    C[(size_t)z * n + e0 + b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[z], md.q, md.mu), md.q);
+    out[e0 + b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
   }
+}
+
+__global__ void __launch_bounds__(256) k_crt_p2(const uint16_t* res, int64_t n, P2CrtArgs ra, uint64_t* C) {
+  const int z = blockIdx.y;
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
+  if (e0 >= n) return;
+  crt_pair(res + (size_t)z * ra.n * n, n, ra, z, C + (size_t)z * n, e0);
+}
+
+// Batched: every problem's residues (BatchCrtDesc, res pointing at uint16 residues), in units of 2
+// entries of one prime slot; each problem's units start at a multiple of 256.  ra indexed by
+// database slot.
+__global__ void __launch_bounds__(256) k_crt_p2_batched(const BatchElemHeader* hdr, const BatchCrtDesc* d,
+                                                        P2CrtArgs ra) {
+  __shared__ int64_t begins[kMaxBatch + kMaxPrimes];  // one entry per problem (items + split levels)
+  const int n = hdr->n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) begins[i] = d[i].elem_begin;
+  __syncthreads();
+  const int64_t total = hdr->total;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < total; base += (int64_t)gridDim.x * 256) {
+    int lo = 0, hi = n - 1;  // last problem whose first unit is <= base (uniform over the block)
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (begins[mid] <= base) lo = mid; else hi = mid - 1;
+    }
+    const BatchCrtDesc& p = d[__builtin_amdgcn_readfirstlane(lo)];
+    const int64_t nq = (p.n + 1) / 2;
+    const int64_t e = base + threadIdx.x - p.elem_begin;
+    if (e >= (int64_t)p.nz * nq) continue;
+    const int z = (int)(e / nq);
+    const int64_t i = e - z * nq;
+    const int slot = z < p.level ? z : p.pslot;
+    crt_pair(reinterpret_cast<const uint16_t*>(p.res) + (size_t)z * ra.n * p.n, p.n, ra, slot, p.C + (size_t)z * p.n,
+             2 * i);
+  }
+}
+
+hipError_t launch_crt_p2_batched(const BatchElemHeader* hdr, const BatchCrtDesc* d, const P2CrtArgs& ra, int grid,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_crt_p2_batched, dim3((unsigned)grid), dim3(256), 0, s, hdr, d, ra);
+  return hipGetLastError();
 }
 
 hipError_t launch_crt_p2(const uint16_t* res, int nz, int64_t n, const P2CrtArgs& ra, uint64_t* C, hipStream_t s) {

@@ -42,7 +42,8 @@ def env():
     P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
     keys = H.hfe_keygen(P, KEY_SEED)
     m_db = torch.from_numpy(c.m_db).to(dev)
-    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED,
+                          H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8 | H.HFE_FORM_P2_I8)
     rng = np.random.default_rng(7)
     # items: (m_q rows, level, row0, rows); the first is the oracle case itself
     specs = [(c.m_q, 2, 0, w.d1, Q_SEED), (rng.integers(-1, 2, (3, w.d2)), 1, 10, 100, 501),
@@ -118,6 +119,24 @@ def test_single_rns_calls_equal_digit_form_on_every_item(env):
     _check_results(env, res, "single rns")
 
 
+def test_batched_n2_equals_single_calls_and_oracle(env):
+    _say("[gpu-batched] hfe_ccmm_batched n^2")
+    res = H.hfe_ccmm_batched(env["db"], env["items"], H.HFE_FORM_P2_I8)
+    torch.cuda.synchronize()
+    _check_results(env, res, "batched n^2")
+
+
+def test_single_n2_calls_equal_digit_form_on_every_item(env):
+    # the items include an odd d3 x R_out (1 column x 129 rows), where the n^2 CRT reads its 2-byte
+    # residues one by one, and even ones, where it reads 4-byte words
+    _say("[gpu-batched] single hfe_ccmm calls, n^2 form, every item")
+    res = [H.hfe_ccmm(env["db"], q, row0, rows, H.HFE_FORM_P2_I8) for q, row0, rows in env["items"]]
+    torch.cuda.synchronize()
+    n_db = env["c"].P.n_db
+    assert any(mq.shape[0] * (n_db + it[2]) % 2 for mq, it in zip(env["mqs"], env["items"]))
+    _check_results(env, res, "single n^2")
+
+
 def test_batched_plain_equals_i8(env):
     _say("[gpu-batched] hfe_ccmm_batched plain")
     a = H.hfe_ccmm_batched(env["db"], env["items"], H.HFE_FORM_PLAIN_U64)
@@ -126,11 +145,14 @@ def test_batched_plain_equals_i8(env):
         assert np.array_equal(_residues(x), _residues(y))
 
 
-@pytest.mark.parametrize("form", ["i8", "rns"])
+PLAN_FORMS = {"i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}
+
+
+@pytest.mark.parametrize("form", ["i8", "rns", "p2"])
 def test_plan_graph_replays(env, form):
     items = env["items"]
     _say(f"[gpu-batched] plan ({form}): eager run, graph capture, replays with eager work between")
-    plan = H.hfe_plan_create(env["db"], 8, 512, 2, H.HFE_FORM_I8_MFMA if form == "i8" else H.HFE_FORM_RNS_I8)
+    plan = H.hfe_plan_create(env["db"], 8, 512, 2, PLAN_FORMS[form])
     H.hfe_plan_run(plan, items, use_graph=False)
     torch.cuda.synchronize()
     _check_results(env, [H.hfe_plan_result(plan, i) for i in range(len(items))], "plan eager")

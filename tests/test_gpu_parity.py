@@ -194,10 +194,3 @@ def test_api_errors_on_device_handles():
     with pytest.raises(H.HfeError) as e:
         H.hfe_encrypt(g.keys, g.m_q, 3, 1)                          # level above L = 2
     assert e.value.status == -3
-    # the n^2 form runs in single calls only
-    with pytest.raises(H.HfeError) as e:
-        H.hfe_ccmm_batched(g.db, [(g.qct, 0, 10)], H.HFE_FORM_P2_I8)
-    assert e.value.status == -1
-    with pytest.raises(H.HfeError) as e:
-        H.hfe_plan_create(g.db, 2, 64, 2, H.HFE_FORM_P2_I8)
-    assert e.value.status == -1

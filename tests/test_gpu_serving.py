@@ -36,7 +36,8 @@ def env():
     _say("[gpu-serving] tinymulti: keygen / encrypt database")
     P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
     keys = H.hfe_keygen(P, KEY_SEED)
-    db = H.hfe_encrypt_db(keys, torch.from_numpy(c.m_db).to(dev), DB_SEED, H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
+    db = H.hfe_encrypt_db(keys, torch.from_numpy(c.m_db).to(dev), DB_SEED,
+                          H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8 | H.HFE_FORM_P2_I8)
     rng = np.random.default_rng(11)
     reqs = []
     for i, d3 in enumerate([1, 7, 16, 33, 2, 40, 16, 5, 24, 3, 12, 9]):
@@ -63,10 +64,10 @@ def _run(srv, env, idx, burst):
     return {i: o.cpu().numpy() for i, o in outs.items()}
 
 
-FORMS = {"i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8}
+FORMS = {"i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}
 
 
-@pytest.mark.parametrize("form", ["i8", "rns"])
+@pytest.mark.parametrize("form", ["i8", "rns", "p2"])
 def test_same_result_alone_and_in_the_mix(env, form):
     _say(f"[gpu-serving] server ({form}): requests alone, then in a burst")
     srv = H.hfe_server_create(env["db"], 2 << 30, 64, 8, 2, 2, FORMS[form])
