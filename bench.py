@@ -131,13 +131,13 @@ def run_batched(args, H, torch):
     """Uneven batch: items of 1-64 eyes x 16 shifts at levels 1-5 (2-6 primes with p) against
     database shards of 2,048-14,336 codes, as one batched call (grouped persistent launches; the
     workspace sized to the batch, which a plan would size for its worst case), against the same
-    items as one hfe_ccmm call each, for both int8 forms."""
+    items as one hfe_ccmm call each, for the three int8 forms."""
     w = S.PAPER_SHARE_L5
     n_db, K = 1 << w.log_n_db, w.d2 + (1 << w.log_n_q)
     mix = S.batched_mix(w.seed, args.batch_items, w.d1, 64, w.n_q_primes, 2048)
     shifts = [int(x) for x in S.default_shifts(16)]
     log(f"batched: encrypting the {w.d1}-code database with {w.n_q_primes} query primes + p (int8 forms)")
-    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
+    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8 | H.HFE_FORM_P2_I8)
     items = []
     for i, it in enumerate(mix):
         items.append((encrypt_eyes(H, torch, keys, w, i, it.eyes, it.level, shifts), it.row0, it.rows))
@@ -152,7 +152,11 @@ def run_batched(args, H, torch):
     tq.free()
     qs, p_special = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1).primes()
     n_mod = rns_moduli(w, max(list(qs) + [p_special]))
-    for name, form, per_mac in (("i8", H.HFE_FORM_I8_MFMA, 50), ("rns", H.HFE_FORM_RNS_I8, 2 * n_mod)):
+    n_b = p2_bases(w, max(list(qs) + [p_special]))
+    tiles = {"rns": f"rns 256x256, {n_mod} moduli", "p2": f"n^2 128x256, {n_b} bases"}
+    for name, form, per_mac in (("i8", H.HFE_FORM_I8_MFMA, 50), ("rns", H.HFE_FORM_RNS_I8, 2 * n_mod),
+                                ("p2", H.HFE_FORM_P2_I8, 2 * 3 * n_b)):
+        torch.cuda.empty_cache()                            # the previous form's workspace
         res = H.hfe_ccmm_batched(db, items, form)           # warm-up (workspace into torch's cache)
         same = all(np.array_equal(H.hfe_export(res[i], 0, 0, 1 << 16),
                                   H.hfe_export(H.hfe_ccmm(db, q, r0, nr, form), 0, 0, 1 << 16))
@@ -176,7 +180,7 @@ def run_batched(args, H, torch):
                 "higher_is_better": True, "form": name, "ms_per_batch": plan_ms, "int8_tops": tops,
                 "frac_of_peak": tops / PEAK_I8_TOPS, "sequential_ms": seq_ms,
                 "speedup_vs_sequential": seq_ms / plan_ms, "same_residues_as_single_calls": bool(same),
-                "tile": H.hfe_i8_variant_name(tuned) if name == "i8" else f"rns 256x256, {n_mod} moduli",
+                "tile": H.hfe_i8_variant_name(tuned) if name == "i8" else tiles[name],
                 "dtype": "i8", "data": "synthetic",
                 "config": {"workload": "batched_" + w.name, "items": len(mix), "eyes": "1-64", "shifts": 16,
                            "levels": "1-5 query primes + p", "rows": "2048-14336", "columns": cols}}
@@ -193,12 +197,12 @@ def run_serving(args, H, torch):
     w = S.PAPER_SHARE
     shifts = [int(x) for x in S.default_shifts(16)]
     log(f"serving: encrypting the {w.d1}-code database (int8 form)")
-    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8)
+    form = {"rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}.get(args.serve_form, H.HFE_FORM_I8_MFMA)
+    keys, db = encrypt_database(H, torch, w, form)
     dev = torch.device("cuda", 0)
     pool = {e: encrypt_eyes(H, torch, keys, w, 1000 + e, e, w.level, shifts) for e in range(1, 33)}
     torch.cuda.synchronize()
     lines = []
-    form = H.HFE_FORM_RNS_I8 if args.serve_form == "rns" else H.HFE_FORM_I8_MFMA
     for rate in args.rates:
         n = max(8, int(rate * args.serve_seconds))
         t_arr, eyes = S.poisson_arrivals(w.seed + int(rate), n, rate, 32)
@@ -260,7 +264,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving: seconds of arrivals per rate")
     ap.add_argument("--serve-cols", type=int, default=2048, help="serving: query columns per step")
     ap.add_argument("--serve-budget-gib", type=int, default=64, help="serving: workspace memory budget")
-    ap.add_argument("--serve-form", choices=("i8", "rns"), default="rns", help="serving: int8 form of the server")
+    ap.add_argument("--serve-form", choices=("i8", "rns", "p2"), default="rns", help="serving: int8 form of the server")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="with --ccmm-only: also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
