@@ -6,9 +6,12 @@
 * K just below 2^17, the largest the RNS form accepts (int32 sums of 128 x 128 products), where it
   needs 12 small moduli instead of 11.
 
-At both sizes the three forms must give the same residues (every digit tile configuration
-included), and decryption must give exactly the plaintext products M_DB M_Q (computed with numpy
-integers), with a ragged query count (d3 = 5) and database rows (d1 = 70).
+* K = 2^16, the largest the n^2 form accepts (int32 sums of 2 K products of digits up to 125).
+
+At every size the forms must give the same residues (every digit tile configuration included), and
+decryption must give exactly the plaintext products M_DB M_Q (computed with numpy integers), with a
+ragged query count (d3 = 5) and database rows (d1 = 70).  Then the degenerate inputs: fully masked
+codes, and empty row ranges and batches.
 """
 import sys
 
@@ -68,3 +71,67 @@ def test_long_k_all_forms_agree_and_decrypt_exactly(d2):
         finally:
             H.hfe_set_i8_variant(-1)
         assert np.array_equal(out, ref), f"tile {H.hfe_i8_variant_name(v)} differs"
+
+
+def test_fully_masked_codes_decide_no_match_in_every_form():
+    """Degenerate inputs of the method: query eyes and database codes whose masks are all zero
+    (no usable bit), beside ordinary ones.  A masked pair has IP = 0 and overlap 0, so its score is
+    undefined and the decision must be 'no match'; every other pair must still equal the popcount
+    truth.  All four forms, full path (encode, encrypt, contraction, decrypt, match)."""
+    from oracle import iris as OI
+    log_n_db, log_n_q, d1, d2, level = 9, 10, 40, 512, 2
+    n_eyes, shifts = 3, [0, 1, -2]
+    rng = np.random.default_rng(77)
+    db_codes = rng.integers(0, 2, (d1, d2)).astype(np.uint8)
+    db_masks = (rng.random((d1, d2)) < 0.9).astype(np.uint8)
+    q_codes = rng.integers(0, 2, (n_eyes, d2)).astype(np.uint8)
+    q_masks = (rng.random((n_eyes, d2)) < 0.9).astype(np.uint8)
+    db_masks[[0, 17, d1 - 1]] = 0                    # fully masked database codes
+    q_masks[1] = 0                                   # a fully masked query eye
+    db_codes[5] = q_codes[0]                         # and one exact match
+    db_masks[5] = q_masks[0]
+    qc, qm = OI.shifted_queries(q_codes, q_masks, np.array(shifts))
+    ip_true, ov = OI.truth(qc, qm, db_codes, db_masks)
+    dec_true = OI.decide(ip_true, ov)
+    assert not dec_true[:, [0, 17, d1 - 1]].any() and not dec_true[3:6].any() and dec_true[0, 5]
+    dev = torch.device("cuda", 0)
+    P = H.hfe_default_params(log_n_db, log_n_q, level, d2, d1)
+    keys = H.hfe_keygen(P, 41)
+    t = {k: torch.from_numpy(v).to(dev) for k, v in
+         dict(dc=db_codes, dm=db_masks, qc=q_codes, qm=q_masks).items()}
+    _say("[gpu-edge] masked codes: encode, encrypt")
+    db = H.hfe_encrypt_db(keys, H.hfe_encode(t["dc"], t["dm"], [0]), 42, sum(FORMS))
+    q = H.hfe_encrypt(keys, H.hfe_encode(t["qc"], t["qm"], shifts), level, 43)
+    for form in FORMS:
+        _say(f"[gpu-edge] masked codes: form {form}")
+        r = H.hfe_ccmm(db, q, 0, d1, form)
+        _, ip = H.hfe_decrypt(keys, r, v=False)
+        dec, eye = H.hfe_match(ip, t["qm"], shifts, t["dm"])
+        torch.cuda.synchronize()
+        assert np.array_equal(ip.cpu().numpy(), ip_true), f"form {form}: IP"
+        assert np.array_equal(dec.cpu().numpy().astype(bool), dec_true), f"form {form}: decisions"
+        assert np.array_equal(eye.cpu().numpy().astype(bool), OI.match_per_eye(dec_true, len(shifts)))
+
+
+def test_empty_inputs_are_rejected():
+    """Empty row ranges and empty batches are shape errors, not launches."""
+    log_n_db, log_n_q, d1, d2, level = 7, 9, 8, 256, 1
+    dev = torch.device("cuda", 0)
+    P = H.hfe_default_params(log_n_db, log_n_q, level, d2, d1)
+    keys = H.hfe_keygen(P, 5)
+    m = torch.ones((d1, d2), dtype=torch.int8, device=dev)
+    db = H.hfe_encrypt_db(keys, m, 6, sum(FORMS))
+    q = H.hfe_encrypt(keys, m[:2].contiguous(), level, 7)
+    for form in FORMS:
+        with pytest.raises(H.HfeError) as e:
+            H.hfe_ccmm(db, q, 0, 0, form)                          # no database rows
+        assert e.value.status == -2
+        with pytest.raises(H.HfeError) as e:
+            H.hfe_ccmm(db, q, d1, 1, form)                         # range past the end
+        assert e.value.status == -2
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_ccmm_batched(db, [], H.HFE_FORM_I8_MFMA)              # empty batch
+    assert e.value.status == -1
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_ccmm_batched(db, [(q, 0, 0)], H.HFE_FORM_P2_I8)       # empty item
+    assert e.value.status == -2
