@@ -766,7 +766,8 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(launch_crt_rns(res.as<uint8_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), C.as<uint64_t>(), s));
   } else if (form == HFE_FORM_P2_I8) {
     const int n = D->n_p2;
-    const int64_t d3_pad = (d3 + kP2TileQ - 1) / kP2TileQ * kP2TileQ;
+    const int tq = p2_tile_q(&d3, &R_out, &nz, 1);  // query tile width by padded work
+    const int64_t d3_pad = (d3 + tq - 1) / tq * tq;
     const size_t planeX = (size_t)D->KB * d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
     HFE_TRY(Xd.alloc((size_t)nz * 2 * n * planeX, s));
@@ -791,7 +792,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     pg.d3 = d3;
     pg.d3_pad = d3_pad;
     HFE_LAUNCH(mark(1));
-    HFE_LAUNCH(launch_gemm_p2(pg, s));
+    HFE_LAUNCH(launch_gemm_p2(pg, tq, s));
     HFE_LAUNCH(launch_crt_p2(res.as<uint16_t>(), nz, d3 * R_out, make_p2_crt_args(K, level, n), C.as<uint64_t>(), s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
@@ -1028,17 +1029,16 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
   for (int b = 0; b < np; ++b)
     if (gr.p[b].owner != b) feeds[gr.p[b].owner] = 1;
   for (int b = 0; b < np; ++b) R_out[b] = (gr.p[b].a_rows ? ndb : 0) + gr.p[b].rows;
-  // RNS form: each problem's query tile width by its own padded work; the 256-column problems come
+  // RNS and n^2 forms: each problem's query tile width by its own padded work; the 256-column problems come
   // first in the tables (one launch each width).  Owners' planes are padded for the widest tiles.
   std::vector<int> tq(np, 0), ord(np);
   for (int b = 0; b < np; ++b) {
     ord[b] = b;
-    if (rns) {
-      const int nzb = gr.p[b].level + 1;
-      tq[b] = rns_tile_q(&gr.p[b].d3, &R_out[b], &nzb, 1);
-    }
+    const int nzb = gr.p[b].level + 1;
+    if (rns) tq[b] = rns_tile_q(&gr.p[b].d3, &R_out[b], &nzb, 1);
+    if (fs.p2) tq[b] = p2_tile_q(&gr.p[b].d3, &R_out[b], &nzb, 1);
   }
-  if (rns) std::stable_partition(ord.begin(), ord.end(), [&](int b) { return tq[b] == 256; });
+  if (small) std::stable_partition(ord.begin(), ord.end(), [&](int b) { return tq[b] == 256; });
   // query planes of the owners: whole tiles, and for an owner that feeds split problems room for
   // their last tile, which may reach qpad - 1 columns past the owner's columns
   for (int b = 0; b < np; ++b) {
@@ -1088,9 +1088,9 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
       }
     }
     tiles += rns      ? rns_batched_tiles(d3, R_out[b], nz, planes, tq[b])
-             : fs.p2 ? p2_batched_tiles(d3, R_out[b], nz, D->n_p2)
+             : fs.p2 ? p2_batched_tiles(d3, R_out[b], nz, D->n_p2, tq[b])
                      : i8_batched_tiles(variant, d3, R_out[b], nz);
-    if (rns && tq[b] == 256) {
+    if (small && tq[b] == 256) {
       tiles_wide = tiles;
       n_wide = k + 1;
     }
@@ -1154,8 +1154,8 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
     BatchHeader* gh = reinterpret_cast<BatchHeader*>(blob + L.gh);
     gh->total_tiles = tiles;
     gh->n = np;
-    gh->tiles_wide = rns ? tiles_wide : tiles;
-    gh->n_wide = rns ? n_wide : np;
+    gh->tiles_wide = small ? tiles_wide : tiles;
+    gh->n_wide = small ? n_wide : np;
     BatchElemHeader* lh = reinterpret_cast<BatchElemHeader*>(blob + L.lh);
     lh->total = lift_e;
     lh->n = n;
@@ -1226,12 +1226,15 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
     std::memset(&a, 0, sizeof(a));
     a.hdr = hdr;
     a.next = const_cast<uint32_t*>(hdr->next);
+    a.next_narrow = const_cast<uint32_t*>(hdr->next_narrow);
     a.desc = reinterpret_cast<const BatchDesc*>(dblob + L.gd);
     a.Dq = D->p2.as<int8_t>();
     a.n_bases = D->n_p2;
     a.KB = D->KB;
     a.R_pad = D->R_pad;
-    HFE_LAUNCH(launch_gemm_p2_batched(a, gemm_grid_for(form, 0), s));
+    // the 256-column problems, then the 128-column ones (either launch may find no tiles)
+    HFE_LAUNCH(launch_gemm_p2_batched(a, gemm_grid_for(form, 0), 256, s));
+    HFE_LAUNCH(launch_gemm_p2_batched(a, gemm_grid_for(form, 0), 128, s));
     HFE_LAUNCH(launch_crt_p2_batched(reinterpret_cast<const BatchElemHeader*>(dblob + L.ch),
                                      reinterpret_cast<const BatchCrtDesc*>(dblob + L.cd),
                                      make_p2_crt_args(D->keys, D->keys->L, D->n_p2), elem_grid, s));

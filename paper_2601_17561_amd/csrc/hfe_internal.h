@@ -291,16 +291,19 @@ hipError_t launch_split_db_p2(const uint64_t* Dt_prime, int64_t K, int64_t R, in
                               uint64_t q, int n_bases, int8_t* planes_prime, hipStream_t s);
 hipError_t launch_lift_p2(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
                           const LiftArgs& la, int n_bases, int8_t* Xq, hipStream_t s);
-constexpr int kP2TileR = 128, kP2TileQ = 256;  // n^2 workgroup tile: rows, query columns
+constexpr int kP2TileQ = 256;  // n^2 workgroup tile: widest query columns (256 x 128 rows, or 128 x 256)
 struct P2GemmArgs {
   int nz, n_bases;
   const int8_t* Dq[kMaxPrimes];                // [2 n_bases][KB][R_pad][64] per prime slot
   const int8_t* Xq[kMaxPrimes];                // [2 n_bases][KB][d3_pad][64]
   int32_t n[kP2MaxBases];                      // bases
   uint16_t* res;                               // [nz][n_bases][d3][R_out], residues < n^2
-  int64_t KB, R_pad, n_db, row0, R_out, d3, d3_pad;  // d3_pad a multiple of kP2TileQ
+  int64_t KB, R_pad, n_db, row0, R_out, d3, d3_pad;  // d3_pad a multiple of the query tile width
 };
-hipError_t launch_gemm_p2(const P2GemmArgs& g, hipStream_t s);
+// tq: query columns of the workgroup tile, 128 or 256 (g.d3_pad a multiple of it)
+hipError_t launch_gemm_p2(const P2GemmArgs& g, int tq, hipStream_t s);
+// the tile width with less padded work for problems of d3 columns, R_out rows and nz prime slots
+int p2_tile_q(const int64_t* d3, const int64_t* R_out, const int* nz, int n);
 struct P2CrtArgs {
   int n;                                       // bases in use
   int32_t m[kP2MaxBases];                      // n_j^2
@@ -333,18 +336,20 @@ struct RnsBatchArgs {
 int64_t rns_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_mod, int tq);
 hipError_t launch_gemm_rns_batched(const RnsBatchArgs& a, int grid, int tq, hipStream_t s);
 // Batched n^2 contraction: problem b's tiles are [tile_begin, tile_begin + p2_batched_tiles(...)),
-// ordered (z, base, XCD-ordered tile); one persistent launch claims every problem's tiles through
-// hdr->next.  Residues (uint16) go to desc.res.
+// ordered (z, base, XCD-ordered tile); the launch with tq = 256 serves problems [0, hdr->n_wide)
+// through hdr->next, the one with tq = 128 the others through hdr->next_narrow.  Residues (uint16)
+// go to desc.res.
 struct P2BatchArgs {
   const BatchHeader* hdr;
-  uint32_t* next;                              // hdr->next
+  uint32_t* next;                              // hdr->next (256-column tiles)
+  uint32_t* next_narrow;                       // hdr->next_narrow (128-column tiles)
   const BatchDesc* desc;
   const int8_t* Dq;                            // database planes, all slots: [slot][2 n_bases][KB][R_pad][64]
   int32_t n_bases, pad_;
   int64_t KB, R_pad;
 };
-int64_t p2_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_bases);
-hipError_t launch_gemm_p2_batched(const P2BatchArgs& a, int grid, hipStream_t s);
+int64_t p2_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_bases, int tq);
+hipError_t launch_gemm_p2_batched(const P2BatchArgs& a, int grid, int tq, hipStream_t s);
 // ra indexed by database slot; d[b].res points at uint16 residues
 hipError_t launch_crt_p2_batched(const BatchElemHeader* hdr, const BatchCrtDesc* d, const P2CrtArgs& ra, int grid,
                                  hipStream_t s);
@@ -393,8 +398,8 @@ struct BatchHeader {
   int64_t total_tiles;            // multiple of kXcds
   int32_t n, pad_;
   uint32_t next[kXcds];           // tiles claimed per XCD; zero in every uploaded table
-  // RNS form: problems [0, n_wide) use 256-column query tiles (tiles [0, tiles_wide)), the rest
-  // 128-column tiles, claimed by a second launch through next_narrow
+  // RNS and n^2 forms: problems [0, n_wide) use 256-column query tiles (tiles [0, tiles_wide)),
+  // the rest 128-column tiles, claimed by a second launch through next_narrow
   uint32_t next_narrow[kXcds];
   int64_t tiles_wide;
   int32_t n_wide, pad2_;

@@ -75,17 +75,20 @@ hipError_t launch_lift_p2(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB,
 }
 
 // ------------------------------------------------------------------ contraction per base
-// Workgroup tile: 128 database rows x 256 query columns of one (prime, base), 8 waves (two per
-// SIMD), each owning 64 query columns x 64 rows as 2 x 2 blocks of 32 x 32 with two int32
-// accumulators: G0 += M N and G1 += M N' + M' N (v_mfma_i32_32x32x32_i8), three MFMAs per block
-// and K-chunk.  An LDS stage holds one 64-byte K-block of both query planes (2 x 256 rows) and both
-// database planes (2 x 128 rows), 48 KiB, fed by direct global-to-LDS loads with the digit form's
-// row swizzle; three stages (144 KiB, one workgroup per CU).  Per K-block the workgroup loads 48 KiB
-// for 96 MFMAs, the same bytes per MFMA as the RNS tile of 256 x 256.
+// Workgroup tile: TR database rows x TQ query columns of one (prime, base), TQ x TR = 128 x 256 or
+// 256 x 128, 8 waves (two per SIMD), each owning 64 query columns x 64 rows as 2 x 2 blocks of
+// 32 x 32 with two int32 accumulators: G0 += M N and G1 += M N' + M' N (v_mfma_i32_32x32x32_i8),
+// three MFMAs per block and K-chunk.  An LDS stage holds one 64-byte K-block of both query planes
+// (2 x TQ rows) and both database planes (2 x TR rows), 48 KiB, fed by direct global-to-LDS loads
+// with the digit form's row swizzle; three stages (144 KiB, one workgroup per CU).  Per K-block the
+// workgroup loads 48 KiB for 96 MFMAs, the same bytes per MFMA as the RNS tile of 256 x 256.  The
+// host takes the 128-column tile when it pads the query columns less (small problems of a batch).
 // Exactness: |M|, |M'|, |N|, |N'| <= 125, so |G1| <= 2 K 125^2 < 2^31 for K <= 2^16 (checked by the
 // host).
+template <int TQ_>
 struct P2Cfg {
-  static constexpr int TQ = kP2TileQ, TR = kP2TileR;
+  static_assert(TQ_ == 128 || TQ_ == 256, "query tile of 128 or 256 columns");
+  static constexpr int TQ = TQ_, TR = 128 * 256 / TQ_;
   static constexpr int WQB = 2, WRB = 2;  // 32 x 32 blocks per wave
   static constexpr int NQ = TQ / (32 * WQB), NR = TR / (32 * WRB), NW = NQ * NR;
   static constexpr int STAGES = 3;
@@ -108,8 +111,9 @@ struct P2Tile {
   int64_t KB, R_pad, d3_pad, n_db, row0, R_out, d3, r0, c0;
 };
 
+template <int TQ>
 __device__ __forceinline__ void p2_tile(const P2Tile& g, int8_t* lds) {
-  using C = P2Cfg;
+  using C = P2Cfg<TQ>;
   const int j = g.j;
   const int64_t r0 = g.r0, c0 = g.c0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -235,9 +239,10 @@ __device__ __forceinline__ void p2_tile(const P2Tile& g, int8_t* lds) {
   }
 }
 
-__global__ void __launch_bounds__(64 * P2Cfg::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+template <int TQ>
+__global__ void __launch_bounds__(64 * P2Cfg<TQ>::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_gemm_p2(P2GemmArgs g) {
-  using C = P2Cfg;
+  using C = P2Cfg<TQ>;
   __shared__ __attribute__((aligned(16))) int8_t lds[C::LDS];
   const int j = blockIdx.y, z = blockIdx.z;
   const int64_t n_ct = (g.d3 + C::TQ - 1) / C::TQ, n_rt = (g.R_out + C::TR - 1) / C::TR;
@@ -247,29 +252,33 @@ k_gemm_p2(P2GemmArgs g) {
   P2Tile t{g.Xq[z] + (size_t)(2 * j) * g.KB * g.d3_pad * kKB, g.Dq[z] + (size_t)(2 * j) * g.KB * g.R_pad * kKB,
            g.res + ((size_t)z * g.n_bases + j) * g.d3 * g.R_out, j, g.KB, g.R_pad, g.d3_pad, g.n_db, g.row0,
            g.R_out, g.d3, rt * C::TR, ct * C::TQ};
-  p2_tile(t, lds);
+  p2_tile<TQ>(t, lds);
 }
 
 // Persistent batched form: problem b's tiles are ordered (z, base, XCD-ordered tile), starting at its
 // tile_begin; workgroups claim tiles in order from one counter per XCD (tile t = 8 i + xcd), as the
-// digit form's batched kernel.
-__global__ void __launch_bounds__(64 * P2Cfg::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// digit form's batched kernel.  The 256-column launch serves problems [0, n_wide) (tiles
+// [0, tiles_wide), counters next), the 128-column launch the others (counters next_narrow).
+template <int TQ>
+__global__ void __launch_bounds__(64 * P2Cfg<TQ>::NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_gemm_p2_batched(P2BatchArgs a) {
-  using C = P2Cfg;
+  using C = P2Cfg<TQ>;
   __shared__ __attribute__((aligned(16))) int8_t lds[C::LDS];
-  const int np = a.hdr->n;
-  const int64_t total = a.hdr->total_tiles;
+  constexpr bool narrow = TQ == 128;
+  const int p_lo = narrow ? a.hdr->n_wide : 0, p_hi = narrow ? a.hdr->n : a.hdr->n_wide;
+  const int64_t t_lo = narrow ? a.hdr->tiles_wide : 0, t_hi = narrow ? a.hdr->total_tiles : a.hdr->tiles_wide;
+  uint32_t* next = narrow ? a.next_narrow : a.next;
   const int xcd = blockIdx.x % kXcds;
-  const int64_t per_xcd = total / kXcds;
+  const int64_t per_xcd = (t_hi - t_lo) / kXcds;
   for (;;) {
     __syncthreads();  // the previous tile is done with LDS
-    if (threadIdx.x == 0) *reinterpret_cast<uint32_t*>(lds) = atomicAdd(a.next + xcd, 1u);
+    if (threadIdx.x == 0) *reinterpret_cast<uint32_t*>(lds) = atomicAdd(next + xcd, 1u);
     __syncthreads();
     const int64_t jc = (uint32_t)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t*>(lds));
     __syncthreads();  // every thread has read the claim before the tile overwrites LDS
     if (jc >= per_xcd) break;
-    const int64_t t = jc * kXcds + xcd;
-    int lo = 0, hi = np - 1;  // last problem whose first tile is <= t
+    const int64_t t = t_lo + jc * kXcds + xcd;
+    int lo = p_lo, hi = p_hi - 1;  // last problem of this launch whose first tile is <= t
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (a.desc[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
@@ -287,27 +296,51 @@ k_gemm_p2_batched(P2BatchArgs a) {
               a.Dq + (size_t)(d.slot[z] * a.n_bases + j) * 2 * a.KB * a.R_pad * kKB,
               reinterpret_cast<uint16_t*>(d.res) + ((size_t)z * a.n_bases + j) * d.d3 * d.R_out, j, a.KB, a.R_pad,
               d.d3_pad, d.n_db, d.row0, d.R_out, d.d3, rt * C::TR, ct * C::TQ};
-    p2_tile(tl, lds);
+    p2_tile<TQ>(tl, lds);
   }
 }
 
-int64_t p2_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_bases) {
-  const int64_t n_ct = (d3 + kP2TileQ - 1) / kP2TileQ, n_rt = (R_out + kP2TileR - 1) / kP2TileR;
+static int64_t p2_rows_of(int tq) { return 128 * 256 / tq; }
+
+int64_t p2_batched_tiles(int64_t d3, int64_t R_out, int nz, int n_bases, int tq) {
+  const int64_t tr = p2_rows_of(tq);
+  const int64_t n_ct = (d3 + tq - 1) / tq, n_rt = (R_out + tr - 1) / tr;
   return (n_rt + kXcds - 1) / kXcds * kXcds * n_ct * nz * n_bases;
 }
 
-hipError_t launch_gemm_p2_batched(const P2BatchArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_gemm_p2_batched, dim3((unsigned)grid), dim3(64 * P2Cfg::NW), 0, s, a);
+// Query tile of the n^2 contraction for a set of problems: the width with less padded work (rows
+// padded to the tile's TR, columns to its TQ); ties go to 256.
+int p2_tile_q(const int64_t* d3, const int64_t* R_out, const int* nz, int n) {
+  double w128 = 0, w256 = 0;
+  for (int i = 0; i < n; ++i) {
+    w128 += (double)((R_out[i] + 255) / 256 * 256) * ((d3[i] + 127) / 128 * 128) * nz[i];
+    w256 += (double)((R_out[i] + 127) / 128 * 128) * ((d3[i] + 255) / 256 * 256) * nz[i];
+  }
+  return w128 < w256 ? 128 : 256;
+}
+
+hipError_t launch_gemm_p2_batched(const P2BatchArgs& a, int grid, int tq, hipStream_t s) {
+  if (tq == 128)
+    hipLaunchKernelGGL(k_gemm_p2_batched<128>, dim3((unsigned)grid), dim3(64 * P2Cfg<128>::NW), 0, s, a);
+  else if (tq == 256)
+    hipLaunchKernelGGL(k_gemm_p2_batched<256>, dim3((unsigned)grid), dim3(64 * P2Cfg<256>::NW), 0, s, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_p2(const P2GemmArgs& g, hipStream_t s) {
+hipError_t launch_gemm_p2(const P2GemmArgs& g, int tq, hipStream_t s) {
   if (g.R_out <= 0 || g.d3 <= 0) return hipSuccess;
-  if (g.d3_pad % kP2TileQ != 0 || g.n_bases < 1 || g.n_bases > kP2MaxBases) return hipErrorInvalidValue;
-  const int64_t n_ct = (g.d3 + kP2TileQ - 1) / kP2TileQ, n_rt = (g.R_out + kP2TileR - 1) / kP2TileR;
+  if ((tq != 128 && tq != 256) || g.d3_pad % tq != 0 || g.n_bases < 1 || g.n_bases > kP2MaxBases)
+    return hipErrorInvalidValue;
+  const int64_t tr = p2_rows_of(tq);
+  const int64_t n_ct = (g.d3 + tq - 1) / tq, n_rt = (g.R_out + tr - 1) / tr;
   const int64_t n_rt8 = (n_rt + kXcds - 1) / kXcds * kXcds;
   dim3 grid((unsigned)(n_rt8 * n_ct), (unsigned)g.n_bases, (unsigned)g.nz);
-  hipLaunchKernelGGL(k_gemm_p2, grid, dim3(64 * P2Cfg::NW), 0, s, g);
+  if (tq == 128)
+    hipLaunchKernelGGL(k_gemm_p2<128>, grid, dim3(64 * P2Cfg<128>::NW), 0, s, g);
+  else
+    hipLaunchKernelGGL(k_gemm_p2<256>, grid, dim3(64 * P2Cfg<256>::NW), 0, s, g);
   return hipGetLastError();
 }
 
