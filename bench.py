@@ -153,7 +153,8 @@ def run_batched(args, H, torch):
     qs, p_special = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1).primes()
     n_mod = rns_moduli(w, max(list(qs) + [p_special]))
     n_b = p2_bases(w, max(list(qs) + [p_special]))
-    tiles = {"rns": f"rns 256x256, {n_mod} moduli", "p2": f"n^2 128x256, {n_b} bases"}
+    tiles = {"rns": f"rns 256 or 128 columns per problem, {n_mod} moduli",
+             "p2": f"n^2 256 or 128 columns per problem, {n_b} bases"}
     for name, form, per_mac in (("i8", H.HFE_FORM_I8_MFMA, 50), ("rns", H.HFE_FORM_RNS_I8, 2 * n_mod),
                                 ("p2", H.HFE_FORM_P2_I8, 2 * 3 * n_b)):
         torch.cuda.empty_cache()                            # the previous form's workspace
