@@ -128,6 +128,21 @@ hfe_status hfe_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int
 hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, uint64_t seed,
                           uint32_t forms, void* stream, hfe_db** out);
 
+/* The encrypted database is the artefact prepared once and kept (Section 6.3: it is stored and
+ * stays resident, and its size is the scheme's main storage cost), so it can be written to a file
+ * and read back instead of being encrypted again.
+ * hfe_db_save: writes `db` (every form it was prepared for) to the file `path` (host path; created
+ *   or truncated), after the work already queued on `stream`.  Synchronous: the file is complete
+ *   when the call returns.  Host memory used: a 64 MiB pinned staging buffer.
+ * hfe_db_load: reads a file written by hfe_db_save under the same keys (parameters and secrets,
+ *   checked by a fingerprint) into a new resident database; `stream` orders the copies, and the
+ *   data is on the device when the call returns.  Release the result with hfe_free.
+ * Errors: HFE_EINVAL for an invalid handle, a NULL path, a file that cannot be opened or written,
+ * one that is not a database file of this library version, was written under other keys, or is
+ * truncated or longer than its header says; HFE_ENOMEM / HFE_EDEVICE from the device. */
+hfe_status hfe_db_save(const hfe_db* db, const char* path, void* stream);
+hfe_status hfe_db_load(const hfe_keys* keys, const char* path, void* stream, hfe_db** out);
+
 /* Query encryption in MSRLWE form (Section 2.3): per column c and query prime,
  * a_c uniform in R_{N_Q}, b_c = -S_Q a_c + Delta_level m_c + e_c (chunks of N_Q rows share
  * a_c, each under its own secret).  m_q: d3 x d2 ternary (device); 1 <= level <= L. */

@@ -38,7 +38,8 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_last_error", "hfe_cdt_table", "hfe_profile", "hfe_profile_ms", "hfe_i8_variants",
             "hfe_i8_variant_name", "hfe_set_i8_variant", "hfe_ccmm_batched", "hfe_plan_create", "hfe_plan_run",
             "hfe_plan_result", "hfe_autotune", "hfe_autotune_save", "hfe_autotune_load", "hfe_server_create",
-            "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_stats", "hfe_server_reset_stats")
+            "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_stats", "hfe_server_reset_stats",
+            "hfe_db_save", "hfe_db_load")
 
 
 class HfeError(RuntimeError):
@@ -91,6 +92,8 @@ _SIGS = {
     "hfe_encode": [_vp, _vp, _i64, _i32, ctypes.POINTER(_i32), _i32, _vp, _vp],
     "hfe_encrypt_db": [_vp, _vp, _i64, _u64, _u32, _vp, ctypes.POINTER(_vp)],
     "hfe_encrypt": [_vp, _vp, _i64, _u32, _u64, _vp, ctypes.POINTER(_vp)],
+    "hfe_db_save": [_vp, ctypes.c_char_p, _vp],
+    "hfe_db_load": [_vp, ctypes.c_char_p, _vp, ctypes.POINTER(_vp)],
     "hfe_ccmm": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_vp)],
     "hfe_decrypt": [_vp, _vp, _vp, _vp, _vp],
     "hfe_match": [_vp, _vp, _i64, ctypes.POINTER(_i32), _i32, _vp, _i64, _i32, _u32, _u32, _vp, _vp, _vp],
@@ -273,6 +276,18 @@ def hfe_encrypt_db(keys: Handle, m_db, seed: int, forms: int = HFE_FORM_PLAIN_U6
     out = _vp()
     _check(_lib.hfe_encrypt_db(keys.ptr, _dev_ptr(m_db, torch.int8), d1, seed, forms, _stream(stream),
                                ctypes.byref(out)), "hfe_encrypt_db")
+    return Handle(out.value, (keys,))
+
+
+def hfe_db_save(db: Handle, path, stream=None) -> None:
+    """Write the encrypted database (every prepared form) to `path`; returns when the file is complete."""
+    _check(_lib.hfe_db_save(db.ptr, os.fsencode(path), _stream(stream)), "hfe_db_save")
+
+
+def hfe_db_load(keys: Handle, path, stream=None) -> Handle:
+    """Read a database written by hfe_db_save under the same keys back onto the device."""
+    out = _vp()
+    _check(_lib.hfe_db_load(keys.ptr, os.fsencode(path), _stream(stream), ctypes.byref(out)), "hfe_db_load")
     return Handle(out.value, (keys,))
 
 

@@ -1,0 +1,101 @@
+"""Saving and loading the encrypted database (hfe_db_save / hfe_db_load).
+
+A database written to a file and read back under the same keys must give bit-identical results in
+every form it was prepared for (and the same plain residues); a file written under other keys, a
+truncated file, a file with trailing bytes and a file that is not a database are refused.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+H = pytest.importorskip("paper_2601_17561_amd")
+
+ALL = H.HFE_FORM_PLAIN_U64 | H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8 | H.HFE_FORM_P2_I8
+INT8 = (H.HFE_FORM_I8_MFMA, H.HFE_FORM_RNS_I8, H.HFE_FORM_P2_I8)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    log_n_db, log_n_q, d1, d2, level, d3 = 8, 9, 150, 700, 2, 7
+    dev = torch.device("cuda", 0)
+    P = H.hfe_default_params(log_n_db, log_n_q, level, d2, d1)
+    keys = H.hfe_keygen(P, 61)
+    other = H.hfe_keygen(P, 62)
+    rng = np.random.default_rng(63)
+    m_db = torch.from_numpy(rng.integers(-1, 2, (d1, d2)).astype(np.int8)).to(dev)
+    m_q = torch.from_numpy(rng.integers(-1, 2, (d3, d2)).astype(np.int8)).to(dev)
+    _say("[gpu-store] keygen, encrypt the database in every form")
+    db = H.hfe_encrypt_db(keys, m_db, 64, ALL)
+    q = H.hfe_encrypt(keys, m_q, level, 65)
+    torch.cuda.synchronize()
+    return dict(keys=keys, other=other, db=db, q=q, d1=d1)
+
+
+def _result(db, q, row0, rows, form):
+    return H.hfe_export(H.hfe_ccmm(db, q, row0, rows, form), 0)
+
+
+def test_round_trip_gives_identical_results_in_every_form(env, tmp_path):
+    path = tmp_path / "db.hfe"
+    _say("[gpu-store] save, load")
+    H.hfe_db_save(env["db"], path)
+    loaded = H.hfe_db_load(env["keys"], path)
+    assert np.array_equal(H.hfe_export(loaded, 0), H.hfe_export(env["db"], 0))
+    for form in (H.HFE_FORM_PLAIN_U64,) + INT8:
+        for row0, rows in ((0, env["d1"]), (37, 50)):
+            _say(f"[gpu-store] ccmm form {form} rows [{row0}, {row0 + rows})")
+            a = _result(env["db"], env["q"], row0, rows, form)
+            b = _result(loaded, env["q"], row0, rows, form)
+            assert np.array_equal(a, b), f"form {form}: loaded database differs"
+
+
+def test_subset_of_forms_round_trips(env, tmp_path):
+    m_db = torch.from_numpy(np.random.default_rng(66).integers(-1, 2, (40, 700)).astype(np.int8)).cuda()
+    db = H.hfe_encrypt_db(env["keys"], m_db, 67, H.HFE_FORM_RNS_I8)
+    path = tmp_path / "rns.hfe"
+    H.hfe_db_save(db, path)
+    loaded = H.hfe_db_load(env["keys"], path)
+    assert np.array_equal(_result(db, env["q"], 0, 40, H.HFE_FORM_RNS_I8),
+                          _result(loaded, env["q"], 0, 40, H.HFE_FORM_RNS_I8))
+    with pytest.raises(H.HfeError) as e:                            # not prepared for the digit form
+        H.hfe_ccmm(loaded, env["q"], 0, 40, H.HFE_FORM_I8_MFMA)
+    assert e.value.status == -1
+
+
+def test_bad_files_are_refused(env, tmp_path):
+    path = tmp_path / "db.hfe"
+    H.hfe_db_save(env["db"], path)
+    data = path.read_bytes()
+    with pytest.raises(H.HfeError) as e:                            # other keys
+        H.hfe_db_load(env["other"], path)
+    assert e.value.status == -1 and "other keys" in str(e.value)
+    short = tmp_path / "short.hfe"
+    short.write_bytes(data[:-1000])
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_db_load(env["keys"], short)
+    assert e.value.status == -1 and "truncated" in str(e.value)
+    longer = tmp_path / "long.hfe"
+    longer.write_bytes(data + b"\0")
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_db_load(env["keys"], longer)
+    assert e.value.status == -1 and "trailing" in str(e.value)
+    junk = tmp_path / "junk.hfe"
+    junk.write_bytes(os.urandom(4096))
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_db_load(env["keys"], junk)
+    assert e.value.status == -1
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_db_load(env["keys"], tmp_path / "missing.hfe")
+    assert e.value.status == -1
