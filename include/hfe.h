@@ -26,7 +26,9 @@
  *
  * Layouts (row-major unless stated; "residue" = uint64 in [0, prime))
  *  - Ternary matrices: int8 in {-1, 0, 1}.  M_DB: d1 x d2, one database code per row.
- *    M_Q: d3 x d2, one query vector per row (the paper's M_Q is its transpose).
+ *    M_Q: d3 x d2, one query vector per row (the paper's M_Q is its transpose).  The encryption
+ *    calls check the entries on the device and return HFE_EINVAL for any other value (they wait
+ *    for that check: the call returns after the work queued before it on the stream).
  *  - Primes: the database carries query primes q_0..q_{L-1} and one special prime p.
  *    A query of level l uses q_0..q_{l-1}; its scaling factor is
  *    Delta_l = 2^(floor(log2(q_0 ... q_{l-1})) - gap_bits).

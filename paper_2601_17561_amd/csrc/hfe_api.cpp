@@ -548,6 +548,45 @@ static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t
   return HFE_OK;
 }
 
+// Entries of a ternary input outside {-1, 0, 1} (they would break the bound |M m| <= d2 that the
+// scale leaves room for).  begin enqueues a check kernel and the copy of its flag into a pinned
+// word; the caller then enqueues its own work, and end waits for the check alone (an event after
+// the copy), so the device never idles for it.  The pinned word is one per host thread, kept
+// until the process ends; a call waits for it before returning, so calls never share it.
+struct TernaryCheck {
+  DevBuf flag;
+  hipEvent_t ev = nullptr;
+  uint32_t* host = nullptr;
+  ~TernaryCheck() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+static uint32_t* pinned_flag() {
+  thread_local uint32_t* p = nullptr;
+  if (!p && hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+    p = nullptr;
+  return p;
+}
+
+static hfe_status check_ternary_begin(const int8_t* m, int64_t n, hipStream_t s, TernaryCheck& c) {
+  c.host = pinned_flag();
+  if (!c.host) return fail(HFE_ENOMEM, "pinned host allocation failed");
+  HFE_TRY(c.flag.alloc(sizeof(uint32_t), s));
+  HFE_LAUNCH(hipMemsetAsync(c.flag.ptr, 0, sizeof(uint32_t), s));
+  HFE_LAUNCH(launch_check_ternary(m, n, c.flag.as<uint32_t>(), s));
+  HFE_LAUNCH(hipMemcpyAsync(c.host, c.flag.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HFE_LAUNCH(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+  HFE_LAUNCH(hipEventRecord(c.ev, s));
+  return HFE_OK;
+}
+
+static hfe_status check_ternary_end(TernaryCheck& c, const char* what) {
+  HFE_LAUNCH(hipEventSynchronize(c.ev));
+  if (*c.host) return fail(HFE_EINVAL, std::string(what) + " has entries outside {-1, 0, 1}");
+  return HFE_OK;
+}
+
 hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, uint64_t seed, uint32_t forms,
                           void* stream, hfe_db** out) {
   if (!out) return fail(HFE_EINVAL, "out is NULL");
@@ -557,9 +596,12 @@ hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, 
   if (d1 < 1 || d1 > (int64_t)K->P.max_db_rows)
     return fail(HFE_ESHAPE, "d1 must be 1 .. max_db_rows");
   if (forms == 0 || (forms & ~15u)) return fail(HFE_EINVAL, "forms must be a non-empty set of hfe_form");
+  TernaryCheck chk;
+  HFE_TRY(check_ternary_begin(m_db, d1 * (int64_t)K->P.d2, (hipStream_t)stream, chk));
   hfe_db* D = new (std::nothrow) hfe_db();
   if (!D) return fail(HFE_ENOMEM, "host allocation failed");
   hfe_status st = encrypt_db_impl(K, m_db, d1, seed, forms, (hipStream_t)stream, D);
+  if (st == HFE_OK) st = check_ternary_end(chk, "m_db");  // a refused input: buffers freed in stream order
   if (st != HFE_OK) {
     delete D;
     return st;
@@ -579,6 +621,8 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
   if (level < 1 || (int)level > K->L) return fail(HFE_ELEVEL, "level must be 1 .. n_q_primes");
   hipStream_t s = (hipStream_t)stream;
   const hfe_params& P = K->P;
+  TernaryCheck chk;
+  HFE_TRY(check_ternary_begin(m_q, d3 * (int64_t)P.d2, s, chk));
   const int64_t nq = 1ll << P.log_n_q;
   hfe_qct* Q = new (std::nothrow) hfe_qct();
   if (!Q) return fail(HFE_ENOMEM, "host allocation failed");
@@ -611,6 +655,11 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
       delete Q;
       return hip_fail(e, "launch_q_encrypt");
     }
+  }
+  st = check_ternary_end(chk, "m_q");  // a refused input: the ciphertext is freed in stream order
+  if (st != HFE_OK) {
+    delete Q;
+    return st;
   }
   *out = Q;
   return HFE_OK;

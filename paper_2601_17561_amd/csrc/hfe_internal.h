@@ -444,6 +444,8 @@ struct DecodeArgs {
 hipError_t launch_decode(const uint64_t* y, int64_t n, const DecodeArgs& da, double* v, int32_t* ip,
                          hipStream_t s);
 
+// flag[0] |= 1 if any of the n int8 entries of m lies outside {-1, 0, 1}
+hipError_t launch_check_ternary(const int8_t* m, int64_t n, uint32_t* flag, hipStream_t s);
 hipError_t launch_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int32_t d2,
                          const int32_t* shifts_dev, int32_t n_shifts, int8_t* out, hipStream_t s);
 

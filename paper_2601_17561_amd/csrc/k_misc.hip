@@ -28,6 +28,37 @@ __global__ void k_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, 
   }
 }
 
+// Input check of a ternary matrix: flag[0] |= 1 if any of its n entries lies outside {-1, 0, 1}.
+// Thread: 16 entries (one 16-byte load when m is 16-byte aligned), grid-stride.
+__global__ void __launch_bounds__(256) k_check_ternary(const int8_t* m, int64_t n, uint32_t* flag) {
+  const bool vec = (reinterpret_cast<uintptr_t>(m) & 15) == 0;
+  uint32_t bad = 0;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16; i < n;
+       i += (int64_t)gridDim.x * blockDim.x * 16) {
+    if (vec && i + 16 <= n) {
+      const uint4 w = *reinterpret_cast<const uint4*>(m + i);
+      const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        // byte b is in {-1, 0, 1} iff u = b + 1 (mod 256) is in {0, 1, 2}: no bit above bit 1, and
+        // not bits 0 and 1 together (u = 3); the per-byte increment carries into bit 7 at most
+        const uint32_t u = ((v[k] & 0x7f7f7f7fu) + 0x01010101u) ^ (v[k] & 0x80808080u);
+        bad |= (u & 0xfcfcfcfcu) | (u & (u >> 1) & 0x01010101u);
+      }
+    } else {
+      for (int64_t j = i; j < n && j < i + 16; ++j) bad |= (uint32_t)(m[j] < -1 || m[j] > 1);
+    }
+  }
+  if (bad) atomicOr(flag, 1u);
+}
+
+hipError_t launch_check_ternary(const int8_t* m, int64_t n, uint32_t* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 16 * 256 - 1) / (16 * 256), 4096);
+  hipLaunchKernelGGL(k_check_ternary, dim3((unsigned)blocks), dim3(256), 0, s, m, n, flag);
+  return hipGetLastError();
+}
+
 hipError_t launch_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int32_t d2,
                          const int32_t* shifts, int32_t n_shifts, int8_t* out, hipStream_t s) {
   if (n <= 0 || d2 <= 0) return hipSuccess;

@@ -135,3 +135,27 @@ def test_empty_inputs_are_rejected():
     with pytest.raises(H.HfeError) as e:
         H.hfe_ccmm_batched(db, [(q, 0, 0)], H.HFE_FORM_P2_I8)       # empty item
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("bad", [2, -2, 127, -128], ids=["2", "-2", "127", "-128"])
+def test_non_ternary_inputs_are_rejected(bad):
+    """An entry outside {-1, 0, 1} would break the bound |M m| <= d2 that the scale leaves room
+    for; both encryption calls refuse it, in the vector body and in the ragged tail of the check."""
+    log_n_db, log_n_q, d1, d2, level = 7, 9, 9, 250, 1          # d1 x d2 and 3 x d2 not multiples of 16
+    dev = torch.device("cuda", 0)
+    keys = H.hfe_keygen(H.hfe_default_params(log_n_db, log_n_q, level, d2, d1), 8)
+    rng = np.random.default_rng(bad & 0xff)
+    for pos in (0, 1234 % (d1 * d2), d1 * d2 - 1):             # head, vector body, ragged tail
+        m = rng.integers(-1, 2, (d1, d2)).astype(np.int8)
+        m.reshape(-1)[pos] = bad
+        with pytest.raises(H.HfeError) as e:
+            H.hfe_encrypt_db(keys, torch.from_numpy(m).to(dev), 9, H.HFE_FORM_I8_MFMA)
+        assert e.value.status == -1 and "outside" in str(e.value)
+        q = np.ascontiguousarray(m[:3])
+        if pos < 3 * d2:
+            with pytest.raises(H.HfeError) as e:
+                H.hfe_encrypt(keys, torch.from_numpy(q).to(dev), level, 10)
+            assert e.value.status == -1
+    ok = rng.integers(-1, 2, (d1, d2)).astype(np.int8)
+    H.hfe_encrypt_db(keys, torch.from_numpy(ok).to(dev), 9, H.HFE_FORM_I8_MFMA)   # ternary: accepted
+    H.hfe_encrypt(keys, torch.from_numpy(np.ascontiguousarray(ok[:3])).to(dev), level, 10)
