@@ -159,6 +159,10 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
 hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
                     void* stream, hfe_rct** out);
 
+/* An empty result handle shaped for query q against every code of db (level x d3 x (N_DB + d1)
+ * residues, allocated on `stream`), for hfe_server_submit_encrypted.  Release with hfe_free. */
+hfe_status hfe_result_create(const hfe_db* db, const hfe_qct* q, void* stream, hfe_rct** out);
+
 /* Batched CCMM: item i is its own CCMM of items[i].q (any level, any column count) against the
  * database codes [items[i].row0, items[i].row0 + items[i].rows), all against one database.
  * Items with the same level and row range form one problem, their query columns side by side (so
@@ -224,6 +228,11 @@ hfe_status hfe_autotune_load(const char* path);
  *   hfe_server_submit: q (its keys must be the server's; level <= max_level) stays borrowed
  *     until the ticket completes; ip_out: device int32 d3 x d1 (query-major) receives the
  *     decrypted inner products against every database code.
+ *   hfe_server_submit_encrypted: the same, but the request's encrypted result (the rescaled
+ *     residues against every database code, as hfe_ccmm returns them) is copied into `result`,
+ *     a handle from hfe_result_create for this query, which stays borrowed until the ticket
+ *     completes; the key holder decrypts it with hfe_decrypt afterwards.  The server then needs
+ *     no secret for that request.
  *   hfe_server_poll: *state = 0 queued, 1 running, 2 done, or a negative status: HFE_EBUSY
  *     (rejected as larger than one step, or still queued when the server was freed), another
  *     status (its step failed).
@@ -244,6 +253,7 @@ hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_co
                              int32_t max_items_per_step, int32_t n_slots, uint32_t max_level, int32_t form,
                              hfe_server** out);
 hfe_status hfe_server_submit(hfe_server* srv, const hfe_qct* q, int32_t* ip_out, uint64_t* ticket);
+hfe_status hfe_server_submit_encrypted(hfe_server* srv, const hfe_qct* q, hfe_rct* result, uint64_t* ticket);
 hfe_status hfe_server_poll(hfe_server* srv, uint64_t ticket, int32_t* state);
 hfe_status hfe_server_wait(hfe_server* srv, uint64_t ticket, int64_t timeout_ms);
 hfe_status hfe_server_stats(hfe_server* srv, hfe_server_report* out);

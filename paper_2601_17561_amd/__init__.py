@@ -39,7 +39,7 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_i8_variant_name", "hfe_set_i8_variant", "hfe_ccmm_batched", "hfe_plan_create", "hfe_plan_run",
             "hfe_plan_result", "hfe_autotune", "hfe_autotune_save", "hfe_autotune_load", "hfe_server_create",
             "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_stats", "hfe_server_reset_stats",
-            "hfe_db_save", "hfe_db_load")
+            "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted")
 
 
 class HfeError(RuntimeError):
@@ -93,6 +93,8 @@ _SIGS = {
     "hfe_encrypt_db": [_vp, _vp, _i64, _u64, _u32, _vp, ctypes.POINTER(_vp)],
     "hfe_encrypt": [_vp, _vp, _i64, _u32, _u64, _vp, ctypes.POINTER(_vp)],
     "hfe_db_save": [_vp, ctypes.c_char_p, _vp],
+    "hfe_result_create": [_vp, _vp, _vp, ctypes.POINTER(_vp)],
+    "hfe_server_submit_encrypted": [_vp, _vp, _vp, ctypes.POINTER(_u64)],
     "hfe_db_load": [_vp, ctypes.c_char_p, _vp, ctypes.POINTER(_vp)],
     "hfe_ccmm": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_vp)],
     "hfe_decrypt": [_vp, _vp, _vp, _vp, _vp],
@@ -449,6 +451,22 @@ def hfe_server_submit(srv: Server, q: Handle, ip_out) -> int:
     t = _u64()
     _check(_lib.hfe_server_submit(srv.ptr, q.ptr, _dev_ptr(ip_out, torch.int32), ctypes.byref(t)), "hfe_server_submit")
     srv._live[int(t.value)] = (q, ip_out)
+    return int(t.value)
+
+
+def hfe_result_create(db: Handle, q: Handle, stream=None) -> Handle:
+    """An empty encrypted-result handle shaped for query q against every database code."""
+    out = _vp()
+    _check(_lib.hfe_result_create(db.ptr, q.ptr, _stream(stream), ctypes.byref(out)), "hfe_result_create")
+    return Handle(out.value, (db, q))
+
+
+def hfe_server_submit_encrypted(srv: Server, q: Handle, result: Handle) -> int:
+    """result: a handle from hfe_result_create for q; receives the request's encrypted result."""
+    t = _u64()
+    _check(_lib.hfe_server_submit_encrypted(srv.ptr, q.ptr, result.ptr, ctypes.byref(t)),
+           "hfe_server_submit_encrypted")
+    srv._live[int(t.value)] = (q, result)
     return int(t.value)
 
 

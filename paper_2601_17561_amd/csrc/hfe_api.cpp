@@ -890,6 +890,33 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
   return HFE_OK;
 }
 
+hfe_status hfe_result_create(const hfe_db* db, const hfe_qct* q, void* stream, hfe_rct** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  const hfe_qct* Qc = as_handle<hfe_qct>(q, kQct);
+  if (!D || !Qc) return fail(HFE_EINVAL, "invalid database or query handle");
+  if (Qc->keys != D->keys) return fail(HFE_EINVAL, "database and query use different keys");
+  hfe_rct* R = new (std::nothrow) hfe_rct();
+  if (!R) return fail(HFE_ENOMEM, "host allocation failed");
+  R->kind = kRct;
+  R->stream = (hipStream_t)stream;
+  R->keys = D->keys;
+  R->level = Qc->level;
+  R->d3 = Qc->d3;
+  R->row0 = 0;
+  R->rows = D->d1;
+  R->R_out = (1ll << D->keys->P.log_n_db) + D->d1;
+  hfe_status st = R->out.alloc(sizeof(uint64_t) * (size_t)R->level * R->d3 * R->R_out, (hipStream_t)stream);
+  if (st != HFE_OK) {
+    delete R;
+    return st;
+  }
+  R->outp = R->out.as<uint64_t>();
+  *out = R;
+  return HFE_OK;
+}
+
 int32_t hfe_i8_variants(void) { return i8_variant_count(); }
 
 const char* hfe_i8_variant_name(int32_t v) { return i8_variant_name(v); }

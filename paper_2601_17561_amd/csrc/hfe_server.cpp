@@ -24,7 +24,8 @@ double now_s() {
 
 struct Request {
   const hfe_qct* q = nullptr;
-  int32_t* ip_out = nullptr;
+  int32_t* ip_out = nullptr;   // decrypted inner products, or
+  hfe_rct* ct_out = nullptr;   // the encrypted result (copied from the step's workspace)
   int64_t d3 = 0;
   int level = 0;
   int state = 0;  // 0 queued, 1 running, 2 done, < 0 rejected
@@ -167,11 +168,20 @@ void hfe_server::run() {
       const hfe_rct* view = nullptr;
       st = hfe_plan_result(sl.plan, (int32_t)i, &view);
       int32_t* ip_out = nullptr;
+      hfe_rct* ct_out = nullptr;
       {
         std::lock_guard<std::mutex> l(mu);
         ip_out = reqs[tickets[i]].ip_out;
+        ct_out = reqs[tickets[i]].ct_out;
       }
-      if (st == HFE_OK) st = decrypt_impl(db->keys, view, nullptr, ip_out, sl.y.as<uint64_t>() + off, sl.stream);
+      if (st != HFE_OK) break;
+      if (ct_out) {
+        const size_t bytes = sizeof(uint64_t) * (size_t)view->level * view->d3 * view->R_out;
+        if (hipMemcpyAsync(ct_out->outp, view->outp, bytes, hipMemcpyDeviceToDevice, sl.stream) != hipSuccess)
+          st = fail(HFE_EDEVICE, "copy of an encrypted result failed");
+      } else {
+        st = decrypt_impl(db->keys, view, nullptr, ip_out, sl.y.as<uint64_t>() + off, sl.stream);
+      }
       off += (size_t)view->level * view->d3 * view->rows;
     }
     sl.done.srv = this;
@@ -279,6 +289,36 @@ hfe_status hfe_server_submit(hfe_server* srv, const hfe_qct* q, int32_t* ip_out,
   Request& r = S->reqs[tk];
   r.q = q;
   r.ip_out = ip_out;
+  r.d3 = q->d3;
+  r.level = q->level;
+  r.t_submit = now_s();
+  if (S->t_first < 0) S->t_first = r.t_submit;
+  S->queue.push_back(tk);
+  ++S->submitted;
+  S->max_queue = std::max<int64_t>(S->max_queue, (int64_t)S->queue.size());
+  S->cv.notify_all();
+  *ticket = tk;
+  return HFE_OK;
+}
+
+hfe_status hfe_server_submit_encrypted(hfe_server* srv, const hfe_qct* q, hfe_rct* result, uint64_t* ticket) {
+  hfe_server* S = as_server(srv);
+  const HandleBase* qb = static_cast<const HandleBase*>(static_cast<const void*>(q));
+  const HandleBase* rb = static_cast<const HandleBase*>(static_cast<const void*>(result));
+  if (!S || !q || qb->kind != kQct || !result || rb->kind != kRct || !ticket)
+    return fail(HFE_EINVAL, "invalid server, query, result or ticket");
+  if (q->keys != S->db->keys || result->keys != S->db->keys) return fail(HFE_EINVAL, "handles under other keys");
+  if (q->K != S->db->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
+  if (q->level > S->max_level) return fail(HFE_ELEVEL, "query level above the server's maximum");
+  const int64_t ndb = 1ll << S->db->keys->P.log_n_db;
+  if (result->is_view || !result->outp || result->level != q->level || result->d3 != q->d3 || result->row0 != 0 ||
+      result->rows != S->db->d1 || result->R_out != ndb + S->db->d1)
+    return fail(HFE_ESHAPE, "result handle not shaped for this query (use hfe_result_create)");
+  std::lock_guard<std::mutex> l(S->mu);
+  const uint64_t tk = S->next_ticket++;
+  Request& r = S->reqs[tk];
+  r.q = q;
+  r.ct_out = result;
   r.d3 = q->d3;
   r.level = q->level;
   r.t_submit = now_s();

@@ -88,6 +88,39 @@ def test_same_result_alone_and_in_the_mix(env, form):
     srv.free()
 
 
+@pytest.mark.parametrize("form", ["rns", "p2"])
+def test_encrypted_results_equal_single_calls_and_decrypt_exactly(env, form):
+    """Requests that take their result encrypted (the server uses no secret for them), mixed in
+    one burst with requests decrypted by the server: every encrypted result equals the single
+    hfe_ccmm call's residues and decrypts (by the key holder) to the plaintext products."""
+    _say(f"[gpu-serving] server ({form}): encrypted results in a mixed burst")
+    srv = H.hfe_server_create(env["db"], 2 << 30, 64, 8, 2, 2, FORMS[form])
+    d1 = env["c"].w.d1
+    results, tickets, outs = {}, {}, {}
+    for i, (q, mq, _) in enumerate(env["reqs"]):
+        if i % 2 == 0:
+            results[i] = H.hfe_result_create(env["db"], q)
+            tickets[i] = H.hfe_server_submit_encrypted(srv, q, results[i])
+        else:
+            outs[i] = torch.full((mq.shape[0], d1), -7, dtype=torch.int32, device=env["dev"])
+            tickets[i] = H.hfe_server_submit(srv, q, outs[i])
+    for i in tickets:
+        H.hfe_server_wait(srv, tickets[i], 60000)
+    for i, (q, mq, exact) in enumerate(env["reqs"]):
+        if i in results:
+            single = H.hfe_export(H.hfe_ccmm(env["db"], q, 0, d1, FORMS[form]), 0)
+            assert np.array_equal(H.hfe_export(results[i], 0), single), f"request {i}: residues"
+            _, ip = H.hfe_decrypt(env["keys"], results[i], v=False)
+            torch.cuda.synchronize()
+            assert np.array_equal(ip.cpu().numpy(), exact), f"request {i}: decrypted products"
+        else:
+            assert np.array_equal(outs[i].cpu().numpy(), exact), f"request {i}: server-decrypted products"
+    with pytest.raises(H.HfeError) as e:                             # a result shaped for another query
+        H.hfe_server_submit_encrypted(srv, env["reqs"][1][0], H.hfe_result_create(env["db"], env["reqs"][0][0]))
+    assert e.value.status == -2
+    srv.free()
+
+
 def test_small_budget_queues_and_oversized_request_is_rejected(env):
     c = env["c"]
     # a budget that fits about 48 columns per step over 2 slots: the burst runs in several steps
