@@ -207,8 +207,18 @@ def run_serving(args, H, torch):
     for rate in args.rates:
         n = max(8, int(rate * args.serve_seconds))
         t_arr, eyes = S.poisson_arrivals(w.seed + int(rate), n, rate, 32)
-        log(f"serving: {n} requests at {rate} req/s over {t_arr[-1]:.1f} s")
-        outs = [torch.empty((int(e) * 16, w.d1), dtype=torch.int32, device=dev) for e in eyes]
+        encrypted = args.serve_results == "encrypted"
+        if encrypted:
+            # result handles are preallocated by the clients (level x columns x (N_DB + d1)
+            # residues each): keep the first requests whose results fit 120 GiB
+            per_req = [w.level * int(e) * 16 * ((1 << w.log_n_db) + w.d1) * 8 for e in eyes]
+            n = max(8, min(n, int(np.searchsorted(np.cumsum(per_req), 120 << 30))))
+            t_arr, eyes = t_arr[:n], eyes[:n]
+        log(f"serving: {n} requests at {rate} req/s over {t_arr[-1]:.1f} s ({args.serve_results} results)")
+        if encrypted:
+            outs = [H.hfe_result_create(db, pool[int(e)]) for e in eyes]
+        else:
+            outs = [torch.empty((int(e) * 16, w.d1), dtype=torch.int32, device=dev) for e in eyes]
         srv = H.hfe_server_create(db, args.serve_budget_gib << 30, args.serve_cols, 64, 2, w.level, form)
         tickets = []
         t0 = time.perf_counter()
@@ -216,7 +226,10 @@ def run_serving(args, H, torch):
             wait = t0 + t_arr[i] - time.perf_counter()
             if wait > 0:
                 time.sleep(wait)
-            tickets.append(H.hfe_server_submit(srv, pool[int(eyes[i])], outs[i]))
+            if encrypted:
+                tickets.append(H.hfe_server_submit_encrypted(srv, pool[int(eyes[i])], outs[i]))
+            else:
+                tickets.append(H.hfe_server_submit(srv, pool[int(eyes[i])], outs[i]))
         log(f"serving: all {n} submitted after {time.perf_counter() - t0:.1f} s")
         for t in tickets:
             H.hfe_server_wait(srv, t, 600000)
@@ -230,15 +243,20 @@ def run_serving(args, H, torch):
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "service_p50_ms": st["service_p50_ms"],
                 "service_p99_ms": st["service_p99_ms"], "steps": st["steps"],
                 "mean_cols_per_step": st["mean_cols_per_step"], "max_queue": st["max_queue"],
-                "rejected": st["rejected"], "form": args.serve_form, "dtype": "i8", "data": "synthetic",
+                "rejected": st["rejected"], "form": args.serve_form, "results": args.serve_results,
+                "latency": ("arrival -> encrypted result ready" if encrypted else "arrival -> decrypted products"),
+                "dtype": "i8", "data": "synthetic",
                 "config": {"workload": "serving_" + w.name, "eyes": "1-32", "shifts": 16,
                            "arrivals": f"poisson {rate}/s", "window_s": args.serve_seconds,
                            "max_cols_per_step": args.serve_cols, "slots": 2,
                            "mem_budget_gib": args.serve_budget_gib}}
         print(json.dumps(line), flush=True)
         lines.append(line)
-        del outs
         torch.cuda.synchronize()
+        for o in outs:
+            if encrypted:
+                o.free()
+        del outs
     return lines
 
 
@@ -264,6 +282,8 @@ def main():
                     help="serving arrival rates, req/s")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving: seconds of arrivals per rate")
     ap.add_argument("--serve-cols", type=int, default=2048, help="serving: query columns per step")
+    ap.add_argument("--serve-results", choices=("decrypted", "encrypted"), default="decrypted",
+                    help="serving: products decrypted by the server, or encrypted results for the key holder")
     ap.add_argument("--serve-budget-gib", type=int, default=64, help="serving: workspace memory budget")
     ap.add_argument("--serve-form", choices=("i8", "rns", "p2"), default="rns", help="serving: int8 form of the server")
     ap.add_argument("--copy-mib", type=int, default=0,
