@@ -980,7 +980,7 @@ struct BlobLayout {
 int max_problems(int n) { return n + kMaxPrimes; }
 
 struct BatchSizes {
-  size_t xd_bytes = 0, c_elems = 0, res_elems = 0, out_elems = 0;
+  size_t xd_bytes = 0, c_elems = 0, res_bytes = 0, out_elems = 0;
   int64_t cols = 0;
   int max_level = 0, problems = 0;
 };
@@ -1132,7 +1132,7 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
     const int level = P.level, nz = level + 1;
     const int64_t d3 = P.d3;
     c_off[b] = z.c_elems;
-    res_off[b] = z.res_elems;
+    res_off[b] = z.res_bytes;
     if (blob) {
       BatchDesc& g = reinterpret_cast<BatchDesc*>(blob + L.gd)[k];
       std::memset(&g, 0, sizeof(g));
@@ -1176,7 +1176,7 @@ BatchSizes batch_fill(const hfe_db* D, const hfe_batch_item* items, int n, int f
     // each problem's C starts at a multiple of 4 entries and its residues at a multiple of 8 bytes
     // (the CRT's word loads and 16-byte stores)
     z.c_elems += ((size_t)nz * d3 * R_out[b] + 3) / 4 * 4;
-    if (small) z.res_elems += ((size_t)nz * (fs.p2 ? D->n_p2 : planes) * d3 * R_out[b] * fs.res_bytes + 7) / 8 * 8;
+    if (small) z.res_bytes += ((size_t)nz * (fs.p2 ? D->n_p2 : planes) * d3 * R_out[b] * fs.res_bytes + 7) / 8 * 8;
     z.max_level = std::max(z.max_level, level);
   }
   int64_t lift_e = 0, resc_e = 0;
@@ -1415,7 +1415,7 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
   DevBuf Xd, C, res, blob;
   hfe_status st = Xd.alloc(sz0.xd_bytes, s);
   if (st == HFE_OK) st = C.alloc(sizeof(uint64_t) * sz0.c_elems, s);
-  if (st == HFE_OK && sz0.res_elems) st = res.alloc(sz0.res_elems, s);
+  if (st == HFE_OK && sz0.res_bytes) st = res.alloc(sz0.res_bytes, s);
   if (st == HFE_OK) st = blob.alloc(L.bytes, s);
   if (st != HFE_OK) {
     cleanup();
@@ -1522,7 +1522,7 @@ hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, 
   const BatchSizes sz = batch_fill(D, items, n, P->form, 0, nullptr, nullptr, nullptr, nullptr, nullptr, L);
   const int variant =
       P->form == HFE_FORM_I8_MFMA ? choose_batch_variant(D, items, n, sz.max_level, sz.cols / n) : 0;
-  if (sz.cols > P->max_cols || sz.xd_bytes > P->xd_cap || sz.c_elems > P->c_cap || sz.res_elems > P->res_cap ||
+  if (sz.cols > P->max_cols || sz.xd_bytes > P->xd_cap || sz.c_elems > P->c_cap || sz.res_bytes > P->res_cap ||
       sz.out_elems > P->out_cap)
     return fail(HFE_ESHAPE, "batch exceeds the plan's workspace");
   hipStream_t s = (hipStream_t)stream;
