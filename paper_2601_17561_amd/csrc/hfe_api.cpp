@@ -753,7 +753,12 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(R->ev[i], s) : hipSuccess; };
   HFE_LAUNCH(mark(0));
   DevBuf C, Xp, Xd;
-  HFE_TRY(C.alloc(sizeof(uint64_t) * (size_t)nz * d3 * R_out, s));
+  // the small-modulus forms reconstruct and rescale in one pass (no contraction output C)
+  const bool fused = form == HFE_FORM_RNS_I8 || form == HFE_FORM_P2_I8;
+  if (!fused) HFE_TRY(C.alloc(sizeof(uint64_t) * (size_t)nz * d3 * R_out, s));
+  const RescaleArgs ra = make_rescale_args(K, level);
+  HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
+  R->outp = R->out.as<uint64_t>();
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
   g.nz = nz;
@@ -768,7 +773,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   g.d3 = d3;
   g.d3_pad = (d3 + kQueryPad - 1) / kQueryPad * kQueryPad;
   for (int z = 0; z < nz; ++z) {
-    g.C[z] = C.as<uint64_t>() + (size_t)z * d3 * R_out;
+    g.C[z] = fused ? nullptr : C.as<uint64_t>() + (size_t)z * d3 * R_out;
     g.mod[z] = K->mods[slot(z)];
   }
   if (form == HFE_FORM_PLAIN_U64) {
@@ -812,7 +817,8 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     rg.d3_pad = d3_pad;
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_rns(rg, tq, s));
-    HFE_LAUNCH(launch_crt_rns(res.as<uint8_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), C.as<uint64_t>(), s));
+    HFE_LAUNCH(mark(2));
+    HFE_LAUNCH(launch_crt_rescale_rns(res.as<uint8_t>(), d3 * R_out, make_rns_crt_args(K, level, n), ra, R->outp, s));
   } else if (form == HFE_FORM_P2_I8) {
     const int n = D->n_p2;
     const int tq = p2_tile_q(&d3, &R_out, &nz, 1);  // query tile width by padded work
@@ -842,7 +848,8 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     pg.d3_pad = d3_pad;
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_p2(pg, tq, s));
-    HFE_LAUNCH(launch_crt_p2(res.as<uint16_t>(), nz, d3 * R_out, make_p2_crt_args(K, level, n), C.as<uint64_t>(), s));
+    HFE_LAUNCH(mark(2));
+    HFE_LAUNCH(launch_crt_rescale_p2(res.as<uint16_t>(), d3 * R_out, make_p2_crt_args(K, level, n), ra, R->outp, s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
@@ -855,12 +862,11 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_i8(g, pick_i8_variant(level, d3), s));
   }
-  HFE_LAUNCH(mark(2));
-  const RescaleArgs ra = make_rescale_args(K, level);
-  HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
-  R->outp = R->out.as<uint64_t>();
-  HFE_LAUNCH(launch_rescale(C.as<uint64_t>(), C.as<uint64_t>() + (size_t)level * d3 * R_out, d3 * R_out, ra,
-                            R->outp, s));
+  if (!fused) {
+    HFE_LAUNCH(mark(2));
+    HFE_LAUNCH(launch_rescale(C.as<uint64_t>(), C.as<uint64_t>() + (size_t)level * d3 * R_out, d3 * R_out, ra,
+                              R->outp, s));
+  }
   HFE_LAUNCH(mark(3));
   return HFE_OK;
 }

@@ -263,12 +263,9 @@ __device__ __forceinline__ uint64_t crt_entry(const uint8_t* r, int64_t n, const
 // Entries e0 .. e0 + 3 (those below n) of one prime slot: r = that slot's first residue plane
 // ([n_mod][n] bytes), out = its n results.  With n a multiple of 4 the residues of each modulus
 // are read as one 4-byte word and the results written as two 16-byte vectors.
-__device__ __forceinline__ void crt_quad(const uint8_t* r, int64_t n, const RnsCrtArgs& ra, int slot, uint64_t* out,
-                                         int64_t e0) {
-  if ((n & 3) != 0) {
-    for (int b = 0; b < 4 && e0 + b < n; ++b) out[e0 + b] = crt_entry(r + e0 + b, n, ra, slot);
-    return;
-  }
+// The same for n a multiple of 4, into registers: v[b] = entry e0 + b.
+__device__ __forceinline__ void crt_quad_vals(const uint8_t* r, int64_t n, const RnsCrtArgs& ra, int slot,
+                                              int64_t e0, uint64_t v[4]) {
   float frac[4] = {0.f, 0.f, 0.f, 0.f};
   uint64_t acc[4] = {0, 0, 0, 0};
   for (int j = 0; j < ra.n; ++j) {
@@ -284,14 +281,30 @@ __device__ __forceinline__ void crt_quad(const uint8_t* r, int64_t n, const RnsC
     }
   }
   const Mod md = ra.mod[slot];
-  uint64_t v[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const uint64_t a = (uint64_t)(frac[b] + 0.5f);
     v[b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
   }
+}
+
+__device__ __forceinline__ void crt_quad(const uint8_t* r, int64_t n, const RnsCrtArgs& ra, int slot, uint64_t* out,
+                                         int64_t e0) {
+  if ((n & 3) != 0) {
+    for (int b = 0; b < 4 && e0 + b < n; ++b) out[e0 + b] = crt_entry(r + e0 + b, n, ra, slot);
+    return;
+  }
+  uint64_t v[4];
+  crt_quad_vals(r, n, ra, slot, e0, v);
   reinterpret_cast<ulonglong2*>(out + e0)[0] = make_ulonglong2(v[0], v[1]);
   reinterpret_cast<ulonglong2*>(out + e0)[1] = make_ulonglong2(v[2], v[3]);
+}
+
+// RS_p of one entry from its residues: c_i mod q_i for the level's primes and cp mod p.
+__device__ __forceinline__ uint64_t rescale_value(uint64_t c_i, int64_t cp_centered, const RescaleArgs& ra, int i) {
+  const Mod& m = ra.mod[i];
+  const uint64_t d = sub_mod(c_i, from_signed(cp_centered, m.q, m.mu), m.q);
+  return mul_shoup(d, ra.pinv[i], ra.pinv_sh[i], m.q);
 }
 
 // Output entry e of a contraction (C[i] = residues mod q_i, Cp = residues mod p, n entries per

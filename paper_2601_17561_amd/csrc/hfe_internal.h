@@ -426,6 +426,12 @@ struct RescaleArgs {
 };
 hipError_t launch_rescale(const uint64_t* C, const uint64_t* Cp, int64_t n, const RescaleArgs& ra,
                           uint64_t* out, hipStream_t s);
+// Single calls of the small-modulus forms: the CRT of the residues (ra for slots 0 .. level, the
+// special prime last) and the rescale by p in one pass, out[i][e] for the level's primes.
+hipError_t launch_crt_rescale_rns(const uint8_t* res, int64_t n, const RnsCrtArgs& ra, const RescaleArgs& rs,
+                                  uint64_t* out, hipStream_t s);
+hipError_t launch_crt_rescale_p2(const uint16_t* res, int64_t n, const P2CrtArgs& ra, const RescaleArgs& rs,
+                                 uint64_t* out, hipStream_t s);
 
 // Decryption: y[i][c][r] = B_out + (s'_j * A_out)[(row0 + r) mod N_DB] mod q_i.
 hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,

@@ -352,9 +352,9 @@ hipError_t launch_gemm_p2(const P2GemmArgs& g, int tq, hipStream_t s) {
 // C = sum_j y_j ((M/m_j) mod q) - a (M mod q) mod q, the sum below 8 * 2^16 * 2^36.
 // Thread: 2 consecutive entries of one prime slot (blockIdx.y), residues read as one 4-byte word.
 // Entries e0, e0 + 1 (those below n) of one prime slot: r = that slot's first residue plane
-// ([n_bases][n] uint16), out = its n results; ra indexed by `slot`.
-__device__ __forceinline__ void crt_pair(const uint16_t* r, int64_t n, const P2CrtArgs& ra, int slot, uint64_t* out,
-                                         int64_t e0) {
+// ([n_bases][n] uint16); ra indexed by `slot`.  v[b] = entry e0 + b (v[1] is 0 past the end).
+__device__ __forceinline__ void crt_pair_vals(const uint16_t* r, int64_t n, const P2CrtArgs& ra, int slot,
+                                              int64_t e0, uint64_t v[2]) {
   const int cnt = e0 + 1 < n ? 2 : 1;
   float frac[2] = {0.f, 0.f};
   uint64_t acc[2] = {0, 0};
@@ -378,10 +378,47 @@ __device__ __forceinline__ void crt_pair(const uint16_t* r, int64_t n, const P2C
     }
   }
   const Mod md = ra.mod[slot];
+  v[1] = 0;
   for (int b = 0; b < cnt; ++b) {
     const uint64_t a = (uint64_t)(frac[b] + 0.5f);
-    out[e0 + b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
+    v[b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
   }
+}
+
+// The same, stored: out = the slot's n results.
+__device__ __forceinline__ void crt_pair(const uint16_t* r, int64_t n, const P2CrtArgs& ra, int slot, uint64_t* out,
+                                         int64_t e0) {
+  uint64_t v[2];
+  crt_pair_vals(r, n, ra, slot, e0, v);
+  out[e0] = v[0];
+  if (e0 + 1 < n) out[e0 + 1] = v[1];
+}
+
+// CRT and rescale by p in one pass (single calls), as k_crt_rescale_rns: the contraction output C
+// is never written.  Thread: 2 consecutive entries.
+__global__ void __launch_bounds__(256) k_crt_rescale_p2(const uint16_t* res, int64_t n, P2CrtArgs ra, RescaleArgs rs,
+                                                        uint64_t* out) {
+  const int level = rs.level;
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
+  if (e0 >= n) return;
+  const bool two = e0 + 1 < n;
+  uint64_t v[2];
+  crt_pair_vals(res + (size_t)level * ra.n * n, n, ra, level, e0, v);
+  const int64_t cp0 = centered(v[0], rs.p), cp1 = centered(v[1], rs.p);
+  for (int i = 0; i < level; ++i) {
+    crt_pair_vals(res + (size_t)i * ra.n * n, n, ra, i, e0, v);
+    out[(size_t)i * n + e0] = rescale_value(v[0], cp0, rs, i);
+    if (two) out[(size_t)i * n + e0 + 1] = rescale_value(v[1], cp1, rs, i);
+  }
+}
+
+hipError_t launch_crt_rescale_p2(const uint16_t* res, int64_t n, const P2CrtArgs& ra, const RescaleArgs& rs,
+                                 uint64_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 2 * 256 - 1) / (2 * 256);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_crt_rescale_p2, dim3((unsigned)blocks), dim3(256), 0, s, res, n, ra, rs, out);
+  return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(256) k_crt_p2(const uint16_t* res, int64_t n, P2CrtArgs ra, uint64_t* C) {

@@ -348,6 +348,48 @@ __global__ void __launch_bounds__(256) k_crt_rns(const uint8_t* res, int64_t n, 
   crt_quad(res + (size_t)z * ra.n * n, n, ra, z, C + (size_t)z * n, e0);
 }
 
+// CRT and rescale by p in one pass (single calls): per entry the residues of the special prime's
+// slot (z = level) give cp, then each query prime's residue is reconstructed and rescaled,
+// out[i][e] = (C_i - [cp] mod q_i) p^-1 mod q_i, so the contraction output C is never written.
+// Thread: 4 consecutive entries (n a multiple of 4) or, otherwise, one entry.
+__global__ void __launch_bounds__(256) k_crt_rescale_rns(const uint8_t* res, int64_t n, RnsCrtArgs ra,
+                                                         RescaleArgs rs, uint64_t* out) {
+  const int level = rs.level;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((n & 3) == 0) {
+    const int64_t e0 = 4 * t;
+    if (e0 >= n) return;
+    uint64_t v[4];
+    int64_t cp[4];
+    crt_quad_vals(res + (size_t)level * ra.n * n, n, ra, level, e0, v);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cp[b] = centered(v[b], rs.p);
+    for (int i = 0; i < level; ++i) {
+      crt_quad_vals(res + (size_t)i * ra.n * n, n, ra, i, e0, v);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) v[b] = rescale_value(v[b], cp[b], rs, i);
+      reinterpret_cast<ulonglong2*>(out + (size_t)i * n + e0)[0] = make_ulonglong2(v[0], v[1]);
+      reinterpret_cast<ulonglong2*>(out + (size_t)i * n + e0)[1] = make_ulonglong2(v[2], v[3]);
+    }
+  } else {
+    const int64_t e = t;
+    if (e >= n) return;
+    const int64_t cp = centered(crt_entry(res + (size_t)level * ra.n * n + e, n, ra, level), rs.p);
+    for (int i = 0; i < level; ++i)
+      out[(size_t)i * n + e] = rescale_value(crt_entry(res + (size_t)i * ra.n * n + e, n, ra, i), cp, rs, i);
+  }
+}
+
+hipError_t launch_crt_rescale_rns(const uint8_t* res, int64_t n, const RnsCrtArgs& ra, const RescaleArgs& rs,
+                                  uint64_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t per = (n & 3) == 0 ? 4 : 1;
+  const int64_t blocks = (n / per + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_crt_rescale_rns, dim3((unsigned)blocks), dim3(256), 0, s, res, n, ra, rs, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_crt_rns(const uint8_t* res, int nz, int64_t n, const RnsCrtArgs& ra, uint64_t* C,
                           hipStream_t s) {
   if (nz <= 0 || n <= 0) return hipSuccess;
