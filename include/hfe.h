@@ -137,13 +137,15 @@ hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, 
  *   or truncated), after the work already queued on `stream`.  Synchronous: the file is complete
  *   when the call returns.  Host memory used: a 64 MiB pinned staging buffer.
  * hfe_db_load: reads a file written by hfe_db_save under the same keys (parameters and secrets,
- *   checked by a fingerprint) into a new resident database; `stream` orders the copies, and the
- *   data is on the device when the call returns.  Release the result with hfe_free.
+ *   checked by a fingerprint) into a new resident database holding the forms in `forms` (a subset
+ *   of the file's; 0: all of them; the others' bytes are skipped); `stream` orders the copies,
+ *   and the data is on the device when the call returns.  Release the result with hfe_free.
  * Errors: HFE_EINVAL for an invalid handle, a NULL path, a file that cannot be opened or written,
- * one that is not a database file of this library version, was written under other keys, or is
- * truncated or longer than its header says; HFE_ENOMEM / HFE_EDEVICE from the device. */
+ * one that is not a database file of this library version, was written under other keys, lacks a
+ * requested form, or is truncated or longer than its header says; HFE_ENOMEM / HFE_EDEVICE from
+ * the device. */
 hfe_status hfe_db_save(const hfe_db* db, const char* path, void* stream);
-hfe_status hfe_db_load(const hfe_keys* keys, const char* path, void* stream, hfe_db** out);
+hfe_status hfe_db_load(const hfe_keys* keys, const char* path, uint32_t forms, void* stream, hfe_db** out);
 
 /* Query encryption in MSRLWE form (Section 2.3): per column c and query prime,
  * a_c uniform in R_{N_Q}, b_c = -S_Q a_c + Delta_level m_c + e_c (chunks of N_Q rows share

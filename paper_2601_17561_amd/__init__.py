@@ -95,7 +95,7 @@ _SIGS = {
     "hfe_db_save": [_vp, ctypes.c_char_p, _vp],
     "hfe_result_create": [_vp, _vp, _vp, ctypes.POINTER(_vp)],
     "hfe_server_submit_encrypted": [_vp, _vp, _vp, ctypes.POINTER(_u64)],
-    "hfe_db_load": [_vp, ctypes.c_char_p, _vp, ctypes.POINTER(_vp)],
+    "hfe_db_load": [_vp, ctypes.c_char_p, _u32, _vp, ctypes.POINTER(_vp)],
     "hfe_ccmm": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_vp)],
     "hfe_decrypt": [_vp, _vp, _vp, _vp, _vp],
     "hfe_match": [_vp, _vp, _i64, ctypes.POINTER(_i32), _i32, _vp, _i64, _i32, _u32, _u32, _vp, _vp, _vp],
@@ -286,10 +286,11 @@ def hfe_db_save(db: Handle, path, stream=None) -> None:
     _check(_lib.hfe_db_save(db.ptr, os.fsencode(path), _stream(stream)), "hfe_db_save")
 
 
-def hfe_db_load(keys: Handle, path, stream=None) -> Handle:
-    """Read a database written by hfe_db_save under the same keys back onto the device."""
+def hfe_db_load(keys: Handle, path, forms: int = 0, stream=None) -> Handle:
+    """Read a database written by hfe_db_save under the same keys back onto the device; forms: the
+    subset of the stored forms to load (0: all)."""
     out = _vp()
-    _check(_lib.hfe_db_load(keys.ptr, os.fsencode(path), _stream(stream), ctypes.byref(out)), "hfe_db_load")
+    _check(_lib.hfe_db_load(keys.ptr, os.fsencode(path), forms, _stream(stream), ctypes.byref(out)), "hfe_db_load")
     return Handle(out.value, (keys,))
 
 

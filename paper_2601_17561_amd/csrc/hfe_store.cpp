@@ -130,7 +130,7 @@ hfe_status hfe_db_save(const hfe_db* db, const char* path, void* stream) {
   return HFE_OK;
 }
 
-hfe_status hfe_db_load(const hfe_keys* keys, const char* path, void* stream, hfe_db** out) {
+hfe_status hfe_db_load(const hfe_keys* keys, const char* path, uint32_t forms, void* stream, hfe_db** out) {
   if (!out) return fail(HFE_EINVAL, "out is NULL");
   *out = nullptr;
   const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(keys));
@@ -152,6 +152,8 @@ hfe_status hfe_db_load(const hfe_keys* keys, const char* path, void* stream, hfe
       h.n_p2 > kP2MaxBases || ((h.forms & HFE_FORM_RNS_I8) && h.n_rns < 1) ||
       ((h.forms & HFE_FORM_P2_I8) && h.n_p2 < 1))
     return fail(HFE_EINVAL, "database file header does not match the keys");
+  if (forms == 0) forms = h.forms;
+  if ((forms & ~h.forms) != 0) return fail(HFE_EINVAL, "the file does not hold every requested form");
   std::unique_ptr<hfe_db> D(new (std::nothrow) hfe_db());
   if (!D) return fail(HFE_ENOMEM, "host allocation failed");
   D->kind = kDb;
@@ -169,11 +171,20 @@ hfe_status hfe_db_load(const hfe_keys* keys, const char* path, void* stream, hfe
   expected_bytes(D.get(), want);
   for (int i = 0; i < 4; ++i)
     if (want[i] != h.bytes[i]) return fail(HFE_EINVAL, "database file sizes do not match its header");
+  // the requested forms only; the others' bytes are skipped in the file
+  D->forms = forms;
+  const uint32_t form_of[4] = {HFE_FORM_PLAIN_U64, HFE_FORM_I8_MFMA, HFE_FORM_RNS_I8, HFE_FORM_P2_I8};
+  if (!(forms & HFE_FORM_RNS_I8)) D->n_rns = 0;
+  if (!(forms & HFE_FORM_P2_I8)) D->n_p2 = 0;
   DevBuf* bufs[4] = {&D->Dt, &D->digits, &D->rns, &D->p2};
   Pinned stage;
   HFE_CHECK_HIP(hipHostMalloc(&stage.p, kStage, hipHostMallocDefault));
   for (int i = 0; i < 4; ++i) {
     if (!h.bytes[i]) continue;
+    if (!(forms & form_of[i])) {
+      if (std::fseek(f.f, (long)h.bytes[i], SEEK_CUR) != 0) return fail(HFE_EINVAL, "database file is truncated");
+      continue;
+    }
     HFE_TRY(bufs[i]->alloc((size_t)h.bytes[i], s));
     uint8_t* dst = bufs[i]->as<uint8_t>();
     for (uint64_t off = 0; off < h.bytes[i]; off += kStage) {

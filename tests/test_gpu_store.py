@@ -1,8 +1,9 @@
 """Saving and loading the encrypted database (hfe_db_save / hfe_db_load).
 
 A database written to a file and read back under the same keys must give bit-identical results in
-every form it was prepared for (and the same plain residues); a file written under other keys, a
-truncated file, a file with trailing bytes and a file that is not a database are refused.
+every form it was prepared for (and the same plain residues), also when only some of its forms are
+loaded; a file written under other keys, a truncated file, a file with trailing bytes, a file that
+is not a database and a request for a form the file lacks are refused.
 """
 import os
 import sys
@@ -72,6 +73,27 @@ def test_subset_of_forms_round_trips(env, tmp_path):
     with pytest.raises(H.HfeError) as e:                            # not prepared for the digit form
         H.hfe_ccmm(loaded, env["q"], 0, 40, H.HFE_FORM_I8_MFMA)
     assert e.value.status == -1
+
+
+def test_loading_a_subset_of_the_stored_forms(env, tmp_path):
+    path = tmp_path / "all.hfe"
+    H.hfe_db_save(env["db"], path)
+    d1 = env["d1"]
+    for form in INT8:
+        _say(f"[gpu-store] load only form {form}")
+        one = H.hfe_db_load(env["keys"], path, form)
+        assert np.array_equal(_result(one, env["q"], 0, d1, form), _result(env["db"], env["q"], 0, d1, form))
+        other = H.HFE_FORM_PLAIN_U64 if form != H.HFE_FORM_PLAIN_U64 else H.HFE_FORM_I8_MFMA
+        with pytest.raises(H.HfeError) as e:                        # the skipped forms are absent
+            H.hfe_ccmm(one, env["q"], 0, d1, other)
+        assert e.value.status == -1
+        one.free()
+    m_db = torch.from_numpy(np.random.default_rng(68).integers(-1, 2, (20, 700)).astype(np.int8)).cuda()
+    rns_only = tmp_path / "rns_only.hfe"
+    H.hfe_db_save(H.hfe_encrypt_db(env["keys"], m_db, 69, H.HFE_FORM_RNS_I8), rns_only)
+    with pytest.raises(H.HfeError) as e:                            # a form the file lacks
+        H.hfe_db_load(env["keys"], rns_only, H.HFE_FORM_P2_I8)
+    assert e.value.status == -1 and "requested form" in str(e.value)
 
 
 def test_bad_files_are_refused(env, tmp_path):
