@@ -34,7 +34,10 @@ PEAK_I8_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 # Bytes beyond L2 per launch of the contraction on the share workload (d3 = 512), from rocprofv3
 # FETCH_SIZE + WRITE_SIZE scaled by a 1 GiB copy (profiles/pmc_k_gemm_i8_dma_q128_r128_share_q512.md,
 # profiles/pmc_k_gemm_i8_dma2_w2_share_q512.md); reported only for the kernels they were taken on.
-MEASURED_TRAFFIC_GB = {"dma_q128_w2": 28.3, "dma_r128_w2": 30.4, "dma2_w2": 90.1}
+MEASURED_TRAFFIC_GB = {"dma_q128_w2": 28.3, "dma_r128_w2": 30.4, "dma2_w2": 90.1,
+                       # the 256-column RNS and n^2 contractions (profiles/pmc_k_gemm_rns_share_q512.md,
+                       # profiles/pmc_k_gemm_p2_share_q512.md), fetch + write
+                       "rns256": 36.6, "p2_256": 46.1}
 KEY_SEED, DB_SEED, Q_SEED = 11, 22, 33
 
 
@@ -482,6 +485,7 @@ def main():
                 "comparisons_per_s": rns["comparisons_per_s"], "contraction_ms": rns["contraction_ms"],
                 "lift_ms": rns["lift_ms"], "crt_rescale_ms": rns["rescale_ms"],
                 "int8_ops_per_launch": rns_ops,
+                "traffic_gb": MEASURED_TRAFFIC_GB["rns256"] if w.name == S.PAPER_SHARE.name else None,
                 "frac_of_peak": rns_ops / (rns["contraction_ms"] * 1e-3) / 1e12 / PEAK_I8_TOPS,
                 "over_i8_step": i8["ms_per_step"] / rns["ms_per_step"], "equals_i8_ip": same_rns,
                 "phases_ms": rns["phases_ms"]},
@@ -489,6 +493,7 @@ def main():
                "ms_per_step": p2["ms_per_step"], "comparisons_per_s": p2["comparisons_per_s"],
                "contraction_ms": p2["contraction_ms"], "lift_ms": p2["lift_ms"], "crt_rescale_ms": p2["rescale_ms"],
                "int8_ops_per_launch": p2_ops,
+               "traffic_gb": MEASURED_TRAFFIC_GB["p2_256"] if w.name == S.PAPER_SHARE.name else None,
                "frac_of_peak": p2_ops / (p2["contraction_ms"] * 1e-3) / 1e12 / PEAK_I8_TOPS,
                "over_i8_step": i8["ms_per_step"] / p2["ms_per_step"], "equals_i8_ip": same_p2,
                "phases_ms": p2["phases_ms"]},
