@@ -148,9 +148,11 @@ __device__ __forceinline__ int64_t mod_f64(int64_t x, int64_t m, double rcp) {
   return r;
 }
 
-// Per base n_j of kP2Bases: n_j, n_j^2 and their reciprocals, computed at compile time.
+// Per base n_j of kP2Bases: n_j, n_j^2, their reciprocals and ceil(2^32 / n_j), computed at
+// compile time.
 struct P2BaseConsts {
   int32_t n[kP2MaxBases], m[kP2MaxBases];
+  uint32_t magic_n[kP2MaxBases];
   double rcp_n[kP2MaxBases], rcp_m[kP2MaxBases];
 };
 constexpr P2BaseConsts make_p2_base_consts() {
@@ -158,6 +160,7 @@ constexpr P2BaseConsts make_p2_base_consts() {
   for (int j = 0; j < kP2MaxBases; ++j) {
     c.n[j] = kP2Bases[j];
     c.m[j] = kP2Bases[j] * kP2Bases[j];
+    c.magic_n[j] = (uint32_t)(((1ull << 32) + (uint64_t)c.n[j] - 1) / (uint64_t)c.n[j]);
     c.rcp_n[j] = 1.0 / (double)c.n[j];
     c.rcp_m[j] = 1.0 / (double)c.m[j];
   }
@@ -167,13 +170,16 @@ __constant__ static P2BaseConsts kP2C = make_p2_base_consts();
 
 // Centered x (|x| < 2^48) -> (M, M') with x = M + n M' (mod n^2) for n = kP2Bases[j], both in
 // [-(n-1)/2, (n-1)/2]: r = x mod n^2, M = the balanced residue of r mod n, M' = the balanced
-// residue of (r - M) / n (an integer in [0, n]) mod n.
+// residue of (r - M) / n (an integer in [0, n]) mod n.  After the first step everything is below
+// 2^17, where the multiply-high quotient by ceil(2^32 / n) is exact (mod_small).
 __device__ __forceinline__ void p2_digits(int64_t x, int j, int32_t& M, int32_t& Mp) {
   const int32_t n = kP2C.n[j], h = (n - 1) / 2;
-  const int32_t r = (int32_t)mod_f64(x, kP2C.m[j], kP2C.rcp_m[j]);
-  M = (int32_t)mod_f64(r, n, kP2C.rcp_n[j]);
+  const uint32_t magic = kP2C.magic_n[j];
+  const uint32_t r = (uint32_t)mod_f64(x, kP2C.m[j], kP2C.rcp_m[j]);
+  M = (int32_t)mod_small(r, (uint32_t)n, magic);
   if (M > h) M -= n;
-  int32_t t = (int32_t)((double)(r - M) * kP2C.rcp_n[j] + 0.5);  // exact multiple of n: nearest is exact
+  const uint32_t rm = (uint32_t)((int32_t)r - M);  // a multiple of n in [0, n^2 + h]
+  int32_t t = (int32_t)__umulhi(rm, magic);         // (r - M) / n, exact
   if (t == n) t = 0;
   Mp = t > h ? t - n : t;
 }
