@@ -145,6 +145,10 @@ hfe_status hfe_encrypt_db(const hfe_keys* keys, const int8_t* m_db, int64_t d1, 
  * requested form, or is truncated or longer than its header says; HFE_ENOMEM / HFE_EDEVICE from
  * the device. */
 hfe_status hfe_db_save(const hfe_db* db, const char* path, void* stream);
+/* Device bytes the database holds for one form (0: all its forms): the planes of Section 6.3's
+ * storage count, (N_DB + d1) (d2 + N_Q) entries per prime times 8 bytes (plain), 5 (digits),
+ * n (RNS) or 2 n (n^2), in their padded layouts (K rounded up to 64, rows to 64 plus 256). */
+hfe_status hfe_db_bytes(const hfe_db* db, uint32_t form, size_t* bytes);
 hfe_status hfe_db_load(const hfe_keys* keys, const char* path, uint32_t forms, void* stream, hfe_db** out);
 
 /* Query encryption in MSRLWE form (Section 2.3): per column c and query prime,

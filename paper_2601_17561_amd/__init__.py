@@ -39,7 +39,7 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_i8_variant_name", "hfe_set_i8_variant", "hfe_ccmm_batched", "hfe_plan_create", "hfe_plan_run",
             "hfe_plan_result", "hfe_autotune", "hfe_autotune_save", "hfe_autotune_load", "hfe_server_create",
             "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_stats", "hfe_server_reset_stats",
-            "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted")
+            "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes")
 
 
 class HfeError(RuntimeError):
@@ -93,6 +93,7 @@ _SIGS = {
     "hfe_encrypt_db": [_vp, _vp, _i64, _u64, _u32, _vp, ctypes.POINTER(_vp)],
     "hfe_encrypt": [_vp, _vp, _i64, _u32, _u64, _vp, ctypes.POINTER(_vp)],
     "hfe_db_save": [_vp, ctypes.c_char_p, _vp],
+    "hfe_db_bytes": [_vp, _u32, ctypes.POINTER(_sz)],
     "hfe_result_create": [_vp, _vp, _vp, ctypes.POINTER(_vp)],
     "hfe_server_submit_encrypted": [_vp, _vp, _vp, ctypes.POINTER(_u64)],
     "hfe_db_load": [_vp, ctypes.c_char_p, _u32, _vp, ctypes.POINTER(_vp)],
@@ -284,6 +285,13 @@ def hfe_encrypt_db(keys: Handle, m_db, seed: int, forms: int = HFE_FORM_PLAIN_U6
 def hfe_db_save(db: Handle, path, stream=None) -> None:
     """Write the encrypted database (every prepared form) to `path`; returns when the file is complete."""
     _check(_lib.hfe_db_save(db.ptr, os.fsencode(path), _stream(stream)), "hfe_db_save")
+
+
+def hfe_db_bytes(db: Handle, form: int = 0) -> int:
+    """Device bytes the database holds for one form (0: all its forms)."""
+    out = _sz()
+    _check(_lib.hfe_db_bytes(db.ptr, form, ctypes.byref(out)), "hfe_db_bytes")
+    return int(out.value)
 
 
 def hfe_db_load(keys: Handle, path, forms: int = 0, stream=None) -> Handle:

@@ -130,6 +130,23 @@ hfe_status hfe_db_save(const hfe_db* db, const char* path, void* stream) {
   return HFE_OK;
 }
 
+hfe_status hfe_db_bytes(const hfe_db* db, uint32_t form, size_t* bytes) {
+  const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(db));
+  if (!db || hb->kind != kDb || !bytes) return fail(HFE_EINVAL, "invalid database handle or bytes");
+  if (form != 0 && form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 &&
+      form != HFE_FORM_P2_I8)
+    return fail(HFE_EINVAL, "form must be 0 or one hfe_form");
+  if (form != 0 && !(db->forms & form)) return fail(HFE_EINVAL, "database not prepared for this form");
+  uint64_t b[4];
+  expected_bytes(db, b);
+  const uint32_t form_of[4] = {HFE_FORM_PLAIN_U64, HFE_FORM_I8_MFMA, HFE_FORM_RNS_I8, HFE_FORM_P2_I8};
+  size_t total = 0;
+  for (int i = 0; i < 4; ++i)
+    if (form == 0 || form == form_of[i]) total += (size_t)b[i];
+  *bytes = total;
+  return HFE_OK;
+}
+
 hfe_status hfe_db_load(const hfe_keys* keys, const char* path, uint32_t forms, void* stream, hfe_db** out) {
   if (!out) return fail(HFE_EINVAL, "out is NULL");
   *out = nullptr;

@@ -96,6 +96,31 @@ def test_loading_a_subset_of_the_stored_forms(env, tmp_path):
     assert e.value.status == -1 and "requested form" in str(e.value)
 
 
+def test_database_bytes_follow_the_storage_formula(env, tmp_path):
+    """Section 6.3's storage count: (N_DB + d1)(d2 + N_Q) entries per prime, times 8 / 5 / n / 2n bytes for
+    the four forms, in the padded plane layout (K up to a multiple of 64, rows up to a multiple of 64
+    plus 256 zero rows), and the same size a saved file carries."""
+    log_n_db, log_n_q, d1, d2, level = 8, 9, 150, 700, 2
+    R, K, primes = (1 << log_n_db) + d1, d2 + (1 << log_n_q), level + 1
+    KB, R_pad = (K + 63) // 64, (R + 63) // 64 * 64 + 256
+    db = env["db"]
+    plain = H.hfe_db_bytes(db, H.HFE_FORM_PLAIN_U64)
+    assert plain == R * K * primes * 8                                    # exactly the formula
+    digits = H.hfe_db_bytes(db, H.HFE_FORM_I8_MFMA)
+    assert digits == primes * 5 * KB * R_pad * 64 and digits >= R * K * primes * 5
+    rns, p2 = H.hfe_db_bytes(db, H.HFE_FORM_RNS_I8), H.hfe_db_bytes(db, H.HFE_FORM_P2_I8)
+    plane = primes * KB * R_pad * 64
+    assert rns % plane == 0 and p2 % (2 * plane) == 0                     # n moduli, n bases (2 planes each)
+    n_rns, n_p2 = rns // plane, p2 // (2 * plane)
+    assert 1 <= n_rns <= 16 and 1 <= n_p2 <= 8
+    assert H.hfe_db_bytes(db) == plain + digits + rns + p2
+    path = tmp_path / "size.hfe"
+    H.hfe_db_save(db, path)
+    assert path.stat().st_size == 104 + H.hfe_db_bytes(db)               # header + every form's planes
+    with pytest.raises(H.HfeError):
+        H.hfe_db_bytes(db, 3)                                             # not one form
+
+
 def test_bad_files_are_refused(env, tmp_path):
     path = tmp_path / "db.hfe"
     H.hfe_db_save(env["db"], path)
