@@ -118,6 +118,14 @@ TINY = Workload("tiny_n4096_d1_256_d2_1024_q4", 12, 12, 1, 1, 256, 1024, 4, 1,
 TINY_MULTI = Workload("tinymulti_ndb128_nq512_d1_256_d2_1024_q4", 7, 9, 2, 2, 256, 1024, 2, 2,
                       planted=(Planted(1, 200, -1, 0.1),), seed=BASE_SEED + 11)
 
+# Mid-size workload whose shapes cross every tile boundary of the contraction kernels: 956 output
+# rows (256 A rows + 700 codes: ragged against 64-, 128- and 256-row tiles), 272 query columns
+# (17 eyes x 16 shifts: two 128-column tiles plus 16, one 256-column tile plus 16), three chunks
+# per secret stack (d2 = 1280 over N_Q = 512, the last one truncated; 700 codes over N_DB = 256),
+# three query primes plus the special prime.
+MID = Workload("mid_ndb256_nq512_L3p_d1_700_d2_1280_q272", 8, 9, 3, 3, 700, 1280, 17, 16,
+               seed=BASE_SEED + 21)
+
 # One GPU's share at paper scale: N_DB = 2^14, N_Q = 2^13, three query primes
 # plus the special prime, 32 eyes x 16 shifts = 512 query columns against
 # 14,336 database codes of 12,800 bits.
@@ -168,7 +176,7 @@ def random_eyes(seed: int, stream: int, n_eyes: int, d2: int, p_code: float = 0.
             (g.random((n_eyes, d2)) < p_mask).astype(np.uint8))
 
 
-WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, PAPER_SHARE, PAPER_SHARE_L5)}
+WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, MID, PAPER_SHARE, PAPER_SHARE_L5)}
 
 
 def planted_for(w: Workload, count: int = 4) -> Tuple[Planted, ...]:

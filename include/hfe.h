@@ -165,6 +165,16 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
 hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
                     void* stream, hfe_rct** out);
 
+/* The exact product before the rescale, for parity checks of the contraction: the lift and the
+ * contraction of hfe_ccmm in form `form`, without RS_p.  C (device, (level + 1) x d3 x (N_DB + rows)
+ * uint64, caller-owned) receives C[z][c][r] = sum_k D[src(r)][k] L(x_c)[k] mod prime_z for the
+ * level's primes z < level and p (z = level), where L is the centered lift of query column c and
+ * row r < N_DB is A-part row r, row N_DB + i database code row0 + i.  The small-modulus forms
+ * reconstruct these residues with their reconstruction kernel alone (hfe_ccmm fuses it with the
+ * rescale).  Errors as hfe_ccmm; C NULL: HFE_EINVAL. */
+hfe_status hfe_ccmm_product(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
+                            void* stream, uint64_t* C);
+
 /* An empty result handle shaped for query q against every code of db (level x d3 x (N_DB + d1)
  * residues, allocated on `stream`), for hfe_server_submit_encrypted.  Release with hfe_free. */
 hfe_status hfe_result_create(const hfe_db* db, const hfe_qct* q, void* stream, hfe_rct** out);

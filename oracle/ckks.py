@@ -301,3 +301,100 @@ def ccmm_entry(P: Params, d_row: Dict[int, List[int]], xt_col: Dict[int, np.ndar
     x = crt(res, [m for _, m in ids])
     y = rescale_p(x, P.p, Q)
     return [y % qi for qi in moduli]
+
+
+# ---------------------------------------------------------------- row and column blocks (large sizes)
+# Whole database rows, selected query columns and grids of result entries, evaluated from the same
+# definitions as the full-matrix functions above, for workloads whose full matrices do not fit.
+
+def s_q_columns(keys: Keys, v0: int, v1: int) -> np.ndarray:
+    """Columns v0 .. v1 - 1 of S_Q (d2 x (v1 - v0)): row t of chunk j is Neg(s_j)[t - j N_Q]."""
+    P = keys.params
+    n = P.n_q
+    t = np.arange(P.d2)[:, None]
+    v = np.arange(v0, v1)[None, :]
+    d = t % n - v
+    s = keys.s[t // n, d % n]
+    return np.where(d >= 0, s, -s).astype(np.int64)
+
+
+def db_rows(keys: Keys, m_db: np.ndarray, seed: int, pid: int, prime: int, rows: Sequence[int],
+            chunk: int = 512) -> np.ndarray:
+    """Rows `rows` of D mod prime ((len(rows) x K) int64), as encrypt_db defines them: A rows are the
+    uniform elements; B row i = -S_DB[i] A + p [M_DB[i] | M_DB[i] S_Q] + E[i], with A and S_Q taken
+    chunk columns at a time."""
+    P = keys.params
+    rows = [int(r) for r in rows]
+    K = P.K
+    kk = np.arange(K)
+    out = np.empty((len(rows), K), dtype=np.int64)
+    for idx, r in enumerate(rows):
+        if r < P.n_db:
+            out[idx] = prng.uniform_mod(seed, prng.DBA, pid, np.full(K, r), kk, prime)
+    bidx = [idx for idx, r in enumerate(rows) if r >= P.n_db]
+    if not bidx:
+        return out
+    b = [rows[idx] - P.n_db for idx in bidx]
+    M = m_db[b].astype(np.int64)                                            # nb x d2
+    plain = np.empty((len(b), K), dtype=np.int64)
+    plain[:, :P.d2] = M
+    for v0 in range(0, P.n_q, chunk):
+        v1 = min(P.n_q, v0 + chunk)
+        plain[:, P.d2 + v0:P.d2 + v1] = imatmul(M, s_q_columns(keys, v0, v1))
+    S = s_db_rows(keys, b)                                                  # nb x N_DB
+    SA = np.empty((len(b), K), dtype=np.int64)
+    for c0 in range(0, K, chunk):
+        c1 = min(K, c0 + chunk)
+        SA[:, c0:c1] = imatmul(S, prng.uniform_columns(seed, prng.DBA, pid, P.n_db, c0, c1, prime))
+    E = prng.gaussian(seed, prng.DBE, 0, np.repeat(b, K), np.tile(kk, len(b))).reshape(len(b), K)
+    out[bidx] = (-SA + (P.p % prime) * plain + E) % prime
+    return out
+
+
+def query_columns(keys: Keys, m_q_rows: np.ndarray, cols: Sequence[int], level: int, seed: int
+                  ) -> Dict[int, np.ndarray]:
+    """Rows `cols` of XT per query prime i ((len(cols) x K)): encrypt_query restricted to the query
+    columns cols, whose d2 entries are the rows of m_q_rows."""
+    P = keys.params
+    cols = np.asarray(cols, dtype=np.uint64)
+    n = len(cols)
+    t = np.arange(P.n_q, dtype=np.uint64)
+    A = {i: prng.uniform_mod(seed, prng.QA, i, np.repeat(t, n), np.tile(cols, P.n_q), P.q[i]).reshape(P.n_q, n)
+         for i in range(level)}
+    tt = np.arange(P.d2, dtype=np.uint64)
+    E = prng.gaussian(seed, prng.QE, 0, np.repeat(tt, n), np.tile(cols, P.d2)).reshape(P.d2, n)
+    return encrypt_query_with(P, s_q_matrix(keys), m_q_rows, level, A, E)
+
+
+def lift_mod(P: Params, XT: Dict[int, np.ndarray], level: int, prime: int) -> np.ndarray:
+    """L(x) mod prime for every query residue vector (int64, the shape of XT[0]): the CRT value of
+    the residues mod Q (sum of x_i (Q/q_i) ((Q/q_i)^-1 mod q_i), mod Q), centered, reduced mod prime;
+    the arithmetic of crt and centered on Python integers held in object arrays."""
+    moduli = [P.q[i] for i in range(level)]
+    Q = P.Q(level)
+    acc = np.zeros(XT[0].shape, dtype=object)
+    for i, m in enumerate(moduli):
+        Mi = Q // m
+        acc = acc + XT[i].astype(object) * (Mi * pow(Mi, -1, m))
+    acc = acc % Q
+    acc = np.where(acc > Q // 2, acc - Q, acc)
+    return (acc % prime).astype(np.int64)
+
+
+def ccmm_entries(P: Params, d_rows: Dict[int, np.ndarray], xt_cols: Dict[int, np.ndarray], level: int
+                 ) -> Dict[int, np.ndarray]:
+    """Result residues per query prime i ((n_cols x n_rows)) of the entries (row, column) of a grid:
+    d_rows[pid] holds the grid's rows of D per prime stream id, xt_cols[i] its query columns' rows of
+    XT.  Each entry is RS_p of the exact product of its row and the lifted column, as in ccmm."""
+    ids = prime_ids(P, level)
+    moduli = [m for _, m in ids]
+    Q = P.Q(level)
+    C = {pid: modmatmul(d_rows[pid], lift_mod(P, xt_cols, level, prime).T, prime) for pid, prime in ids}
+    nr, nc = C[ids[0][0]].shape
+    res = {i: np.empty((nc, nr), dtype=np.int64) for i in range(level)}
+    for r in range(nr):
+        for c in range(nc):
+            y = rescale_p(crt([int(C[pid][r, c]) for pid, _ in ids], moduli), P.p, Q)
+            for i in range(level):
+                res[i][c, r] = y % P.q[i]
+    return res

@@ -197,6 +197,34 @@ def uniform_matrix(seed: int, purpose: int, sub: int, rows: int, cols: int, q: i
     return out
 
 
+def uniform_columns(seed: int, purpose: int, sub: int, rows: int, c0: int, c1: int, q: int) -> np.ndarray:
+    """(rows x (c1 - c0)) int64 matrix whose column j is elements (i0 = 0..rows-1, i1 = c0 + j): the
+    same values as uniform_matrix, for large sizes.
+
+    For a fixed column i1 the counters (i0 >> 2, i1, 0, 0) run through consecutive values of word 0,
+    so one column is the raw output of numpy's Philox4x64-10 bit generator (an independent library
+    implementation of the same published generator) started at that column's first counter.  numpy
+    increments its 256-bit counter before each block, so the generator is seeded one below it.
+    Words w >= floor(2^64 / q) q take the rejection path of uniform_mod.
+    """
+    blocks = -(-rows // 4)
+    out = np.empty((rows, c1 - c0), dtype=np.int64)
+    bound = np.uint64(((1 << 64) // q) * q)
+    key = np.array([seed & (2**64 - 1), tag(purpose, sub)], dtype=np.uint64)
+    for j, c in enumerate(range(c0, c1)):
+        ctr = (c << 64) - 1 if c else (1 << 256) - 1            # 256-bit counter (0, c, 0, 0) minus one
+        words = [(ctr >> (64 * t)) & (2**64 - 1) for t in range(4)]
+        g = np.random.Philox(key=key, counter=np.array(words, dtype=np.uint64))
+        w = g.random_raw(4 * blocks)[:rows]
+        col = (w % np.uint64(q)).astype(np.int64)
+        bad = np.nonzero(w >= bound)[0]
+        if bad.size:
+            col[bad] = uniform_mod(seed, purpose, sub, bad.astype(np.uint64),
+                                   np.full(bad.size, c, dtype=np.uint64), q)
+        out[:, j] = col
+    return out
+
+
 def gaussian_matrix(seed: int, purpose: int, sub: int, rows: int, cols: int) -> np.ndarray:
     """(rows x cols) Gaussian integers; entry [r, c] is element (i0 = r, i1 = c)."""
     r2 = np.arange(-(-rows // 2), dtype=np.uint64)[:, None]

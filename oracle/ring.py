@@ -66,8 +66,8 @@ def imatmul(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     assert bound < _LIMIT, "imatmul: partial sums could overflow int64"
     if A.size == 0 or B.size == 0:
         return np.zeros((A.shape[0], B.shape[1]), dtype=np.int64)
-    if min(A.shape[0], B.shape[1]) < 64:
-        return A @ B                 # skinny products: numpy's int64 loop is faster
+    if A.shape[0] * B.shape[1] * K < (1 << 22):
+        return A @ B                 # small products: numpy's int64 loop has less overhead
     return torch.from_numpy(np.ascontiguousarray(A)).matmul(
         torch.from_numpy(np.ascontiguousarray(B))).numpy()
 

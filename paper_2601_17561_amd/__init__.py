@@ -39,7 +39,8 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_i8_variant_name", "hfe_set_i8_variant", "hfe_ccmm_batched", "hfe_plan_create", "hfe_plan_run",
             "hfe_plan_result", "hfe_autotune", "hfe_autotune_save", "hfe_autotune_load", "hfe_server_create",
             "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_stats", "hfe_server_reset_stats",
-            "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes")
+            "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes",
+            "hfe_ccmm_product")
 
 
 class HfeError(RuntimeError):
@@ -98,6 +99,7 @@ _SIGS = {
     "hfe_server_submit_encrypted": [_vp, _vp, _vp, ctypes.POINTER(_u64)],
     "hfe_db_load": [_vp, ctypes.c_char_p, _u32, _vp, ctypes.POINTER(_vp)],
     "hfe_ccmm": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_vp)],
+    "hfe_ccmm_product": [_vp, _vp, _i64, _i64, _i32, _vp, _vp],
     "hfe_decrypt": [_vp, _vp, _vp, _vp, _vp],
     "hfe_match": [_vp, _vp, _i64, ctypes.POINTER(_i32), _i32, _vp, _i64, _i32, _u32, _u32, _vp, _vp, _vp],
     "hfe_export": [_vp, _i32, _sz, _vp, _sz, ctypes.POINTER(_sz)],
@@ -314,6 +316,20 @@ def hfe_ccmm(db: Handle, q: Handle, row0: int, rows: int, form: int, stream=None
     out = _vp()
     _check(_lib.hfe_ccmm(db.ptr, q.ptr, row0, rows, form, _stream(stream), ctypes.byref(out)), "hfe_ccmm")
     return Handle(out.value, (db, q))
+
+
+def hfe_ccmm_product(db: Handle, q: Handle, row0: int, rows: int, form: int, C=None, stream=None):
+    """The exact product before the rescale: uint64 GPU tensor ((level + 1) x d3 x (N_DB + rows)),
+    viewed as int64 (residues < 2^36)."""
+    torch = _torch()
+    level, d3, _, _ = hfe_shape(q)
+    n_db = hfe_shape(db)[2] - hfe_shape(db)[1]
+    if C is None:
+        C = torch.empty((level + 1, d3, n_db + rows), dtype=torch.int64,
+                        device=torch.device("cuda", torch.cuda.current_device()))
+    _check(_lib.hfe_ccmm_product(db.ptr, q.ptr, row0, rows, form, _stream(stream), _dev_ptr(C, torch.int64)),
+           "hfe_ccmm_product")
+    return C
 
 
 def hfe_decrypt(keys: Handle, r: Handle, v=None, ip=None, stream=None):

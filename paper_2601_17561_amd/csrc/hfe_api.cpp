@@ -728,8 +728,11 @@ static int pick_i8_variant(int level, int64_t d3) {
   return best;
 }
 
+// C_ext == nullptr: the result (rescaled residues) into R->out.  C_ext != nullptr: only the exact
+// product before the rescale, C_ext[z][c][r] for the level's primes and p (z = level), and R only
+// records the shape.
 static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, int64_t rows, int32_t form,
-                            hipStream_t s, hfe_rct* R) {
+                            hipStream_t s, hfe_rct* R, uint64_t* C_ext = nullptr) {
   const hfe_keys* K = D->keys;
   const int level = Qc->level;
   const int64_t ndb = 1ll << K->P.log_n_db;
@@ -755,10 +758,14 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   DevBuf C, Xp, Xd;
   // the small-modulus forms reconstruct and rescale in one pass (no contraction output C)
   const bool fused = form == HFE_FORM_RNS_I8 || form == HFE_FORM_P2_I8;
-  if (!fused) HFE_TRY(C.alloc(sizeof(uint64_t) * (size_t)nz * d3 * R_out, s));
+  const bool product = C_ext != nullptr;
+  if (!fused && !product) HFE_TRY(C.alloc(sizeof(uint64_t) * (size_t)nz * d3 * R_out, s));
+  uint64_t* Cp = product ? C_ext : C.as<uint64_t>();
   const RescaleArgs ra = make_rescale_args(K, level);
-  HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
-  R->outp = R->out.as<uint64_t>();
+  if (!product) {
+    HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
+    R->outp = R->out.as<uint64_t>();
+  }
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
   g.nz = nz;
@@ -773,7 +780,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   g.d3 = d3;
   g.d3_pad = (d3 + kQueryPad - 1) / kQueryPad * kQueryPad;
   for (int z = 0; z < nz; ++z) {
-    g.C[z] = fused ? nullptr : C.as<uint64_t>() + (size_t)z * d3 * R_out;
+    g.C[z] = fused ? nullptr : Cp + (size_t)z * d3 * R_out;
     g.mod[z] = K->mods[slot(z)];
   }
   if (form == HFE_FORM_PLAIN_U64) {
@@ -818,7 +825,11 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_rns(rg, tq, s));
     HFE_LAUNCH(mark(2));
-    HFE_LAUNCH(launch_crt_rescale_rns(res.as<uint8_t>(), d3 * R_out, make_rns_crt_args(K, level, n), ra, R->outp, s));
+    if (product)
+      HFE_LAUNCH(launch_crt_rns(res.as<uint8_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), Cp, s));
+    else
+      HFE_LAUNCH(launch_crt_rescale_rns(res.as<uint8_t>(), d3 * R_out, make_rns_crt_args(K, level, n), ra, R->outp,
+                                        s));
   } else if (form == HFE_FORM_P2_I8) {
     const int n = D->n_p2;
     const int tq = p2_tile_q(&d3, &R_out, &nz, 1);  // query tile width by padded work
@@ -849,7 +860,11 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_p2(pg, tq, s));
     HFE_LAUNCH(mark(2));
-    HFE_LAUNCH(launch_crt_rescale_p2(res.as<uint16_t>(), d3 * R_out, make_p2_crt_args(K, level, n), ra, R->outp, s));
+    if (product)
+      HFE_LAUNCH(launch_crt_p2(res.as<uint16_t>(), nz, d3 * R_out, make_p2_crt_args(K, level, n), Cp, s));
+    else
+      HFE_LAUNCH(launch_crt_rescale_p2(res.as<uint16_t>(), d3 * R_out, make_p2_crt_args(K, level, n), ra, R->outp,
+                                       s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
@@ -862,10 +877,9 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_i8(g, pick_i8_variant(level, d3), s));
   }
-  if (!fused) {
+  if (!fused && !product) {
     HFE_LAUNCH(mark(2));
-    HFE_LAUNCH(launch_rescale(C.as<uint64_t>(), C.as<uint64_t>() + (size_t)level * d3 * R_out, d3 * R_out, ra,
-                              R->outp, s));
+    HFE_LAUNCH(launch_rescale(Cp, Cp + (size_t)level * d3 * R_out, d3 * R_out, ra, R->outp, s));
   }
   HFE_LAUNCH(mark(3));
   return HFE_OK;
@@ -894,6 +908,23 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
   }
   *out = R;
   return HFE_OK;
+}
+
+hfe_status hfe_ccmm_product(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
+                            void* stream, uint64_t* C) {
+  if (!C) return fail(HFE_EINVAL, "C is NULL");
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  const hfe_qct* Qc = as_handle<hfe_qct>(q, kQct);
+  if (!D || !Qc) return fail(HFE_EINVAL, "invalid database or query handle");
+  if (Qc->keys != D->keys) return fail(HFE_EINVAL, "database and query use different keys");
+  if (Qc->K != D->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
+  if (Qc->level > D->keys->L) return fail(HFE_ELEVEL, "query level above the database primes");
+  if (row0 < 0 || rows < 1 || row0 + rows > D->d1) return fail(HFE_ESHAPE, "row range outside the database");
+  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
+    return fail(HFE_EINVAL, "unknown form");
+  if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
+  hfe_rct R;  // shape record only; the buffers of the call are released in stream order on return
+  return ccmm_impl(D, Qc, row0, rows, form, (hipStream_t)stream, &R, C);
 }
 
 hfe_status hfe_result_create(const hfe_db* db, const hfe_qct* q, void* stream, hfe_rct** out) {

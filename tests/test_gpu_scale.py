@@ -6,12 +6,21 @@ The oracle cannot materialise this size, so the checks are:
   * keys: every secret coefficient equals the oracle's;
   * database and query ciphertexts: sampled entries (A-part and B-part rows, every prime,
     first/last/ragged columns) and whole sampled query columns equal the oracle's
-    single-entry evaluation of the same definitions;
-  * CCMM result: sampled A-part entries recomputed by the oracle from its own database rows
-    and query columns; the int8-MFMA result equals the plain result on every residue;
+    single-entry evaluation of the same definitions; 4,096 more database entries of 32 whole
+    rows (16 of them B rows) equal the oracle's values stored in golden/share_samples.json;
+  * CCMM result: 6,144 result residues (32 rows, A and B, x 64 columns, 8 in every 64-column
+    tile, x 3 primes) equal the oracle's stored values, in every form and every digit tile
+    configuration, on the full row range and on a row shard; sampled A-part entries are also
+    recomputed here from the oracle's rows and columns; all four forms agree on every residue;
+  * the exact product before the rescale, in every form, satisfies C r = D (X r) mod each prime
+    for two random vectors r (Freivalds), with D the database residues and X the lifted query
+    (the query residues, and for p their centered CRT value mod p computed by the oracle); and
+    RS_p of 20,000 sampled product entries, by the oracle's big-integer rescale, equals the result;
   * decryption: every one of the 7,340,032 inner products equals the brute-force popcount
     truth and lies within 0.25 of it; decisions and per-eye matches agree.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -163,3 +172,151 @@ def test_decrypt_equals_popcount_truth_on_all_pairs(run):
     assert np.array_equal(run["eye"].cpu().numpy().astype(bool), eye_ref)
     assert eye_ref.sum() >= len(S.planted_for(W))      # planted eyes are found
     _say(f"[gpu-scale] max |v - IP| = {np.abs(v - ip_true).max():.4f}, matches {int(dec_ref.sum())}")
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "share_samples.json")
+SHARD = (3000, 5000)
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    assert g["workload"] == W.name and g["seeds"] == {"keys": KEY_SEED, "db": DB_SEED, "query": Q_SEED}
+    g["result"] = np.array(g["result"], dtype=np.int64)      # [prime][col][row]
+    g["db"] = np.array(g["db"], dtype=np.int64)              # [slot][row][k]
+    return g
+
+
+def test_golden_database_entries(run, golden):
+    Po = run["Po"]
+    R = Po.n_db + W.d1
+    got = np.empty_like(golden["db"])
+    for z in range(got.shape[0]):
+        for a, r in enumerate(golden["rows"]):
+            for b, k in enumerate(golden["db_cols"]):
+                got[z, a, b] = int(H.hfe_export(run["db"], 0, (z * Po.K + k) * R + r, 1)[0])
+    bad = np.argwhere(got != golden["db"])
+    assert bad.size == 0, f"{len(bad)} database entries differ, first {bad[:3].tolist()}"
+
+
+def _check_golden(res, golden, rows_out, what):
+    """res: [prime][col][row] result residues; rows_out: output row of each golden row (or -1)."""
+    cols = np.array(golden["cols"])
+    sel = [a for a, r in enumerate(rows_out) if r >= 0]
+    got = res[:, cols][:, :, [rows_out[a] for a in sel]]
+    exp = golden["result"][:, :, sel]
+    bad = np.argwhere(got != exp)
+    assert bad.size == 0, f"{what}: {len(bad)} of {exp.size} sampled residues differ, first {bad[:3].tolist()}"
+    return exp.size
+
+
+@pytest.mark.parametrize("form", ["plain", "i8", "rns", "p2"])
+def test_golden_sampled_results(run, golden, form):
+    forms = {"plain": H.HFE_FORM_PLAIN_U64, "i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8,
+             "p2": H.HFE_FORM_P2_I8}
+    Po = run["Po"]
+    n = Po.n_db
+    rows_full = list(golden["rows"])
+    # the shard's output rows: A rows as they are, codes in [row0, row0 + rows) shifted
+    row0, rows = SHARD
+    rows_shard = [r if r < n else (n + r - n - row0 if row0 <= r - n < row0 + rows else -1) for r in rows_full]
+    configs = [None]
+    if form == "i8":
+        configs = list(range(H.hfe_i8_variants()))
+    checked = 0
+    try:
+        for v in configs:
+            if v is not None:
+                H.hfe_set_i8_variant(v)
+            for (r0, nr), rows_out in (((0, W.d1), rows_full), (SHARD, rows_shard)):
+                tag = f"{form}" + (f" tile {H.hfe_i8_variant_name(v)}" if v is not None else "") + f" rows {r0}+{nr}"
+                _say(f"[gpu-scale] golden samples: {tag}")
+                r = H.hfe_ccmm(run["db"], run["qct"], r0, nr, forms[form])
+                res = H.hfe_export(r, 0).reshape(W.level, W.d3, n + nr).astype(np.int64)
+                checked += _check_golden(res, golden, rows_out, tag)
+    finally:
+        H.hfe_set_i8_variant(-1)
+    assert checked >= 4096
+
+
+_lift_p = {}
+
+
+def _lifted_query(run, XT, prime):
+    if prime not in _lift_p:
+        _lift_p[prime] = OC.lift_mod(run["Po"], {i: XT[i] for i in range(W.level)}, W.level, prime)
+    return _lift_p[prime]
+
+
+def _matmul_mod(A, B, prime, chunk=2048):
+    """(A @ B) mod prime for residue matrices (entries in [0, 2^36)), exactly: both operands are
+    split into 18-bit limbs and each limb product is summed by a float64 matrix product.  Every limb
+    product is an integer below 2^36 and every partial sum an integer below K 2^36 < 2^53, so each
+    addition is exact in float64 whatever the summation order; the limbs are recombined with Python
+    integers."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    K = A.shape[1]
+    assert B.shape[0] == K and K * (1 << 36) < (1 << 53)
+    assert A.min() >= 0 and B.min() >= 0 and A.max() < (1 << 36) and B.max() < (1 << 36)
+    m = (1 << 18) - 1
+    acc = [np.zeros((A.shape[0], B.shape[1])) for _ in range(3)]
+    for k0 in range(0, K, chunk):
+        a = A[:, k0:k0 + chunk]
+        b = B[k0:k0 + chunk]
+        a0, a1 = (a & m).astype(np.float64), (a >> 18).astype(np.float64)
+        b0, b1 = (b & m).astype(np.float64), (b >> 18).astype(np.float64)
+        acc[0] += a0 @ b0
+        acc[1] += a0 @ b1 + a1 @ b0
+        acc[2] += a1 @ b1
+    p0, p1, p2 = (x.astype(np.int64).astype(object) for x in acc)
+    return ((p0 + p1 * (1 << 18) + p2 * (1 << 36)) % prime).astype(np.int64)
+
+
+def test_freivalds_product_before_rescale_every_form(run):
+    """C r = D (X r) mod prime for every prime, every form, two random vectors r."""
+    Po = run["Po"]
+    R = Po.n_db + W.d1
+    K = Po.K
+    XT = H.hfe_export(run["qct"], 0).reshape(W.level, W.d3, K).astype(np.int64)
+    forms = {"plain": H.HFE_FORM_PLAIN_U64, "i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8,
+             "p2": H.HFE_FORM_P2_I8}
+    Cs = {}
+    for name, f in forms.items():
+        _say(f"[gpu-scale] product before rescale, form {name}")
+        Cs[name] = H.hfe_ccmm_product(run["db"], run["qct"], 0, W.d1, f).cpu().numpy()
+    run["C_i8"] = Cs["i8"]
+    rng = np.random.default_rng(99)
+    ids = OC.prime_ids(Po, W.level)
+    for z, (pid, prime) in enumerate(ids):
+        _say(f"[gpu-scale] Freivalds, prime slot {z}")
+        X = XT[z] if z < W.level else _lifted_query(run, XT, prime)           # d3 x K
+        rv = rng.integers(0, prime, (W.d3, 2), dtype=np.int64)
+        y = _matmul_mod(X.T, rv, prime)                                        # K x 2
+        Dt = H.hfe_export(run["db"], 0, z * K * R, K * R).astype(np.int64).reshape(K, R)
+        rhs = _matmul_mod(y.T, Dt, prime).T                                    # R x 2: (D y) = (y^T D^T)^T
+        del Dt
+        for name, C in Cs.items():
+            lhs = _matmul_mod(C[z].T, rv, prime)                               # R x 2
+            bad = np.argwhere(lhs != rhs)
+            assert bad.size == 0, f"{name} prime slot {z}: C r != D X r at {len(bad)} rows, first {bad[:3].tolist()}"
+
+
+def test_rescale_of_sampled_product_entries(run):
+    """RS_p by the oracle's big-integer CRT and rounding, on 20,000 sampled entries of the digit
+    form's product, equals the result residues."""
+    Po = run["Po"]
+    C = run.get("C_i8")
+    if C is None:
+        C = H.hfe_ccmm_product(run["db"], run["qct"], 0, W.d1, H.HFE_FORM_I8_MFMA).cpu().numpy()
+    res = H.hfe_export(run["r_i8"], 0).reshape(W.level, W.d3, -1).astype(np.int64)
+    ids = OC.prime_ids(Po, W.level)
+    moduli = [m for _, m in ids]
+    Q = Po.Q(W.level)
+    rng = np.random.default_rng(5)
+    cc = rng.integers(0, W.d3, 20000)
+    rr = rng.integers(0, C.shape[2], 20000)
+    for c, r in zip(cc.tolist(), rr.tolist()):
+        y = OC.rescale_p(OC.crt([int(C[z, c, r]) for z in range(len(ids))], moduli), Po.p, Q)
+        assert [y % qi for qi in moduli[:-1]] == [int(res[i, c, r]) for i in range(W.level)], (c, r)

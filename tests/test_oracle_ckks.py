@@ -164,3 +164,72 @@ def test_single_entry_functions_match_the_full_oracle():
     a = np.arange(P.n_q) * 7919 % 1000
     from oracle.ring import neg_matrix
     assert np.array_equal(OC.negmul_vec(s, a), neg_matrix(s) @ a)
+
+
+def test_block_functions_match_the_full_oracle():
+    """The row, column and grid evaluations used at large sizes (db_rows, query_columns, lift_mod,
+    ccmm_entries, s_q_columns) agree with the full-matrix oracle on the mid workload, whose secret
+    stacks have three chunks with a truncated last one; chunk sizes of the row evaluation are chosen
+    so that the chunks end inside and on the ring boundaries."""
+    c = case(S.MID.name)
+    P = c.P
+    SQ = OC.s_q_matrix(c.keys)
+    assert np.array_equal(OC.s_q_columns(c.keys, 0, P.n_q), SQ)
+    assert np.array_equal(OC.s_q_columns(c.keys, 100, 317), SQ[:, 100:317])
+    rows = [0, 1, P.n_db - 1, P.n_db, P.n_db + 1, P.n_db + 255, P.n_db + 256, P.n_db + c.w.d1 - 1]
+    for pid, prime in OC.prime_ids(P, len(P.q)):
+        for chunk in (100, 512):
+            assert np.array_equal(OC.db_rows(c.keys, c.m_db, DB_SEED, pid, prime, rows, chunk=chunk), c.D[pid][rows])
+    cols = [0, 5, c.w.d3 - 1, 130]
+    qc = OC.query_columns(c.keys, c.m_q[cols], cols, c.w.level, Q_SEED)
+    for i in range(c.w.level):
+        assert np.array_equal(qc[i], c.XT[i][cols])
+    L = OC.lift_query(P, {i: c.XT[i][cols] for i in range(c.w.level)}, c.w.level)
+    for _, prime in OC.prime_ids(P, c.w.level):
+        lm = OC.lift_mod(P, {i: c.XT[i][cols] for i in range(c.w.level)}, c.w.level, prime)
+        assert lm.tolist() == [[v % prime for v in col] for col in L]
+    out_rows = rows[:3] + [P.n_db + 17, P.n_db + 699]
+    d = {pid: c.D[pid][out_rows] for pid, _ in OC.prime_ids(P, c.w.level)}
+    e = OC.ccmm_entries(P, d, qc, c.w.level)
+    for i in range(c.w.level):
+        assert np.array_equal(e[i], c.out[i][np.ix_(cols, out_rows)])
+
+
+def test_uniform_columns_equal_the_oracle_philox():
+    """The bulk generator (numpy's Philox bit generator) gives the elements of uniform_matrix, on
+    columns 0 (whose counter wraps below zero) and beyond, with and without the rejection path."""
+    from oracle.params import ntt_primes
+    q = ntt_primes(1)[0]
+    for qq in (q, (1 << 63) + 25):
+        A = prng.uniform_matrix(11, prng.DBA, 3, 41, 9, qq)
+        for c0, c1 in ((0, 9), (4, 7)):
+            assert np.array_equal(prng.uniform_columns(11, prng.DBA, 3, 41, c0, c1, qq), A[:, c0:c1])
+
+
+def test_share_golden_samples_agree_with_the_single_entry_oracle():
+    """Entries of golden/share_samples.json (written by make_share_samples.py with the row, column and
+    grid functions) recomputed by the single-entry functions db_entry and ccmm_entry."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "share_samples.json")) as f:
+        g = json.load(f)
+    w = S.PAPER_SHARE
+    assert g["workload"] == w.name
+    P = params_for(w)
+    keys = OC.keygen(P, g["seeds"]["keys"])
+    inp = S.make_inputs(w)
+    m_db = OI.ternary(inp["db_codes"], inp["db_masks"])
+    ids = OC.prime_ids(P, len(P.q))
+    rows, kcols = g["rows"], g["db_cols"]
+    for z, a, b in ((0, 0, 0), (3, 31, 31), (1, 20, 5), (2, 17, 30), (3, 16, 12), (0, 24, 9)):
+        pid, prime = ids[z]
+        assert OC.db_entry(keys, m_db, g["seeds"]["db"], pid, prime, rows[a], kcols[b]) == g["db"][z][a][b]
+    qc, qm = OI.shifted_queries(inp["q_codes"], inp["q_masks"], inp["shifts"])
+    m_q = OI.ternary(qc, qm)
+    kk = np.arange(P.K)
+    for a, b in ((0, 0), (7, 63)):              # A-part rows: whole rows of uniform elements
+        r, col = rows[a], g["cols"][b]
+        xt = OC.query_column(keys, m_q[col], w.level, g["seeds"]["query"], col)
+        d_row = {pid: prng.uniform_mod(g["seeds"]["db"], prng.DBA, pid, np.full(P.K, r), kk, prime)
+                 for pid, prime in OC.prime_ids(P, w.level)}
+        assert OC.ccmm_entry(P, d_row, xt, w.level) == [g["result"][i][b][a] for i in range(w.level)]

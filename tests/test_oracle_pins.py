@@ -232,6 +232,35 @@ def test_decision_threshold_semantics():
     assert OI.decide(ip, ov).tolist() == [[False, True, False, False]]
 
 
+def test_match_per_eye_by_brute_force():
+    """match_per_eye: eye e matches iff some decision of its shift columns e * n_shifts + s (the
+    eye-major order of shifted_queries) against some database row is true; checked by loops over
+    eyes, shifts and rows, on random decisions and on single planted decisions at every position
+    (an eye-major / shift-major mix-up or a dropped row fails the single-decision cases)."""
+    rng = np.random.default_rng(4)
+    n_eyes, n_shifts, rows = 5, 3, 7
+
+    def brute(dec):
+        return np.array([any(dec[e * n_shifts + s, r] for s in range(n_shifts) for r in range(rows))
+                         for e in range(n_eyes)])
+
+    for _ in range(20):
+        dec = rng.random((n_eyes * n_shifts, rows)) < 0.03
+        assert np.array_equal(OI.match_per_eye(dec, n_shifts), brute(dec))
+    for col in range(n_eyes * n_shifts):
+        for r in range(rows):
+            dec = np.zeros((n_eyes * n_shifts, rows), dtype=bool)
+            dec[col, r] = True
+            want = np.zeros(n_eyes, dtype=bool)
+            want[col // n_shifts] = True
+            assert np.array_equal(OI.match_per_eye(dec, n_shifts), want)
+    qc = np.zeros((2, 8), dtype=np.uint8)
+    qm = np.ones((2, 8), dtype=np.uint8)
+    qc[1, 0] = 1                                            # eye 1 differs from eye 0 at bit 0
+    cols_c, _ = OI.shifted_queries(qc, qm, np.array([0, 1, 2]))
+    assert cols_c[3:].any() and not cols_c[:3].any()        # columns 3..5 are eye 1's shifts
+
+
 def test_shifted_queries_roll_code_and_mask_together():
     c = np.array([[1, 0, 0, 0, 0]], dtype=np.uint8)
     m = np.array([[1, 1, 0, 0, 0]], dtype=np.uint8)
