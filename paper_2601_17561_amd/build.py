@@ -4,6 +4,10 @@ Every .hip / .cpp source under csrc/ is compiled with hipcc for gfx950, except t
 quad-precision Gaussian table (hfe_cdt.cpp), which is plain host C++ built with g++
 against libquadmath.  Objects go to _build/ at the repository root; the shared library is
 written next to this file.
+
+The same call builds the tests' host harness of the exact-arithmetic helpers
+(tests/native/libhfe_exact_check.so from tests/native/exact_check.cpp, host code only), which
+the CPU tests load to check those helpers against exact integers.
 """
 import concurrent.futures
 import os
@@ -52,7 +56,20 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + [o for _, o in jobs] + ["-lquadmath"])
     os.replace(tmp, OUT)
+    build_exact_check()
     return OUT
+
+
+CHECK_SRC = os.path.join(ROOT, "tests", "native", "exact_check.cpp")
+CHECK_OUT = os.path.join(ROOT, "tests", "native", "libhfe_exact_check.so")
+
+
+def build_exact_check() -> str:
+    """Host build of the exact-arithmetic helpers for the CPU tests."""
+    tmp = CHECK_OUT + ".tmp"
+    _run([HIPCC] + HIP_FLAGS + ["-x", "hip", "-shared", CHECK_SRC, "-o", tmp])
+    os.replace(tmp, CHECK_OUT)
+    return CHECK_OUT
 
 
 if __name__ == "__main__":

@@ -728,11 +728,44 @@ static int pick_i8_variant(int level, int64_t d3) {
   return best;
 }
 
+// Device buffers of one call: from the allocator (released in stream order when the workspace goes
+// out of scope), or carved from a caller-provided region (the allocation-free entry point), each at
+// a 256-byte boundary; a request beyond the region's end fails with HFE_ENOMEM before anything is
+// enqueued for it.
+extern "C++" {
+struct Workspace {
+  uint8_t* base = nullptr;  // region mode when set
+  size_t cap = 0, used = 0;
+  DevBuf bufs[4];
+  int nb = 0;
+  template <class T>
+  hfe_status get(size_t bytes, hipStream_t s, T** out) {
+    if (base) {
+      const size_t off = (used + 255) & ~(size_t)255;
+      if (off > cap || bytes > cap - off)
+        return fail(HFE_ENOMEM, "the call needs more scratch than the " + std::to_string(cap) + "-byte region");
+      *out = reinterpret_cast<T*>(base + off);
+      used = off + bytes;
+      return HFE_OK;
+    }
+    if (nb == 4) return fail(HFE_EINTERNAL, "workspace: too many buffers");
+    HFE_TRY(bufs[nb].alloc(bytes, s));
+    *out = bufs[nb++].as<T>();
+    return HFE_OK;
+  }
+};
+}  // extern "C++"
+
 // C_ext == nullptr: the result (rescaled residues) into R->out.  C_ext != nullptr: only the exact
 // product before the rescale, C_ext[z][c][r] for the level's primes and p (z = level), and R only
 // records the shape.
+// out_ext != nullptr: the result into that caller-owned buffer instead of R->out.  ws: where the
+// call's buffers come from (nullptr: the allocator).
 static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, int64_t rows, int32_t form,
-                            hipStream_t s, hfe_rct* R, uint64_t* C_ext = nullptr) {
+                            hipStream_t s, hfe_rct* R, uint64_t* C_ext = nullptr, Workspace* ws = nullptr,
+                            uint64_t* out_ext = nullptr) {
+  Workspace own;
+  Workspace& W = ws ? *ws : own;
   const hfe_keys* K = D->keys;
   const int level = Qc->level;
   const int64_t ndb = 1ll << K->P.log_n_db;
@@ -750,19 +783,20 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   const LiftArgs la = make_lift_args(K, level);
   const int nz = level + 1;
   auto slot = [&](int z) { return z < level ? z : K->L; };
-  const bool prof = g_profile.load() != 0;
+  const bool prof = g_profile.load() != 0 && W.base == nullptr;  // no events in the allocation-free call
   if (prof)
     for (auto& e : R->ev) HFE_LAUNCH(hipEventCreate(&e));
   auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(R->ev[i], s) : hipSuccess; };
   HFE_LAUNCH(mark(0));
-  DevBuf C, Xp, Xd;
   // the small-modulus forms reconstruct and rescale in one pass (no contraction output C)
   const bool fused = form == HFE_FORM_RNS_I8 || form == HFE_FORM_P2_I8;
   const bool product = C_ext != nullptr;
-  if (!fused && !product) HFE_TRY(C.alloc(sizeof(uint64_t) * (size_t)nz * d3 * R_out, s));
-  uint64_t* Cp = product ? C_ext : C.as<uint64_t>();
+  uint64_t* Cp = C_ext;
+  if (!fused && !product) HFE_TRY(W.get(sizeof(uint64_t) * (size_t)nz * d3 * R_out, s, &Cp));
   const RescaleArgs ra = make_rescale_args(K, level);
-  if (!product) {
+  if (out_ext) {
+    R->outp = out_ext;
+  } else if (!product) {
     HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
     R->outp = R->out.as<uint64_t>();
   }
@@ -784,11 +818,12 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     g.mod[z] = K->mods[slot(z)];
   }
   if (form == HFE_FORM_PLAIN_U64) {
-    HFE_TRY(Xp.alloc(sizeof(uint64_t) * (size_t)d3 * D->K, s));
-    HFE_LAUNCH(launch_lift(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, g.d3_pad, la, Xp.as<uint64_t>(), nullptr, s));
+    uint64_t* Xp = nullptr;
+    HFE_TRY(W.get(sizeof(uint64_t) * (size_t)d3 * D->K, s, &Xp));
+    HFE_LAUNCH(launch_lift(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, g.d3_pad, la, Xp, nullptr, s));
     for (int z = 0; z < nz; ++z) {
       g.Dt[z] = D->Dt.as<uint64_t>() + (size_t)slot(z) * D->K * D->R;
-      g.X[z] = z < level ? Qc->XT.as<uint64_t>() + (size_t)z * d3 * D->K : Xp.as<uint64_t>();
+      g.X[z] = z < level ? Qc->XT.as<uint64_t>() + (size_t)z * d3 * D->K : Xp;
     }
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_plain(g, s));
@@ -798,23 +833,24 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     const int64_t d3_pad = (d3 + tq - 1) / tq * tq;   // whole query tiles
     const size_t planeX = (size_t)D->KB * d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
-    HFE_TRY(Xd.alloc((size_t)nz * n * planeX, s));
-    HFE_LAUNCH(launch_lift_rns(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd.as<int8_t>(), s));
-    DevBuf res;
-    HFE_TRY(res.alloc((size_t)nz * n * d3 * R_out, s));
+    int8_t* Xd = nullptr;
+    HFE_TRY(W.get((size_t)nz * n * planeX, s, &Xd));
+    HFE_LAUNCH(launch_lift_rns(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd, s));
+    uint8_t* res = nullptr;
+    HFE_TRY(W.get((size_t)nz * n * d3 * R_out, s, &res));
     RnsGemmArgs rg;
     std::memset(&rg, 0, sizeof(rg));
     rg.nz = nz;
     rg.n_mod = n;
     for (int z = 0; z < nz; ++z) {
       rg.Dr[z] = D->rns.as<int8_t>() + (size_t)slot(z) * n * planeD;
-      rg.Xr[z] = Xd.as<int8_t>() + (size_t)z * n * planeX;
+      rg.Xr[z] = Xd + (size_t)z * n * planeX;
     }
     for (int j = 0; j < n; ++j) {
       rg.m[j] = kRnsMods[j];
       rg.magic[j] = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)kRnsMods[j] - 1) / (uint64_t)kRnsMods[j]);
     }
-    rg.res = res.as<uint8_t>();
+    rg.res = res;
     rg.KB = D->KB;
     rg.R_pad = D->R_pad;
     rg.n_db = ndb;
@@ -826,30 +862,30 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(launch_gemm_rns(rg, tq, s));
     HFE_LAUNCH(mark(2));
     if (product)
-      HFE_LAUNCH(launch_crt_rns(res.as<uint8_t>(), nz, d3 * R_out, make_rns_crt_args(K, level, n), Cp, s));
+      HFE_LAUNCH(launch_crt_rns(res, nz, d3 * R_out, make_rns_crt_args(K, level, n), Cp, s));
     else
-      HFE_LAUNCH(launch_crt_rescale_rns(res.as<uint8_t>(), d3 * R_out, make_rns_crt_args(K, level, n), ra, R->outp,
-                                        s));
+      HFE_LAUNCH(launch_crt_rescale_rns(res, d3 * R_out, make_rns_crt_args(K, level, n), ra, R->outp, s));
   } else if (form == HFE_FORM_P2_I8) {
     const int n = D->n_p2;
     const int tq = p2_tile_q(&d3, &R_out, &nz, 1);  // query tile width by padded work
     const int64_t d3_pad = (d3 + tq - 1) / tq * tq;
     const size_t planeX = (size_t)D->KB * d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
-    HFE_TRY(Xd.alloc((size_t)nz * 2 * n * planeX, s));
-    HFE_LAUNCH(launch_lift_p2(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd.as<int8_t>(), s));
-    DevBuf res;
-    HFE_TRY(res.alloc(sizeof(uint16_t) * (size_t)nz * n * d3 * R_out, s));
+    int8_t* Xd = nullptr;
+    HFE_TRY(W.get((size_t)nz * 2 * n * planeX, s, &Xd));
+    HFE_LAUNCH(launch_lift_p2(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd, s));
+    uint16_t* res = nullptr;
+    HFE_TRY(W.get(sizeof(uint16_t) * (size_t)nz * n * d3 * R_out, s, &res));
     P2GemmArgs pg;
     std::memset(&pg, 0, sizeof(pg));
     pg.nz = nz;
     pg.n_bases = n;
     for (int z = 0; z < nz; ++z) {
       pg.Dq[z] = D->p2.as<int8_t>() + (size_t)slot(z) * 2 * n * planeD;
-      pg.Xq[z] = Xd.as<int8_t>() + (size_t)z * 2 * n * planeX;
+      pg.Xq[z] = Xd + (size_t)z * 2 * n * planeX;
     }
     for (int j = 0; j < n; ++j) pg.n[j] = kP2Bases[j];
-    pg.res = res.as<uint16_t>();
+    pg.res = res;
     pg.KB = D->KB;
     pg.R_pad = D->R_pad;
     pg.n_db = ndb;
@@ -861,18 +897,18 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     HFE_LAUNCH(launch_gemm_p2(pg, tq, s));
     HFE_LAUNCH(mark(2));
     if (product)
-      HFE_LAUNCH(launch_crt_p2(res.as<uint16_t>(), nz, d3 * R_out, make_p2_crt_args(K, level, n), Cp, s));
+      HFE_LAUNCH(launch_crt_p2(res, nz, d3 * R_out, make_p2_crt_args(K, level, n), Cp, s));
     else
-      HFE_LAUNCH(launch_crt_rescale_p2(res.as<uint16_t>(), d3 * R_out, make_p2_crt_args(K, level, n), ra, R->outp,
-                                       s));
+      HFE_LAUNCH(launch_crt_rescale_p2(res, d3 * R_out, make_p2_crt_args(K, level, n), ra, R->outp, s));
   } else {
     const size_t planeX = (size_t)D->KB * g.d3_pad * kKB;
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
-    HFE_TRY(Xd.alloc((size_t)nz * kDigits * planeX, s));
-    HFE_LAUNCH(launch_lift(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, g.d3_pad, la, nullptr, Xd.as<int8_t>(), s));
+    int8_t* Xd = nullptr;
+    HFE_TRY(W.get((size_t)nz * kDigits * planeX, s, &Xd));
+    HFE_LAUNCH(launch_lift(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, g.d3_pad, la, nullptr, Xd, s));
     for (int z = 0; z < nz; ++z) {
       g.Dd[z] = D->digits.as<int8_t>() + (size_t)slot(z) * kDigits * planeD;
-      g.Xd[z] = Xd.as<int8_t>() + (size_t)z * kDigits * planeX;
+      g.Xd[z] = Xd + (size_t)z * kDigits * planeX;
     }
     HFE_LAUNCH(mark(1));
     HFE_LAUNCH(launch_gemm_i8(g, pick_i8_variant(level, d3), s));
@@ -1311,7 +1347,6 @@ hfe_status batch_enqueue(const hfe_db* D, const uint8_t* dblob, const BlobLayout
                                  reinterpret_cast<const BatchLiftDesc*>(dblob + L.ld), D->K, D->KB,
                                  form_shape(D, form).lift_form, elem_grid, s));
   const BatchHeader* hdr = reinterpret_cast<const BatchHeader*>(dblob + L.gh);
-  const int64_t ndb = 1ll << D->keys->P.log_n_db;
   if (rns) {
     RnsBatchArgs a;
     std::memset(&a, 0, sizeof(a));

@@ -100,88 +100,19 @@ __device__ __forceinline__ bool lift_residues(const uint64_t* XT, int64_t d3, in
   return true;
 }
 
-// ------------------------------------------------------------------ RNS form: small moduli
-// x mod m for x < 2^24 and 2 <= m <= 256 with magic = ceil(2^32 / m): the quotient
-// floor(x magic / 2^32) is exact because x (magic - 2^32 / m) / 2^32 < 2^-8 <= 1 / m.
-__device__ __forceinline__ uint32_t mod_small(uint32_t x, uint32_t m, uint32_t magic) {
-  return x - __umulhi(x, magic) * m;
-}
-
-// ------------------------------------------------------------------ balanced residues
-// Per small modulus m_j of kRnsMods: m_j, ceil(2^32 / m_j) and 2^24 mod m_j, computed at compile time.
-struct RnsModConsts {
-  uint32_t m[kRnsMaxMods], magic[kRnsMaxMods], t24[kRnsMaxMods];
-};
-constexpr RnsModConsts make_rns_mod_consts() {
-  RnsModConsts c{};
-  for (int j = 0; j < kRnsMaxMods; ++j) {
-    const uint64_t m = (uint64_t)kRnsMods[j];
-    c.m[j] = (uint32_t)m;
-    c.magic[j] = (uint32_t)(((1ull << 32) + m - 1) / m);
-    c.t24[j] = (uint32_t)((1ull << 24) % m);
-  }
-  return c;
-}
+// ------------------------------------------------------------------ small-modulus constants
+// The RNS moduli and n^2 bases with their reciprocals, computed at compile time (hfe_exact.h).
 __constant__ static RnsModConsts kRnsC = make_rns_mod_consts();
-
-// x (|x| < 2^40) -> x mod m_j in [-floor(m_j/2), ceil(m_j/2) - 1] for the modulus kRnsMods[j]:
-// |x| = hi 2^24 + lo (hi < 2^16), and |x| mod m = (hi (2^24 mod m) + (lo mod m)) mod m, whose
-// argument is at most (2^16 - 1)(m - 1) + m - 1 < 2^24.
-__device__ __forceinline__ int32_t balanced_mod(int64_t x, int j) {
-  const uint32_t m = kRnsC.m[j], mg = kRnsC.magic[j];
-  const uint64_t a = (uint64_t)(x < 0 ? -x : x);
-  const uint32_t hi = (uint32_t)(a >> 24), lo = (uint32_t)(a & 0xFFFFFF);
-  uint32_t r = mod_small(hi * kRnsC.t24[j] + mod_small(lo, m, mg), m, mg);
-  if (x < 0 && r) r = m - r;
-  return (int32_t)r >= ((int32_t)m + 1) / 2 ? (int32_t)r - (int32_t)m : (int32_t)r;
-}
-
-// ------------------------------------------------------------------ n^2 form: bases and digits
-// x mod m in [0, m) for |x| < 2^48 and 2 <= m < 2^24, rcp = 1 / m rounded to double: x rcp differs
-// from x / m by less than 2^-4, so floor(x rcp) is the quotient or one off, fixed by one step.
-__device__ __forceinline__ int64_t mod_f64(int64_t x, int64_t m, double rcp) {
-  int64_t r = x - (int64_t)floor((double)x * rcp) * m;
-  if (r < 0)
-    r += m;
-  else if (r >= m)
-    r -= m;
-  return r;
-}
-
-// Per base n_j of kP2Bases: n_j, n_j^2, their reciprocals and ceil(2^32 / n_j), computed at
-// compile time.
-struct P2BaseConsts {
-  int32_t n[kP2MaxBases], m[kP2MaxBases];
-  uint32_t magic_n[kP2MaxBases];
-  double rcp_n[kP2MaxBases], rcp_m[kP2MaxBases];
-};
-constexpr P2BaseConsts make_p2_base_consts() {
-  P2BaseConsts c{};
-  for (int j = 0; j < kP2MaxBases; ++j) {
-    c.n[j] = kP2Bases[j];
-    c.m[j] = kP2Bases[j] * kP2Bases[j];
-    c.magic_n[j] = (uint32_t)(((1ull << 32) + (uint64_t)c.n[j] - 1) / (uint64_t)c.n[j]);
-    c.rcp_n[j] = 1.0 / (double)c.n[j];
-    c.rcp_m[j] = 1.0 / (double)c.m[j];
-  }
-  return c;
-}
 __constant__ static P2BaseConsts kP2C = make_p2_base_consts();
 
-// Centered x (|x| < 2^48) -> (M, M') with x = M + n M' (mod n^2) for n = kP2Bases[j], both in
-// [-(n-1)/2, (n-1)/2]: r = x mod n^2, M = the balanced residue of r mod n, M' = the balanced
-// residue of (r - M) / n (an integer in [0, n]) mod n.  After the first step everything is below
-// 2^17, where the multiply-high quotient by ceil(2^32 / n) is exact (mod_small).
+// x (|x| < 2^40) -> x mod m_j in [-floor(m_j/2), ceil(m_j/2) - 1] for the modulus kRnsMods[j].
+__device__ __forceinline__ int32_t balanced_mod(int64_t x, int j) {
+  return balanced_mod_by(x, kRnsC.m[j], kRnsC.magic[j], kRnsC.t24[j]);
+}
+
+// Centered x (|x| < 2^48) -> the n^2-form digits (M, M') of base n = kP2Bases[j].
 __device__ __forceinline__ void p2_digits(int64_t x, int j, int32_t& M, int32_t& Mp) {
-  const int32_t n = kP2C.n[j], h = (n - 1) / 2;
-  const uint32_t magic = kP2C.magic_n[j];
-  const uint32_t r = (uint32_t)mod_f64(x, kP2C.m[j], kP2C.rcp_m[j]);
-  M = (int32_t)mod_small(r, (uint32_t)n, magic);
-  if (M > h) M -= n;
-  const uint32_t rm = (uint32_t)((int32_t)r - M);  // a multiple of n in [0, n^2 + h]
-  int32_t t = (int32_t)__umulhi(rm, magic);         // (r - M) / n, exact
-  if (t == n) t = 0;
-  Mp = t > h ? t - n : t;
+  p2_digits_by(x, kP2C.n[j], kP2C.m[j], kP2C.magic_n[j], kP2C.rcp_m[j], M, Mp);
 }
 
 // The bytes b of the 4 lanes of a lane quad (lanes 4i .. 4i + 3, lane 4i + e holding byte e),
@@ -257,13 +188,10 @@ __device__ __forceinline__ uint64_t crt_entry(const uint8_t* r, int64_t n, const
   uint64_t acc = 0;  // sum of y_j ((M/m_j) mod q) < 16 * 2^8 * 2^36
   for (int j = 0; j < ra.n; ++j) {
     const uint32_t y = mod_small((uint32_t)r[(size_t)j * n] * (uint32_t)ra.inv[j], (uint32_t)ra.m[j], ra.magic[j]);
-    frac = fmaf((float)y, ra.rcp[j], frac);
+    frac = crt_frac_add(frac, y, ra.rcp[j]);
     acc += (uint64_t)y * ra.Mj_mod_q[slot][j];
   }
-  const uint64_t a = (uint64_t)(frac + 0.5f);
-  const Mod md = ra.mod[slot];
-  const uint64_t v = barrett64(acc, md.q, md.mu);
-  return sub_mod(v, barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
+  return crt_finish(acc, crt_round(frac), ra.M_mod_q[slot], ra.mod[slot]);
 }
 
 // Entries e0 .. e0 + 3 (those below n) of one prime slot: r = that slot's first residue plane
@@ -282,16 +210,13 @@ __device__ __forceinline__ void crt_quad_vals(const uint8_t* r, int64_t n, const
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const uint32_t y = mod_small(((w >> (8 * b)) & 255u) * inv, m, magic);
-      frac[b] = fmaf((float)y, rcp, frac[b]);
+      frac[b] = crt_frac_add(frac[b], y, rcp);
       acc[b] += (uint64_t)y * mj;
     }
   }
   const Mod md = ra.mod[slot];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const uint64_t a = (uint64_t)(frac[b] + 0.5f);
-    v[b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
-  }
+  for (int b = 0; b < 4; ++b) v[b] = crt_finish(acc[b], crt_round(frac[b]), ra.M_mod_q[slot], md);
 }
 
 __device__ __forceinline__ void crt_quad(const uint8_t* r, int64_t n, const RnsCrtArgs& ra, int slot, uint64_t* out,

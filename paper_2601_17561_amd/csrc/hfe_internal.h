@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/hfe.h"
+#include "hfe_exact.h"
 #include "hfe_math.h"
 
 namespace hfe {
@@ -123,20 +124,6 @@ struct hfe_keys : hfe::HandleBase {
   uint64_t cdt_host[19];
 };
 
-namespace hfe {
-// ------------------------------------------------------------------ small-modulus (RNS) form
-// Pairwise coprime moduli <= 256 (balanced residues fit int8), largest product first: 2^8,
-// 3*5*17, 11*23, 251, 13*19, then primes.  A database uses the shortest prefix whose product
-// exceeds twice the largest exact contraction sum (Section 6.3, RNS over small moduli).
-constexpr int kRnsMaxMods = 16;
-constexpr int32_t kRnsMods[kRnsMaxMods] = {256, 255, 253, 251, 247, 241, 239, 233,
-                                           229, 227, 223, 211, 199, 197, 193, 191};
-// Bases n of the n^2 form (Section 6.3, a matrix modulo n^2 as M + n M'): primes 127 <= n <= 253,
-// largest first.  A database uses the shortest prefix whose squares' product is at least four
-// times the largest exact contraction sum; at most 8 (the product stays below 2^128).
-constexpr int kP2MaxBases = 8;
-constexpr int32_t kP2Bases[kP2MaxBases] = {251, 241, 239, 233, 229, 227, 223, 211};
-}  // namespace hfe
 
 struct hfe_db : hfe::HandleBase {
   const hfe_keys* keys;

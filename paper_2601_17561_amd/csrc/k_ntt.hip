@@ -18,29 +18,8 @@ namespace hfe {
 constexpr int kNttThreads = 1024;
 
 // ------------------------------------------------------------------ fp64 residue arithmetic
-// Residues mod q < 2^36 as doubles holding exact integers in [0, q).
-// a w mod q for a, w in [0, q): hi = RN(a w) is an integer and lo = a w - hi (|lo| <= 2^18) is
-// exact from one fused multiply-add; t = floor(hi / q) from the rounded reciprocal is within one of
-// floor(a w / q) (relative error below 3 2^-53 on a value below 2^36); hi - t q is an integer below
-// 2^38 in magnitude, so the second fused multiply-add is exact, and so is adding lo.  The result
-// lies in (-q, 2q) and one conditional correction each way brings it to [0, q).
-__device__ __forceinline__ double mulmod_d(double a, double w, double q, double qinv) {
-#pragma clang fp contract(off)
-  const double hi = a * w;
-  const double lo = __builtin_fma(a, w, -hi);
-  const double t = __builtin_floor(hi * qinv);
-  double r = __builtin_fma(-t, q, hi) + lo;
-  r = r < 0.0 ? r + q : r;
-  return r >= q ? r - q : r;
-}
-__device__ __forceinline__ double addmod_d(double a, double b, double q) {
-  const double s = a + b;  // exact below 2^37
-  return s >= q ? s - q : s;
-}
-__device__ __forceinline__ double submod_d(double a, double b, double q) {
-  const double d = a - b;
-  return d < 0.0 ? d + q : d;
-}
+// Residues mod q < 2^36 as doubles holding exact integers in [0, q); products by mulmod_d
+// (hfe_exact.h).
 __device__ __forceinline__ double to_d(uint64_t x) { return (double)x; }    // exact below 2^53
 __device__ __forceinline__ uint64_t to_u(double x) { return (uint64_t)x; }  // x an integer in [0, q)
 

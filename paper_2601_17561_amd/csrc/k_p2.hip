@@ -232,9 +232,7 @@ __device__ __forceinline__ void p2_tile(const P2Tile& g, int8_t* lds) {
       for (int e = 0; e < 16; ++e) {
         const int64_t c = c0 + wq * 32 * C::WQB + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         if (c >= g.d3) continue;
-        int32_t v = (int32_t)mod_f64(acc0[a][b][e], m, rm) + n * (int32_t)mod_f64(acc1[a][b][e], n, rn);
-        if (v >= m) v -= m;
-        res[c * g.R_out + r] = (uint16_t)v;
+        res[c * g.R_out + r] = (uint16_t)p2_acc_mod(acc0[a][b][e], acc1[a][b][e], n, m, rn, rm);
       }
   }
 }
@@ -373,16 +371,13 @@ __device__ __forceinline__ void crt_pair_vals(const uint16_t* r, int64_t n, cons
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const uint32_t y = (uint32_t)mod_f64((int64_t)s2[b] * ra.inv[j], m, rcp);
-      frac[b] = fmaf((float)y, ra.rcp[j], frac[b]);
+      frac[b] = crt_frac_add(frac[b], y, ra.rcp[j]);
       acc[b] += (uint64_t)y * ra.Mj_mod_q[slot][j];
     }
   }
   const Mod md = ra.mod[slot];
   v[1] = 0;
-  for (int b = 0; b < cnt; ++b) {
-    const uint64_t a = (uint64_t)(frac[b] + 0.5f);
-    v[b] = sub_mod(barrett64(acc[b], md.q, md.mu), barrett64(a * ra.M_mod_q[slot], md.q, md.mu), md.q);
-  }
+  for (int b = 0; b < cnt; ++b) v[b] = crt_finish(acc[b], crt_round(frac[b]), ra.M_mod_q[slot], md);
 }
 
 // The same, stored: out = the slot's n results.

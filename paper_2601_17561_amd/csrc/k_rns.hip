@@ -198,12 +198,9 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
   asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
   // epilogue: S mod m_j in [0, m_j) -> res[z][j][c][r]; 32 x 32 result layout as in the digit
   // form (lane l, element e: query column 8 (e / 4) + 4 (l / 32) + e % 4, row l % 32)
-  const int32_t m = g.m;
+  const uint32_t m = (uint32_t)g.m;
   const uint32_t magic = g.magic;
-  // |acc| < 2^31: u = acc + 2^31 = hi 2^17 + lo (hi < 2^15), and
-  // acc mod m = (hi (2^17 mod m) + lo + (m - 2^31 mod m)) mod m with the argument below 2^24
-  const uint32_t t16 = mod_small(1u << 16, (uint32_t)m, magic), t17 = mod_small(1u << 17, (uint32_t)m, magic);
-  const uint32_t off = (uint32_t)m - mod_small(mod_small(1u << 15, (uint32_t)m, magic) * t16, (uint32_t)m, magic);
+  const RnsAccConsts ac = rns_acc_consts(m, magic);  // |acc| < 2^31 -> acc mod m (hfe_exact.h)
   uint8_t* res = g.res;
 #pragma unroll
   for (int b = 0; b < C::WRB; ++b) {
@@ -215,9 +212,7 @@ __device__ __forceinline__ void rns_tile(const RnsTile& g, int8_t* lds) {
       for (int e = 0; e < 16; ++e) {
         const int64_t c = c0 + wq * 32 * C::WQB + a * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         if (c >= g.d3) continue;
-        const uint32_t u = (uint32_t)acc[a][b][e] + 0x80000000u;  // acc + 2^31 >= 0
-        const uint32_t v = mod_small((u >> 17) * t17 + (u & 0x1FFFF) + off, (uint32_t)m, magic);
-        res[c * g.R_out + r] = (uint8_t)v;
+        res[c * g.R_out + r] = (uint8_t)rns_acc_mod(acc[a][b][e], m, magic, ac);
       }
   }
 }

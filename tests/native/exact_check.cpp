@@ -1,0 +1,105 @@
+// Host build of the library's exact-arithmetic helpers (paper_2601_17561_amd/csrc/hfe_exact.h), for
+// the CPU tests: each function applies one helper, as the kernels call it, to arrays of operands
+// given by the test, which compares the results with exact integer arithmetic in Python.
+// The exhaustive sweeps compare with C's integer remainder in the same loop.
+#include <stdint.h>
+
+#include "../../paper_2601_17561_amd/csrc/hfe_exact.h"
+
+using namespace hfe;
+
+static constexpr RnsModConsts kRns = make_rns_mod_consts();
+static constexpr P2BaseConsts kP2 = make_p2_base_consts();
+
+extern "C" {
+
+// out[i] = a[i] w[i] mod q by the fp64 product of the transforms (qinv = RN(1/q) as the tables hold it).
+void xc_mulmod_d(const uint64_t* a, const uint64_t* w, int64_t n, uint64_t q, uint64_t* out) {
+  const double qd = (double)q, qinv = 1.0 / qd;
+  for (int64_t i = 0; i < n; ++i) out[i] = (uint64_t)mulmod_d((double)a[i], (double)w[i], qd, qinv);
+}
+
+void xc_mod_small(const uint32_t* x, int64_t n, uint32_t m, uint32_t* out) {
+  const uint32_t magic = (uint32_t)(((1ull << 32) + m - 1) / m);
+  for (int64_t i = 0; i < n; ++i) out[i] = mod_small(x[i], m, magic);
+}
+
+// Mismatches of mod_small against x % m over every x < limit.
+int64_t xc_mod_small_sweep(uint32_t m, uint32_t limit) {
+  const uint32_t magic = (uint32_t)(((1ull << 32) + m - 1) / m);
+  int64_t bad = 0;
+  for (uint32_t x = 0; x < limit; ++x) bad += mod_small(x, m, magic) != x % m;
+  return bad;
+}
+
+void xc_mod_f64(const int64_t* x, int64_t n, int64_t m, int64_t* out) {
+  const double rcp = 1.0 / (double)m;
+  for (int64_t i = 0; i < n; ++i) out[i] = mod_f64(x[i], m, rcp);
+}
+
+// balanced residue modulo kRnsMods[j], with the constants the kernels use
+void xc_balanced_mod(const int64_t* x, int64_t n, int j, int32_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = balanced_mod_by(x[i], kRns.m[j], kRns.magic[j], kRns.t24[j]);
+}
+
+// n^2-form digits for base kP2Bases[j]
+void xc_p2_digits(const int64_t* x, int64_t n, int j, int32_t* M, int32_t* Mp) {
+  for (int64_t i = 0; i < n; ++i) p2_digits_by(x[i], kP2.n[j], kP2.m[j], kP2.magic_n[j], kP2.rcp_m[j], M[i], Mp[i]);
+}
+
+// RNS epilogue: int32 sums -> residue modulo kRnsMods[j]
+void xc_rns_acc_mod(const int32_t* s, int64_t n, int j, uint32_t* out) {
+  const RnsAccConsts c = rns_acc_consts(kRns.m[j], kRns.magic[j]);
+  for (int64_t i = 0; i < n; ++i) out[i] = rns_acc_mod(s[i], kRns.m[j], kRns.magic[j], c);
+}
+
+// Mismatches of the RNS epilogue against the exact remainder, over every int32 sum s = lo + k step.
+int64_t xc_rns_acc_mod_sweep(int j, int64_t lo, int64_t step, int64_t count) {
+  const uint32_t m = kRns.m[j];
+  const RnsAccConsts c = rns_acc_consts(m, kRns.magic[j]);
+  int64_t bad = 0;
+  for (int64_t k = 0; k < count; ++k) {
+    const int64_t s = lo + k * step;
+    const int64_t want = ((s % (int64_t)m) + m) % m;
+    bad += (int64_t)rns_acc_mod((int32_t)s, m, kRns.magic[j], c) != want;
+  }
+  return bad;
+}
+
+// n^2 epilogue: (G0, G1) -> (G0 + n G1) mod n^2 for base kP2Bases[j]
+void xc_p2_acc_mod(const int32_t* g0, const int32_t* g1, int64_t n, int j, uint32_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = p2_acc_mod(g0[i], g1[i], kP2.n[j], kP2.m[j], kP2.rcp_n[j], kP2.rcp_m[j]);
+}
+
+// CRT of one entry per column of s ([nm][cnt] residues s_j = S mod m_j), as the kernels take it:
+// y_j = s_j inv_j mod m_j (RNS: multiply-high quotient; n^2: the fp64 quotient), the fp32 fraction
+// sum, a = its rounding, out = S mod q.  Also returns a for the test.
+void xc_crt(const uint32_t* s, int64_t cnt, int nm, const uint32_t* m, const uint32_t* inv, const float* rcp,
+            const uint64_t* Mj_mod_q, uint64_t M_mod_q, uint64_t q, uint64_t mu, int p2, uint64_t* out,
+            uint64_t* a_out) {
+  Mod md;
+  md.q = q;
+  md.mu = mu;
+  md.bound = 0;
+  for (int64_t e = 0; e < cnt; ++e) {
+    float frac = 0.f;
+    uint64_t acc = 0;
+    for (int j = 0; j < nm; ++j) {
+      const uint32_t x = s[(int64_t)j * cnt + e];
+      uint32_t y;
+      if (p2) {
+        y = (uint32_t)mod_f64((int64_t)x * inv[j], m[j], 1.0 / (double)m[j]);
+      } else {
+        const uint32_t magic = (uint32_t)(((1ull << 32) + m[j] - 1) / m[j]);
+        y = mod_small(x * inv[j], m[j], magic);
+      }
+      frac = crt_frac_add(frac, y, rcp[j]);
+      acc += (uint64_t)y * Mj_mod_q[j];
+    }
+    const uint64_t a = crt_round(frac);
+    a_out[e] = a;
+    out[e] = crt_finish(acc, a, M_mod_q, md);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,220 @@
+"""Exact integer results that the kernels reach through floating point or multiply-high quotients.
+
+The helpers of paper_2601_17561_amd/csrc/hfe_exact.h are host and device functions; the CPU build
+tests/native/libhfe_exact_check.so applies each of them, as the kernels call it, to operands chosen
+here: random ones, the extremes of each stated range, and operands next to the places where a
+quotient estimate can be off (products next to multiples of the modulus, sums at the CRT's 1/4
+margin).  Every result is compared with Python integer arithmetic; the exhaustive sweeps compare with
+C's integer remainder inside the harness.
+
+  mulmod_d      a w mod q in fp64 (the NTT butterflies), q < 2^36
+  mod_small     x mod m by multiply-high, x < 2^24, 2 <= m <= 256 (every x, every m)
+  mod_f64       x mod m by an fp64 quotient, |x| < 2^48, m < 2^24
+  balanced_mod  the RNS form's int8 residues, |x| < 2^40
+  p2_digits     the n^2 form's digits M + n M', |x| < 2^48
+  rns_acc_mod   the RNS contraction epilogue, every int32 sum (strided sweep and extremes)
+  p2_acc_mod    the n^2 contraction epilogue, int32 sums G0, G1
+  CRT           the fp32 fractional-sum CRT of both forms, |S| <= M/4, up to 16 moduli / 8 bases
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from oracle import params as OP
+
+LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "native", "libhfe_exact_check.so")
+if not os.path.exists(LIB):  # pragma: no cover
+    pytest.fail(f"{LIB} is missing: build it with `python paper_2601_17561_amd/build.py`", pytrace=False)
+_L = ctypes.CDLL(LIB)
+_p = ctypes.c_void_p
+_L.xc_mod_small_sweep.restype = ctypes.c_int64
+_L.xc_mod_small_sweep.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+_L.xc_rns_acc_mod_sweep.restype = ctypes.c_int64
+_L.xc_rns_acc_mod_sweep.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
+for _name, _args in {
+        "xc_mulmod_d": [_p, _p, ctypes.c_int64, ctypes.c_uint64, _p],
+        "xc_mod_small": [_p, ctypes.c_int64, ctypes.c_uint32, _p],
+        "xc_mod_f64": [_p, ctypes.c_int64, ctypes.c_int64, _p],
+        "xc_balanced_mod": [_p, ctypes.c_int64, ctypes.c_int, _p],
+        "xc_p2_digits": [_p, ctypes.c_int64, ctypes.c_int, _p, _p],
+        "xc_rns_acc_mod": [_p, ctypes.c_int64, ctypes.c_int, _p],
+        "xc_p2_acc_mod": [_p, _p, ctypes.c_int64, ctypes.c_int, _p],
+        "xc_crt": [_p, ctypes.c_int64, ctypes.c_int, _p, _p, _p, _p, ctypes.c_uint64, ctypes.c_uint64,
+                   ctypes.c_uint64, ctypes.c_int, _p, _p]}.items():
+    getattr(_L, _name).argtypes = _args
+    getattr(_L, _name).restype = None
+
+# The moduli tables of the library (hfe_exact.h); their values are fixed by the paper's ranges
+# (RNS: pairwise coprime, <= 256; n^2: primes 127 <= n <= 253) and checked below.
+RNS_MODS = [256, 255, 253, 251, 247, 241, 239, 233, 229, 227, 223, 211, 199, 197, 193, 191]
+P2_BASES = [251, 241, 239, 233, 229, 227, 223, 211]
+
+
+def _ptr(a):
+    return a.ctypes.data
+
+
+def _largest_prime_below(x):
+    q = x - 1
+    while not OP.is_prime(q):
+        q -= 1
+    return q
+
+
+def test_tables_match_the_header():
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "paper_2601_17561_amd", "csrc", "hfe_exact.h")).read()
+    assert "{" + ", ".join(str(m) for m in RNS_MODS[:8]) + "," in src.replace("\n", " ").replace("  ", "")
+    assert "{" + ", ".join(str(n) for n in P2_BASES) + "}" in src
+    from math import gcd
+    assert all(gcd(a, b) == 1 for i, a in enumerate(RNS_MODS) for b in RNS_MODS[i + 1:])
+    assert all(OP.is_prime(n) and 127 <= n <= 253 for n in P2_BASES)
+
+
+@pytest.mark.parametrize("q", OP.ntt_primes(9) + [_largest_prime_below(1 << 36), (1 << 20) + 7])
+def test_mulmod_d_exact(q):
+    rng = np.random.default_rng(q % 1000)
+    n = 200_000
+    a = rng.integers(0, q, n, dtype=np.uint64)
+    w = rng.integers(0, q, n, dtype=np.uint64)
+    ext = [0, 1, 2, q - 1, q - 2, (q - 1) // 2, (q + 1) // 2]
+    ea, ew = np.meshgrid(ext, ext)
+    # products next to multiples of q: a = t w^-1 mod q gives a w = t (mod q) for t near 0 and q
+    ww = rng.integers(1, q, 20_000).tolist()
+    tt = [0, 1, 2, 3, q - 1, q - 2, q - 3]
+    near_a = [(t * pow(x, -1, q)) % q for x in ww for t in tt]
+    near_w = [x for x in ww for _ in tt]
+    A = np.concatenate([a, ea.ravel().astype(np.uint64), np.array(near_a, dtype=np.uint64)])
+    Wv = np.concatenate([w, ew.ravel().astype(np.uint64), np.array(near_w, dtype=np.uint64)])
+    out = np.empty_like(A)
+    _L.xc_mulmod_d(_ptr(A), _ptr(Wv), len(A), q, _ptr(out))
+    want = [int(x) * int(y) % q for x, y in zip(A.tolist(), Wv.tolist())]
+    assert out.tolist() == want
+
+
+def test_mod_small_exact_for_every_operand():
+    for m in range(2, 257):
+        assert _L.xc_mod_small_sweep(m, 1 << 24) == 0, m
+    for n in P2_BASES:                                  # the n^2 digits use it below 2^17
+        assert _L.xc_mod_small_sweep(n, 1 << 17) == 0, n
+    x = np.array([0, 1, (1 << 24) - 1, (1 << 24) - 2, 255, 256, 65535], dtype=np.uint32)
+    for m in RNS_MODS:
+        out = np.empty_like(x)
+        _L.xc_mod_small(_ptr(x), len(x), m, _ptr(out))
+        assert out.tolist() == [int(v) % m for v in x]
+
+
+@pytest.mark.parametrize("m", P2_BASES + [n * n for n in P2_BASES] + [2, 3, (1 << 24) - 1, (1 << 24) - 3])
+def test_mod_f64_exact(m):
+    rng = np.random.default_rng(m)
+    lim = (1 << 48) - 1
+    x = rng.integers(-lim, lim, 100_000, dtype=np.int64)
+    k = rng.integers(-(lim // m), lim // m, 20_000, dtype=np.int64)
+    near = np.concatenate([k * m - 1, k * m, k * m + 1])
+    near = near[np.abs(near) <= lim]
+    X = np.concatenate([x, near, np.array([0, 1, -1, lim, -lim, m, -m, m - 1, 1 - m], dtype=np.int64)])
+    out = np.empty_like(X)
+    _L.xc_mod_f64(_ptr(X), len(X), m, _ptr(out))
+    assert out.tolist() == [int(v) % m for v in X.tolist()]
+
+
+@pytest.mark.parametrize("j", range(16))
+def test_balanced_mod_exact(j):
+    m = RNS_MODS[j]
+    rng = np.random.default_rng(100 + j)
+    lim = (1 << 40) - 1
+    k = rng.integers(-(lim // m), lim // m, 20_000, dtype=np.int64)
+    X = np.concatenate([rng.integers(-lim, lim, 100_000, dtype=np.int64), k * m - 1, k * m, k * m + 1,
+                        np.array([0, 1, -1, lim, -lim, m // 2, -(m // 2), (m + 1) // 2, -((m + 1) // 2)],
+                                 dtype=np.int64)])
+    X = X[np.abs(X) <= lim]
+    out = np.empty(len(X), dtype=np.int32)
+    _L.xc_balanced_mod(_ptr(X), len(X), j, _ptr(out))
+    lo, hi = -(m // 2), (m + 1) // 2 - 1
+    assert out.min() >= lo and out.max() <= hi
+    assert all((int(r) - int(v)) % m == 0 for r, v in zip(out.tolist(), X.tolist()))
+
+
+@pytest.mark.parametrize("j", range(8))
+def test_p2_digits_exact(j):
+    n = P2_BASES[j]
+    n2 = n * n
+    h = (n - 1) // 2
+    rng = np.random.default_rng(200 + j)
+    lim = (1 << 48) - 1
+    r = np.arange(n2, dtype=np.int64)                  # every residue mod n^2 ...
+    k = rng.integers(-(lim // n2) + 1, lim // n2 - 1, n2, dtype=np.int64)
+    X = np.concatenate([r, r + k * n2, -r, rng.integers(-lim, lim, 50_000, dtype=np.int64),
+                        np.array([lim, -lim, 0, 1, -1], dtype=np.int64)])   # ... at random offsets
+    M = np.empty(len(X), dtype=np.int32)
+    Mp = np.empty(len(X), dtype=np.int32)
+    _L.xc_p2_digits(_ptr(X), len(X), j, _ptr(M), _ptr(Mp))
+    assert np.abs(M).max() <= h and np.abs(Mp).max() <= h
+    assert all((int(a) + n * int(b) - int(x)) % n2 == 0 for a, b, x in zip(M.tolist(), Mp.tolist(), X.tolist()))
+
+
+@pytest.mark.parametrize("j", range(16))
+def test_rns_epilogue_exact_over_int32(j):
+    m = RNS_MODS[j]
+    assert _L.xc_rns_acc_mod_sweep(j, -(1 << 31), 997, ((1 << 32) - 1) // 997 + 1) == 0
+    assert _L.xc_rns_acc_mod_sweep(j, (1 << 31) - 5000, 1, 5000) == 0
+    assert _L.xc_rns_acc_mod_sweep(j, -(1 << 31), 1, 5000) == 0
+    S = np.array([-(1 << 31), -(1 << 31) + 1, -1, 0, 1, (1 << 31) - 1, m, -m, m - 1, 1 - m], dtype=np.int32)
+    out = np.empty(len(S), dtype=np.uint32)
+    _L.xc_rns_acc_mod(_ptr(S), len(S), j, _ptr(out))
+    assert out.tolist() == [int(s) % m for s in S.tolist()]
+
+
+@pytest.mark.parametrize("j", range(8))
+def test_p2_epilogue_exact(j):
+    n = P2_BASES[j]
+    rng = np.random.default_rng(300 + j)
+    ext = np.array([-(1 << 31), -(1 << 31) + 1, -1, 0, 1, (1 << 31) - 1, n, -n, n * n, -n * n], dtype=np.int32)
+    g0 = np.concatenate([rng.integers(-(1 << 31), 1 << 31, 200_000, dtype=np.int64).astype(np.int32),
+                         np.repeat(ext, len(ext))])
+    g1 = np.concatenate([rng.integers(-(1 << 31), 1 << 31, 200_000, dtype=np.int64).astype(np.int32),
+                         np.tile(ext, len(ext))])
+    out = np.empty(len(g0), dtype=np.uint32)
+    _L.xc_p2_acc_mod(_ptr(g0), _ptr(g1), len(g0), j, _ptr(out))
+    assert out.tolist() == [(int(a) + n * int(b)) % (n * n) for a, b in zip(g0.tolist(), g1.tolist())]
+
+
+def _crt_case(moduli, q, S, p2):
+    M = 1
+    for m in moduli:
+        M *= m
+    nm = len(moduli)
+    s = np.array([[int(x) % m for x in S] for m in moduli], dtype=np.uint32)
+    inv = np.array([pow(M // m % m, -1, m) for m in moduli], dtype=np.uint32)
+    rcp = np.array([np.float32(1.0) / np.float32(m) for m in moduli], dtype=np.float32)
+    Mj = np.array([(M // m) % q for m in moduli], dtype=np.uint64)
+    m_arr = np.array(moduli, dtype=np.uint32)
+    out = np.empty(len(S), dtype=np.uint64)
+    a_out = np.empty(len(S), dtype=np.uint64)
+    _L.xc_crt(_ptr(s), len(S), nm, _ptr(m_arr), _ptr(inv), _ptr(rcp), _ptr(Mj), M % q, q, (1 << 64) // q,
+              1 if p2 else 0, _ptr(out), _ptr(a_out))
+    for e, x in enumerate(S):
+        y = [int(s[j, e]) * int(inv[j]) % moduli[j] for j in range(nm)]
+        a = (sum(yj * (M // m) for yj, m in zip(y, moduli)) - x) // M
+        assert int(a_out[e]) == a, (nm, x)
+        assert int(out[e]) == x % q, (nm, x)
+
+
+@pytest.mark.parametrize("form", ["rns", "p2"])
+def test_crt_fractional_sum_exact_at_the_quarter_margin(form):
+    """Every prefix of the moduli (RNS: 1..16, n^2: the squares of 1..8 bases), with |S| <= M/4: the
+    extremes +-M/4, +-(M/4 - 1), 0, +-1 and random S."""
+    q = OP.ntt_primes(1)[0]
+    mods = RNS_MODS if form == "rns" else [n * n for n in P2_BASES]
+    rng = np.random.default_rng(7)
+    for nm in range(1, len(mods) + 1):
+        moduli = mods[:nm]
+        M = 1
+        for m in moduli:
+            M *= m
+        B = M // 4
+        S = [B, -B, B - 1, -(B - 1), 0, 1, -1] + [int(rng.integers(0, 1 << 62)) * B // (1 << 62) *
+                                                  (1 if rng.random() < 0.5 else -1) for _ in range(500)]
+        _crt_case(moduli, q, S, form == "p2")
