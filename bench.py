@@ -234,8 +234,7 @@ def run_serving(args, H, torch):
             else:
                 tickets.append(H.hfe_server_submit(srv, pool[int(eyes[i])], outs[i]))
         log(f"serving: all {n} submitted after {time.perf_counter() - t0:.1f} s")
-        for t in tickets:
-            H.hfe_server_wait(srv, t, 600000)
+        H.hfe_server_drain(srv, 600000)
         dt = time.perf_counter() - t0
         st = H.hfe_server_stats(srv)
         srv.free()

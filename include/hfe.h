@@ -255,15 +255,24 @@ hfe_status hfe_autotune_load(const char* path);
  *   hfe_server_wait: blocks until the ticket is done (HFE_OK) or failed (its negative status),
  *     at most timeout_ms (< 0: no limit; then HFE_EBUSY, and hfe_server_poll tells a timeout,
  *     state 0 or 1, from a rejection).
+ *   hfe_server_drain: blocks until no request is queued and no step runs (HFE_OK), at most
+ *     timeout_ms (< 0: no limit; then HFE_EBUSY).  Every ticket submitted before the call has
+ *     then finished, including those already beyond the retention window below.
  *   hfe_server_stats: counts and latencies (arrival -> result ready; admission -> ready) of the
- *     requests completed since creation or the last reset.
+ *     requests completed since creation or the last reset: percentiles over the most recent
+ *     65,536 completions, the mean over all of them.  retained: request records the server
+ *     holds (queued, running, and the last 1,024 finished); max_busy_slots: the most slots
+ *     that held a step at once; overlap_pairs: pairs of steps on different slots whose device
+ *     intervals (timing events around each step on its stream) intersected.
  *   hfe_server_reset_stats: clears the statistics and forgets finished requests (their tickets
- *     become unknown); the server keeps every finished request until then. */
+ *     become unknown).  Without resets the server keeps the records of the last 1,024 finished
+ *     tickets (older ones become unknown to poll and wait), so its host memory stays bounded. */
 typedef struct hfe_server hfe_server;
 typedef struct {
   int64_t submitted, completed, rejected, steps, max_queue;
   double p50_ms, p99_ms, service_p50_ms, service_p99_ms, mean_ms;
   double req_per_s, cmp_per_s, mean_cols_per_step, elapsed_s;
+  int64_t retained, max_busy_slots, overlap_pairs;
 } hfe_server_report;
 hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_cols_per_step,
                              int32_t max_items_per_step, int32_t n_slots, uint32_t max_level, int32_t form,
@@ -272,6 +281,7 @@ hfe_status hfe_server_submit(hfe_server* srv, const hfe_qct* q, int32_t* ip_out,
 hfe_status hfe_server_submit_encrypted(hfe_server* srv, const hfe_qct* q, hfe_rct* result, uint64_t* ticket);
 hfe_status hfe_server_poll(hfe_server* srv, uint64_t ticket, int32_t* state);
 hfe_status hfe_server_wait(hfe_server* srv, uint64_t ticket, int64_t timeout_ms);
+hfe_status hfe_server_drain(hfe_server* srv, int64_t timeout_ms);
 hfe_status hfe_server_stats(hfe_server* srv, hfe_server_report* out);
 hfe_status hfe_server_reset_stats(hfe_server* srv);
 
@@ -316,6 +326,20 @@ hfe_status hfe_shape(const void* handle, int64_t* dims);
  * profiling. */
 hfe_status hfe_profile(int32_t enable);
 hfe_status hfe_profile_ms(const hfe_rct* r, float* ms, int32_t n);
+
+/* Rate probes: the instruction ceilings of the two contraction forms (Section 6.3's int8 matrix
+ * products and the plain 64-bit residue products), measured on the current device.
+ *   which = HFE_PROBE_MFMA_I8: int8 MFMA products (32 x 32 x 32) whose operands stream random
+ *     bits, as the digit planes of ciphertexts do; *rate = int8 operations per second (two per
+ *     multiply-add).
+ *   HFE_PROBE_MFMA_I8_ZERO: the same products on all-zero operands (the issue ceiling).
+ *   HFE_PROBE_VALU_MAD_U64: 32 x 32 -> 64-bit multiply-adds (v_mad_u64_u32) per second, lane
+ *     operations; the plain form spends four per residue multiply-add.
+ * iters >= 1: loop trips per wave of the timed launch (one untimed launch of iters / 8 + 1 trips
+ * runs first).  The call allocates a small sink buffer, synchronises `stream` and returns the
+ * rate of the timed launch (HIP events on `stream`).  HFE_EINVAL for another `which`. */
+enum { HFE_PROBE_MFMA_I8 = 1, HFE_PROBE_MFMA_I8_ZERO = 2, HFE_PROBE_VALU_MAD_U64 = 3 };
+hfe_status hfe_probe_rate(int32_t which, int64_t iters, void* stream, double* rate);
 
 /* Tile configurations of the int8-MFMA contraction kernel.  hfe_i8_variants() returns their
  * number (configuration 0 is the default); hfe_i8_variant_name(v) names one (NULL if v is out of

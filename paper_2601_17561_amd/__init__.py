@@ -28,6 +28,7 @@ HFE_FORM_PLAIN_U64 = 1
 HFE_FORM_I8_MFMA = 2
 HFE_FORM_RNS_I8 = 4
 HFE_FORM_P2_I8 = 8
+HFE_PROBE_MFMA_I8, HFE_PROBE_MFMA_I8_ZERO, HFE_PROBE_VALU_MAD_U64 = 1, 2, 3
 HFE_MAX_QPRIMES = 8
 
 STATUS_NAMES = {0: "HFE_OK", -1: "HFE_EINVAL", -2: "HFE_ESHAPE", -3: "HFE_ELEVEL", -4: "HFE_ENOMEM",
@@ -38,9 +39,9 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_last_error", "hfe_cdt_table", "hfe_profile", "hfe_profile_ms", "hfe_i8_variants",
             "hfe_i8_variant_name", "hfe_set_i8_variant", "hfe_ccmm_batched", "hfe_plan_create", "hfe_plan_run",
             "hfe_plan_result", "hfe_autotune", "hfe_autotune_save", "hfe_autotune_load", "hfe_server_create",
-            "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_stats", "hfe_server_reset_stats",
+            "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_drain", "hfe_server_stats", "hfe_server_reset_stats",
             "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes",
-            "hfe_ccmm_product")
+            "hfe_ccmm_product", "hfe_probe_rate")
 
 
 class HfeError(RuntimeError):
@@ -66,7 +67,8 @@ class hfe_batch_item(ctypes.Structure):
 class hfe_server_report(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected", "steps", "max_queue")] + \
                [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "service_p50_ms", "service_p99_ms", "mean_ms",
-                                               "req_per_s", "cmp_per_s", "mean_cols_per_step", "elapsed_s")]
+                                               "req_per_s", "cmp_per_s", "mean_cols_per_step", "elapsed_s")] + \
+               [(n, ctypes.c_int64) for n in ("retained", "max_busy_slots", "overlap_pairs")]
 
 
 if not os.path.exists(LIB_PATH):
@@ -107,6 +109,7 @@ _SIGS = {
     "hfe_cdt_table": [_vp],
     "hfe_profile": [_i32],
     "hfe_profile_ms": [_vp, _vp, _i32],
+    "hfe_probe_rate": [_i32, _i64, _vp, ctypes.POINTER(ctypes.c_double)],
     "hfe_set_i8_variant": [_i32],
     "hfe_ccmm_batched": [_vp, ctypes.POINTER(hfe_batch_item), _i32, _i32, _vp, ctypes.POINTER(_vp)],
     "hfe_plan_create": [_vp, _i32, _i64, _u32, _i32, ctypes.POINTER(_vp)],
@@ -119,6 +122,7 @@ _SIGS = {
     "hfe_server_submit": [_vp, _vp, _vp, ctypes.POINTER(_u64)],
     "hfe_server_poll": [_vp, _u64, ctypes.POINTER(_i32)],
     "hfe_server_wait": [_vp, _u64, _i64],
+    "hfe_server_drain": [_vp, _i64],
     "hfe_server_stats": [_vp, ctypes.POINTER(hfe_server_report)],
     "hfe_server_reset_stats": [_vp],
 }
@@ -384,6 +388,14 @@ def hfe_profile_ms(r: Handle, n: int = 3) -> list:
     return [float(out[i]) for i in range(n)]
 
 
+def hfe_probe_rate(which: int, iters: int, stream=None) -> float:
+    """Measured instruction rate of a probe (int8 ops/s for the MFMA probes, multiply-adds/s for
+    the VALU probe); synchronises the stream."""
+    out = ctypes.c_double()
+    _check(_lib.hfe_probe_rate(which, iters, _stream(stream), ctypes.byref(out)), "hfe_probe_rate")
+    return float(out.value)
+
+
 def hfe_i8_variants() -> int:
     return int(_lib.hfe_i8_variants())
 
@@ -461,6 +473,16 @@ class Server(Handle):
         super().__init__(ptr, parents)
         self._live = {}
 
+    def _keep(self, ticket: int, refs) -> None:
+        # the server forgets finished tickets beyond its retention window; drop the references of
+        # every ticket it no longer runs, so that a long-lived server does not grow this table
+        self._live[ticket] = refs
+        if len(self._live) > 4096:
+            st = _i32()
+            for tk in list(self._live):
+                if _lib.hfe_server_poll(self.ptr, tk, ctypes.byref(st)) != 0 or st.value == 2 or st.value < 0:
+                    del self._live[tk]
+
 
 def hfe_server_create(db: Handle, mem_budget: int, max_cols_per_step: int, max_items_per_step: int = 64,
                       n_slots: int = 2, max_level: int = 1, form: int = HFE_FORM_I8_MFMA) -> Server:
@@ -475,7 +497,7 @@ def hfe_server_submit(srv: Server, q: Handle, ip_out) -> int:
     torch = _torch()
     t = _u64()
     _check(_lib.hfe_server_submit(srv.ptr, q.ptr, _dev_ptr(ip_out, torch.int32), ctypes.byref(t)), "hfe_server_submit")
-    srv._live[int(t.value)] = (q, ip_out)
+    srv._keep(int(t.value), (q, ip_out))
     return int(t.value)
 
 
@@ -491,7 +513,7 @@ def hfe_server_submit_encrypted(srv: Server, q: Handle, result: Handle) -> int:
     t = _u64()
     _check(_lib.hfe_server_submit_encrypted(srv.ptr, q.ptr, result.ptr, ctypes.byref(t)),
            "hfe_server_submit_encrypted")
-    srv._live[int(t.value)] = (q, result)
+    srv._keep(int(t.value), (q, result))
     return int(t.value)
 
 
@@ -510,6 +532,12 @@ def hfe_server_wait(srv: Server, ticket: int, timeout_ms: int = -1) -> None:
         st = _i32()
         if _lib.hfe_server_poll(srv.ptr, ticket, ctypes.byref(st)) == 0 and (st.value == 2 or st.value < 0):
             srv._live.pop(ticket, None)
+
+
+def hfe_server_drain(srv: Server, timeout_ms: int = -1) -> None:
+    """Block until nothing is queued or running on the server."""
+    _check(_lib.hfe_server_drain(srv.ptr, timeout_ms), "hfe_server_drain")
+    srv._live.clear()
 
 
 def hfe_server_stats(srv: Server) -> dict:

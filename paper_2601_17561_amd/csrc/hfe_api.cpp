@@ -756,6 +756,8 @@ struct Workspace {
 };
 }  // extern "C++"
 
+// Every buffer of the call is obtained before its first launch, so a workspace that cannot supply
+// one fails the call with nothing enqueued.
 // C_ext == nullptr: the result (rescaled residues) into R->out.  C_ext != nullptr: only the exact
 // product before the rescale, C_ext[z][c][r] for the level's primes and p (z = level), and R only
 // records the shape.
@@ -835,9 +837,9 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
     int8_t* Xd = nullptr;
     HFE_TRY(W.get((size_t)nz * n * planeX, s, &Xd));
-    HFE_LAUNCH(launch_lift_rns(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd, s));
     uint8_t* res = nullptr;
     HFE_TRY(W.get((size_t)nz * n * d3 * R_out, s, &res));
+    HFE_LAUNCH(launch_lift_rns(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd, s));
     RnsGemmArgs rg;
     std::memset(&rg, 0, sizeof(rg));
     rg.nz = nz;
@@ -873,9 +875,9 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
     const size_t planeD = (size_t)D->KB * D->R_pad * kKB;
     int8_t* Xd = nullptr;
     HFE_TRY(W.get((size_t)nz * 2 * n * planeX, s, &Xd));
-    HFE_LAUNCH(launch_lift_p2(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd, s));
     uint16_t* res = nullptr;
     HFE_TRY(W.get(sizeof(uint16_t) * (size_t)nz * n * d3 * R_out, s, &res));
+    HFE_LAUNCH(launch_lift_p2(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, n, Xd, s));
     P2GemmArgs pg;
     std::memset(&pg, 0, sizeof(pg));
     pg.nz = nz;
@@ -1698,6 +1700,39 @@ hfe_status hfe_autotune(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_
     g_tuned[{Qc->level, d3_bucket(Qc->d3)}] = best_v;
   }
   *best = best_v;
+  return HFE_OK;
+}
+
+hfe_status hfe_probe_rate(int32_t which, int64_t iters, void* stream, double* rate) {
+  if (!rate) return fail(HFE_EINVAL, "rate is NULL");
+  *rate = 0;
+  if (which < HFE_PROBE_MFMA_I8 || which > HFE_PROBE_VALU_MAD_U64) return fail(HFE_EINVAL, "unknown probe");
+  if (iters < 1) return fail(HFE_EINVAL, "iters must be positive");
+  hipStream_t s = (hipStream_t)stream;
+  const bool valu = which == HFE_PROBE_VALU_MAD_U64;
+  const int grid = device_cus() * (valu ? 8 : 4);
+  DevBuf sink;
+  HFE_TRY(sink.alloc((size_t)grid * 256 * 8, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hfe_status st = HFE_OK;
+  float ms = 0;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(HFE_EDEVICE, "event creation failed");
+  if (st == HFE_OK) {
+    hipError_t e = launch_probe(which, iters / 8 + 1, grid, sink.ptr, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_probe(which, iters, grid, sink.ptr, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) st = hip_fail(e, "rate probe");
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != HFE_OK) return st;
+  // MFMA: 4 waves per workgroup, 128 products of 32 x 32 x 32 per trip, 2 operations per
+  // multiply-add; VALU: 64 multiply-adds per lane per trip
+  const double ops = valu ? (double)grid * 256 * iters * 64 : (double)grid * 4 * iters * 128 * 32768.0 * 2;
+  *rate = ms > 0 ? ops / (ms * 1e-3) : 0.0;
   return HFE_OK;
 }
 

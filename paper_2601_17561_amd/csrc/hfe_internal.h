@@ -358,6 +358,9 @@ struct GemmArgs {
   int64_t K, KB, R_db, R_pad, n_db, row0, rows, R_out, d3, d3_pad;
 };
 hipError_t launch_gemm_plain(const GemmArgs& g, hipStream_t s);
+// rate probes (k_probe.hip): which 1 = int8 MFMA on streaming random operands, 2 = on zero
+// operands, 3 = v_mad_u64_u32; grid workgroups of 256 threads, sink >= grid * 256 * 8 bytes
+hipError_t launch_probe(int which, int64_t iters, int grid, void* sink, hipStream_t s);
 hipError_t launch_gemm_i8(const GemmArgs& g, int variant, hipStream_t s);
 constexpr int kMaxI8Variants = 16;  // upper bound of i8_variant_count()
 int i8_variant_count();

@@ -2,6 +2,14 @@
 // CCMM + per-request decryption) on a ring of preallocated slots, each with its own stream,
 // workspace (an hfe_plan) and decryption scratch.  Completion is signalled by a host function
 // enqueued behind each step, which timestamps the requests and frees the slot.
+//
+// Host state stays bounded for a server that runs indefinitely: finished request records are
+// kept for the last kRetainFinished finished tickets only, and latency samples for the last
+// kLatWindow completions (percentiles are taken over that window, the mean over every completion
+// since the last reset).  Each step is bracketed by timing events on its slot's stream; when a
+// slot is reused (or the statistics are read) the step's device interval is compared with the
+// intervals of the other slots' steps, which counts the pairs of steps that ran on the device at
+// the same time.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -42,9 +50,38 @@ struct StepDone {
 struct Slot {
   hfe_plan* plan = nullptr;
   hipStream_t stream = nullptr;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;  // device interval of the slot's last step
+  bool timed = false;                               // both events recorded, interval not yet read
   DevBuf y;
   bool busy = false;
   StepDone done;
+};
+
+constexpr size_t kRetainFinished = 1024;  // finished request records kept for poll / wait
+constexpr size_t kLatWindow = 65536;      // latency samples kept for the percentiles
+constexpr size_t kIntervals = 64;         // device intervals of recent steps kept for overlap
+
+// Fixed-capacity ring of the most recent samples.
+struct Window {
+  std::vector<double> v;
+  size_t next = 0;
+  void push(double x) {
+    if (v.size() < kLatWindow) {
+      v.push_back(x);
+    } else {
+      v[next] = x;
+      next = (next + 1) % kLatWindow;
+    }
+  }
+  void clear() {
+    v.clear();
+    next = 0;
+  }
+};
+
+struct Interval {
+  int slot;
+  float t0, t1;  // ms after the server's reference event
 };
 
 double pct(std::vector<double> v, double p) {
@@ -66,15 +103,22 @@ struct hfe_server : hfe::HandleBase {
   std::condition_variable cv;
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, hfe::Request> reqs;
+  std::deque<uint64_t> finished;  // tickets in the order they finished (done or failed)
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread worker;
+  hipEvent_t ev_ref = nullptr;  // recorded once at creation: origin of the device intervals
+  std::deque<hfe::Interval> intervals;
   // statistics since creation / reset
-  std::vector<double> lat, svc;
+  hfe::Window lat, svc;
+  double lat_sum = 0;
   int64_t submitted = 0, completed = 0, rejected = 0, steps = 0, max_queue = 0, cols_steps = 0;
+  int64_t busy_now = 0, max_busy = 0, overlap_pairs = 0;
   double t_first = -1, t_last = 0, cmp = 0;
 
   void finish_step(int si);
+  void retire(uint64_t tk);       // caller holds mu
+  void read_interval(int si);     // caller holds mu
   void run();
 };
 
@@ -83,6 +127,31 @@ using namespace hfe;
 static void on_step_done(void* p) {
   StepDone* d = static_cast<StepDone*>(p);
   d->srv->finish_step(d->slot);
+}
+
+void hfe_server::retire(uint64_t tk) {
+  finished.push_back(tk);
+  while (finished.size() > kRetainFinished) {
+    auto it = reqs.find(finished.front());
+    if (it != reqs.end() && (it->second.state == 2 || it->second.state < 0)) reqs.erase(it);
+    finished.pop_front();
+  }
+}
+
+void hfe_server::read_interval(int si) {
+  Slot& sl = *slots[si];
+  if (!sl.timed || sl.busy) return;
+  sl.timed = false;
+  float t0 = 0, t1 = 0;
+  if (hipEventElapsedTime(&t0, ev_ref, sl.ev_begin) != hipSuccess ||
+      hipEventElapsedTime(&t1, ev_ref, sl.ev_end) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  for (const Interval& o : intervals)
+    if (o.slot != si && o.t0 < t1 && t0 < o.t1) ++overlap_pairs;
+  intervals.push_back({si, t0, t1});
+  if (intervals.size() > kIntervals) intervals.pop_front();
 }
 
 void hfe_server::finish_step(int si) {
@@ -95,13 +164,17 @@ void hfe_server::finish_step(int si) {
     Request& r = it->second;
     r.state = 2;
     r.t_done = t;
-    lat.push_back((t - r.t_submit) * 1e3);
-    svc.push_back((t - r.t_admit) * 1e3);
+    const double ms = (t - r.t_submit) * 1e3;
+    lat.push(ms);
+    lat_sum += ms;
+    svc.push((t - r.t_admit) * 1e3);
     ++completed;
     cmp += (double)r.d3 * db->d1;
     t_last = t;
+    retire(tk);
   }
   sl.busy = false;
+  --busy_now;
   cv.notify_all();
 }
 
@@ -127,7 +200,10 @@ void hfe_server::run() {
             if (s->busy) return false;
           return true;
         });
-        for (uint64_t tk : queue) reqs[tk].state = HFE_EBUSY;
+        for (uint64_t tk : queue) {
+          reqs[tk].state = HFE_EBUSY;
+          retire(tk);
+        }
         queue.clear();
         return;
       }
@@ -145,6 +221,7 @@ void hfe_server::run() {
           r.state = HFE_EBUSY;
           r.t_done = t;
           ++rejected;
+          retire(queue.front());
           queue.pop_front();
           continue;
         }
@@ -157,11 +234,14 @@ void hfe_server::run() {
         queue.pop_front();
       }
       if (items.empty()) continue;
+      read_interval(si);
       slots[si]->busy = true;
+      max_busy = std::max(max_busy, ++busy_now);
       ++steps;
       cols_steps += cols;
     }
     Slot& sl = *slots[si];
+    const bool timed = hipEventRecord(sl.ev_begin, sl.stream) == hipSuccess;
     hfe_status st = hfe_plan_run(sl.plan, items.data(), (int32_t)items.size(), 1, sl.stream);
     size_t off = 0;
     for (size_t i = 0; st == HFE_OK && i < items.size(); ++i) {
@@ -187,12 +267,21 @@ void hfe_server::run() {
     sl.done.srv = this;
     sl.done.slot = si;
     sl.done.tickets = tickets;
+    if (st == HFE_OK && timed && hipEventRecord(sl.ev_end, sl.stream) == hipSuccess) {
+      std::lock_guard<std::mutex> l(mu);
+      sl.timed = true;  // read once the step is done and the slot is free
+    }
     hipError_t e = hipSuccess;
     if (st == HFE_OK) e = hipLaunchHostFunc(sl.stream, on_step_done, &sl.done);
     if (st != HFE_OK || e != hipSuccess) {
       std::lock_guard<std::mutex> l(mu);
-      for (uint64_t tk : tickets) reqs[tk].state = st != HFE_OK ? st : HFE_EDEVICE;
+      for (uint64_t tk : tickets) {
+        reqs[tk].state = st != HFE_OK ? st : HFE_EDEVICE;
+        retire(tk);
+      }
+      sl.timed = false;
       sl.busy = false;
+      --busy_now;
       cv.notify_all();
     }
   }
@@ -211,8 +300,11 @@ void destroy_server(void* handle) {
     if (sl->stream) (void)hipStreamSynchronize(sl->stream);
     hfe_free(sl->plan);
     sl->y.reset();
+    if (sl->ev_begin) (void)hipEventDestroy(sl->ev_begin);
+    if (sl->ev_end) (void)hipEventDestroy(sl->ev_end);
     if (sl->stream) (void)hipStreamDestroy(sl->stream);
   }
+  if (S->ev_ref) (void)hipEventDestroy(S->ev_ref);
   S->kind = 0;
   delete S;
 }
@@ -262,11 +354,18 @@ hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_co
     if (st == HFE_OK) st = sl->y.alloc(sizeof(uint64_t) * (size_t)max_level * cols * db->d1, nullptr);
     if (st == HFE_OK && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) != hipSuccess)
       st = fail(HFE_EDEVICE, "stream creation failed");
+    if (st == HFE_OK && (hipEventCreate(&sl->ev_begin) != hipSuccess || hipEventCreate(&sl->ev_end) != hipSuccess))
+      st = fail(HFE_EDEVICE, "event creation failed");
     S->slots.push_back(std::move(sl));
     if (st != HFE_OK) {
       destroy_server(S);
       return st;
     }
+  }
+  if (hipEventCreate(&S->ev_ref) != hipSuccess || hipEventRecord(S->ev_ref, S->slots[0]->stream) != hipSuccess ||
+      hipEventSynchronize(S->ev_ref) != hipSuccess) {
+    destroy_server(S);
+    return fail(HFE_EDEVICE, "reference event failed");
   }
   S->worker = std::thread([S] { S->run(); });
   *out = S;
@@ -363,27 +462,52 @@ hfe_status hfe_server_wait(hfe_server* srv, uint64_t ticket, int64_t timeout_ms)
   return HFE_OK;
 }
 
+hfe_status hfe_server_drain(hfe_server* srv, int64_t timeout_ms) {
+  hfe_server* S = as_server(srv);
+  if (!S) return fail(HFE_EINVAL, "invalid server");
+  std::unique_lock<std::mutex> l(S->mu);
+  auto idle = [&] {
+    if (!S->queue.empty()) return false;
+    for (auto& s : S->slots)
+      if (s->busy) return false;
+    return true;
+  };
+  if (timeout_ms < 0)
+    S->cv.wait(l, idle);
+  else if (!S->cv.wait_for(l, std::chrono::milliseconds(timeout_ms), idle))
+    return fail(HFE_EBUSY, "timed out");
+  return HFE_OK;
+}
+
 hfe_status hfe_server_stats(hfe_server* srv, hfe_server_report* out) {
   hfe_server* S = as_server(srv);
   if (!S || !out) return fail(HFE_EINVAL, "invalid server or out");
-  std::lock_guard<std::mutex> l(S->mu);
   std::memset(out, 0, sizeof(*out));
-  out->submitted = S->submitted;
-  out->completed = S->completed;
-  out->rejected = S->rejected;
-  out->steps = S->steps;
-  out->max_queue = S->max_queue;
-  out->p50_ms = pct(S->lat, 0.50);
-  out->p99_ms = pct(S->lat, 0.99);
-  out->service_p50_ms = pct(S->svc, 0.50);
-  out->service_p99_ms = pct(S->svc, 0.99);
-  double sum = 0;
-  for (double x : S->lat) sum += x;
-  out->mean_ms = S->lat.empty() ? 0.0 : sum / S->lat.size();
-  out->elapsed_s = S->t_first < 0 ? 0.0 : S->t_last - S->t_first;
-  out->req_per_s = out->elapsed_s > 0 ? S->completed / out->elapsed_s : 0.0;
-  out->cmp_per_s = out->elapsed_s > 0 ? S->cmp / out->elapsed_s : 0.0;
-  out->mean_cols_per_step = S->steps ? (double)S->cols_steps / S->steps : 0.0;
+  std::vector<double> lat, svc;
+  {
+    // copies under the lock, sorting outside it: the completion callbacks take the same lock
+    std::lock_guard<std::mutex> l(S->mu);
+    for (size_t i = 0; i < S->slots.size(); ++i) S->read_interval((int)i);
+    lat = S->lat.v;
+    svc = S->svc.v;
+    out->submitted = S->submitted;
+    out->completed = S->completed;
+    out->rejected = S->rejected;
+    out->steps = S->steps;
+    out->max_queue = S->max_queue;
+    out->mean_ms = S->completed ? S->lat_sum / S->completed : 0.0;
+    out->elapsed_s = S->t_first < 0 ? 0.0 : S->t_last - S->t_first;
+    out->req_per_s = out->elapsed_s > 0 ? S->completed / out->elapsed_s : 0.0;
+    out->cmp_per_s = out->elapsed_s > 0 ? S->cmp / out->elapsed_s : 0.0;
+    out->mean_cols_per_step = S->steps ? (double)S->cols_steps / S->steps : 0.0;
+    out->retained = (int64_t)S->reqs.size();
+    out->max_busy_slots = S->max_busy;
+    out->overlap_pairs = S->overlap_pairs;
+  }
+  out->p50_ms = pct(lat, 0.50);
+  out->p99_ms = pct(lat, 0.99);
+  out->service_p50_ms = pct(svc, 0.50);
+  out->service_p99_ms = pct(std::move(svc), 0.99);
   return HFE_OK;
 }
 
@@ -393,7 +517,11 @@ hfe_status hfe_server_reset_stats(hfe_server* srv) {
   std::lock_guard<std::mutex> l(S->mu);
   S->lat.clear();
   S->svc.clear();
+  S->lat_sum = 0;
   S->submitted = S->completed = S->rejected = S->steps = S->max_queue = S->cols_steps = 0;
+  S->max_busy = S->busy_now;
+  S->overlap_pairs = 0;
+  S->intervals.clear();
   S->t_first = -1;
   S->t_last = 0;
   S->cmp = 0;
@@ -403,6 +531,7 @@ hfe_status hfe_server_reset_stats(hfe_server* srv) {
     else
       ++it;
   }
+  S->finished.clear();
   return HFE_OK;
 }
 

@@ -141,3 +141,29 @@ def test_small_budget_queues_and_oversized_request_is_rejected(env):
     assert e.value.status == -6
     assert H.hfe_server_stats(srv)["rejected"] == 1
     srv.free()
+
+
+def test_long_burst_keeps_server_state_bounded_and_overlaps_steps(env):
+    """A burst of 1,500 one-column requests: every result equals the plaintext product, the server
+    holds at most its retention window of finished request records afterwards (older tickets are
+    unknown), both slots held steps at once, and steps of the two slots overlapped on the device."""
+    _say("[gpu-serving] server (rns): long burst of one-column requests")
+    srv = H.hfe_server_create(env["db"], 2 << 30, 64, 8, 2, 2, H.HFE_FORM_RNS_I8)
+    q, mq, exact = env["reqs"][0]
+    assert mq.shape[0] == 1
+    n, d1 = 1500, env["c"].w.d1
+    out = torch.full((n, d1), -7, dtype=torch.int32, device=env["dev"])
+    tickets = [H.hfe_server_submit(srv, q, out[i:i + 1]) for i in range(n)]
+    H.hfe_server_drain(srv, 120000)
+    st = H.hfe_server_stats(srv)
+    _say(f"[gpu-serving] long burst: steps {st['steps']} retained {st['retained']} "
+         f"max busy slots {st['max_busy_slots']} overlapping step pairs {st['overlap_pairs']}")
+    assert np.array_equal(out.cpu().numpy(), np.broadcast_to(exact, (n, d1)))
+    assert st["completed"] == n and st["retained"] <= 1024
+    with pytest.raises(H.HfeError) as e:                            # forgotten: beyond the window
+        H.hfe_server_poll(srv, tickets[0])
+    assert e.value.status == -1
+    assert H.hfe_server_poll(srv, tickets[-1]) == 2                 # within the window
+    assert st["max_busy_slots"] == 2
+    assert st["overlap_pairs"] >= 1
+    srv.free()
