@@ -175,6 +175,28 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
 hfe_status hfe_ccmm_product(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
                             void* stream, uint64_t* C);
 
+/* Allocation-free CCMM, for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same lift, contraction and
+ * rescale as hfe_ccmm, in any form, with the same results, but the call's device buffers (query
+ * planes, the contraction output or the small-modulus residues) come from a static device array
+ * of HFE_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the process
+ * ends, and the result goes to caller memory.  No hipMalloc, hipFree or allocator call is made.
+ *   out: device, level x d3 x (N_DB + rows) uint64 (caller-owned), receives the rescaled residues
+ *        in the order of hfe_export(rct, 0): [prime < level][column][A_out (N_DB) | B_out (rows)].
+ * Errors: those of hfe_ccmm; out NULL: HFE_EINVAL; a call whose buffers exceed the array (e.g. more
+ * than about 128 query columns of the digit form, or 16 of the RNS form, against a database of
+ * K = 20,992 and 30,720 rows at three query primes plus p): HFE_ENOMEM with nothing enqueued;
+ * HFE_EDEVICE if the array's address cannot be resolved.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams or host threads) race on it and must be ordered by the caller.  Nothing in the array
+ * needs clearing between calls (each call writes every byte it reads).
+ * hfe_noalloc_init: resolves the array's address on the current device ahead of the first call
+ * (optional; the first call on a device does it otherwise). */
+#define HFE_NOALLOC_SCRATCH_BYTES (256ull << 20)
+hfe_status hfe_noalloc_init(void);
+hfe_status hfe_ccmm_noalloc(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
+                            uint64_t* out, void* stream);
+
 /* An empty result handle shaped for query q against every code of db (level x d3 x (N_DB + d1)
  * residues, allocated on `stream`), for hfe_server_submit_encrypted.  Release with hfe_free. */
 hfe_status hfe_result_create(const hfe_db* db, const hfe_qct* q, void* stream, hfe_rct** out);

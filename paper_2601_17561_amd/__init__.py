@@ -30,6 +30,7 @@ HFE_FORM_RNS_I8 = 4
 HFE_FORM_P2_I8 = 8
 HFE_PROBE_MFMA_I8, HFE_PROBE_MFMA_I8_ZERO, HFE_PROBE_VALU_MAD_U64 = 1, 2, 3
 HFE_MAX_QPRIMES = 8
+HFE_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 STATUS_NAMES = {0: "HFE_OK", -1: "HFE_EINVAL", -2: "HFE_ESHAPE", -3: "HFE_ELEVEL", -4: "HFE_ENOMEM",
                 -5: "HFE_EDEVICE", -6: "HFE_EBUSY", -7: "HFE_EOVERFLOW", -8: "HFE_EINTERNAL"}
@@ -41,7 +42,7 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_plan_result", "hfe_autotune", "hfe_autotune_save", "hfe_autotune_load", "hfe_server_create",
             "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_drain", "hfe_server_stats", "hfe_server_reset_stats",
             "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes",
-            "hfe_ccmm_product", "hfe_probe_rate")
+            "hfe_ccmm_product", "hfe_probe_rate", "hfe_noalloc_init", "hfe_ccmm_noalloc")
 
 
 class HfeError(RuntimeError):
@@ -102,6 +103,8 @@ _SIGS = {
     "hfe_db_load": [_vp, ctypes.c_char_p, _u32, _vp, ctypes.POINTER(_vp)],
     "hfe_ccmm": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_vp)],
     "hfe_ccmm_product": [_vp, _vp, _i64, _i64, _i32, _vp, _vp],
+    "hfe_noalloc_init": [],
+    "hfe_ccmm_noalloc": [_vp, _vp, _i64, _i64, _i32, _vp, _vp],
     "hfe_decrypt": [_vp, _vp, _vp, _vp, _vp],
     "hfe_match": [_vp, _vp, _i64, ctypes.POINTER(_i32), _i32, _vp, _i64, _i32, _u32, _u32, _vp, _vp, _vp],
     "hfe_export": [_vp, _i32, _sz, _vp, _sz, ctypes.POINTER(_sz)],
@@ -334,6 +337,23 @@ def hfe_ccmm_product(db: Handle, q: Handle, row0: int, rows: int, form: int, C=N
     _check(_lib.hfe_ccmm_product(db.ptr, q.ptr, row0, rows, form, _stream(stream), _dev_ptr(C, torch.int64)),
            "hfe_ccmm_product")
     return C
+
+
+def hfe_noalloc_init() -> None:
+    _check(_lib.hfe_noalloc_init(), "hfe_noalloc_init")
+
+
+def hfe_ccmm_noalloc(db: Handle, q: Handle, row0: int, rows: int, form: int, out, stream=None):
+    """The allocation-free CCMM: the rescaled residues into `out`, a caller-allocated int64 GPU
+    tensor of level x d3 x (N_DB + rows) (uint64 residues < 2^36); returns out."""
+    torch = _torch()
+    level, d3, _, _ = hfe_shape(q)
+    n_db = hfe_shape(db)[2] - hfe_shape(db)[1]
+    if out.numel() < level * d3 * (n_db + rows):
+        raise ValueError(f"out holds {out.numel()} residues, the call writes {level * d3 * (n_db + rows)}")
+    _check(_lib.hfe_ccmm_noalloc(db.ptr, q.ptr, row0, rows, form, _dev_ptr(out, torch.int64), _stream(stream)),
+           "hfe_ccmm_noalloc")
+    return out
 
 
 def hfe_decrypt(keys: Handle, r: Handle, v=None, ip=None, stream=None):

@@ -923,12 +923,8 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   return HFE_OK;
 }
 
-hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form, void* stream,
-                    hfe_rct** out) {
-  if (!out) return fail(HFE_EINVAL, "out is NULL");
-  *out = nullptr;
-  const hfe_db* D = as_handle<hfe_db>(db, kDb);
-  const hfe_qct* Qc = as_handle<hfe_qct>(q, kQct);
+// Argument checks shared by the single-call CCMM entry points.
+static hfe_status check_ccmm_args(const hfe_db* D, const hfe_qct* Qc, int64_t row0, int64_t rows, int32_t form) {
   if (!D || !Qc) return fail(HFE_EINVAL, "invalid database or query handle");
   if (Qc->keys != D->keys) return fail(HFE_EINVAL, "database and query use different keys");
   if (Qc->K != D->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
@@ -937,6 +933,32 @@ hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t ro
   if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
     return fail(HFE_EINVAL, "unknown form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
+  return HFE_OK;
+}
+
+// The CCMM of hfe_ccmm with every device buffer of the call carved from [region, region + cap)
+// and the rescaled result written to `out` ([level][d3][N_DB + rows]); nothing is allocated.
+extern "C++" hfe_status hfe::ccmm_region(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
+                            hipStream_t s, uint64_t* out, void* region, size_t cap) {
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  const hfe_qct* Qc = as_handle<hfe_qct>(q, kQct);
+  HFE_TRY(check_ccmm_args(D, Qc, row0, rows, form));
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  if (!region) return fail(HFE_EINTERNAL, "no scratch region");
+  Workspace ws;
+  ws.base = static_cast<uint8_t*>(region);
+  ws.cap = cap;
+  hfe_rct R;  // shape record only
+  return ccmm_impl(D, Qc, row0, rows, form, s, &R, nullptr, &ws, out);
+}
+
+hfe_status hfe_ccmm(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form, void* stream,
+                    hfe_rct** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  const hfe_qct* Qc = as_handle<hfe_qct>(q, kQct);
+  HFE_TRY(check_ccmm_args(D, Qc, row0, rows, form));
   hfe_rct* R = new (std::nothrow) hfe_rct();
   if (!R) return fail(HFE_ENOMEM, "host allocation failed");
   hfe_status st = ccmm_impl(D, Qc, row0, rows, form, (hipStream_t)stream, R);
@@ -953,14 +975,7 @@ hfe_status hfe_ccmm_product(const hfe_db* db, const hfe_qct* q, int64_t row0, in
   if (!C) return fail(HFE_EINVAL, "C is NULL");
   const hfe_db* D = as_handle<hfe_db>(db, kDb);
   const hfe_qct* Qc = as_handle<hfe_qct>(q, kQct);
-  if (!D || !Qc) return fail(HFE_EINVAL, "invalid database or query handle");
-  if (Qc->keys != D->keys) return fail(HFE_EINVAL, "database and query use different keys");
-  if (Qc->K != D->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
-  if (Qc->level > D->keys->L) return fail(HFE_ELEVEL, "query level above the database primes");
-  if (row0 < 0 || rows < 1 || row0 + rows > D->d1) return fail(HFE_ESHAPE, "row range outside the database");
-  if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
-    return fail(HFE_EINVAL, "unknown form");
-  if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
+  HFE_TRY(check_ccmm_args(D, Qc, row0, rows, form));
   hfe_rct R;  // shape record only; the buffers of the call are released in stream order on return
   return ccmm_impl(D, Qc, row0, rows, form, (hipStream_t)stream, &R, C);
 }

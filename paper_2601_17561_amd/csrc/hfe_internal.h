@@ -531,4 +531,8 @@ FormShape form_shape(const hfe_db* D, int form);
 // Decryption of a result into caller-provided scratch y ([level][d3][rows] uint64).
 hfe_status decrypt_impl(const hfe_keys* K, const hfe_rct* R, double* v, int32_t* ip, uint64_t* y, hipStream_t s);
 void destroy_server(void* handle);  // hfe_server.cpp
+// hfe_ccmm with every device buffer of the call carved from [region, region + cap) and the
+// rescaled result written to out; HFE_ENOMEM (nothing enqueued) if the call needs more.
+hfe_status ccmm_region(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
+                       hipStream_t s, uint64_t* out, void* region, size_t cap);
 }  // namespace hfe
