@@ -134,6 +134,20 @@ PAPER_SHARE = Workload("share_ndb16384_nq8192_L3p_d1_14336_d2_12800_q512", 14, 1
 
 
 
+# Ring degree 2^16 (the transmission ring of Appendix C.1), one layer at a time so that the
+# oracle stays tractable: a database layer of N_DB = 2^16 with a small query layer, and a query
+# layer of N_Q = 2^16 with a small database layer; one query prime plus p, 256 codes of 1024 bits,
+# 4 query columns (query 0 a planted copy of database row 17).
+BIG_DB = Workload("bigdb_ndb65536_nq512_L1p_d1_256_d2_1024_q4", 16, 9, 1, 1, 256, 1024, 4, 1,
+                  planted=(Planted(0, 17, 0, 0.1),), seed=BASE_SEED + 31)
+BIG_Q = Workload("bigq_ndb512_nq65536_L1p_d1_256_d2_1024_q4", 9, 16, 1, 1, 256, 1024, 4, 1,
+                 planted=(Planted(0, 17, 0, 0.1),), seed=BASE_SEED + 32)
+
+# The share workload with both ring degrees at 2^16 (the configuration's literal N): the same
+# templates (same seed), K = 12,800 + 2^16 and 2^16 + 14,336 output rows.
+PAPER_LIT = dataclasses.replace(PAPER_SHARE, name="lit_ndb65536_nq65536_L3p_d1_14336_d2_12800_q512",
+                                log_n_db=16, log_n_q=16)
+
 # Database of the batched workload: the share's shapes with five query primes, so that batch
 # items can run at levels 1..5 (2..6 primes with the special prime).
 PAPER_SHARE_L5 = dataclasses.replace(PAPER_SHARE, name="share_ndb16384_nq8192_L5p_d1_14336_d2_12800",
@@ -176,7 +190,8 @@ def random_eyes(seed: int, stream: int, n_eyes: int, d2: int, p_code: float = 0.
             (g.random((n_eyes, d2)) < p_mask).astype(np.uint8))
 
 
-WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, MID, PAPER_SHARE, PAPER_SHARE_L5)}
+WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, MID, PAPER_SHARE, PAPER_SHARE_L5, BIG_DB,
+                                                      BIG_Q, PAPER_LIT)}
 
 
 def planted_for(w: Workload, count: int = 4) -> Tuple[Planted, ...]:

@@ -78,9 +78,10 @@ typedef enum { HFE_FORM_PLAIN_U64 = 1, HFE_FORM_I8_MFMA = 2, HFE_FORM_RNS_I8 = 4
 #define HFE_MAX_QPRIMES 8
 
 typedef struct {
-  uint32_t log_n_db;              /* N_DB = 2^log_n_db, database ring degree, 1..14 (the */
-                                  /* transforms are LDS-resident: 2^14 x 8 B = 128 KiB)  */
-  uint32_t log_n_q;               /* N_Q = 2^log_n_q, query ring degree, 1..14           */
+  uint32_t log_n_db;              /* N_DB = 2^log_n_db, database ring degree, 1..16 (up  */
+                                  /* to 2^14 one LDS-resident transform per polynomial,  */
+                                  /* 2^15 and 2^16 two passes through device memory)     */
+  uint32_t log_n_q;               /* N_Q = 2^log_n_q, query ring degree, 1..16           */
   uint32_t n_q_primes;            /* L, query primes carried by the database, 1..8       */
   uint64_t q[HFE_MAX_QPRIMES];    /* q_0..q_{L-1}: distinct primes < 2^36, = 1 mod 2N    */
   uint64_t p;                     /* special prime < 2^36, = 1 mod 2N, distinct from q_i */
@@ -236,6 +237,13 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
 typedef struct hfe_plan hfe_plan;
 hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols, uint32_t max_level,
                            int32_t form, hfe_plan** out);
+/* hfe_plan_create_for: a plan whose workspace is sized exactly for the batch `items` (n items):
+ * the query planes, contraction output, residues and results that batch needs, rather than the
+ * worst case of a column count and level over the whole database.  It runs that batch and any
+ * batch of at most n items whose needs fit every one of those capacities (else hfe_plan_run
+ * returns HFE_ESHAPE).  Errors as hfe_plan_create and hfe_ccmm_batched's item checks. */
+hfe_status hfe_plan_create_for(const hfe_db* db, const hfe_batch_item* items, int32_t n, int32_t form,
+                               hfe_plan** out);
 hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, int32_t use_graph,
                         void* stream);
 hfe_status hfe_plan_result(const hfe_plan* plan, int32_t i, const hfe_rct** view);

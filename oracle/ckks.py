@@ -53,7 +53,8 @@ def keygen(params: Params, seed: int) -> Keys:
 def s_q_matrix(keys: Keys) -> np.ndarray:
     """S_Q: d2 x N_Q, the stack of Neg(s_j) truncated to d2 rows."""
     P = keys.params
-    return np.concatenate([neg_matrix(keys.s[j]) for j in range(P.k)], axis=0)[:P.d2]
+    # only the first d2 rows of the stack exist: secret j contributes min(N_Q, d2 - j N_Q) rows
+    return np.concatenate([neg_matrix(keys.s[j], min(P.n_q, P.d2 - j * P.n_q)) for j in range(P.k)], axis=0)
 
 
 def s_db_rows(keys: Keys, rows: Sequence[int]) -> np.ndarray:

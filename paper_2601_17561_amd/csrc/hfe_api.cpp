@@ -154,9 +154,9 @@ void garner_consts(const hfe_keys* k, int level, uint64_t garner[HFE_MAX_QPRIMES
 // ------------------------------------------------------------------ validation
 static hfe_status check_params(const hfe_params* P) {
   if (!P) return fail(HFE_EINVAL, "params is NULL");
-  if (P->log_n_db < 1 || P->log_n_db > (uint32_t)kMaxLogN || P->log_n_q < 1 ||
-      P->log_n_q > (uint32_t)kMaxLogN)
-    return fail(HFE_EINVAL, "ring degrees must be 2^1 .. 2^14");
+  if (P->log_n_db < 1 || P->log_n_db > (uint32_t)kMaxLogNBig || P->log_n_q < 1 ||
+      P->log_n_q > (uint32_t)kMaxLogNBig)
+    return fail(HFE_EINVAL, "ring degrees must be 2^1 .. 2^16");
   if (P->n_q_primes < 1 || P->n_q_primes > HFE_MAX_QPRIMES)
     return fail(HFE_EINVAL, "n_q_primes must be 1..8");
   if (P->d2 < 1 || P->d2 > (1u << 20)) return fail(HFE_EINVAL, "d2 must be 1 .. 2^20");
@@ -501,7 +501,30 @@ static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t
   HFE_LAUNCH(launch_transpose_i8(m_db, d1, P.d2, MT.as<int8_t>(), s));
   HFE_LAUNCH(launch_db_T(m_db, d1, (int32_t)P.d2, K->sconj_hat.as<uint64_t>(), K->k, K->tab_q[0].tab,
                          Trow.as<int32_t>(), Tt.as<int32_t>(), s));
-  HFE_TRY(D->Dt.alloc(sizeof(uint64_t) * (size_t)np * D->K * D->R, s));
+  // With the plain form kept, every prime's residues stay in D->Dt.  Otherwise one prime at a time
+  // is encrypted into a scratch buffer and split into the int8 forms' planes, so the residues of
+  // all primes (8 bytes per entry and prime) never need to be resident at once.
+  const bool keep_plain = (forms & HFE_FORM_PLAIN_U64) != 0;
+  const size_t prime_elems = (size_t)D->K * D->R;
+  DevBuf one;
+  if (keep_plain)
+    HFE_TRY(D->Dt.alloc(sizeof(uint64_t) * (size_t)np * prime_elems, s));
+  else
+    HFE_TRY(one.alloc(sizeof(uint64_t) * prime_elems, s));
+  const size_t plane = (size_t)D->KB * D->R_pad * kKB;
+  if (forms & HFE_FORM_I8_MFMA) HFE_TRY(D->digits.alloc((size_t)np * kDigits * plane, s));
+  if (forms & HFE_FORM_RNS_I8) {
+    int n = 0;
+    HFE_TRY(rns_moduli_for(K, D->K, &n));
+    D->n_rns = n;
+    HFE_TRY(D->rns.alloc((size_t)np * n * plane, s));
+  }
+  if (forms & HFE_FORM_P2_I8) {
+    int n = 0;
+    HFE_TRY(p2_bases_for(K, D->K, &n));
+    D->n_p2 = n;
+    HFE_TRY(D->p2.alloc((size_t)np * 2 * n * plane, s));
+  }
   DbEncArgs a;
   a.seed = seed;
   a.MT = MT.as<int8_t>();
@@ -513,38 +536,20 @@ static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t
   a.R = D->R;
   a.k_db = K->k_db;
   a.p = P.p;
-  for (int z = 0; z < np; ++z)
-    HFE_LAUNCH(launch_db_encrypt(a, D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, K->prime_id[z],
-                                 K->mods[z], K->tab_db[z].tab,
+  for (int z = 0; z < np; ++z) {
+    uint64_t* Dz = keep_plain ? D->Dt.as<uint64_t>() + (size_t)z * prime_elems : one.as<uint64_t>();
+    HFE_LAUNCH(launch_db_encrypt(a, Dz, K->prime_id[z], K->mods[z], K->tab_db[z].tab,
                                  K->sdb_hat.as<uint64_t>() + (size_t)z * K->k_db * 2 * ndb, s));
-  if (forms & HFE_FORM_I8_MFMA) {
-    const size_t plane = (size_t)D->KB * D->R_pad * kKB;
-    HFE_TRY(D->digits.alloc((size_t)np * kDigits * plane, s));
-    for (int z = 0; z < np; ++z)
-      HFE_LAUNCH(launch_split_db(D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, D->K, D->R, D->KB, D->R_pad,
-                                 K->primes[z], D->digits.as<int8_t>() + (size_t)z * kDigits * plane, s));
+    if (forms & HFE_FORM_I8_MFMA)
+      HFE_LAUNCH(launch_split_db(Dz, D->K, D->R, D->KB, D->R_pad, K->primes[z],
+                                 D->digits.as<int8_t>() + (size_t)z * kDigits * plane, s));
+    if (forms & HFE_FORM_RNS_I8)
+      HFE_LAUNCH(launch_split_db_rns(Dz, D->K, D->R, D->KB, D->R_pad, K->primes[z], D->n_rns,
+                                     D->rns.as<int8_t>() + (size_t)z * D->n_rns * plane, s));
+    if (forms & HFE_FORM_P2_I8)
+      HFE_LAUNCH(launch_split_db_p2(Dz, D->K, D->R, D->KB, D->R_pad, K->primes[z], D->n_p2,
+                                    D->p2.as<int8_t>() + (size_t)z * 2 * D->n_p2 * plane, s));
   }
-  if (forms & HFE_FORM_RNS_I8) {
-    int n = 0;
-    HFE_TRY(rns_moduli_for(K, D->K, &n));
-    D->n_rns = n;
-    const size_t plane = (size_t)D->KB * D->R_pad * kKB;
-    HFE_TRY(D->rns.alloc((size_t)np * n * plane, s));
-    for (int z = 0; z < np; ++z)
-      HFE_LAUNCH(launch_split_db_rns(D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, D->K, D->R, D->KB, D->R_pad,
-                                     K->primes[z], n, D->rns.as<int8_t>() + (size_t)z * n * plane, s));
-  }
-  if (forms & HFE_FORM_P2_I8) {
-    int n = 0;
-    HFE_TRY(p2_bases_for(K, D->K, &n));
-    D->n_p2 = n;
-    const size_t plane = (size_t)D->KB * D->R_pad * kKB;
-    HFE_TRY(D->p2.alloc((size_t)np * 2 * n * plane, s));
-    for (int z = 0; z < np; ++z)
-      HFE_LAUNCH(launch_split_db_p2(D->Dt.as<uint64_t>() + (size_t)z * D->K * D->R, D->K, D->R, D->KB, D->R_pad,
-                                    K->primes[z], n, D->p2.as<int8_t>() + (size_t)z * 2 * n * plane, s));
-  }
-  if (!(forms & HFE_FORM_PLAIN_U64)) D->Dt.reset();
   return HFE_OK;
 }
 
@@ -1528,17 +1533,10 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
   return HFE_OK;
 }
 
-hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols, uint32_t max_level, int32_t form,
-                           hfe_plan** out) {
-  if (!out) return fail(HFE_EINVAL, "out is NULL");
-  *out = nullptr;
-  const hfe_db* D = as_handle<hfe_db>(db, kDb);
-  if (!D) return fail(HFE_EINVAL, "invalid database handle");
-  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
-    return fail(HFE_EINVAL, "plans run an int8 form");
-  if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
-  if (max_items < 1 || max_items > kMaxBatch) return fail(HFE_EINVAL, "max_items must be 1 .. 256");
-  if (max_cols < 1 || max_level < 1 || (int)max_level > D->keys->L) return fail(HFE_EINVAL, "bad capacity");
+// A plan with the given workspace capacities (bytes of query planes and small-modulus residues,
+// elements of the contraction output and of the results).
+static hfe_status plan_alloc(const hfe_db* D, int form, int32_t max_items, int64_t max_cols, int max_level,
+                             size_t xd_cap, size_t c_cap, size_t res_cap, size_t out_cap, hfe_plan** out) {
   hfe_plan* P = new (std::nothrow) hfe_plan();
   if (!P) return fail(HFE_ENOMEM, "host allocation failed");
   P->kind = kPlan;
@@ -1547,30 +1545,16 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   P->form = form;
   P->max_items = max_items;
   P->max_cols = max_cols;
-  P->max_level = (int)max_level;
-  const FormShape fs = form_shape(D, form);
-  const int planes = fs.planes;
-  const int64_t qpad = fs.qpad;
-  const int64_t ndb = 1ll << D->keys->P.log_n_db;
-  const int64_t R_max = ndb + D->d1;
-  // an owner problem pads at most qpad - 1 columns per item (two items at least when it also feeds
-  // split problems, which need up to 2 (qpad - 1))
-  const int64_t cols_pad = max_cols + (int64_t)max_items * (qpad - 1);
-  P->xd_cap = (size_t)(max_level + 1) * planes * D->KB * cols_pad * kKB;
-  // + the alignment of each problem's start
-  P->c_cap = (size_t)(max_level + 1) * max_cols * R_max + 4 * (size_t)max_problems(max_items);
-  // residues of the small-modulus forms (bytes; one per modulus or two per base), each problem's
-  // start aligned to 8 bytes
-  const int res_planes = fs.p2 ? D->n_p2 : fs.rns ? D->n_rns : 0;
-  P->res_cap = fs.res_bytes ? (size_t)(max_level + 1) * res_planes * max_cols * R_max * fs.res_bytes +
-                                  8 * (size_t)max_problems(max_items)
-                            : 0;
-  P->out_cap = (size_t)max_level * max_cols * R_max;
+  P->max_level = max_level;
+  P->xd_cap = xd_cap;
+  P->c_cap = c_cap;
+  P->res_cap = res_cap;
+  P->out_cap = out_cap;
   const BlobLayout L(max_items, max_problems(max_items));
   P->blob_bytes = L.bytes;
   hfe_status st = P->ws_xd.alloc(P->xd_cap, nullptr);
   if (st == HFE_OK) st = P->ws_c.alloc(sizeof(uint64_t) * P->c_cap, nullptr);
-  if (st == HFE_OK && fs.res_bytes) st = P->ws_res.alloc(P->res_cap, nullptr);
+  if (st == HFE_OK && P->res_cap) st = P->ws_res.alloc(P->res_cap, nullptr);
   if (st == HFE_OK) st = P->ws_out.alloc(sizeof(uint64_t) * P->out_cap, nullptr);
   if (st == HFE_OK) st = P->desc.alloc(L.bytes, nullptr);
   hipError_t e = hipSuccess;
@@ -1595,6 +1579,56 @@ hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols
   }
   *out = P;
   return HFE_OK;
+}
+
+static hfe_status check_plan_form(const hfe_db* D, int32_t form) {
+  if (!D) return fail(HFE_EINVAL, "invalid database handle");
+  if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
+    return fail(HFE_EINVAL, "plans run an int8 form");
+  if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
+  return HFE_OK;
+}
+
+hfe_status hfe_plan_create(const hfe_db* db, int32_t max_items, int64_t max_cols, uint32_t max_level, int32_t form,
+                           hfe_plan** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  HFE_TRY(check_plan_form(D, form));
+  if (max_items < 1 || max_items > kMaxBatch) return fail(HFE_EINVAL, "max_items must be 1 .. 256");
+  if (max_cols < 1 || max_level < 1 || (int)max_level > D->keys->L) return fail(HFE_EINVAL, "bad capacity");
+  const FormShape fs = form_shape(D, form);
+  const int planes = fs.planes;
+  const int64_t qpad = fs.qpad;
+  const int64_t ndb = 1ll << D->keys->P.log_n_db;
+  const int64_t R_max = ndb + D->d1;
+  // an owner problem pads at most qpad - 1 columns per item (two items at least when it also feeds
+  // split problems, which need up to 2 (qpad - 1))
+  const int64_t cols_pad = max_cols + (int64_t)max_items * (qpad - 1);
+  const size_t xd_cap = (size_t)(max_level + 1) * planes * D->KB * cols_pad * kKB;
+  // + the alignment of each problem's start
+  const size_t c_cap = (size_t)(max_level + 1) * max_cols * R_max + 4 * (size_t)max_problems(max_items);
+  // residues of the small-modulus forms (bytes; one per modulus or two per base), each problem's
+  // start aligned to 8 bytes
+  const int res_planes = fs.p2 ? D->n_p2 : fs.rns ? D->n_rns : 0;
+  const size_t res_cap = fs.res_bytes ? (size_t)(max_level + 1) * res_planes * max_cols * R_max * fs.res_bytes +
+                                            8 * (size_t)max_problems(max_items)
+                                      : 0;
+  const size_t out_cap = (size_t)max_level * max_cols * R_max;
+  return plan_alloc(D, form, max_items, max_cols, (int)max_level, xd_cap, c_cap, res_cap, out_cap, out);
+}
+
+hfe_status hfe_plan_create_for(const hfe_db* db, const hfe_batch_item* items, int32_t n, int32_t form,
+                               hfe_plan** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  const hfe_db* D = as_handle<hfe_db>(db, kDb);
+  HFE_TRY(check_plan_form(D, form));
+  if (!items || n < 1 || n > kMaxBatch) return fail(HFE_EINVAL, "a batch holds 1 .. 256 items");
+  for (int i = 0; i < n; ++i) HFE_TRY(check_item(D, items[i]));
+  const BlobLayout L(n, max_problems(n));
+  const BatchSizes sz = batch_fill(D, items, n, form, 0, nullptr, nullptr, nullptr, nullptr, nullptr, L);
+  return plan_alloc(D, form, n, sz.cols, sz.max_level, sz.xd_bytes, sz.c_elems, sz.res_bytes, sz.out_elems, out);
 }
 
 hfe_status hfe_plan_run(hfe_plan* plan, const hfe_batch_item* items, int32_t n, int32_t use_graph, void* stream) {

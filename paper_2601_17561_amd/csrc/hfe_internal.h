@@ -19,6 +19,7 @@ constexpr int kDigits = 5;                       // balanced base-256 digits per
 constexpr int kKB = 64;                          // K bytes per digit block
 constexpr int kRowPad = 256;                     // extra zero rows after the digit planes
 constexpr int kMaxLogN = 14;                     // ring degrees handled by the LDS-resident NTT
+constexpr int kMaxLogNBig = 16;                  // ring degrees handled at all (two-pass NTT above 2^14)
 constexpr int kXcds = 8;                         // accelerator complex dies (one L2 each) of an MI355X
 
 // ------------------------------------------------------------------ errors
@@ -214,6 +215,20 @@ struct QEncArgs {
 hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prime_id,
                             const Mod& m, uint64_t delta_mod, NttTab tab_q,
                             const uint64_t* s_hat_prime, hipStream_t s);
+
+// The same operations for ring degrees above 2^14 (k_ntt_big.hip): two-pass transforms through
+// device workspaces taken from the allocator; the LDS-resident launchers forward to these.
+hipError_t launch_ntt_fwd_big(uint64_t* a, int64_t count, int64_t stride, NttTab tab, bool with_shoup,
+                              hipStream_t s);
+hipError_t launch_db_T_big(const int8_t* m_db, int64_t d1, int32_t d2, const uint64_t* sconj_hat, int k,
+                           NttTab tab_q0, int32_t* Trow, hipStream_t s);
+hipError_t launch_db_encrypt_big(const DbEncArgs& a, uint64_t* Dt_prime, uint32_t prime_id, const Mod& m,
+                                 NttTab tab_db, const uint64_t* sdb_hat_prime, hipStream_t s);
+hipError_t launch_q_encrypt_big(const QEncArgs& a, uint64_t* XT_prime, uint32_t prime_id, const Mod& m,
+                                uint64_t delta_mod, NttTab tab_q, const uint64_t* s_hat_prime, hipStream_t s);
+hipError_t launch_dec_products_big(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,
+                                   int64_t rows, NttTab tab, const uint64_t* sdb_hat_prime, int j0, int j1,
+                                   uint64_t* y_prime, hipStream_t s);
 
 // Digit split of the database: Dt [K][R] residues mod q -> digits [5][KB][R_pad][64].
 hipError_t launch_split_db(const uint64_t* Dt_prime, int64_t K, int64_t R, int64_t KB,

@@ -1,5 +1,7 @@
 // Negacyclic NTT (LDS-resident, ring degrees up to 2^14) and the kernels built on it:
 // secret-key transforms, T = M_DB S_Q, database and query encryption, decryption products.
+// Larger ring degrees (2^15, 2^16) go through the two-pass transforms of k_ntt_big.hip, which the
+// launchers below call with the same arguments.
 //
 // Products in R_n = Z[X]/(X^n + 1) mod a 36-bit prime q (Section 2.2.1) are computed as
 // INTT(NTT(a) . NTT(s)) with the merged negacyclic transforms of Longa and Naehrig (2016):
@@ -173,6 +175,7 @@ __global__ void __launch_bounds__(kNttThreads) k_ntt_fwd(uint64_t* a, int64_t st
 hipError_t launch_ntt_fwd(uint64_t* a, int64_t count, int64_t stride, NttTab tab, bool with_shoup,
                           hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  if (tab.logn > kMaxLogN) return launch_ntt_fwd_big(a, count, stride, tab, with_shoup, s);
   const size_t lds = sizeof(double) << tab.logn;
   hipError_t e = allow_lds(k_ntt_fwd, lds);
   if (e != hipSuccess) return e;
@@ -260,7 +263,8 @@ hipError_t launch_db_T(const int8_t* m_db, int64_t d1, int32_t d2, const uint64_
   if (d1 <= 0) return hipSuccess;
   const int n = 1 << tab_q0.logn;
   const size_t lds = sizeof(double) * n;
-  hipError_t e = by_regs(regs_per_thread(tab_q0.logn), [&](auto rc) {
+  hipError_t e = tab_q0.logn > kMaxLogN ? launch_db_T_big(m_db, d1, d2, sconj_hat, k, tab_q0, Trow, s)
+                                        : by_regs(regs_per_thread(tab_q0.logn), [&](auto rc) {
     constexpr int R = decltype(rc)::value;
     hipError_t e2 = allow_lds(k_db_T<R>, lds);
     if (e2 != hipSuccess) return e2;
@@ -342,6 +346,7 @@ k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, cons
 hipError_t launch_db_encrypt(const DbEncArgs& a, uint64_t* Dt_prime, uint32_t prime_id, const Mod& m,
                              NttTab tab_db, const uint64_t* sdb_hat_prime, hipStream_t s) {
   if (a.K <= 0) return hipSuccess;
+  if (tab_db.logn > kMaxLogN) return launch_db_encrypt_big(a, Dt_prime, prime_id, m, tab_db, sdb_hat_prime, s);
   const size_t lds = sizeof(double) << tab_db.logn;
   return by_regs(regs_per_thread(tab_db.logn), [&](auto rc) {
     constexpr int R = decltype(rc)::value;
@@ -421,6 +426,7 @@ hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prim
                             uint64_t delta_mod, NttTab tab_q, const uint64_t* s_hat_prime,
                             hipStream_t s) {
   if (a.d3 <= 0) return hipSuccess;
+  if (tab_q.logn > kMaxLogN) return launch_q_encrypt_big(a, XT_prime, prime_id, m, delta_mod, tab_q, s_hat_prime, s);
   const size_t lds = sizeof(double) << tab_q.logn;
   return by_regs(regs_per_thread(tab_q.logn), [&](auto rc) {
     constexpr int R = decltype(rc)::value;
@@ -466,6 +472,8 @@ hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_
   const int64_t n = 1ll << n_db_log;
   const int j0 = (int)(row0 / n), j1 = (int)((row0 + rows - 1) / n);
   if (j1 >= k_db) return hipErrorInvalidValue;
+  if (tab.logn > kMaxLogN)
+    return launch_dec_products_big(out_prime, d3, R_out, row0, rows, tab, sdb_hat_prime, j0, j1, y_prime, s);
   const size_t lds = sizeof(double) << tab.logn;
   hipError_t e = allow_lds(k_dec_products, lds);
   if (e != hipSuccess) return e;

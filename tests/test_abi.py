@@ -57,7 +57,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(log_n_db=0), -1),
-    (dict(log_n_q=15), -1),
+    (dict(log_n_q=17), -1),                 # ring degrees 2^1 .. 2^16
     (dict(n_q_primes=0), -1),
     (dict(t_num=4, t_den=8), -1),
     (dict(t_den=0), -1),
