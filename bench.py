@@ -79,37 +79,93 @@ def p2_bases(w: S.Workload, qmax: int) -> int:
     raise ValueError("contraction too long for the n^2 bases")
 
 
-def cpu_baseline(w: S.Workload, inp, rows_sample: int, cols_sample: int):
-    """The oracle's CCMM (lift, exact contraction, CRT rescale) on a slice of the workload."""
-    import torch
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_block(args):
+    """One worker of the oracle contraction: its block of database rows (uniform residues per
+    prime, not timed; the oracle's work does not depend on their values), then the oracle's CCMM
+    of that block (timed), started together with the other workers at a barrier."""
+    w, P, XT, row_lo, rows, barrier = args
+    from oracle import ckks as OC
+    from oracle import params as OP
+    rng = np.random.default_rng(row_lo)
+    D = {pid: rng.integers(0, prime, (rows, P.K), dtype=np.int64) for pid, prime in OC.prime_ids(P, w.level)}
+    Ps = OP.Params(log_n_db=int(np.log2(rows)), log_n_q=P.log_n_q, q=P.q, p=P.p, d2=P.d2,
+                   max_db_rows=P.max_db_rows)
+    barrier.wait()
+    t0 = time.perf_counter()
+    OC.ccmm(Ps, D, XT, w.level, 0, 0)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(w: S.Workload, inp, workers: int, rows_per_worker: int, cols: int, enc_cols: int,
+                 dec_rows: int):
+    """The oracle timed on the host: query encryption of enc_cols columns, the CCMM (lift, exact
+    contraction, CRT rescale) of workers x rows_per_worker database rows x cols query columns in a
+    process pool (one row block per worker, started together), and decryption of cols columns x
+    dec_rows codes; each part scaled linearly to the workload's columns and rows, summed per step.
+    Runs before the GPU is touched, so the pool's fork copies no device state."""
+    import multiprocessing as mp
     from oracle import ckks as OC
     from oracle import iris as OI
     from oracle import params as OP
+
     from oracle import prng
 
     P = OP.make_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
     keys = OC.keygen(P, KEY_SEED)
-    qc, qm = OI.shifted_queries(inp["q_codes"][:1], inp["q_masks"][:1], inp["shifts"][:cols_sample])
+    qc, qm = OI.shifted_queries(inp["q_codes"][:2], inp["q_masks"][:2], inp["shifts"])
     mq = OI.ternary(qc, qm)
-    XT = OC.encrypt_query(keys, mq, w.level, Q_SEED)
-    # database rows of the sample: the first rows of D (A-part), drawn from the database stream
-    log_rows = int(np.log2(rows_sample))
-    Ps = OP.Params(log_n_db=log_rows, log_n_q=P.log_n_q, q=P.q, p=P.p, d2=P.d2, max_db_rows=P.max_db_rows)
-    D = {pid: prng.uniform_matrix(DB_SEED, prng.DBA, pid, rows_sample, P.K, prime)
-         for pid, prime in OC.prime_ids(P, len(P.q))}
+    SQ = OC.s_q_matrix(keys)  # the secret matrix: key set-up, built once (as the library's keygen tables)
     t0 = time.perf_counter()
-    OC.ccmm(Ps, D, XT, w.level, 0, 0)
-    dt = time.perf_counter() - t0
+    A = {i: prng.uniform_matrix(Q_SEED, prng.QA, i, P.n_q, enc_cols, P.q[i]) for i in range(w.level)}
+    E = prng.gaussian_matrix(Q_SEED, prng.QE, 0, P.d2, enc_cols)
+    OC.encrypt_query_with(P, SQ, mq[:enc_cols], w.level, A, E)
+    t_enc = time.perf_counter() - t0
+    XT = OC.encrypt_query(keys, mq[:cols], w.level, Q_SEED)
+    t0 = time.perf_counter()
+    OC.lift_query(P, XT, w.level)
+    t_lift = time.perf_counter() - t0  # per query column; every worker repeats it for its block
+    ctx = mp.get_context("fork")
+    barrier = ctx.Manager().Barrier(workers)
+    with ctx.Pool(workers) as pool:
+        times = pool.map(_oracle_block, [(w, P, XT, i * rows_per_worker, rows_per_worker, barrier)
+                                         for i in range(workers)])
+    t_ccmm = max(times)
+    t_rows = max(t_ccmm - t_lift, 0.0)  # the row-dependent part: contraction and CRT rescale
+    # decryption of the sample: A_out for cols columns over the N_DB A rows, B_out for dec_rows codes
+    rng = np.random.default_rng(5)
+    out = {i: np.concatenate([rng.integers(0, P.q[i], (cols, P.n_db)), rng.integers(0, P.q[i], (cols, dec_rows))],
+                             axis=1).astype(np.int64) for i in range(w.level)}
+    t0 = time.perf_counter()
+    OC.decrypt(keys, out, w.level, 0, dec_rows)
+    t_dec = time.perf_counter() - t0
     work = algorithmic_work(w)
-    # the full step needs R_out x d3 output residues per prime for d1 x d3 comparisons
-    cmp_per_s = w.d1 * rows_sample * cols_sample / (dt * work["R_out"])
-    return dict(value=cmp_per_s, unit="comparisons/s", cores=1, kind="oracle",
-                sample=(f"oracle CCMM (centered CRT lift, exact int64-limb contraction, CRT rescale) of "
-                        f"{rows_sample} database rows x {cols_sample} query columns x full K={P.K} x "
-                        f"{w.level + 1} primes in {dt:.1f} s, scaled by rows {rows_sample}/{work['R_out']}; "
-                        f"encryption and decryption not included; numpy int64 products, 1 thread "
-                        f"(torch threads available: {torch.get_num_threads()})"),
-                seconds=dt)
+    step_s = (t_enc * w.d3 / enc_cols
+              + t_lift * w.d3 / cols
+              + t_rows * (work["R_out"] / (workers * rows_per_worker)) * (w.d3 / cols)
+              + t_dec * (w.d1 / dec_rows) * (w.d3 / cols))
+    return dict(value=w.d1 * w.d3 / step_s, unit="comparisons/s", cores=workers, kind="oracle",
+                cpu_model=_cpu_model(), host_cpus=os.cpu_count(),
+                sample=(f"oracle step extrapolated from samples: query encryption of {enc_cols} columns in "
+                        f"{t_enc:.1f} s (1 core, secret matrix prebuilt); CCMM centered CRT lift of {cols} "
+                        f"columns in {t_lift:.1f} s (1 core); exact int64-limb contraction and CRT rescale of "
+                        f"{workers} x {rows_per_worker} database rows x {cols} columns x full K={P.K} x "
+                        f"{w.level + 1} primes in {t_rows:.1f} s ({workers} processes, one row block each, "
+                        f"their lift time subtracted); decryption of {cols} columns x {dec_rows} codes in "
+                        f"{t_dec:.1f} s (1 core); scaled linearly to {w.d3} columns, {work['R_out']} "
+                        f"contraction rows and {w.d1} codes: {step_s:.0f} s per step"),
+                parts_s={"encrypt": t_enc, "lift": t_lift, "contraction_rescale": t_rows, "decrypt": t_dec},
+                step_s=step_s)
 
 
 def encrypt_database(H, torch, w, forms):
@@ -130,17 +186,20 @@ def encrypt_eyes(H, torch, keys, w, stream_id, eyes, level, shifts):
     return H.hfe_encrypt(keys, m_q, level, Q_SEED + stream_id)
 
 
-def run_batched(args, H, torch):
-    """Uneven batch: items of 1-64 eyes x 16 shifts at levels 1-5 (2-6 primes with p) against
-    database shards of 2,048-14,336 codes, as one batched call (grouped persistent launches; the
-    workspace sized to the batch, which a plan would size for its worst case), against the same
-    items as one hfe_ccmm call each, for the three int8 forms."""
+def run_batched(args, H, torch, forms=("i8", "rns", "p2"), steps=None, compare_sequential=True):
+    """Uneven batch (configuration 4): items of 1-64 eyes x 16 shifts at levels 1-5 (2-6 primes
+    with p) against database shards of 2,048-14,336 codes, run through a plan sized for the batch:
+    one grouped lift launch, ONE persistent contraction launch over every item's tiles, the grouped
+    reconstruction (small-modulus forms) and rescale, captured once into a hipGraph that every timed
+    run replays.  Optionally the same items as one hfe_ccmm call each.  Returns one dict per form."""
     w = S.PAPER_SHARE_L5
+    steps = steps or args.steps
     n_db, K = 1 << w.log_n_db, w.d2 + (1 << w.log_n_q)
     mix = S.batched_mix(w.seed, args.batch_items, w.d1, 64, w.n_q_primes, 2048)
     shifts = [int(x) for x in S.default_shifts(16)]
-    log(f"batched: encrypting the {w.d1}-code database with {w.n_q_primes} query primes + p (int8 forms)")
-    keys, db = encrypt_database(H, torch, w, H.HFE_FORM_I8_MFMA | H.HFE_FORM_RNS_I8 | H.HFE_FORM_P2_I8)
+    codes = {"i8": H.HFE_FORM_I8_MFMA, "rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}
+    log(f"batched: encrypting the {w.d1}-code database with {w.n_q_primes} query primes + p ({', '.join(forms)})")
+    keys, db = encrypt_database(H, torch, w, sum(codes[f] for f in forms))
     items = []
     for i, it in enumerate(mix):
         items.append((encrypt_eyes(H, torch, keys, w, i, it.eyes, it.level, shifts), it.row0, it.rows))
@@ -148,66 +207,96 @@ def run_batched(args, H, torch):
     cols = sum(it.eyes * 16 for it in mix)
     macs = sum((n_db + it.rows) * K * it.eyes * 16 * (it.level + 1) for it in mix)
     comparisons = sum(it.rows * it.eyes * 16 for it in mix)
-    log(f"batched: {len(mix)} items, {cols} query columns; autotuning the digit tile")
-    # the plan looks the autotuner's table up by its largest level and mean column count
-    tq = encrypt_eyes(H, torch, keys, w, 999, 32, w.n_q_primes, shifts)
-    tuned = H.hfe_autotune(db, tq, 0, w.d1, reps=1)
-    tq.free()
+    tuned = None
+    if "i8" in forms:
+        log(f"batched: {len(mix)} items, {cols} query columns; autotuning the digit tile")
+        # plans look the autotuner's table up by the batch's largest level and mean column count
+        tq = encrypt_eyes(H, torch, keys, w, 999, 32, w.n_q_primes, shifts)
+        tuned = H.hfe_autotune(db, tq, 0, w.d1, reps=1)
+        tq.free()
     qs, p_special = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1).primes()
     n_mod = rns_moduli(w, max(list(qs) + [p_special]))
     n_b = p2_bases(w, max(list(qs) + [p_special]))
     tiles = {"rns": f"rns 256 or 128 columns per problem, {n_mod} moduli",
              "p2": f"n^2 256 or 128 columns per problem, {n_b} bases"}
-    for name, form, per_mac in (("i8", H.HFE_FORM_I8_MFMA, 50), ("rns", H.HFE_FORM_RNS_I8, 2 * n_mod),
-                                ("p2", H.HFE_FORM_P2_I8, 2 * 3 * n_b)):
-        torch.cuda.empty_cache()                            # the previous form's workspace
-        res = H.hfe_ccmm_batched(db, items, form)           # warm-up (workspace into torch's cache)
-        same = all(np.array_equal(H.hfe_export(res[i], 0, 0, 1 << 16),
+    per_mac = {"i8": 50, "rns": 2 * n_mod, "p2": 2 * 3 * n_b}
+    out = []
+    for name in forms:
+        form = codes[name]
+        torch.cuda.empty_cache()
+        plan = H.hfe_plan_create_for(db, items, form)
+        H.hfe_plan_run(plan, items, use_graph=True)        # captures the graph
+        torch.cuda.synchronize()
+        same = all(np.array_equal(H.hfe_export(H.hfe_plan_result(plan, i), 0, 0, 1 << 16),
                                   H.hfe_export(H.hfe_ccmm(db, q, r0, nr, form), 0, 0, 1 << 16))
                    for i, (q, r0, nr) in list(enumerate(items))[:4])
-        del res
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            for r in H.hfe_ccmm_batched(db, items, form):
-                r.free()
+        ev[0].record()
+        for _ in range(steps):
+            H.hfe_plan_run(plan, items, use_graph=True)
+        ev[1].record()
         torch.cuda.synchronize()
-        plan_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        t0 = time.perf_counter()
-        for q, r0, nr in items:
-            H.hfe_ccmm(db, q, r0, nr, form).free()
-        torch.cuda.synchronize()
-        seq_ms = (time.perf_counter() - t0) * 1e3
-        tops = per_mac * macs / (plan_ms * 1e-3) / 1e12
-        line = {"metric": "batched encrypted CCMM, comparisons/s (grouped persistent launches)",
-                "value": comparisons / (plan_ms * 1e-3), "unit": "comparisons/s", "n_gpus": 1, "steps": args.steps,
-                "higher_is_better": True, "form": name, "ms_per_batch": plan_ms, "int8_tops": tops,
-                "frac_of_peak": tops / PEAK_I8_TOPS, "sequential_ms": seq_ms,
-                "speedup_vs_sequential": seq_ms / plan_ms, "same_residues_as_single_calls": bool(same),
-                "tile": H.hfe_i8_variant_name(tuned) if name == "i8" else tiles[name],
-                "dtype": "i8", "data": "synthetic",
-                "config": {"workload": "batched_" + w.name, "items": len(mix), "eyes": "1-64", "shifts": 16,
-                           "levels": "1-5 query primes + p", "rows": "2048-14336", "columns": cols}}
-        print(json.dumps(line), flush=True)
+        batch_ms = (time.perf_counter() - t0) * 1e3 / steps
+        dev_ms = ev[0].elapsed_time(ev[1]) / steps
+        plan.free()
+        seq_ms = None
+        if compare_sequential:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for q, r0, nr in items:
+                H.hfe_ccmm(db, q, r0, nr, form).free()
+            torch.cuda.synchronize()
+            seq_ms = (time.perf_counter() - t0) * 1e3
+        tops = per_mac[name] * macs / (batch_ms * 1e-3) / 1e12
+        res = {"form": name, "value": comparisons / (batch_ms * 1e-3), "unit": "comparisons/s",
+               "ms_per_batch": batch_ms, "device_ms_per_batch": dev_ms, "int8_tops": tops,
+               "frac_of_peak": tops / PEAK_I8_TOPS, "sequential_ms": seq_ms,
+               "speedup_vs_sequential": (seq_ms / batch_ms) if seq_ms else None,
+               "same_residues_as_single_calls": bool(same), "graph": True, "steps": steps,
+               "tile": H.hfe_i8_variant_name(tuned) if name == "i8" else tiles[name],
+               "items": len(mix), "columns": cols, "residue_macs": macs, "comparisons": comparisons}
+        log(f"batched {name}: {batch_ms:.1f} ms per batch ({res['value']:.3e} comparisons/s, "
+            f"{100 * res['frac_of_peak']:.1f}% of int8 peak), graph replay; sequential {seq_ms}")
+        out.append(res)
+    for q, _, _ in items:
+        q.free()
+    db.free()
+    keys.free()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
 
 
-def run_serving(args, H, torch):
-    """Poisson arrivals of 1-32 eyes x 16 shifts against the resident share database, through
-    the continuous-batching server; throughput and arrival-to-result latency percentiles.
+def batched_line(r, w=S.PAPER_SHARE_L5):
+    return {"metric": "batched encrypted CCMM, comparisons/s (one plan: grouped launches, one persistent "
+                      "contraction launch, replayed hipGraph)",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "i8", "data": "synthetic", **r,
+            "config": {"workload": "batched_" + w.name, "items": r["items"], "eyes": "1-64", "shifts": 16,
+                       "levels": "1-5 query primes + p", "rows": "2048-14336", "columns": r["columns"]}}
+
+
+def run_serving(args, H, torch, rates=None, form_name=None):
+    """Configuration 5: Poisson arrivals of 1-32 eyes x 16 shifts against the resident share
+    database, through the continuous-batching server; throughput and arrival-to-result latency
+    percentiles per arrival rate.  Returns one dict per rate.
 
     Queries are encrypted before the timed window (clients encrypt on their side): one ciphertext
     per eye count 1..32 serves every request of that size, so a 10 s window at 200 req/s needs
     4.3 GB of query ciphertexts rather than one per request."""
     w = S.PAPER_SHARE
+    rates = rates or args.rates
+    form_name = form_name or args.serve_form
     shifts = [int(x) for x in S.default_shifts(16)]
-    log(f"serving: encrypting the {w.d1}-code database (int8 form)")
-    form = {"rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}.get(args.serve_form, H.HFE_FORM_I8_MFMA)
+    form = {"rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}.get(form_name, H.HFE_FORM_I8_MFMA)
+    log(f"serving: encrypting the {w.d1}-code database ({form_name} form)")
     keys, db = encrypt_database(H, torch, w, form)
     dev = torch.device("cuda", 0)
     pool = {e: encrypt_eyes(H, torch, keys, w, 1000 + e, e, w.level, shifts) for e in range(1, 33)}
     torch.cuda.synchronize()
     lines = []
-    for rate in args.rates:
+    for rate in rates:
         n = max(8, int(rate * args.serve_seconds))
         t_arr, eyes = S.poisson_arrivals(w.seed + int(rate), n, rate, 32)
         encrypted = args.serve_results == "encrypted"
@@ -239,27 +328,103 @@ def run_serving(args, H, torch):
         st = H.hfe_server_stats(srv)
         srv.free()
         cmp = int(eyes.sum()) * 16 * w.d1
-        line = {"metric": "encrypted 1:N serving, comparisons/s with continuous batching",
-                "value": cmp / dt, "unit": "comparisons/s", "n_gpus": 1, "higher_is_better": True,
-                "offered_req_per_s": rate, "requests": n, "served_req_per_s": n / dt, "seconds": dt,
+        line = {"value": cmp / dt, "unit": "comparisons/s", "offered_req_per_s": rate, "requests": n,
+                "served_req_per_s": n / dt, "seconds": dt,
                 "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "service_p50_ms": st["service_p50_ms"],
                 "service_p99_ms": st["service_p99_ms"], "steps": st["steps"],
                 "mean_cols_per_step": st["mean_cols_per_step"], "max_queue": st["max_queue"],
-                "rejected": st["rejected"], "form": args.serve_form, "results": args.serve_results,
+                "rejected": st["rejected"], "max_busy_slots": st["max_busy_slots"],
+                "overlap_pairs": st["overlap_pairs"], "form": form_name, "results": args.serve_results,
                 "latency": ("arrival -> encrypted result ready" if encrypted else "arrival -> decrypted products"),
-                "dtype": "i8", "data": "synthetic",
-                "config": {"workload": "serving_" + w.name, "eyes": "1-32", "shifts": 16,
-                           "arrivals": f"poisson {rate}/s", "window_s": args.serve_seconds,
-                           "max_cols_per_step": args.serve_cols, "slots": 2,
-                           "mem_budget_gib": args.serve_budget_gib}}
-        print(json.dumps(line), flush=True)
+                "window_s": args.serve_seconds, "max_cols_per_step": args.serve_cols, "slots": 2,
+                "mem_budget_gib": args.serve_budget_gib}
+        log(f"serving {form_name} at {rate} req/s: served {n / dt:.1f} req/s, p50 {st['p50_ms']:.0f} ms, "
+            f"p99 {st['p99_ms']:.0f} ms, {cmp / dt:.3e} comparisons/s")
         lines.append(line)
         torch.cuda.synchronize()
         for o in outs:
             if encrypted:
                 o.free()
         del outs
+    for q in pool.values():
+        q.free()
+    db.free()
+    keys.free()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     return lines
+
+
+def serving_line(r, w=S.PAPER_SHARE):
+    return {"metric": "encrypted 1:N serving, comparisons/s with continuous batching", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "i8", "data": "synthetic", **r,
+            "config": {"workload": "serving_" + w.name, "eyes": "1-32", "shifts": 16,
+                       "arrivals": f"poisson {r['offered_req_per_s']}/s", "window_s": r["window_s"],
+                       "max_cols_per_step": r["max_cols_per_step"], "slots": 2,
+                       "mem_budget_gib": r["mem_budget_gib"]}}
+
+
+def run_lit(args, H, torch):
+    """The share step at ring degree 2^16 for both layers (N_DB = N_Q = 2^16): the database is
+    encrypted one prime at a time straight into its digit planes (125 GB; its 200 GB of residues are
+    never resident together), then encode -> encrypt -> CCMM (int8 digits) -> decrypt -> match.
+    The decrypted inner products are checked against the plaintext products of the same templates
+    (ternary matrices multiplied in float32 on the device, exact below 2^24)."""
+    w = S.PAPER_LIT
+    work = algorithmic_work(w)
+    dev = torch.device("cuda", 0)
+    inp = S.make_inputs(w)
+    P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
+    keys = H.hfe_keygen(P, KEY_SEED)
+    db_codes = torch.from_numpy(inp["db_codes"]).to(dev)
+    db_masks = torch.from_numpy(inp["db_masks"]).to(dev)
+    q_codes = torch.from_numpy(inp["q_codes"]).to(dev)
+    q_masks = torch.from_numpy(inp["q_masks"]).to(dev)
+    shifts = [int(x) for x in inp["shifts"]]
+    log(f"lit: encrypting the {w.d1}-code database at N_DB = N_Q = 2^16 (digit form, one prime at a time)")
+    t0 = time.perf_counter()
+    m_db = H.hfe_encode(db_codes, db_masks, [0])
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_I8_MFMA)
+    torch.cuda.synchronize()
+    t_db = time.perf_counter() - t0
+    log(f"lit: database encrypted in {t_db:.2f} s ({H.hfe_db_bytes(db) / 1e9:.1f} GB of digit planes)")
+    H.hfe_set_i8_variant(args.variant)
+    ms_steps, kernel_ms, ip = [], [], None
+    H.hfe_profile(True)
+    for i in range(args.lit_steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m_q = H.hfe_encode(q_codes, q_masks, shifts)
+        qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+        r = H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_I8_MFMA)
+        _, ip = H.hfe_decrypt(keys, r, v=False)
+        _, eye = H.hfe_match(ip, q_masks, shifts, db_masks, want_decision=False)
+        torch.cuda.synchronize()
+        if i > 0:                                   # the first step warms up
+            ms_steps.append((time.perf_counter() - t0) * 1e3)
+            kernel_ms.append(H.hfe_profile_ms(r, 3)[1])
+        r.free()
+        qct.free()
+    H.hfe_profile(False)
+    mq = H.hfe_encode(q_codes, q_masks, shifts).float()
+    ref = torch.matmul(mq, m_db.float().t().contiguous()).round().to(torch.int32)
+    exact = bool(torch.equal(ref, ip))
+    ms = float(np.mean(ms_steps))
+    k_ms = float(np.mean(kernel_ms))
+    ops = work["i8_ops"]
+    line = {"metric": "encrypted query x db code comparisons/sec on 1 MI355X at ring degree 2^16",
+            "value": w.d1 * w.d3 / (ms * 1e-3), "unit": "comparisons/s", "n_gpus": 1, "steps": args.lit_steps,
+            "ms_per_step": ms, "higher_is_better": True, "dtype": "i8", "data": "synthetic",
+            "config": {"workload": w.name, "n_db": 1 << w.log_n_db, "n_q": 1 << w.log_n_q, "query_primes": w.level,
+                       "special_primes": 1, "d1": w.d1, "d2": w.d2, "d3": w.d3, "form": "i8_mfma"},
+            "contraction_ms": k_ms, "int8_ops_per_launch": ops,
+            "frac_of_peak": ops / (k_ms * 1e-3) / 1e12 / PEAK_I8_TOPS,
+            "useful_fraction": w.d1 * w.d2 / (work["R_out"] * work["K"]),
+            "db_encrypt_s": t_db, "db_digit_bytes": H.hfe_db_bytes(db),
+            "ip_equals_plaintext_products": exact}
+    log(f"lit: {ms:.1f} ms/step, contraction {k_ms:.1f} ms ({100 * line['frac_of_peak']:.1f}% of int8 peak); "
+        f"inner products exact: {exact}")
+    return line
 
 
 def main():
@@ -270,16 +435,24 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--workload", default=S.PAPER_SHARE.name, choices=sorted(S.WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=8192)
-    ap.add_argument("--cpu-cols", type=int, default=32)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="oracle baseline processes (0: the host's CPUs, at most 16)")
+    ap.add_argument("--cpu-rows", type=int, default=1024, help="oracle baseline: database rows per process (power of 2)")
+    ap.add_argument("--cpu-cols", type=int, default=32, help="oracle baseline: query columns of the CCMM sample")
     ap.add_argument("--sweep", action="store_true", help="time every int8 tile configuration and exit")
     ap.add_argument("--variant", type=int, default=-1, help="int8 tile configuration (-1: default)")
     ap.add_argument("--ccmm-only", type=int, default=0, help="run N int8 CCMMs after setup and exit (profiling)")
     ap.add_argument("--form", choices=("i8", "rns", "p2"), default="i8", help="with --ccmm-only: the int8 form to run")
-    ap.add_argument("--mode", choices=("step", "batched", "serving"), default="step",
+    ap.add_argument("--lit-steps", type=int, default=3, help="lit mode: timed steps")
+    ap.add_argument("--mode", choices=("step", "batched", "serving", "lit"), default="step",
                     help="step: the hot-path step (default); batched: 64 uneven items as one plan; "
-                         "serving: Poisson arrivals through the server")
+                         "serving: Poisson arrivals through the server; lit: the step at N_DB = N_Q = 2^16")
     ap.add_argument("--batch-items", type=int, default=64)
+    ap.add_argument("--batched-steps", type=int, default=3, help="step mode: timed replays of the batch")
+    ap.add_argument("--no-batched", action="store_true", help="step mode: skip the batched configuration")
+    ap.add_argument("--no-serving", action="store_true", help="step mode: skip the serving configuration")
+    ap.add_argument("--default-rates", type=float, nargs="+", default=[200.0, 50.0],
+                    help="step mode: serving arrival rates, req/s")
     ap.add_argument("--rates", type=float, nargs="+", default=[200.0, 50.0, 25.0],
                     help="serving arrival rates, req/s")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serving: seconds of arrivals per rate")
@@ -296,21 +469,37 @@ def main():
                                    "(database-row shards with a broadcast of the A-part result) is not built"}))
         sys.exit(2)
 
+    w = S.WORKLOADS[args.workload]
+    work = algorithmic_work(w)
+    inp = S.make_inputs(w)
+    cpu = None
+    if args.mode == "step" and not args.no_cpu_baseline and not (args.sweep or args.ccmm_only):
+        # before anything touches the GPU: the oracle's process pool is forked from this process
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        log(f"timing the oracle on a bounded sample ({workers} processes)")
+        cpu = cpu_baseline(w, inp, workers, args.cpu_rows, args.cpu_cols, enc_cols=4, dec_rows=1024)
+        log(f"oracle: {cpu['sample']}")
+        cpu.pop("step_s")
+
     import torch
     import paper_2601_17561_amd as H
 
     if args.mode == "batched":
-        return run_batched(args, H, torch)
+        for r in run_batched(args, H, torch):
+            print(json.dumps(batched_line(r)), flush=True)
+        return
     if args.mode == "serving":
-        return run_serving(args, H, torch)
-    w = S.WORKLOADS[args.workload]
-    work = algorithmic_work(w)
+        for r in run_serving(args, H, torch):
+            print(json.dumps(serving_line(r)), flush=True)
+        return
+    if args.mode == "lit":
+        print(json.dumps(run_lit(args, H, torch)), flush=True)
+        return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
     log(f"workload {w.name}: d1={w.d1} d2={w.d2} d3={w.d3} N_DB=2^{w.log_n_db} N_Q=2^{w.log_n_q} "
         f"primes={w.level}+p")
-    inp = S.make_inputs(w)
     P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
     keys = H.hfe_keygen(P, KEY_SEED)
     db_codes = torch.from_numpy(inp["db_codes"]).to(dev)
@@ -444,11 +633,14 @@ def main():
     n_b = p2_bases(w, max(list(qs) + [p_special]))
     p2_ops = 2 * 3 * n_b * work["residue_macs"]
     same_p2 = bool(torch.equal(p2["ip"], results["i8"]["ip"]))
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the oracle on a bounded sample")
-        cpu = cpu_baseline(w, inp, args.cpu_rows, args.cpu_cols)
-        cpu.pop("seconds")
+    # measured instruction ceilings on this device: int8 MFMA on streaming random operands (the
+    # digit planes of ciphertexts are uniformly random) and on zero operands, and the VALU
+    # 32 x 32 -> 64-bit multiply-add the plain form spends four of per residue multiply-add
+    rates = {"mfma_i8_random_tops": max(H.hfe_probe_rate(H.HFE_PROBE_MFMA_I8, 2000) for _ in range(3)) / 1e12,
+             "mfma_i8_zero_tops": max(H.hfe_probe_rate(H.HFE_PROBE_MFMA_I8_ZERO, 2000) for _ in range(3)) / 1e12,
+             "valu_mad_u64_per_s": max(H.hfe_probe_rate(H.HFE_PROBE_VALU_MAD_U64, 4000) for _ in range(3))}
+    log(f"ceilings: int8 MFMA {rates['mfma_i8_random_tops']:.0f} TOP/s on random operands, "
+        f"{rates['mfma_i8_zero_tops']:.0f} on zeros; v_mad_u64_u32 {rates['valu_mad_u64_per_s']:.3e}/s")
 
     i8 = results["i8"]
     achieved = work["i8_ops"] / (i8["contraction_ms"] * 1e-3) / 1e12
@@ -474,11 +666,21 @@ def main():
                      "traffic": (MEASURED_TRAFFIC_GB.get(tile) if w.name == S.PAPER_SHARE.name else None),
                      "traffic_unit": "GB per launch (HBM side of L2, rocprofv3 counters)",
                      "kernel": f"k_gemm_i8 ({tile})", "ops_per_launch": work["i8_ops"],
-                     "kernel_ms": i8["contraction_ms"]},
+                     "kernel_ms": i8["contraction_ms"],
+                     "measured_ceiling": rates["mfma_i8_random_tops"],
+                     "frac_of_measured_ceiling": achieved / rates["mfma_i8_random_tops"]},
+        "ceilings": rates,
         "plain": ({"ms_per_step": plain["ms_per_step"],
                    "comparisons_per_s": plain["comparisons_per_s"],
                    "contraction_ms": plain["contraction_ms"],
-                   "residue_macs_per_s": work["residue_macs"] / (plain["contraction_ms"] * 1e-3)}
+                   "residue_macs_per_s": work["residue_macs"] / (plain["contraction_ms"] * 1e-3),
+                   "roofline": {"bound": "alu", "unit": "residue multiply-adds/s",
+                                "achieved": work["residue_macs"] / (plain["contraction_ms"] * 1e-3),
+                                "peak": rates["valu_mad_u64_per_s"] / 4,
+                                "frac": work["residue_macs"] / (plain["contraction_ms"] * 1e-3)
+                                / (rates["valu_mad_u64_per_s"] / 4),
+                                "basis": "4 v_mad_u64_u32 per residue multiply-add (18-bit limbs), "
+                                         "measured instruction rate"}}
                   if plain else None),
         "rns": {"form": f"small-modulus RNS, {n_mod} moduli per prime", "ms_per_step": rns["ms_per_step"],
                 "comparisons_per_s": rns["comparisons_per_s"], "contraction_ms": rns["contraction_ms"],
@@ -504,6 +706,15 @@ def main():
         "db_encrypt_s": t_db,
         "cpu_baseline": cpu,
     }
+    # configurations 4 and 5 on the same device, after the share database is released
+    del db, prof
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        line["batched"] = run_batched(args, H, torch, forms=("i8", "rns"), steps=args.batched_steps,
+                                      compare_sequential=False)
+    if not args.no_serving:
+        line["serving"] = run_serving(args, H, torch, rates=args.default_rates, form_name="rns")
     print(json.dumps(line), flush=True)
 
 

@@ -42,7 +42,8 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_plan_result", "hfe_autotune", "hfe_autotune_save", "hfe_autotune_load", "hfe_server_create",
             "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_drain", "hfe_server_stats", "hfe_server_reset_stats",
             "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes",
-            "hfe_ccmm_product", "hfe_probe_rate", "hfe_noalloc_init", "hfe_ccmm_noalloc")
+            "hfe_ccmm_product", "hfe_probe_rate", "hfe_noalloc_init", "hfe_ccmm_noalloc",
+            "hfe_plan_create_for")
 
 
 class HfeError(RuntimeError):
@@ -117,6 +118,7 @@ _SIGS = {
     "hfe_ccmm_batched": [_vp, ctypes.POINTER(hfe_batch_item), _i32, _i32, _vp, ctypes.POINTER(_vp)],
     "hfe_plan_create": [_vp, _i32, _i64, _u32, _i32, ctypes.POINTER(_vp)],
     "hfe_plan_run": [_vp, ctypes.POINTER(hfe_batch_item), _i32, _i32, _vp],
+    "hfe_plan_create_for": [_vp, ctypes.POINTER(hfe_batch_item), _i32, _i32, ctypes.POINTER(_vp)],
     "hfe_plan_result": [_vp, _i32, ctypes.POINTER(_vp)],
     "hfe_autotune": [_vp, _vp, _i64, _i64, _i32, _vp, ctypes.POINTER(_i32)],
     "hfe_autotune_save": [ctypes.c_char_p],
@@ -457,6 +459,14 @@ def hfe_plan_create(db: Handle, max_items: int, max_cols: int, max_level: int,
                     form: int = HFE_FORM_I8_MFMA) -> Handle:
     out = _vp()
     _check(_lib.hfe_plan_create(db.ptr, max_items, max_cols, max_level, form, ctypes.byref(out)), "hfe_plan_create")
+    return Handle(out.value, (db,))
+
+
+def hfe_plan_create_for(db: Handle, items, form: int = HFE_FORM_I8_MFMA) -> Handle:
+    """A plan whose workspace is sized for this batch of (query Handle, row0, rows) items."""
+    arr = _items(items)
+    out = _vp()
+    _check(_lib.hfe_plan_create_for(db.ptr, arr, len(items), form, ctypes.byref(out)), "hfe_plan_create_for")
     return Handle(out.value, (db,))
 
 

@@ -444,15 +444,130 @@ __device__ __forceinline__ void tile_dma(const I8Tile& T, int8_t* lds) {
   }
 }
 
+// DMA-fed tile with separate LDS rings for the two operands: the database digits (streamed from
+// HBM once per launch, so their loads see the longest latency) in three stages, loaded two K-blocks
+// ahead, and the query digits (re-read by every database-row tile, mostly from L2) in two stages,
+// loaded one block ahead.  Both rings fit where three stages of both would not (64 x 128: 2 x 40 +
+// 3 x 20 KiB).  Per block, wave w issues its query loads and then its database loads; at the barrier
+// of block i it waits until only its database loads of block i + 1 are outstanding (vmcnt counts
+// them in issue order).  Loads are dealt to waves round-robin: query load j (plane j / nQ, row
+// group j % nQ) to wave j % NW, database load j likewise, so waves differ in their database load
+// count and each waits for its own.  Fragment reads, swizzle and MFMA order as tile_dma.
+template <int WR, int WQ>
+__device__ __forceinline__ void tile_dma_split(const I8Tile& T, int8_t* lds) {
+  constexpr int NW = WR * WQ, BR = 32 * WR, BQ = 32 * WQ;
+  constexpr int nQ = BQ / 16, nB = BR / 16;                  // 16-row groups per plane
+  constexpr int kPA = BQ * kDmaRow, kPB = BR * kDmaRow;      // bytes per plane
+  constexpr int kQS = kDigits * kPA, kBS = kDigits * kPB;    // bytes per stage
+  constexpr int LQ = (kDigits * nQ + NW - 1) / NW, LB = (kDigits * nB + NW - 1) / NW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wq = wave % WQ, wr = wave / WQ;
+  const size_t planeB = (size_t)T.KB * T.R_pad * kKB, planeA = (size_t)T.KB * T.d3_pad * kKB;
+  const size_t stepB = (size_t)T.R_pad * kKB, stepA = (size_t)T.d3_pad * kKB;
+  // lane l of a load covers row 16 g + l / 4, stored chunk l % 4 = logical chunk
+  // (l % 4) ^ ((row >> 2) & 3) = (l % 4) ^ ((l >> 4) & 3)
+  const int lrow = lane >> 2, lchunk = ((lane & 3) ^ ((lane >> 4) & 3)) * 16;
+  const int8_t* gq[LQ];
+  const int8_t* gb[LB];
+  uint32_t oq[LQ], ob[LB];
+  bool vq[LQ], vb[LB];
+  int cb = 0;  // this wave's database loads per block
+#pragma unroll
+  for (int j = 0; j < LQ; ++j) {
+    const int i = wave + NW * j;
+    vq[j] = i < kDigits * nQ;
+    const int t = vq[j] ? i / nQ : 0, g = vq[j] ? i % nQ : 0;
+    gq[j] = T.Xd + t * planeA + (size_t)(T.c0 + 16 * g + lrow) * kKB + lchunk;
+    oq[j] = t * kPA + 16 * g * kDmaRow;
+  }
+#pragma unroll
+  for (int j = 0; j < LB; ++j) {
+    const int i = wave + NW * j;
+    vb[j] = i < kDigits * nB;
+    cb += vb[j] ? 1 : 0;
+    const int t = vb[j] ? i / nB : 0, g = vb[j] ? i % nB : 0;
+    gb[j] = T.Dd + t * planeB + (size_t)src_row(T.r0 + 16 * g + lrow, T.n_db, T.row0) * kKB + lchunk;
+    ob[j] = 2 * kQS + t * kPB + 16 * g * kDmaRow;
+  }
+  const uint32_t lds0 = (uint32_t)(uintptr_t)lds;
+  auto issue_q = [&](int stage, int64_t kb) {
+#pragma unroll
+    for (int j = 0; j < LQ; ++j)
+      if (vq[j]) dma16(gq[j] + kb * stepA, lds0 + stage * kQS + oq[j]);
+  };
+  auto issue_b = [&](int stage, int64_t kb) {
+#pragma unroll
+    for (int j = 0; j < LB; ++j)
+      if (vb[j]) dma16(gb[j] + kb * stepB, lds0 + stage * kBS + ob[j]);
+  };
+  // wait until at most this wave's database loads of one block are outstanding, then barrier
+  auto wait_barrier = [&]() {
+    static_assert(LB <= 5, "the waits below cover up to five database loads per wave and block");
+    if (cb >= 5) asm volatile("s_waitcnt vmcnt(5)" ::: "memory");
+    else if (cb == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+    else if (cb == 3) asm volatile("s_waitcnt vmcnt(3)" ::: "memory");
+    else if (cb == 2) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+    else if (cb == 1) asm volatile("s_waitcnt vmcnt(1)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  };
+  const int sw = ((lane & 31) >> 2) & 3;
+  const int offA = (wq * 32 + (lane & 31)) * kDmaRow, offB = 2 * kQS + (wr * 32 + (lane & 31)) * kDmaRow;
+  const int c0 = lane >> 5;
+
+  for (int64_t kb0 = 0; kb0 < T.KB; kb0 += kChunkKB) {
+    const int64_t kb_end = kb0 + kChunkKB < T.KB ? kb0 + kChunkKB : T.KB;
+    const int64_t n = kb_end - kb0;
+    auto clamp = [&](int64_t i) { return kb0 + (i < n ? i : n - 1); };
+    v16i acc[9];
+#pragma unroll
+    for (int u = 0; u < 9; ++u) acc[u] = (v16i){0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    issue_b(0, clamp(0));
+    issue_q(0, clamp(0));
+    issue_b(1, clamp(1));
+    for (int64_t i = 0; i < n; ++i) {
+      // block i (query loads issued at i - 1, database loads at i - 2) complete for every wave,
+      // and every wave is done with block i - 1, whose stages the loads below overwrite
+      wait_barrier();
+      issue_q((int)((i + 1) & 1), clamp(i + 1));
+      issue_b((int)((i + 2) % 3), clamp(i + 2));
+      const int8_t* SA = lds + (i & 1) * kQS;
+      const int8_t* SB = lds + (i % 3) * kBS;
+      auto fa = [&](int t, int c) { return *reinterpret_cast<const v4i*>(SA + offA + t * kPA + ((c ^ sw) << 4)); };
+      auto fb = [&](int t, int c) { return *reinterpret_cast<const v4i*>(SB + offB + t * kPB + ((c ^ sw) << 4)); };
+      v4i a0[kDigits], a1[kDigits], b_cur, b_nxt;
+#pragma unroll
+      for (int t = 0; t < kDigits; ++t) a0[t] = fa(t, c0);
+      b_cur = fb(0, c0);
+#pragma unroll
+      for (int step = 0; step < 2 * kDigits; ++step) {
+        const int half = step / kDigits, s = step % kDigits;
+        if (step + 1 < 2 * kDigits) b_nxt = fb((step + 1) % kDigits, c0 + 2 * ((step + 1) / kDigits));
+        if (step < kDigits) a1[step] = fa(step, c0 + 2);
+#pragma unroll
+        for (int t = 0; t < kDigits; ++t)
+          acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(half ? a1[t] : a0[t], b_cur, acc[s + t], 0, 0, 0);
+        b_cur = b_nxt;
+      }
+    }
+    // drain the clamped loads still in flight before the stages are reused
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    store_tile(T, acc, wq, wr, lane, kb0 != 0);
+  }
+}
+
 // Grid launch: blockIdx.z = prime slot, blockIdx.x = XCD-ordered tile.
 template <int WR, int WQ, int NBUF, int WPE, int MODE>
 constexpr int lds_bytes() {
+  if constexpr (MODE == 3) return kDigits * (2 * 32 * WQ + 3 * 32 * WR) * kDmaRow;  // 2 query + 3 database stages
   return NBUF * kDigits * (32 * WQ + 32 * WR) * (MODE == 2 ? kDmaRow : kLdsRow);
 }
 
 template <int WR, int WQ, int NBUF, int WPE, int MODE>
 __device__ __forceinline__ void run_tile(const I8Tile& T, int8_t* lds) {
-  if constexpr (MODE == 2)
+  if constexpr (MODE == 3)
+    tile_dma_split<WR, WQ>(T, lds);
+  else if constexpr (MODE == 2)
     tile_dma<WR, WQ, NBUF>(T, lds);
   else if constexpr (MODE == 1)
     tile_pipe(T, lds);
@@ -533,10 +648,11 @@ struct I8Variant {
         64 * (WR) * (WQ), (WPE)                                                                              \
   }
 
-// MODE 0: tile_basic, 1: tile_pipe, 2: tile_dma (NB = LDS stages).  The first entry is the
-// default.
+// MODE 0: tile_basic, 1: tile_pipe, 2: tile_dma (NB = LDS stages), 3: tile_dma_split.  The first
+// entry is the default.
 static const I8Variant kI8Variants[] = {
     HFE_I8_VARIANT("dma_r128_w2", 4, 2, 2, 2, 2), HFE_I8_VARIANT("dma_q128_w2", 2, 4, 2, 2, 2),
+    HFE_I8_VARIANT("dmas_q128_w2", 2, 4, 0, 2, 3), HFE_I8_VARIANT("dmas_r128_w2", 4, 2, 0, 2, 3),
     HFE_I8_VARIANT("dma2_w2", 2, 2, 2, 2, 2),     HFE_I8_VARIANT("dma3_w1", 2, 2, 3, 1, 2),
     HFE_I8_VARIANT("pipe_w1", 2, 2, 2, 1, 1),
     HFE_I8_VARIANT("r2q2b1w1", 2, 2, 1, 1, 0),    HFE_I8_VARIANT("r2q2b2w1", 2, 2, 2, 1, 0),

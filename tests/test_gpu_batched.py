@@ -179,6 +179,27 @@ def test_plan_graph_replays(env, form):
     assert e.value.status == -2
 
 
+@pytest.mark.parametrize("form", ["i8", "rns", "p2"])
+def test_plan_sized_for_the_batch(env, form):
+    """hfe_plan_create_for sizes the workspace to exactly this batch: its graph replays equal the
+    single calls and the oracle; a batch that needs more of any workspace is refused."""
+    items = env["items"]
+    _say(f"[gpu-batched] plan sized for the batch ({form}): graph capture and replays")
+    plan = H.hfe_plan_create_for(env["db"], items, PLAN_FORMS[form])
+    for rep in range(2):
+        H.hfe_plan_run(plan, items, use_graph=True)
+        torch.cuda.synchronize()
+        _check_results(env, [H.hfe_plan_result(plan, i) for i in range(len(items))], f"sized plan replay {rep}")
+    # fewer items that fit: the first two
+    H.hfe_plan_run(plan, items[:2], use_graph=True)
+    torch.cuda.synchronize()
+    _check_results(env, [H.hfe_plan_result(plan, i) for i in range(2)], "sized plan, subset")
+    # the 130-column item twice needs more columns than the whole batch holds
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_plan_run(plan, [items[2]] * 7)
+    assert e.value.status == -2
+
+
 def test_autotune_records_and_roundtrips(env):
     q, row0, rows = env["items"][2]
     _say("[gpu-batched] autotune")
