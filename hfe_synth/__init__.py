@@ -143,6 +143,14 @@ BIG_DB = Workload("bigdb_ndb65536_nq512_L1p_d1_256_d2_1024_q4", 16, 9, 1, 1, 256
 BIG_Q = Workload("bigq_ndb512_nq65536_L1p_d1_256_d2_1024_q4", 9, 16, 1, 1, 256, 1024, 4, 1,
                  planted=(Planted(0, 17, 0, 0.1),), seed=BASE_SEED + 32)
 
+# Workloads of the n^2 modulus chain (Section 6.3): n_q_primes counts the query moduli n^2 (the
+# special part has 3 more).  Tiny: rings of 2^9, 256 codes of 512 bits, 2 eyes x 2 shifts; mid: the
+# mid workload's shapes (every tile boundary of the n^2 contraction) with the chain's moduli.
+CHAIN_TINY = Workload("chain_ndb512_nq512_L7_d1_256_d2_512_q4", 9, 9, 7, 7, 256, 512, 2, 2,
+                      planted=(Planted(0, 17, 0, 0.1),), seed=BASE_SEED + 41)
+CHAIN_MID = Workload("chain_ndb256_nq512_L7_d1_700_d2_1280_q272", 8, 9, 7, 7, 700, 1280, 17, 16,
+                     seed=BASE_SEED + 42)
+
 # The share workload with both ring degrees at 2^16 (the configuration's literal N): the same
 # templates (same seed), K = 12,800 + 2^16 and 2^16 + 14,336 output rows.
 PAPER_LIT = dataclasses.replace(PAPER_SHARE, name="lit_ndb65536_nq65536_L3p_d1_14336_d2_12800_q512",
@@ -191,7 +199,7 @@ def random_eyes(seed: int, stream: int, n_eyes: int, d2: int, p_code: float = 0.
 
 
 WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, MID, PAPER_SHARE, PAPER_SHARE_L5, BIG_DB,
-                                                      BIG_Q, PAPER_LIT)}
+                                                      BIG_Q, PAPER_LIT, CHAIN_TINY, CHAIN_MID)}
 
 
 def planted_for(w: Workload, count: int = 4) -> Tuple[Planted, ...]:

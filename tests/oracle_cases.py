@@ -11,6 +11,7 @@ from typing import Dict
 import numpy as np
 
 import hfe_synth as S
+from oracle import chain as OCH
 from oracle import ckks as OC
 from oracle import iris as OI
 from oracle import params as OP
@@ -61,3 +62,46 @@ def case(name: str, row0: int = 0, rows: int = -1) -> Case:
     v, ip = OC.decrypt(keys, out, w.level, row0, rows)
     ip_true, ov = OI.truth(qc, qm, inp["db_codes"][row0:row0 + rows], inp["db_masks"][row0:row0 + rows])
     return Case(w, P, keys, inp, m_db, qc, qm, m_q, D, XT, row0, rows, out, v, ip, ip_true, ov)
+
+
+CHAIN_P_MODS = 3   # moduli of the chain's special part P in the test workloads
+
+
+@dataclasses.dataclass
+class ChainCase:
+    w: S.Workload
+    C: OCH.ChainParams
+    keys: OC.Keys
+    inputs: Dict
+    m_db: np.ndarray
+    q_codes: np.ndarray
+    q_masks: np.ndarray
+    m_q: np.ndarray
+    D: Dict[int, np.ndarray]
+    XT: Dict[int, np.ndarray]
+    level: int
+    out: Dict[int, np.ndarray]
+    v: list
+    ip: np.ndarray
+    ip_true: np.ndarray
+    overlap: np.ndarray
+
+
+@functools.lru_cache(maxsize=None)
+def chain_case(name: str, level: int = -1) -> ChainCase:
+    """The oracle end to end over the n^2 modulus chain (query moduli: the workload's n_q_primes;
+    special part: CHAIN_P_MODS), at `level` query moduli (default: all)."""
+    w = S.WORKLOADS[name]
+    C = OCH.make_chain_params(w.log_n_db, w.log_n_q, w.n_q_primes, CHAIN_P_MODS, w.d2, w.d1)
+    level = w.n_q_primes if level < 0 else level
+    inp = S.make_inputs(w)
+    keys = OCH.chain_keygen(C, KEY_SEED)
+    m_db = OI.ternary(inp["db_codes"], inp["db_masks"])
+    qc, qm = OI.shifted_queries(inp["q_codes"], inp["q_masks"], inp["shifts"])
+    m_q = OI.ternary(qc, qm)
+    D = OCH.encrypt_db(C, keys, m_db, DB_SEED)
+    XT = OCH.encrypt_query(C, keys, m_q, level, Q_SEED)
+    out = OCH.ccmm(C, D, XT, level, 0, w.d1)
+    v, ip = OCH.decrypt(C, keys, out, level, 0, w.d1)
+    ip_true, ov = OI.truth(qc, qm, inp["db_codes"], inp["db_masks"])
+    return ChainCase(w, C, keys, inp, m_db, qc, qm, m_q, D, XT, level, out, v, ip, ip_true, ov)
