@@ -442,8 +442,10 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="time every int8 tile configuration and exit")
     ap.add_argument("--variant", type=int, default=-1, help="int8 tile configuration (-1: default)")
     ap.add_argument("--ccmm-only", type=int, default=0, help="run N int8 CCMMs after setup and exit (profiling)")
-    ap.add_argument("--form", choices=("i8", "rns", "p2"), default="i8", help="with --ccmm-only: the int8 form to run")
+    ap.add_argument("--form", choices=("i8", "rns", "p2", "chain"), default="i8",
+                    help="with --ccmm-only: the int8 form to run (chain: the n^2 modulus chain)")
     ap.add_argument("--lit-steps", type=int, default=3, help="lit mode: timed steps")
+    ap.add_argument("--chain-q-mods", type=int, default=7, help="n^2 chain: query moduli (3 more form P)")
     ap.add_argument("--mode", choices=("step", "batched", "serving", "lit"), default="step",
                     help="step: the hot-path step (default); batched: 64 uneven items as one plan; "
                          "serving: Poisson arrivals through the server; lit: the step at N_DB = N_Q = 2^16")
@@ -517,18 +519,36 @@ def main():
     del m_db
     log(f"database encrypted in {t_db:.2f} s")
 
+    chain_kd = {}
+    # the paper's own modulus chain (Section 6.3): query moduli n^2 for the largest primes n <= 253 (as
+    # many as give Q about the bits of the level's 36-bit primes), 3 more for P; the same secrets
+    chain_q = args.chain_q_mods
+    Cp = H.hfe_chain_default_params(w.log_n_db, w.log_n_q, chain_q, 3, w.d2, w.d1)
+    chain_kd["keys"] = H.hfe_chain_keygen(Cp, KEY_SEED)
+    chain_kd["level"] = chain_q
+    m_db = H.hfe_encode(db_codes, db_masks, [0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chain_kd["db"] = H.hfe_encrypt_db(chain_kd["keys"], m_db, DB_SEED, H.HFE_FORM_P2_I8)
+    torch.cuda.synchronize()
+    t_chain_db = time.perf_counter() - t0
+    del m_db
+    log(f"n^2 chain: {chain_q} query moduli + 3 special ({Cp.q_bases()} | {Cp.p_bases()}), database in "
+        f"{t_chain_db:.2f} s")
+
     def step(form, profile_out=None, marks=None):
         # marks: 6 events recorded on the stream the library runs on (torch's current stream)
         # around encode, encrypt, CCMM, decrypt and match
         mark = (lambda i: marks[i].record()) if marks is not None else (lambda i: None)
+        k_, db_, lvl = (chain_kd["keys"], chain_kd["db"], chain_kd["level"]) if form == "chain" else (keys, db, w.level)
         mark(0)
         m_q = H.hfe_encode(q_codes, q_masks, shifts)
         mark(1)
-        qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+        qct = H.hfe_encrypt(k_, m_q, lvl, Q_SEED)
         mark(2)
-        r = H.hfe_ccmm(db, qct, 0, w.d1, form)
+        r = H.hfe_ccmm(db_, qct, 0, w.d1, H.HFE_FORM_P2_I8 if form == "chain" else form)
         mark(3)
-        _, ip = H.hfe_decrypt(keys, r, v=False)
+        _, ip = H.hfe_decrypt(k_, r, v=False)
         mark(4)
         _, eye = H.hfe_match(ip, q_masks, shifts, db_masks, want_decision=False)
         mark(5)
@@ -554,8 +574,12 @@ def main():
         m_q = H.hfe_encode(q_codes, q_masks, shifts)
         qct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
         form = {"rns": H.HFE_FORM_RNS_I8, "p2": H.HFE_FORM_P2_I8}.get(args.form, H.HFE_FORM_I8_MFMA)
+        db_ = db
+        if args.form == "chain":
+            qct = H.hfe_encrypt(chain_kd["keys"], m_q, chain_kd["level"], Q_SEED)
+            form, db_ = H.HFE_FORM_P2_I8, chain_kd["db"]
         for _ in range(args.ccmm_only):
-            H.hfe_ccmm(db, qct, 0, w.d1, form).free()
+            H.hfe_ccmm(db_, qct, 0, w.d1, form).free()
         torch.cuda.synchronize()
         log(f"ran {args.ccmm_only} int8 CCMMs")
         if args.copy_mib:
@@ -591,6 +615,7 @@ def main():
     for name, form, steps, warm in (("i8", H.HFE_FORM_I8_MFMA, args.steps, args.warmup),
                                     ("rns", H.HFE_FORM_RNS_I8, args.steps, args.warmup),
                                     ("p2", H.HFE_FORM_P2_I8, args.steps, args.warmup),
+                                    ("chain", "chain", args.steps, args.warmup),
                                     ("plain", H.HFE_FORM_PLAIN_U64, args.plain_steps, 1)):
         if steps <= 0:
             continue
@@ -633,6 +658,12 @@ def main():
     n_b = p2_bases(w, max(list(qs) + [p_special]))
     p2_ops = 2 * 3 * n_b * work["residue_macs"]
     same_p2 = bool(torch.equal(p2["ip"], results["i8"]["ip"]))
+    same_chain = bool(torch.equal(results["chain"]["ip"], results["i8"]["ip"]))
+    chain_slots = chain_q + 3
+    chain_ops = 2 * 3 * chain_slots * work["R_out"] * work["K"] * w.d3
+    import math
+    chain_q_bits = sum(2 * math.log2(n) for n in Cp.q_bases())
+    chain_p_bits = sum(2 * math.log2(n) for n in Cp.p_bases())
     # measured instruction ceilings on this device: int8 MFMA on streaming random operands (the
     # digit planes of ciphertexts are uniformly random) and on zero operands, and the VALU
     # 32 x 32 -> 64-bit multiply-add the plain form spends four of per residue multiply-add
@@ -698,6 +729,18 @@ def main():
                "frac_of_peak": p2_ops / (p2["contraction_ms"] * 1e-3) / 1e12 / PEAK_I8_TOPS,
                "over_i8_step": i8["ms_per_step"] / p2["ms_per_step"], "equals_i8_ip": same_p2,
                "phases_ms": p2["phases_ms"]},
+        "chain": {"form": f"the paper's n^2 modulus chain: {chain_q} query moduli n^2 ({Cp.q_bases()}), P of 3 "
+                          f"({Cp.p_bases()}), 3 int8 products per modulus, no integer rebuilt",
+                  "ms_per_step": results["chain"]["ms_per_step"],
+                  "comparisons_per_s": results["chain"]["comparisons_per_s"],
+                  "contraction_ms": results["chain"]["contraction_ms"], "lift_ms": results["chain"]["lift_ms"],
+                  "rescale_ms": results["chain"]["rescale_ms"],
+                  "int8_ops_per_launch": chain_ops,
+                  "frac_of_peak": chain_ops / (results["chain"]["contraction_ms"] * 1e-3) / 1e12 / PEAK_I8_TOPS,
+                  "Q_bits": chain_q_bits, "P_bits": chain_p_bits, "db_encrypt_s": t_chain_db,
+                  "over_i8_step": i8["ms_per_step"] / results["chain"]["ms_per_step"],
+                  "over_rns_step": rns["ms_per_step"] / results["chain"]["ms_per_step"],
+                  "equals_i8_ip": same_chain, "phases_ms": results["chain"]["phases_ms"]},
         "i8_over_plain_step": plain["ms_per_step"] / i8["ms_per_step"] if plain else None,
         "stages_ms": {"lift_split": i8["lift_ms"], "contraction": i8["contraction_ms"],
                       "contraction_median": i8["contraction_median_ms"], "rescale": i8["rescale_ms"]},
@@ -706,8 +749,10 @@ def main():
         "db_encrypt_s": t_db,
         "cpu_baseline": cpu,
     }
-    # configurations 4 and 5 on the same device, after the share database is released
+    # configurations 4 and 5 on the same device, after the share databases are released
     del db, prof
+    chain_kd.pop("db")
+    chain_kd.clear()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     if not args.no_batched:

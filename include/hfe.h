@@ -115,6 +115,43 @@ hfe_status hfe_default_params(uint32_t log_n_db, uint32_t log_n_q, uint32_t n_q_
  * drawn from the Philox4x64-10 streams keyed by `seed`.  Synchronous. */
 hfe_status hfe_keygen(const hfe_params* params, uint64_t seed, hfe_keys** out);
 
+/* The paper's own modulus chain (Section 6.3, "Fast PPMM using int8 cuBLAS"): the ciphertext
+ * modulus is a product of squares n^2 of primes 127 <= n <= 253, so a product modulo it is a product
+ * modulo each n^2, three int8 MFMA products of the digits M + n M' (|M|, |M'| <= 126), with no exact
+ * integer to rebuild.  Query modulus Q_l = n_0^2 ... n_{l-1}^2 (l <= n_q_mods); special part
+ * P = the product of the next n_p_mods squares, the database scale and the rescale divisor
+ * (RS_P(x) = floor(x / P + 1/2) mod Q_l; P odd); database modulus Q P.  The secrets, the ring degrees
+ * and the scale Delta_l = 2^(floor(log2 Q_l) - gap_bits) are as for the prime family; products with
+ * the ternary secrets are exact integers (at most N n^2 / 2 in magnitude) computed through the NTT
+ * modulo ntt_prime.  Keys from hfe_chain_keygen work with hfe_encrypt_db (forms HFE_FORM_P2_I8, plus
+ * HFE_FORM_PLAIN_U64 to keep the residues for hfe_export: [modulus: query bases, then the special
+ * part's][column][row], each mod its n^2), hfe_encrypt, hfe_ccmm and hfe_ccmm_noalloc (form
+ * HFE_FORM_P2_I8; needs d2 + N_Q <= 2^16), hfe_ccmm_product (C: (level + n_p_mods) x d3 x (N_DB + rows)
+ * residues, the level's query moduli then the special ones), hfe_decrypt, hfe_match, hfe_export and
+ * hfe_shape; batches, plans, the server, the autotuner and database files refuse them (HFE_EINVAL).
+ * Result residues are mod n_j^2 in the order [j < level][column][A_out | B_out]. */
+#define HFE_CHAIN_MAX_BASES 11
+typedef struct {
+  uint32_t log_n_db, log_n_q;       /* ring degrees, 1..16 each                                  */
+  uint32_t n_q_mods;                /* query moduli, 1..8                                        */
+  uint32_t n_p_mods;                /* special moduli, 1..3                                      */
+  uint32_t bases[HFE_CHAIN_MAX_BASES]; /* n: the query bases, then the special part's; distinct  */
+                                    /* primes in [127, 253]                                      */
+  uint64_t ntt_prime;               /* prime < 2^36, = 1 mod 2N, for the secret products         */
+  uint32_t gap_bits;                /* Delta_l = 2^(floor(log2 Q_l) - gap_bits)                  */
+  uint32_t d2, max_db_rows;         /* code length; largest d1 the keys cover                    */
+  uint32_t t_num, t_den;            /* match threshold                                           */
+} hfe_chain_params;
+/* Defaults: the largest primes of the range first (query bases), the next ones for P; ntt_prime
+ * the largest prime < 2^36 that is 1 mod 2^17; gap 20; threshold 3/8. */
+hfe_status hfe_chain_default_params(uint32_t log_n_db, uint32_t log_n_q, uint32_t n_q_mods, uint32_t n_p_mods,
+                                    uint32_t d2, uint32_t max_db_rows, hfe_chain_params* out);
+/* Key generation for the chain: the same ternary secrets as hfe_keygen with the same seed.
+ * HFE_EINVAL for parameters outside the ranges above; HFE_EOVERFLOW as hfe_keygen for d2 against
+ * gap_bits.  A level whose Q_l has fewer than gap_bits + 2 bits is refused by hfe_encrypt
+ * (HFE_ELEVEL). */
+hfe_status hfe_chain_keygen(const hfe_chain_params* params, uint64_t seed, hfe_keys** out);
+
 /* Masked ternary encoding (Section 2.1.3) with cyclic shifts (Section 2.1.2):
  * out[(e * n_shifts + s) * d2 + t] = m' - 2 (c' AND m') with c' = code row e and m' = mask
  * row e, both rolled by shifts[s] (rolled[t] = x[(t - shifts[s]) mod d2]).

@@ -43,7 +43,7 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_drain", "hfe_server_stats", "hfe_server_reset_stats",
             "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes",
             "hfe_ccmm_product", "hfe_probe_rate", "hfe_noalloc_init", "hfe_ccmm_noalloc",
-            "hfe_plan_create_for")
+            "hfe_plan_create_for", "hfe_chain_default_params", "hfe_chain_keygen")
 
 
 class HfeError(RuntimeError):
@@ -60,6 +60,22 @@ class hfe_params(ctypes.Structure):
 
     def primes(self):
         return [int(self.q[i]) for i in range(self.n_q_primes)], int(self.p)
+
+
+HFE_CHAIN_MAX_BASES = 11
+
+
+class hfe_chain_params(ctypes.Structure):
+    _fields_ = [("log_n_db", ctypes.c_uint32), ("log_n_q", ctypes.c_uint32), ("n_q_mods", ctypes.c_uint32),
+                ("n_p_mods", ctypes.c_uint32), ("bases", ctypes.c_uint32 * HFE_CHAIN_MAX_BASES),
+                ("ntt_prime", ctypes.c_uint64), ("gap_bits", ctypes.c_uint32), ("d2", ctypes.c_uint32),
+                ("max_db_rows", ctypes.c_uint32), ("t_num", ctypes.c_uint32), ("t_den", ctypes.c_uint32)]
+
+    def q_bases(self):
+        return [int(self.bases[i]) for i in range(self.n_q_mods)]
+
+    def p_bases(self):
+        return [int(self.bases[self.n_q_mods + i]) for i in range(self.n_p_mods)]
 
 
 class hfe_batch_item(ctypes.Structure):
@@ -94,6 +110,8 @@ _SIGS = {
     "hfe_set_allocator": [_ALLOC_FN, _DEALLOC_FN, _vp],
     "hfe_default_params": [_u32, _u32, _u32, _u32, _u32, ctypes.POINTER(hfe_params)],
     "hfe_keygen": [ctypes.POINTER(hfe_params), _u64, ctypes.POINTER(_vp)],
+    "hfe_chain_default_params": [_u32, _u32, _u32, _u32, _u32, _u32, ctypes.POINTER(hfe_chain_params)],
+    "hfe_chain_keygen": [ctypes.POINTER(hfe_chain_params), _u64, ctypes.POINTER(_vp)],
     "hfe_encode": [_vp, _vp, _i64, _i32, ctypes.POINTER(_i32), _i32, _vp, _vp],
     "hfe_encrypt_db": [_vp, _vp, _i64, _u64, _u32, _vp, ctypes.POINTER(_vp)],
     "hfe_encrypt": [_vp, _vp, _i64, _u32, _u64, _vp, ctypes.POINTER(_vp)],
@@ -271,6 +289,20 @@ def hfe_keygen(params: hfe_params, seed: int) -> Handle:
     return Handle(out.value)
 
 
+def hfe_chain_default_params(log_n_db: int, log_n_q: int, n_q_mods: int, n_p_mods: int, d2: int,
+                             max_db_rows: int) -> hfe_chain_params:
+    C = hfe_chain_params()
+    _check(_lib.hfe_chain_default_params(log_n_db, log_n_q, n_q_mods, n_p_mods, d2, max_db_rows, ctypes.byref(C)),
+           "hfe_chain_default_params")
+    return C
+
+
+def hfe_chain_keygen(params: hfe_chain_params, seed: int) -> Handle:
+    out = _vp()
+    _check(_lib.hfe_chain_keygen(ctypes.byref(params), seed, ctypes.byref(out)), "hfe_chain_keygen")
+    return Handle(out.value)
+
+
 def hfe_encode(codes, masks, shifts: Sequence[int], out=None, stream=None):
     """codes, masks: uint8 (n x d2) GPU tensors; returns int8 ((n * len(shifts)) x d2)."""
     torch = _torch()
@@ -329,7 +361,7 @@ def hfe_ccmm(db: Handle, q: Handle, row0: int, rows: int, form: int, stream=None
 
 def hfe_ccmm_product(db: Handle, q: Handle, row0: int, rows: int, form: int, C=None, stream=None):
     """The exact product before the rescale: uint64 GPU tensor ((level + 1) x d3 x (N_DB + rows)),
-    viewed as int64 (residues < 2^36)."""
+    viewed as int64 (residues < 2^36).  For the n^2 chain pass C of (level + n_p_mods) rows."""
     torch = _torch()
     level, d3, _, _ = hfe_shape(q)
     n_db = hfe_shape(db)[2] - hfe_shape(db)[1]

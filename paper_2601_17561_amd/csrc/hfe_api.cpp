@@ -32,6 +32,8 @@ static hfe_status hip_fail(hipError_t e, const char* what) {
               std::string(what) + ": " + hipGetErrorString(e));
 }
 
+static hfe_status hip_ok_or_fail(hipError_t e) { return e == hipSuccess ? HFE_OK : hip_fail(e, "launch"); }
+
 #define HFE_LAUNCH(expr)                              \
   do {                                                \
     hipError_t _e = (expr);                           \
@@ -126,28 +128,36 @@ uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a 
 // floor(log2(q_0 ... q_{l-1})) - gap
 int delta_log(const hfe_keys* k, int level) {
   Big Q(1);
-  for (int i = 0; i < level; ++i) Q.mul(k->primes[i]);
+  for (int i = 0; i < level; ++i) Q.mul(k->family ? k->cmod[i].q : k->primes[i]);
   return Q.bit_length() - 1 - (int)k->P.gap_bits;
 }
 
-void garner_consts(const hfe_keys* k, int level, uint64_t garner[HFE_MAX_QPRIMES][HFE_MAX_QPRIMES],
-                   uint64_t* half_digits) {
+// The n^2 chain: random-stream id of the modulus n^2 (the prime family uses 0..8 and 16).
+uint32_t chain_stream(int32_t n) { return 256u + (uint32_t)n; }
+
+// Garner constants of the moduli q[0..level) (pairwise coprime) and the mixed-radix digits of (Q - 1) / 2.
+void garner_consts_of(const uint64_t* q, int level, uint64_t garner[HFE_MAX_QPRIMES][HFE_MAX_QPRIMES],
+                      uint64_t* half_digits) {
   for (int i = 0; i < level; ++i) {
-    const uint64_t qi = k->primes[i];
+    const uint64_t qi = q[i];
     uint64_t prod = 1 % qi;
     for (int j = 0; j < i; ++j) {
       garner[i][j] = prod;  // q_0..q_{j-1} mod q_i
-      prod = mulmod(prod, k->primes[j] % qi, qi);
+      prod = mulmod(prod, q[j] % qi, qi);
     }
     garner[i][i] = inv_mod(prod, qi);
   }
   // mixed-radix digits of (Q - 1) / 2: halve (q_0 - 1, ..., q_{l-1} - 1) from the top digit
   uint64_t carry = 0;
   for (int i = level - 1; i >= 0; --i) {
-    const u128 cur = (u128)(k->primes[i] - 1) + (u128)carry * k->primes[i];
+    const u128 cur = (u128)(q[i] - 1) + (u128)carry * q[i];
     half_digits[i] = (uint64_t)(cur / 2);
     carry = (uint64_t)(cur % 2);
   }
+}
+void garner_consts(const hfe_keys* k, int level, uint64_t garner[HFE_MAX_QPRIMES][HFE_MAX_QPRIMES],
+                   uint64_t* half_digits) {
+  garner_consts_of(k->primes, level, garner, half_digits);
 }
 }  // namespace
 
@@ -363,6 +373,84 @@ hfe_status hfe_keygen(const hfe_params* params, uint64_t seed, hfe_keys** out) {
 }
 
 // ------------------------------------------------------------------ encode
+hfe_status hfe_chain_default_params(uint32_t log_n_db, uint32_t log_n_q, uint32_t n_q_mods, uint32_t n_p_mods,
+                                    uint32_t d2, uint32_t max_db_rows, hfe_chain_params* out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  if (n_q_mods < 1 || n_q_mods > HFE_MAX_QPRIMES || n_p_mods < 1 || n_p_mods > (uint32_t)kChainMaxP)
+    return fail(HFE_EINVAL, "n_q_mods must be 1..8 and n_p_mods 1..3");
+  hfe_chain_params C;
+  std::memset(&C, 0, sizeof(C));
+  C.log_n_db = log_n_db;
+  C.log_n_q = log_n_q;
+  C.n_q_mods = n_q_mods;
+  C.n_p_mods = n_p_mods;
+  uint32_t k = 0;
+  for (uint32_t n = 253; n >= 127 && k < n_q_mods + n_p_mods; --n)
+    if (is_prime_u64(n)) C.bases[k++] = n;
+  const uint64_t step = 1ull << 17;
+  uint64_t c = ((1ull << 36) - 1) / step * step + 1;
+  while (!is_prime_u64(c)) c -= step;
+  C.ntt_prime = c;
+  C.gap_bits = 20;
+  C.d2 = d2;
+  C.max_db_rows = max_db_rows;
+  C.t_num = 3;
+  C.t_den = 8;
+  *out = C;
+  return HFE_OK;
+}
+
+hfe_status hfe_chain_keygen(const hfe_chain_params* C, uint64_t seed, hfe_keys** out) {
+  if (!out) return fail(HFE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!C) return fail(HFE_EINVAL, "params is NULL");
+  if (C->n_q_mods < 1 || C->n_q_mods > HFE_MAX_QPRIMES || C->n_p_mods < 1 || C->n_p_mods > (uint32_t)kChainMaxP)
+    return fail(HFE_EINVAL, "n_q_mods must be 1..8 and n_p_mods 1..3");
+  const int nm = (int)(C->n_q_mods + C->n_p_mods);
+  for (int i = 0; i < nm; ++i) {
+    const uint32_t n = C->bases[i];
+    if (n < 127 || n > 253 || !is_prime_u64(n)) return fail(HFE_EINVAL, "chain bases must be primes in [127, 253]");
+    for (int j = 0; j < i; ++j)
+      if (C->bases[j] == n) return fail(HFE_EINVAL, "chain bases must be distinct");
+  }
+  // the secrets and the tables of the NTT prime come from the prime family's key generation, with
+  // the NTT prime as q_0 and another prime = 1 mod 2^17 as p (its tables are not used)
+  hfe_params P;
+  std::memset(&P, 0, sizeof(P));
+  P.log_n_db = C->log_n_db;
+  P.log_n_q = C->log_n_q;
+  P.n_q_primes = 1;
+  P.q[0] = C->ntt_prime;
+  const uint64_t step = 1ull << 17;
+  uint64_t c = ((1ull << 36) - 1) / step * step + 1;
+  while (c == C->ntt_prime || !is_prime_u64(c)) c -= step;
+  P.p = c;
+  P.gap_bits = C->gap_bits;
+  P.d2 = C->d2;
+  P.max_db_rows = C->max_db_rows;
+  P.t_num = C->t_num;
+  P.t_den = C->t_den;
+  HFE_TRY(check_params(&P));
+  hfe_keys* K = new (std::nothrow) hfe_keys();
+  if (!K) return fail(HFE_ENOMEM, "host allocation failed");
+  hfe_status st = keygen_impl(&P, seed, K);
+  if (st != HFE_OK) {
+    delete K;
+    return st;
+  }
+  K->family = 1;
+  K->cq = (int)C->n_q_mods;
+  K->cp = (int)C->n_p_mods;
+  K->cP = 1;
+  for (int i = 0; i < nm; ++i) {
+    K->cbase[i] = (int32_t)C->bases[i];
+    K->cmod[i] = make_mod((uint64_t)C->bases[i] * C->bases[i]);
+    if (i >= K->cq) K->cP *= K->cmod[i].q;
+  }
+  *out = K;
+  return HFE_OK;
+}
+
 hfe_status hfe_encode(const uint8_t* codes, const uint8_t* masks, int64_t n, int32_t d2,
                       const int32_t* shifts, int32_t n_shifts, int8_t* out, void* stream) {
   if (!codes || !masks || !shifts || !out) return fail(HFE_EINVAL, "NULL argument");
@@ -479,8 +567,70 @@ static P2CrtArgs make_p2_crt_args(const hfe_keys* K, int level, int n) {
   return ra;
 }
 
+// The database over the n^2 chain: T through the NTT prime, then for each modulus (query moduli,
+// then the special part's) the encryption with scale P and the split into that modulus' slot of
+// the n^2 planes (special moduli first).  The plain form keeps every modulus' residues.
+static hfe_status chain_encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t d1, uint64_t seed,
+                                        uint32_t forms, hipStream_t s, hfe_db* D) {
+  const hfe_params& P = K->P;
+  const int64_t ndb = 1ll << P.log_n_db, nq = 1ll << P.log_n_q;
+  if (!(forms & HFE_FORM_P2_I8) || (forms & ~(uint32_t)(HFE_FORM_P2_I8 | HFE_FORM_PLAIN_U64)))
+    return fail(HFE_EINVAL, "the n^2 modulus chain takes HFE_FORM_P2_I8 (and HFE_FORM_PLAIN_U64 to keep residues)");
+  D->kind = kDb;
+  D->stream = s;
+  D->keys = K;
+  D->d1 = d1;
+  D->R = ndb + d1;
+  D->K = (int64_t)P.d2 + nq;
+  if (D->K > (1ll << 16)) return fail(HFE_ESHAPE, "the n^2 contraction needs d2 + N_Q <= 2^16");
+  D->KB = (D->K + kKB - 1) / kKB;
+  D->R_pad = (D->R + 63) / 64 * 64 + kRowPad;
+  D->forms = forms;
+  const int nm = K->cq + K->cp;
+  D->slots_plain = nm;
+  D->slots_planes = 1;
+  D->n_p2 = nm;
+  DevBuf MT, Trow, Tt;
+  HFE_TRY(MT.alloc((size_t)P.d2 * d1, s));
+  HFE_TRY(Trow.alloc(sizeof(int32_t) * (size_t)nq * d1, s));
+  HFE_TRY(Tt.alloc(sizeof(int32_t) * (size_t)nq * d1, s));
+  HFE_LAUNCH(launch_transpose_i8(m_db, d1, P.d2, MT.as<int8_t>(), s));
+  HFE_LAUNCH(launch_db_T(m_db, d1, (int32_t)P.d2, K->sconj_hat.as<uint64_t>(), K->k, K->tab_q[0].tab,
+                         Trow.as<int32_t>(), Tt.as<int32_t>(), s));
+  const bool keep_plain = (forms & HFE_FORM_PLAIN_U64) != 0;
+  const size_t prime_elems = (size_t)D->K * D->R;
+  DevBuf one;
+  if (keep_plain)
+    HFE_TRY(D->Dt.alloc(sizeof(uint64_t) * (size_t)nm * prime_elems, s));
+  else
+    HFE_TRY(one.alloc(sizeof(uint64_t) * prime_elems, s));
+  const size_t plane = (size_t)D->KB * D->R_pad * kKB;
+  HFE_TRY(D->p2.alloc((size_t)nm * 2 * plane, s));
+  DbEncArgs a;
+  a.seed = seed;
+  a.MT = MT.as<int8_t>();
+  a.Tt = Tt.as<int32_t>();
+  a.cdt = K->cdt.as<uint64_t>();
+  a.d1 = d1;
+  a.d2 = P.d2;
+  a.K = D->K;
+  a.R = D->R;
+  a.k_db = K->k_db;
+  a.p = K->cP;
+  for (int i = 0; i < nm; ++i) {
+    uint64_t* Di = keep_plain ? D->Dt.as<uint64_t>() + (size_t)i * prime_elems : one.as<uint64_t>();
+    HFE_LAUNCH(launch_db_encrypt(a, Di, chain_stream(K->cbase[i]), K->cmod[i], K->tab_db[0].tab,
+                                 K->sdb_hat.as<uint64_t>(), s));
+    const int slot = i < K->cq ? K->cp + i : i - K->cq;
+    HFE_LAUNCH(launch_chain_split_db(Di, D->K, D->R, D->KB, D->R_pad, chain_base(K->cbase[i]),
+                                     D->p2.as<int8_t>() + (size_t)slot * 2 * plane, s));
+  }
+  return HFE_OK;
+}
+
 static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t d1, uint64_t seed,
                                   uint32_t forms, hipStream_t s, hfe_db* D) {
+  if (K->family) return chain_encrypt_db_impl(K, m_db, d1, seed, forms, s, D);
   const hfe_params& P = K->P;
   const int64_t ndb = 1ll << P.log_n_db, nq = 1ll << P.log_n_q;
   D->kind = kDb;
@@ -493,6 +643,7 @@ static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t
   D->R_pad = (D->R + 63) / 64 * 64 + kRowPad;
   D->forms = forms;
   const int np = K->n_primes;
+  D->slots_plain = D->slots_planes = np;
 
   DevBuf MT, Trow, Tt;
   HFE_TRY(MT.alloc((size_t)P.d2 * d1, s));
@@ -623,7 +774,8 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
   const hfe_keys* K = as_handle<hfe_keys>(keys, kKeys);
   if (!K || !m_q) return fail(HFE_EINVAL, "invalid keys or m_q");
   if (d3 < 1 || d3 > (1 << 20)) return fail(HFE_ESHAPE, "d3 must be 1 .. 2^20");
-  if (level < 1 || (int)level > K->L) return fail(HFE_ELEVEL, "level must be 1 .. n_q_primes");
+  if (level < 1 || (int)level > (K->family ? K->cq : K->L)) return fail(HFE_ELEVEL, "level must be 1 .. n_q_primes");
+  if (delta_log(K, (int)level) < 1) return fail(HFE_ELEVEL, "the level's modulus leaves no room for the scale");
   hipStream_t s = (hipStream_t)stream;
   const hfe_params& P = K->P;
   TernaryCheck chk;
@@ -652,10 +804,14 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
   a.k = K->k;
   const int dl = delta_log(K, (int)level);
   for (uint32_t i = 0; i < level; ++i) {
-    const uint64_t delta_mod = pow_mod(2, (uint64_t)dl, K->primes[i]);
-    hipError_t e = launch_q_encrypt(a, Q->XT.as<uint64_t>() + (size_t)i * d3 * Q->K, K->prime_id[i], K->mods[i],
-                                    delta_mod, K->tab_q[i].tab,
-                                    K->s_hat.as<uint64_t>() + (size_t)i * K->k * 2 * nq, s);
+    // the n^2 chain: modulus n_i^2, products with the secrets through the NTT prime (slot 0)
+    const bool ch = K->family != 0;
+    const Mod& md = ch ? K->cmod[i] : K->mods[i];
+    const uint64_t delta_mod = pow_mod(2, (uint64_t)dl, md.q);
+    hipError_t e = launch_q_encrypt(a, Q->XT.as<uint64_t>() + (size_t)i * d3 * Q->K,
+                                    ch ? chain_stream(K->cbase[i]) : K->prime_id[i], md, delta_mod,
+                                    K->tab_q[ch ? 0 : i].tab,
+                                    K->s_hat.as<uint64_t>() + (size_t)(ch ? 0 : i) * K->k * 2 * nq, s);
     if (e != hipSuccess) {
       delete Q;
       return hip_fail(e, "launch_q_encrypt");
@@ -768,6 +924,104 @@ struct Workspace {
 // records the shape.
 // out_ext != nullptr: the result into that caller-owned buffer instead of R->out.  ws: where the
 // call's buffers come from (nullptr: the allocator).
+// The CCMM over the n^2 chain (Section 6.3): lift the query from Q_l to the special moduli and split
+// every slot into M, M'; one n^2 contraction launch over the slots [0, cp + l) (three int8 products
+// per modulus, residues mod n^2 directly); RS_P into the result [l][d3][N_DB + rows].
+static hfe_status chain_ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, int64_t rows, int32_t form,
+                                  hipStream_t s, hfe_rct* R, Workspace& W, uint64_t* out_ext, uint64_t* C_ext) {
+  const hfe_keys* K = D->keys;
+  if (form != HFE_FORM_P2_I8) return fail(HFE_EINVAL, "the n^2 modulus chain runs HFE_FORM_P2_I8");
+  const int level = Qc->level, np = K->cp, slots = np + level;
+  int64_t d3 = Qc->d3, R_out = R->R_out;
+  const int64_t ndb = 1ll << K->P.log_n_db;
+  ChainLiftArgs la;
+  std::memset(&la, 0, sizeof(la));
+  la.level = level;
+  la.np = np;
+  uint64_t qm[HFE_MAX_QPRIMES];
+  for (int j = 0; j < level; ++j) {
+    qm[j] = K->cmod[j].q;
+    la.q[j] = qm[j];
+    la.mu[j] = K->cmod[j].mu;
+  }
+  garner_consts_of(qm, level, la.garner, la.half_digits);
+  for (int t = 0; t < np; ++t) {
+    const uint64_t pm = K->cmod[K->cq + t].q;
+    la.pm[t] = pm;
+    la.pmu[t] = K->cmod[K->cq + t].mu;
+    uint64_t prod = 1 % pm;
+    for (int j = 0; j < level; ++j) {
+      la.mprod[t][j] = prod;
+      prod = mulmod(prod, qm[j] % pm, pm);
+    }
+    la.Q_mod[t] = prod;
+    la.base[t] = chain_base(K->cbase[K->cq + t]);
+  }
+  for (int j = 0; j < level; ++j) la.base[np + j] = chain_base(K->cbase[j]);
+  const int tq = p2_tile_q(&d3, &R_out, &slots, 1);
+  const int64_t d3_pad = (d3 + tq - 1) / tq * tq;
+  const size_t planeX = (size_t)D->KB * d3_pad * kKB;
+  int8_t* Xd = nullptr;
+  HFE_TRY(W.get((size_t)slots * 2 * planeX, s, &Xd));
+  uint16_t* res = nullptr;
+  HFE_TRY(W.get(sizeof(uint16_t) * (size_t)slots * d3 * R_out, s, &res));
+  if (out_ext) {
+    R->outp = out_ext;
+  } else if (!C_ext) {
+    HFE_TRY(R->out.alloc(sizeof(uint64_t) * (size_t)level * d3 * R_out, s));
+    R->outp = R->out.as<uint64_t>();
+  }
+  const bool prof = g_profile.load() != 0 && W.base == nullptr && !C_ext;
+  if (prof)
+    for (auto& e : R->ev) HFE_LAUNCH(hipEventCreate(&e));
+  auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(R->ev[i], s) : hipSuccess; };
+  HFE_LAUNCH(mark(0));
+  HFE_LAUNCH(launch_chain_lift(Qc->XT.as<uint64_t>(), d3, D->K, D->KB, d3_pad, la, Xd, s));
+  P2GemmArgs pg;
+  std::memset(&pg, 0, sizeof(pg));
+  pg.nz = 1;
+  pg.n_bases = slots;
+  pg.Dq[0] = D->p2.as<int8_t>();
+  pg.Xq[0] = Xd;
+  for (int j = 0; j < slots; ++j) {
+    pg.n[j] = la.base[j].n;
+    pg.m[j] = la.base[j].m;
+    pg.rn[j] = la.base[j].rcp_n;
+    pg.rm[j] = la.base[j].rcp_m;
+  }
+  pg.res = res;
+  pg.KB = D->KB;
+  pg.R_pad = D->R_pad;
+  pg.n_db = ndb;
+  pg.row0 = row0;
+  pg.R_out = R_out;
+  pg.d3 = d3;
+  pg.d3_pad = d3_pad;
+  HFE_LAUNCH(mark(1));
+  HFE_LAUNCH(launch_gemm_p2(pg, tq, s));
+  if (C_ext) return hip_ok_or_fail(launch_chain_widen(res, d3 * R_out, level, np, C_ext, s));
+  HFE_LAUNCH(mark(2));
+  ChainRescaleArgs ra;
+  std::memset(&ra, 0, sizeof(ra));
+  ra.level = level;
+  ra.np = np;
+  ra.P = K->cP;
+  uint64_t pre = 1;
+  for (int t = 0; t < np; ++t) {
+    ra.pm[t] = la.pm[t];
+    ra.pmu[t] = la.pmu[t];
+    ra.pinv[t] = inv_mod(pre % la.pm[t], la.pm[t]);
+    pre *= la.pm[t];
+  }
+  for (int j = 0; j < level; ++j) {
+    ra.mod[j] = K->cmod[j];
+    ra.Pinv[j] = inv_mod(K->cP % qm[j], qm[j]);
+  }
+  HFE_LAUNCH(launch_chain_rescale(res, d3 * R_out, ra, R->outp, s));
+  HFE_LAUNCH(mark(3));
+  return HFE_OK;
+}
+
 static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, int64_t rows, int32_t form,
                             hipStream_t s, hfe_rct* R, uint64_t* C_ext = nullptr, Workspace* ws = nullptr,
                             uint64_t* out_ext = nullptr) {
@@ -786,6 +1040,7 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
   R->row0 = row0;
   R->rows = rows;
   R->R_out = R_out;
+  if (K->family) return chain_ccmm_impl(D, Qc, row0, rows, form, s, R, W, out_ext, C_ext);
 
   const LiftArgs la = make_lift_args(K, level);
   const int nz = level + 1;
@@ -891,7 +1146,12 @@ static hfe_status ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t row0, in
       pg.Dq[z] = D->p2.as<int8_t>() + (size_t)slot(z) * 2 * n * planeD;
       pg.Xq[z] = Xd + (size_t)z * 2 * n * planeX;
     }
-    for (int j = 0; j < n; ++j) pg.n[j] = kP2Bases[j];
+    for (int j = 0; j < n; ++j) {
+      pg.n[j] = kP2Bases[j];
+      pg.m[j] = kP2Bases[j] * kP2Bases[j];
+      pg.rn[j] = 1.0 / (double)pg.n[j];
+      pg.rm[j] = 1.0 / (double)pg.m[j];
+    }
     pg.res = res;
     pg.KB = D->KB;
     pg.R_pad = D->R_pad;
@@ -933,7 +1193,8 @@ static hfe_status check_ccmm_args(const hfe_db* D, const hfe_qct* Qc, int64_t ro
   if (!D || !Qc) return fail(HFE_EINVAL, "invalid database or query handle");
   if (Qc->keys != D->keys) return fail(HFE_EINVAL, "database and query use different keys");
   if (Qc->K != D->K) return fail(HFE_ESHAPE, "query and database code lengths differ");
-  if (Qc->level > D->keys->L) return fail(HFE_ELEVEL, "query level above the database primes");
+  if (Qc->level > (D->keys->family ? D->keys->cq : D->keys->L))
+    return fail(HFE_ELEVEL, "query level above the database primes");
   if (row0 < 0 || rows < 1 || row0 + rows > D->d1) return fail(HFE_ESHAPE, "row range outside the database");
   if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
     return fail(HFE_EINVAL, "unknown form");
@@ -1452,6 +1713,7 @@ hfe_status hfe_ccmm_batched(const hfe_db* db, const hfe_batch_item* items, int32
                             hfe_rct** outs) {
   const hfe_db* D = as_handle<hfe_db>(db, kDb);
   if (!D || !items || !outs) return fail(HFE_EINVAL, "invalid database, items or outs");
+  if (D->keys->family) return fail(HFE_EINVAL, "batches do not run the n^2 modulus chain");
   if (n < 1 || n > kMaxBatch) return fail(HFE_EINVAL, "batch size must be 1 .. 256");
   if (form != HFE_FORM_PLAIN_U64 && form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
     return fail(HFE_EINVAL, "unknown form");
@@ -1583,6 +1845,7 @@ static hfe_status plan_alloc(const hfe_db* D, int form, int32_t max_items, int64
 
 static hfe_status check_plan_form(const hfe_db* D, int32_t form) {
   if (!D) return fail(HFE_EINVAL, "invalid database handle");
+  if (D->keys->family) return fail(HFE_EINVAL, "plans do not run the n^2 modulus chain");
   if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
     return fail(HFE_EINVAL, "plans run an int8 form");
   if (!(D->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");
@@ -1829,21 +2092,24 @@ hfe_status hfe::decrypt_impl(const hfe_keys* K, const hfe_rct* R, double* v, int
   const hfe_params& P = K->P;
   const int64_t ndb = 1ll << P.log_n_db;
   const int level = R->level;
+  const bool ch = K->family != 0;  // n^2 chain: moduli cmod, secret products through the NTT prime
   for (int i = 0; i < level; ++i)
     HFE_LAUNCH(launch_dec_products(R->outp + (size_t)i * R->d3 * R->R_out, R->d3, R->R_out, R->row0, R->rows,
-                                   (int)P.log_n_db, K->tab_db[i].tab,
-                                   K->sdb_hat.as<uint64_t>() + (size_t)i * K->k_db * 2 * ndb, K->k_db,
-                                   y + (size_t)i * R->d3 * R->rows, s));
+                                   (int)P.log_n_db, K->tab_db[ch ? 0 : i].tab,
+                                   K->sdb_hat.as<uint64_t>() + (size_t)(ch ? 0 : i) * K->k_db * 2 * ndb, K->k_db,
+                                   y + (size_t)i * R->d3 * R->rows, s, ch ? &K->cmod[i] : nullptr));
   DecodeArgs da;
   std::memset(&da, 0, sizeof(da));
   da.level = level;
+  uint64_t qs[HFE_MAX_QPRIMES];
   for (int i = 0; i < level; ++i) {
-    da.q[i] = K->primes[i];
-    da.mu[i] = K->mods[i].mu;
+    qs[i] = ch ? K->cmod[i].q : K->primes[i];
+    da.q[i] = qs[i];
+    da.mu[i] = ch ? K->cmod[i].mu : K->mods[i].mu;
   }
-  garner_consts(K, level, da.garner, da.half_digits);
+  garner_consts_of(qs, level, da.garner, da.half_digits);
   Big Q(1);
-  for (int i = 0; i < level; ++i) Q.mul(K->primes[i]);
+  for (int i = 0; i < level; ++i) Q.mul(qs[i]);
   for (size_t j = 0; j < 5 && j < Q.w.size(); ++j) da.Qw[j] = Q.w[j];
   da.delta_log = delta_log(K, level);
   HFE_LAUNCH(launch_decode(y, R->d3 * R->rows, da, v, ip, s));
@@ -1907,7 +2173,7 @@ hfe_status hfe_export(const void* handle, int32_t which, size_t offset, uint64_t
   } else if (kind == kDb) {
     const hfe_db* D = static_cast<const hfe_db*>(handle);
     if (which != 0) return fail(HFE_EINVAL, "db export: which must be 0");
-    total = (size_t)D->keys->n_primes * D->R * D->K;
+    total = (size_t)D->slots_plain * D->R * D->K;
     dev = D->Dt.ptr;
     if (dst && !dev) return fail(HFE_EINVAL, "database kept no uint64 residues (plain form not requested)");
   } else if (kind == kQct) {
@@ -1938,13 +2204,13 @@ hfe_status hfe_shape(const void* handle, int64_t* dims) {
   const uint32_t kind = static_cast<const HandleBase*>(handle)->kind;
   if (kind == kKeys) {
     const hfe_keys* K = static_cast<const hfe_keys*>(handle);
-    dims[0] = K->L;
+    dims[0] = K->family ? K->cq : K->L;
     dims[1] = K->k;
     dims[2] = K->k_db;
     dims[3] = (int64_t)K->P.d2 + (1ll << K->P.log_n_q);
   } else if (kind == kDb) {
     const hfe_db* D = static_cast<const hfe_db*>(handle);
-    dims[0] = D->keys->L;
+    dims[0] = D->keys->family ? D->keys->cq : D->keys->L;
     dims[1] = D->d1;
     dims[2] = D->R;
     dims[3] = D->K;

@@ -61,7 +61,23 @@ uint64_t pow_mod(uint64_t a, uint64_t e, uint64_t q) {
   return r;
 }
 
-uint64_t inv_mod(uint64_t a, uint64_t q) { return pow_mod(a, q - 2, q); }  // q prime
+// a^-1 mod q for gcd(a, q) = 1, any modulus q (prime or not: the n^2 chain's moduli are squares), by
+// the extended Euclidean algorithm; 0 when no inverse exists.
+uint64_t inv_mod(uint64_t a, uint64_t q) {
+  int64_t t0 = 0, t1 = 1;
+  uint64_t r0 = q, r1 = a % q;
+  while (r1) {
+    const uint64_t k = r0 / r1;
+    const uint64_t r2 = r0 - k * r1;
+    const int64_t t2 = t0 - (int64_t)k * t1;  // |t| <= q < 2^63
+    r0 = r1;
+    r1 = r2;
+    t0 = t1;
+    t1 = t2;
+  }
+  if (r0 != 1) return 0;
+  return t0 < 0 ? (uint64_t)(t0 + (int64_t)q) : (uint64_t)t0;
+}
 
 Mod make_mod(uint64_t q) {
   Mod m;

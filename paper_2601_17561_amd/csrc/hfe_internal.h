@@ -123,6 +123,13 @@ struct hfe_keys : hfe::HandleBase {
   hfe::DevBuf sdb_hat;                     // [prime][k_db][N_DB]: NTT(s'_j), + Shoup
   hfe::DevBuf cdt;                         // 19 uint64
   uint64_t cdt_host[19];
+  // The n^2 modulus chain (Section 6.3): family 1.  The secrets, the tables of primes[0] (the NTT
+  // prime of the exact secret products) and everything above are as for the prime family.
+  int family = 0;                          // 0: 36-bit NTT primes; 1: the n^2 modulus chain
+  int cq = 0, cp = 0;                      // chain: query moduli, special moduli
+  int32_t cbase[24] = {};                  // chain bases n: the query bases, then the special part's
+  hfe::Mod cmod[24] = {};                  // chain moduli n^2, same order
+  uint64_t cP = 0;                         // chain: P, the product of the special moduli
 };
 
 
@@ -138,6 +145,10 @@ struct hfe_db : hfe::HandleBase {
   hfe::DevBuf rns;                         // [prime][n_rns][KB][R_pad][64] int8, RNS form
   int n_p2 = 0;                            // bases n in use (n^2 form)
   hfe::DevBuf p2;                          // [prime][2 n_p2][KB][R_pad][64] int8: M, M' per base
+  // Prime slots of the plain residues and of the int8 planes: the keys' primes for the prime family;
+  // for the n^2 chain, the moduli (query, then special) of Dt and one slot of n_p2 = cp + cq bases
+  // (the special moduli first) for the planes.
+  int slots_plain = 0, slots_planes = 0;
 };
 
 struct hfe_qct : hfe::HandleBase {
@@ -228,7 +239,7 @@ hipError_t launch_q_encrypt_big(const QEncArgs& a, uint64_t* XT_prime, uint32_t 
                                 uint64_t delta_mod, NttTab tab_q, const uint64_t* s_hat_prime, hipStream_t s);
 hipError_t launch_dec_products_big(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,
                                    int64_t rows, NttTab tab, const uint64_t* sdb_hat_prime, int j0, int j1,
-                                   uint64_t* y_prime, hipStream_t s);
+                                   const Mod& arith, uint64_t* y_prime, hipStream_t s);
 
 // Digit split of the database: Dt [K][R] residues mod q -> digits [5][KB][R_pad][64].
 hipError_t launch_split_db(const uint64_t* Dt_prime, int64_t K, int64_t R, int64_t KB,
@@ -294,11 +305,13 @@ hipError_t launch_split_db_p2(const uint64_t* Dt_prime, int64_t K, int64_t R, in
 hipError_t launch_lift_p2(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
                           const LiftArgs& la, int n_bases, int8_t* Xq, hipStream_t s);
 constexpr int kP2TileQ = 256;  // n^2 workgroup tile: widest query columns (256 x 128 rows, or 128 x 256)
+constexpr int kP2ArgBases = 16;  // bases one contraction launch takes (the n^2 chain uses up to 12)
 struct P2GemmArgs {
   int nz, n_bases;
   const int8_t* Dq[kMaxPrimes];                // [2 n_bases][KB][R_pad][64] per prime slot
   const int8_t* Xq[kMaxPrimes];                // [2 n_bases][KB][d3_pad][64]
-  int32_t n[kP2MaxBases];                      // bases
+  int32_t n[kP2ArgBases], m[kP2ArgBases];      // base j: n_j and n_j^2
+  double rn[kP2ArgBases], rm[kP2ArgBases];     // RN(1 / n_j), RN(1 / n_j^2)
   uint16_t* res;                               // [nz][n_bases][d3][R_out], residues < n^2
   int64_t KB, R_pad, n_db, row0, R_out, d3, d3_pad;  // d3_pad a multiple of the query tile width
 };
@@ -316,6 +329,49 @@ struct P2CrtArgs {
   uint64_t M_mod_q[kMaxPrimes];                // M mod that prime
 };
 hipError_t launch_crt_p2(const uint16_t* res, int nz, int64_t n, const P2CrtArgs& ra, uint64_t* C, hipStream_t s);
+
+// ------------------------------------------------------------------ the n^2 modulus chain (k_chain.hip)
+// Ciphertext moduli m = n^2 for primes 127 <= n <= 253 (Section 6.3): query moduli m_0..m_{L-1}, a
+// special part of np moduli m'_s (the rescale divisor P = prod m'_s).  Contraction slots: the special
+// moduli first (slot s), then the query moduli (slot np + j), so that a level l uses slots
+// [0, np + l).
+constexpr int kChainMaxP = 3;                            // P = prod m'_s < 2^48: its CRT fits 64 bits
+constexpr int kChainMaxSlots = kChainMaxP + HFE_MAX_QPRIMES;
+struct ChainBase {
+  int32_t n, m;        // n, n^2
+  uint32_t magic_n;    // ceil(2^32 / n)
+  double rcp_n, rcp_m; // RN(1 / n), RN(1 / n^2)
+};
+ChainBase chain_base(int32_t n);
+struct ChainLiftArgs {
+  int level, np;
+  uint64_t q[HFE_MAX_QPRIMES], mu[HFE_MAX_QPRIMES];      // query moduli m_j
+  uint64_t garner[HFE_MAX_QPRIMES][HFE_MAX_QPRIMES];     // Garner constants of the query moduli
+  uint64_t half_digits[HFE_MAX_QPRIMES];                 // mixed-radix digits of (Q - 1) / 2
+  uint64_t pm[kChainMaxP], pmu[kChainMaxP];              // special moduli m'_s
+  uint64_t mprod[kChainMaxP][HFE_MAX_QPRIMES];           // m_0 .. m_{i-1} mod m'_s
+  uint64_t Q_mod[kChainMaxP];                            // Q_level mod m'_s
+  ChainBase base[kChainMaxSlots];                        // per slot
+};
+struct ChainRescaleArgs {
+  int level, np;
+  uint64_t pm[kChainMaxP], pmu[kChainMaxP];              // special moduli
+  uint64_t pinv[kChainMaxP];                             // (m'_0 .. m'_{s-1})^-1 mod m'_s
+  uint64_t P;                                            // prod m'_s
+  Mod mod[HFE_MAX_QPRIMES];                              // query moduli
+  uint64_t Pinv[HFE_MAX_QPRIMES];                        // P^-1 mod m_j
+};
+// Residues Dt [K][R] mod b.m -> the slot's two planes [2][KB][R_pad][64] (M, M').
+hipError_t launch_chain_split_db(const uint64_t* Dt, int64_t K, int64_t R, int64_t KB, int64_t R_pad,
+                                 const ChainBase& b, int8_t* planes, hipStream_t s);
+// Query residues XT [level][d3][K] -> planes Xq [slot][2][KB][d3_pad][64] of every slot.
+hipError_t launch_chain_lift(const uint64_t* XT, int64_t d3, int64_t K, int64_t KB, int64_t d3_pad,
+                             const ChainLiftArgs& la, int8_t* Xq, hipStream_t s);
+// Contraction residues res [slot][n] (uint16, n = d3 R_out) -> RS_P, out [level][n] (uint64).
+hipError_t launch_chain_rescale(const uint16_t* res, int64_t n, const ChainRescaleArgs& ra, uint64_t* out,
+                                hipStream_t s);
+// Contraction residues res [slot][n] -> C [level + np][n] uint64 (query moduli, then the special ones).
+hipError_t launch_chain_widen(const uint16_t* res, int64_t n, int level, int np, uint64_t* C, hipStream_t s);
 
 struct BatchDesc;
 struct BatchHeader;
@@ -439,9 +495,11 @@ hipError_t launch_crt_rescale_p2(const uint16_t* res, int64_t n, const P2CrtArgs
                                  uint64_t* out, hipStream_t s);
 
 // Decryption: y[i][c][r] = B_out + (s'_j * A_out)[(row0 + r) mod N_DB] mod q_i.
+// arith: the modulus of the residues when it is not the table's prime (the n^2 chain; products then
+// go through the table's prime, see k_ntt.hip); nullptr: the table's prime.
 hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,
                                int64_t rows, int n_db_log, NttTab tab, const uint64_t* sdb_hat_prime,
-                               int k_db, uint64_t* y_prime, hipStream_t s);
+                               int k_db, uint64_t* y_prime, hipStream_t s, const Mod* arith = nullptr);
 
 struct DecodeArgs {
   int level;

@@ -318,6 +318,7 @@ hfe_status hfe_server_create(const hfe_db* db, size_t mem_budget, int64_t max_co
   *out = nullptr;
   const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(db));
   if (!db || hb->kind != kDb) return fail(HFE_EINVAL, "invalid database handle");
+  if (db->keys->family) return fail(HFE_EINVAL, "the server does not run the n^2 modulus chain");
   if (form != HFE_FORM_I8_MFMA && form != HFE_FORM_RNS_I8 && form != HFE_FORM_P2_I8)
     return fail(HFE_EINVAL, "the server runs an int8 form");
   if (!(db->forms & (uint32_t)form)) return fail(HFE_EINVAL, "database not prepared for this form");

@@ -72,9 +72,9 @@ struct File {
 
 // The device buffers of a database in file order, with their expected sizes.
 void expected_bytes(const hfe_db* D, uint64_t out[4]) {
-  const size_t np = (size_t)D->keys->n_primes;
+  const size_t np = (size_t)D->slots_planes;
   const size_t plane = (size_t)D->KB * D->R_pad * kKB;
-  out[0] = (D->forms & HFE_FORM_PLAIN_U64) ? sizeof(uint64_t) * np * D->K * D->R : 0;
+  out[0] = (D->forms & HFE_FORM_PLAIN_U64) ? sizeof(uint64_t) * (size_t)D->slots_plain * D->K * D->R : 0;
   out[1] = (D->forms & HFE_FORM_I8_MFMA) ? np * kDigits * plane : 0;
   out[2] = (D->forms & HFE_FORM_RNS_I8) ? np * D->n_rns * plane : 0;
   out[3] = (D->forms & HFE_FORM_P2_I8) ? np * 2 * D->n_p2 * plane : 0;
@@ -88,6 +88,7 @@ hfe_status hfe_db_save(const hfe_db* db, const char* path, void* stream) {
   const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(db));
   if (!db || hb->kind != kDb) return fail(HFE_EINVAL, "invalid database handle");
   if (!path) return fail(HFE_EINVAL, "path is NULL");
+  if (db->keys->family != 0) return fail(HFE_EINVAL, "databases of the n^2 modulus chain are not stored");
   const hipStream_t s = (hipStream_t)stream;
   FileHeader h;
   std::memset(&h, 0, sizeof(h));
@@ -153,6 +154,7 @@ hfe_status hfe_db_load(const hfe_keys* keys, const char* path, uint32_t forms, v
   const HandleBase* hb = static_cast<const HandleBase*>(static_cast<const void*>(keys));
   if (!keys || hb->kind != kKeys) return fail(HFE_EINVAL, "invalid keys handle");
   if (!path) return fail(HFE_EINVAL, "path is NULL");
+  if (keys->family != 0) return fail(HFE_EINVAL, "databases of the n^2 modulus chain are not stored");
   const hipStream_t s = (hipStream_t)stream;
   File f;
   f.f = std::fopen(path, "rb");
@@ -184,6 +186,7 @@ hfe_status hfe_db_load(const hfe_keys* keys, const char* path, uint32_t forms, v
   D->forms = h.forms;
   D->n_rns = (h.forms & HFE_FORM_RNS_I8) ? h.n_rns : 0;
   D->n_p2 = (h.forms & HFE_FORM_P2_I8) ? h.n_p2 : 0;
+  D->slots_plain = D->slots_planes = keys->n_primes;
   uint64_t want[4];
   expected_bytes(D.get(), want);
   for (int i = 0; i < 4; ++i)

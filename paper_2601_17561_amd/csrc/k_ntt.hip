@@ -25,6 +25,19 @@ constexpr int kNttThreads = 1024;
 __device__ __forceinline__ double to_d(uint64_t x) { return (double)x; }    // exact below 2^53
 __device__ __forceinline__ uint64_t to_u(double x) { return (uint64_t)x; }  // x an integer in [0, q)
 
+// The n^2 modulus chain multiplies by the ternary secrets through the NTT prime q of the tables: a
+// residue x mod m (m = n^2 < 2^16) enters as its centered integer taken mod q, and every product
+// coefficient is an integer of magnitude at most N m / 2 <= 2^31 < q / 2, so the centered result mod
+// q is that integer, which is then reduced mod m.  (For the 36-bit primes m = q and neither step
+// runs.)
+__device__ __forceinline__ double to_ntt(uint64_t x, uint64_t m, uint64_t q) {
+  const int64_t c = centered(x, m);
+  return (double)(c >= 0 ? (uint64_t)c : q - (uint64_t)(-c));
+}
+__device__ __forceinline__ uint64_t from_ntt(double v, uint64_t q, const Mod& M) {
+  return from_signed(centered((uint64_t)v, q), M.q, M.mu);
+}
+
 // Both transforms run in rounds of up to three butterfly stages: a thread loads a group of 2^S
 // coefficients into registers, applies S stages there and stores them back, so a transform of
 // degree 2^logn takes ceil(logn / 3) LDS passes and barriers instead of logn.
@@ -284,7 +297,7 @@ hipError_t launch_db_T(const int8_t* m_db, int64_t d1, int32_t d2, const uint64_
 // chunk j: B[i][c] = -(s'_j a_c)[i - j N_DB] + p * plain[i][c] + e(i, c) (stream DBE).
 // plain = M_DB for c < d2, T for c >= d2.  Column c of D is stored contiguously: Dt[c][row].
 
-template <int R>
+template <int R, bool CHAIN>
 __global__ void __launch_bounds__(kNttThreads)
 k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, const uint64_t* sdb_hat) {
   extern __shared__ double lds[];
@@ -302,7 +315,7 @@ k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, cons
         const uint64_t w = b.v[j];
         const uint64_t x = w < M.bound ? barrett64(w, q, M.mu)
                                        : uniform_at(A.seed, key_a, (uint64_t)v, (uint64_t)c, M);
-        lds[v] = to_d(x);
+        lds[v] = CHAIN ? to_ntt(x, q, T.q) : to_d(x);
         col[v] = x;
       }
     }
@@ -335,7 +348,7 @@ k_db_encrypt(DbEncArgs A, uint64_t* Dt, uint32_t prime_id, Mod M, NttTab T, cons
       const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)i, (uint64_t)c, A.cdt);
       const uint64_t ppl = pl >= 0 ? barrett64(pm * (uint64_t)pl, q, M.mu)
                                    : sub_mod(0, barrett64(pm * (uint64_t)(-pl), q, M.mu), q);
-      uint64_t val = sub_mod(ppl, to_u(lds[i - lo]), q);
+      uint64_t val = sub_mod(ppl, CHAIN ? from_ntt(lds[i - lo], T.q, M) : to_u(lds[i - lo]), q);
       val = add_mod(val, from_signed(e, q, M.mu), q);
       col[n + i] = val;
     }
@@ -348,12 +361,14 @@ hipError_t launch_db_encrypt(const DbEncArgs& a, uint64_t* Dt_prime, uint32_t pr
   if (a.K <= 0) return hipSuccess;
   if (tab_db.logn > kMaxLogN) return launch_db_encrypt_big(a, Dt_prime, prime_id, m, tab_db, sdb_hat_prime, s);
   const size_t lds = sizeof(double) << tab_db.logn;
+  const bool chain = m.q != tab_db.q;  // residues mod n^2, products through the table's prime
   return by_regs(regs_per_thread(tab_db.logn), [&](auto rc) {
     constexpr int R = decltype(rc)::value;
-    hipError_t e = allow_lds(k_db_encrypt<R>, lds);
+    auto kern = chain ? k_db_encrypt<R, true> : k_db_encrypt<R, false>;
+    hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_db_encrypt<R>, dim3((unsigned)a.K), dim3(ntt_block(tab_db.logn)), lds, s, a,
-                       Dt_prime, prime_id, m, tab_db, sdb_hat_prime);
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.K), dim3(ntt_block(tab_db.logn)), lds, s, a, Dt_prime, prime_id, m,
+                       tab_db, sdb_hat_prime);
     return hipGetLastError();
   });
 }
@@ -363,7 +378,7 @@ hipError_t launch_db_encrypt(const DbEncArgs& a, uint64_t* Dt_prime, uint32_t pr
 // for each chunk j of N_Q code rows b[t] = -(s_j a_c)[t - j N_Q] + Delta m[c][t] + e(t, c).
 // Output row c of XT: [b_c (d2) | a_c (N_Q)].
 
-template <int R>
+template <int R, bool CHAIN>
 __global__ void __launch_bounds__(kNttThreads)
 k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, NttTab T,
             const uint64_t* s_hat) {
@@ -383,7 +398,7 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
         const uint64_t w = b.v[j];
         const uint64_t x = w < M.bound ? barrett64(w, q, M.mu)
                                        : uniform_at(A.seed, key_a, (uint64_t)t, (uint64_t)c, M);
-        lds[t] = to_d(x);
+        lds[t] = CHAIN ? to_ntt(x, q, T.q) : to_d(x);
         arow[t] = x;
       }
     }
@@ -414,7 +429,7 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
       const int8_t mv = m[t];
       const uint64_t dm = mv == 1 ? delta : (mv == -1 ? (delta ? q - delta : 0) : 0);
       const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)t, (uint64_t)c, A.cdt);
-      uint64_t val = sub_mod(dm, to_u(lds[t - lo]), q);
+      uint64_t val = sub_mod(dm, CHAIN ? from_ntt(lds[t - lo], T.q, M) : to_u(lds[t - lo]), q);
       val = add_mod(val, from_signed(e, q, M.mu), q);
       row[t] = val;
     }
@@ -428,12 +443,14 @@ hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prim
   if (a.d3 <= 0) return hipSuccess;
   if (tab_q.logn > kMaxLogN) return launch_q_encrypt_big(a, XT_prime, prime_id, m, delta_mod, tab_q, s_hat_prime, s);
   const size_t lds = sizeof(double) << tab_q.logn;
+  const bool chain = m.q != tab_q.q;  // residues mod n^2, products through the table's prime
   return by_regs(regs_per_thread(tab_q.logn), [&](auto rc) {
     constexpr int R = decltype(rc)::value;
-    hipError_t e = allow_lds(k_q_encrypt<R>, lds);
+    auto kern = chain ? k_q_encrypt<R, true> : k_q_encrypt<R, false>;
+    hipError_t e = allow_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_q_encrypt<R>, dim3((unsigned)a.d3), dim3(ntt_block(tab_q.logn)), lds, s, a,
-                       XT_prime, prime_id, m, delta_mod, tab_q, s_hat_prime);
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.d3), dim3(ntt_block(tab_q.logn)), lds, s, a, XT_prime, prime_id, m,
+                       delta_mod, tab_q, s_hat_prime);
     return hipGetLastError();
   });
 }
@@ -442,16 +459,17 @@ hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prim
 // Workgroup (c, j): y[c][r] = B_out[c][r] + (s'_j * A_out[c])[(row0 + r) - j N_DB] for the
 // selected rows r whose database row row0 + r lies in chunk j.
 
+template <bool CHAIN>
 __global__ void __launch_bounds__(kNttThreads)
 k_dec_products(const uint64_t* out, int64_t R_out, int64_t row0, int64_t rows, NttTab T,
-               const uint64_t* sdb_hat, int j0, uint64_t* y) {
+               const uint64_t* sdb_hat, int j0, Mod M, uint64_t* y) {
   extern __shared__ double lds[];
   const int n = 1 << T.logn;
   const int64_t c = blockIdx.x;
   const int j = j0 + (int)blockIdx.y;
-  const uint64_t q = T.q;
+  const uint64_t q = M.q;  // the arithmetic modulus (the table's prime, or n^2 of the chain)
   const uint64_t* ocol = out + c * R_out;
-  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = to_d(ocol[v]);
+  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = CHAIN ? to_ntt(ocol[v], q, T.q) : to_d(ocol[v]);
   __syncthreads();
   ntt_fwd_lds(lds, T);
   const uint64_t* w = sdb_hat + (int64_t)j * 2 * n;
@@ -462,23 +480,31 @@ k_dec_products(const uint64_t* out, int64_t R_out, int64_t row0, int64_t rows, N
   if (lo < 0) lo = 0;
   if (hi > rows) hi = rows;
   for (int64_t r = lo + threadIdx.x; r < hi; r += blockDim.x)
-    y[c * rows + r] = add_mod(ocol[n + r], to_u(lds[row0 + r - (int64_t)j * n]), q);
+    y[c * rows + r] = add_mod(ocol[n + r], CHAIN ? from_ntt(lds[row0 + r - (int64_t)j * n], T.q, M)
+                                                 : to_u(lds[row0 + r - (int64_t)j * n]), q);
 }
 
 hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,
                                int64_t rows, int n_db_log, NttTab tab, const uint64_t* sdb_hat_prime,
-                               int k_db, uint64_t* y_prime, hipStream_t s) {
+                               int k_db, uint64_t* y_prime, hipStream_t s, const Mod* arith) {
   if (d3 <= 0 || rows <= 0) return hipSuccess;
   const int64_t n = 1ll << n_db_log;
   const int j0 = (int)(row0 / n), j1 = (int)((row0 + rows - 1) / n);
   if (j1 >= k_db) return hipErrorInvalidValue;
+  Mod M;
+  M.q = tab.q;
+  M.mu = 0;
+  M.bound = 0;
+  if (arith) M = *arith;
+  const bool chain = M.q != tab.q;
   if (tab.logn > kMaxLogN)
-    return launch_dec_products_big(out_prime, d3, R_out, row0, rows, tab, sdb_hat_prime, j0, j1, y_prime, s);
+    return launch_dec_products_big(out_prime, d3, R_out, row0, rows, tab, sdb_hat_prime, j0, j1, M, y_prime, s);
   const size_t lds = sizeof(double) << tab.logn;
-  hipError_t e = allow_lds(k_dec_products, lds);
+  auto kern = chain ? k_dec_products<true> : k_dec_products<false>;
+  hipError_t e = allow_lds(kern, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_dec_products, dim3((unsigned)d3, (unsigned)(j1 - j0 + 1)), dim3(ntt_block(tab.logn)),
-                     lds, s, out_prime, R_out, row0, rows, tab, sdb_hat_prime, j0, y_prime);
+  hipLaunchKernelGGL(kern, dim3((unsigned)d3, (unsigned)(j1 - j0 + 1)), dim3(ntt_block(tab.logn)), lds, s, out_prime,
+                     R_out, row0, rows, tab, sdb_hat_prime, j0, M, y_prime);
   return hipGetLastError();
 }
 

@@ -232,9 +232,22 @@ __global__ void k_big_store_hat(const double* W, int n, uint64_t q, uint64_t* a,
   if (shoup) a[(int64_t)blockIdx.y * stride + n + v] = shoup_quot(x, q);
 }
 
-// Uniform a-polynomial of column c0 + y (stream key_a, element (v, c)), written to
-// dst[(c0 + y) * dst_stride + v] and, as doubles, to W[y].
-__global__ void k_big_uniform(uint64_t seed, uint64_t key_a, Mod M, int64_t c0, int n, uint64_t* dst,
+// The n^2 modulus chain takes its products through the table's prime q (as the LDS-resident
+// kernels): a residue mod m enters as its centered integer mod q, a product coefficient (an integer
+// of magnitude below q / 2) leaves centered and reduced mod m.  With m = q both are identities.
+__device__ __forceinline__ double big_to_ntt(uint64_t x, const Mod& M, uint64_t q) {
+  if (M.q == q) return (double)x;
+  const int64_t c = centered(x, M.q);
+  return (double)(c >= 0 ? (uint64_t)c : q - (uint64_t)(-c));
+}
+__device__ __forceinline__ uint64_t big_from_ntt(double v, uint64_t q, const Mod& M) {
+  if (M.q == q) return (uint64_t)v;
+  return from_signed(centered((uint64_t)v, q), M.q, M.mu);
+}
+
+// Uniform a-polynomial of column c0 + y (stream key_a, element (v, c)) mod M, written to
+// dst[(c0 + y) * dst_stride + v] and, as the NTT's doubles (residues mod q), to W[y].
+__global__ void k_big_uniform(uint64_t seed, uint64_t key_a, Mod M, uint64_t q, int64_t c0, int n, uint64_t* dst,
                               int64_t dst_stride, double* W) {
   const int v4 = blockIdx.x * blockDim.x + threadIdx.x;
   if (4 * v4 >= n) return;
@@ -247,7 +260,7 @@ __global__ void k_big_uniform(uint64_t seed, uint64_t key_a, Mod M, int64_t c0, 
       const uint64_t w = b.v[j];
       const uint64_t x = w < M.bound ? barrett64(w, M.q, M.mu) : uniform_at(seed, key_a, (uint64_t)v, (uint64_t)c, M);
       dst[c * dst_stride + v] = x;
-      W[(int64_t)blockIdx.y * n + v] = (double)x;
+      W[(int64_t)blockIdx.y * n + v] = big_to_ntt(x, M, q);
     }
   }
 }
@@ -278,7 +291,7 @@ __global__ void k_big_store_T(const double* W, int64_t i0, int n, uint64_t q, in
 
 // Database rows of chunk j for column c0 + y: B[i][c] = p plain[i][c] - (s'_j a_c)[i - j n] + e(i, c).
 __global__ void k_big_emit_db(const double* W2, DbEncArgs A, int64_t c0, int j, int n, uint64_t* Dt, Mod M,
-                              uint64_t key_e) {
+                              uint64_t qt, uint64_t key_e) {
   const int64_t c = c0 + blockIdx.y;
   const int64_t i = (int64_t)j * n + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.d1 || i >= (int64_t)(j + 1) * n) return;
@@ -287,14 +300,14 @@ __global__ void k_big_emit_db(const double* W2, DbEncArgs A, int64_t c0, int j, 
   const int32_t pl = c < A.d2 ? (int32_t)A.MT[c * A.d1 + i] : A.Tt[(c - A.d2) * A.d1 + i];
   const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)i, (uint64_t)c, A.cdt);
   const uint64_t ppl = pl >= 0 ? barrett64(pm * (uint64_t)pl, q, M.mu) : sub_mod(0, barrett64(pm * (uint64_t)(-pl), q, M.mu), q);
-  uint64_t val = sub_mod(ppl, (uint64_t)W2[(int64_t)blockIdx.y * n + (i - (int64_t)j * n)], q);
+  uint64_t val = sub_mod(ppl, big_from_ntt(W2[(int64_t)blockIdx.y * n + (i - (int64_t)j * n)], qt, M), q);
   val = add_mod(val, from_signed(e, q, M.mu), q);
   Dt[c * A.R + n + i] = val;
 }
 
 // Query rows of chunk j for column c0 + y: b[t] = Delta m[c][t] - (s_j a_c)[t - j n] + e(t, c).
 __global__ void k_big_emit_q(const double* W2, QEncArgs A, int64_t c0, int j, int n, uint64_t* XT, Mod M,
-                             uint64_t delta, uint64_t key_e) {
+                             uint64_t qt, uint64_t delta, uint64_t key_e) {
   const int64_t c = c0 + blockIdx.y;
   const int64_t t = (int64_t)j * n + blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= A.d2 || t >= (int64_t)(j + 1) * n) return;
@@ -302,26 +315,26 @@ __global__ void k_big_emit_q(const double* W2, QEncArgs A, int64_t c0, int j, in
   const int8_t mv = A.m_q[c * A.d2 + t];
   const uint64_t dm = mv == 1 ? delta : (mv == -1 ? (delta ? q - delta : 0) : 0);
   const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)t, (uint64_t)c, A.cdt);
-  uint64_t val = sub_mod(dm, (uint64_t)W2[(int64_t)blockIdx.y * n + (t - (int64_t)j * n)], q);
+  uint64_t val = sub_mod(dm, big_from_ntt(W2[(int64_t)blockIdx.y * n + (t - (int64_t)j * n)], qt, M), q);
   val = add_mod(val, from_signed(e, q, M.mu), q);
   XT[c * A.K + t] = val;
 }
 
-// A-part of result column c0 + y as doubles.
-__global__ void k_big_load_col(const uint64_t* out, int64_t R_out, int64_t c0, int n, double* W) {
+// A-part of result column c0 + y as the NTT's doubles.
+__global__ void k_big_load_col(const uint64_t* out, int64_t R_out, int64_t c0, int n, Mod M, uint64_t q, double* W) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) W[(int64_t)blockIdx.y * n + v] = (double)out[(c0 + blockIdx.y) * R_out + v];
+  if (v < n) W[(int64_t)blockIdx.y * n + v] = big_to_ntt(out[(c0 + blockIdx.y) * R_out + v], M, q);
 }
 
 // y[c][r] = B_out[c][r] + (s'_j A_out[c])[(row0 + r) - j n] for the selected rows in chunk j.
 __global__ void k_big_emit_dec(const double* W2, const uint64_t* out, int64_t R_out, int64_t row0, int64_t rows,
-                               int64_t c0, int j, int n, uint64_t q, uint64_t* y) {
+                               int64_t c0, int j, int n, Mod M, uint64_t qt, uint64_t* y) {
   const int64_t c = c0 + blockIdx.y;
   const int64_t lo = std::max<int64_t>((int64_t)j * n - row0, 0), hi = std::min<int64_t>((int64_t)(j + 1) * n - row0, rows);
   const int64_t r = lo + blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= hi) return;
   y[c * rows + r] = add_mod(out[c * R_out + n + r],
-                            (uint64_t)W2[(int64_t)blockIdx.y * n + (row0 + r - (int64_t)j * n)], q);
+                            big_from_ntt(W2[(int64_t)blockIdx.y * n + (row0 + r - (int64_t)j * n)], qt, M), M.q);
 }
 
 static dim3 elem_grid(int64_t n, int64_t cols) { return dim3((unsigned)((n + 255) / 256), (unsigned)cols); }
@@ -387,7 +400,7 @@ hipError_t launch_db_encrypt_big(const DbEncArgs& a, uint64_t* Dt, uint32_t prim
   for (int64_t c0 = 0; e == hipSuccess && c0 < a.K; c0 += nb) {
     const int64_t cnt = std::min(nb, a.K - c0);
     hipLaunchKernelGGL(k_big_uniform, dim3((unsigned)((n / 4 + 255) / 256), (unsigned)cnt), dim3(256), 0, s, a.seed,
-                       stream_tag(kDbA, prime_id), M, c0, n, Dt, a.R, W.as<double>());
+                       stream_tag(kDbA, prime_id), M, T.q, c0, n, Dt, a.R, W.as<double>());
     e = hipGetLastError();
     if (e == hipSuccess) e = big_transform(W.as<double>(), cnt, T, true, s);
     for (int j = 0; e == hipSuccess && j < chunks; ++j) {
@@ -397,7 +410,7 @@ hipError_t launch_db_encrypt_big(const DbEncArgs& a, uint64_t* Dt, uint32_t prim
       if (e == hipSuccess) e = big_transform(W2.as<double>(), cnt, T, false, s);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_big_emit_db, elem_grid(n, cnt), dim3(256), 0, s, W2.as<double>(), a, c0, j, n, Dt, M,
-                           stream_tag(kDbE, 0));
+                           T.q, stream_tag(kDbE, 0));
         e = hipGetLastError();
       }
     }
@@ -416,7 +429,7 @@ hipError_t launch_q_encrypt_big(const QEncArgs& a, uint64_t* XT, uint32_t prime_
     const int64_t cnt = std::min(nb, a.d3 - c0);
     // a_c goes to row c of XT after the d2 b-coefficients: dst = XT + d2, stride K
     hipLaunchKernelGGL(k_big_uniform, dim3((unsigned)((n / 4 + 255) / 256), (unsigned)cnt), dim3(256), 0, s, a.seed,
-                       stream_tag(kQA, prime_id), M, c0, n, XT + a.d2, a.K, W.as<double>());
+                       stream_tag(kQA, prime_id), M, T.q, c0, n, XT + a.d2, a.K, W.as<double>());
     e = hipGetLastError();
     if (e == hipSuccess) e = big_transform(W.as<double>(), cnt, T, true, s);
     for (int j = 0; e == hipSuccess && j < a.k; ++j) {
@@ -426,7 +439,7 @@ hipError_t launch_q_encrypt_big(const QEncArgs& a, uint64_t* XT, uint32_t prime_
       if (e == hipSuccess) e = big_transform(W2.as<double>(), cnt, T, false, s);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_big_emit_q, elem_grid(n, cnt), dim3(256), 0, s, W2.as<double>(), a, c0, j, n, XT, M,
-                           delta, stream_tag(kQE, 0));
+                           T.q, delta, stream_tag(kQE, 0));
         e = hipGetLastError();
       }
     }
@@ -435,7 +448,8 @@ hipError_t launch_q_encrypt_big(const QEncArgs& a, uint64_t* XT, uint32_t prime_
 }
 
 hipError_t launch_dec_products_big(const uint64_t* out, int64_t d3, int64_t R_out, int64_t row0, int64_t rows,
-                                   NttTab T, const uint64_t* sdb_hat, int j0, int j1, uint64_t* y, hipStream_t s) {
+                                   NttTab T, const uint64_t* sdb_hat, int j0, int j1, const Mod& M, uint64_t* y,
+                                   hipStream_t s) {
   const int n = 1 << T.logn;
   const int64_t nb = big_batch(T.logn, d3);
   DevBuf W, W2;
@@ -443,7 +457,7 @@ hipError_t launch_dec_products_big(const uint64_t* out, int64_t d3, int64_t R_ou
   if (e == hipSuccess) e = ws_alloc(W2, sizeof(double) * nb * n, s);
   for (int64_t c0 = 0; e == hipSuccess && c0 < d3; c0 += nb) {
     const int64_t cnt = std::min(nb, d3 - c0);
-    hipLaunchKernelGGL(k_big_load_col, elem_grid(n, cnt), dim3(256), 0, s, out, R_out, c0, n, W.as<double>());
+    hipLaunchKernelGGL(k_big_load_col, elem_grid(n, cnt), dim3(256), 0, s, out, R_out, c0, n, M, T.q, W.as<double>());
     e = hipGetLastError();
     if (e == hipSuccess) e = big_transform(W.as<double>(), cnt, T, true, s);
     for (int j = j0; e == hipSuccess && j <= j1; ++j) {
@@ -453,7 +467,7 @@ hipError_t launch_dec_products_big(const uint64_t* out, int64_t d3, int64_t R_ou
       if (e == hipSuccess) e = big_transform(W2.as<double>(), cnt, T, false, s);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_big_emit_dec, elem_grid(n, cnt), dim3(256), 0, s, W2.as<double>(), out, R_out, row0,
-                           rows, c0, j, n, T.q, y);
+                           rows, c0, j, n, M, T.q, y);
         e = hipGetLastError();
       }
     }

@@ -108,13 +108,14 @@ struct P2Tile {
   const int8_t* D;
   uint16_t* res;
   int j;
+  int32_t bn, bm;        // the base n and n^2 of this product
+  double brn, brm;       // RN(1 / n), RN(1 / n^2)
   int64_t KB, R_pad, d3_pad, n_db, row0, R_out, d3, r0, c0;
 };
 
 template <int TQ>
 __device__ __forceinline__ void p2_tile(const P2Tile& g, int8_t* lds) {
   using C = P2Cfg<TQ>;
-  const int j = g.j;
   const int64_t r0 = g.r0, c0 = g.c0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wq = wave % C::NQ, wr = wave / C::NQ;
@@ -219,8 +220,8 @@ __device__ __forceinline__ void p2_tile(const P2Tile& g, int8_t* lds) {
   // epilogue: S mod n^2 = (G0 mod n^2 + n (G1 mod n)) mod n^2 -> res[z][j][c][r]; 32 x 32 result
   // layout as in the digit form (lane l, element e: query column 8 (e / 4) + 4 (l / 32) + e % 4,
   // row l % 32)
-  const int32_t n = kP2C.n[j], m = kP2C.m[j];
-  const double rn = kP2C.rcp_n[j], rm = kP2C.rcp_m[j];
+  const int32_t n = g.bn, m = g.bm;
+  const double rn = g.brn, rm = g.brm;
   uint16_t* res = g.res;
 #pragma unroll
   for (int b = 0; b < C::WRB; ++b) {
@@ -248,8 +249,8 @@ k_gemm_p2(P2GemmArgs g) {
   const int64_t rt = (jj / n_ct) * kXcds + xcd, ct = jj % n_ct;
   if (rt >= n_rt) return;
   P2Tile t{g.Xq[z] + (size_t)(2 * j) * g.KB * g.d3_pad * kKB, g.Dq[z] + (size_t)(2 * j) * g.KB * g.R_pad * kKB,
-           g.res + ((size_t)z * g.n_bases + j) * g.d3 * g.R_out, j, g.KB, g.R_pad, g.d3_pad, g.n_db, g.row0,
-           g.R_out, g.d3, rt * C::TR, ct * C::TQ};
+           g.res + ((size_t)z * g.n_bases + j) * g.d3 * g.R_out, j, g.n[j], g.m[j], g.rn[j], g.rm[j], g.KB, g.R_pad,
+           g.d3_pad, g.n_db, g.row0, g.R_out, g.d3, rt * C::TR, ct * C::TQ};
   p2_tile<TQ>(t, lds);
 }
 
@@ -292,8 +293,9 @@ k_gemm_p2_batched(P2BatchArgs a) {
     if (rt >= n_rt) continue;
     P2Tile tl{d.Xd + (size_t)(z * a.n_bases + j) * 2 * a.KB * d.d3_pad * kKB,
               a.Dq + (size_t)(d.slot[z] * a.n_bases + j) * 2 * a.KB * a.R_pad * kKB,
-              reinterpret_cast<uint16_t*>(d.res) + ((size_t)z * a.n_bases + j) * d.d3 * d.R_out, j, a.KB, a.R_pad,
-              d.d3_pad, d.n_db, d.row0, d.R_out, d.d3, rt * C::TR, ct * C::TQ};
+              reinterpret_cast<uint16_t*>(d.res) + ((size_t)z * a.n_bases + j) * d.d3 * d.R_out, j, kP2C.n[j],
+              kP2C.m[j], kP2C.rcp_n[j], kP2C.rcp_m[j], a.KB, a.R_pad, d.d3_pad, d.n_db, d.row0, d.R_out, d.d3,
+              rt * C::TR, ct * C::TQ};
     p2_tile<TQ>(tl, lds);
   }
 }
@@ -329,7 +331,7 @@ hipError_t launch_gemm_p2_batched(const P2BatchArgs& a, int grid, int tq, hipStr
 
 hipError_t launch_gemm_p2(const P2GemmArgs& g, int tq, hipStream_t s) {
   if (g.R_out <= 0 || g.d3 <= 0) return hipSuccess;
-  if ((tq != 128 && tq != 256) || g.d3_pad % tq != 0 || g.n_bases < 1 || g.n_bases > kP2MaxBases)
+  if ((tq != 128 && tq != 256) || g.d3_pad % tq != 0 || g.n_bases < 1 || g.n_bases > kP2ArgBases)
     return hipErrorInvalidValue;
   const int64_t tr = p2_rows_of(tq);
   const int64_t n_ct = (g.d3 + tq - 1) / tq, n_rt = (g.R_out + tr - 1) / tr;

@@ -47,6 +47,19 @@ void xc_p2_digits(const int64_t* x, int64_t n, int j, int32_t* M, int32_t* Mp) {
   for (int64_t i = 0; i < n; ++i) p2_digits_by(x[i], kP2.n[j], kP2.m[j], kP2.magic_n[j], kP2.rcp_m[j], M[i], Mp[i]);
 }
 
+// The same two n^2 helpers for any base n, with the constants the n^2 modulus chain passes its
+// kernels (ceil(2^32 / n), RN(1 / n), RN(1 / n^2)).
+void xc_p2_digits_n(const int64_t* x, int64_t cnt, int32_t n, int32_t* M, int32_t* Mp) {
+  const uint32_t magic = (uint32_t)(((1ull << 32) + (uint64_t)n - 1) / (uint64_t)n);
+  const int32_t m = n * n;
+  const double rcp_m = 1.0 / (double)m;
+  for (int64_t i = 0; i < cnt; ++i) p2_digits_by(x[i], n, m, magic, rcp_m, M[i], Mp[i]);
+}
+void xc_p2_acc_mod_n(const int32_t* g0, const int32_t* g1, int64_t cnt, int32_t n, uint32_t* out) {
+  const int32_t m = n * n;
+  for (int64_t i = 0; i < cnt; ++i) out[i] = p2_acc_mod(g0[i], g1[i], n, m, 1.0 / (double)n, 1.0 / (double)m);
+}
+
 // RNS epilogue: int32 sums -> residue modulo kRnsMods[j]
 void xc_rns_acc_mod(const int32_t* s, int64_t n, int j, uint32_t* out) {
   const RnsAccConsts c = rns_acc_consts(kRns.m[j], kRns.magic[j]);

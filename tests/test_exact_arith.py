@@ -41,6 +41,8 @@ for _name, _args in {
         "xc_p2_digits": [_p, ctypes.c_int64, ctypes.c_int, _p, _p],
         "xc_rns_acc_mod": [_p, ctypes.c_int64, ctypes.c_int, _p],
         "xc_p2_acc_mod": [_p, _p, ctypes.c_int64, ctypes.c_int, _p],
+        "xc_p2_digits_n": [_p, ctypes.c_int64, ctypes.c_int32, _p, _p],
+        "xc_p2_acc_mod_n": [_p, _p, ctypes.c_int64, ctypes.c_int32, _p],
         "xc_crt": [_p, ctypes.c_int64, ctypes.c_int, _p, _p, _p, _p, ctypes.c_uint64, ctypes.c_uint64,
                    ctypes.c_uint64, ctypes.c_int, _p, _p]}.items():
     getattr(_L, _name).argtypes = _args
@@ -218,3 +220,31 @@ def test_crt_fractional_sum_exact_at_the_quarter_margin(form):
         S = [B, -B, B - 1, -(B - 1), 0, 1, -1] + [int(rng.integers(0, 1 << 62)) * B // (1 << 62) *
                                                   (1 if rng.random() < 0.5 else -1) for _ in range(500)]
         _crt_case(moduli, q, S, form == "p2")
+
+
+CHAIN_BASES = [n for n in range(253, 126, -1) if all(n % d for d in range(2, int(n ** 0.5) + 1))]
+
+
+@pytest.mark.parametrize("n", CHAIN_BASES)
+def test_chain_digits_and_epilogue_exact_for_every_base(n):
+    """The n^2 modulus chain's split (centered residues mod n^2, |x| < n^2) and contraction epilogue with
+    the constants its kernels take, for each of the 24 primes 127 <= n <= 253: every residue, and
+    random and extreme int32 sums."""
+    n2 = n * n
+    h = (n - 1) // 2
+    X = np.concatenate([np.arange(-(n2 // 2), n2 // 2 + 1, dtype=np.int64), np.array([n2, -n2], dtype=np.int64)])
+    M = np.empty(len(X), dtype=np.int32)
+    Mp = np.empty(len(X), dtype=np.int32)
+    _L.xc_p2_digits_n(_ptr(X), len(X), n, _ptr(M), _ptr(Mp))
+    assert np.abs(M).max() <= h and np.abs(Mp).max() <= h
+    assert np.all((M.astype(np.int64) + n * Mp.astype(np.int64) - X) % n2 == 0)
+    rng = np.random.default_rng(n)
+    ext = np.array([-(1 << 31), -(1 << 31) + 1, -1, 0, 1, (1 << 31) - 1, n, -n, n2, -n2], dtype=np.int32)
+    g0 = np.concatenate([rng.integers(-(1 << 31), 1 << 31, 50_000, dtype=np.int64).astype(np.int32),
+                         np.repeat(ext, len(ext))])
+    g1 = np.concatenate([rng.integers(-(1 << 31), 1 << 31, 50_000, dtype=np.int64).astype(np.int32),
+                         np.tile(ext, len(ext))])
+    out = np.empty(len(g0), dtype=np.uint32)
+    _L.xc_p2_acc_mod_n(_ptr(g0), _ptr(g1), len(g0), n, _ptr(out))
+    want = (g0.astype(np.int64) + n * g1.astype(np.int64)) % n2
+    assert np.array_equal(out.astype(np.int64), want)
