@@ -17,4 +17,9 @@ Modules:
   ring    -- negacyclic products (schoolbook) and exact integer matrix products
   ckks    -- keygen, database / query encryption, CCMM, rescale, decryption
   iris    -- masked ternary encoding, shifts, popcount truth and decisions
+  smallmod -- the int8 digit planes of the small-modulus (p^2) product of Section 6.3
+  chain   -- the CCMM over the modulus chain of products n^2 (Section 6.3)
+  bigmul  -- exact negacyclic products at ring degrees up to 2^16
+  formatswitch -- the query's ring switch 2^16 -> N_Q, MSRLWE conversion and
+             modulus switch (Appendix C.1)
 """
