@@ -38,7 +38,13 @@ MEASURED_TRAFFIC_GB = {"dma_q128_w2": 28.3, "dma_r128_w2": 30.4, "dma2_w2": 90.1
                        # the 256-column RNS and n^2 contractions (profiles/pmc_k_gemm_rns_share_q512.md,
                        # profiles/pmc_k_gemm_p2_share_q512.md), fetch + write
                        "rns256": 36.6, "p2_256": 46.1}
-KEY_SEED, DB_SEED, Q_SEED = 11, 22, 33
+KEY_SEED, DB_SEED, Q_SEED, TX_SEED = 11, 22, 33, 44
+# fp64 vector instructions per second of the chip (256 CUs x 64 lanes x 2.4 GHz; the 78.6 TFLOP/s peak
+# counts a fused multiply-add as two) and the fp64 instructions of one error-free modular product as
+# the transforms run it (multiply, fused multiply-add, multiply by 1/q, floor, fused multiply-add, add,
+# two compares, two corrections): the ceiling of the modular products FormatSwitch is built from.
+FP64_INSTR_PER_S = 256 * 64 * 2.4e9
+FP64_PER_MODMUL = 10
 
 
 def log(msg):
@@ -427,6 +433,90 @@ def run_lit(args, H, torch):
     return line
 
 
+def fs_modmuls(w: S.Workload, log_n_t: int):
+    """Modular products of one FormatSwitch of the workload's queries, by kernel: ring switch
+    ((level + 1) rho forward transforms of degree N_Q per ciphertext and slot, a product-accumulate of
+    mask and key per coefficient, two inverse transforms with their 1/n), conversion (k (level + 1)
+    forward transforms per column and slot, 1 + k products per coefficient, 1 + k inverse transforms)."""
+    nq, l = 1 << w.log_n_q, w.level
+    rho = 1 << (log_n_t - w.log_n_q)
+    k = -(-w.d2 // nq)
+    lg = w.log_n_q
+    fwd, inv = nq // 2 * lg, nq // 2 * lg + nq
+    ring = w.d3 * k * (l + 2) * ((l + 1) * rho * fwd + 2 * (l + 1) * rho * nq + 2 * inv)
+    conv = w.d3 * (l + 2) * (k * (l + 1) * (fwd + (1 + k) * nq) + (1 + k) * inv)
+    return {"ring": ring, "conv": conv, "rho": rho, "k": k}
+
+
+def run_format_switch(args, H, torch, steps=5):
+    """FormatSwitch (Appendix C.1) of the share workload's 512 query columns from the transmission ring
+    2^16: keys, the client's transmission encryption, then `steps` timed switches (after one warm-up)
+    with the stage events of the library on its stream.  The switched query goes through the CCMM
+    (digit form) and must decrypt to the inner products of the same queries encrypted directly."""
+    w = S.FS_SHARE
+    log_n_t = S.FS_LOG_N_T[w.name]
+    dev = torch.device("cuda", 0)
+    inp = S.make_inputs(w)
+    P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
+    keys = H.hfe_keygen(P, KEY_SEED)
+    t0 = time.perf_counter()
+    fk = H.hfe_fs_keygen(keys, w.level, log_n_t, KEY_SEED)
+    torch.cuda.synchronize()
+    t_keys = time.perf_counter() - t0
+    shifts = [int(x) for x in inp["shifts"]]
+    m_q = H.hfe_encode(torch.from_numpy(inp["q_codes"]).to(dev), torch.from_numpy(inp["q_masks"]).to(dev), shifts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = H.hfe_fs_encrypt(fk, m_q, TX_SEED)
+    torch.cuda.synchronize()
+    t_tx = time.perf_counter() - t0
+    log(f"format switch: keys in {t_keys:.2f} s, transmission of {w.d3} columns ({T.numel() * 8 / 1e9:.2f} GB) "
+        f"in {t_tx * 1e3:.0f} ms")
+    H.hfe_profile(True)
+    ms, stages = [], []
+    qct = None
+    for i in range(steps + 1):
+        if qct is not None:
+            qct.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qct = H.hfe_format_switch(fk, T, w.d3)
+        torch.cuda.synchronize()
+        if i > 0:
+            ms.append((time.perf_counter() - t0) * 1e3)
+            stages.append(H.hfe_fs_profile_ms(qct, 4))
+    H.hfe_profile(False)
+    st = np.mean(np.array(stages), axis=0)
+    m_db = H.hfe_encode(torch.from_numpy(inp["db_codes"]).to(dev), torch.from_numpy(inp["db_masks"]).to(dev), [0])
+    db = H.hfe_encrypt_db(keys, m_db, DB_SEED, H.HFE_FORM_I8_MFMA)
+    _, ip_fs = H.hfe_decrypt(keys, H.hfe_ccmm(db, qct, 0, w.d1, H.HFE_FORM_I8_MFMA), v=False)
+    q_direct = H.hfe_encrypt(keys, m_q, w.level, Q_SEED)
+    _, ip_direct = H.hfe_decrypt(keys, H.hfe_ccmm(db, q_direct, 0, w.d1, H.HFE_FORM_I8_MFMA), v=False)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(ip_fs, ip_direct))
+    mm = fs_modmuls(w, log_n_t)
+    ceiling = FP64_INSTR_PER_S / FP64_PER_MODMUL
+    ring_rate = mm["ring"] / (st[1] * 1e-3)
+    out = {
+        "workload": w.name, "n_t": 1 << log_n_t, "n_q": 1 << w.log_n_q, "rho": mm["rho"], "level": w.level,
+        "transmission_primes": w.level + 1, "d2": w.d2, "d3": w.d3, "chunks_per_column": mm["k"],
+        "ciphertexts": w.d3 * mm["k"], "ms": float(np.mean(ms)), "ms_min": float(np.min(ms)),
+        "columns_per_s": w.d3 / (float(np.mean(ms)) * 1e-3),
+        "stages_ms": {"digits": float(st[0]), "ring_switch": float(st[1]), "conversion": float(st[2]),
+                      "rescales_output": float(st[3])},
+        "roofline": {"bound": "alu", "kernel": "k_fs_ring", "achieved": ring_rate / 1e12,
+                     "peak": ceiling / 1e12, "unit": "T modmul/s", "frac": ring_rate / ceiling,
+                     "modmuls_per_launch": mm["ring"], "kernel_ms": float(st[1]), "traffic": None},
+        "conversion_modmul_rate_T": mm["conv"] / (st[2] * 1e-3) / 1e12,
+        "keygen_s": t_keys, "transmission_encrypt_ms": t_tx * 1e3, "transmission_bytes": T.numel() * 8,
+        "ccmm_ip_equals_direct_encryption": same,
+    }
+    log(f"format switch: {out['ms']:.2f} ms for {w.d3} columns ({out['columns_per_s']:.0f} columns/s); stages "
+        f"{', '.join(f'{k} {v:.2f}' for k, v in out['stages_ms'].items())} ms; ring switch at "
+        f"{100 * out['roofline']['frac']:.1f}% of the modular-product ceiling; CCMM equals direct: {same}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -446,7 +536,9 @@ def main():
                     help="with --ccmm-only: the int8 form to run (chain: the n^2 modulus chain)")
     ap.add_argument("--lit-steps", type=int, default=3, help="lit mode: timed steps")
     ap.add_argument("--chain-q-mods", type=int, default=7, help="n^2 chain: query moduli (3 more form P)")
-    ap.add_argument("--mode", choices=("step", "batched", "serving", "lit"), default="step",
+    ap.add_argument("--no-fs", action="store_true", help="step mode: skip FormatSwitch")
+    ap.add_argument("--fs-steps", type=int, default=5, help="FormatSwitch: timed switches")
+    ap.add_argument("--mode", choices=("step", "batched", "serving", "lit", "fs"), default="step",
                     help="step: the hot-path step (default); batched: 64 uneven items as one plan; "
                          "serving: Poisson arrivals through the server; lit: the step at N_DB = N_Q = 2^16")
     ap.add_argument("--batch-items", type=int, default=64)
@@ -496,6 +588,9 @@ def main():
         return
     if args.mode == "lit":
         print(json.dumps(run_lit(args, H, torch)), flush=True)
+        return
+    if args.mode == "fs":
+        print(json.dumps(run_format_switch(args, H, torch, steps=args.fs_steps)), flush=True)
         return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -760,6 +855,10 @@ def main():
                                       compare_sequential=False)
     if not args.no_serving:
         line["serving"] = run_serving(args, H, torch, rates=args.default_rates, form_name="rns")
+    if not args.no_fs:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        line["format_switch"] = run_format_switch(args, H, torch, steps=args.fs_steps)
     print(json.dumps(line), flush=True)
 
 

@@ -383,6 +383,46 @@ hfe_status hfe_match(const int32_t* ip, const uint8_t* q_masks, int64_t n_eyes,
 hfe_status hfe_export(const void* handle, int32_t which, size_t offset, uint64_t* dst, size_t n,
                       size_t* count);
 
+/* ---------------------------------------------------------------- FormatSwitch (Appendix C.1)
+ * The query reaches the CCMM from a transmission ring R_{N_T} (N_T = 2^16 in the paper): RLWE
+ * ciphertexts (a, b) modulo Q' = q_0 .. q_l under a transmission secret s_T, one per chunk j of
+ * N_Q code positions of a query column c (ciphertext col = c k + j), the chunk's entries m at the
+ * coefficients of degree divisible by rho = N_T / N_Q:  b = -a s_T + (Delta_l q_l) m~ + e.
+ * FormatSwitch turns them into the query ciphertext of level l that hfe_ccmm takes: a key switch
+ * from s_T to s'(X^rho) (one digit [a (Q'/q_i)^-1]_{q_i} per prime, keys modulo Q' p, rescale by
+ * p) followed by the extraction of the coefficients of degree divisible by rho (the trace: a
+ * ciphertext under s' in R_{N_Q}), the conversion of the k chunks of a column to the MSRLWE format
+ * under the CCMM secrets s_0 .. s_{k-1} (conversion keys whose masks are shared by the k outputs,
+ * rescale by p), and the modulus switch from Q' to q_0 .. q_{l-1} (rescale by q_l), which brings
+ * the scale from Delta_l q_l to Delta_l.
+ * Transmission layout T (uint64 residues): [prime i <= l][col < d3 k][a | b][t < N_T]. */
+typedef struct hfe_fskeys hfe_fskeys;
+
+/* FormatSwitch keys for queries of level `level` (1 <= level < n_q_primes of `keys`: the
+ * transmission modulus takes one prime more) from ring degree 2^log_n_t (log_n_q <= log_n_t <= 16):
+ * s_T, s' and the ring-switching and conversion keys, drawn from `seed` (streams of their own).
+ * Needs keys of the prime family with 6 <= log_n_q <= 14; keeps a reference to `keys` (keep them
+ * alive).  hfe_export(fskeys, 0 | 1) gives s_T (N_T) | s' (N_Q); hfe_shape gives {level,
+ * log_n_t, rho, k}.  Device memory: about 2 (level + 1) (level + 2) N_T doubles of keys. */
+hfe_status hfe_fs_keygen(const hfe_keys* keys, uint32_t level, uint32_t log_n_t, uint64_t seed, hfe_fskeys** out);
+
+/* Number of uint64 in the transmission ciphertexts of d3 query columns: (level+1) d3 k 2 N_T. */
+hfe_status hfe_fs_transmit_count(const hfe_fskeys* fk, int64_t d3, int64_t* count);
+
+/* The client's transmission encryption of M_Q (d3 x d2 ternary, device) into T (device, the count
+ * above), draws from `seed`.  Uses a workspace of d3 k (level + 1) N_T doubles.  HFE_EINVAL for
+ * entries outside {-1, 0, 1} (the call waits for that check). */
+hfe_status hfe_fs_encrypt(const hfe_fskeys* fk, const int8_t* m_q, int64_t d3, uint64_t seed, uint64_t* T,
+                          void* stream);
+
+/* FormatSwitch of the transmission ciphertexts T of d3 query columns (layout above, residues below
+ * their primes; T is only read) into a query ciphertext of level `level` under the CCMM keys, for
+ * hfe_ccmm.  Workspace: d3 k ((level + 1) N_T + 2 (level + 2) N_Q) + 3 (level + 2) d3 N_Q doubles
+ * for k <= 2.  With hfe_profile(1) the query records its stage boundaries, read by
+ * hfe_fs_profile_ms (0: digits, 1: ring switch, 2: conversion, 3: rescales and output). */
+hfe_status hfe_format_switch(const hfe_fskeys* fk, const uint64_t* T, int64_t d3, void* stream, hfe_qct** out);
+hfe_status hfe_fs_profile_ms(const hfe_qct* q, float* ms, int32_t n);
+
 /* Shape queries of a handle (host): dims[0..3] = {level or L, d3 or d1, rows, K}. */
 hfe_status hfe_shape(const void* handle, int64_t* dims);
 

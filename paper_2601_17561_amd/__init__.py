@@ -43,7 +43,8 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_server_submit", "hfe_server_poll", "hfe_server_wait", "hfe_server_drain", "hfe_server_stats", "hfe_server_reset_stats",
             "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes",
             "hfe_ccmm_product", "hfe_probe_rate", "hfe_noalloc_init", "hfe_ccmm_noalloc",
-            "hfe_plan_create_for", "hfe_chain_default_params", "hfe_chain_keygen")
+            "hfe_plan_create_for", "hfe_chain_default_params", "hfe_chain_keygen", "hfe_fs_keygen",
+            "hfe_fs_transmit_count", "hfe_fs_encrypt", "hfe_format_switch", "hfe_fs_profile_ms")
 
 
 class HfeError(RuntimeError):
@@ -148,6 +149,11 @@ _SIGS = {
     "hfe_server_drain": [_vp, _i64],
     "hfe_server_stats": [_vp, ctypes.POINTER(hfe_server_report)],
     "hfe_server_reset_stats": [_vp],
+    "hfe_fs_keygen": [_vp, _u32, _u32, _u64, ctypes.POINTER(_vp)],
+    "hfe_fs_transmit_count": [_vp, _i64, ctypes.POINTER(_i64)],
+    "hfe_fs_encrypt": [_vp, _vp, _i64, _u64, _vp, _vp],
+    "hfe_format_switch": [_vp, _vp, _i64, _vp, ctypes.POINTER(_vp)],
+    "hfe_fs_profile_ms": [_vp, _vp, _i32],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -301,6 +307,46 @@ def hfe_chain_keygen(params: hfe_chain_params, seed: int) -> Handle:
     out = _vp()
     _check(_lib.hfe_chain_keygen(ctypes.byref(params), seed, ctypes.byref(out)), "hfe_chain_keygen")
     return Handle(out.value)
+
+
+def hfe_fs_keygen(keys: Handle, level: int, log_n_t: int, seed: int) -> Handle:
+    """FormatSwitch keys (Appendix C.1) for queries of level `level` from ring degree 2^log_n_t."""
+    out = _vp()
+    _check(_lib.hfe_fs_keygen(keys.ptr, level, log_n_t, seed, ctypes.byref(out)), "hfe_fs_keygen")
+    return Handle(out.value, (keys,))
+
+
+def hfe_fs_transmit_count(fk: Handle, d3: int) -> int:
+    n = _i64()
+    _check(_lib.hfe_fs_transmit_count(fk.ptr, d3, ctypes.byref(n)), "hfe_fs_transmit_count")
+    return int(n.value)
+
+
+def hfe_fs_encrypt(fk: Handle, m_q, seed: int, T=None, stream=None):
+    """Transmission ciphertexts of M_Q (d3 x d2 int8 GPU tensor): uint64 residues as an int64 GPU tensor,
+    layout [prime i <= level][d3 k][a | b][N_T] (flat)."""
+    torch = _torch()
+    d3 = m_q.shape[0]
+    if T is None:
+        T = torch.empty(hfe_fs_transmit_count(fk, d3), dtype=torch.int64, device=m_q.device)
+    _check(_lib.hfe_fs_encrypt(fk.ptr, _dev_ptr(m_q, torch.int8), d3, seed, _dev_ptr(T, torch.int64),
+                               _stream(stream)), "hfe_fs_encrypt")
+    return T
+
+
+def hfe_format_switch(fk: Handle, T, d3: int, stream=None) -> Handle:
+    """Query ciphertext (for hfe_ccmm) from the transmission ciphertexts T of d3 query columns."""
+    torch = _torch()
+    out = _vp()
+    _check(_lib.hfe_format_switch(fk.ptr, _dev_ptr(T, torch.int64), d3, _stream(stream), ctypes.byref(out)),
+           "hfe_format_switch")
+    return Handle(out.value, (fk,))
+
+
+def hfe_fs_profile_ms(q: Handle, n: int = 4):
+    ms = (ctypes.c_float * n)()
+    _check(_lib.hfe_fs_profile_ms(q.ptr, ms, n), "hfe_fs_profile_ms")
+    return [float(x) for x in ms]
 
 
 def hfe_encode(codes, masks, shifts: Sequence[int], out=None, stream=None):

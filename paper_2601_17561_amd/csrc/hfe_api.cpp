@@ -125,12 +125,6 @@ struct Big {  // little-endian 64-bit words
 
 uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
 
-// floor(log2(q_0 ... q_{l-1})) - gap
-int delta_log(const hfe_keys* k, int level) {
-  Big Q(1);
-  for (int i = 0; i < level; ++i) Q.mul(k->family ? k->cmod[i].q : k->primes[i]);
-  return Q.bit_length() - 1 - (int)k->P.gap_bits;
-}
 
 // The n^2 chain: random-stream id of the modulus n^2 (the prime family uses 0..8 and 16).
 uint32_t chain_stream(int32_t n) { return 256u + (uint32_t)n; }
@@ -160,6 +154,15 @@ void garner_consts(const hfe_keys* k, int level, uint64_t garner[HFE_MAX_QPRIMES
   garner_consts_of(k->primes, level, garner, half_digits);
 }
 }  // namespace
+
+// floor(log2(q_0 ... q_{l-1})) - gap
+int delta_log(const hfe_keys* k, int level) {
+  Big Q(1);
+  for (int i = 0; i < level; ++i) Q.mul(k->family ? k->cmod[i].q : k->primes[i]);
+  return Q.bit_length() - 1 - (int)k->P.gap_bits;
+}
+
+bool profiling() { return g_profile.load() != 0; }
 
 // ------------------------------------------------------------------ validation
 static hfe_status check_params(const hfe_params* P) {
@@ -198,6 +201,32 @@ static T* as_handle(const void* h, uint32_t kind) {
   if (!h) return nullptr;
   const HandleBase* b = static_cast<const HandleBase*>(h);
   return b->kind == kind ? static_cast<T*>(const_cast<void*>(h)) : nullptr;
+}
+
+
+static uint32_t* pinned_flag() {
+  thread_local uint32_t* p = nullptr;
+  if (!p && hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
+    p = nullptr;
+  return p;
+}
+
+hfe_status check_ternary_begin(const int8_t* m, int64_t n, hipStream_t s, TernaryCheck& c) {
+  c.host = pinned_flag();
+  if (!c.host) return fail(HFE_ENOMEM, "pinned host allocation failed");
+  HFE_TRY(c.flag.alloc(sizeof(uint32_t), s));
+  HFE_LAUNCH(hipMemsetAsync(c.flag.ptr, 0, sizeof(uint32_t), s));
+  HFE_LAUNCH(launch_check_ternary(m, n, c.flag.as<uint32_t>(), s));
+  HFE_LAUNCH(hipMemcpyAsync(c.host, c.flag.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HFE_LAUNCH(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
+  HFE_LAUNCH(hipEventRecord(c.ev, s));
+  return HFE_OK;
+}
+
+hfe_status check_ternary_end(TernaryCheck& c, const char* what) {
+  HFE_LAUNCH(hipEventSynchronize(c.ev));
+  if (*c.host) return fail(HFE_EINVAL, std::string(what) + " has entries outside {-1, 0, 1}");
+  return HFE_OK;
 }
 
 }  // namespace hfe
@@ -701,45 +730,6 @@ static hfe_status encrypt_db_impl(const hfe_keys* K, const int8_t* m_db, int64_t
       HFE_LAUNCH(launch_split_db_p2(Dz, D->K, D->R, D->KB, D->R_pad, K->primes[z], D->n_p2,
                                     D->p2.as<int8_t>() + (size_t)z * 2 * D->n_p2 * plane, s));
   }
-  return HFE_OK;
-}
-
-// Entries of a ternary input outside {-1, 0, 1} (they would break the bound |M m| <= d2 that the
-// scale leaves room for).  begin enqueues a check kernel and the copy of its flag into a pinned
-// word; the caller then enqueues its own work, and end waits for the check alone (an event after
-// the copy), so the device never idles for it.  The pinned word is one per host thread, kept
-// until the process ends; a call waits for it before returning, so calls never share it.
-struct TernaryCheck {
-  DevBuf flag;
-  hipEvent_t ev = nullptr;
-  uint32_t* host = nullptr;
-  ~TernaryCheck() {
-    if (ev) (void)hipEventDestroy(ev);
-  }
-};
-
-static uint32_t* pinned_flag() {
-  thread_local uint32_t* p = nullptr;
-  if (!p && hipHostMalloc(reinterpret_cast<void**>(&p), sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
-    p = nullptr;
-  return p;
-}
-
-static hfe_status check_ternary_begin(const int8_t* m, int64_t n, hipStream_t s, TernaryCheck& c) {
-  c.host = pinned_flag();
-  if (!c.host) return fail(HFE_ENOMEM, "pinned host allocation failed");
-  HFE_TRY(c.flag.alloc(sizeof(uint32_t), s));
-  HFE_LAUNCH(hipMemsetAsync(c.flag.ptr, 0, sizeof(uint32_t), s));
-  HFE_LAUNCH(launch_check_ternary(m, n, c.flag.as<uint32_t>(), s));
-  HFE_LAUNCH(hipMemcpyAsync(c.host, c.flag.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  HFE_LAUNCH(hipEventCreateWithFlags(&c.ev, hipEventDisableTiming));
-  HFE_LAUNCH(hipEventRecord(c.ev, s));
-  return HFE_OK;
-}
-
-static hfe_status check_ternary_end(TernaryCheck& c, const char* what) {
-  HFE_LAUNCH(hipEventSynchronize(c.ev));
-  if (*c.host) return fail(HFE_EINVAL, std::string(what) + " has entries outside {-1, 0, 1}");
   return HFE_OK;
 }
 
@@ -2176,6 +2166,12 @@ hfe_status hfe_export(const void* handle, int32_t which, size_t offset, uint64_t
     total = (size_t)D->slots_plain * D->R * D->K;
     dev = D->Dt.ptr;
     if (dst && !dev) return fail(HFE_EINVAL, "database kept no uint64 residues (plain form not requested)");
+  } else if (kind == kFsKeys) {
+    const hfe_fskeys* F = static_cast<const hfe_fskeys*>(handle);
+    if (which != 0 && which != 1) return fail(HFE_EINVAL, "FormatSwitch keys export: which must be 0 or 1");
+    const std::vector<int8_t>& src = which == 0 ? F->st_host : F->sr_host;
+    total = src.size();
+    host8 = src.data();
   } else if (kind == kQct) {
     const hfe_qct* Q = static_cast<const hfe_qct*>(handle);
     if (which != 0) return fail(HFE_EINVAL, "qct export: which must be 0");
@@ -2214,6 +2210,12 @@ hfe_status hfe_shape(const void* handle, int64_t* dims) {
     dims[1] = D->d1;
     dims[2] = D->R;
     dims[3] = D->K;
+  } else if (kind == kFsKeys) {
+    const hfe_fskeys* F = static_cast<const hfe_fskeys*>(handle);
+    dims[0] = F->C.level;
+    dims[1] = F->C.logn_t;
+    dims[2] = F->C.rho;
+    dims[3] = F->C.k;
   } else if (kind == kQct) {
     const hfe_qct* Q = static_cast<const hfe_qct*>(handle);
     dims[0] = Q->level;
@@ -2259,6 +2261,10 @@ void hfe_free(void* handle) {
       break;
     case kServer:
       destroy_server(handle);
+      break;
+    case kFsKeys:
+      b->kind = 0;
+      delete static_cast<hfe_fskeys*>(handle);
       break;
     default:
       break;

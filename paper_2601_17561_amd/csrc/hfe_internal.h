@@ -96,7 +96,8 @@ struct NttTabOwner {
 
 // ------------------------------------------------------------------ handles
 enum Kind : uint32_t {
-  kKeys = 0x4b455953, kDb = 0x44422020, kQct = 0x51435420, kRct = 0x52435420, kPlan = 0x504c414e, kServer = 0x53525652
+  kKeys = 0x4b455953, kDb = 0x44422020, kQct = 0x51435420, kRct = 0x52435420, kPlan = 0x504c414e, kServer = 0x53525652,
+  kFsKeys = 0x46534b59
 };
 
 struct HandleBase {
@@ -156,6 +157,11 @@ struct hfe_qct : hfe::HandleBase {
   int level;
   int64_t d3, K;
   hfe::DevBuf XT;                          // [level][d3][K] uint64: row c = [b_c | a_c]
+  hipEvent_t ev[5] = {};                   // FormatSwitch stage boundaries when profiling
+  ~hfe_qct() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 struct hfe_rct : hfe::HandleBase {
@@ -608,4 +614,92 @@ void destroy_server(void* handle);  // hfe_server.cpp
 // rescaled result written to out; HFE_ENOMEM (nothing enqueued) if the call needs more.
 hfe_status ccmm_region(const hfe_db* db, const hfe_qct* q, int64_t row0, int64_t rows, int32_t form,
                        hipStream_t s, uint64_t* out, void* region, size_t cap);
+}  // namespace hfe
+
+namespace hfe {
+// Entries of a ternary input outside {-1, 0, 1} (they would break the bound |M m| <= d2 that the
+// scale leaves room for).  begin enqueues a check kernel and the copy of its flag into a pinned
+// word; the caller then enqueues its own work, and end waits for the check alone (an event after
+// the copy), so the device never idles for it.  The pinned word is one per host thread, kept
+// until the process ends; a call waits for it before returning, so calls never share it.
+struct TernaryCheck {
+  DevBuf flag;
+  hipEvent_t ev = nullptr;
+  uint32_t* host = nullptr;
+  ~TernaryCheck() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+hfe_status check_ternary_begin(const int8_t* m, int64_t n, hipStream_t s, TernaryCheck& c);
+hfe_status check_ternary_end(TernaryCheck& c, const char* what);
+int delta_log(const hfe_keys* k, int level);  // floor(log2(q_0 ... q_{l-1})) - gap
+bool profiling();                             // hfe_profile(1) in effect
+}  // namespace hfe
+
+// ------------------------------------------------------------------ FormatSwitch (Appendix C.1)
+namespace hfe {
+// Stream purposes of the FormatSwitch draws: transmission secret s_T, ring-switch secret s', masks and
+// errors of the ring-switching keys, of the conversion keys and of the transmission ciphertexts.
+enum : uint64_t { kTSec = 7, kRSec = 8, kRkA = 9, kRkE = 10, kCkA = 11, kCkE = 12, kTxA = 13, kTxE = 14 };
+
+// Slots of a FormatSwitch at CCMM level l: q_0 .. q_l (the transmission modulus Q'), then p.
+struct FsConsts {
+  int level;                     // l
+  int nz;                        // l + 2
+  int k;                         // chunks of N_Q code positions per query column
+  int rho;                       // N_T / N_Q
+  int logn_q, logn_t;
+  int64_t d2;
+  double zd[kMaxPrimes], zinv[kMaxPrimes];  // slot moduli and RN(1 / z)
+  double ghat[kMaxPrimes];       // digit factor ((Q' / q_i) mod q_i)^-1 mod q_i, i <= l
+  double pinv[kMaxPrimes];       // p^-1 mod q_i, i <= l
+  double qlinv[kMaxPrimes];      // q_l^-1 mod q_i, i < l
+  double scale[kMaxPrimes];      // Delta_l q_l mod q_i, i <= l (transmission scale)
+  uint64_t gk[kMaxPrimes][kMaxPrimes];  // [z][i]: gadget p (Q' / q_i) mod z
+  uint32_t pid[kMaxPrimes];      // random-stream id of slot z
+  Mod mod[kMaxPrimes];           // slot z
+  NttTab tab[kMaxPrimes];        // ring N_Q, slot z
+};
+}  // namespace hfe
+
+struct hfe_fskeys : hfe::HandleBase {
+  const hfe_keys* keys;
+  hfe::FsConsts C;
+  std::vector<int8_t> st_host;   // s_T, N_T ternary coefficients
+  std::vector<int8_t> sr_host;   // s', N_Q ternary coefficients
+  hfe::DevBuf st;                // s_T (int8, N_T)
+  hfe::DevBuf rk;                // [z][i <= l][mask | key][rho][N_Q] doubles: NTT of the key parts, see k_fswitch.hip
+  hfe::DevBuf ck;                // [z][i <= l][j < k][1 + k][N_Q] doubles: NTT of k_ij, beta_ij0 .. beta_ij(k-1)
+  hfe::DevBuf st_hat;            // [i <= l][rho][N_Q] uint64: NTT of the polyphase parts of s_T
+  hfe::DevBuf y_hat;             // [i <= l][N_Q] uint64: NTT of the monomial Y
+  hfe::DevBuf cdt;               // the Gaussian table (19 uint64)
+};
+
+namespace hfe {
+// Key material: out = [z][i][2][rho][N_Q] (rk) or [z][i][j][1 + k][N_Q] (ck) coefficient residues
+// before their transforms; then the finishing passes write the doubles of the NTT-domain keys.
+hipError_t launch_fs_rk_coeffs(const FsConsts& C, uint64_t seed, const int8_t* st, const uint64_t* cdt,
+                               uint64_t* out, hipStream_t s);
+hipError_t launch_fs_rk_finish(const FsConsts& C, const uint64_t* coef_hat, const uint64_t* sr_hat,
+                               double* rk, hipStream_t s);
+hipError_t launch_fs_ck_coeffs(const FsConsts& C, uint64_t seed, const int8_t* sr, const uint64_t* cdt,
+                               uint64_t* out, hipStream_t s);
+// s_hat: the CCMM secrets' transforms, [prime][k][2 N_Q] uint64 (values, then Shoup companions), p at
+// prime index p_index.
+hipError_t launch_fs_ck_finish(const FsConsts& C, const uint64_t* coef_hat, const uint64_t* s_hat, int p_index,
+                               double* ck, hipStream_t s);
+// Transmission encryption of ncols = d3 k ciphertexts; Ahat scratch [ncols][l + 1][rho][N_Q] doubles.
+hipError_t launch_fs_tx(const FsConsts& C, uint64_t seed, const int8_t* m_q, int64_t d3, const uint64_t* st_hat,
+                        const uint64_t* y_hat, const uint64_t* cdt, double* Ahat, uint64_t* T, hipStream_t s);
+// The switch: digits Dg [ncols][l + 1][rho][N_Q] doubles; ring-switched Aring, Bring [nz][ncols][N_Q];
+// converted Aconv [nz][d3][N_Q], Bconv [nz][d3][k][N_Q] (doubles); XT the query ciphertext.
+struct FsWork {
+  double* Dg;
+  double* Aring;
+  double* Bring;
+  double* Aconv;
+  double* Bconv;
+};
+hipError_t launch_fs_switch(const FsConsts& C, const uint64_t* T, int64_t d3, const double* rk, const double* ck,
+                            const FsWork& w, uint64_t* XT, int64_t K, hipStream_t s, hipEvent_t* ev);
 }  // namespace hfe

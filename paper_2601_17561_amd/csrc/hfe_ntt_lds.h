@@ -1,0 +1,169 @@
+// LDS-resident negacyclic NTT (ring degrees up to 2^14) shared by the kernels that transform one
+// polynomial per workgroup: the merged transforms of Longa and Naehrig (2016), forward Cooley-Tukey
+// with twiddles psi^brv(i) (output in bit-reversed order), inverse Gentleman-Sande with psi^-brv(i)
+// and a final 1/n scale.  Residues mod a 36-bit prime are held as doubles (exact integers below 2^36)
+// and multiplied with the error-free fp64 product mulmod_d of hfe_exact.h.
+#pragma once
+#include <type_traits>
+
+#include "hfe_internal.h"
+
+namespace hfe {
+constexpr int kNttThreads = 1024;
+
+// ------------------------------------------------------------------ fp64 residue arithmetic
+// Residues mod q < 2^36 as doubles holding exact integers in [0, q); products by mulmod_d
+// (hfe_exact.h).
+__device__ __forceinline__ double to_d(uint64_t x) { return (double)x; }    // exact below 2^53
+__device__ __forceinline__ uint64_t to_u(double x) { return (uint64_t)x; }  // x an integer in [0, q)
+
+// Both transforms run in rounds of up to three butterfly stages: a thread loads a group of 2^S
+// coefficients into registers, applies S stages there and stores them back, so a transform of
+// degree 2^logn takes ceil(logn / 3) LDS passes and barriers instead of logn.
+//
+// Forward (Cooley-Tukey) round with first half-size t: group g holds a[base + k stride], k < 2^S,
+// stride = t / 2^(S-1), base = B 2t + r (B = g / stride, r = g mod stride).  Stage s (half-size
+// t / 2^s, m = n / (2t) 2^s blocks) pairs k and k + 2^(S-1-s); the pair lies in block
+// B 2^s + (k >> (S - s)), whose twiddle is psi[m + block].
+template <int S>
+__device__ __forceinline__ void fwd_round(double* a, const NttTab& T, int n, int t) {
+  constexpr int G = 1 << S;
+  const double q = T.qd, qinv = T.qinv;
+  const int stride = t >> (S - 1), m1 = n / (2 * t);
+  for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
+    const int B = g / stride, r = g - B * stride;
+    const int base = B * 2 * t + r;
+    double x[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) x[k] = a[base + k * stride];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int h = 1 << (S - 1 - s);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        if (k & h) continue;
+        const int w = (m1 << s) + (B << s) + (k >> (S - s));
+        const double U = x[k];
+        const double V = mulmod_d(x[k + h], T.psi_d[w], q, qinv);
+        x[k] = addmod_d(U, V, q);
+        x[k + h] = submod_d(U, V, q);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) a[base + k * stride] = x[k];
+  }
+  __syncthreads();
+}
+
+// Inverse (Gentleman-Sande) round with first half-size t: group g holds a[base + k t], k < 2^S,
+// base = B 2^S t + r (B = g / t, r = g mod t).  Stage s (half-size 2^s t, m = n / (2^(s+1) t)
+// blocks) pairs k and k + 2^s; the pair lies in block B 2^(S-1-s) + (k >> (s + 1)), twiddle
+// ipsi[m + block].  With scale, the round ends with the 1/n factor.
+template <int S>
+__device__ __forceinline__ void inv_round(double* a, const NttTab& T, int n, int t, bool scale) {
+  constexpr int G = 1 << S;
+  const double q = T.qd, qinv = T.qinv;
+  for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
+    const int B = g / t, r = g - B * t;
+    const int base = B * G * t + r;
+    double x[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) x[k] = a[base + k * t];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int h = 1 << s;
+      const int m = n / (2 * h * t);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        if (k & h) continue;
+        const int w = m + (B << (S - 1 - s)) + (k >> (s + 1));
+        const double U = x[k], V = x[k + h];
+        x[k] = addmod_d(U, V, q);
+        x[k + h] = mulmod_d(submod_d(U, V, q), T.ipsi_d[w], q, qinv);
+      }
+    }
+    if (scale) {
+#pragma unroll
+      for (int k = 0; k < G; ++k) x[k] = mulmod_d(x[k], T.n_inv_d, q, qinv);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) a[base + k * t] = x[k];
+  }
+  __syncthreads();
+}
+
+// Forward negacyclic NTT in place (output in bit-reversed order).
+__device__ __forceinline__ void ntt_fwd_lds(double* a, const NttTab& T) {
+  const int n = 1 << T.logn;
+  int t = n >> 1, left = T.logn;
+  while (left > 0) {
+    if (left >= 3) {
+      fwd_round<3>(a, T, n, t);
+      t >>= 3;
+      left -= 3;
+    } else if (left == 2) {
+      fwd_round<2>(a, T, n, t);
+      t >>= 2;
+      left -= 2;
+    } else {
+      fwd_round<1>(a, T, n, t);
+      t >>= 1;
+      left -= 1;
+    }
+  }
+}
+
+// Inverse negacyclic NTT in place (input in bit-reversed order), including the 1/n factor.
+__device__ __forceinline__ void ntt_inv_lds(double* a, const NttTab& T) {
+  const int n = 1 << T.logn;
+  int t = 1, left = T.logn;
+  while (left > 0) {
+    if (left >= 3) {
+      inv_round<3>(a, T, n, t, left == 3);
+      t <<= 3;
+      left -= 3;
+    } else if (left == 2) {
+      inv_round<2>(a, T, n, t, true);
+      t <<= 2;
+      left -= 2;
+    } else {
+      inv_round<1>(a, T, n, t, true);
+      t <<= 1;
+      left -= 1;
+    }
+  }
+}
+
+static int ntt_block(int logn) {
+  int half = 1 << (logn > 0 ? logn - 1 : 0);
+  int b = half < 64 ? 64 : half;
+  return b > kNttThreads ? kNttThreads : b;
+}
+
+template <class K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// R: NTT-domain coefficients each thread keeps in registers, n / blockDim (1 .. 16 for n <= 2^14),
+// a template parameter so that the register arrays are no larger than the transform needs.
+static int regs_per_thread(int logn) {
+  const int r = (1 << logn) / ntt_block(logn);
+  return r < 1 ? 1 : r;
+}
+// f(std::integral_constant<int, R>{}) for the runtime count r
+template <class F>
+static hipError_t by_regs(int r, F f) {
+  switch (r) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace hfe

@@ -105,3 +105,41 @@ def chain_case(name: str, level: int = -1) -> ChainCase:
     v, ip = OCH.decrypt(C, keys, out, level, 0, w.d1)
     ip_true, ov = OI.truth(qc, qm, inp["db_codes"], inp["db_masks"])
     return ChainCase(w, C, keys, inp, m_db, qc, qm, m_q, D, XT, level, out, v, ip, ip_true, ov)
+
+
+TX_SEED = 404      # seed of the transmission encryption in the FormatSwitch cases
+
+
+@dataclasses.dataclass
+class FsCase:
+    w: S.Workload
+    log_n_t: int
+    P: OP.Params
+    F: object                 # oracle.formatswitch.FSKeys
+    inputs: Dict
+    q_codes: np.ndarray
+    q_masks: np.ndarray
+    m_q: np.ndarray
+    T: np.ndarray             # [prime i <= level][d3 k][a | b][N_T], the library's layout
+    XT: np.ndarray            # [prime i < level][d3][d2 + N_Q]
+    ip_true: np.ndarray       # popcount truth of every query column against every database code
+
+
+@functools.lru_cache(maxsize=None)
+def fs_case(name: str) -> FsCase:
+    """FormatSwitch (Appendix C.1) of a workload's queries: keys from KEY_SEED (the CCMM keys and the
+    switch's own), transmission ciphertexts from TX_SEED, the switched query, the popcount truth."""
+    from oracle import formatswitch as FS
+    w = S.WORKLOADS[name]
+    log_n_t = S.FS_LOG_N_T[name]
+    P = params_for(w)
+    F = FS.fs_keygen(P, w.level, log_n_t, KEY_SEED)
+    inp = S.make_inputs(w)
+    qc, qm = OI.shifted_queries(inp["q_codes"], inp["q_masks"], inp["shifts"])
+    m_q = OI.ternary(qc, qm)
+    ct = FS.encrypt_transmit(F, m_q, TX_SEED)
+    XTd = FS.format_switch(F, ct, m_q.shape[0])
+    T = np.stack([ct[q] for q in F.primes_in()])
+    XT = np.stack([XTd[i] for i in range(w.level)])
+    ip_true, _ = OI.truth(qc, qm, inp["db_codes"], inp["db_masks"])
+    return FsCase(w, log_n_t, P, F, inp, qc, qm, m_q, T, XT, ip_true)
