@@ -25,10 +25,46 @@ __device__ __forceinline__ uint64_t to_u(double x) { return (uint64_t)x; }  // x
 // stride = t / 2^(S-1), base = B 2t + r (B = g / stride, r = g mod stride).  Stage s (half-size
 // t / 2^s, m = n / (2t) 2^s blocks) pairs k and k + 2^(S-1-s); the pair lies in block
 // B 2^s + (k >> (S - s)), whose twiddle is psi[m + block].
+// The S stages of one forward round on the group held in registers x[0 .. 2^S) (first twiddle block
+// m1 = n / (2t), group block B as above).
 template <int S>
-__device__ __forceinline__ void fwd_round(double* a, const NttTab& T, int n, int t) {
+__device__ __forceinline__ void fwd_stages(double* x, const NttTab& T, int m1, int B) {
   constexpr int G = 1 << S;
   const double q = T.qd, qinv = T.qinv;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int h = 1 << (S - 1 - s);
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      if (k & h) continue;
+      const int w = (m1 << s) + (B << s) + (k >> (S - s));
+      const double U = x[k];
+      const double V = mulmod_d(x[k + h], T.psi_d[w], q, qinv);
+      x[k] = addmod_d(U, V, q);
+      x[k + h] = submod_d(U, V, q);
+    }
+  }
+}
+
+// The same stages on values kept in [0, 4q) (ct_butterfly_lazy): inputs below 4q, outputs below 4q.
+template <int S>
+__device__ __forceinline__ void fwd_stages_lazy(double* x, const NttTab& T, int m1, int B) {
+  constexpr int G = 1 << S;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int h = 1 << (S - 1 - s);
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      if (k & h) continue;
+      const int w = (m1 << s) + (B << s) + (k >> (S - s));
+      ct_butterfly_lazy(x[k], x[k + h], T.psi_d[w], T.qd, T.qinv);
+    }
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void fwd_round_lazy(double* a, const NttTab& T, int n, int t) {
+  constexpr int G = 1 << S;
   const int stride = t >> (S - 1), m1 = n / (2 * t);
   for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
     const int B = g / stride, r = g - B * stride;
@@ -36,19 +72,24 @@ __device__ __forceinline__ void fwd_round(double* a, const NttTab& T, int n, int
     double x[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) x[k] = a[base + k * stride];
+    fwd_stages_lazy<S>(x, T, m1, B);
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int h = 1 << (S - 1 - s);
+    for (int k = 0; k < G; ++k) a[base + k * stride] = x[k];
+  }
+  __syncthreads();
+}
+
+template <int S>
+__device__ __forceinline__ void fwd_round(double* a, const NttTab& T, int n, int t) {
+  constexpr int G = 1 << S;
+  const int stride = t >> (S - 1), m1 = n / (2 * t);
+  for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
+    const int B = g / stride, r = g - B * stride;
+    const int base = B * 2 * t + r;
+    double x[G];
 #pragma unroll
-      for (int k = 0; k < G; ++k) {
-        if (k & h) continue;
-        const int w = (m1 << s) + (B << s) + (k >> (S - s));
-        const double U = x[k];
-        const double V = mulmod_d(x[k + h], T.psi_d[w], q, qinv);
-        x[k] = addmod_d(U, V, q);
-        x[k + h] = submod_d(U, V, q);
-      }
-    }
+    for (int k = 0; k < G; ++k) x[k] = a[base + k * stride];
+    fwd_stages<S>(x, T, m1, B);
 #pragma unroll
     for (int k = 0; k < G; ++k) a[base + k * stride] = x[k];
   }

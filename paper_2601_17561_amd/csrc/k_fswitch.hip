@@ -285,9 +285,78 @@ __global__ void k_fs_digits(FsConsts C, const uint64_t* T, int64_t ncols, double
   }
 }
 
+// Forward transforms fused with their load and their use.  With blockDim = n / (8 GPT), the first
+// round (S0 = (log n - 1) mod 3 + 1 stages, t = n / 2: group g holds the coefficients g + k n / 2^S0)
+// reads its coefficients from global memory into registers, the middle rounds of three stages run
+// through LDS, and the last round (t = 4: group g holds the contiguous coefficients 8g .. 8g + 7 of
+// the bit-reversed output) stays in registers, where the caller multiplies by the keys: two LDS
+// passes and two barriers fewer per transform than a load, the transform and a reload.  The
+// butterflies reduce lazily (values below 4q, hfe_exact.h): the transform's outputs are congruent to
+// the exact ones and below 4q, which the lazy products of the multiply-accumulate take as they are.
+
+// First round: loads every value this thread's groups need (before the barrier that lets it
+// overwrite LDS), then the S0 stages and the store.
+template <int GPT, int S0, class Load>
+__device__ __forceinline__ void fused_first_round(double* lds, const NttTab& T, Load load) {
+  constexpr int G = 1 << S0;
+  constexpr int M = 8 * GPT / G;  // groups per thread
+  const int n = 1 << T.logn, ng = n >> S0;
+  double y[M][G];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int k = 0; k < G; ++k) y[m][k] = load(threadIdx.x + m * blockDim.x + k * ng);
+  __syncthreads();  // the previous transform's last round has read LDS
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int g = threadIdx.x + m * blockDim.x;
+    fwd_stages_lazy<S0>(y[m], T, 1, 0);
+#pragma unroll
+    for (int k = 0; k < G; ++k) lds[g + k * ng] = y[m][k];
+  }
+  __syncthreads();
+}
+
+template <int GPT, int S0, class Load>
+__device__ __forceinline__ void ntt_fwd_fused(double* lds, const NttTab& T, Load load, double (&x)[GPT][8]) {
+  const int n = 1 << T.logn;
+  fused_first_round<GPT, S0>(lds, T, load);
+  for (int t = (n >> 1) >> S0; t > 4; t >>= 3) fwd_round_lazy<3>(lds, T, n, t);
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) {
+    const int g = threadIdx.x + j * blockDim.x;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[j][k] = lds[8 * g + k];
+    fwd_stages_lazy<3>(x[j], T, n >> 3, g);
+  }
+}
+
+// acc (below 2q) + x w (x below 4q), kept below 2q.
+__device__ __forceinline__ double mac_lazy(double acc, double x, double w, double q, double qinv) {
+  const double s = acc + mulmod_lazy_d(x, w, q, qinv);
+  return s >= q + q ? s - (q + q) : s;
+}
+
+// Inverse transform of the values x (positions 8g + k as above) through LDS, written to out in
+// natural order; x below 2q (the lazy accumulators).
+template <int GPT>
+__device__ __forceinline__ void ntt_inv_store(double* lds, const NttTab& T, const double (&x)[GPT][8], double* out) {
+  const int n = 1 << T.logn;
+  __syncthreads();  // earlier readers of LDS are done
+#pragma unroll
+  for (int j = 0; j < GPT; ++j) {
+    const int g = threadIdx.x + j * blockDim.x;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) lds[8 * g + k] = x[j][k] >= T.qd ? x[j][k] - T.qd : x[j][k];
+  }
+  __syncthreads();
+  ntt_inv_lds(lds, T);
+  for (int v = threadIdx.x; v < n; v += blockDim.x) out[v] = lds[v];
+}
+
 // Workgroup (col, z): the ring switch of ciphertext col in slot z, before RS_p:
 // Aring = sum_{i, r} d_{i,r} K~mask_{z,i,r},  Bring = sum_{i, r} d_{i,r} K~key_{z,i,r}  (in R_{N_Q}).
-template <int R>
+template <int GPT, int S0>
 __global__ void __launch_bounds__(kNttThreads)
 k_fs_ring(FsConsts C, int64_t ncols, const double* Dg, const double* rk, double* Aring, double* Bring) {
   extern __shared__ double lds[];
@@ -297,50 +366,39 @@ k_fs_ring(FsConsts C, int64_t ncols, const double* Dg, const double* rk, double*
   const int64_t col = f / C.nz;
   const int z = (int)(f - col * C.nz);
   const int nq = 1 << C.logn_q;
+  const NttTab& T = C.tab[z];
   const double q = C.zd[z], qinv = C.zinv[z];
-  double accA[R], accB[R];
+  double accA[GPT][8], accB[GPT][8], x[GPT][8];
 #pragma unroll
-  for (int k = 0; k < R; ++k) accA[k] = accB[k] = 0.0;
+  for (int j = 0; j < GPT; ++j)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) accA[j][k] = accB[j][k] = 0.0;
   for (int i = 0; i <= C.level; ++i) {
     for (int r = 0; r < C.rho; ++r) {
       const double* src = Dg + (((size_t)col * (C.level + 1) + i) * C.rho + r) * nq;
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const int v = threadIdx.x + k * blockDim.x;
-        lds[v] = red_once(src[v], q);
-      }
-      __syncthreads();
-      ntt_fwd_lds(lds, C.tab[z]);
+      ntt_fwd_fused<GPT, S0>(lds, T, [&](int pos) { return red_once(src[pos], q); }, x);
       const double* ka = rk + (((size_t)z * (C.level + 1) + i) * 2 * C.rho + r) * nq;
       const double* kb = ka + (size_t)C.rho * nq;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const int v = threadIdx.x + k * blockDim.x;
-        const double x = lds[v];
-        accA[k] = addmod_d(accA[k], mulmod_d(x, ka[v], q, qinv), q);
-        accB[k] = addmod_d(accB[k], mulmod_d(x, kb[v], q, qinv), q);
+      for (int j = 0; j < GPT; ++j) {
+        const int v0 = 8 * (threadIdx.x + j * blockDim.x);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          accA[j][k] = mac_lazy(accA[j][k], x[j][k], ka[v0 + k], q, qinv);
+          accB[j][k] = mac_lazy(accB[j][k], x[j][k], kb[v0 + k], q, qinv);
+        }
       }
     }
   }
-  for (int part = 0; part < 2; ++part) {
-#pragma unroll
-    for (int k = 0; k < R; ++k) lds[threadIdx.x + k * blockDim.x] = part ? accB[k] : accA[k];
-    __syncthreads();
-    ntt_inv_lds(lds, C.tab[z]);
-    double* o = (part ? Bring : Aring) + ((size_t)z * ncols + col) * nq;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int v = threadIdx.x + k * blockDim.x;
-      o[v] = lds[v];
-    }
-  }
+  ntt_inv_store<GPT>(lds, T, accA, Aring + ((size_t)z * ncols + col) * nq);
+  ntt_inv_store<GPT>(lds, T, accB, Bring + ((size_t)z * ncols + col) * nq);
 }
 
 // Workgroup (c, z, g): the conversion of column c's k chunks in slot z, before RS_p, for the outputs
 // j' in [2g, 2g + 2) (and the shared mask when g = 0):
 // Aconv = sum_{i, j} d_i(a'_j) k_ij,  Bconv_j' = sum_{i, j} d_i(a'_j) beta_ij'.
-// The chunks' masks a'_j = RS_p(Aring) are formed as they are loaded.
-template <int R>
+// The chunks' masks a'_j = RS_p(Aring) and their digits are formed as the transforms load them.
+template <int GPT, int S0>
 __global__ void __launch_bounds__(kNttThreads)
 k_fs_conv(FsConsts C, int64_t d3, const double* Aring, const double* ck, double* Aconv, double* Bconv) {
   extern __shared__ double lds[];
@@ -354,51 +412,43 @@ k_fs_conv(FsConsts C, int64_t d3, const double* Aring, const double* ck, double*
   const int nq = 1 << C.logn_q;
   const int64_t ncols = d3 * C.k;
   const int l = C.level;
+  const NttTab& T = C.tab[z];
   const double q = C.zd[z], qinv = C.zinv[z], pd = C.zd[l + 1];
   const int j0 = 2 * g;
   const int nb = C.k - j0 < 2 ? C.k - j0 : 2;
-  double accA[R], accB[2][R];
+  double accA[GPT][8], accB0[GPT][8], accB1[GPT][8], x[GPT][8];
 #pragma unroll
-  for (int k = 0; k < R; ++k) accA[k] = accB[0][k] = accB[1][k] = 0.0;
+  for (int jj = 0; jj < GPT; ++jj)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) accA[jj][k] = accB0[jj][k] = accB1[jj][k] = 0.0;
   for (int j = 0; j < C.k; ++j) {
     const int64_t col = c * C.k + j;
     const double* Ap = Aring + ((size_t)(l + 1) * ncols + col) * nq;
     for (int i = 0; i <= l; ++i) {
       const double* Ai = Aring + ((size_t)i * ncols + col) * nq;
-      const double qi = C.zd[i], qiinv = C.zinv[i];
-#pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const int v = threadIdx.x + k * blockDim.x;
-        const double a1 = rs_d(Ai[v], Ap[v], pd, qi, qiinv, C.pinv[i]);
-        lds[v] = red_once(mulmod_d(a1, C.ghat[i], qi, qiinv), q);
-      }
-      __syncthreads();
-      ntt_fwd_lds(lds, C.tab[z]);
+      const double qi = C.zd[i], qiinv = C.zinv[i], pinv = C.pinv[i], gh = C.ghat[i];
+      ntt_fwd_fused<GPT, S0>(
+          lds, T,
+          [&](int v) { return red_once(mulmod_d(rs_d(Ai[v], Ap[v], pd, qi, qiinv, pinv), gh, qi, qiinv), q); }, x);
       const double* kk = ck + (((size_t)z * (l + 1) + i) * C.k + j) * (1 + C.k) * nq;
+      const double* kb0 = kk + (size_t)(1 + j0) * nq;
+      const double* kb1 = kk + (size_t)(nb > 1 ? 2 + j0 : 1 + j0) * nq;
 #pragma unroll
-      for (int k = 0; k < R; ++k) {
-        const int v = threadIdx.x + k * blockDim.x;
-        const double x = lds[v];
-        if (g == 0) accA[k] = addmod_d(accA[k], mulmod_d(x, kk[v], q, qinv), q);
-        accB[0][k] = addmod_d(accB[0][k], mulmod_d(x, kk[(size_t)(1 + j0) * nq + v], q, qinv), q);
-        if (nb > 1) accB[1][k] = addmod_d(accB[1][k], mulmod_d(x, kk[(size_t)(2 + j0) * nq + v], q, qinv), q);
+      for (int jj = 0; jj < GPT; ++jj) {
+        const int v0 = 8 * (threadIdx.x + jj * blockDim.x);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const double xv = x[jj][k];
+          if (g == 0) accA[jj][k] = mac_lazy(accA[jj][k], xv, kk[v0 + k], q, qinv);
+          accB0[jj][k] = mac_lazy(accB0[jj][k], xv, kb0[v0 + k], q, qinv);
+          if (nb > 1) accB1[jj][k] = mac_lazy(accB1[jj][k], xv, kb1[v0 + k], q, qinv);
+        }
       }
     }
   }
-  for (int part = (g == 0 ? 0 : 1); part <= nb; ++part) {
-#pragma unroll
-    for (int k = 0; k < R; ++k)
-      lds[threadIdx.x + k * blockDim.x] = part == 0 ? accA[k] : (part == 1 ? accB[0][k] : accB[1][k]);
-    __syncthreads();
-    ntt_inv_lds(lds, C.tab[z]);
-    double* o = part == 0 ? Aconv + ((size_t)z * d3 + c) * nq
-                          : Bconv + (((size_t)z * d3 + c) * C.k + (j0 + part - 1)) * nq;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const int v = threadIdx.x + k * blockDim.x;
-      o[v] = lds[v];
-    }
-  }
+  if (g == 0) ntt_inv_store<GPT>(lds, T, accA, Aconv + ((size_t)z * d3 + c) * nq);
+  ntt_inv_store<GPT>(lds, T, accB0, Bconv + (((size_t)z * d3 + c) * C.k + j0) * nq);
+  if (nb > 1) ntt_inv_store<GPT>(lds, T, accB1, Bconv + (((size_t)z * d3 + c) * C.k + j0 + 1) * nq);
 }
 
 // Element (c, u): RS_p of the converted parts, the ring-switched b' = b(rho u) + RS_p(Bring), and
@@ -443,12 +493,43 @@ __global__ void k_fs_finish(FsConsts C, const uint64_t* T, int64_t d3, const dou
   }
 }
 
+// The fused kernels: blockDim = N_Q / (8 GPT) threads (GPT = 2 at N_Q = 2^14, 1024 threads).
+template <int GPT, int S0>
+static hipError_t launch_fused_as(const FsConsts& C, int64_t ncols, int64_t d3, const FsWork& w, const double* rk,
+                                  const double* ck, bool conv, hipStream_t s) {
+  const size_t lds = sizeof(double) << C.logn_q;
+  const int threads = (1 << C.logn_q) / (8 * GPT);
+  if (!conv) {
+    hipError_t e = allow_lds(k_fs_ring<GPT, S0>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fs_ring<GPT, S0>), dim3(xcd_grid(ncols * C.nz)), dim3(threads), lds, s, C, ncols, w.Dg,
+                       rk, w.Aring, w.Bring);
+  } else {
+    hipError_t e = allow_lds(k_fs_conv<GPT, S0>, lds);
+    if (e != hipSuccess) return e;
+    const int groups = (C.k + 1) / 2;
+    hipLaunchKernelGGL((k_fs_conv<GPT, S0>), dim3(xcd_grid(d3 * C.nz * groups)), dim3(threads), lds, s, C, d3,
+                       w.Aring, ck, w.Aconv, w.Bconv);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_fused(const FsConsts& C, int64_t ncols, int64_t d3, const FsWork& w, const double* rk,
+                               const double* ck, bool conv, hipStream_t s) {
+  const int s0 = (C.logn_q - 1) % 3 + 1;
+  if (C.logn_q <= 13) {
+    if (s0 == 1) return launch_fused_as<1, 1>(C, ncols, d3, w, rk, ck, conv, s);
+    if (s0 == 2) return launch_fused_as<1, 2>(C, ncols, d3, w, rk, ck, conv, s);
+    return launch_fused_as<1, 3>(C, ncols, d3, w, rk, ck, conv, s);
+  }
+  return launch_fused_as<2, 2>(C, ncols, d3, w, rk, ck, conv, s);  // 2^14 = 2^(2 + 3 + 3 + 3 + 3)
+}
+
 hipError_t launch_fs_switch(const FsConsts& C, const uint64_t* T, int64_t d3, const double* rk, const double* ck,
                             const FsWork& w, uint64_t* XT, int64_t K, hipStream_t s, hipEvent_t* ev) {
   if (d3 <= 0) return hipSuccess;
   const int64_t ncols = d3 * C.k;
   const int nq = 1 << C.logn_q;
-  const size_t lds = sizeof(double) << C.logn_q;
   if (ev) (void)hipEventRecord(ev[0], s);
   {
     hipLaunchKernelGGL(k_fs_digits, dim3((unsigned)(ncols * (C.level + 1))), dim3(256), 0, s, C, T, ncols, w.Dg);
@@ -456,21 +537,10 @@ hipError_t launch_fs_switch(const FsConsts& C, const uint64_t* T, int64_t d3, co
     if (e != hipSuccess) return e;
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  hipError_t e = by_regs(regs_per_thread(C.logn_q), [&](auto rc) -> hipError_t {
-    constexpr int R = decltype(rc)::value;
-    hipError_t e2 = allow_lds(k_fs_ring<R>, lds);
-    if (e2 == hipSuccess) e2 = allow_lds(k_fs_conv<R>, lds);
-    if (e2 != hipSuccess) return e2;
-    hipLaunchKernelGGL(k_fs_ring<R>, dim3(xcd_grid(ncols * C.nz)), dim3(ntt_block(C.logn_q)), lds, s, C, ncols,
-                       w.Dg, rk, w.Aring, w.Bring);
-    e2 = hipGetLastError();
-    if (e2 != hipSuccess) return e2;
-    if (ev) (void)hipEventRecord(ev[2], s);
-    const int groups = (C.k + 1) / 2;
-    hipLaunchKernelGGL(k_fs_conv<R>, dim3(xcd_grid(d3 * C.nz * groups)), dim3(ntt_block(C.logn_q)), lds, s, C, d3,
-                       w.Aring, ck, w.Aconv, w.Bconv);
-    return hipGetLastError();
-  });
+  hipError_t e = launch_fused(C, ncols, d3, w, rk, ck, false, s);
+  if (e != hipSuccess) return e;
+  if (ev) (void)hipEventRecord(ev[2], s);
+  e = launch_fused(C, ncols, d3, w, rk, ck, true, s);
   if (e != hipSuccess) return e;
   if (ev) (void)hipEventRecord(ev[3], s);
   {

@@ -19,6 +19,23 @@ void xc_mulmod_d(const uint64_t* a, const uint64_t* w, int64_t n, uint64_t q, ui
   for (int64_t i = 0; i < n; ++i) out[i] = (uint64_t)mulmod_d((double)a[i], (double)w[i], qd, qinv);
 }
 
+// out[i] = the lazy product of a[i] (in [0, 4q)) and w[i]: congruent to a w mod q, in [0, 2q).
+void xc_mulmod_lazy_d(const uint64_t* a, const uint64_t* w, int64_t n, uint64_t q, uint64_t* out) {
+  const double qd = (double)q, qinv = 1.0 / qd;
+  for (int64_t i = 0; i < n; ++i) out[i] = (uint64_t)mulmod_lazy_d((double)a[i], (double)w[i], qd, qinv);
+}
+
+// The lazy butterfly on (x[i], y[i]) (both in [0, 4q)) with twiddle w[i]; results in place.
+void xc_butterfly_lazy(uint64_t* x, uint64_t* y, const uint64_t* w, int64_t n, uint64_t q) {
+  const double qd = (double)q, qinv = 1.0 / qd;
+  for (int64_t i = 0; i < n; ++i) {
+    double X = (double)x[i], Y = (double)y[i];
+    ct_butterfly_lazy(X, Y, (double)w[i], qd, qinv);
+    x[i] = (uint64_t)X;
+    y[i] = (uint64_t)Y;
+  }
+}
+
 void xc_mod_small(const uint32_t* x, int64_t n, uint32_t m, uint32_t* out) {
   const uint32_t magic = (uint32_t)(((1ull << 32) + m - 1) / m);
   for (int64_t i = 0; i < n; ++i) out[i] = mod_small(x[i], m, magic);

@@ -8,6 +8,9 @@ margin).  Every result is compared with Python integer arithmetic; the exhaustiv
 C's integer remainder inside the harness.
 
   mulmod_d      a w mod q in fp64 (the NTT butterflies), q < 2^36
+  mulmod_lazy_d, ct_butterfly_lazy
+                the lazy product (a < 4q, result below 2q) and butterfly (values below 4q) of the
+                FormatSwitch transforms
   mod_small     x mod m by multiply-high, x < 2^24, 2 <= m <= 256 (every x, every m)
   mod_f64       x mod m by an fp64 quotient, |x| < 2^48, m < 2^24
   balanced_mod  the RNS form's int8 residues, |x| < 2^40
@@ -35,6 +38,8 @@ _L.xc_rns_acc_mod_sweep.restype = ctypes.c_int64
 _L.xc_rns_acc_mod_sweep.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
 for _name, _args in {
         "xc_mulmod_d": [_p, _p, ctypes.c_int64, ctypes.c_uint64, _p],
+        "xc_mulmod_lazy_d": [_p, _p, ctypes.c_int64, ctypes.c_uint64, _p],
+        "xc_butterfly_lazy": [_p, _p, _p, ctypes.c_int64, ctypes.c_uint64],
         "xc_mod_small": [_p, ctypes.c_int64, ctypes.c_uint32, _p],
         "xc_mod_f64": [_p, ctypes.c_int64, ctypes.c_int64, _p],
         "xc_balanced_mod": [_p, ctypes.c_int64, ctypes.c_int, _p],
@@ -94,6 +99,34 @@ def test_mulmod_d_exact(q):
     _L.xc_mulmod_d(_ptr(A), _ptr(Wv), len(A), q, _ptr(out))
     want = [int(x) * int(y) % q for x, y in zip(A.tolist(), Wv.tolist())]
     assert out.tolist() == want
+
+
+@pytest.mark.parametrize("q", OP.ntt_primes(4) + [_largest_prime_below(1 << 36)])
+def test_lazy_product_and_butterfly(q):
+    """The lazy forms of the FormatSwitch transforms: a w congruent mod q and below 2q for a < 4q; the
+    butterfly (X, Y) -> (X + W Y, X - W Y) congruent mod q with both results below 4q."""
+    rng = np.random.default_rng(q % 997)
+    n = 200_000
+    ext = [0, 1, 2, q - 1, q, q + 1, 2 * q - 1, 2 * q, 2 * q + 1, 3 * q, 4 * q - 2, 4 * q - 1]
+    a = np.concatenate([rng.integers(0, 4 * q, n, dtype=np.uint64), np.repeat(ext, len(ext[:7])).astype(np.uint64)])
+    w = np.concatenate([rng.integers(0, q, n, dtype=np.uint64),
+                        np.tile([0, 1, 2, q - 1, q - 2, (q - 1) // 2, (q + 1) // 2], len(ext)).astype(np.uint64)])
+    # products next to multiples of q
+    ww = rng.integers(1, q, 20_000).tolist()
+    near = [((t * pow(x, -1, q)) % q + k * q, x) for x in ww for t in (0, 1, q - 1) for k in (0, 3)]
+    a = np.concatenate([a, np.array([u for u, _ in near], dtype=np.uint64)])
+    w = np.concatenate([w, np.array([v for _, v in near], dtype=np.uint64)])
+    out = np.empty_like(a)
+    _L.xc_mulmod_lazy_d(_ptr(a), _ptr(w), len(a), q, _ptr(out))
+    A, Wl, O = a.tolist(), w.tolist(), out.tolist()
+    assert all(o < 2 * q and (o - x * y) % q == 0 for x, y, o in zip(A, Wl, O))
+    x = a.copy()
+    y = np.roll(a, 1).copy()
+    X0, Y0 = x.tolist(), y.tolist()
+    _L.xc_butterfly_lazy(_ptr(x), _ptr(y), _ptr(w), len(x), q)
+    assert all(u < 4 * q and v < 4 * q for u, v in zip(x.tolist(), y.tolist()))
+    assert all((u - (x0 + t * y0)) % q == 0 and (v - (x0 - t * y0)) % q == 0
+               for u, v, x0, y0, t in zip(x.tolist(), y.tolist(), X0, Y0, Wl))
 
 
 def test_mod_small_exact_for_every_operand():
