@@ -40,11 +40,11 @@ MEASURED_TRAFFIC_GB = {"dma_q128_w2": 28.3, "dma_r128_w2": 30.4, "dma2_w2": 90.1
                        "rns256": 36.6, "p2_256": 46.1}
 KEY_SEED, DB_SEED, Q_SEED, TX_SEED = 11, 22, 33, 44
 # fp64 vector instructions per second of the chip (256 CUs x 64 lanes x 2.4 GHz; the 78.6 TFLOP/s peak
-# counts a fused multiply-add as two) and the fp64 instructions of one error-free modular product as
-# the transforms run it (multiply, fused multiply-add, multiply by 1/q, floor, fused multiply-add, add,
-# two compares, two corrections): the ceiling of the modular products FormatSwitch is built from.
+# counts a fused multiply-add as two) and the fp64 instructions of one exact modular product in the
+# signed form the FormatSwitch transforms use (multiply, fused multiply-add, multiply by 1/q, rint,
+# fused multiply-add, add): the ceiling of the modular products FormatSwitch is built from.
 FP64_INSTR_PER_S = 256 * 64 * 2.4e9
-FP64_PER_MODMUL = 10
+FP64_PER_MODMUL = 6
 
 
 def log(msg):
@@ -591,6 +591,11 @@ def main():
         return
     if args.mode == "fs":
         print(json.dumps(run_format_switch(args, H, torch, steps=args.fs_steps)), flush=True)
+        if args.copy_mib:  # a plain device copy of known size (counter calibration)
+            src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            log(f"copied {args.copy_mib} MiB")
         return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

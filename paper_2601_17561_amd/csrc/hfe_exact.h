@@ -30,32 +30,34 @@ HFE_HD double mulmod_d(double a, double w, double q, double qinv) {
   r = r < 0.0 ? r + q : r;
   return r >= q ? r - q : r;
 }
-// a w mod q up to one multiple of q, for a in [0, 4q), w in [0, q), q < 2^36: the steps of mulmod_d
-// with one correction.  a w < 2^74, so hi = RN(a w) is an integer and lo = a w - hi is exact; the
-// quotient a w / q is below 2^38 and t = floor(hi qinv) is off from its floor by at most one either
-// way, so hi - t q + lo is an exact integer in [-q, 2q) and one correction gives [0, 2q).
-HFE_HD double mulmod_lazy_d(double a, double w, double q, double qinv) {
+// Signed transforms (the FormatSwitch kernels): values are integers held as doubles, congruent to
+// the residues and bounded in magnitude, never corrected inside a transform.
+// a w mod q as a centered representative, for integers |a| <= 16q and w in [0, q), q < 2^36:
+// P = a w is below 2^76 in magnitude, hi = RN(P) an integer with |hi - P| <= 2^22, lo = P - hi exact
+// from one fused multiply-add; u = hi qinv is within 2^-11 of P / q (|d| / q <= 2^-13 plus a relative
+// error below 2^-52 on a quotient below 2^40), so t = rint(u) is within 1/2 + 2^-11 of P / q and
+// P - t q = (hi - t q) + lo is an exact integer of magnitude at most (1/2 + 2^-11) q.
+HFE_HD double mulmod_c_d(double a, double w, double q, double qinv) {
 #pragma clang fp contract(off)
   const double hi = a * w;
   const double lo = __builtin_fma(a, w, -hi);
-  const double t = __builtin_floor(hi * qinv);
-  const double r = __builtin_fma(-t, q, hi) + lo;
-  return r < 0.0 ? r + q : r;
+  const double t = __builtin_rint(hi * qinv);
+  return __builtin_fma(-t, q, hi) + lo;
 }
-// Cooley-Tukey butterfly on values kept in [0, 4q) (Harvey's lazy reduction): X to [0, 2q), T = W Y in
-// [0, 2q), then X + T and X - T + 2q, both in [0, 4q) and exact (below 2^39).
-HFE_HD void ct_butterfly_lazy(double& X, double& Y, double W, double q, double qinv) {
-  const double q2 = q + q;
-  const double x = X >= q2 ? X - q2 : X;
-  const double t = mulmod_lazy_d(Y, W, q, qinv);
+// x - q rint(x / q) for an integer |x| < 2^47: exact, of magnitude at most (1/2 + 2^-11) q.
+HFE_HD double reduce_c_d(double x, double q, double qinv) {
+#pragma clang fp contract(off)
+  return __builtin_fma(-__builtin_rint(x * qinv), q, x);
+}
+// A centered value (|x| < q) to its residue in [0, q).
+HFE_HD double residue_of_c(double x, double q) { return x < 0.0 ? x + q : x; }
+// Cooley-Tukey butterfly on signed values: (X, Y) -> (X + W Y, X - W Y) with W Y centered.  Each
+// stage adds at most (1/2 + 2^-11) q to the magnitude: inputs below 2q stay below 9.1q over 14 stages.
+HFE_HD void ct_butterfly_c(double& X, double& Y, double W, double q, double qinv) {
+  const double t = mulmod_c_d(Y, W, q, qinv);
+  const double x = X;
   X = x + t;
-  Y = (x - t) + q2;
-}
-// [0, 4q) -> [0, q)
-HFE_HD double reduce4_d(double x, double q) {
-  const double q2 = q + q;
-  x = x >= q2 ? x - q2 : x;
-  return x >= q ? x - q : x;
+  Y = x - t;
 }
 HFE_HD double addmod_d(double a, double b, double q) {
   const double s = a + b;  // exact below 2^37

@@ -46,9 +46,9 @@ __device__ __forceinline__ void fwd_stages(double* x, const NttTab& T, int m1, i
   }
 }
 
-// The same stages on values kept in [0, 4q) (ct_butterfly_lazy): inputs below 4q, outputs below 4q.
+// The same stages on signed values (ct_butterfly_c): each stage adds at most about q/2 to the magnitude.
 template <int S>
-__device__ __forceinline__ void fwd_stages_lazy(double* x, const NttTab& T, int m1, int B) {
+__device__ __forceinline__ void fwd_stages_c(double* x, const NttTab& T, int m1, int B) {
   constexpr int G = 1 << S;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -57,13 +57,13 @@ __device__ __forceinline__ void fwd_stages_lazy(double* x, const NttTab& T, int 
     for (int k = 0; k < G; ++k) {
       if (k & h) continue;
       const int w = (m1 << s) + (B << s) + (k >> (S - s));
-      ct_butterfly_lazy(x[k], x[k + h], T.psi_d[w], T.qd, T.qinv);
+      ct_butterfly_c(x[k], x[k + h], T.psi_d[w], T.qd, T.qinv);
     }
   }
 }
 
 template <int S>
-__device__ __forceinline__ void fwd_round_lazy(double* a, const NttTab& T, int n, int t) {
+__device__ __forceinline__ void fwd_round_c(double* a, const NttTab& T, int n, int t) {
   constexpr int G = 1 << S;
   const int stride = t >> (S - 1), m1 = n / (2 * t);
   for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
@@ -72,7 +72,7 @@ __device__ __forceinline__ void fwd_round_lazy(double* a, const NttTab& T, int n
     double x[G];
 #pragma unroll
     for (int k = 0; k < G; ++k) x[k] = a[base + k * stride];
-    fwd_stages_lazy<S>(x, T, m1, B);
+    fwd_stages_c<S>(x, T, m1, B);
 #pragma unroll
     for (int k = 0; k < G; ++k) a[base + k * stride] = x[k];
   }

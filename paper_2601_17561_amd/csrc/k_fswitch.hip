@@ -20,10 +20,6 @@
 
 namespace hfe {
 
-// x in [0, 2z) -> [0, z) (a digit below q_i taken mod another slot modulus z; all moduli lie within
-// a factor 2 of each other).
-__device__ __forceinline__ double red_once(double x, double z) { return x >= z ? x - z : x; }
-
 // Rescale of one coefficient by the modulus D: (x_q - [x_D]) D^-1 mod q, with [x_D] the centered
 // residue in (-D/2, D/2) and dinv = D^-1 mod q.  x_q - [x_D] lies in (-D/2, q + D/2), and D < 2q, so
 // one correction each way brings it to [0, q).
@@ -291,8 +287,9 @@ __global__ void k_fs_digits(FsConsts C, const uint64_t* T, int64_t ncols, double
 // through LDS, and the last round (t = 4: group g holds the contiguous coefficients 8g .. 8g + 7 of
 // the bit-reversed output) stays in registers, where the caller multiplies by the keys: two LDS
 // passes and two barriers fewer per transform than a load, the transform and a reload.  The
-// butterflies reduce lazily (values below 4q, hfe_exact.h): the transform's outputs are congruent to
-// the exact ones and below 4q, which the lazy products of the multiply-accumulate take as they are.
+// butterflies run on signed values without corrections (ct_butterfly_c, hfe_exact.h): inputs below 2q
+// (the digits, below q_i < 2z) leave a transform of degree up to 2^14 below 9.1q, congruent to the
+// exact outputs, which the centered products of the multiply-accumulate take as they are.
 
 // First round: loads every value this thread's groups need (before the barrier that lets it
 // overwrite LDS), then the S0 stages and the store.
@@ -310,7 +307,7 @@ __device__ __forceinline__ void fused_first_round(double* lds, const NttTab& T, 
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int g = threadIdx.x + m * blockDim.x;
-    fwd_stages_lazy<S0>(y[m], T, 1, 0);
+    fwd_stages_c<S0>(y[m], T, 1, 0);
 #pragma unroll
     for (int k = 0; k < G; ++k) lds[g + k * ng] = y[m][k];
   }
@@ -321,24 +318,24 @@ template <int GPT, int S0, class Load>
 __device__ __forceinline__ void ntt_fwd_fused(double* lds, const NttTab& T, Load load, double (&x)[GPT][8]) {
   const int n = 1 << T.logn;
   fused_first_round<GPT, S0>(lds, T, load);
-  for (int t = (n >> 1) >> S0; t > 4; t >>= 3) fwd_round_lazy<3>(lds, T, n, t);
+  for (int t = (n >> 1) >> S0; t > 4; t >>= 3) fwd_round_c<3>(lds, T, n, t);
 #pragma unroll
   for (int j = 0; j < GPT; ++j) {
     const int g = threadIdx.x + j * blockDim.x;
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[j][k] = lds[8 * g + k];
-    fwd_stages_lazy<3>(x[j], T, n >> 3, g);
+    fwd_stages_c<3>(x[j], T, n >> 3, g);
   }
 }
 
-// acc (below 2q) + x w (x below 4q), kept below 2q.
-__device__ __forceinline__ double mac_lazy(double acc, double x, double w, double q, double qinv) {
-  const double s = acc + mulmod_lazy_d(x, w, q, qinv);
-  return s >= q + q ? s - (q + q) : s;
+// acc + x w with the centered product (|x| <= 16q): acc stays an exact integer, below (1/2 + 2^-11) q
+// times the number of terms (at most 4096 here) in magnitude.
+__device__ __forceinline__ double mac_c(double acc, double x, double w, double q, double qinv) {
+  return acc + mulmod_c_d(x, w, q, qinv);
 }
 
 // Inverse transform of the values x (positions 8g + k as above) through LDS, written to out in
-// natural order; x below 2q (the lazy accumulators).
+// natural order; x signed accumulators (reduced to [0, q) first).
 template <int GPT>
 __device__ __forceinline__ void ntt_inv_store(double* lds, const NttTab& T, const double (&x)[GPT][8], double* out) {
   const int n = 1 << T.logn;
@@ -347,7 +344,7 @@ __device__ __forceinline__ void ntt_inv_store(double* lds, const NttTab& T, cons
   for (int j = 0; j < GPT; ++j) {
     const int g = threadIdx.x + j * blockDim.x;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) lds[8 * g + k] = x[j][k] >= T.qd ? x[j][k] - T.qd : x[j][k];
+    for (int k = 0; k < 8; ++k) lds[8 * g + k] = residue_of_c(reduce_c_d(x[j][k], T.qd, T.qinv), T.qd);
   }
   __syncthreads();
   ntt_inv_lds(lds, T);
@@ -376,7 +373,7 @@ k_fs_ring(FsConsts C, int64_t ncols, const double* Dg, const double* rk, double*
   for (int i = 0; i <= C.level; ++i) {
     for (int r = 0; r < C.rho; ++r) {
       const double* src = Dg + (((size_t)col * (C.level + 1) + i) * C.rho + r) * nq;
-      ntt_fwd_fused<GPT, S0>(lds, T, [&](int pos) { return red_once(src[pos], q); }, x);
+      ntt_fwd_fused<GPT, S0>(lds, T, [&](int pos) { return src[pos]; }, x);  // digits below q_i < 2z
       const double* ka = rk + (((size_t)z * (C.level + 1) + i) * 2 * C.rho + r) * nq;
       const double* kb = ka + (size_t)C.rho * nq;
 #pragma unroll
@@ -384,8 +381,8 @@ k_fs_ring(FsConsts C, int64_t ncols, const double* Dg, const double* rk, double*
         const int v0 = 8 * (threadIdx.x + j * blockDim.x);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          accA[j][k] = mac_lazy(accA[j][k], x[j][k], ka[v0 + k], q, qinv);
-          accB[j][k] = mac_lazy(accB[j][k], x[j][k], kb[v0 + k], q, qinv);
+          accA[j][k] = mac_c(accA[j][k], x[j][k], ka[v0 + k], q, qinv);
+          accB[j][k] = mac_c(accB[j][k], x[j][k], kb[v0 + k], q, qinv);
         }
       }
     }
@@ -429,7 +426,7 @@ k_fs_conv(FsConsts C, int64_t d3, const double* Aring, const double* ck, double*
       const double qi = C.zd[i], qiinv = C.zinv[i], pinv = C.pinv[i], gh = C.ghat[i];
       ntt_fwd_fused<GPT, S0>(
           lds, T,
-          [&](int v) { return red_once(mulmod_d(rs_d(Ai[v], Ap[v], pd, qi, qiinv, pinv), gh, qi, qiinv), q); }, x);
+          [&](int v) { return mulmod_d(rs_d(Ai[v], Ap[v], pd, qi, qiinv, pinv), gh, qi, qiinv); }, x);
       const double* kk = ck + (((size_t)z * (l + 1) + i) * C.k + j) * (1 + C.k) * nq;
       const double* kb0 = kk + (size_t)(1 + j0) * nq;
       const double* kb1 = kk + (size_t)(nb > 1 ? 2 + j0 : 1 + j0) * nq;
@@ -439,9 +436,9 @@ k_fs_conv(FsConsts C, int64_t d3, const double* Aring, const double* ck, double*
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const double xv = x[jj][k];
-          if (g == 0) accA[jj][k] = mac_lazy(accA[jj][k], xv, kk[v0 + k], q, qinv);
-          accB0[jj][k] = mac_lazy(accB0[jj][k], xv, kb0[v0 + k], q, qinv);
-          if (nb > 1) accB1[jj][k] = mac_lazy(accB1[jj][k], xv, kb1[v0 + k], q, qinv);
+          if (g == 0) accA[jj][k] = mac_c(accA[jj][k], xv, kk[v0 + k], q, qinv);
+          accB0[jj][k] = mac_c(accB0[jj][k], xv, kb0[v0 + k], q, qinv);
+          if (nb > 1) accB1[jj][k] = mac_c(accB1[jj][k], xv, kb1[v0 + k], q, qinv);
         }
       }
     }

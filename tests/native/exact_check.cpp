@@ -19,21 +19,37 @@ void xc_mulmod_d(const uint64_t* a, const uint64_t* w, int64_t n, uint64_t q, ui
   for (int64_t i = 0; i < n; ++i) out[i] = (uint64_t)mulmod_d((double)a[i], (double)w[i], qd, qinv);
 }
 
-// out[i] = the lazy product of a[i] (in [0, 4q)) and w[i]: congruent to a w mod q, in [0, 2q).
-void xc_mulmod_lazy_d(const uint64_t* a, const uint64_t* w, int64_t n, uint64_t q, uint64_t* out) {
+// out[i] = the centered product of a[i] (|a| <= 16q) and w[i] (in [0, q)), as int64.
+void xc_mulmod_c_d(const int64_t* a, const uint64_t* w, int64_t n, uint64_t q, int64_t* out) {
   const double qd = (double)q, qinv = 1.0 / qd;
-  for (int64_t i = 0; i < n; ++i) out[i] = (uint64_t)mulmod_lazy_d((double)a[i], (double)w[i], qd, qinv);
+  for (int64_t i = 0; i < n; ++i) out[i] = (int64_t)mulmod_c_d((double)a[i], (double)w[i], qd, qinv);
 }
 
-// The lazy butterfly on (x[i], y[i]) (both in [0, 4q)) with twiddle w[i]; results in place.
-void xc_butterfly_lazy(uint64_t* x, uint64_t* y, const uint64_t* w, int64_t n, uint64_t q) {
+// out[i] = reduce_c_d(x[i]) then residue_of_c, as uint64.
+void xc_reduce_c_d(const int64_t* x, int64_t n, uint64_t q, uint64_t* out) {
   const double qd = (double)q, qinv = 1.0 / qd;
-  for (int64_t i = 0; i < n; ++i) {
-    double X = (double)x[i], Y = (double)y[i];
-    ct_butterfly_lazy(X, Y, (double)w[i], qd, qinv);
-    x[i] = (uint64_t)X;
-    y[i] = (uint64_t)Y;
-  }
+  for (int64_t i = 0; i < n; ++i) out[i] = (uint64_t)residue_of_c(reduce_c_d((double)x[i], qd, qinv), qd);
+}
+
+// A forward transform of length 2^logn through ct_butterfly_c (the stage order of the kernels, twiddles
+// w[m + j] as in the tables, w given as integers), then reduce_c_d: out[i] in [0, q).  Also returns the
+// largest magnitude met between stages.
+int64_t xc_ntt_signed(const int64_t* in, const uint64_t* w, int logn, uint64_t q, uint64_t* out) {
+  const int n = 1 << logn;
+  const double qd = (double)q, qinv = 1.0 / qd;
+  double* a = new double[n];
+  for (int i = 0; i < n; ++i) a[i] = (double)in[i];
+  double big = 0.0;
+  for (int m = 1, t = n / 2; m < n; m *= 2, t /= 2)
+    for (int j = 0; j < m; ++j)
+      for (int i = 2 * j * t; i < 2 * j * t + t; ++i) {
+        ct_butterfly_c(a[i], a[i + t], (double)w[m + j], qd, qinv);
+        big = __builtin_fabs(a[i]) > big ? __builtin_fabs(a[i]) : big;
+        big = __builtin_fabs(a[i + t]) > big ? __builtin_fabs(a[i + t]) : big;
+      }
+  for (int i = 0; i < n; ++i) out[i] = (uint64_t)residue_of_c(reduce_c_d(a[i], qd, qinv), qd);
+  delete[] a;
+  return (int64_t)big;
 }
 
 void xc_mod_small(const uint32_t* x, int64_t n, uint32_t m, uint32_t* out) {

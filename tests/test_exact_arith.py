@@ -8,9 +8,9 @@ margin).  Every result is compared with Python integer arithmetic; the exhaustiv
 C's integer remainder inside the harness.
 
   mulmod_d      a w mod q in fp64 (the NTT butterflies), q < 2^36
-  mulmod_lazy_d, ct_butterfly_lazy
-                the lazy product (a < 4q, result below 2q) and butterfly (values below 4q) of the
-                FormatSwitch transforms
+  mulmod_c_d, reduce_c_d, ct_butterfly_c
+                the signed product (|a| <= 16q, centered result), reduction and butterfly of the
+                FormatSwitch transforms, and a whole transform built from them
   mod_small     x mod m by multiply-high, x < 2^24, 2 <= m <= 256 (every x, every m)
   mod_f64       x mod m by an fp64 quotient, |x| < 2^48, m < 2^24
   balanced_mod  the RNS form's int8 residues, |x| < 2^40
@@ -38,8 +38,9 @@ _L.xc_rns_acc_mod_sweep.restype = ctypes.c_int64
 _L.xc_rns_acc_mod_sweep.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
 for _name, _args in {
         "xc_mulmod_d": [_p, _p, ctypes.c_int64, ctypes.c_uint64, _p],
-        "xc_mulmod_lazy_d": [_p, _p, ctypes.c_int64, ctypes.c_uint64, _p],
-        "xc_butterfly_lazy": [_p, _p, _p, ctypes.c_int64, ctypes.c_uint64],
+        "xc_mulmod_c_d": [_p, _p, ctypes.c_int64, ctypes.c_uint64, _p],
+        "xc_reduce_c_d": [_p, ctypes.c_int64, ctypes.c_uint64, _p],
+        "xc_ntt_signed": [_p, _p, ctypes.c_int, ctypes.c_uint64, _p],
         "xc_mod_small": [_p, ctypes.c_int64, ctypes.c_uint32, _p],
         "xc_mod_f64": [_p, ctypes.c_int64, ctypes.c_int64, _p],
         "xc_balanced_mod": [_p, ctypes.c_int64, ctypes.c_int, _p],
@@ -52,6 +53,7 @@ for _name, _args in {
                    ctypes.c_uint64, ctypes.c_int, _p, _p]}.items():
     getattr(_L, _name).argtypes = _args
     getattr(_L, _name).restype = None
+_L.xc_ntt_signed.restype = ctypes.c_int64
 
 # The moduli tables of the library (hfe_exact.h); their values are fixed by the paper's ranges
 # (RNS: pairwise coprime, <= 256; n^2: primes 127 <= n <= 253) and checked below.
@@ -102,31 +104,55 @@ def test_mulmod_d_exact(q):
 
 
 @pytest.mark.parametrize("q", OP.ntt_primes(4) + [_largest_prime_below(1 << 36)])
-def test_lazy_product_and_butterfly(q):
-    """The lazy forms of the FormatSwitch transforms: a w congruent mod q and below 2q for a < 4q; the
-    butterfly (X, Y) -> (X + W Y, X - W Y) congruent mod q with both results below 4q."""
-    rng = np.random.default_rng(q % 997)
+def test_signed_product_and_reduction(q):
+    """The signed arithmetic of the FormatSwitch transforms: a w congruent mod q and at most
+    (1/2 + 2^-11) q in magnitude for |a| <= 16q; x - q rint(x / q) then the residue in [0, q)."""
+    rng = np.random.default_rng(q % 991)
     n = 200_000
-    ext = [0, 1, 2, q - 1, q, q + 1, 2 * q - 1, 2 * q, 2 * q + 1, 3 * q, 4 * q - 2, 4 * q - 1]
-    a = np.concatenate([rng.integers(0, 4 * q, n, dtype=np.uint64), np.repeat(ext, len(ext[:7])).astype(np.uint64)])
-    w = np.concatenate([rng.integers(0, q, n, dtype=np.uint64),
-                        np.tile([0, 1, 2, q - 1, q - 2, (q - 1) // 2, (q + 1) // 2], len(ext)).astype(np.uint64)])
-    # products next to multiples of q
+    lim = 16 * q
+    ext = [0, 1, -1, q - 1, -(q - 1), q, -q, 2 * q + 1, lim, -lim, lim - 1, -(lim - 1), q // 2, -(q // 2)]
+    wx = [0, 1, 2, q - 1, q - 2, (q - 1) // 2, (q + 1) // 2]
+    a = np.concatenate([rng.integers(-lim, lim + 1, n, dtype=np.int64), np.repeat(ext, len(wx)).astype(np.int64)])
+    w = np.concatenate([rng.integers(0, q, n, dtype=np.uint64), np.tile(wx, len(ext)).astype(np.uint64)])
+    # products next to half-multiples of q (where the rounded quotient may go either way)
     ww = rng.integers(1, q, 20_000).tolist()
-    near = [((t * pow(x, -1, q)) % q + k * q, x) for x in ww for t in (0, 1, q - 1) for k in (0, 3)]
-    a = np.concatenate([a, np.array([u for u, _ in near], dtype=np.uint64)])
+    near = [(((t * pow(x, -1, q)) % q) + k * q, x) for x in ww for t in (q // 2, q // 2 + 1, 0, 1) for k in (-16, 3, 15)]
+    a = np.concatenate([a, np.array([u for u, _ in near], dtype=np.int64)])
     w = np.concatenate([w, np.array([v for _, v in near], dtype=np.uint64)])
     out = np.empty_like(a)
-    _L.xc_mulmod_lazy_d(_ptr(a), _ptr(w), len(a), q, _ptr(out))
-    A, Wl, O = a.tolist(), w.tolist(), out.tolist()
-    assert all(o < 2 * q and (o - x * y) % q == 0 for x, y, o in zip(A, Wl, O))
-    x = a.copy()
-    y = np.roll(a, 1).copy()
-    X0, Y0 = x.tolist(), y.tolist()
-    _L.xc_butterfly_lazy(_ptr(x), _ptr(y), _ptr(w), len(x), q)
-    assert all(u < 4 * q and v < 4 * q for u, v in zip(x.tolist(), y.tolist()))
-    assert all((u - (x0 + t * y0)) % q == 0 and (v - (x0 - t * y0)) % q == 0
-               for u, v, x0, y0, t in zip(x.tolist(), y.tolist(), X0, Y0, Wl))
+    _L.xc_mulmod_c_d(_ptr(a), _ptr(w), len(a), q, _ptr(out))
+    bound = q // 2 + q // 2048 + 1
+    assert all(abs(o) <= bound and (o - x * y) % q == 0 for x, y, o in zip(a.tolist(), w.tolist(), out.tolist()))
+    x = np.concatenate([rng.integers(-(1 << 47) + 1, 1 << 47, n, dtype=np.int64), np.array(ext, dtype=np.int64)])
+    r = np.empty(len(x), dtype=np.uint64)
+    _L.xc_reduce_c_d(_ptr(x), len(x), q, _ptr(r))
+    assert r.tolist() == [v % q for v in x.tolist()]
+
+
+@pytest.mark.parametrize("logn", [7, 13, 14])
+def test_signed_transform_equals_the_negacyclic_evaluation(logn):
+    """A whole forward transform through the signed butterflies (inputs in [0, 2q), the digits' range)
+    equals the exact one (the integer transform reduced mod q), and its values stay below 9.1q."""
+    q = OP.ntt_primes(1)[0]
+    n = 1 << logn
+    g = 2
+    while pow(g, (q - 1) // 2, q) == 1:     # a quadratic non-residue: psi = g^((q-1)/2n) has order 2n
+        g += 1
+    psi = pow(g, (q - 1) // (2 * n), q)
+    assert pow(psi, n, q) == q - 1
+    brv = [int(format(i, f"0{logn}b")[::-1], 2) for i in range(n)]
+    w = np.array([pow(psi, brv[i], q) for i in range(n)], dtype=np.uint64)
+    rng = np.random.default_rng(logn)
+    x = rng.integers(0, 2 * q, n, dtype=np.int64)
+    x[:4] = 2 * q - 1
+    out = np.empty(n, dtype=np.uint64)
+    big = _L.xc_ntt_signed(_ptr(x), _ptr(w), logn, q, _ptr(out))
+    assert big < 9.1 * q
+    xs = [int(v) for v in x.tolist()]
+    # merged negacyclic transform: output i is the evaluation at psi^(2 brv(i) + 1)
+    for i in list(range(0, n, max(1, n // 64))) + [n - 1]:
+        z = pow(psi, 2 * brv[i] + 1, q)
+        assert int(out[i]) == sum(c * pow(z, t, q) for t, c in enumerate(xs)) % q
 
 
 def test_mod_small_exact_for_every_operand():
