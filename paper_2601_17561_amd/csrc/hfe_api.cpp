@@ -933,12 +933,14 @@ static hfe_status chain_ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t ro
     qm[j] = K->cmod[j].q;
     la.q[j] = qm[j];
     la.mu[j] = K->cmod[j].mu;
+    la.qmagic[j] = magic_u32((uint32_t)qm[j]);
   }
   garner_consts_of(qm, level, la.garner, la.half_digits);
   for (int t = 0; t < np; ++t) {
     const uint64_t pm = K->cmod[K->cq + t].q;
     la.pm[t] = pm;
     la.pmu[t] = K->cmod[K->cq + t].mu;
+    la.pmagic[t] = magic_u32((uint32_t)pm);
     uint64_t prod = 1 % pm;
     for (int j = 0; j < level; ++j) {
       la.mprod[t][j] = prod;
@@ -1001,11 +1003,13 @@ static hfe_status chain_ccmm_impl(const hfe_db* D, const hfe_qct* Qc, int64_t ro
     ra.pm[t] = la.pm[t];
     ra.pmu[t] = la.pmu[t];
     ra.pinv[t] = inv_mod(pre % la.pm[t], la.pm[t]);
+    ra.pmagic[t] = la.pmagic[t];
     pre *= la.pm[t];
   }
   for (int j = 0; j < level; ++j) {
     ra.mod[j] = K->cmod[j];
     ra.Pinv[j] = inv_mod(K->cP % qm[j], qm[j]);
+    ra.qmagic[j] = la.qmagic[j];
   }
   HFE_LAUNCH(launch_chain_rescale(res, d3 * R_out, ra, R->outp, s));
   HFE_LAUNCH(mark(3));

@@ -77,6 +77,17 @@ HFE_HD uint32_t umulhi32(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)
 // (Also exact for x < 2^17 and any m < 2^15: x (magic - 2^32/m) < 2^17 < 2^32 / m.)
 HFE_HD uint32_t mod_small(uint32_t x, uint32_t m, uint32_t magic) { return x - umulhi32(x, magic) * m; }
 
+// x mod m for any x < 2^32 and 2 <= m <= 2^16, magic = ceil(2^32 / m): x magic / 2^32 exceeds x / m by
+// x (magic - 2^32 / m) / 2^32 < 1, so the estimate is the quotient or one more; one correction.
+HFE_HD uint32_t mod_u32(uint32_t x, uint32_t m, uint32_t magic) {
+  const uint32_t qe = umulhi32(x, magic);
+  const int64_t r = (int64_t)x - (int64_t)qe * (int64_t)m;
+  return (uint32_t)(r < 0 ? r + m : r);
+}
+// a b mod m for a, b < m <= 2^16 (the n^2 moduli of the modulus chain): a b < 2^32.
+HFE_HD uint32_t mulmod_u16(uint32_t a, uint32_t b, uint32_t m, uint32_t magic) { return mod_u32(a * b, m, magic); }
+HFE_HD uint32_t magic_u32(uint32_t m) { return (uint32_t)(((1ull << 32) + m - 1) / m); }
+
 // x mod m in [0, m) for |x| < 2^48 and 2 <= m < 2^24, rcp = RN(1 / m): x rcp differs from x / m by
 // less than 2^-4, so floor(x rcp) is the quotient or one off, fixed by one step.
 HFE_HD int64_t mod_f64(int64_t x, int64_t m, double rcp) {

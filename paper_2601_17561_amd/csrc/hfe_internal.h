@@ -357,6 +357,7 @@ struct ChainLiftArgs {
   uint64_t pm[kChainMaxP], pmu[kChainMaxP];              // special moduli m'_s
   uint64_t mprod[kChainMaxP][HFE_MAX_QPRIMES];           // m_0 .. m_{i-1} mod m'_s
   uint64_t Q_mod[kChainMaxP];                            // Q_level mod m'_s
+  uint32_t qmagic[HFE_MAX_QPRIMES], pmagic[kChainMaxP];  // ceil(2^32 / m) of the query and special moduli
   ChainBase base[kChainMaxSlots];                        // per slot
 };
 struct ChainRescaleArgs {
@@ -366,6 +367,7 @@ struct ChainRescaleArgs {
   uint64_t P;                                            // prod m'_s
   Mod mod[HFE_MAX_QPRIMES];                              // query moduli
   uint64_t Pinv[HFE_MAX_QPRIMES];                        // P^-1 mod m_j
+  uint32_t qmagic[HFE_MAX_QPRIMES], pmagic[kChainMaxP];  // ceil(2^32 / m)
 };
 // Residues Dt [K][R] mod b.m -> the slot's two planes [2][KB][R_pad][64] (M, M').
 hipError_t launch_chain_split_db(const uint64_t* Dt, int64_t K, int64_t R, int64_t KB, int64_t R_pad,

@@ -72,23 +72,45 @@ __global__ void __launch_bounds__(256) k_chain_lift(const uint64_t* XT, int64_t 
   if (k >= KB * kKB) return;
   const int64_t c = blockIdx.y;
   const bool valid = c < d3 && k < K;
-  uint64_t y[HFE_MAX_QPRIMES] = {}, v[HFE_MAX_QPRIMES] = {};
-  uint64_t lp[kChainMaxP] = {};
+  // every modulus is n^2 <= 2^16: Garner's digits and the lift to the special moduli in 32-bit products
+  uint32_t y[HFE_MAX_QPRIMES] = {}, v[HFE_MAX_QPRIMES] = {};
+  uint32_t lp[kChainMaxP] = {};
   if (valid) {
 #pragma unroll
     for (int i = 0; i < HFE_MAX_QPRIMES; ++i)
-      if (i < la.level) y[i] = XT[((int64_t)i * d3 + c) * K + k];
-    garner_digits(y, la.level, la.garner, la.q, la.mu, v);
-    const bool neg = above_half(v, la.half_digits, la.level);
+      if (i < la.level) y[i] = (uint32_t)XT[((int64_t)i * d3 + c) * K + k];
+#pragma unroll
+    for (int i = 0; i < HFE_MAX_QPRIMES; ++i) {
+      if (i >= la.level) break;
+      const uint32_t qi = (uint32_t)la.q[i], mg = la.qmagic[i];
+      uint32_t acc = 0;  // (v_0 + v_1 m_0 + ... ) mod m_i
+#pragma unroll
+      for (int j = 0; j < i; ++j) {
+        acc += mulmod_u16(mod_u32(v[j], qi, mg), (uint32_t)la.garner[i][j], qi, mg);
+        acc = acc >= qi ? acc - qi : acc;
+      }
+      v[i] = i == 0 ? y[0] : mulmod_u16(y[i] >= acc ? y[i] - acc : y[i] + qi - acc, (uint32_t)la.garner[i][i], qi, mg);
+    }
+    bool neg = false, decided = false;  // the lift above (Q - 1) / 2, compared on the digits from the top
+#pragma unroll
+    for (int i = HFE_MAX_QPRIMES - 1; i >= 0; --i)
+      if (i < la.level && !decided && v[i] != (uint32_t)la.half_digits[i]) {
+        neg = v[i] > (uint32_t)la.half_digits[i];
+        decided = true;
+      }
 #pragma unroll
     for (int s = 0; s < kChainMaxP; ++s) {
       if (s >= la.np) break;
-      const uint64_t pm = la.pm[s], pmu = la.pmu[s];
-      uint64_t acc = 0;
+      const uint32_t pm = (uint32_t)la.pm[s], mg = la.pmagic[s];
+      uint32_t acc = 0;
 #pragma unroll
       for (int i = 0; i < HFE_MAX_QPRIMES; ++i)
-        if (i < la.level) acc = add_mod(acc, mul_mod(barrett64(v[i], pm, pmu), la.mprod[s][i], pm, pmu), pm);
-      lp[s] = neg ? sub_mod(acc, la.Q_mod[s], pm) : acc;
+        if (i < la.level) {
+          acc += mulmod_u16(mod_u32(v[i], pm, mg), (uint32_t)la.mprod[s][i], pm, mg);
+          acc = acc >= pm ? acc - pm : acc;
+        }
+      const uint32_t qm = (uint32_t)la.Q_mod[s];
+      lp[s] = neg ? (acc >= qm ? acc - qm : acc + pm - qm) : acc;
     }
   }
   const bool writer = (threadIdx.x & 3) == 0;
@@ -135,7 +157,8 @@ __global__ void __launch_bounds__(256) k_chain_rescale(const uint16_t* res, int6
       if (s >= ra.np) break;
       const uint64_t pm = ra.pm[s], pmu = ra.pmu[s];
       const uint64_t r = res[(int64_t)s * n + e];
-      const uint64_t d = mul_mod(sub_mod(r, barrett64(X, pm, pmu), pm), ra.pinv[s], pm, pmu);
+      const uint64_t d = mulmod_u16((uint32_t)sub_mod(r, barrett64(X, pm, pmu), pm), (uint32_t)ra.pinv[s],
+                                    (uint32_t)pm, ra.pmagic[s]);
       X += d * pre;
       pre *= pm;
     }
@@ -145,7 +168,8 @@ __global__ void __launch_bounds__(256) k_chain_rescale(const uint16_t* res, int6
       if (j >= ra.level) break;
       const Mod& M = ra.mod[j];
       const uint64_t cj = res[(int64_t)(ra.np + j) * n + e];
-      out[(int64_t)j * n + e] = mul_mod(sub_mod(cj, from_signed(xp, M.q, M.mu), M.q), ra.Pinv[j], M.q, M.mu);
+      out[(int64_t)j * n + e] = mulmod_u16((uint32_t)sub_mod(cj, from_signed(xp, M.q, M.mu), M.q),
+                                           (uint32_t)ra.Pinv[j], (uint32_t)M.q, ra.qmagic[j]);
     }
   }
 }

@@ -52,6 +52,29 @@ int64_t xc_ntt_signed(const int64_t* in, const uint64_t* w, int logn, uint64_t q
   return (int64_t)big;
 }
 
+// Mismatches of mod_u32 against x % m: every x < 2^24, every x within 3 of a multiple of m up to 2^32,
+// 2^32 - 1, and n_random pseudo-random x (splitmix64).
+int64_t xc_mod_u32_sweep(uint32_t m, int64_t n_random) {
+  const uint32_t magic = magic_u32(m);
+  int64_t bad = 0;
+  for (uint32_t x = 0; x < (1u << 24); ++x) bad += mod_u32(x, m, magic) != x % m;
+  for (uint64_t k = 1; k * m < (1ull << 32) + 4; ++k)
+    for (int d = -3; d <= 3; ++d) {
+      const int64_t x = (int64_t)(k * m) + d;
+      if (x >= 0 && x < (int64_t)(1ull << 32)) bad += mod_u32((uint32_t)x, m, magic) != (uint32_t)x % m;
+    }
+  bad += mod_u32(0xFFFFFFFFu, m, magic) != 0xFFFFFFFFu % m;
+  uint64_t z = 0x9E3779B97F4A7C15ull * m;
+  for (int64_t i = 0; i < n_random; ++i) {
+    z += 0x9E3779B97F4A7C15ull;
+    uint64_t t = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    t = (t ^ (t >> 27)) * 0x94D049BB133111EBull;
+    const uint32_t x = (uint32_t)(t ^ (t >> 31));
+    bad += mod_u32(x, m, magic) != x % m;
+  }
+  return bad;
+}
+
 void xc_mod_small(const uint32_t* x, int64_t n, uint32_t m, uint32_t* out) {
   const uint32_t magic = (uint32_t)(((1ull << 32) + m - 1) / m);
   for (int64_t i = 0; i < n; ++i) out[i] = mod_small(x[i], m, magic);

@@ -12,6 +12,7 @@ C's integer remainder inside the harness.
                 the signed product (|a| <= 16q, centered result), reduction and butterfly of the
                 FormatSwitch transforms, and a whole transform built from them
   mod_small     x mod m by multiply-high, x < 2^24, 2 <= m <= 256 (every x, every m)
+  mod_u32       x mod m by multiply-high with one correction, x < 2^32, m <= 2^16 (the chain's n^2)
   mod_f64       x mod m by an fp64 quotient, |x| < 2^48, m < 2^24
   balanced_mod  the RNS form's int8 residues, |x| < 2^40
   p2_digits     the n^2 form's digits M + n M', |x| < 2^48
@@ -54,6 +55,8 @@ for _name, _args in {
     getattr(_L, _name).argtypes = _args
     getattr(_L, _name).restype = None
 _L.xc_ntt_signed.restype = ctypes.c_int64
+_L.xc_mod_u32_sweep.restype = ctypes.c_int64
+_L.xc_mod_u32_sweep.argtypes = [ctypes.c_uint32, ctypes.c_int64]
 
 # The moduli tables of the library (hfe_exact.h); their values are fixed by the paper's ranges
 # (RNS: pairwise coprime, <= 256; n^2: primes 127 <= n <= 253) and checked below.
@@ -153,6 +156,13 @@ def test_signed_transform_equals_the_negacyclic_evaluation(logn):
     for i in list(range(0, n, max(1, n // 64))) + [n - 1]:
         z = pow(psi, 2 * brv[i] + 1, q)
         assert int(out[i]) == sum(c * pow(z, t, q) for t, c in enumerate(xs)) % q
+
+
+@pytest.mark.parametrize("m", [255, 256, 16129, 38809, 39601, 44521, 49729, 51529, 57121, 63001, 65536])
+def test_mod_u32_exact(m):
+    """x mod m for 32-bit x and the n^2 moduli (127^2 .. 251^2 and the default chain's): every x < 2^24,
+    every x within 3 of a multiple of m, 2^32 - 1, and 2 M pseudo-random x."""
+    assert _L.xc_mod_u32_sweep(m, 2_000_000) == 0
 
 
 def test_mod_small_exact_for_every_operand():
