@@ -135,17 +135,31 @@ HFE_HD uint64_t uniform_at(uint64_t seed, uint64_t key1, uint64_t i0, uint64_t i
   return 0;
 }
 
+// The CDT sample of one word pair: magnitude = #{j : w >= T[j]}, negative iff magnitude > 0 and the
+// sign word is odd.
+HFE_HD int32_t cdt_sample(uint64_t w, uint64_t sw, const uint64_t* cdt) {
+  int32_t mag = 0;
+#pragma unroll
+  for (int j = 0; j < 19; ++j) mag += (w >= cdt[j]) ? 1 : 0;
+  return ((sw & 1) && mag) ? -mag : mag;
+}
+
 // Discrete Gaussian at element (i0, i1): block (i0 >> 1, i1, 0, 0), words (2h, 2h + 1) with
 // h = i0 & 1; magnitude = #{j : w >= T[j]}, negative iff magnitude > 0 and the sign word is odd.
 HFE_HD int32_t gaussian_at(uint64_t seed, uint64_t key1, uint64_t i0, uint64_t i1,
                            const uint64_t* cdt) {
   Philox4 b = philox4x64_10(seed, key1, i0 >> 1, i1, 0, 0);
   const bool h = (i0 & 1) != 0;  // words 2h, 2h + 1 of the block (selected, not indexed: registers)
-  const uint64_t w = h ? b.v[2] : b.v[0], sw = h ? b.v[3] : b.v[1];
-  int32_t mag = 0;
-#pragma unroll
-  for (int j = 0; j < 19; ++j) mag += (w >= cdt[j]) ? 1 : 0;
-  return ((sw & 1) && mag) ? -mag : mag;
+  return cdt_sample(h ? b.v[2] : b.v[0], h ? b.v[3] : b.v[1], cdt);
+}
+
+// The Gaussians of elements (2u, i1) and (2u + 1, i1) from their one block: the same values as two
+// gaussian_at calls for half the Philox evaluations.
+HFE_HD void gaussian_pair_at(uint64_t seed, uint64_t key1, uint64_t u, uint64_t i1, const uint64_t* cdt,
+                             int32_t& e0, int32_t& e1) {
+  Philox4 b = philox4x64_10(seed, key1, u, i1, 0, 0);
+  e0 = cdt_sample(b.v[0], b.v[1], cdt);
+  e1 = cdt_sample(b.v[2], b.v[3], cdt);
 }
 
 }  // namespace hfe

@@ -154,6 +154,28 @@ __device__ __forceinline__ void ntt_fwd_lds(double* a, const NttTab& T) {
   }
 }
 
+// The same transform on signed values without corrections (fwd_round_c): inputs in [0, q) give
+// outputs congruent to the exact ones, below 8.1q in magnitude for degrees up to 2^14.
+__device__ __forceinline__ void ntt_fwd_lds_c(double* a, const NttTab& T) {
+  const int n = 1 << T.logn;
+  int t = n >> 1, left = T.logn;
+  while (left > 0) {
+    if (left >= 3) {
+      fwd_round_c<3>(a, T, n, t);
+      t >>= 3;
+      left -= 3;
+    } else if (left == 2) {
+      fwd_round_c<2>(a, T, n, t);
+      t >>= 2;
+      left -= 2;
+    } else {
+      fwd_round_c<1>(a, T, n, t);
+      t >>= 1;
+      left -= 1;
+    }
+  }
+}
+
 // Inverse negacyclic NTT in place (input in bit-reversed order), including the 1/n factor.
 __device__ __forceinline__ void ntt_inv_lds(double* a, const NttTab& T) {
   const int n = 1 << T.logn;

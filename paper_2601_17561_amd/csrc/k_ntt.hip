@@ -248,8 +248,9 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
     }
   }
   __syncthreads();
-  // NTT(a_c) once, kept in registers (n / blockDim = R values per thread) for all chunks.
-  ntt_fwd_lds(lds, T);
+  // NTT(a_c) once (signed, uncorrected: below 8.1q), kept in registers (n / blockDim = R values per
+  // thread) for all chunks.
+  ntt_fwd_lds_c(lds, T);
   double ahat[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -263,19 +264,25 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int t = threadIdx.x + r * blockDim.x;
-      if (t < n) lds[t] = mulmod_d(ahat[r], to_d(w[t]), T.qd, T.qinv);
+      if (t < n) lds[t] = residue_of_c(mulmod_c_d(ahat[r], to_d(w[t]), T.qd, T.qinv), T.qd);
     }
     __syncthreads();
     ntt_inv_lds(lds, T);
     const int64_t lo = (int64_t)j * n;
     const int64_t hi = lo + n < A.d2 ? lo + n : A.d2;
-    for (int64_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-      const int8_t mv = m[t];
-      const uint64_t dm = mv == 1 ? delta : (mv == -1 ? (delta ? q - delta : 0) : 0);
-      const int32_t e = gaussian_at(A.seed, key_e, (uint64_t)t, (uint64_t)c, A.cdt);
-      uint64_t val = sub_mod(dm, CHAIN ? from_ntt(lds[t - lo], T.q, M) : to_u(lds[t - lo]), q);
-      val = add_mod(val, from_signed(e, q, M.mu), q);
-      row[t] = val;
+    // positions in pairs (lo is even): both Gaussians of a pair come from one Philox block
+    for (int64_t t = lo + 2 * (int64_t)threadIdx.x; t < hi; t += 2 * (int64_t)blockDim.x) {
+      int32_t e2[2];
+      gaussian_pair_at(A.seed, key_e, (uint64_t)t >> 1, (uint64_t)c, A.cdt, e2[0], e2[1]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (t + h >= hi) break;
+        const int8_t mv = m[t + h];
+        const uint64_t dm = mv == 1 ? delta : (mv == -1 ? (delta ? q - delta : 0) : 0);
+        uint64_t val = sub_mod(dm, CHAIN ? from_ntt(lds[t + h - lo], T.q, M) : to_u(lds[t + h - lo]), q);
+        val = add_mod(val, from_signed(e2[h], q, M.mu), q);
+        row[t + h] = val;
+      }
     }
     __syncthreads();
   }
@@ -315,9 +322,10 @@ k_dec_products(const uint64_t* out, int64_t R_out, int64_t row0, int64_t rows, N
   const uint64_t* ocol = out + c * R_out;
   for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = CHAIN ? to_ntt(ocol[v], q, T.q) : to_d(ocol[v]);
   __syncthreads();
-  ntt_fwd_lds(lds, T);
+  ntt_fwd_lds_c(lds, T);  // signed, uncorrected: below 8.1q
   const uint64_t* w = sdb_hat + (int64_t)j * 2 * n;
-  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = mulmod_d(lds[v], to_d(w[v]), T.qd, T.qinv);
+  for (int v = threadIdx.x; v < n; v += blockDim.x)
+    lds[v] = residue_of_c(mulmod_c_d(lds[v], to_d(w[v]), T.qd, T.qinv), T.qd);
   __syncthreads();
   ntt_inv_lds(lds, T);
   int64_t lo = (int64_t)j * n - row0, hi = lo + n;
