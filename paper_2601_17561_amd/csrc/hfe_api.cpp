@@ -2102,6 +2102,9 @@ hfe_status hfe::decrypt_impl(const hfe_keys* K, const hfe_rct* R, double* v, int
     da.mu[i] = ch ? K->cmod[i].mu : K->mods[i].mu;
   }
   garner_consts_of(qs, level, da.garner, da.half_digits);
+  da.small = ch ? 1 : 0;
+  if (ch)
+    for (int i = 0; i < level; ++i) da.magic[i] = magic_u32((uint32_t)qs[i]);
   Big Q(1);
   for (int i = 0; i < level; ++i) Q.mul(qs[i]);
   for (size_t j = 0; j < 5 && j < Q.w.size(); ++j) da.Qw[j] = Q.w[j];

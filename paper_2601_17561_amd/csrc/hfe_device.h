@@ -66,6 +66,26 @@ __device__ __forceinline__ void garner_digits(const uint64_t* y, int level,
   }
 }
 
+// The same digits when every modulus is at most 2^16 (the n^2 chain), in 32-bit products:
+// magic[i] = ceil(2^32 / q_i), and the Garner constants below q_i.
+template <class T>
+__device__ __forceinline__ void garner_digits_u16(const T* y, int level, const uint64_t (*garner)[HFE_MAX_QPRIMES],
+                                                  const uint64_t* q, const uint32_t* magic, T* v) {
+#pragma unroll
+  for (int i = 0; i < HFE_MAX_QPRIMES; ++i) {
+    if (i >= level) break;
+    const uint32_t qi = (uint32_t)q[i], mg = magic[i];
+    uint32_t acc = 0;  // (v_0 + v_1 q_0 + ...) mod q_i
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      acc += mulmod_u16(mod_u32((uint32_t)v[j], qi, mg), (uint32_t)garner[i][j], qi, mg);
+      acc = acc >= qi ? acc - qi : acc;
+    }
+    const uint32_t yi = (uint32_t)y[i];
+    v[i] = i == 0 ? (T)yi : (T)mulmod_u16(yi >= acc ? yi - acc : yi + qi - acc, (uint32_t)garner[i][i], qi, mg);
+  }
+}
+
 // Y > (Q - 1)/2, compared on mixed-radix digits from the most significant one.
 __device__ __forceinline__ bool above_half(const uint64_t* v, const uint64_t* half, int level) {
   bool gt = false, decided = false;

@@ -517,6 +517,8 @@ struct DecodeArgs {
   uint64_t half_digits[HFE_MAX_QPRIMES];
   uint64_t Qw[5];           // Q as 64-bit words
   int delta_log;
+  int small;                // every modulus at most 2^16 (the n^2 chain): Garner in 32-bit products
+  uint32_t magic[HFE_MAX_QPRIMES];  // ceil(2^32 / q_i) when small
 };
 hipError_t launch_decode(const uint64_t* y, int64_t n, const DecodeArgs& da, double* v, int32_t* ip,
                          hipStream_t s);

@@ -79,18 +79,7 @@ __global__ void __launch_bounds__(256) k_chain_lift(const uint64_t* XT, int64_t 
 #pragma unroll
     for (int i = 0; i < HFE_MAX_QPRIMES; ++i)
       if (i < la.level) y[i] = (uint32_t)XT[((int64_t)i * d3 + c) * K + k];
-#pragma unroll
-    for (int i = 0; i < HFE_MAX_QPRIMES; ++i) {
-      if (i >= la.level) break;
-      const uint32_t qi = (uint32_t)la.q[i], mg = la.qmagic[i];
-      uint32_t acc = 0;  // (v_0 + v_1 m_0 + ... ) mod m_i
-#pragma unroll
-      for (int j = 0; j < i; ++j) {
-        acc += mulmod_u16(mod_u32(v[j], qi, mg), (uint32_t)la.garner[i][j], qi, mg);
-        acc = acc >= qi ? acc - qi : acc;
-      }
-      v[i] = i == 0 ? y[0] : mulmod_u16(y[i] >= acc ? y[i] - acc : y[i] + qi - acc, (uint32_t)la.garner[i][i], qi, mg);
-    }
+    garner_digits_u16(y, la.level, la.garner, la.q, la.qmagic, v);
     bool neg = false, decided = false;  // the lift above (Q - 1) / 2, compared on the digits from the top
 #pragma unroll
     for (int i = HFE_MAX_QPRIMES - 1; i >= 0; --i)

@@ -181,7 +181,10 @@ __global__ void k_decode(const uint64_t* y, int64_t n, DecodeArgs da, double* v,
 #pragma unroll
     for (int i = 0; i < HFE_MAX_QPRIMES; ++i)
       if (i < da.level) r[i] = y[(int64_t)i * n + e];
-    garner_digits(r, da.level, da.garner, da.q, da.mu, g);
+    if (da.small)
+      garner_digits_u16(r, da.level, da.garner, da.q, da.magic, g);
+    else
+      garner_digits(r, da.level, da.garner, da.q, da.mu, g);
     // Horner: Y = g_{l-1}; Y = Y * q_i + g_i for i = l-2 .. 0 (5 words, little endian)
     uint64_t w[5] = {0, 0, 0, 0, 0};
 #pragma unroll
