@@ -792,6 +792,21 @@ hfe_status hfe_encrypt(const hfe_keys* keys, const int8_t* m_q, int64_t d3, uint
   a.d2 = P.d2;
   a.K = Q->K;
   a.k = K->k;
+  // the errors are the same integers for every prime: drawn once when more than one prime needs them
+  // (the LDS-resident transforms; the two-pass ones draw their own)
+  DevBuf errs;
+  if (level > 1 && P.log_n_q <= (uint32_t)kMaxLogN) {
+    st = errs.alloc((size_t)d3 * P.d2, s);
+    if (st == HFE_OK) {
+      const hipError_t e = launch_q_errors(seed, a.cdt, d3, P.d2, errs.as<int8_t>(), s);
+      if (e != hipSuccess) st = hip_fail(e, "launch_q_errors");
+    }
+    if (st != HFE_OK) {
+      delete Q;
+      return st;
+    }
+    a.e = errs.as<int8_t>();
+  }
   const int dl = delta_log(K, (int)level);
   for (uint32_t i = 0; i < level; ++i) {
     // the n^2 chain: modulus n_i^2, products with the secrets through the NTT prime (slot 0)

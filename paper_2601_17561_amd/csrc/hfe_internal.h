@@ -228,7 +228,11 @@ struct QEncArgs {
   const uint64_t* cdt;
   int64_t d3, d2, K;
   int k;
+  const int8_t* e = nullptr;  // the query errors e(t, c), d3 x d2, when drawn once for every prime
 };
+// The query errors of an encryption (stream QE, element (t, c); the same for every prime) into
+// e[c][t], d3 x d2 (|e| <= 19 fits int8), two positions from each Philox block.
+hipError_t launch_q_errors(uint64_t seed, const uint64_t* cdt, int64_t d3, int64_t d2, int8_t* e, hipStream_t s);
 hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prime_id,
                             const Mod& m, uint64_t delta_mod, NttTab tab_q,
                             const uint64_t* s_hat_prime, hipStream_t s);

@@ -270,10 +270,16 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
     ntt_inv_lds(lds, T);
     const int64_t lo = (int64_t)j * n;
     const int64_t hi = lo + n < A.d2 ? lo + n : A.d2;
-    // positions in pairs (lo is even): both Gaussians of a pair come from one Philox block
+    // positions in pairs (lo is even): the errors drawn once for every prime, or both Gaussians of a
+    // pair from one Philox block
     for (int64_t t = lo + 2 * (int64_t)threadIdx.x; t < hi; t += 2 * (int64_t)blockDim.x) {
       int32_t e2[2];
-      gaussian_pair_at(A.seed, key_e, (uint64_t)t >> 1, (uint64_t)c, A.cdt, e2[0], e2[1]);
+      if (A.e) {
+        e2[0] = A.e[c * A.d2 + t];
+        e2[1] = t + 1 < hi ? A.e[c * A.d2 + t + 1] : 0;
+      } else {
+        gaussian_pair_at(A.seed, key_e, (uint64_t)t >> 1, (uint64_t)c, A.cdt, e2[0], e2[1]);
+      }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (t + h >= hi) break;
@@ -286,6 +292,26 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
     }
     __syncthreads();
   }
+}
+
+__global__ void k_q_errors(uint64_t seed, const uint64_t* cdt, int64_t d3, int64_t d2, int8_t* e) {
+  const int64_t half = (d2 + 1) / 2, n = d3 * half;
+  const uint64_t key_e = stream_tag(kQE, 0);
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = x / half, u = x - c * half;
+    int32_t e0, e1;
+    gaussian_pair_at(seed, key_e, (uint64_t)u, (uint64_t)c, cdt, e0, e1);
+    e[c * d2 + 2 * u] = (int8_t)e0;
+    if (2 * u + 1 < d2) e[c * d2 + 2 * u + 1] = (int8_t)e1;
+  }
+}
+
+hipError_t launch_q_errors(uint64_t seed, const uint64_t* cdt, int64_t d3, int64_t d2, int8_t* e, hipStream_t s) {
+  const int64_t n = d3 * ((d2 + 1) / 2);
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+  hipLaunchKernelGGL(k_q_errors, dim3((unsigned)blocks), dim3(256), 0, s, seed, cdt, d3, d2, e);
+  return hipGetLastError();
 }
 
 hipError_t launch_q_encrypt(const QEncArgs& a, uint64_t* XT_prime, uint32_t prime_id, const Mod& m,
