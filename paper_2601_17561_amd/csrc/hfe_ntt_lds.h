@@ -133,6 +133,43 @@ __device__ __forceinline__ void inv_round(double* a, const NttTab& T, int n, int
   __syncthreads();
 }
 
+// The inverse round on signed values: the round first takes its values (any integers below 2^47 in
+// magnitude) to centered representatives (reduce_c_d, at most (1/2 + 2^-11) q), so that its S <= 3
+// Gentleman-Sande stages (X + Y, and (X - Y) W centered) keep every value below 4.01q and every
+// product operand below 8.02q; the last round scales by 1/n and returns residues in [0, q).
+template <int S>
+__device__ __forceinline__ void inv_round_c(double* a, const NttTab& T, int n, int t, bool last) {
+  constexpr int G = 1 << S;
+  const double q = T.qd, qinv = T.qinv;
+  for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
+    const int B = g / t, r = g - B * t;
+    const int base = B * G * t + r;
+    double x[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) x[k] = reduce_c_d(a[base + k * t], q, qinv);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int h = 1 << s;
+      const int m = n / (2 * h * t);
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        if (k & h) continue;
+        const int w = m + (B << (S - 1 - s)) + (k >> (s + 1));
+        const double U = x[k], V = x[k + h];
+        x[k] = U + V;
+        x[k + h] = mulmod_c_d(U - V, T.ipsi_d[w], q, qinv);
+      }
+    }
+    if (last) {
+#pragma unroll
+      for (int k = 0; k < G; ++k) x[k] = residue_of_c(mulmod_c_d(x[k], T.n_inv_d, q, qinv), q);
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) a[base + k * t] = x[k];
+  }
+  __syncthreads();
+}
+
 // Forward negacyclic NTT in place (output in bit-reversed order).
 __device__ __forceinline__ void ntt_fwd_lds(double* a, const NttTab& T) {
   const int n = 1 << T.logn;
@@ -171,6 +208,28 @@ __device__ __forceinline__ void ntt_fwd_lds_c(double* a, const NttTab& T) {
     } else {
       fwd_round_c<1>(a, T, n, t);
       t >>= 1;
+      left -= 1;
+    }
+  }
+}
+
+// The inverse on signed inputs (any integers below 2^47 in magnitude) through inv_round_c; outputs in
+// [0, q), the same residues as ntt_inv_lds of the inputs' residues.
+__device__ __forceinline__ void ntt_inv_lds_c(double* a, const NttTab& T) {
+  const int n = 1 << T.logn;
+  int t = 1, left = T.logn;
+  while (left > 0) {
+    if (left >= 3) {
+      inv_round_c<3>(a, T, n, t, left == 3);
+      t <<= 3;
+      left -= 3;
+    } else if (left == 2) {
+      inv_round_c<2>(a, T, n, t, true);
+      t <<= 2;
+      left -= 2;
+    } else {
+      inv_round_c<1>(a, T, n, t, true);
+      t <<= 1;
       left -= 1;
     }
   }

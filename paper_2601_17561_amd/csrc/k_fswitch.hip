@@ -229,7 +229,7 @@ k_fs_tx_b(FsConsts C, uint64_t seed, const int8_t* m_q, int64_t ncols, const uin
 #pragma unroll
   for (int k = 0; k < R; ++k) lds[threadIdx.x + k * blockDim.x] = acc[k];
   __syncthreads();
-  ntt_inv_lds(lds, C.tab[i]);
+  ntt_inv_lds_c(lds, C.tab[i]);
   const int64_t c = col / C.k, j = col - c * C.k;
   const Mod& M = C.mod[i];
   const uint64_t sc = (uint64_t)C.scale[i];
@@ -335,7 +335,7 @@ __device__ __forceinline__ double mac_c(double acc, double x, double w, double q
 }
 
 // Inverse transform of the values x (positions 8g + k as above) through LDS, written to out in
-// natural order; x signed accumulators (reduced to [0, q) first).
+// natural order; x signed accumulators (below 2^47 in magnitude; the signed inverse reduces them).
 template <int GPT>
 __device__ __forceinline__ void ntt_inv_store(double* lds, const NttTab& T, const double (&x)[GPT][8], double* out) {
   const int n = 1 << T.logn;
@@ -344,10 +344,10 @@ __device__ __forceinline__ void ntt_inv_store(double* lds, const NttTab& T, cons
   for (int j = 0; j < GPT; ++j) {
     const int g = threadIdx.x + j * blockDim.x;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) lds[8 * g + k] = residue_of_c(reduce_c_d(x[j][k], T.qd, T.qinv), T.qd);
+    for (int k = 0; k < 8; ++k) lds[8 * g + k] = x[j][k];
   }
   __syncthreads();
-  ntt_inv_lds(lds, T);
+  ntt_inv_lds_c(lds, T);
   for (int v = threadIdx.x; v < n; v += blockDim.x) out[v] = lds[v];
 }
 

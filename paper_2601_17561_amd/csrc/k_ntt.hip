@@ -264,10 +264,10 @@ k_q_encrypt(QEncArgs A, uint64_t* XT, uint32_t prime_id, Mod M, uint64_t delta, 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int t = threadIdx.x + r * blockDim.x;
-      if (t < n) lds[t] = residue_of_c(mulmod_c_d(ahat[r], to_d(w[t]), T.qd, T.qinv), T.qd);
+      if (t < n) lds[t] = mulmod_c_d(ahat[r], to_d(w[t]), T.qd, T.qinv);  // centered
     }
     __syncthreads();
-    ntt_inv_lds(lds, T);
+    ntt_inv_lds_c(lds, T);  // residues in [0, q)
     const int64_t lo = (int64_t)j * n;
     const int64_t hi = lo + n < A.d2 ? lo + n : A.d2;
     // positions in pairs (lo is even): the errors drawn once for every prime, or both Gaussians of a
@@ -350,10 +350,9 @@ k_dec_products(const uint64_t* out, int64_t R_out, int64_t row0, int64_t rows, N
   __syncthreads();
   ntt_fwd_lds_c(lds, T);  // signed, uncorrected: below 8.1q
   const uint64_t* w = sdb_hat + (int64_t)j * 2 * n;
-  for (int v = threadIdx.x; v < n; v += blockDim.x)
-    lds[v] = residue_of_c(mulmod_c_d(lds[v], to_d(w[v]), T.qd, T.qinv), T.qd);
+  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = mulmod_c_d(lds[v], to_d(w[v]), T.qd, T.qinv);
   __syncthreads();
-  ntt_inv_lds(lds, T);
+  ntt_inv_lds_c(lds, T);  // residues in [0, q)
   int64_t lo = (int64_t)j * n - row0, hi = lo + n;
   if (lo < 0) lo = 0;
   if (hi > rows) hi = rows;

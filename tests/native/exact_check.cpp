@@ -75,6 +75,49 @@ int64_t xc_mod_u32_sweep(uint32_t m, int64_t n_random) {
   return bad;
 }
 
+// The inverse transform of the kernels on signed values (rounds of up to three Gentleman-Sande stages,
+// each round starting from centered representatives, the last one scaling by n_inv), twiddles iw[m + j]
+// as in the tables: out[i] in [0, q).  Returns the largest magnitude met inside a round.
+int64_t xc_intt_signed(const int64_t* in, const uint64_t* iw, int logn, uint64_t q, uint64_t n_inv, uint64_t* out) {
+  const int n = 1 << logn;
+  const double qd = (double)q, qinv = 1.0 / qd;
+  double* a = new double[n];
+  for (int i = 0; i < n; ++i) a[i] = (double)in[i];
+  double big = 0.0;
+  int t = 1, left = logn;
+  while (left > 0) {
+    const int S = left >= 3 ? 3 : left;
+    const bool last = left == S;
+    const int G = 1 << S;
+    for (int g = 0; g < (n >> S); ++g) {
+      const int B = g / t, r = g - B * t, base = B * G * t + r;
+      double x[8];
+      for (int k = 0; k < G; ++k) x[k] = reduce_c_d(a[base + k * t], qd, qinv);
+      for (int s = 0; s < S; ++s) {
+        const int h = 1 << s, m = n / (2 * h * t);
+        for (int k = 0; k < G; ++k) {
+          if (k & h) continue;
+          const int w = m + (B << (S - 1 - s)) + (k >> (s + 1));
+          const double U = x[k], V = x[k + h];
+          const double d = U - V;
+          big = __builtin_fabs(d) > big ? __builtin_fabs(d) : big;
+          x[k] = U + V;
+          x[k + h] = mulmod_c_d(d, (double)iw[w], qd, qinv);
+          big = __builtin_fabs(x[k]) > big ? __builtin_fabs(x[k]) : big;
+        }
+      }
+      if (last)
+        for (int k = 0; k < G; ++k) x[k] = residue_of_c(mulmod_c_d(x[k], (double)n_inv, qd, qinv), qd);
+      for (int k = 0; k < G; ++k) a[base + k * t] = x[k];
+    }
+    t <<= S;
+    left -= S;
+  }
+  for (int i = 0; i < n; ++i) out[i] = (uint64_t)a[i];
+  delete[] a;
+  return (int64_t)big;
+}
+
 void xc_mod_small(const uint32_t* x, int64_t n, uint32_t m, uint32_t* out) {
   const uint32_t magic = (uint32_t)(((1ull << 32) + m - 1) / m);
   for (int64_t i = 0; i < n; ++i) out[i] = mod_small(x[i], m, magic);

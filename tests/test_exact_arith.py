@@ -55,6 +55,8 @@ for _name, _args in {
     getattr(_L, _name).argtypes = _args
     getattr(_L, _name).restype = None
 _L.xc_ntt_signed.restype = ctypes.c_int64
+_L.xc_intt_signed.restype = ctypes.c_int64
+_L.xc_intt_signed.argtypes = [_p, _p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, _p]
 _L.xc_mod_u32_sweep.restype = ctypes.c_int64
 _L.xc_mod_u32_sweep.argtypes = [ctypes.c_uint32, ctypes.c_int64]
 
@@ -163,6 +165,37 @@ def test_mod_u32_exact(m):
     """x mod m for 32-bit x and the n^2 moduli (127^2 .. 251^2 and the default chain's): every x < 2^24,
     every x within 3 of a multiple of m, 2^32 - 1, and 2 M pseudo-random x."""
     assert _L.xc_mod_u32_sweep(m, 2_000_000) == 0
+
+
+@pytest.mark.parametrize("logn", [7, 12, 13, 14])
+def test_signed_inverse_transform_inverts_the_forward_one(logn):
+    """The signed inverse transform of the kernels (rounds from centered representatives) applied to the
+    exact forward transform returns the input, for inputs of any sign and size up to 2^40, and keeps every
+    value inside a round below 8.02q."""
+    q = OP.ntt_primes(1)[0]
+    n = 1 << logn
+    g = 2
+    while pow(g, (q - 1) // 2, q) == 1:
+        g += 1
+    psi = pow(g, (q - 1) // (2 * n), q)
+    brv = [int(format(i, f"0{logn}b")[::-1], 2) for i in range(n)]
+    ipsi = pow(psi, q - 2, q)
+    iw = np.array([pow(ipsi, brv[i], q) for i in range(n)], dtype=np.uint64)
+    w = np.array([pow(psi, brv[i], q) for i in range(n)], dtype=np.uint64)
+    rng = np.random.default_rng(logn + 100)
+    x = rng.integers(0, q, n, dtype=np.int64)
+    xs = [int(v) for v in x.tolist()]
+    # the forward transform (pinned against the evaluation at psi^(2 brv(i) + 1) above), then the inputs
+    # of the inverse spread over representatives of both signs and large magnitude
+    fwd = np.empty(n, dtype=np.uint64)
+    _L.xc_ntt_signed(_ptr(x), _ptr(w), logn, q, _ptr(fwd))
+    ev = [int(v) for v in fwd.tolist()]
+    k = rng.integers(-(1 << 4), 1 << 4, n)
+    inp = np.array([v + int(t) * q for v, t in zip(ev, k.tolist())], dtype=np.int64)
+    out = np.empty(n, dtype=np.uint64)
+    big = _L.xc_intt_signed(_ptr(inp), _ptr(iw), logn, q, pow(n, q - 2, q), _ptr(out))
+    assert big < 8.02 * q
+    assert out.tolist() == xs
 
 
 def test_mod_small_exact_for_every_operand():
