@@ -174,6 +174,69 @@ def cpu_baseline(w: S.Workload, inp, workers: int, rows_per_worker: int, cols: i
                 step_s=step_s)
 
 
+def _cpu_chain(args):
+    """The chain oracle's CCMM (lift, exact products mod every n^2, CRT and RS_P) on rows x cols of the
+    share shape (uniform residues: the oracle's work does not depend on their values), one core."""
+    w, chain_q, rows, cols = args
+    from oracle import chain as OCH
+    rng = np.random.default_rng(9)
+    C = OCH.make_chain_params(int(np.log2(rows)), w.log_n_q, chain_q, 3, w.d2, w.d1)
+    D = {n: rng.integers(0, n * n, (rows, C.K), dtype=np.int64) for n in C.all_bases()}
+    XT = {n: rng.integers(0, n * n, (cols, C.K), dtype=np.int64) for n in C.q_bases}
+    t0 = time.perf_counter()
+    OCH.lift_query(C, XT, chain_q)
+    t_lift = time.perf_counter() - t0  # per query column; the CCMM below repeats it
+    t0 = time.perf_counter()
+    OCH.ccmm(C, D, XT, chain_q, 0, 0)
+    return t_lift, max(time.perf_counter() - t0 - t_lift, 0.0), C.K
+
+
+def _cpu_fs(args):
+    """The FormatSwitch oracle on one query column of the share workload from ring degree 2^16, one
+    core: keys, transmission encryption and the switch timed apart."""
+    inp, = args
+    from oracle import formatswitch as FS
+    from oracle import iris as OI
+    from oracle import params as OP
+    fw = S.FS_SHARE
+    P = OP.make_params(fw.log_n_db, fw.log_n_q, fw.n_q_primes, fw.d2, fw.d1)
+    t0 = time.perf_counter()
+    F = FS.fs_keygen(P, fw.level, S.FS_LOG_N_T[fw.name], KEY_SEED)
+    t_keys = time.perf_counter() - t0
+    qc, qm = OI.shifted_queries(inp["q_codes"][:1], inp["q_masks"][:1], inp["shifts"][:1])
+    t0 = time.perf_counter()
+    ct = FS.encrypt_transmit(F, OI.ternary(qc, qm), TX_SEED)
+    t_tx = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    FS.format_switch(F, ct, 1)
+    return t_keys, t_tx, time.perf_counter() - t0
+
+
+def cpu_baseline_chain_fs(w: S.Workload, inp, chain_q: int, rows: int = 128, cols: int = 4):
+    """The oracle beside two more measurements, in two processes side by side (one core each): the n^2
+    chain's CCMM on a sample scaled to the step's rows and columns, and FormatSwitch of one query column
+    scaled to the workload's columns.  Runs before the GPU is touched."""
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(2) as pool:
+        rc = pool.apply_async(_cpu_chain, ((w, chain_q, rows, cols),))
+        rf = pool.apply_async(_cpu_fs, ((inp,),))
+        t_lift, t_rows, K = rc.get()
+        t_keys, t_tx, t_fs = rf.get()
+    work = algorithmic_work(w)
+    chain_step = t_lift * (w.d3 / cols) + t_rows * (work["R_out"] / rows) * (w.d3 / cols)
+    chain = dict(value=w.d1 * w.d3 / chain_step, unit="comparisons/s", cores=1, kind="oracle",
+                 sample=(f"the chain oracle's CCMM of {rows} database rows x {cols} columns x full K={K} over "
+                         f"{chain_q} + 3 moduli n^2 (1 core): centered lift of the {cols} columns {t_lift:.1f} s, "
+                         f"exact products, CRT and RS_P {t_rows:.1f} s; scaled to {work['R_out']} rows and "
+                         f"{w.d3} columns: {chain_step:.0f} s per CCMM (encryption and decryption not included)"))
+    fw = S.FS_SHARE
+    fs = dict(value=1.0 / t_fs, unit="columns/s", cores=1, kind="oracle",
+              sample=(f"the FormatSwitch oracle on one query column of the share workload (2^16 -> 2^13, level "
+                      f"{fw.level}): keys {t_keys:.1f} s, transmission encryption {t_tx:.1f} s, the switch "
+                      f"{t_fs:.1f} s (1 core); {t_fs * fw.d3:.0f} s for the {fw.d3} columns"))
+    return chain, fs
+
+
 def encrypt_database(H, torch, w, forms):
     inp_db = S.db_templates(w.seed, w.d1, w.d2)
     P = H.hfe_default_params(w.log_n_db, w.log_n_q, w.n_q_primes, w.d2, w.d1)
@@ -566,7 +629,7 @@ def main():
     w = S.WORKLOADS[args.workload]
     work = algorithmic_work(w)
     inp = S.make_inputs(w)
-    cpu = None
+    cpu = cpu_chain = cpu_fs = None
     if args.mode == "step" and not args.no_cpu_baseline and not (args.sweep or args.ccmm_only):
         # before anything touches the GPU: the oracle's process pool is forked from this process
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
@@ -574,6 +637,10 @@ def main():
         cpu = cpu_baseline(w, inp, workers, args.cpu_rows, args.cpu_cols, enc_cols=4, dec_rows=1024)
         log(f"oracle: {cpu['sample']}")
         cpu.pop("step_s")
+        if w.name == S.PAPER_SHARE.name:
+            cpu_chain, cpu_fs = cpu_baseline_chain_fs(w, inp, args.chain_q_mods)
+            log(f"oracle: {cpu_chain['sample']}")
+            log(f"oracle: {cpu_fs['sample']}")
 
     import torch
     import paper_2601_17561_amd as H
@@ -840,7 +907,8 @@ def main():
                   "Q_bits": chain_q_bits, "P_bits": chain_p_bits, "db_encrypt_s": t_chain_db,
                   "over_i8_step": i8["ms_per_step"] / results["chain"]["ms_per_step"],
                   "over_rns_step": rns["ms_per_step"] / results["chain"]["ms_per_step"],
-                  "equals_i8_ip": same_chain, "phases_ms": results["chain"]["phases_ms"]},
+                  "equals_i8_ip": same_chain, "phases_ms": results["chain"]["phases_ms"],
+                  "cpu_baseline": cpu_chain},
         "i8_over_plain_step": plain["ms_per_step"] / i8["ms_per_step"] if plain else None,
         "stages_ms": {"lift_split": i8["lift_ms"], "contraction": i8["contraction_ms"],
                       "contraction_median": i8["contraction_median_ms"], "rescale": i8["rescale_ms"]},
@@ -864,6 +932,7 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         line["format_switch"] = run_format_switch(args, H, torch, steps=args.fs_steps)
+        line["format_switch"]["cpu_baseline"] = cpu_fs
     print(json.dumps(line), flush=True)
 
 
