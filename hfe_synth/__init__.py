@@ -201,7 +201,8 @@ def random_eyes(seed: int, stream: int, n_eyes: int, d2: int, p_code: float = 0.
 # Workloads of FormatSwitch (Appendix C.1): the query arrives in a transmission ring of degree
 # 2^FS_LOG_N_T[name] modulo one prime more than the CCMM level (n_q_primes = level + 1).  Tiny:
 # 2^10 -> 2^7 (rho 8), two chunks per column; mid: 2^12 -> 2^9 with three chunks per column (1,100
-# positions); paper: the paper's 2^16 -> 2^13 with its 12,800-bit codes at level 3.
+# positions); paper: the paper's 2^16 -> 2^13 with its 12,800-bit codes at level 3; wide: 2^15 -> 2^14,
+# the largest query ring (two register groups per thread in the fused transforms).
 FS_TINY = Workload("fs_ndb128_nq128_nt1024_L2_d1_64_d2_200_q3", 7, 7, 3, 2, 64, 200, 3, 1,
                    planted=(Planted(0, 5, 0, 0.1),), seed=BASE_SEED + 51)
 FS_FLAT = dataclasses.replace(FS_TINY, name="fs_ndb128_nq128_nt128_L1_d1_64_d2_200_q3", n_q_primes=2, level=1)
@@ -209,15 +210,19 @@ FS_MID = Workload("fs_ndb256_nq512_nt4096_L2_d1_300_d2_1100_q5", 8, 9, 3, 2, 300
                   planted=(Planted(2, 100, 0, 0.1),), seed=BASE_SEED + 52)
 FS_PAPER = Workload("fs_ndb16384_nq8192_nt65536_L3_d1_256_d2_12800_q2", 14, 13, 4, 3, 256, 12800, 2, 1,
                     planted=(Planted(1, 17, 0, 0.1),), seed=BASE_SEED + 53)
+FS_WIDE = Workload("fs_ndb128_nq16384_nt32768_L1_d1_64_d2_300_q2", 7, 14, 2, 1, 64, 300, 2, 1,
+                   planted=(Planted(0, 9, 0, 0.1),), seed=BASE_SEED + 54)
 # The share workload's queries (512 columns) through FormatSwitch: its keys carry a fourth prime for
 # the transmission modulus; the CCMM runs at level 3 as in the share workload.
 FS_SHARE = dataclasses.replace(PAPER_SHARE, name="fs_share_ndb16384_nq8192_nt65536_L3_d1_14336_d2_12800_q512",
                                n_q_primes=4, level=3)
-FS_LOG_N_T = {FS_TINY.name: 10, FS_FLAT.name: 7, FS_MID.name: 12, FS_PAPER.name: 16, FS_SHARE.name: 16}
+FS_LOG_N_T = {FS_TINY.name: 10, FS_FLAT.name: 7, FS_MID.name: 12, FS_PAPER.name: 16, FS_SHARE.name: 16,
+              FS_WIDE.name: 15}
 
 WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, MID, PAPER_SHARE, PAPER_SHARE_L5, BIG_DB,
                                                       BIG_Q, PAPER_LIT, CHAIN_TINY, CHAIN_MID,
-                                                      FS_TINY, FS_FLAT, FS_MID, FS_PAPER, FS_SHARE)}
+                                                      FS_TINY, FS_FLAT, FS_MID, FS_PAPER, FS_SHARE,
+                                                      FS_WIDE)}
 
 
 def planted_for(w: Workload, count: int = 4) -> Tuple[Planted, ...]:

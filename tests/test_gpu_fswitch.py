@@ -5,7 +5,8 @@ oracle/formatswitch.py bit-exactly: the secrets s_T and s', every residue of the
 ciphertexts, and every residue of the switched query ciphertext.  The switched query then goes
 through the CCMM in every form the shape allows and must decrypt to the popcount truth.
 Workloads: 2^10 -> 2^7 (rho 8, two chunks per column, levels 2), 2^7 -> 2^7 (rho 1: the key switch
-alone), 2^12 -> 2^9 (three chunks per column: two groups of conversion outputs), and the paper's
+alone), 2^12 -> 2^9 (three chunks per column: two groups of conversion outputs), 2^15 -> 2^14 (the largest
+query ring: two register groups per thread in the fused transforms), and the paper's
 2^16 -> 2^13 at level 3 with 12,800-bit codes, checked against the oracle's hashes of every residue
 (tests/golden/fs_paper.json, written by tests/golden/make_fs_paper.py from the oracle alone).
 """
@@ -65,7 +66,7 @@ def _ccmm_decrypts_to_truth(w, db, qct, keys, ip_true, forms):
         assert np.array_equal(ip.cpu().numpy(), ip_true), f"{f}: decryption after FormatSwitch != popcount truth"
 
 
-@pytest.mark.parametrize("wname", [S.FS_TINY.name, S.FS_FLAT.name, S.FS_MID.name])
+@pytest.mark.parametrize("wname", [S.FS_TINY.name, S.FS_FLAT.name, S.FS_MID.name, S.FS_WIDE.name])
 def test_format_switch_bit_exact(wname):
     w = S.WORKLOADS[wname]
     _say(f"[gpu-fs] {wname}: oracle (CPU)")
