@@ -55,8 +55,9 @@ hfe_status fs_consts(const hfe_keys* K, int l, int log_n_t, FsConsts& C) {
     lo = q < lo ? q : lo;
     hi = q > hi ? q : hi;
   }
-  // digits below q_i are taken mod every slot modulus with one subtraction, and every rescale corrects
-  // once each way: both need the moduli within a factor 2 of each other
+  // digits below q_i enter the signed transforms of every slot modulus z as they are (below 2z, the
+  // transforms' input bound), and every rescale corrects once each way: both need the moduli within a
+  // factor 2 of each other
   if (hi >= 2 * lo) return fail(HFE_EINVAL, "FormatSwitch needs q_0 .. q_level and p within a factor 2");
   const uint64_t p = K->primes[K->L];
   const uint64_t ql = K->primes[l];

@@ -175,7 +175,6 @@ hipError_t launch_fs_ck_finish(const FsConsts& C, const uint64_t* coef_hat, cons
 // T layout: [i <= l][col][a | b][N_T].
 
 // Workgroup (col, i rho + r): draws part r of a, writes its coefficients to T, and its transform.
-template <int R>
 __global__ void __launch_bounds__(kNttThreads)
 k_fs_tx_a(FsConsts C, uint64_t seed, int64_t ncols, double* Ahat, uint64_t* T) {
   extern __shared__ double lds[];
@@ -254,10 +253,10 @@ hipError_t launch_fs_tx(const FsConsts& C, uint64_t seed, const int8_t* m_q, int
   const dim3 grid((unsigned)ncols, (unsigned)((C.level + 1) * C.rho));
   return by_regs(regs_per_thread(C.logn_q), [&](auto rc) -> hipError_t {
     constexpr int R = decltype(rc)::value;
-    hipError_t e = allow_lds(k_fs_tx_a<R>, lds);
+    hipError_t e = allow_lds(k_fs_tx_a, lds);
     if (e == hipSuccess) e = allow_lds(k_fs_tx_b<R>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fs_tx_a<R>, grid, dim3(ntt_block(C.logn_q)), lds, s, C, seed, ncols, Ahat, T);
+    hipLaunchKernelGGL(k_fs_tx_a, grid, dim3(ntt_block(C.logn_q)), lds, s, C, seed, ncols, Ahat, T);
     hipLaunchKernelGGL(k_fs_tx_b<R>, grid, dim3(ntt_block(C.logn_q)), lds, s, C, seed, m_q, ncols, st_hat, y_hat,
                        cdt, Ahat, T);
     return hipGetLastError();
