@@ -225,6 +225,61 @@ WORKLOADS: Dict[str, Workload] = {w.name: w for w in (TINY, TINY_MULTI, MID, PAP
                                                       FS_WIDE)}
 
 
+# ---------------------------------------------------------------- normalise and fold
+# Inputs of the fold (Algorithm 2 after the CCMM): per score ciphertext c and slot j, the mask count
+# ||m_q AND m_db||_1 (Binomial(d2, 0.81): two masks of density 0.9) and the inner product
+# IP = round(score * count), with non-matching scores drawn from the normal law of Appendix C.2 (mean
+# 0.008, standard deviation 0.06) clipped to [-0.233, 0.3], and one planted matching score in
+# [0.35, 0.6] per group of k ciphertexts (at most one match per slot of a group: the folding
+# assumption).  Slots past d1 (the database entries of the last block) hold IP 0 with count 1.
+
+@dataclasses.dataclass(frozen=True)
+class FoldWorkload:
+    name: str
+    log_n: int           # ring degree of the fold
+    k: int               # folding factor
+    rho: int             # score ciphertexts per database block (query columns)
+    blocks: int          # database blocks of N/2 entries
+    d2: int              # code length (scale of the mask counts)
+    d1: int              # database entries (<= blocks N/2)
+    seed: int
+
+    @property
+    def count(self) -> int:
+        return self.blocks * self.rho
+
+
+def fold_inputs(w: FoldWorkload) -> Tuple[np.ndarray, np.ndarray]:
+    """(ip, counts), int32 arrays of shape (count, N/2), block-major (ciphertext b rho + c)."""
+    g = _rng(w.seed, 7)
+    slots = (1 << w.log_n) // 2
+    counts = g.binomial(w.d2, 0.81, (w.count, slots)).astype(np.int64)
+    scores = np.clip(g.normal(0.008, 0.06, (w.count, slots)), -0.233, 0.3)
+    groups = -(-w.rho // w.k)
+    for b in range(w.blocks):
+        for r in range(groups):
+            size = min(w.k, w.rho - r * w.k)
+            c = b * w.rho + r * w.k + int(g.integers(0, size))
+            scores[c, int(g.integers(0, slots))] = g.uniform(0.35, 0.6)
+    ip = np.rint(scores * counts).astype(np.int64)
+    for b in range(w.blocks):
+        live = w.d1 - b * slots
+        if live < slots:
+            lo = max(live, 0)
+            ip[b * w.rho:(b + 1) * w.rho, lo:] = 0
+            counts[b * w.rho:(b + 1) * w.rho, lo:] = 1
+    return ip.astype(np.int32), counts.astype(np.int32)
+
+
+FOLD_TINY = FoldWorkload("fold_n128_k4_rho6_b2", 7, 4, 6, 2, 200, 120, BASE_SEED + 61)
+FOLD_MID = FoldWorkload("fold_n1024_k16_rho20_b1", 10, 16, 20, 1, 1100, 512, BASE_SEED + 62)
+FOLD_PAPER = FoldWorkload("fold_n16384_k16_rho16_b1", 14, 16, 16, 1, 12800, 8192, BASE_SEED + 63)
+# The share workload's scores: 512 query columns against 14,336 database entries in two blocks of 8,192
+# slots at the fold's ring degree 2^14 (k = 16 as in Appendix C.2).
+FOLD_SHARE = FoldWorkload("fold_share_n16384_k16_rho512_b2_d1_14336", 14, 16, 512, 2, 12800, 14336, BASE_SEED + 64)
+FOLD_WORKLOADS: Dict[str, FoldWorkload] = {w.name: w for w in (FOLD_TINY, FOLD_MID, FOLD_PAPER, FOLD_SHARE)}
+
+
 def planted_for(w: Workload, count: int = 4) -> Tuple[Planted, ...]:
     """Planted eyes for a workload: its own list if given, else `count` random ones."""
     if w.planted:

@@ -423,6 +423,51 @@ hfe_status hfe_fs_encrypt(const hfe_fskeys* fk, const int8_t* m_q, int64_t d3, u
 hfe_status hfe_format_switch(const hfe_fskeys* fk, const uint64_t* T, int64_t d3, void* stream, hfe_qct** out);
 hfe_status hfe_fs_profile_ms(const hfe_qct* q, float* ms, int32_t n);
 
+/* ---------------------------------------------------------------- normalise and fold
+ * The step after the CCMM in Algorithm 2 (Section 4.1-4.3, Appendix C.2): a block of rho score
+ * ciphertexts ct_c, c < rho (slot j of ct_c holds the inner product of query column c with database
+ * entry j), becomes ceil(rho / k) ciphertexts
+ *   ct'_r = sum_{r' < min(k, rho - r k)} Rot_{r k + r'}( f( ct_{r k + r'} (.) Ecd(1 / count_{r k + r'}) ) )
+ * where count_c[j] = ||m_q,c AND m_db,j||_1 normalises the inner products into scores (a plaintext
+ * product), f is the degree-7 folding polynomial of Appendix C.2, evaluated in three levels, and Rot_r
+ * moves slot i to slot i + r (Section 4.3: slot i of the result holds the score of entry i - r).
+ * CKKS at ring degree N = 2^log_n (N/2 real slots, slot j at the root zeta^(5^j mod 2N)), secret of
+ * Hamming weight 32, moduli q_0 (36 bits), q_1 .. q_3 (near 2^23: the three levels of f at the scale of
+ * Appendix C.2), q_4 (36 bits: the normalisation) and a special prime p (36 bits) for key switching
+ * (one digit per prime).  Inputs are encrypted at scale 2^20 at level 4; the rotations and the sums of
+ * a group run at level 1 before one last rescale; folded ciphertexts sit at level 0 with scale 2^24.
+ * Rot_{r k + r'} is applied as Rot_{r k} after Rot_{r'}.  Ciphertexts live on the device in the NTT domain; hfe_export(fct, 0)
+ * gives their coefficient residues [count][b | a][q_0 .. q_level][N], hfe_shape(fct) {level, count,
+ * N, scale}, hfe_export(foldkeys, 0) the secret (N coefficients), hfe_shape(foldkeys) {log_n, k,
+ * rho, rotation keys}. */
+typedef struct hfe_foldkeys hfe_foldkeys;
+typedef struct hfe_fct hfe_fct;
+
+/* Keys for folds with factor k of blocks of at most rho ciphertexts (6 <= log_n <= 14, 1 <= k, rho
+ * <= N/2): the secret, relinearisation keys at levels 1 .. 3 and rotation keys (level 1) for the
+ * amounts 1 .. min(k, rho) - 1 and r k (1 <= r < ceil(rho / k)), drawn from `seed`.  Device memory:
+ * about (68 + 13 (keys of rotation)) N doubles. */
+hfe_status hfe_fold_keygen(uint32_t log_n, uint32_t k, uint32_t rho, uint64_t seed, hfe_foldkeys** out);
+
+/* Encryption of `count` vectors of N/2 inner products (device int32, [count][N/2], each in
+ * -2^24 .. 2^24) at scale 2^10 and level 4, draws from `seed`.  HFE_EINVAL for a value out of range
+ * (the call waits for that check). */
+hfe_status hfe_fold_encrypt(const hfe_foldkeys* fk, const int32_t* ip, int64_t count, uint64_t seed, void* stream,
+                            hfe_fct** out);
+
+/* The fold of the ciphertexts `in` (level 4, count a multiple of rho, rho at most the keys' rho) in
+ * blocks of rho, with the mask counts (device int32, [count][N/2], each in 1 .. 2^24; the call waits
+ * for that check): count / rho * ceil(rho / k) ciphertexts at level 0, block-major.  Workspace: about
+ * 14 count N uint64.  With hfe_profile(1) the result records its stage boundaries, read by
+ * hfe_fold_profile_ms (0: the normalisation plaintexts, 1: normalisation, 2: f, 3: rotations and sums). */
+hfe_status hfe_fold(const hfe_foldkeys* fk, const hfe_fct* in, const int32_t* counts, int64_t rho, void* stream,
+                    hfe_fct** out);
+hfe_status hfe_fold_profile_ms(const hfe_fct* ct, float* ms, int32_t n);
+
+/* Decryption and decoding of folded ciphertexts (level 0) into values (device doubles,
+ * [count][N/2]): the real parts of the slots divided by the scale. */
+hfe_status hfe_fold_decrypt(const hfe_foldkeys* fk, const hfe_fct* ct, double* values, void* stream);
+
 /* Shape queries of a handle (host): dims[0..3] = {level or L, d3 or d1, rows, K}. */
 hfe_status hfe_shape(const void* handle, int64_t* dims);
 

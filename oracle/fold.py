@@ -16,14 +16,17 @@ residues mod q_0 .. q_l, and b + a s = Delta m + e.
 
 Parameters (the paper fixes degree, depth, scale and key weight; the rest are readings):
   ring degree N = 2^log_n, N/2 real slots; slot j is the evaluation at zeta^(5^j mod 2N), zeta = e^(i pi / N)
-  q_0 a 36-bit prime (holds the folded sum), q_1 .. q_4 primes near 2^23 (Appendix C.2: Delta = 2^23),
-  p a 36-bit special prime for key switching; all = 1 mod 2^17
+  q_0 a 36-bit prime (holds the folded sum), q_1 .. q_3 primes near 2^23 (the three levels of f at
+  Delta = 2^23, Appendix C.2), q_4 a 36-bit prime (the normalisation's level), p a 36-bit special prime
+  for key switching; all = 1 mod 2^17
   secret s ternary of Hamming weight h = 32 (Appendix C.2)
-  input: the inner products IP (integers) at scale 2^10 at level 4; mu encoded at scale 2^36
-  normalise: x = RS_{q_4}(ct (.) Ecd(mu)) at level 3, scale S1 = 2^46 / q_4
+  input: the inner products IP (integers) at scale 2^20 at level 4; mu encoded at scale 2^40
+  normalise: x = RS_{q_4}(ct (.) Ecd(mu)) at level 3, scale S1 = 2^60 / q_4 (about 2^24)
   f = (c0 + c1 x) + x^2 (c2 + c3 x) + x^4 ((c4 + c5 x) + x^2 (c6 + c7 x)): three levels, five products
   with relinearisation; every constant is encoded at the scale that makes the terms it joins equal in
-  scale, so the result sits at level 0 with scale F = 2^24 exactly (up to the constants' rounding)
+  scale, so that f sits at level 1 with scale G = 2^24 q_1 (up to the constants' rounding); the last
+  rescale waits until the rotations and the sum of a group are done (rotations at level 1, where the
+  key-switching error is far below the scale), and brings the folded sum to level 0, scale F = 2^24
   Rot_{r k + r'} = Rot_{r k} o Rot_{r'}: the k - 1 rotations inside a group, then one by r k on the sum
   key switching: one digit per prime, d_i = [a (Q_l / q_i)^-1]_{q_i}, keys
   K_i = (k_i, -k_i s + p (Q_l / q_i) s_from + e_i) mod Q_l p, then RS_p (as for FormatSwitch)
@@ -40,7 +43,8 @@ Random streams (Philox, the layout of oracle.prng):
   FKE   sub 0: key errors at (coef t, kappa * 8 + i)
   FXA   sub = stream id: input ciphertext masks at (coef t, ciphertext index)
   FXE   sub 0: input errors at (coef t, ciphertext index)
-  key kappa: relinearisation at level l is l - 1 (l = 1, 2, 3); rotation by the a-th amount is 3 + a.
+  key kappa: relinearisation at level l is l - 1 (l = 1, 2, 3); rotation by the a-th amount (level 1) is
+  3 + a.
 """
 from __future__ import annotations
 
@@ -59,12 +63,13 @@ FSEC, FKA, FKE, FXA, FXE = 15, 16, 17, 18, 19
 H_WEIGHT = 32
 # f(x) = sum_j c_j x^j, the folding polynomial of Appendix C.2 (degree 7, k = 16)
 COEFFS = (0.004105, -0.173510, -2.528271, 24.347349, 124.161550, -412.746212, 376.961251, 106.553952)
-LOG_IN = 10          # scale of the input inner products
-LOG_MU = 36          # scale of the normalisation plaintext
+LOG_IN = 20          # scale of the input inner products
+LOG_MU = 40          # scale of the normalisation plaintext
 LOG_F = 24           # scale of the folded result
 W_BITS = 30          # mu_j is encoded from w_j = round(2^30 / count_j)
 C_BITS = 19          # cosine table precision
-LEVELS = 4           # q_1 .. q_4: normalise + three levels of f
+LEVELS = 4           # q_1 .. q_4: three levels of f + normalise
+ROT_LEVEL = 1        # level of the rotations and group sums
 
 
 @dataclasses.dataclass(frozen=True)
@@ -97,9 +102,9 @@ class FoldParams:
 
 
 def fold_params(log_n: int, k: int = 16) -> FoldParams:
-    big = ntt_primes(2)                       # 36-bit, = 1 mod 2^17
-    small = ntt_primes(LEVELS, 23, 17)        # the four largest below 2^23
-    return FoldParams(log_n, (big[0],) + tuple(small), big[1], k)
+    big = ntt_primes(3)                       # 36-bit, = 1 mod 2^17: q_0, p, q_4
+    small = ntt_primes(3, 23, 17)             # the three largest below 2^23: q_1 .. q_3
+    return FoldParams(log_n, (big[0],) + tuple(small) + (big[2],), big[1], k)
 
 
 # ---------------------------------------------------------------- encoding
@@ -243,7 +248,7 @@ def fold_keygen(P: FoldParams, seed: int, amounts: Sequence[int]) -> FoldKeys:
     relin = {lvl: _ks_key(P, seed, lvl - 1, lvl, s, s2) for lvl in (1, 2, 3)}
     rot = {}
     for a_idx, r in enumerate(amounts):
-        rot[r] = _ks_key(P, seed, 3 + a_idx, 0, s, automorphism(s, rot_galois(P, r)).astype(np.int64))
+        rot[r] = _ks_key(P, seed, 3 + a_idx, ROT_LEVEL, s, automorphism(s, rot_galois(P, r)).astype(np.int64))
     return FoldKeys(P, s, tuple(amounts), relin, rot)
 
 
@@ -254,7 +259,7 @@ Ct = Tuple[int, Dict[int, np.ndarray], Dict[int, np.ndarray]]
 
 
 def encrypt(FK: FoldKeys, ip: np.ndarray, seed: int, index: int) -> Ct:
-    """Input ciphertext `index`: the inner products ip (N/2 integers) at scale 2^10, level 4."""
+    """Input ciphertext `index`: the inner products ip (N/2 integers) at scale 2^20, level 4."""
     P = FK.P
     n = P.n
     t = np.arange(n, dtype=np.uint64)
@@ -353,8 +358,8 @@ def key_switch(P: FoldParams, level: int, x: Dict[int, np.ndarray], key) -> Tupl
     return rescale_by(B, P.p, primes), rescale_by(A, P.p, primes)
 
 
-def mul(FK: FoldKeys, ct1: Ct, ct2: Ct) -> Ct:
-    """Product with relinearisation, then RS by the level's last prime."""
+def mul(FK: FoldKeys, ct1: Ct, ct2: Ct, rescaled: bool = True) -> Ct:
+    """Product with relinearisation, then (by default) RS by the level's last prime."""
     P = FK.P
     l, b1, a1 = ct1
     l2, b2, a2 = ct2
@@ -366,20 +371,20 @@ def mul(FK: FoldKeys, ct1: Ct, ct2: Ct) -> Ct:
         d2[z] = negmul_mod(a1[z], a2[z], z)
     B, A = key_switch(P, l, d2, FK.relin[l])
     out = (l, {z: (d0[z] + B[z]) % z for z in d0}, {z: (d1[z] + A[z]) % z for z in d1})
-    return rescale(P, out)
+    return rescale(P, out) if rescaled else out
 
 
 def rotate(FK: FoldKeys, ct: Ct, r: int) -> Ct:
-    """Rot_r at level 0: (sigma(b) + B, A) with (B, A) = KS(sigma(a)) to s."""
+    """Rot_r at level 1: (sigma(b) + B, A) with (B, A) = KS(sigma(a)) to s."""
     P = FK.P
     l, b, a = ct
-    assert l == 0
+    assert l == ROT_LEVEL
     g = rot_galois(P, r)
-    q0 = P.q[0]
-    sb = automorphism(b[q0], g, q0)
-    sa = automorphism(a[q0], g, q0)
-    B, A = key_switch(P, 0, {q0: sa}, FK.rot[r])
-    return (0, {q0: (sb + B[q0]) % q0}, {q0: A[q0]})
+    primes = P.moduli(l)
+    sb = {z: automorphism(b[z], g, z) for z in primes}
+    sa = {z: automorphism(a[z], g, z) for z in primes}
+    B, A = key_switch(P, l, sa, FK.rot[r])
+    return (l, {z: (sb[z] + B[z]) % z for z in primes}, A)
 
 
 # ---------------------------------------------------------------- scales and the polynomial
@@ -397,6 +402,7 @@ class Schedule:
     U: float
     T3: float
     T1: float
+    G: float                  # scale of f at level 1: F q_1
     k: Tuple[int, ...]        # integer constants k_0 .. k_7
 
 
@@ -407,18 +413,19 @@ def schedule(P: FoldParams) -> Schedule:
     S1 = float(1 << (LOG_IN + LOG_MU)) / q4               # x = RS_{q_4}(ct * mu), level 3
     S2 = (S1 * S1) / q3                                    # x^2, level 2
     S4 = (S2 * S2) / q2                                    # x^4, level 1
-    F = float(1 << LOG_F)                                  # the result, level 0
-    U = (F * q1) / S4                                      # x^4 * inner at level 0 has scale F
+    F = float(1 << LOG_F)                                  # the folded result, level 0
+    G = F * q1                                             # f at level 1 (exact: 24 + 23 bits)
+    U = G / S4                                             # x^4 * inner at level 1 has scale G
     T3 = (U * q2) / S2                                     # x^2 * L3 at level 1 has scale U
-    T1 = (F * q2) / S2                                     # x^2 * L1 at level 1 has scale F
+    T1 = (G * q2) / S2                                     # x^2 * L1 at level 1 has scale G
     E7 = (T3 * q3) / S1                                    # c7 x at level 2 has scale T3
     E3 = (T1 * q3) / S1
     E5 = (U * q3) / S1
-    E1 = (F * q3) / S1
+    E1 = (G * q3) / S1
     c = COEFFS
-    k = (rnd(c[0] * F), rnd(c[1] * E1), rnd(c[2] * T1), rnd(c[3] * E3),
+    k = (rnd(c[0] * G), rnd(c[1] * E1), rnd(c[2] * T1), rnd(c[3] * E3),
          rnd(c[4] * U), rnd(c[5] * E5), rnd(c[6] * T3), rnd(c[7] * E7))
-    return Schedule(S1, S2, S4, F, U, T3, T1, k)
+    return Schedule(S1, S2, S4, F, U, T3, T1, G, k)
 
 
 def normalise(FK: FoldKeys, ct: Ct, counts: np.ndarray) -> Ct:
@@ -428,18 +435,18 @@ def normalise(FK: FoldKeys, ct: Ct, counts: np.ndarray) -> Ct:
 
 
 def poly_f(FK: FoldKeys, x: Ct) -> Ct:
-    """f(x) at level 0, scale F, for x at level 3, scale S1."""
+    """f(x) at level 1, scale G = F q_1, for x at level 3, scale S1."""
     P = FK.P
     k = schedule(P).k
     x2 = mul(FK, x, x)                                                    # level 2
     L3 = add_const(rescale(P, mul_const(x, k[7])), k[6])                  # level 2
     L1 = add_const(rescale(P, mul_const(x, k[3])), k[2])                  # level 2
     L2 = add_const(drop(P, rescale(P, mul_const(x, k[5])), 1), k[4])      # level 1
-    L0 = add_const(drop(P, rescale(P, mul_const(x, k[1])), 0), k[0])      # level 0
+    L0 = add_const(drop(P, rescale(P, mul_const(x, k[1])), 1), k[0])      # level 1
     x4 = mul(FK, x2, x2)                                                  # level 1
     inner = add(mul(FK, x2, L3), L2)                                      # level 1
-    t1 = drop(P, mul(FK, x2, L1), 0)                                      # level 0
-    t4 = mul(FK, x4, inner)                                               # level 0
+    t1 = mul(FK, x2, L1)                                                  # level 1
+    t4 = mul(FK, x4, inner, rescaled=False)                               # level 1, scale G
     return add(add(L0, t1), t4)
 
 
@@ -461,7 +468,7 @@ def fold(FK: FoldKeys, cts: List[Ct], counts: np.ndarray, rho: int) -> List[Ct]:
                 acc = y if acc is None else add(acc, y)
             if r:
                 acc = rotate(FK, acc, r * P.k)
-            out.append(acc)
+            out.append(rescale(P, acc))
     return out
 
 

@@ -44,7 +44,8 @@ EXPORTED = ("hfe_set_allocator", "hfe_default_params", "hfe_keygen", "hfe_encode
             "hfe_db_save", "hfe_db_load", "hfe_result_create", "hfe_server_submit_encrypted", "hfe_db_bytes",
             "hfe_ccmm_product", "hfe_probe_rate", "hfe_noalloc_init", "hfe_ccmm_noalloc",
             "hfe_plan_create_for", "hfe_chain_default_params", "hfe_chain_keygen", "hfe_fs_keygen",
-            "hfe_fs_transmit_count", "hfe_fs_encrypt", "hfe_format_switch", "hfe_fs_profile_ms")
+            "hfe_fs_transmit_count", "hfe_fs_encrypt", "hfe_format_switch", "hfe_fs_profile_ms",
+            "hfe_fold_keygen", "hfe_fold_encrypt", "hfe_fold", "hfe_fold_profile_ms", "hfe_fold_decrypt")
 
 
 class HfeError(RuntimeError):
@@ -154,6 +155,11 @@ _SIGS = {
     "hfe_fs_encrypt": [_vp, _vp, _i64, _u64, _vp, _vp],
     "hfe_format_switch": [_vp, _vp, _i64, _vp, ctypes.POINTER(_vp)],
     "hfe_fs_profile_ms": [_vp, _vp, _i32],
+    "hfe_fold_keygen": [_u32, _u32, _u32, _u64, ctypes.POINTER(_vp)],
+    "hfe_fold_encrypt": [_vp, _vp, _i64, _u64, _vp, ctypes.POINTER(_vp)],
+    "hfe_fold": [_vp, _vp, _vp, _i64, _vp, ctypes.POINTER(_vp)],
+    "hfe_fold_profile_ms": [_vp, _vp, _i32],
+    "hfe_fold_decrypt": [_vp, _vp, _vp, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -347,6 +353,48 @@ def hfe_fs_profile_ms(q: Handle, n: int = 4):
     ms = (ctypes.c_float * n)()
     _check(_lib.hfe_fs_profile_ms(q.ptr, ms, n), "hfe_fs_profile_ms")
     return [float(x) for x in ms]
+
+
+def hfe_fold_keygen(log_n: int, k: int, rho: int, seed: int) -> Handle:
+    """Keys of the fold (Algorithm 2): secret, relinearisation and rotation keys at ring degree 2^log_n."""
+    out = _vp()
+    _check(_lib.hfe_fold_keygen(log_n, k, rho, seed, ctypes.byref(out)), "hfe_fold_keygen")
+    return Handle(out.value)
+
+
+def hfe_fold_encrypt(fk: Handle, ip, seed: int, stream=None) -> Handle:
+    """Encryption of inner products ip (count x N/2 int32 GPU tensor) at level 4."""
+    torch = _torch()
+    out = _vp()
+    _check(_lib.hfe_fold_encrypt(fk.ptr, _dev_ptr(ip, torch.int32), ip.shape[0], seed, _stream(stream),
+                                 ctypes.byref(out)), "hfe_fold_encrypt")
+    return Handle(out.value, (fk,))
+
+
+def hfe_fold(fk: Handle, ct: Handle, counts, rho: int, stream=None) -> Handle:
+    """The fold of ct in blocks of rho with the mask counts (count x N/2 int32 GPU tensor)."""
+    torch = _torch()
+    out = _vp()
+    _check(_lib.hfe_fold(fk.ptr, ct.ptr, _dev_ptr(counts, torch.int32), rho, _stream(stream), ctypes.byref(out)),
+           "hfe_fold")
+    return Handle(out.value, (fk,))
+
+
+def hfe_fold_profile_ms(ct: Handle, n: int = 4):
+    ms = (ctypes.c_float * n)()
+    _check(_lib.hfe_fold_profile_ms(ct.ptr, ms, n), "hfe_fold_profile_ms")
+    return [float(x) for x in ms]
+
+
+def hfe_fold_decrypt(fk: Handle, ct: Handle, values=None, stream=None):
+    """Slot values of folded ciphertexts: a count x N/2 float64 GPU tensor."""
+    torch = _torch()
+    level, count, n, _ = hfe_shape(ct)
+    if values is None:
+        values = torch.empty((count, n // 2), dtype=torch.float64, device="cuda")
+    _check(_lib.hfe_fold_decrypt(fk.ptr, ct.ptr, _dev_ptr(values, torch.float64), _stream(stream)),
+           "hfe_fold_decrypt")
+    return values
 
 
 def hfe_encode(codes, masks, shifts: Sequence[int], out=None, stream=None):

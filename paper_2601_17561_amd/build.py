@@ -24,8 +24,8 @@ ARCH = "gfx950"
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", os.path.join(ROOT, "include")]
-HIP_SOURCES = ["k_ntt.hip", "k_ntt_big.hip", "k_misc.hip", "k_gemm.hip", "k_batch.hip", "k_rns.hip", "k_p2.hip", "k_chain.hip", "k_fswitch.hip", "k_probe.hip", "hfe_noalloc.hip", "hfe_api.cpp", "hfe_host.cpp", "hfe_server.cpp",
-               "hfe_store.cpp", "hfe_fswitch.cpp"]
+HIP_SOURCES = ["k_ntt.hip", "k_ntt_big.hip", "k_misc.hip", "k_gemm.hip", "k_batch.hip", "k_rns.hip", "k_p2.hip", "k_chain.hip", "k_fswitch.hip", "k_fold.hip", "k_probe.hip", "hfe_noalloc.hip", "hfe_api.cpp", "hfe_host.cpp", "hfe_server.cpp",
+               "hfe_store.cpp", "hfe_fswitch.cpp", "hfe_fold.cpp"]
 GXX_SOURCES = ["hfe_cdt.cpp"]
 
 

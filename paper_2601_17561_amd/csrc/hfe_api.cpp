@@ -2194,6 +2194,21 @@ hfe_status hfe_export(const void* handle, int32_t which, size_t offset, uint64_t
     const std::vector<int8_t>& src = which == 0 ? F->st_host : F->sr_host;
     total = src.size();
     host8 = src.data();
+  } else if (kind == kFoldKeys) {
+    const hfe_foldkeys* F = static_cast<const hfe_foldkeys*>(handle);
+    if (which != 0) return fail(HFE_EINVAL, "fold keys export: which must be 0");
+    total = F->s_host.size();
+    host8 = F->s_host.data();
+  } else if (kind == kFct) {
+    const hfe_fct* X = static_cast<const hfe_fct*>(handle);
+    if (which != 0) return fail(HFE_EINVAL, "fold ciphertext export: which must be 0");
+    total = (size_t)X->count * 2 * (X->level + 1) * ((size_t)1 << X->keys->C.logn);
+    if (count) *count = total;
+    if (!dst) return HFE_OK;
+    if (offset > total || n > total - offset) return fail(HFE_ESHAPE, "export range outside the array");
+    DevBuf tmp;
+    HFE_TRY(fold_export(X, tmp, X->stream));
+    return copy_out(tmp.as<uint64_t>() + offset, dst, n * sizeof(uint64_t));
   } else if (kind == kQct) {
     const hfe_qct* Q = static_cast<const hfe_qct*>(handle);
     if (which != 0) return fail(HFE_EINVAL, "qct export: which must be 0");
@@ -2238,6 +2253,18 @@ hfe_status hfe_shape(const void* handle, int64_t* dims) {
     dims[1] = F->C.logn_t;
     dims[2] = F->C.rho;
     dims[3] = F->C.k;
+  } else if (kind == kFoldKeys) {
+    const hfe_foldkeys* F = static_cast<const hfe_foldkeys*>(handle);
+    dims[0] = F->C.logn;
+    dims[1] = F->k;
+    dims[2] = F->rho;
+    dims[3] = (int64_t)F->amounts.size();
+  } else if (kind == kFct) {
+    const hfe_fct* X = static_cast<const hfe_fct*>(handle);
+    dims[0] = X->level;
+    dims[1] = X->count;
+    dims[2] = 1ll << X->keys->C.logn;
+    dims[3] = (int64_t)X->scale;
   } else if (kind == kQct) {
     const hfe_qct* Q = static_cast<const hfe_qct*>(handle);
     dims[0] = Q->level;
@@ -2287,6 +2314,14 @@ void hfe_free(void* handle) {
     case kFsKeys:
       b->kind = 0;
       delete static_cast<hfe_fskeys*>(handle);
+      break;
+    case kFoldKeys:
+      b->kind = 0;
+      delete static_cast<hfe_foldkeys*>(handle);
+      break;
+    case kFct:
+      b->kind = 0;
+      delete static_cast<hfe_fct*>(handle);
       break;
     default:
       break;

@@ -97,7 +97,7 @@ struct NttTabOwner {
 // ------------------------------------------------------------------ handles
 enum Kind : uint32_t {
   kKeys = 0x4b455953, kDb = 0x44422020, kQct = 0x51435420, kRct = 0x52435420, kPlan = 0x504c414e, kServer = 0x53525652,
-  kFsKeys = 0x46534b59
+  kFsKeys = 0x46534b59, kFoldKeys = 0x464c4b59, kFct = 0x46435420
 };
 
 struct HandleBase {
@@ -710,4 +710,111 @@ struct FsWork {
 };
 hipError_t launch_fs_switch(const FsConsts& C, const uint64_t* T, int64_t d3, const double* rk, const double* ck,
                             const FsWork& w, uint64_t* XT, int64_t K, hipStream_t s, hipEvent_t* ev);
+}  // namespace hfe
+
+// ------------------------------------------------------------------ normalise and fold (Algorithm 2)
+namespace hfe {
+// Stream purposes of the fold's draws: secret positions and signs, key masks and errors, input masks
+// and errors.
+enum : uint64_t { kFSec = 15, kFKA = 16, kFKE = 17, kFXA = 18, kFXE = 19 };
+constexpr int kFoldLevels = 4;   // q_1 .. q_4: the normalisation and three levels of f
+constexpr int kFoldSlots = 6;    // q_0 .. q_4, then p
+constexpr int kFoldH = 32;       // Hamming weight of the fold's secret (Appendix C.2)
+
+struct SlotMap {
+  int8_t z[kFoldSlots];          // slot position -> modulus index (0 .. 4: q_i, 5: p)
+};
+struct SlotFactor {
+  double v[kFoldSlots];          // one residue per slot position
+};
+struct KeyGadget {
+  double v[kFoldSlots][kFoldLevels];  // [slot position][digit]: p (Q_l / q_i) mod z
+};
+
+struct FoldConsts {
+  int logn;
+  double zd[kFoldSlots], zinv[kFoldSlots];
+  Mod mod[kFoldSlots];
+  uint32_t pid[kFoldSlots];      // random-stream ids (i, or 16 for p)
+  NttTab tab[kFoldSlots];
+};
+}  // namespace hfe
+
+struct hfe_foldkeys : hfe::HandleBase {
+  hfe::FoldConsts C;
+  int k;                                   // folding factor
+  int rho;                                 // ciphertexts per block the rotation keys cover
+  std::vector<int32_t> amounts;            // rotation amounts with keys
+  std::vector<int8_t> s_host;              // the secret (N ternary, weight 32)
+  hfe::NttTabOwner tabs[hfe::kFoldSlots];
+  hfe::DevBuf s_hat;                       // [slot][N] NTT residues of s
+  hfe::DevBuf relin;                       // levels 1 .. 3, each [s][i][2][N] doubles (see k_fold.hip)
+  int64_t relin_off[hfe::kFoldLevels] = {};  // offset (doubles) of the key of level l
+  hfe::DevBuf rot;                         // [amount][3 slots][2 digits][2][N] doubles (level 1)
+  hfe::DevBuf perm;                        // [amount][N] int32: NTT-point permutation of each rotation
+  hfe::DevBuf ctab;                        // [2N] int32 cosine table of the encoder
+  hfe::DevBuf cosd;                        // [2N] doubles: cos(pi t / N) for the decoder
+  hfe::DevBuf gpow;                        // [N/2] int32: 5^j mod 2N
+  hfe::DevBuf cdt;                         // the Gaussian table
+  uint64_t ksum[8] = {};                   // integer constants of f (k_0 .. k_7 as two's complement)
+  double sched[8] = {};                    // S1, S2, S4, F, U, T3, T1, G
+};
+
+struct hfe_fct : hfe::HandleBase {
+  const hfe_foldkeys* keys;
+  int level;
+  int64_t count;
+  double scale;
+  hfe::DevBuf ct;                          // [count][2][level + 1][N] NTT-domain residues
+  hipEvent_t ev[5] = {};                   // profiled fold: start, encode, normalise, f, rotations and sums
+  ~hfe_fct() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace hfe {
+hipError_t launch_fold_weights(const int32_t* values, int64_t total, int mode, int64_t* w, uint32_t* bad,
+                               hipStream_t s);
+hipError_t launch_fold_encode(const int64_t* w, int64_t items, int logn, int sh, const int32_t* ctab,
+                              const int32_t* gpow, int64_t* out, hipStream_t s);
+hipError_t launch_fold_fwd(const FoldConsts& C, const int64_t* src, int64_t si, int64_t ss, uint64_t* dst, int64_t di,
+                           int64_t ds, const SlotMap& zm, int nsl, int64_t items, hipStream_t s);
+hipError_t launch_fold_inv(const FoldConsts& C, const uint64_t* src, int64_t si, int64_t ss, void* dst, int64_t di,
+                           int64_t ds, const SlotMap& zm, int nsl, int mode, const SlotFactor& f, int64_t items,
+                           hipStream_t s);
+hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const uint64_t* dig, const double* keys, int64_t kstride,
+                              const int32_t* kidx, uint64_t* acc, int64_t* accp, int64_t items, hipStream_t s);
+hipError_t launch_fold_lift(const FoldConsts& C, const int64_t* cen, const uint64_t* x, int64_t xi, int64_t xp,
+                            const uint64_t* add, int64_t ai, int64_t ap, uint64_t* out, int64_t oi, int64_t op,
+                            const SlotMap& zm, int nsl, const SlotFactor& inv, int64_t items, hipStream_t s);
+hipError_t launch_fold_mul_pt(const FoldConsts& C, const uint64_t* ct, const uint64_t* pt, uint64_t* out,
+                              int64_t items, int nsl, hipStream_t s);
+hipError_t launch_fold_tensor(const FoldConsts& C, const uint64_t* x, const uint64_t* y, uint64_t* d, int64_t items,
+                              int nsl, hipStream_t s);
+hipError_t launch_fold_affine(const FoldConsts& C, const uint64_t* x, uint64_t* out, int64_t items, int nsl,
+                              const SlotFactor& kres, const SlotFactor& cres, hipStream_t s);
+hipError_t launch_fold_add(const FoldConsts& C, const uint64_t* x, int xs, const uint64_t* y, int ys, uint64_t* out,
+                           int64_t items, int nsl, hipStream_t s);
+hipError_t launch_fold_perm(const FoldConsts& C, const uint64_t* x, const int32_t* src, const int32_t* amt,
+                            const int32_t* perm, uint64_t* out, int64_t items, int nsl, hipStream_t s);
+hipError_t launch_fold_group_sum(const FoldConsts& C, const uint64_t* f, const uint64_t* rotated, const int32_t* beg,
+                                 const int32_t* mem, uint64_t* out, int64_t groups, int nsl, hipStream_t s);
+hipError_t launch_fold_scatter(const FoldConsts& C, const uint64_t* y, const int32_t* dst, uint64_t* x, int64_t items,
+                               int nsl, hipStream_t s);
+hipError_t launch_fold_key_coeffs(const FoldConsts& C, uint64_t seed, int kappa, int level, const SlotMap& zm,
+                                  const uint64_t* cdt, uint64_t* out, hipStream_t s);
+hipError_t launch_fold_key_finish(const FoldConsts& C, int level, const SlotMap& zm, const uint64_t* coef_hat,
+                                  const uint64_t* s_hat, const uint64_t* from_hat, const KeyGadget& gk, double* key,
+                                  hipStream_t s);
+hipError_t launch_fold_add_errors(const FoldConsts& C, uint64_t seed, const uint64_t* cdt, int64_t* m, int64_t items,
+                                  hipStream_t s);
+hipError_t launch_fold_encrypt(const FoldConsts& C, uint64_t seed, const uint64_t* s_hat, uint64_t* ct, int64_t items,
+                               hipStream_t s);
+hipError_t launch_fold_dec_products(const FoldConsts& C, const uint64_t* ct, const uint64_t* s_hat, uint64_t* out,
+                                    int64_t items, hipStream_t s);
+hipError_t launch_fold_decode(const int64_t* m, int64_t items, int logn, const double* cosd, const int32_t* gpow,
+                              double inv_scale, double* v, hipStream_t s);
+// Coefficient-form residues [count][2][level + 1][N] of a fold ciphertext array (hfe_export).
+hfe_status fold_export(const hfe_fct* X, DevBuf& out, hipStream_t s);
 }  // namespace hfe

@@ -1,0 +1,609 @@
+// Normalise and fold (Algorithm 2, Section 4.3, Appendix C.2): the kernels of a small CKKS evaluator at
+// ring degree N <= 2^14 over the slots q_0 .. q_4 and the special prime p (slot 5).
+//
+// Ciphertexts are kept in the NTT domain as uint64 residues, [item][part (b, a)][slot][N]; every
+// transform is one polynomial per workgroup in LDS (hfe_ntt_lds.h).  The operations a fold needs are
+// built from a few passes:
+//   k_fold_encode     the integer slot encoder (plaintext coefficients from integer slot values)
+//   k_fold_fwd        signed coefficients -> NTT-domain residues, for several slots
+//   k_fold_inv        NTT-domain residues -> coefficients (residues, centered, or digits of a key switch)
+//   k_fold_ks_mac     sum_i NTT(d_i) K_i for one slot: each digit's transform in LDS, the products
+//                     accumulated in registers; the special prime's sum is transformed back and centered
+//   k_fold_lift       (x - NTT([y]_div)) div^-1 (+ an addend) on every kept slot: RS_div and the end of a
+//                     key switch
+//   elementwise       plaintext and ciphertext products (tensor), constants, sums, the automorphism
+//                     of a rotation as a permutation of the NTT points, group sums, key and input draws
+#include "hfe_ntt_lds.h"
+
+namespace hfe {
+namespace {
+
+__device__ __forceinline__ double mm_d(double a, double b, int z, const FoldConsts& C) {
+  return mulmod_d(a, b, C.zd[z], C.zinv[z]);
+}
+
+// ------------------------------------------------------------------ encoder
+// Slot weights: w = v (mode 0, |v| <= 2^24) or round(2^30 / v) = floor((2^31 + v) / (2v)) (mode 1,
+// 1 <= v <= 2^24); a value outside its range sets *bad and is replaced by 0 (mode 0) or 1 (mode 1).
+__global__ void k_fold_weights(const int32_t* values, int64_t total, int mode, int64_t* w, uint32_t* bad) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t v = values[e];
+    if (mode) {
+      if (v < 1 || v > (1 << 24)) {
+        atomicOr(bad, 1u);
+        v = 1;
+      }
+      w[e] = ((int64_t(1) << 31) + v) / (2 * v);
+    } else {
+      if (v < -(1 << 24) || v > (1 << 24)) {
+        atomicOr(bad, 1u);
+        v = 0;
+      }
+      w[e] = v;
+    }
+  }
+}
+
+// m_i = floor((sum_j w_j Ctab[(i g_j) mod 2N] + 2^(sh-1)) / 2^sh) for the N coefficients of item c
+// (w[c][j], |w_j| <= 2^30).  One thread per coefficient; the item's weights and the powers g_j sit in
+// LDS.  Every product is below 2^49 and every sum below 2^62, so the integer result is exact and
+// independent of the order of the sum.
+__global__ void __launch_bounds__(256) k_fold_encode(const int64_t* wts, int logn, int sh, const int32_t* ctab,
+                                                     const int32_t* gpow, int64_t* out) {
+  extern __shared__ int64_t enc_lds[];
+  const int n = 1 << logn, half = n >> 1;
+  int64_t* w = enc_lds;
+  int32_t* g = reinterpret_cast<int32_t*>(enc_lds + half);
+  const int64_t c = blockIdx.y;
+  for (int j = threadIdx.x; j < half; j += blockDim.x) {
+    w[j] = wts[c * half + j];
+    g[j] = gpow[j];
+  }
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int mask = 2 * n - 1;
+  int64_t acc = 0;
+  for (int j = 0; j < half; ++j) acc += w[j] * (int64_t)ctab[(i * g[j]) & mask];
+  out[c * n + i] = (acc + (int64_t(1) << (sh - 1))) >> sh;
+}
+
+// ------------------------------------------------------------------ transforms
+// job = item * nsl + s: src[item * si + s * ss + t] (signed, |x| < 2^63) mod z_s -> forward NTT ->
+// dst[item * di + s * ds + t].
+__global__ void __launch_bounds__(kNttThreads) k_fold_fwd(FoldConsts C, const int64_t* src, int64_t si, int64_t ss,
+                                                        uint64_t* dst, int64_t di, int64_t ds, SlotMap zm, int nsl) {
+  extern __shared__ double lds[];
+  const int n = 1 << C.logn;
+  const int64_t item = blockIdx.x / nsl;
+  const int s = blockIdx.x - (int)(item * nsl);
+  const int z = zm.z[s];
+  const Mod md = C.mod[z];
+  const int64_t* x = src + item * si + s * ss;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(x[t], md.q, md.mu));
+  __syncthreads();
+  ntt_fwd_lds(lds, C.tab[z]);
+  uint64_t* y = dst + item * di + s * ds;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = to_u(lds[t]);
+}
+
+// job = item * nsl + s: inverse NTT of src[item * si + s * ss] mod z_s; mode 0: residues (uint64),
+// 1: centered (int64), 2: residues times factor[s] mod z_s (the digits of a key switch).
+__global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, const uint64_t* src, int64_t si, int64_t ss,
+                                                        void* dst, int64_t di, int64_t ds, SlotMap zm, int nsl,
+                                                        int mode, SlotFactor f) {
+  extern __shared__ double lds[];
+  const int n = 1 << C.logn;
+  const int64_t item = blockIdx.x / nsl;
+  const int s = blockIdx.x - (int)(item * nsl);
+  const int z = zm.z[s];
+  const uint64_t* x = src + item * si + s * ss;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(x[t]);
+  __syncthreads();
+  ntt_inv_lds(lds, C.tab[z]);
+  const int64_t off = item * di + s * ds;
+  if (mode == 1) {
+    int64_t* y = static_cast<int64_t*>(dst) + off;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = centered(to_u(lds[t]), C.mod[z].q);
+  } else {
+    uint64_t* y = static_cast<uint64_t*>(dst) + off;
+    const double fz = f.v[s];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = to_u(mode == 2 ? mm_d(lds[t], fz, z, C) : lds[t]);
+  }
+}
+
+// ------------------------------------------------------------------ key switching
+// job = item * (level + 2) + s, slot z = s (s <= level) or p (s = level + 1).  For each digit i <= level
+// (dig[item][i][N], residues mod q_i): reduce mod z, forward NTT in LDS, multiply by the key's two
+// parts for (z, i) and accumulate in registers (R coefficients per thread and part).  The key of the
+// item is keys + kidx[item] * kstride (kidx NULL: key 0), laid out [s][i][2][N] doubles.  Slots of Q_l
+// store the NTT-domain sums to acc[item][part][s][N]; the special prime's sums are transformed back,
+// centered and stored to accp[item][part][N].
+template <int R>
+__global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int level, const uint64_t* dig,
+                                                           const double* keys, int64_t kstride, const int32_t* kidx,
+                                                           uint64_t* acc, int64_t* accp) {
+  extern __shared__ double lds[];
+  const int n = 1 << C.logn;
+  const int nsl = level + 2;
+  const int64_t item = blockIdx.x / nsl;
+  const int s = blockIdx.x - (int)(item * nsl);
+  const bool special = s == level + 1;
+  const int z = special ? 5 : s;
+  const Mod md = C.mod[z];
+  const double* key = keys + (kidx ? (int64_t)kidx[item] : 0) * kstride + (int64_t)s * (level + 1) * 2 * n;
+  double ab[R], aa[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) ab[r] = aa[r] = 0.0;
+  for (int i = 0; i <= level; ++i) {
+    const uint64_t* d = dig + (item * (level + 1) + i) * n;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(barrett64(d[t], md.q, md.mu));
+    __syncthreads();
+    ntt_fwd_lds(lds, C.tab[z]);
+    const double* kb = key + (int64_t)i * 2 * n;   // part 0: mask k_i, part 1: beta_i
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int t = threadIdx.x + r * blockDim.x;
+      const double v = lds[t];
+      aa[r] = addmod_d(aa[r], mm_d(v, kb[t], z, C), C.zd[z]);
+      ab[r] = addmod_d(ab[r], mm_d(v, kb[n + t], z, C), C.zd[z]);
+    }
+    __syncthreads();
+  }
+  if (!special) {
+    uint64_t* ob = acc + ((item * 2 + 0) * (level + 1) + s) * n;
+    uint64_t* oa = acc + ((item * 2 + 1) * (level + 1) + s) * n;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int t = threadIdx.x + r * blockDim.x;
+      ob[t] = to_u(ab[r]);
+      oa[t] = to_u(aa[r]);
+    }
+    return;
+  }
+  for (int part = 0; part < 2; ++part) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[threadIdx.x + r * blockDim.x] = part ? aa[r] : ab[r];
+    __syncthreads();
+    ntt_inv_lds(lds, C.tab[z]);
+    int64_t* o = accp + (item * 2 + part) * n;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) o[t] = centered(to_u(lds[t]), md.q);
+    __syncthreads();
+  }
+}
+
+// job = (item * 2 + part) * nsl + s, slot z = zm.z[s]:
+// out = (x - NTT_z(cen mod z)) inv[s] (+ add) mod z, with cen = cen[(item * 2 + part) * N + t].
+__global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, const int64_t* cen, const uint64_t* x,
+                                                         int64_t xi, int64_t xp, const uint64_t* add, int64_t ai,
+                                                         int64_t ap, uint64_t* out, int64_t oi, int64_t op,
+                                                         SlotMap zm, int nsl, SlotFactor inv) {
+  extern __shared__ double lds[];
+  const int n = 1 << C.logn;
+  const int64_t ip = blockIdx.x / nsl;
+  const int s = blockIdx.x - (int)(ip * nsl);
+  const int64_t item = ip >> 1;
+  const int part = (int)(ip & 1);
+  const int z = zm.z[s];
+  const Mod md = C.mod[z];
+  const int64_t* c = cen + ip * n;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(c[t], md.q, md.mu));
+  __syncthreads();
+  ntt_fwd_lds(lds, C.tab[z]);
+  const uint64_t* xx = x + item * xi + part * xp + (int64_t)s * n;
+  // ap = 0: the addend belongs to part 0 only (a rotation adds sigma(b) to B)
+  const uint64_t* aa = (add && (part == 0 || ap != 0)) ? add + item * ai + part * ap + (int64_t)s * n : nullptr;
+  uint64_t* o = out + item * oi + part * op + (int64_t)s * n;
+  const double zd = C.zd[z], w = inv.v[s];
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    double v = mm_d(submod_d(to_d(xx[t]), lds[t], zd), w, z, C);
+    if (aa) v = addmod_d(v, to_d(aa[t]), zd);
+    o[t] = to_u(v);
+  }
+}
+
+// ------------------------------------------------------------------ elementwise
+// Plaintext product: out[item][part][s] = ct[item][part][s] pt[item][s] (nsl slots q_0 .. q_{nsl-1}).
+__global__ void k_fold_mul_pt(FoldConsts C, const uint64_t* ct, const uint64_t* pt, uint64_t* out, int64_t items,
+                              int nsl) {
+  const int n = 1 << C.logn;
+  const int64_t total = items * 2 * nsl * (int64_t)n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e & (n - 1));
+    const int64_t r = e >> C.logn;
+    const int s = (int)(r % nsl);
+    const int64_t item = r / (2 * nsl);
+    out[e] = to_u(mm_d(to_d(ct[e]), to_d(pt[(item * nsl + s) * n + t]), s, C));
+  }
+}
+
+// Tensor of x and y at nsl slots: d[item][0 | 1 | 2][s] = b_x b_y, a_x b_y + a_y b_x, a_x a_y.
+__global__ void k_fold_tensor(FoldConsts C, const uint64_t* x, const uint64_t* y, uint64_t* d, int64_t items, int nsl) {
+  const int n = 1 << C.logn;
+  const int64_t per = (int64_t)nsl * n;
+  const int64_t total = items * per;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t item = e / per, w = e - item * per;
+    const int s = (int)(w >> C.logn);
+    const double zd = C.zd[s];
+    const double bx = to_d(x[item * 2 * per + w]), ax = to_d(x[item * 2 * per + per + w]);
+    const double by = to_d(y[item * 2 * per + w]), ay = to_d(y[item * 2 * per + per + w]);
+    uint64_t* o = d + item * 3 * per + w;
+    o[0] = to_u(mm_d(bx, by, s, C));
+    o[per] = to_u(addmod_d(mm_d(ax, by, s, C), mm_d(ay, bx, s, C), zd));
+    o[2 * per] = to_u(mm_d(ax, ay, s, C));
+  }
+}
+
+// out = x k (both parts; kres[s] = k mod q_s), then b += c (cres[s] = c mod q_s; the constant
+// polynomial c is c at every NTT point), at nsl slots.  Either step may be the identity (k = 1, c = 0).
+__global__ void k_fold_affine(FoldConsts C, const uint64_t* x, uint64_t* out, int64_t items, int nsl, SlotFactor kres,
+                              SlotFactor cres) {
+  const int n = 1 << C.logn;
+  const int64_t total = items * 2 * nsl * (int64_t)n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e >> C.logn;
+    const int s = (int)(r % nsl);
+    const bool b = ((r / nsl) & 1) == 0;
+    double v = mm_d(to_d(x[e]), kres.v[s], s, C);
+    if (b) v = addmod_d(v, cres.v[s], C.zd[s]);
+    out[e] = to_u(v);
+  }
+}
+
+// out = x + y at nsl slots; x and y may carry more slots than out (xs, ys: their slot counts), so that
+// dropping primes and adding is one pass.
+__global__ void k_fold_add(FoldConsts C, const uint64_t* x, int xs, const uint64_t* y, int ys, uint64_t* out,
+                           int64_t items, int nsl) {
+  const int n = 1 << C.logn;
+  const int64_t total = items * 2 * nsl * (int64_t)n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e & (n - 1));
+    const int64_t r = e >> C.logn;
+    const int s = (int)(r % nsl);
+    const int64_t ip = r / nsl;  // item * 2 + part
+    double v = to_d(x[(ip * xs + s) * n + t]);
+    if (y) v = addmod_d(v, to_d(y[(ip * ys + s) * n + t]), C.zd[s]);
+    out[e] = to_u(v);
+  }
+}
+
+// Rotation's automorphism on gathered items with nsl slots: out[u][part][s][t] =
+// x[src[u]][part][s][perm[amt[u]][t]] (the NTT points of every prime are ordered alike).
+__global__ void k_fold_perm(FoldConsts C, const uint64_t* x, const int32_t* src, const int32_t* amt,
+                            const int32_t* perm, uint64_t* out, int64_t items, int nsl) {
+  const int n = 1 << C.logn;
+  const int64_t per = 2 * (int64_t)nsl * n;
+  const int64_t total = items * per;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e & (n - 1));
+    const int64_t u = e / per, w = e - u * per;
+    out[e] = x[(int64_t)src[u] * per + (w - t) + perm[(int64_t)amt[u] * n + t]];
+  }
+}
+
+// Group sums of items with nsl slots: out[g] = sum over the members of group g; members are listed in
+// mem[beg[g] .. beg[g+1]) as idx * 2 + (rotated ? 1 : 0), rotated[idx] or f[idx].
+__global__ void k_fold_group_sum(FoldConsts C, const uint64_t* f, const uint64_t* rotated, const int32_t* beg,
+                                 const int32_t* mem, uint64_t* out, int64_t groups, int nsl) {
+  const int n = 1 << C.logn;
+  const int64_t per = 2 * (int64_t)nsl * n;
+  const int64_t total = groups * per;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = e / per, w = e - g * per;
+    const double zd = C.zd[(int)((w >> C.logn) % nsl)];
+    double v = 0.0;
+    for (int m = beg[g]; m < beg[g + 1]; ++m) {
+      const int32_t code = mem[m];
+      const uint64_t* b = (code & 1) ? rotated : f;
+      v = addmod_d(v, to_d(b[(int64_t)(code >> 1) * per + w]), zd);
+    }
+    out[e] = to_u(v);
+  }
+}
+
+// Scatter rotated items back: x[dst[u]] = y[u] (items with nsl slots).
+__global__ void k_fold_scatter(FoldConsts C, const uint64_t* y, const int32_t* dst, uint64_t* x, int64_t items,
+                               int nsl) {
+  const int n = 1 << C.logn;
+  const int64_t per = 2 * (int64_t)nsl * n;
+  const int64_t total = items * per;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = e / per, w = e - u * per;
+    x[(int64_t)dst[u] * per + w] = y[e];
+  }
+}
+
+// ------------------------------------------------------------------ draws
+// Key coefficients: for key kappa (column kappa * 8 + i), slot s of the key's slot list zm and digit
+// i <= level: out[s][i][0][t] = uniform mod z (stream FKA, sub = stream id of z), out[s][i][1][t] =
+// the Gaussian error (stream FKE, sub 0) as a residue mod z.
+__global__ void k_fold_key_coeffs(FoldConsts C, uint64_t seed, int kappa, int level, SlotMap zm, const uint64_t* cdt,
+                                  uint64_t* out) {
+  const int n = 1 << C.logn;
+  const int nsl = level + 2;
+  const int64_t total = (int64_t)nsl * (level + 1) * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e & (n - 1));
+    const int64_t r = e >> C.logn;
+    const int i = (int)(r % (level + 1));
+    const int s = (int)(r / (level + 1));
+    const int z = zm.z[s];
+    const Mod md = C.mod[z];
+    const uint64_t col = (uint64_t)kappa * 8 + (uint64_t)i;
+    const uint64_t u = uniform_at(seed, stream_tag(kFKA, C.pid[z]), (uint64_t)t, col, md);
+    const int32_t g = gaussian_at(seed, stream_tag(kFKE, 0), (uint64_t)t, col, cdt);
+    out[(r * 2 + 0) * n + t] = u;
+    out[(r * 2 + 1) * n + t] = from_signed(g, md.q, md.mu);
+  }
+}
+
+// Key finish, NTT domain: beta = -k s + g_{s,i} s_from + e, stored as doubles [s][i][2][N]
+// (part 0: k, part 1: beta).  s_hat, from_hat: [slot z][N] NTT residues; gk[s][i] = p (Q_l / q_i) mod z.
+__global__ void k_fold_key_finish(FoldConsts C, int level, SlotMap zm, const uint64_t* coef_hat, const uint64_t* s_hat,
+                                  const uint64_t* from_hat, KeyGadget gk, double* key) {
+  const int n = 1 << C.logn;
+  const int64_t total = (int64_t)(level + 2) * (level + 1) * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(e & (n - 1));
+    const int64_t r = e >> C.logn;
+    const int i = (int)(r % (level + 1));
+    const int s = (int)(r / (level + 1));
+    const int z = zm.z[s];
+    const double zd = C.zd[z];
+    const double k = to_d(coef_hat[(r * 2 + 0) * n + t]);
+    const double err = to_d(coef_hat[(r * 2 + 1) * n + t]);
+    double beta = submod_d(err, mm_d(k, to_d(s_hat[(int64_t)z * n + t]), z, C), zd);
+    beta = addmod_d(beta, mm_d(gk.v[s][i], to_d(from_hat[(int64_t)z * n + t]), z, C), zd);
+    key[(r * 2 + 0) * n + t] = k;
+    key[(r * 2 + 1) * n + t] = beta;
+  }
+}
+
+// Input errors: m[c][t] += the Gaussian at (t, c) of stream FXE.
+__global__ void k_fold_add_errors(FoldConsts C, uint64_t seed, const uint64_t* cdt, int64_t* m, int64_t items) {
+  const int n = 1 << C.logn;
+  const int64_t total = items * (int64_t)n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e >> C.logn;
+    const int t = (int)(e & (n - 1));
+    m[e] += gaussian_at(seed, stream_tag(kFXE, 0), (uint64_t)t, (uint64_t)c, cdt);
+  }
+}
+
+// Input masks and bodies, job = c * 5 + z: a (stream FXA, sub = stream id of q_z, element (t, c)) ->
+// NTT -> ct[c][1][z]; ct[c][0][z] = (m + e)_hat - a_hat s_hat (the encoded inner products with their
+// errors are already in ct[c][0][z]).
+__global__ void __launch_bounds__(kNttThreads) k_fold_encrypt(FoldConsts C, uint64_t seed, const uint64_t* s_hat,
+                                                            uint64_t* ct) {
+  extern __shared__ double lds[];
+  const int n = 1 << C.logn;
+  const int64_t c = blockIdx.x / 5;
+  const int z = (int)(blockIdx.x - c * 5);
+  const Mod md = C.mod[z];
+  for (int t = threadIdx.x; t < n; t += blockDim.x)
+    lds[t] = to_d(uniform_at(seed, stream_tag(kFXA, C.pid[z]), (uint64_t)t, (uint64_t)c, md));
+  __syncthreads();
+  ntt_fwd_lds(lds, C.tab[z]);
+  uint64_t* b = ct + ((c * 2 + 0) * 5 + z) * n;
+  uint64_t* a = ct + ((c * 2 + 1) * 5 + z) * n;
+  const double zd = C.zd[z];
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const double av = lds[t];
+    a[t] = to_u(av);
+    b[t] = to_u(submod_d(to_d(b[t]), mm_d(av, to_d(s_hat[(int64_t)z * n + t]), z, C), zd));
+  }
+}
+
+// Decryption at level 0 in the NTT domain: out[c][t] = b + a s mod q_0 (then an inverse transform).
+__global__ void k_fold_dec_products(FoldConsts C, const uint64_t* ct, const uint64_t* s_hat, uint64_t* out,
+                                    int64_t items) {
+  const int n = 1 << C.logn;
+  const int64_t total = items * (int64_t)n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e >> C.logn;
+    const int t = (int)(e & (n - 1));
+    const double b = to_d(ct[(c * 2 + 0) * n + t]), a = to_d(ct[(c * 2 + 1) * n + t]);
+    out[e] = to_u(addmod_d(b, mm_d(a, to_d(s_hat[t]), 0, C), C.zd[0]));
+  }
+}
+
+// Decoding (floating point): v[c][j] = sum_i m_i cos(pi i g_j / N) / scale, one thread per slot.
+__global__ void __launch_bounds__(256) k_fold_decode(const int64_t* m, int logn, const double* cosd,
+                                                     const int32_t* gpow, double inv_scale, double* v) {
+  extern __shared__ double dec_lds[];
+  const int n = 1 << logn, half = n >> 1;
+  const int64_t c = blockIdx.y;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dec_lds[i] = (double)m[c * n + i];
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= half) return;
+  const int g = gpow[j], mask = 2 * n - 1;
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += dec_lds[i] * cosd[(i * g) & mask];
+  v[c * half + j] = acc * inv_scale;
+}
+
+unsigned ew_grid(int64_t total) {
+  int64_t g = (total + 255) / 256;
+  return (unsigned)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_fold_weights(const int32_t* values, int64_t total, int mode, int64_t* w, uint32_t* bad,
+                               hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_weights, dim3(ew_grid(total)), dim3(256), 0, s, values, total, mode, w, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_encode(const int64_t* w, int64_t items, int logn, int sh, const int32_t* ctab,
+                              const int32_t* gpow, int64_t* out, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const int n = 1 << logn;
+  const size_t lds = (size_t)(n / 2) * (sizeof(int64_t) + sizeof(int32_t));
+  hipError_t e = allow_lds(k_fold_encode, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fold_encode, dim3((unsigned)((n + 255) / 256), (unsigned)items), dim3(256), lds, s, w, logn,
+                     sh, ctab, gpow, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_fwd(const FoldConsts& C, const int64_t* src, int64_t si, int64_t ss, uint64_t* dst, int64_t di,
+                           int64_t ds, const SlotMap& zm, int nsl, int64_t items, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) << C.logn;
+  hipError_t e = allow_lds(k_fold_fwd, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fold_fwd, dim3((unsigned)(items * nsl)), dim3(ntt_block(C.logn)), lds, s, C, src, si, ss, dst,
+                     di, ds, zm, nsl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_inv(const FoldConsts& C, const uint64_t* src, int64_t si, int64_t ss, void* dst, int64_t di,
+                           int64_t ds, const SlotMap& zm, int nsl, int mode, const SlotFactor& f, int64_t items,
+                           hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) << C.logn;
+  hipError_t e = allow_lds(k_fold_inv, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fold_inv, dim3((unsigned)(items * nsl)), dim3(ntt_block(C.logn)), lds, s, C, src, si, ss, dst,
+                     di, ds, zm, nsl, mode, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const uint64_t* dig, const double* keys, int64_t kstride,
+                              const int32_t* kidx, uint64_t* acc, int64_t* accp, int64_t items, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) << C.logn;
+  return by_regs(regs_per_thread(C.logn), [&](auto rc) -> hipError_t {
+    constexpr int R = decltype(rc)::value;
+    hipError_t e = allow_lds(k_fold_ks_mac<R>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fold_ks_mac<R>, dim3((unsigned)(items * (level + 2))), dim3(ntt_block(C.logn)), lds, s, C,
+                       level, dig, keys, kstride, kidx, acc, accp);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_fold_lift(const FoldConsts& C, const int64_t* cen, const uint64_t* x, int64_t xi, int64_t xp,
+                            const uint64_t* add, int64_t ai, int64_t ap, uint64_t* out, int64_t oi, int64_t op,
+                            const SlotMap& zm, int nsl, const SlotFactor& inv, int64_t items, hipStream_t s) {
+  if (items <= 0 || nsl <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) << C.logn;
+  hipError_t e = allow_lds(k_fold_lift, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fold_lift, dim3((unsigned)(items * 2 * nsl)), dim3(ntt_block(C.logn)), lds, s, C, cen, x, xi,
+                     xp, add, ai, ap, out, oi, op, zm, nsl, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_mul_pt(const FoldConsts& C, const uint64_t* ct, const uint64_t* pt, uint64_t* out,
+                              int64_t items, int nsl, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_mul_pt, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, ct, pt, out, items,
+                     nsl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_tensor(const FoldConsts& C, const uint64_t* x, const uint64_t* y, uint64_t* d, int64_t items,
+                              int nsl, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_tensor, dim3(ew_grid(items * nsl << C.logn)), dim3(256), 0, s, C, x, y, d, items, nsl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_affine(const FoldConsts& C, const uint64_t* x, uint64_t* out, int64_t items, int nsl,
+                              const SlotFactor& kres, const SlotFactor& cres, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_affine, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, x, out, items, nsl,
+                     kres, cres);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_add(const FoldConsts& C, const uint64_t* x, int xs, const uint64_t* y, int ys, uint64_t* out,
+                           int64_t items, int nsl, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_add, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, x, xs, y, ys, out,
+                     items, nsl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_perm(const FoldConsts& C, const uint64_t* x, const int32_t* src, const int32_t* amt,
+                            const int32_t* perm, uint64_t* out, int64_t items, int nsl, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_perm, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, x, src, amt, perm,
+                     out, items, nsl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_group_sum(const FoldConsts& C, const uint64_t* f, const uint64_t* rotated, const int32_t* beg,
+                                 const int32_t* mem, uint64_t* out, int64_t groups, int nsl, hipStream_t s) {
+  if (groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_group_sum, dim3(ew_grid(groups * 2 * nsl << C.logn)), dim3(256), 0, s, C, f, rotated, beg,
+                     mem, out, groups, nsl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_scatter(const FoldConsts& C, const uint64_t* y, const int32_t* dst, uint64_t* x, int64_t items,
+                               int nsl, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_scatter, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, y, dst, x, items,
+                     nsl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_key_coeffs(const FoldConsts& C, uint64_t seed, int kappa, int level, const SlotMap& zm,
+                                  const uint64_t* cdt, uint64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_key_coeffs, dim3(ew_grid((int64_t)(level + 2) * (level + 1) << C.logn)), dim3(256), 0, s,
+                     C, seed, kappa, level, zm, cdt, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_key_finish(const FoldConsts& C, int level, const SlotMap& zm, const uint64_t* coef_hat,
+                                  const uint64_t* s_hat, const uint64_t* from_hat, const KeyGadget& gk, double* key,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_key_finish, dim3(ew_grid((int64_t)(level + 2) * (level + 1) << C.logn)), dim3(256), 0, s,
+                     C, level, zm, coef_hat, s_hat, from_hat, gk, key);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_add_errors(const FoldConsts& C, uint64_t seed, const uint64_t* cdt, int64_t* m, int64_t items,
+                                  hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_add_errors, dim3(ew_grid(items << C.logn)), dim3(256), 0, s, C, seed, cdt, m, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_encrypt(const FoldConsts& C, uint64_t seed, const uint64_t* s_hat, uint64_t* ct, int64_t items,
+                               hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) << C.logn;
+  hipError_t e = allow_lds(k_fold_encrypt, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fold_encrypt, dim3((unsigned)(items * 5)), dim3(ntt_block(C.logn)), lds, s, C, seed, s_hat, ct);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_dec_products(const FoldConsts& C, const uint64_t* ct, const uint64_t* s_hat, uint64_t* out,
+                                    int64_t items, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fold_dec_products, dim3(ew_grid(items << C.logn)), dim3(256), 0, s, C, ct, s_hat, out, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_decode(const int64_t* m, int64_t items, int logn, const double* cosd, const int32_t* gpow,
+                              double inv_scale, double* v, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const int n = 1 << logn;
+  const size_t lds = (size_t)n * sizeof(double);
+  hipError_t e = allow_lds(k_fold_decode, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fold_decode, dim3((unsigned)((n / 2 + 255) / 256), (unsigned)items), dim3(256), lds, s, m, logn,
+                     cosd, gpow, inv_scale, v);
+  return hipGetLastError();
+}
+
+}  // namespace hfe

@@ -143,3 +143,40 @@ def fs_case(name: str) -> FsCase:
     XT = np.stack([XTd[i] for i in range(w.level)])
     ip_true, _ = OI.truth(qc, qm, inp["db_codes"], inp["db_masks"])
     return FsCase(w, log_n_t, P, F, inp, qc, qm, m_q, T, XT, ip_true)
+
+
+FOLD_SEED = 707    # stream seed of the fold's input encryptions
+
+
+@dataclasses.dataclass
+class FoldCase:
+    w: S.FoldWorkload
+    P: object
+    keys: object
+    ip: np.ndarray
+    counts: np.ndarray
+    cts: list
+    out: list
+
+
+def fold_layout(P, cts) -> np.ndarray:
+    """Oracle ciphertexts -> the library's export layout [count][b | a][q_0 .. q_level][N]."""
+    lvl = cts[0][0]
+    arr = np.zeros((len(cts), 2, lvl + 1, P.n), dtype=np.int64)
+    for c, (l, b, a) in enumerate(cts):
+        for z in range(lvl + 1):
+            arr[c, 0, z] = b[P.q[z]]
+            arr[c, 1, z] = a[P.q[z]]
+    return arr
+
+
+@functools.lru_cache(maxsize=None)
+def fold_case(name: str) -> FoldCase:
+    from oracle import fold as OF
+    w = S.FOLD_WORKLOADS[name]
+    P = OF.fold_params(w.log_n, w.k)
+    keys = OF.fold_keygen(P, KEY_SEED, OF.rot_amounts(w.k, w.rho))
+    ip, counts = S.fold_inputs(w)
+    cts = [OF.encrypt(keys, ip[c], FOLD_SEED, c) for c in range(w.count)]
+    out = OF.fold(keys, cts, counts, w.rho)
+    return FoldCase(w, P, keys, ip, counts, cts, out)

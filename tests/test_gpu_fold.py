@@ -1,0 +1,158 @@
+"""GPU parity of normalise and fold (Algorithm 2, Section 4.3, Appendix C.2) against the oracle.
+
+For each workload the library's keys, input encryption and fold are compared with oracle/fold.py
+bit-exactly: the secret, every coefficient residue of the input ciphertexts (level 4) and of the folded
+ciphertexts (level 0).  The folded ciphertexts then decrypt (on the GPU) to the plain folded values
+sum_r' Rot_{r k + r'}(f(IP / count)) within the homomorphic error.
+Workloads: N = 2^7 with k = 4 and blocks of 6 (a full and a partial group, two blocks, a last block of
+empty database slots), N = 2^10 with k = 16 and blocks of 20, and N = 2^14 with the paper's k = 16,
+checked against the oracle's hashes of every residue (tests/golden/fold_paper.json, written by
+tests/golden/make_fold_paper.py from the oracle alone).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import hfe_synth as S
+
+from oracle_cases import FOLD_SEED, KEY_SEED, fold_case, fold_layout
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+H = pytest.importorskip("paper_2601_17561_amd")
+
+F_PRIME = 75.0     # max |f'| over the scores' domain [-0.233, 0.6] (numpy.polyder of Appendix C.2's f: 73.7)
+
+
+def _tol(w, counts):
+    """Bound on |decrypted fold - plain fold|: the input's encryption error (Gaussian of 3.2 per
+    coefficient, sqrt(N/2) per slot, at scale 2^20, six deviations) divided by the smallest mask count
+    and carried through f, plus 0.02, the allowance Appendix C.2 makes for the homomorphic evaluation
+    (N_f widened by 0.02 on each side)."""
+    sigma = 3.2 * np.sqrt((1 << w.log_n) / 2) / 2 ** 20
+    return 0.02 + 6 * sigma * F_PRIME / float(counts.min())
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(w):
+    fk = H.hfe_fold_keygen(w.log_n, w.k, w.rho, KEY_SEED)
+    ip, counts = S.fold_inputs(w)
+    ct = H.hfe_fold_encrypt(fk, torch.from_numpy(ip).cuda(), FOLD_SEED)
+    out = H.hfe_fold(fk, ct, torch.from_numpy(counts).cuda(), w.rho)
+    vals = H.hfe_fold_decrypt(fk, out).cpu().numpy()
+    return fk, ct, out, vals, ip, counts
+
+
+def _exported(h, level, count, n):
+    return H.hfe_export(h, 0).view(np.int64).reshape(count, 2, level + 1, n)
+
+
+def _plain(w, ip, counts):
+    from oracle import fold as OF
+    return OF.fold_plain(ip.astype(np.int64), counts.astype(np.int64), w.rho, w.k)
+
+
+@pytest.mark.parametrize("wname", [S.FOLD_TINY.name, S.FOLD_MID.name])
+def test_fold_bit_exact(wname):
+    w = S.FOLD_WORKLOADS[wname]
+    _say(f"[gpu-fold] {wname}: oracle (CPU)")
+    c = fold_case(wname)
+    _say(f"[gpu-fold] {wname}: library")
+    fk, ct, out, vals, ip, counts = _run(w)
+    n = 1 << w.log_n
+    groups = w.blocks * -(-w.rho // w.k)
+    assert list(H.hfe_shape(fk))[:3] == [w.log_n, w.k, w.rho]
+    assert np.array_equal(H.hfe_export(fk, 0).view(np.int64), c.keys.s)
+    got = _exported(ct, 4, w.count, n)
+    want = fold_layout(c.P, c.cts)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"input ciphertexts: {len(bad)} residues differ, first {bad[:3].tolist()}"
+    assert list(H.hfe_shape(out))[:3] == [0, groups, n]
+    got = _exported(out, 0, groups, n)
+    want = fold_layout(c.P, c.out)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"folded ciphertexts: {len(bad)} residues differ, first {bad[:3].tolist()}"
+    from oracle import fold as OF
+    sched = OF.schedule(c.P)
+    dec = np.array([OF.decode(OF.decrypt(c.keys, o), w.log_n, sched.F) for o in c.out])
+    assert float(np.max(np.abs(vals - dec))) < 1e-9, "GPU decryption differs from the oracle's decoding"
+    err = float(np.max(np.abs(vals - _plain(w, ip, counts))))
+    assert err < _tol(w, counts), f"decrypted fold off the plain values by {err}"
+
+
+def _digest(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a.view(np.int64), dtype="<i8").tobytes()).hexdigest()
+
+
+def _assert_matches(name, got: np.ndarray, g, what):
+    assert list(got.shape) == g["shapes"][name], f"{what}: shape {got.shape}, oracle {g['shapes'][name]}"
+    if _digest(got) == g["sha256"][name]:
+        return
+    msg = f"{what}: residues differ from the oracle"
+    if name in g["samples"]:
+        sm = g["samples"][name]
+        flat = got.view(np.int64).reshape(-1)
+        bad = [(i, int(flat[i]), v) for i, v in zip(sm["index"], sm["value"]) if int(flat[i]) != v]
+        msg += f"; {len(bad)} of {len(sm['index'])} sampled entries differ, first {bad[:3]}"
+    raise AssertionError(msg)
+
+
+def test_fold_paper_degree_matches_the_oracle():
+    w = S.FOLD_PAPER
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fold_paper.json")))[w.name]
+    _say(f"[gpu-fold] {w.name}: library")
+    fk, ct, out, vals, ip, counts = _run(w)
+    n = 1 << w.log_n
+    _assert_matches("s", H.hfe_export(fk, 0).view(np.int64), g, "secret")
+    _assert_matches("ct", _exported(ct, 4, w.count, n), g, "input ciphertexts")
+    _assert_matches("out", _exported(out, 0, 1, n), g, "folded ciphertexts")
+    err = float(np.max(np.abs(vals - _plain(w, ip, counts))))
+    assert err < _tol(w, counts), f"decrypted fold off the plain values by {err}"
+
+
+def test_fold_profile_and_refusals():
+    w = S.FOLD_TINY
+    fk, ct, out, vals, ip, counts = _run(w)
+    cnt = torch.from_numpy(counts).cuda()
+    H.hfe_profile(1)
+    try:
+        o2 = H.hfe_fold(fk, ct, cnt, w.rho)
+        ms = H.hfe_fold_profile_ms(o2, 4)
+    finally:
+        H.hfe_profile(0)
+    assert all(x >= 0.0 for x in ms)
+    assert np.array_equal(H.hfe_export(o2, 0), H.hfe_export(out, 0))
+    with pytest.raises(H.HfeError):
+        H.hfe_fold_profile_ms(out, 4)                                 # made without profiling
+    bad = cnt.clone()
+    bad[1, 3] = 0
+    with pytest.raises(H.HfeError):
+        H.hfe_fold(fk, ct, bad, w.rho)                                # a zero mask count
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_fold(fk, ct, cnt, w.rho + 1)                            # rho beyond the keys
+    assert e.value.status == -2
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_fold(fk, ct, cnt, 5)                                    # 12 ciphertexts: not a multiple of 5
+    assert e.value.status == -2
+    with pytest.raises(H.HfeError) as e:
+        H.hfe_fold(fk, out, cnt, w.rho)                               # a folded ciphertext again
+    assert e.value.status == -3
+    with pytest.raises(H.HfeError):
+        H.hfe_fold_encrypt(fk, torch.full((2, 64), 1 << 25, dtype=torch.int32, device="cuda"), 1)
+    for args in ((5, 4, 4), (15, 4, 4), (7, 4, 65)):
+        with pytest.raises(H.HfeError):
+            H.hfe_fold_keygen(*args, KEY_SEED)
+    other = H.hfe_fold_keygen(w.log_n, w.k, w.rho, KEY_SEED + 1)
+    with pytest.raises(H.HfeError):
+        H.hfe_fold(other, ct, cnt, w.rho)                             # ciphertexts of other keys

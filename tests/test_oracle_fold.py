@@ -99,19 +99,16 @@ def _ks_error(FK, level, x, s_from, key):
     return errs
 
 
-@pytest.mark.parametrize("level", [0, 1, 3])
-def test_key_switch_satisfies_the_decryption_equation(keys, level):
+@pytest.mark.parametrize("level,rotation", [(1, True), (1, False), (3, False)])
+def test_key_switch_satisfies_the_decryption_equation(keys, level, rotation):
     P = keys.P
     rng = np.random.default_rng(level)
     x = {z: rng.integers(0, z, P.n) for z in P.moduli(level)}
-    s2 = _negfold(keys.s, keys.s)
-    if level:
-        errs = _ks_error(keys, level, x, s2, keys.relin[level])
+    if rotation:
+        sg = F.automorphism(keys.s, F.rot_galois(P, 3))
+        errs = _ks_error(keys, level, x, [int(v) for v in sg], keys.rot[3])
     else:
-        g = F.rot_galois(P, 3)
-        sg = F.automorphism(keys.s, g)
-        x = {P.q[0]: x[P.q[0]]}
-        errs = _ks_error(keys, 0, x, [int(v) for v in sg], keys.rot[3])
+        errs = _ks_error(keys, level, x, _negfold(keys.s, keys.s), keys.relin[level])
     for e in errs[1:]:
         assert e == errs[0]                      # one integer error, the same modulo every prime
     qmax = max(P.moduli(level))
@@ -162,21 +159,23 @@ def test_products_rotations_and_f_decrypt_to_the_plain_values(keys):
     prod = F.mul(keys, x[0], x[1])
     assert float(np.max(np.abs(F.decode(F.decrypt(keys, prod), LOGN, S.S2) - xv[0] * xv[1]))) < 1e-4
     y = F.poly_f(keys, x[0])
+    assert y[0] == 1
     fx = F.f_plain(xv[0])
-    assert float(np.max(np.abs(F.decode(F.decrypt(keys, y), LOGN, S.F) - fx))) < 5e-3
+    assert float(np.max(np.abs(F.decode(F.decrypt(keys, y), LOGN, S.G) - fx))) < 5e-3
     ry = F.rotate(keys, y, 3)
-    assert float(np.max(np.abs(F.decode(F.decrypt(keys, ry), LOGN, S.F) - np.roll(fx, 3)))) < 5e-3
+    assert float(np.max(np.abs(F.decode(F.decrypt(keys, ry), LOGN, S.G) - np.roll(fx, 3)))) < 5e-3
 
 
 def test_schedule_joins_terms_at_equal_scales():
     P = F.fold_params(LOGN)
     S = F.schedule(P)
     q = [float(v) for v in P.q]
-    assert S.S4 * S.U / q[1] == pytest.approx(S.F, rel=1e-14)
+    assert S.G == S.F * q[1]                              # f at level 1 becomes F after RS by q_1
+    assert S.S4 * S.U == pytest.approx(S.G, rel=1e-14)
     assert S.S2 * S.T3 / q[2] == pytest.approx(S.U, rel=1e-14)
-    assert S.S2 * S.T1 / q[2] == pytest.approx(S.F, rel=1e-14)
+    assert S.S2 * S.T1 / q[2] == pytest.approx(S.G, rel=1e-14)
     # the integer constants carry c_j at their scales to 2^-20
-    E = [S.F, S.F * q[3] / S.S1, S.T1, S.T1 * q[3] / S.S1, S.U, S.U * q[3] / S.S1, S.T3, S.T3 * q[3] / S.S1]
+    E = [S.G, S.G * q[3] / S.S1, S.T1, S.T1 * q[3] / S.S1, S.U, S.U * q[3] / S.S1, S.T3, S.T3 * q[3] / S.S1]
     for kj, cj, ej in zip(S.k, F.COEFFS, E):
         assert abs(kj / ej - cj) <= 2.0 ** -20 * max(1.0, abs(cj))
 
