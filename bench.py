@@ -40,7 +40,7 @@ MEASURED_TRAFFIC_GB = {"dma_q128_w2": 28.3, "dma_r128_w2": 30.4, "dma2_w2": 90.1
                        # the 256-column RNS and n^2 contractions (profiles/pmc_k_gemm_rns_share_q512.md,
                        # profiles/pmc_k_gemm_p2_share_q512.md), fetch + write
                        "rns256": 36.6, "p2_256": 46.1}
-KEY_SEED, DB_SEED, Q_SEED, TX_SEED = 11, 22, 33, 44
+KEY_SEED, DB_SEED, Q_SEED, TX_SEED, FOLD_SEED = 11, 22, 33, 44, 55
 # fp64 vector instructions per second of the chip (256 CUs x 64 lanes x 2.4 GHz; the 78.6 TFLOP/s peak
 # counts a fused multiply-add as two) and the fp64 instructions of one exact modular product in the
 # signed form the FormatSwitch transforms use (multiply, fused multiply-add, multiply by 1/q, rint,
@@ -582,6 +582,75 @@ def run_format_switch(args, H, torch, steps=5):
     return out
 
 
+# f(x) = sum_j c_j x^j, the folding polynomial of Appendix C.2 (to check the decrypted fold)
+FOLD_COEFFS = (0.004105, -0.173510, -2.528271, 24.347349, 124.161550, -412.746212, 376.961251, 106.553952)
+
+
+def fold_expected(w: S.FoldWorkload, ip: np.ndarray, counts: np.ndarray) -> np.ndarray:
+    """The values the folded ciphertexts must decrypt to: per group, sum_r' roll(f(ip / count), r k + r')."""
+    slots = ip.shape[1]
+    f = np.polyval(np.array(FOLD_COEFFS[::-1]), ip.astype(np.float64) / counts)
+    out = []
+    for b in range(w.blocks):
+        for r in range(-(-w.rho // w.k)):
+            acc = np.zeros(slots)
+            for rp in range(min(w.k, w.rho - r * w.k)):
+                acc += np.roll(f[b * w.rho + r * w.k + rp], r * w.k + rp)
+            out.append(acc)
+    return np.array(out)
+
+
+def run_fold(args, H, torch, steps=3):
+    """Normalise and fold (Algorithm 2 after the CCMM) of the share workload's scores: 512 query columns
+    against 14,336 database entries, two blocks of 8,192 slots at ring degree 2^14, k = 16.  Keys and
+    the encryption of the inner products first (untimed), then `steps` timed folds after one warm-up with
+    the library's stage events.  The folded ciphertexts are decrypted on the GPU and checked against the
+    plain folded values."""
+    w = S.FOLD_SHARE
+    ip, counts = S.fold_inputs(w)
+    t0 = time.perf_counter()
+    fk = H.hfe_fold_keygen(w.log_n, w.k, w.rho, KEY_SEED)
+    torch.cuda.synchronize()
+    t_keys = time.perf_counter() - t0
+    ip_d, cnt_d = torch.from_numpy(ip).cuda(), torch.from_numpy(counts).cuda()
+    t0 = time.perf_counter()
+    ct = H.hfe_fold_encrypt(fk, ip_d, FOLD_SEED)
+    torch.cuda.synchronize()
+    t_enc = time.perf_counter() - t0
+    log(f"fold: keys in {t_keys:.2f} s, {w.count} score ciphertexts encrypted in {t_enc * 1e3:.0f} ms")
+    H.hfe_profile(True)
+    ms, stages = [], []
+    out = None
+    for i in range(steps + 1):
+        if out is not None:
+            out.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = H.hfe_fold(fk, ct, cnt_d, w.rho)
+        torch.cuda.synchronize()
+        if i > 0:
+            ms.append((time.perf_counter() - t0) * 1e3)
+            stages.append(H.hfe_fold_profile_ms(out, 4))
+    H.hfe_profile(False)
+    st = np.mean(np.array(stages), axis=0)
+    vals = H.hfe_fold_decrypt(fk, out).cpu().numpy()
+    err = float(np.max(np.abs(vals - fold_expected(w, ip, counts))))
+    groups = w.blocks * -(-w.rho // w.k)
+    mean = float(np.mean(ms))
+    res = {
+        "workload": w.name, "n": 1 << w.log_n, "k": w.k, "rho": w.rho, "blocks": w.blocks, "d1": w.d1,
+        "ciphertexts": w.count, "folded_ciphertexts": groups, "slots": w.count * (1 << w.log_n) // 2,
+        "ms": mean, "ms_min": float(np.min(ms)), "ciphertexts_per_s": w.count / (mean * 1e-3),
+        "scores_per_s": w.d1 * (w.count // w.blocks) / (mean * 1e-3),
+        "stages_ms": {"mu_plaintexts": float(st[0]), "normalise": float(st[1]), "f": float(st[2]),
+                      "rotations_sums": float(st[3])},
+        "keygen_s": t_keys, "encrypt_ms": t_enc * 1e3, "max_abs_error_vs_plain": err,
+    }
+    log(f"fold: {mean:.2f} ms for {w.count} ciphertexts ({res['ciphertexts_per_s']:.0f} ciphertexts/s); stages "
+        f"{', '.join(f'{k} {v:.2f}' for k, v in res['stages_ms'].items())} ms; max error vs plain {err:.2e}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -603,7 +672,9 @@ def main():
     ap.add_argument("--chain-q-mods", type=int, default=7, help="n^2 chain: query moduli (3 more form P)")
     ap.add_argument("--no-fs", action="store_true", help="step mode: skip FormatSwitch")
     ap.add_argument("--fs-steps", type=int, default=5, help="FormatSwitch: timed switches")
-    ap.add_argument("--mode", choices=("step", "batched", "serving", "lit", "fs"), default="step",
+    ap.add_argument("--no-fold", action="store_true", help="step mode: skip normalise and fold")
+    ap.add_argument("--fold-steps", type=int, default=3, help="fold: timed folds")
+    ap.add_argument("--mode", choices=("step", "batched", "serving", "lit", "fs", "fold"), default="step",
                     help="step: the hot-path step (default); batched: 64 uneven items as one plan; "
                          "serving: Poisson arrivals through the server; lit: the step at N_DB = N_Q = 2^16")
     ap.add_argument("--batch-items", type=int, default=64)
@@ -657,6 +728,9 @@ def main():
         return
     if args.mode == "lit":
         print(json.dumps(run_lit(args, H, torch)), flush=True)
+        return
+    if args.mode == "fold":
+        print(json.dumps(run_fold(args, H, torch, steps=args.fold_steps)), flush=True)
         return
     if args.mode == "fs":
         print(json.dumps(run_format_switch(args, H, torch, steps=args.fs_steps)), flush=True)

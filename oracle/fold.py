@@ -31,10 +31,10 @@ Parameters (the paper fixes degree, depth, scale and key weight; the rest are re
   key switching: one digit per prime, d_i = [a (Q_l / q_i)^-1]_{q_i}, keys
   K_i = (k_i, -k_i s + p (Q_l / q_i) s_from + e_i) mod Q_l p, then RS_p (as for FormatSwitch)
 
-Encoding.  Ecd rounds (2/N) sum_j z_j cos(pi i g_j / N), g_j = 5^j mod 2N, to integers.  Both sides of
-the comparison take this decision with the same integer arithmetic: the cosines are the integers
-C[t] = round(2^19 cos(pi t / N)) (t < 2N), a slot value is an integer w_j at scale 2^e, and
-m_i = round(sum_j w_j C[(i g_j) mod 2N] / 2^(log_n + 18 - e)), exact in 64-bit integers.  The decoder is
+Encoding.  Ecd rounds the real polynomial whose slots are the given values, (2/N) sum_j z_j
+cos(pi i g_j / N) with g_j = 5^j mod 2N, to integers.  It is computed as a length-N/2 inverse DFT
+(encode below) in a fixed sequence of IEEE double operations, so that another implementation of the
+same sequence takes the same rounding decisions; it is pinned against the definition.  The decoder is
 the floating-point definition (tests only).
 
 Random streams (Philox, the layout of oracle.prng):
@@ -67,7 +67,6 @@ LOG_IN = 20          # scale of the input inner products
 LOG_MU = 40          # scale of the normalisation plaintext
 LOG_F = 24           # scale of the folded result
 W_BITS = 30          # mu_j is encoded from w_j = round(2^30 / count_j)
-C_BITS = 19          # cosine table precision
 LEVELS = 4           # q_1 .. q_4: three levels of f + normalise
 ROT_LEVEL = 1        # level of the rotations and group sums
 
@@ -119,30 +118,60 @@ def galois_5(n: int) -> np.ndarray:
     return out
 
 
-def cos_table(n: int) -> np.ndarray:
-    """C[t] = round(2^19 cos(pi t / N)), t < 2N (math.cos: the C library's cosine)."""
-    return np.array([math.floor(math.cos(math.pi * t / n) * (1 << C_BITS) + 0.5) for t in range(2 * n)],
-                    dtype=np.int64)
+def _brv(x: int, bits: int) -> int:
+    return int(format(x, "0%db" % bits)[::-1], 2) if bits else 0
 
 
-def encode_int(w: np.ndarray, log_n: int, e: int) -> np.ndarray:
-    """Integer slot values w (N/2 of them, at scale 2^e) -> plaintext coefficients (int64, N):
-    m_i = floor((sum_j w_j C[(i g_j) mod 2N] + 2^(sh-1)) / 2^sh), sh = log_n + 18 - e."""
+def slot_tables(log_n: int):
+    """W[u] = e^(-2 pi i u / M) (u < M/2), Z[i] = zeta^i (i < M), pos[j] = brv(k_j), k_j = (g_j - 1) / 4,
+    M = N/2; cosines and sines from the C library (math.cos, math.sin)."""
     n = 1 << log_n
-    g = galois_5(n)
-    C = cos_table(n)
+    m = n // 2
+    W = np.array([[math.cos(2.0 * math.pi * u / m), -math.sin(2.0 * math.pi * u / m)] for u in range(m // 2)])
+    Z = np.array([[math.cos(math.pi * i / n), math.sin(math.pi * i / n)] for i in range(m)])
+    k = (galois_5(n) - 1) // 4
+    pos = np.array([_brv(int(v), log_n - 1) for v in k], dtype=np.int64)
+    return W.reshape(-1, 2), Z, pos, k
+
+
+def encode(w: np.ndarray, log_n: int, e: int) -> np.ndarray:
+    """Integer slot values w (N/2 of them) at scale 2^e -> plaintext coefficients (int64, N).
+
+    The real polynomial m with m(zeta^(g_j)) = w_j 2^e: with M = N/2, g_j = 1 + 4 k_j and
+    u_i = m_i + i m_(i+M), the slots are the DFT of length M (root w = e^(2 pi i / M)) of u_i zeta^i at
+    k_j, so u_i = zeta^-i (1/M) sum_k zhat_k w^(-i k).  The inverse DFT is the radix-2 transform in
+    decimation in time on bit-reversed input, each butterfly (a, c) -> (a + W c, a - W c) with
+    W c = (Wr cr - Wi ci, Wr ci + Wi cr), in IEEE doubles (numpy's elementwise products and sums, no
+    fused multiply-add); then u_i = ((xr c + xi s) / M, (xi c - xr s) / M) with zeta^i = (c, s), and
+    m_i = floor(Re u_i + 1/2), m_(i+M) = floor(Im u_i + 1/2)."""
+    n = 1 << log_n
+    M = n // 2
+    W, Z, pos, _ = slot_tables(log_n)
     w = np.asarray(w, dtype=np.int64)
-    assert w.shape == (n // 2,)
-    sh = log_n + (C_BITS - 1) - e
-    assert sh >= 1
-    out = np.empty(n, dtype=np.int64)
-    blk = max(1, (1 << 22) // n)
-    for i0 in range(0, n, blk):
-        i = np.arange(i0, min(n, i0 + blk), dtype=np.int64)
-        idx = (i[:, None] * g[None, :]) & (2 * n - 1)
-        s = C[idx] @ w                        # exact: every |w_j C| < 2^49, N/2 <= 2^13 terms
-        out[i0:i0 + len(i)] = (s + (1 << (sh - 1))) >> sh
-    return out
+    assert w.shape == (M,) and int(np.max(np.abs(w), initial=0)) < (1 << 52 - max(e, 0))
+    xr = np.zeros(M)
+    xi = np.zeros(M)
+    xr[pos] = w.astype(np.float64) * float(2.0 ** e)
+    half = 1
+    while half < M:
+        step = M // (2 * half)
+        b = np.arange(M // 2)
+        t = b % half
+        ia = (b // half) * 2 * half + t
+        ic = ia + half
+        wr, wi = W[t * step, 0], W[t * step, 1]
+        cr, ci = xr[ic], xi[ic]
+        pr = wr * cr - wi * ci
+        pi = wr * ci + wi * cr
+        ar, ai = xr[ia].copy(), xi[ia].copy()
+        xr[ia], xi[ia] = ar + pr, ai + pi
+        xr[ic], xi[ic] = ar - pr, ai - pi
+        half *= 2
+    inv_m = 1.0 / M
+    c, s_ = Z[:, 0], Z[:, 1]
+    ur = (xr * c + xi * s_) * inv_m
+    ui = (xi * c - xr * s_) * inv_m
+    return np.concatenate([np.floor(ur + 0.5), np.floor(ui + 0.5)]).astype(np.int64)
 
 
 def mu_weights(counts: np.ndarray) -> np.ndarray:
@@ -264,7 +293,7 @@ def encrypt(FK: FoldKeys, ip: np.ndarray, seed: int, index: int) -> Ct:
     n = P.n
     t = np.arange(n, dtype=np.uint64)
     col = np.full(n, index, dtype=np.uint64)
-    m = encode_int(ip, P.log_n, LOG_IN)
+    m = encode(ip, P.log_n, LOG_IN)
     e = prng.gaussian(seed, FXE, 0, t, col)
     b, a = {}, {}
     for z in P.moduli(LEVELS):
@@ -430,7 +459,7 @@ def schedule(P: FoldParams) -> Schedule:
 
 def normalise(FK: FoldKeys, ct: Ct, counts: np.ndarray) -> Ct:
     """x = RS_{q_4}(ct (.) Ecd(1 / counts)) at level 3."""
-    m = encode_int(mu_weights(counts), FK.P.log_n, LOG_MU - W_BITS)
+    m = encode(mu_weights(counts), FK.P.log_n, LOG_MU - W_BITS)
     return rescale(FK.P, mul_plain(ct, m))
 
 

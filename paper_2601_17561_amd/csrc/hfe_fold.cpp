@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "hfe_internal.h"
+#include "hfe_slots.h"
 
 namespace hfe {
 namespace {
@@ -62,10 +63,8 @@ void ntt_primes_below(int bits, int count, uint64_t* out) {
 // f(x) = sum_j c_j x^j, the folding polynomial of Appendix C.2 (degree 7, k = 16).
 constexpr double kCoeffs[8] = {0.004105, -0.173510, -2.528271, 24.347349, 124.161550, -412.746212, 376.961251,
                                106.553952};
-constexpr int kLogIn = 20, kLogMu = 40, kLogF = 24, kCBits = 19, kWBits = 30;
+constexpr int kLogIn = 20, kLogMu = 40, kLogF = 24, kWBits = 30;
 constexpr int kRotLevel = 1;  // level of the rotations and group sums
-
-int64_t round_half_up(double v) { return (int64_t)std::floor(v + 0.5); }
 
 // The scales of x, x^2, x^4 and of the terms of f, and the integer constants k_0 .. k_7 of f: each scale
 // is one product and one quotient of doubles, in a fixed order, so that every implementation of the
@@ -289,23 +288,16 @@ hfe_status fold_keygen_impl(int logn, int k, int rho, uint64_t seed, hfe_foldkey
   }
   HFE_TRY(put(F->perm, perm.data(), perm.size() * sizeof(int32_t), s));
 
-  // encoder and decoder tables
+  // the slot transforms' tables
   {
-    std::vector<int32_t> ct(2 * (size_t)n), gp((size_t)n / 2);
-    std::vector<double> cd(2 * (size_t)n);
-    for (int t = 0; t < 2 * n; ++t) {
-      const double c = std::cos(M_PI * (double)t / (double)n);
-      cd[(size_t)t] = c;
-      ct[(size_t)t] = (int32_t)std::floor(c * (double)(1 << kCBits) + 0.5);
-    }
-    uint64_t g = 1;
-    for (int j = 0; j < n / 2; ++j) {
-      gp[(size_t)j] = (int32_t)g;
-      g = g * 5 % (2ull * n);
-    }
-    HFE_TRY(put(F->ctab, ct.data(), ct.size() * 4, s));
-    HFE_TRY(put(F->cosd, cd.data(), cd.size() * 8, s));
-    HFE_TRY(put(F->gpow, gp.data(), gp.size() * 4, s));
+    const int m = n / 2;
+    std::vector<double> W(m), Z(2 * (size_t)m);
+    std::vector<int32_t> pos(m), kj(m);
+    slot_tables(logn, W.data(), Z.data(), pos.data(), kj.data());
+    HFE_TRY(put(F->slot_w, W.data(), W.size() * 8, s));
+    HFE_TRY(put(F->slot_z, Z.data(), Z.size() * 8, s));
+    HFE_TRY(put(F->slot_pos, pos.data(), pos.size() * 4, s));
+    HFE_TRY(put(F->slot_k, kj.data(), kj.size() * 4, s));
   }
   FD_LAUNCH(hipStreamSynchronize(s));
   return HFE_OK;
@@ -437,8 +429,8 @@ hfe_status fold_impl(const hfe_foldkeys* F, const hfe_fct* in, const int32_t* co
   HFE_TRY(w.alloc((size_t)n * (N / 2) * 8, s));
   FD_LAUNCH(launch_fold_weights(counts, n * (N / 2), 1, w.as<int64_t>(), flag.as<uint32_t>(), s));
   HFE_TRY(m.alloc((size_t)n * N * 8, s));
-  FD_LAUNCH(launch_fold_encode(w.as<int64_t>(), n, logn, logn + (kCBits - 1) - (kLogMu - kWBits),
-                               F->ctab.as<int32_t>(), F->gpow.as<int32_t>(), m.as<int64_t>(), s));
+  FD_LAUNCH(launch_fold_encode(w.as<int64_t>(), n, logn, std::ldexp(1.0, kLogMu - kWBits), F->slot_w.as<double>(),
+                               F->slot_z.as<double>(), F->slot_pos.as<int32_t>(), m.as<int64_t>(), s));
   w.reset();
   HFE_TRY(mu.alloc((size_t)n * 5 * N * 8, s));
   FD_LAUNCH(launch_fold_fwd(C, m.as<int64_t>(), N, 0, mu.as<uint64_t>(), 5 * N, N, slots_upto(4, false), 5, n, s));
@@ -603,8 +595,8 @@ hfe_status hfe_fold_encrypt(const hfe_foldkeys* fk, const int32_t* ip, int64_t c
     HFE_TRY(w.alloc((size_t)count * (N / 2) * 8, s));
     FD_LAUNCH(launch_fold_weights(ip, count * (N / 2), 0, w.as<int64_t>(), flag.as<uint32_t>(), s));
     HFE_TRY(m.alloc((size_t)count * N * 8, s));
-    FD_LAUNCH(launch_fold_encode(w.as<int64_t>(), count, C.logn, C.logn + (kCBits - 1) - kLogIn,
-                                 F->ctab.as<int32_t>(), F->gpow.as<int32_t>(), m.as<int64_t>(), s));
+    FD_LAUNCH(launch_fold_encode(w.as<int64_t>(), count, C.logn, std::ldexp(1.0, kLogIn), F->slot_w.as<double>(),
+                                 F->slot_z.as<double>(), F->slot_pos.as<int32_t>(), m.as<int64_t>(), s));
     FD_LAUNCH(launch_fold_add_errors(C, seed, F->cdt.as<uint64_t>(), m.as<int64_t>(), count, s));
     HFE_TRY(X->ct.alloc((size_t)count * 2 * 5 * N * 8, s));
     FD_LAUNCH(launch_fold_fwd(C, m.as<int64_t>(), N, 0, X->ct.as<uint64_t>(), 2 * 5 * N, N, slots_upto(4, false), 5,
@@ -673,8 +665,8 @@ hfe_status hfe_fold_decrypt(const hfe_foldkeys* fk, const hfe_fct* ct, double* v
   FD_LAUNCH(launch_fold_dec_products(C, X->ct.as<uint64_t>(), F->s_hat.as<uint64_t>(), h.as<uint64_t>(), X->count, s));
   SlotMap z0{};
   FD_LAUNCH(launch_fold_inv(C, h.as<uint64_t>(), N, 0, m.ptr, N, 0, z0, 1, 1, SlotFactor{}, X->count, s));
-  FD_LAUNCH(launch_fold_decode(m.as<int64_t>(), X->count, C.logn, F->cosd.as<double>(), F->gpow.as<int32_t>(),
-                               1.0 / X->scale, values, s));
+  FD_LAUNCH(launch_fold_decode(m.as<int64_t>(), X->count, C.logn, F->slot_w.as<double>(), F->slot_z.as<double>(),
+                               F->slot_k.as<int32_t>(), 1.0 / X->scale, values, s));
   FD_LAUNCH(hipStreamSynchronize(s));
   return HFE_OK;
 }

@@ -752,9 +752,10 @@ struct hfe_foldkeys : hfe::HandleBase {
   int64_t relin_off[hfe::kFoldLevels] = {};  // offset (doubles) of the key of level l
   hfe::DevBuf rot;                         // [amount][3 slots][2 digits][2][N] doubles (level 1)
   hfe::DevBuf perm;                        // [amount][N] int32: NTT-point permutation of each rotation
-  hfe::DevBuf ctab;                        // [2N] int32 cosine table of the encoder
-  hfe::DevBuf cosd;                        // [2N] doubles: cos(pi t / N) for the decoder
-  hfe::DevBuf gpow;                        // [N/2] int32: 5^j mod 2N
+  hfe::DevBuf slot_w;                      // the slot transforms' tables (hfe_slots.h): W [M/2] complex,
+  hfe::DevBuf slot_z;                      // Z [M] complex (zeta^i),
+  hfe::DevBuf slot_pos;                    // pos [M] int32, where slot j enters the encoder's transform,
+  hfe::DevBuf slot_k;                      // k [M] int32, where the decoder's transform leaves it
   hfe::DevBuf cdt;                         // the Gaussian table
   uint64_t ksum[8] = {};                   // integer constants of f (k_0 .. k_7 as two's complement)
   double sched[8] = {};                    // S1, S2, S4, F, U, T3, T1, G
@@ -776,8 +777,8 @@ struct hfe_fct : hfe::HandleBase {
 namespace hfe {
 hipError_t launch_fold_weights(const int32_t* values, int64_t total, int mode, int64_t* w, uint32_t* bad,
                                hipStream_t s);
-hipError_t launch_fold_encode(const int64_t* w, int64_t items, int logn, int sh, const int32_t* ctab,
-                              const int32_t* gpow, int64_t* out, hipStream_t s);
+hipError_t launch_fold_encode(const int64_t* w, int64_t items, int logn, double scale, const double* W,
+                              const double* Z, const int32_t* pos, int64_t* out, hipStream_t s);
 hipError_t launch_fold_fwd(const FoldConsts& C, const int64_t* src, int64_t si, int64_t ss, uint64_t* dst, int64_t di,
                            int64_t ds, const SlotMap& zm, int nsl, int64_t items, hipStream_t s);
 hipError_t launch_fold_inv(const FoldConsts& C, const uint64_t* src, int64_t si, int64_t ss, void* dst, int64_t di,
@@ -813,8 +814,8 @@ hipError_t launch_fold_encrypt(const FoldConsts& C, uint64_t seed, const uint64_
                                hipStream_t s);
 hipError_t launch_fold_dec_products(const FoldConsts& C, const uint64_t* ct, const uint64_t* s_hat, uint64_t* out,
                                     int64_t items, hipStream_t s);
-hipError_t launch_fold_decode(const int64_t* m, int64_t items, int logn, const double* cosd, const int32_t* gpow,
-                              double inv_scale, double* v, hipStream_t s);
+hipError_t launch_fold_decode(const int64_t* m, int64_t items, int logn, const double* W, const double* Z,
+                              const int32_t* kj, double inv_scale, double* v, hipStream_t s);
 // Coefficient-form residues [count][2][level + 1][N] of a fold ciphertext array (hfe_export).
 hfe_status fold_export(const hfe_fct* X, DevBuf& out, hipStream_t s);
 }  // namespace hfe

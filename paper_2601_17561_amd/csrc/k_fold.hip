@@ -4,7 +4,7 @@
 // Ciphertexts are kept in the NTT domain as uint64 residues, [item][part (b, a)][slot][N]; every
 // transform is one polynomial per workgroup in LDS (hfe_ntt_lds.h).  The operations a fold needs are
 // built from a few passes:
-//   k_fold_encode     the integer slot encoder (plaintext coefficients from integer slot values)
+//   k_fold_encode     the slot encoder (plaintext coefficients from integer slot values, hfe_slots.h)
 //   k_fold_fwd        signed coefficients -> NTT-domain residues, for several slots
 //   k_fold_inv        NTT-domain residues -> coefficients (residues, centered, or digits of a key switch)
 //   k_fold_ks_mac     sum_i NTT(d_i) K_i for one slot: each digit's transform in LDS, the products
@@ -14,6 +14,7 @@
 //   elementwise       plaintext and ciphertext products (tensor), constants, sums, the automorphism
 //                     of a rotation as a permutation of the NTT points, group sums, key and input draws
 #include "hfe_ntt_lds.h"
+#include "hfe_slots.h"
 
 namespace hfe {
 namespace {
@@ -44,28 +45,40 @@ __global__ void k_fold_weights(const int32_t* values, int64_t total, int mode, i
   }
 }
 
-// m_i = floor((sum_j w_j Ctab[(i g_j) mod 2N] + 2^(sh-1)) / 2^sh) for the N coefficients of item c
-// (w[c][j], |w_j| <= 2^30).  One thread per coefficient; the item's weights and the powers g_j sit in
-// LDS.  Every product is below 2^49 and every sum below 2^62, so the integer result is exact and
-// independent of the order of the sum.
-__global__ void __launch_bounds__(256) k_fold_encode(const int64_t* wts, int logn, int sh, const int32_t* ctab,
-                                                     const int32_t* gpow, int64_t* out) {
-  extern __shared__ int64_t enc_lds[];
-  const int n = 1 << logn, half = n >> 1;
-  int64_t* w = enc_lds;
-  int32_t* g = reinterpret_cast<int32_t*>(enc_lds + half);
-  const int64_t c = blockIdx.y;
-  for (int j = threadIdx.x; j < half; j += blockDim.x) {
-    w[j] = wts[c * half + j];
-    g[j] = gpow[j];
+// The slot encoder (hfe_slots.h), one workgroup per item c: the M = N/2 slot values w[c][j] 2^e enter an
+// inverse DFT of length M at bit-reversed positions pos[j] in LDS (real and imaginary parts, N doubles),
+// log2 M radix-2 stages, then the untwist and the rounding: out[c][i], out[c][M + i].
+__global__ void __launch_bounds__(kNttThreads) k_fold_encode(const int64_t* w, int logn, double scale,
+                                                           const double* W, const double* Z, const int32_t* pos,
+                                                           int64_t* out) {
+  extern __shared__ double lds[];
+  const int M = 1 << (logn - 1);
+  double* xr = lds;
+  double* xi = lds + M;
+  const int64_t c = blockIdx.x;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    const int p = pos[j];
+    xr[p] = (double)w[c * M + j] * scale;  // exact: |w| < 2^31, scale a power of two
+    xi[p] = 0.0;
   }
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int mask = 2 * n - 1;
-  int64_t acc = 0;
-  for (int j = 0; j < half; ++j) acc += w[j] * (int64_t)ctab[(i * g[j]) & mask];
-  out[c * n + i] = (acc + (int64_t(1) << (sh - 1))) >> sh;
+  for (int half = 1, lh = 0; half < M; half *= 2, ++lh) {
+    const int step = M / (2 * half);
+    for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
+      const int t = b & (half - 1);
+      const int ia = ((b >> lh) << (lh + 1)) + t, ic = ia + half;
+      slot_butterfly(xr[ia], xi[ia], xr[ic], xi[ic], W[2 * t * step], W[2 * t * step + 1]);
+    }
+    __syncthreads();
+  }
+  const double inv_m = 1.0 / (double)M;
+  int64_t* o = out + c * 2 * M;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    double ur, ui;
+    slot_untwist(xr[i], xi[i], Z[2 * i], Z[2 * i + 1], inv_m, ur, ui);
+    o[i] = round_half_up(ur);
+    o[M + i] = round_half_up(ui);
+  }
 }
 
 // ------------------------------------------------------------------ transforms
@@ -408,20 +421,33 @@ __global__ void k_fold_dec_products(FoldConsts C, const uint64_t* ct, const uint
   }
 }
 
-// Decoding (floating point): v[c][j] = sum_i m_i cos(pi i g_j / N) / scale, one thread per slot.
-__global__ void __launch_bounds__(256) k_fold_decode(const int64_t* m, int logn, const double* cosd,
-                                                     const int32_t* gpow, double inv_scale, double* v) {
-  extern __shared__ double dec_lds[];
-  const int n = 1 << logn, half = n >> 1;
-  const int64_t c = blockIdx.y;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dec_lds[i] = (double)m[c * n + i];
+// Decoding (floating point), one workgroup per item: the slots m(zeta^(g_j)) of the centered coefficients
+// m[c][0 .. N) as the DFT of length M of (m_i + i m_(M+i)) zeta^i (conjugate twiddles of the encoder's,
+// bit-reversed input), real parts divided by the scale: v[c][j] at the transform's output k_j.
+__global__ void __launch_bounds__(kNttThreads) k_fold_decode(const int64_t* m, int logn, const double* W,
+                                                           const double* Z, const int32_t* kj, double inv_scale,
+                                                           double* v) {
+  extern __shared__ double lds[];
+  const int M = 1 << (logn - 1);
+  double* xr = lds;
+  double* xi = lds + M;
+  const int64_t c = blockIdx.x;
+  const int64_t* mc = m + c * 2 * M;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const int p = (int)slot_brv((uint32_t)i, logn - 1);
+    slot_twist((double)mc[i], (double)mc[M + i], Z[2 * i], Z[2 * i + 1], xr[p], xi[p]);
+  }
   __syncthreads();
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= half) return;
-  const int g = gpow[j], mask = 2 * n - 1;
-  double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += dec_lds[i] * cosd[(i * g) & mask];
-  v[c * half + j] = acc * inv_scale;
+  for (int half = 1, lh = 0; half < M; half *= 2, ++lh) {
+    const int step = M / (2 * half);
+    for (int b = threadIdx.x; b < M / 2; b += blockDim.x) {
+      const int t = b & (half - 1);
+      const int ia = ((b >> lh) << (lh + 1)) + t, ic = ia + half;
+      slot_butterfly(xr[ia], xi[ia], xr[ic], xi[ic], W[2 * t * step], -W[2 * t * step + 1]);
+    }
+    __syncthreads();
+  }
+  for (int j = threadIdx.x; j < M; j += blockDim.x) v[c * M + j] = xr[kj[j]] * inv_scale;
 }
 
 unsigned ew_grid(int64_t total) {
@@ -439,15 +465,14 @@ hipError_t launch_fold_weights(const int32_t* values, int64_t total, int mode, i
   return hipGetLastError();
 }
 
-hipError_t launch_fold_encode(const int64_t* w, int64_t items, int logn, int sh, const int32_t* ctab,
-                              const int32_t* gpow, int64_t* out, hipStream_t s) {
+hipError_t launch_fold_encode(const int64_t* w, int64_t items, int logn, double scale, const double* W,
+                              const double* Z, const int32_t* pos, int64_t* out, hipStream_t s) {
   if (items <= 0) return hipSuccess;
-  const int n = 1 << logn;
-  const size_t lds = (size_t)(n / 2) * (sizeof(int64_t) + sizeof(int32_t));
+  const size_t lds = sizeof(double) << logn;
   hipError_t e = allow_lds(k_fold_encode, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fold_encode, dim3((unsigned)((n + 255) / 256), (unsigned)items), dim3(256), lds, s, w, logn,
-                     sh, ctab, gpow, out);
+  hipLaunchKernelGGL(k_fold_encode, dim3((unsigned)items), dim3(ntt_block(logn)), lds, s, w, logn, scale, W, Z, pos,
+                     out);
   return hipGetLastError();
 }
 
@@ -594,15 +619,14 @@ hipError_t launch_fold_dec_products(const FoldConsts& C, const uint64_t* ct, con
   return hipGetLastError();
 }
 
-hipError_t launch_fold_decode(const int64_t* m, int64_t items, int logn, const double* cosd, const int32_t* gpow,
-                              double inv_scale, double* v, hipStream_t s) {
+hipError_t launch_fold_decode(const int64_t* m, int64_t items, int logn, const double* W, const double* Z,
+                              const int32_t* kj, double inv_scale, double* v, hipStream_t s) {
   if (items <= 0) return hipSuccess;
-  const int n = 1 << logn;
-  const size_t lds = (size_t)n * sizeof(double);
+  const size_t lds = sizeof(double) << logn;
   hipError_t e = allow_lds(k_fold_decode, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fold_decode, dim3((unsigned)((n / 2 + 255) / 256), (unsigned)items), dim3(256), lds, s, m, logn,
-                     cosd, gpow, inv_scale, v);
+  hipLaunchKernelGGL(k_fold_decode, dim3((unsigned)items), dim3(ntt_block(logn)), lds, s, m, logn, W, Z, kj,
+                     inv_scale, v);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../paper_2601_17561_amd/csrc/hfe_exact.h"
+#include "../../paper_2601_17561_amd/csrc/hfe_slots.h"
 
 using namespace hfe;
 
@@ -12,6 +13,26 @@ static constexpr RnsModConsts kRns = make_rns_mod_consts();
 static constexpr P2BaseConsts kP2 = make_p2_base_consts();
 
 extern "C" {
+
+// The fold's slot encoder (hfe_slots.h) on w (N/2 integers) at scale 2^e: out = N integer coefficients.
+void xc_slot_encode(const int64_t* w, int logn, int e, int64_t* out) {
+  const int64_t n = int64_t(1) << logn, m = n / 2;
+  double* W = new double[m];
+  double* Z = new double[2 * m];
+  int32_t* pos = new int32_t[m];
+  int32_t* kj = new int32_t[m];
+  double* z = new double[m];
+  double* scratch = new double[2 * m];
+  slot_tables(logn, W, Z, pos, kj);
+  for (int64_t j = 0; j < m; ++j) z[j] = (double)w[j] * ldexp(1.0, e);
+  slot_encode_host(z, logn, W, Z, pos, scratch, out);
+  delete[] W;
+  delete[] Z;
+  delete[] pos;
+  delete[] kj;
+  delete[] z;
+  delete[] scratch;
+}
 
 // out[i] = a[i] w[i] mod q by the fp64 product of the transforms (qinv = RN(1/q) as the tables hold it).
 void xc_mulmod_d(const uint64_t* a, const uint64_t* w, int64_t n, uint64_t q, uint64_t* out) {

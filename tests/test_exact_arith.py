@@ -42,6 +42,7 @@ for _name, _args in {
         "xc_mulmod_c_d": [_p, _p, ctypes.c_int64, ctypes.c_uint64, _p],
         "xc_reduce_c_d": [_p, ctypes.c_int64, ctypes.c_uint64, _p],
         "xc_ntt_signed": [_p, _p, ctypes.c_int, ctypes.c_uint64, _p],
+        "xc_slot_encode": [_p, ctypes.c_int, ctypes.c_int, _p],
         "xc_mod_small": [_p, ctypes.c_int64, ctypes.c_uint32, _p],
         "xc_mod_f64": [_p, ctypes.c_int64, ctypes.c_int64, _p],
         "xc_balanced_mod": [_p, ctypes.c_int64, ctypes.c_int, _p],
@@ -350,3 +351,23 @@ def test_chain_digits_and_epilogue_exact_for_every_base(n):
     _L.xc_p2_acc_mod_n(_ptr(g0), _ptr(g1), len(g0), n, _ptr(out))
     want = (g0.astype(np.int64) + n * g1.astype(np.int64)) % n2
     assert np.array_equal(out.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("log_n,e", [(7, 20), (10, 10), (14, 10), (14, 20)])
+def test_slot_encoder_matches_the_oracle_bit_for_bit(log_n, e):
+    """The fold's slot encoder as the kernel runs it (hfe_slots.h, host build) takes the same rounding
+    decisions as the oracle's encoder (oracle/fold.py, numpy): the same sequence of IEEE operations on the
+    same tables.  Inner products (|w| <= 2^14) at scale 2^20 and normalisation weights (up to 2^30, with
+    the dynamic range of counts from 1 to 2^14) at scale 2^10."""
+    from oracle import fold as OF
+    rng = np.random.default_rng(log_n + e)
+    m = (1 << log_n) // 2
+    if e == 20:
+        w = rng.integers(-(1 << 14), 1 << 14, m)
+    else:
+        c = rng.integers(1, 1 << 14, m)
+        w = ((1 << 31) + c) // (2 * c)
+    w = w.astype(np.int64)
+    out = np.empty(1 << log_n, dtype=np.int64)
+    _L.xc_slot_encode(_ptr(w), log_n, e, _ptr(out))
+    assert np.array_equal(out, OF.encode(w, log_n, e))

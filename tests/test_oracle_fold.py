@@ -1,8 +1,9 @@
 """Pins of the normalise-and-fold oracle (oracle/fold.py; Section 4, Algorithm 2, Appendix C.2).
 
 Each step is checked against something other than itself:
-  * the integer encoder against the floating-point definition of Ecd within its quantisation bound,
-    and the slot order against evaluation of the polynomial at the complex roots zeta^(5^j) (numpy);
+  * the encoder (an inverse DFT of length N/2) against the definition of Ecd summed directly, within the
+    rounding, and the slot order against evaluation of the polynomial at the complex roots zeta^(5^j)
+    (numpy);
   * the automorphism of Rot_r against slot rotation in the direction of Section 4.3 (slot i of
     Rot_r(v) holds v_(i - r)), by evaluation at the roots;
   * the sparse secret's weight and values;
@@ -46,17 +47,20 @@ def _roots_eval(m, log_n):
     return np.polyval(np.array([float(v) for v in m[::-1]]), z)
 
 
-def test_encoder_within_its_quantisation_bound_of_the_definition():
-    n = 1 << LOGN
-    rng = np.random.default_rng(0)
-    w = rng.integers(-(1 << 20), 1 << 20, n // 2)
+@pytest.mark.parametrize("log_n", [6, 7, 10])
+def test_encoder_rounds_the_definition(log_n):
+    """Ecd by the length-N/2 inverse DFT against (2/N) sum_j z_j cos(pi i g_j / N) summed directly: within
+    1/2 (the rounding) plus the transforms' floating-point error, on both signs and a wide range."""
+    n = 1 << log_n
+    rng = np.random.default_rng(log_n)
+    w = rng.integers(-(1 << 26), 1 << 26, n // 2)
+    w[: n // 8] = rng.integers(-3, 4, n // 8)
     e = 6
-    m = F.encode_int(w, LOGN, e)
+    m = F.encode(w, log_n, e)
     g = np.array([pow(5, j, 2 * n) for j in range(n // 2)])
     i = np.arange(n)
     exact = (2.0 / n) * (np.cos(np.pi * ((i[:, None] * g[None, :]) % (2 * n)) / n) @ (w * 2.0 ** e))
-    bound = 0.5 + float(np.abs(w).max()) * 2.0 ** (e - F.C_BITS - 1) * 1.01
-    assert float(np.max(np.abs(m - exact))) <= bound
+    assert float(np.max(np.abs(m - exact))) <= 0.5 + 1e-12 * float(np.abs(w).max()) * 2.0 ** e * log_n
 
 
 def test_slots_are_the_evaluations_at_the_powers_of_5():
@@ -66,9 +70,9 @@ def test_slots_are_the_evaluations_at_the_powers_of_5():
     want = _roots_eval(m, LOGN)
     assert np.allclose(F.decode(m, LOGN, 1.0), want.real, atol=1e-8)
     z = rng.integers(-5000, 5000, n // 2)
-    back = F.decode(F.encode_int(z, LOGN, 10), LOGN, 2.0 ** 10)
+    back = F.decode(F.encode(z, LOGN, 10), LOGN, 2.0 ** 10)
     assert float(np.max(np.abs(back - z))) < 0.05
-    assert np.allclose(_roots_eval(F.encode_int(z, LOGN, 10), LOGN).imag / 2 ** 10, 0, atol=0.05)
+    assert np.allclose(_roots_eval(F.encode(z, LOGN, 10), LOGN).imag / 2 ** 10, 0, atol=0.05)
 
 
 @pytest.mark.parametrize("r", [1, 3, 20])
@@ -76,7 +80,7 @@ def test_rotation_automorphism_moves_slot_i_to_i_plus_r(r):
     P = F.fold_params(LOGN, 4)
     rng = np.random.default_rng(r)
     z = rng.integers(-5000, 5000, P.slots)
-    m = F.encode_int(z, LOGN, 10)
+    m = F.encode(z, LOGN, 10)
     got = _roots_eval(F.automorphism(m, F.rot_galois(P, r)), LOGN).real / 2 ** 10
     assert float(np.max(np.abs(got - np.roll(z, r)))) < 0.05
 
