@@ -95,9 +95,10 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_fwd(FoldConsts C, const in
   const int64_t* x = src + item * si + s * ss;
   for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(x[t], md.q, md.mu));
   __syncthreads();
-  ntt_fwd_lds(lds, C.tab[z]);
+  ntt_fwd_lds_c(lds, C.tab[z]);
   uint64_t* y = dst + item * di + s * ds;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = to_u(lds[t]);
+  const double zd = C.zd[z], zi = C.zinv[z];
+  for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = to_u(residue_of_c(reduce_c_d(lds[t], zd, zi), zd));
 }
 
 // job = item * nsl + s: inverse NTT of src[item * si + s * ss] mod z_s; mode 0: residues (uint64),
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, const ui
   const uint64_t* x = src + item * si + s * ss;
   for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(x[t]);
   __syncthreads();
-  ntt_inv_lds(lds, C.tab[z]);
+  ntt_inv_lds_c(lds, C.tab[z]);
   const int64_t off = item * di + s * ds;
   if (mode == 1) {
     int64_t* y = static_cast<int64_t*>(dst) + off;
@@ -145,6 +146,9 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
   const int z = special ? 5 : s;
   const Mod md = C.mod[z];
   const double* key = keys + (kidx ? (int64_t)kidx[item] : 0) * kstride + (int64_t)s * (level + 1) * 2 * n;
+  // signed transforms: each digit's transform is below 8.1z in magnitude, each product centered within
+  // (1/2 + 2^-11) z, so the sums over at most 4 digits stay below 2.1z
+  const double zd = C.zd[z], zi = C.zinv[z];
   double ab[R], aa[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) ab[r] = aa[r] = 0.0;
@@ -152,14 +156,14 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
     const uint64_t* d = dig + (item * (level + 1) + i) * n;
     for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(barrett64(d[t], md.q, md.mu));
     __syncthreads();
-    ntt_fwd_lds(lds, C.tab[z]);
+    ntt_fwd_lds_c(lds, C.tab[z]);
     const double* kb = key + (int64_t)i * 2 * n;   // part 0: mask k_i, part 1: beta_i
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int t = threadIdx.x + r * blockDim.x;
       const double v = lds[t];
-      aa[r] = addmod_d(aa[r], mm_d(v, kb[t], z, C), C.zd[z]);
-      ab[r] = addmod_d(ab[r], mm_d(v, kb[n + t], z, C), C.zd[z]);
+      aa[r] += mulmod_c_d(v, kb[t], zd, zi);
+      ab[r] += mulmod_c_d(v, kb[n + t], zd, zi);
     }
     __syncthreads();
   }
@@ -169,8 +173,8 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int t = threadIdx.x + r * blockDim.x;
-      ob[t] = to_u(ab[r]);
-      oa[t] = to_u(aa[r]);
+      ob[t] = to_u(residue_of_c(reduce_c_d(ab[r], zd, zi), zd));
+      oa[t] = to_u(residue_of_c(reduce_c_d(aa[r], zd, zi), zd));
     }
     return;
   }
@@ -178,7 +182,7 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
 #pragma unroll
     for (int r = 0; r < R; ++r) lds[threadIdx.x + r * blockDim.x] = part ? aa[r] : ab[r];
     __syncthreads();
-    ntt_inv_lds(lds, C.tab[z]);
+    ntt_inv_lds_c(lds, C.tab[z]);
     int64_t* o = accp + (item * 2 + part) * n;
     for (int t = threadIdx.x; t < n; t += blockDim.x) o[t] = centered(to_u(lds[t]), md.q);
     __syncthreads();
@@ -202,16 +206,16 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, const i
   const int64_t* c = cen + ip * n;
   for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(c[t], md.q, md.mu));
   __syncthreads();
-  ntt_fwd_lds(lds, C.tab[z]);
+  ntt_fwd_lds_c(lds, C.tab[z]);  // signed, below 8.1z
   const uint64_t* xx = x + item * xi + part * xp + (int64_t)s * n;
   // ap = 0: the addend belongs to part 0 only (a rotation adds sigma(b) to B)
   const uint64_t* aa = (add && (part == 0 || ap != 0)) ? add + item * ai + part * ap + (int64_t)s * n : nullptr;
   uint64_t* o = out + item * oi + part * op + (int64_t)s * n;
-  const double zd = C.zd[z], w = inv.v[s];
+  const double zd = C.zd[z], zi = C.zinv[z], w = inv.v[s];
   for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    double v = mm_d(submod_d(to_d(xx[t]), lds[t], zd), w, z, C);
-    if (aa) v = addmod_d(v, to_d(aa[t]), zd);
-    o[t] = to_u(v);
+    double v = mulmod_c_d(to_d(xx[t]) - lds[t], w, zd, zi);  // |x - NTT| < 9.1z: centered product
+    if (aa) v += to_d(aa[t]);                                 // in (-0.51z, 1.51z)
+    o[t] = to_u(v < 0.0 ? v + zd : (v >= zd ? v - zd : v));
   }
 }
 
