@@ -214,16 +214,34 @@ def _cpu_fs(args):
     return t_keys, t_tx, time.perf_counter() - t0
 
 
-def cpu_baseline_chain_fs(w: S.Workload, inp, chain_q: int, rows: int = 128, cols: int = 4):
-    """The oracle beside two more measurements, in two processes side by side (one core each): the n^2
-    chain's CCMM on a sample scaled to the step's rows and columns, and FormatSwitch of one query column
-    scaled to the workload's columns.  Runs before the GPU is touched."""
+def _cpu_fold(args):
+    """The fold oracle at the share workload's ring degree 2^14 on one group of `cts` score ciphertexts
+    (one core): keys and encryption untimed, the fold timed."""
+    cts, = args
+    from oracle import fold as OF
+    fw = S.FOLD_SHARE
+    P = OF.fold_params(fw.log_n, fw.k)
+    FK = OF.fold_keygen(P, KEY_SEED, OF.rot_amounts(fw.k, cts))
+    ip, counts = S.fold_inputs(fw)
+    enc = [OF.encrypt(FK, ip[c].astype(np.int64), FOLD_SEED, c) for c in range(cts)]
+    t0 = time.perf_counter()
+    OF.fold(FK, enc, counts[:cts].astype(np.int64), cts)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_chain_fs(w: S.Workload, inp, chain_q: int, rows: int = 128, cols: int = 4, fold_cts: int = 2):
+    """The oracle beside three more measurements, in three processes side by side (one core each): the n^2
+    chain's CCMM on a sample scaled to the step's rows and columns, FormatSwitch of one query column
+    scaled to the workload's columns, and the fold of a group of `fold_cts` score ciphertexts scaled to the
+    fold workload's ciphertexts.  Runs before the GPU is touched."""
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(2) as pool:
+    with mp.get_context("fork").Pool(3) as pool:
         rc = pool.apply_async(_cpu_chain, ((w, chain_q, rows, cols),))
         rf = pool.apply_async(_cpu_fs, ((inp,),))
+        rd = pool.apply_async(_cpu_fold, ((fold_cts,),))
         t_lift, t_rows, K = rc.get()
         t_keys, t_tx, t_fs = rf.get()
+        t_fold = rd.get()
     work = algorithmic_work(w)
     chain_step = t_lift * (w.d3 / cols) + t_rows * (work["R_out"] / rows) * (w.d3 / cols)
     chain = dict(value=w.d1 * w.d3 / chain_step, unit="comparisons/s", cores=1, kind="oracle",
@@ -236,7 +254,13 @@ def cpu_baseline_chain_fs(w: S.Workload, inp, chain_q: int, rows: int = 128, col
               sample=(f"the FormatSwitch oracle on one query column of the share workload (2^16 -> 2^13, level "
                       f"{fw.level}): keys {t_keys:.1f} s, transmission encryption {t_tx:.1f} s, the switch "
                       f"{t_fs:.1f} s (1 core); {t_fs * fw.d3:.0f} s for the {fw.d3} columns"))
-    return chain, fs
+    dw = S.FOLD_SHARE
+    fold = dict(value=fold_cts / t_fold, unit="ciphertexts/s", cores=1, kind="oracle",
+                sample=(f"the fold oracle at ring degree 2^{dw.log_n} on a group of {fold_cts} score ciphertexts "
+                        f"(normalisation, f, {fold_cts - 1} rotation, the rescale; keys and encryption untimed): "
+                        f"{t_fold:.1f} s (1 core); {t_fold / fold_cts * dw.count:.0f} s for the {dw.count} "
+                        f"ciphertexts"))
+    return chain, fs, fold
 
 
 def encrypt_database(H, torch, w, forms):
@@ -600,6 +624,31 @@ def fold_expected(w: S.FoldWorkload, ip: np.ndarray, counts: np.ndarray) -> np.n
     return np.array(out)
 
 
+def fold_modmuls(w: S.FoldWorkload):
+    """Modular products of the f stage of one fold (all ciphertexts), counted from its operations: a
+    transform of degree N is N/2 log N butterflies of one product (an inverse adds N for its 1/N).
+    A product of ciphertexts at level l: the tensor's a_x a_y and the digit factor on l + 1 inverse
+    transforms, (l + 2)(l + 1) forward transforms of the digits with two key products per coefficient,
+    two inverse transforms at p, 2 (l + 1) forward transforms with p^-1 and the tensor terms b_x b_y,
+    a_x b_y + a_y b_x (four products per coefficient over both parts), then a rescale (two inverse and
+    2 l forward transforms with one product per coefficient).  A constant term rescaled from level 3 to
+    `to`: two inverse transforms of the constant times the last slot, 2 (to + 1) forward transforms with two
+    products per coefficient."""
+    n, lg = 1 << w.log_n, w.log_n
+    fwd, inv = n // 2 * lg, n // 2 * lg + n
+
+    def mul(l, rescaled=True):
+        ks = ((l + 1) * (inv + 2 * n) + (l + 2) * (l + 1) * (fwd + 2 * n) + 2 * inv
+              + 2 * (l + 1) * (fwd + n) + (l + 1) * 4 * n)
+        return ks + ((2 * inv + 2 * l * (fwd + n)) if rescaled else 0)
+
+    def const(to):
+        return 2 * (inv + n) + 2 * (to + 1) * (fwd + 2 * n)
+
+    f = mul(3) + const(2) + const(2) + const(1) + const(1) + 3 * mul(2) + mul(1, rescaled=False)
+    return w.count * f
+
+
 def run_fold(args, H, torch, steps=3):
     """Normalise and fold (Algorithm 2 after the CCMM) of the share workload's scores: 512 query columns
     against 14,336 database entries, two blocks of 8,192 slots at ring degree 2^14, k = 16.  Keys and
@@ -646,8 +695,15 @@ def run_fold(args, H, torch, steps=3):
                       "rotations_sums": float(st[3])},
         "keygen_s": t_keys, "encrypt_ms": t_enc * 1e3, "max_abs_error_vs_plain": err,
     }
+    mm = fold_modmuls(w)
+    ceiling = FP64_INSTR_PER_S / FP64_PER_MODMUL
+    rate = mm / (st[2] * 1e-3)
+    res["roofline"] = {"bound": "alu", "kernel": "f stage (k_fold_ks_mac, k_fold_lift, k_fold_inv, element-wise passes)",
+                       "achieved": rate / 1e12, "peak": ceiling / 1e12, "unit": "T modmul/s", "frac": rate / ceiling,
+                       "modmuls_per_launch": mm, "kernel_ms": float(st[2]), "traffic": None}
     log(f"fold: {mean:.2f} ms for {w.count} ciphertexts ({res['ciphertexts_per_s']:.0f} ciphertexts/s); stages "
-        f"{', '.join(f'{k} {v:.2f}' for k, v in res['stages_ms'].items())} ms; max error vs plain {err:.2e}")
+        f"{', '.join(f'{k} {v:.2f}' for k, v in res['stages_ms'].items())} ms; max error vs plain {err:.2e}; "
+        f"f stage at {100 * res['roofline']['frac']:.1f}% of the modular-product ceiling")
     return res
 
 
@@ -702,7 +758,7 @@ def main():
     w = S.WORKLOADS[args.workload]
     work = algorithmic_work(w)
     inp = S.make_inputs(w)
-    cpu = cpu_chain = cpu_fs = None
+    cpu = cpu_chain = cpu_fs = cpu_fold = None
     if args.mode == "step" and not args.no_cpu_baseline and not (args.sweep or args.ccmm_only):
         # before anything touches the GPU: the oracle's process pool is forked from this process
         workers = args.cpu_workers or min(16, os.cpu_count() or 1)
@@ -711,9 +767,10 @@ def main():
         log(f"oracle: {cpu['sample']}")
         cpu.pop("step_s")
         if w.name == S.PAPER_SHARE.name:
-            cpu_chain, cpu_fs = cpu_baseline_chain_fs(w, inp, args.chain_q_mods)
+            cpu_chain, cpu_fs, cpu_fold = cpu_baseline_chain_fs(w, inp, args.chain_q_mods)
             log(f"oracle: {cpu_chain['sample']}")
             log(f"oracle: {cpu_fs['sample']}")
+            log(f"oracle: {cpu_fold['sample']}")
 
     import torch
     import paper_2601_17561_amd as H
@@ -1009,6 +1066,11 @@ def main():
         torch.cuda.empty_cache()
         line["format_switch"] = run_format_switch(args, H, torch, steps=args.fs_steps)
         line["format_switch"]["cpu_baseline"] = cpu_fs
+    if not args.no_fold:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        line["fold"] = run_fold(args, H, torch, steps=args.fold_steps)
+        line["fold"]["cpu_baseline"] = cpu_fold
     print(json.dumps(line), flush=True)
 
 

@@ -314,68 +314,11 @@ struct Ev {
 
 int64_t ct_words(const Ev& e, int l) { return e.n * 2 * (l + 1) * e.N; }
 
-// RS by q_l: x [n][2][l+1][N] -> out [n][2][l][N].
-hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out) {
-  DevBuf cen;
-  HFE_TRY(cen.alloc((size_t)e.n * 2 * e.N * 8, e.s));
-  SlotMap one{};
-  one.z[0] = (int8_t)l;
-  FD_LAUNCH(launch_fold_inv(e.C, x + l * e.N, (l + 1) * e.N, 0, cen.ptr, e.N, 0, one, 1, 1, SlotFactor{}, e.n * 2,
-                            e.s));
-  SlotFactor inv{};
-  const uint64_t ql = e.C.mod[l].q;
-  for (int j = 0; j < l; ++j) inv.v[j] = (double)inv_mod(ql % e.C.mod[j].q, e.C.mod[j].q);
-  FD_LAUNCH(launch_fold_lift(e.C, cen.as<int64_t>(), x, 2 * (l + 1) * e.N, (l + 1) * e.N, nullptr, 0, 0, out,
-                             2 * l * e.N, l * e.N, slots_upto(l - 1, false), l, inv, e.n, e.s));
-  return HFE_OK;
-}
-
-// Key switch at level l of the polynomial src (item stride si, slots 0 .. l at stride N): out (item
-// stride oi, part stride op, slots 0 .. l) = RS_p(sum_i d_i K_i) + add (item stride ai, part stride ap;
-// ap = 0: the addend is added to part 0 only).  keys + kidx[item] * kstride is the item's key.
-hfe_status key_switch(const Ev& e, int l, const uint64_t* src, int64_t si, const double* keys, int64_t kstride,
-                      const int32_t* kidx, const uint64_t* add, int64_t ai, int64_t ap, uint64_t* out, int64_t oi,
-                      int64_t op) {
-  DevBuf dig, acc, accp;
-  HFE_TRY(dig.alloc((size_t)e.n * (l + 1) * e.N * 8, e.s));
-  HFE_TRY(acc.alloc((size_t)e.n * 2 * (l + 1) * e.N * 8, e.s));
-  HFE_TRY(accp.alloc((size_t)e.n * 2 * e.N * 8, e.s));
-  SlotFactor gh{};
-  for (int i = 0; i <= l; ++i) {
-    const uint64_t qi = e.C.mod[i].q;
-    uint64_t qhat = 1;  // (Q_l / q_i) mod q_i
-    for (int j = 0; j <= l; ++j)
-      if (j != i) qhat = mm(qhat, e.C.mod[j].q % qi, qi);
-    gh.v[i] = (double)inv_mod(qhat, qi);
-  }
-  FD_LAUNCH(launch_fold_inv(e.C, src, si, e.N, dig.ptr, (l + 1) * e.N, e.N, slots_upto(l, false), l + 1, 2, gh, e.n,
-                            e.s));
-  FD_LAUNCH(launch_fold_ks_mac(e.C, l, dig.as<uint64_t>(), keys, kstride, kidx, acc.as<uint64_t>(),
-                               accp.as<int64_t>(), e.n, e.s));
-  SlotFactor pinv{};
-  const uint64_t p = e.C.mod[5].q;
-  for (int j = 0; j <= l; ++j) pinv.v[j] = (double)inv_mod(p % e.C.mod[j].q, e.C.mod[j].q);
-  FD_LAUNCH(launch_fold_lift(e.C, accp.as<int64_t>(), acc.as<uint64_t>(), 2 * (l + 1) * e.N, (l + 1) * e.N, add, ai,
-                             ap, out, oi, op, slots_upto(l, false), l + 1, pinv, e.n, e.s));
-  return HFE_OK;
-}
-
-// x y with relinearisation at level l, then RS by q_l: out [n][2][l][N] (rescaled = false: the
-// relinearised product itself, [n][2][l + 1][N]).
-hfe_status mul(const Ev& e, const uint64_t* x, const uint64_t* y, int l, uint64_t* out, bool rescaled = true) {
-  const int64_t per = (l + 1) * e.N;
-  DevBuf d, t;
-  HFE_TRY(d.alloc((size_t)e.n * 3 * per * 8, e.s));
-  FD_LAUNCH(launch_fold_tensor(e.C, x, y, d.as<uint64_t>(), e.n, l + 1, e.s));
-  const double* key = e.F->relin.as<double>() + e.F->relin_off[l];
-  if (!rescaled)
-    return key_switch(e, l, d.as<uint64_t>() + 2 * per, 3 * per, key, 0, nullptr, d.as<uint64_t>(), 3 * per, per, out,
-                      2 * per, per);
-  HFE_TRY(t.alloc((size_t)ct_words(e, l) * 8, e.s));
-  HFE_TRY(key_switch(e, l, d.as<uint64_t>() + 2 * per, 3 * per, key, 0, nullptr, d.as<uint64_t>(), 3 * per, per,
-                     t.as<uint64_t>(), 2 * per, per));
-  return rescale(e, t.as<uint64_t>(), l, out);
-}
+// A ciphertext array at level l in the fold's layout [n][b | a][slot][N].
+struct View {
+  const uint64_t* p = nullptr;
+  int l = 0;
+};
 
 SlotFactor const_res(const FoldConsts& C, int64_t k, int nsl) {
   SlotFactor r{};
@@ -383,18 +326,143 @@ SlotFactor const_res(const FoldConsts& C, int64_t k, int nsl) {
   return r;
 }
 
-// RS(k x) at level l -> level l - 1, then down to level `to` (dropping primes), then + c.
-hfe_status const_term(const Ev& e, const uint64_t* x, int l, int64_t k, int to, int64_t c, DevBuf& out) {
-  DevBuf t, r;
-  HFE_TRY(t.alloc((size_t)ct_words(e, l) * 8, e.s));
-  HFE_TRY(r.alloc((size_t)ct_words(e, l - 1) * 8, e.s));
-  FD_LAUNCH(launch_fold_affine(e.C, x, t.as<uint64_t>(), e.n, l + 1, const_res(e.C, k, l + 1), SlotFactor{}, e.s));
-  HFE_TRY(rescale(e, t.as<uint64_t>(), l, r.as<uint64_t>()));
-  HFE_TRY(out.alloc((size_t)ct_words(e, to) * 8, e.s));
-  FD_LAUNCH(launch_fold_add(e.C, r.as<uint64_t>(), l, nullptr, 0, out.as<uint64_t>(), e.n, to + 1, e.s));
-  FD_LAUNCH(launch_fold_affine(e.C, out.as<uint64_t>(), out.as<uint64_t>(), e.n, to + 1, const_res(e.C, 1, to + 1),
-                               const_res(e.C, c, to + 1), e.s));
+// Options of a rescale: x times k first (a constant), keep only slots 0 .. to (a mod-drop), add c to b and
+// add2 (an array at level `to`) to the result.
+struct RsOpts {
+  bool has_k = false;
+  int64_t k = 1;
+  int to = -1;  // -1: l - 1
+  int64_t c = 0;
+  const uint64_t* add2 = nullptr;
+};
+
+// RS by q_l: x [n][2][l+1][N] -> out [n][2][to+1][N].
+hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out, const RsOpts& o = RsOpts()) {
+  const int to = o.to < 0 ? l - 1 : o.to;
+  DevBuf cen;
+  HFE_TRY(cen.alloc((size_t)e.n * 2 * e.N * 8, e.s));
+  FoldInv ia;
+  ia.src = x + l * e.N;
+  ia.si = (l + 1) * e.N;
+  ia.zm.z[0] = (int8_t)l;
+  ia.nsl = 1;
+  ia.mode = 1;
+  if (o.has_k) {
+    ia.has_pre = 1;
+    ia.pre.v[0] = (double)residue(o.k, e.C.mod[l].q);
+  }
+  ia.dst = cen.ptr;
+  ia.di = e.N;
+  FD_LAUNCH(launch_fold_inv(e.C, ia, e.n * 2, e.s));
+  FoldLift la;
+  la.cen = cen.as<int64_t>();
+  la.x = x;
+  la.xi = 2 * (l + 1) * e.N;
+  la.xp = (l + 1) * e.N;
+  if (o.has_k) {
+    la.has_xmul = 1;
+    la.xmul = const_res(e.C, o.k, to + 1);
+  }
+  la.cres = const_res(e.C, o.c, to + 1);
+  if (o.add2) {
+    la.add2 = o.add2;
+    la.a2i = 2 * (to + 1) * e.N;
+    la.a2p = (to + 1) * e.N;
+  }
+  la.out = out;
+  la.oi = 2 * (to + 1) * e.N;
+  la.op = (to + 1) * e.N;
+  la.zm = slots_upto(to, false);
+  la.nsl = to + 1;
+  const uint64_t ql = e.C.mod[l].q;
+  for (int j = 0; j <= to; ++j) la.inv.v[j] = (double)inv_mod(ql % e.C.mod[j].q, e.C.mod[j].q);
+  FD_LAUNCH(launch_fold_lift(e.C, la, e.n, e.s));
   return HFE_OK;
+}
+
+// Key switch at level l: digits of the polynomial src (item stride si, slots 0 .. l at stride N), or of the
+// product src y (the a parts of a tensor) when y is given; the result RS_p(sum_i d_i K_i) plus the addends
+// that `tail` names goes to tail.out.  keys + kidx[item] * kstride is the item's key.
+hfe_status key_switch(const Ev& e, int l, const uint64_t* src, const uint64_t* y, int64_t si, const double* keys,
+                      int64_t kstride, const int32_t* kidx, FoldLift tail) {
+  DevBuf dig, acc, accp;
+  HFE_TRY(dig.alloc((size_t)e.n * (l + 1) * e.N * 8, e.s));
+  HFE_TRY(acc.alloc((size_t)e.n * 2 * (l + 1) * e.N * 8, e.s));
+  HFE_TRY(accp.alloc((size_t)e.n * 2 * e.N * 8, e.s));
+  FoldInv ia;
+  ia.src = src;
+  ia.y = y;
+  ia.si = si;
+  ia.ss = e.N;
+  ia.dst = dig.ptr;
+  ia.di = (l + 1) * e.N;
+  ia.ds = e.N;
+  ia.zm = slots_upto(l, false);
+  ia.nsl = l + 1;
+  ia.mode = 2;
+  for (int i = 0; i <= l; ++i) {
+    const uint64_t qi = e.C.mod[i].q;
+    uint64_t qhat = 1;  // (Q_l / q_i) mod q_i
+    for (int j = 0; j <= l; ++j)
+      if (j != i) qhat = mm(qhat, e.C.mod[j].q % qi, qi);
+    ia.f.v[i] = (double)inv_mod(qhat, qi);
+  }
+  FD_LAUNCH(launch_fold_inv(e.C, ia, e.n, e.s));
+  FD_LAUNCH(launch_fold_ks_mac(e.C, l, dig.as<uint64_t>(), keys, kstride, kidx, acc.as<uint64_t>(),
+                               accp.as<int64_t>(), e.n, e.s));
+  tail.cen = accp.as<int64_t>();
+  tail.x = acc.as<uint64_t>();
+  tail.xi = 2 * (l + 1) * e.N;
+  tail.xp = (l + 1) * e.N;
+  tail.zm = slots_upto(l, false);
+  tail.nsl = l + 1;
+  const uint64_t p = e.C.mod[5].q;
+  for (int j = 0; j <= l; ++j) tail.inv.v[j] = (double)inv_mod(p % e.C.mod[j].q, e.C.mod[j].q);
+  FD_LAUNCH(launch_fold_lift(e.C, tail, e.n, e.s));
+  return HFE_OK;
+}
+
+// x y with relinearisation at level l (the tensor's d2 formed in the digit pass, d0 and d1 in the key
+// switch's last pass), then RS by q_l: out [n][2][l][N] plus add2 (level l - 1); rescaled = false: the
+// relinearised product itself, [n][2][l + 1][N], plus add2 (level l).
+hfe_status mul(const Ev& e, const uint64_t* x, const uint64_t* y, int l, uint64_t* out, bool rescaled = true,
+               const uint64_t* add2 = nullptr) {
+  const int64_t per = (l + 1) * e.N;
+  const double* key = e.F->relin.as<double>() + e.F->relin_off[l];
+  FoldLift tail;
+  tail.tx = x;
+  tail.ty = y;
+  tail.ti = 2 * per;
+  tail.tp = per;
+  tail.oi = 2 * per;
+  tail.op = per;
+  if (!rescaled) {
+    tail.out = out;
+    if (add2) {
+      tail.add2 = add2;
+      tail.a2i = 2 * per;
+      tail.a2p = per;
+    }
+    return key_switch(e, l, x + per, y + per, 2 * per, key, 0, nullptr, tail);
+  }
+  DevBuf t;
+  HFE_TRY(t.alloc((size_t)ct_words(e, l) * 8, e.s));
+  tail.out = t.as<uint64_t>();
+  HFE_TRY(key_switch(e, l, x + per, y + per, 2 * per, key, 0, nullptr, tail));
+  RsOpts o;
+  o.add2 = add2;
+  return rescale(e, t.as<uint64_t>(), l, out, o);
+}
+
+// RS(k x) at level l -> level l - 1, kept at the slots of level `to` (a mod-drop), then + c.
+hfe_status const_term(const Ev& e, const uint64_t* x, int l, int64_t k, int to, int64_t c, DevBuf& out) {
+  HFE_TRY(out.alloc((size_t)ct_words(e, to) * 8, e.s));
+  RsOpts o;
+  o.has_k = true;
+  o.k = k;
+  o.to = to;
+  o.c = c;
+  return rescale(e, x, l, out.as<uint64_t>(), o);
 }
 
 // Rotations at level 1 of the items src[u] of x ([.][2][2][N]) by the amounts with key index amt[u]
@@ -409,8 +477,15 @@ hfe_status rotate(const hfe_foldkeys* F, hipStream_t s, const uint64_t* x, const
   DevBuf P;
   HFE_TRY(P.alloc((size_t)m * per * 8, s));
   FD_LAUNCH(launch_fold_perm(F->C, x, src, amt, F->perm.as<int32_t>(), P.as<uint64_t>(), m, nsl, s));
-  return key_switch(e, l, P.as<uint64_t>() + nsl * N, per, F->rot.as<double>(), (int64_t)(l + 2) * (l + 1) * 2 * N,
-                    amt, P.as<uint64_t>(), per, 0, out, per, nsl * N);
+  FoldLift tail;
+  tail.add = P.as<uint64_t>();  // sigma(b), to part 0 only
+  tail.ai = per;
+  tail.ap = 0;
+  tail.out = out;
+  tail.oi = per;
+  tail.op = nsl * N;
+  return key_switch(e, l, P.as<uint64_t>() + nsl * N, nullptr, per, F->rot.as<double>(),
+                    (int64_t)(l + 2) * (l + 1) * 2 * N, amt, tail);
 }
 
 hfe_status fold_impl(const hfe_foldkeys* F, const hfe_fct* in, const int32_t* counts, int64_t rho, hipStream_t s,
@@ -447,8 +522,9 @@ hfe_status fold_impl(const hfe_foldkeys* F, const hfe_fct* in, const int32_t* co
   t4.reset();
   if (ev) FD_LAUNCH(hipEventRecord(ev[2], s));
 
-  // f(x) = (c0 + c1 x) + x^2 (c2 + c3 x) + x^4 ((c4 + c5 x) + x^2 (c6 + c7 x)) at level 1, scale G
-  DevBuf x2, x4, L0, L1, L2, L3, t, inner, t1, t4b, f;
+  // f(x) = (c0 + c1 x) + x^2 (c2 + c3 x) + x^4 ((c4 + c5 x) + x^2 (c6 + c7 x)) at level 1, scale G: the
+  // sums formed in the last passes of the products (inner = x^2 L3 + L2; t1 = x^2 L1 + L0; f = x^4 inner + t1)
+  DevBuf x2, x4, L0, L1, L2, L3, inner, t1, f;
   HFE_TRY(x2.alloc((size_t)ct_words(e, 2) * 8, s));
   HFE_TRY(mul(e, x3.as<uint64_t>(), x3.as<uint64_t>(), 3, x2.as<uint64_t>()));
   HFE_TRY(const_term(e, x3.as<uint64_t>(), 3, k[7], 2, k[6], L3));
@@ -458,18 +534,13 @@ hfe_status fold_impl(const hfe_foldkeys* F, const hfe_fct* in, const int32_t* co
   x3.reset();
   HFE_TRY(x4.alloc((size_t)ct_words(e, 1) * 8, s));
   HFE_TRY(mul(e, x2.as<uint64_t>(), x2.as<uint64_t>(), 2, x4.as<uint64_t>()));
-  HFE_TRY(t.alloc((size_t)ct_words(e, 1) * 8, s));
-  HFE_TRY(mul(e, x2.as<uint64_t>(), L3.as<uint64_t>(), 2, t.as<uint64_t>()));
   HFE_TRY(inner.alloc((size_t)ct_words(e, 1) * 8, s));
-  FD_LAUNCH(launch_fold_add(C, t.as<uint64_t>(), 2, L2.as<uint64_t>(), 2, inner.as<uint64_t>(), n, 2, s));
+  HFE_TRY(mul(e, x2.as<uint64_t>(), L3.as<uint64_t>(), 2, inner.as<uint64_t>(), true, L2.as<uint64_t>()));
   HFE_TRY(t1.alloc((size_t)ct_words(e, 1) * 8, s));
-  HFE_TRY(mul(e, x2.as<uint64_t>(), L1.as<uint64_t>(), 2, t1.as<uint64_t>()));
+  HFE_TRY(mul(e, x2.as<uint64_t>(), L1.as<uint64_t>(), 2, t1.as<uint64_t>(), true, L0.as<uint64_t>()));
   x2.reset();
-  HFE_TRY(t4b.alloc((size_t)ct_words(e, 1) * 8, s));
-  HFE_TRY(mul(e, x4.as<uint64_t>(), inner.as<uint64_t>(), 1, t4b.as<uint64_t>(), false));
   HFE_TRY(f.alloc((size_t)ct_words(e, 1) * 8, s));
-  FD_LAUNCH(launch_fold_add(C, L0.as<uint64_t>(), 2, t4b.as<uint64_t>(), 2, f.as<uint64_t>(), n, 2, s));
-  FD_LAUNCH(launch_fold_add(C, f.as<uint64_t>(), 2, t1.as<uint64_t>(), 2, f.as<uint64_t>(), n, 2, s));
+  HFE_TRY(mul(e, x4.as<uint64_t>(), inner.as<uint64_t>(), 1, f.as<uint64_t>(), false, t1.as<uint64_t>()));
   if (ev) FD_LAUNCH(hipEventRecord(ev[3], s));
 
   // rotations inside each group, the group sums, and the rotation of group r by r k
@@ -663,8 +734,14 @@ hfe_status hfe_fold_decrypt(const hfe_foldkeys* fk, const hfe_fct* ct, double* v
   HFE_TRY(h.alloc((size_t)X->count * N * 8, s));
   HFE_TRY(m.alloc((size_t)X->count * N * 8, s));
   FD_LAUNCH(launch_fold_dec_products(C, X->ct.as<uint64_t>(), F->s_hat.as<uint64_t>(), h.as<uint64_t>(), X->count, s));
-  SlotMap z0{};
-  FD_LAUNCH(launch_fold_inv(C, h.as<uint64_t>(), N, 0, m.ptr, N, 0, z0, 1, 1, SlotFactor{}, X->count, s));
+  FoldInv ia;
+  ia.src = h.as<uint64_t>();
+  ia.si = N;
+  ia.dst = m.ptr;
+  ia.di = N;
+  ia.nsl = 1;
+  ia.mode = 1;
+  FD_LAUNCH(launch_fold_inv(C, ia, X->count, s));
   FD_LAUNCH(launch_fold_decode(m.as<int64_t>(), X->count, C.logn, F->slot_w.as<double>(), F->slot_z.as<double>(),
                                F->slot_k.as<int32_t>(), 1.0 / X->scale, values, s));
   FD_LAUNCH(hipStreamSynchronize(s));
@@ -689,8 +766,16 @@ hfe_status fold_export(const hfe_fct* X, DevBuf& out, hipStream_t s) {
   const int64_t N = 1ll << C.logn;
   const int l = X->level;
   HFE_TRY(out.alloc((size_t)X->count * 2 * (l + 1) * N * 8, s));
-  FD_LAUNCH(launch_fold_inv(C, X->ct.as<uint64_t>(), (l + 1) * N, N, out.ptr, (l + 1) * N, N, slots_upto(l, false),
-                            l + 1, 0, SlotFactor{}, X->count * 2, s));
+  FoldInv ia;
+  ia.src = X->ct.as<uint64_t>();
+  ia.si = (l + 1) * N;
+  ia.ss = N;
+  ia.dst = out.ptr;
+  ia.di = (l + 1) * N;
+  ia.ds = N;
+  ia.zm = slots_upto(l, false);
+  ia.nsl = l + 1;
+  FD_LAUNCH(launch_fold_inv(C, ia, X->count * 2, s));
   FD_LAUNCH(hipStreamSynchronize(s));
   return HFE_OK;
 }

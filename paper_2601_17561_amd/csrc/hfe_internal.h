@@ -731,6 +731,42 @@ struct KeyGadget {
   double v[kFoldSlots][kFoldLevels];  // [slot position][digit]: p (Q_l / q_i) mod z
 };
 
+// An inverse transform pass of the fold (k_fold_inv): source src[item si + s ss], optionally times y at the
+// same place or times pre[s]; mode 0 residues, 1 centered, 2 times f[s] (digits); dst[item di + s ds].
+struct FoldInv {
+  const uint64_t* src = nullptr;
+  int64_t si = 0, ss = 0;
+  const uint64_t* y = nullptr;
+  int has_pre = 0;
+  SlotFactor pre{};
+  void* dst = nullptr;
+  int64_t di = 0, ds = 0;
+  SlotMap zm{};
+  int nsl = 0, mode = 0;
+  SlotFactor f{};
+};
+// A lift pass of the fold (k_fold_lift), see k_fold.hip.
+struct FoldLift {
+  const int64_t* cen = nullptr;          // [item][part][N] centered values of the divided-out modulus
+  const uint64_t* x = nullptr;           // kept residues, item stride xi, part stride xp, slot stride N
+  int64_t xi = 0, xp = 0;
+  int has_xmul = 0;
+  SlotFactor xmul{};                     // x times xmul[s] first (a constant's rescale)
+  const uint64_t* add = nullptr;         // addend (ap = 0: part 0 only)
+  int64_t ai = 0, ap = 0;
+  const uint64_t* add2 = nullptr;        // second addend, both parts
+  int64_t a2i = 0, a2p = 0;
+  const uint64_t* tx = nullptr;          // tensor addend of tx, ty (item stride ti, part stride tp)
+  const uint64_t* ty = nullptr;
+  int64_t ti = 0, tp = 0;
+  SlotFactor cres{};                     // constant added to part 0
+  uint64_t* out = nullptr;
+  int64_t oi = 0, op = 0;
+  SlotMap zm{};
+  int nsl = 0;
+  SlotFactor inv{};
+};
+
 struct FoldConsts {
   int logn;
   double zd[kFoldSlots], zinv[kFoldSlots];
@@ -781,22 +817,12 @@ hipError_t launch_fold_encode(const int64_t* w, int64_t items, int logn, double 
                               const double* Z, const int32_t* pos, int64_t* out, hipStream_t s);
 hipError_t launch_fold_fwd(const FoldConsts& C, const int64_t* src, int64_t si, int64_t ss, uint64_t* dst, int64_t di,
                            int64_t ds, const SlotMap& zm, int nsl, int64_t items, hipStream_t s);
-hipError_t launch_fold_inv(const FoldConsts& C, const uint64_t* src, int64_t si, int64_t ss, void* dst, int64_t di,
-                           int64_t ds, const SlotMap& zm, int nsl, int mode, const SlotFactor& f, int64_t items,
-                           hipStream_t s);
+hipError_t launch_fold_inv(const FoldConsts& C, const FoldInv& a, int64_t items, hipStream_t s);
 hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const uint64_t* dig, const double* keys, int64_t kstride,
                               const int32_t* kidx, uint64_t* acc, int64_t* accp, int64_t items, hipStream_t s);
-hipError_t launch_fold_lift(const FoldConsts& C, const int64_t* cen, const uint64_t* x, int64_t xi, int64_t xp,
-                            const uint64_t* add, int64_t ai, int64_t ap, uint64_t* out, int64_t oi, int64_t op,
-                            const SlotMap& zm, int nsl, const SlotFactor& inv, int64_t items, hipStream_t s);
+hipError_t launch_fold_lift(const FoldConsts& C, const FoldLift& a, int64_t items, hipStream_t s);
 hipError_t launch_fold_mul_pt(const FoldConsts& C, const uint64_t* ct, const uint64_t* pt, uint64_t* out,
                               int64_t items, int nsl, hipStream_t s);
-hipError_t launch_fold_tensor(const FoldConsts& C, const uint64_t* x, const uint64_t* y, uint64_t* d, int64_t items,
-                              int nsl, hipStream_t s);
-hipError_t launch_fold_affine(const FoldConsts& C, const uint64_t* x, uint64_t* out, int64_t items, int nsl,
-                              const SlotFactor& kres, const SlotFactor& cres, hipStream_t s);
-hipError_t launch_fold_add(const FoldConsts& C, const uint64_t* x, int xs, const uint64_t* y, int ys, uint64_t* out,
-                           int64_t items, int nsl, hipStream_t s);
 hipError_t launch_fold_perm(const FoldConsts& C, const uint64_t* x, const int32_t* src, const int32_t* amt,
                             const int32_t* perm, uint64_t* out, int64_t items, int nsl, hipStream_t s);
 hipError_t launch_fold_group_sum(const FoldConsts& C, const uint64_t* f, const uint64_t* rotated, const int32_t* beg,

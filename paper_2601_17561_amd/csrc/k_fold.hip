@@ -6,13 +6,15 @@
 // built from a few passes:
 //   k_fold_encode     the slot encoder (plaintext coefficients from integer slot values, hfe_slots.h)
 //   k_fold_fwd        signed coefficients -> NTT-domain residues, for several slots
-//   k_fold_inv        NTT-domain residues -> coefficients (residues, centered, or digits of a key switch)
+//   k_fold_inv        NTT-domain residues (or the product of two, or times a constant) -> coefficients
+//                     (residues, centered, or the digits of a key switch)
 //   k_fold_ks_mac     sum_i NTT(d_i) K_i for one slot: each digit's transform in LDS, the products
 //                     accumulated in registers; the special prime's sum is transformed back and centered
-//   k_fold_lift       (x - NTT([y]_div)) div^-1 (+ an addend) on every kept slot: RS_div and the end of a
-//                     key switch
-//   elementwise       plaintext and ciphertext products (tensor), constants, sums, the automorphism
-//                     of a rotation as a permutation of the NTT points, group sums, key and input draws
+//   k_fold_lift       (x k - NTT([y]_div)) div^-1 plus addends on every kept slot: RS_div of a product, of a
+//                     constant times a ciphertext (with a mod-drop and an added constant), and the end of a
+//                     key switch (with the tensor terms d0, d1 of a product, or sigma(b) of a rotation)
+//   elementwise       plaintext products, the automorphism of a rotation as a permutation of the NTT points,
+//                     group sums, key and input draws
 #include "hfe_ntt_lds.h"
 #include "hfe_slots.h"
 
@@ -101,28 +103,36 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_fwd(FoldConsts C, const in
   for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = to_u(residue_of_c(reduce_c_d(lds[t], zd, zi), zd));
 }
 
-// job = item * nsl + s: inverse NTT of src[item * si + s * ss] mod z_s; mode 0: residues (uint64),
-// 1: centered (int64), 2: residues times factor[s] mod z_s (the digits of a key switch).
-__global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, const uint64_t* src, int64_t si, int64_t ss,
-                                                        void* dst, int64_t di, int64_t ds, SlotMap zm, int nsl,
-                                                        int mode, SlotFactor f) {
+// job = item * nsl + s: inverse NTT of src[item * si + s * ss] mod z_s (times y at the same place when
+// y is given, times pre[s] when has_pre); mode 0: residues (uint64), 1: centered (int64), 2: residues times
+// factor[s] mod z_s (the digits of a key switch).
+__global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, FoldInv a) {
   extern __shared__ double lds[];
   const int n = 1 << C.logn;
-  const int64_t item = blockIdx.x / nsl;
-  const int s = blockIdx.x - (int)(item * nsl);
-  const int z = zm.z[s];
-  const uint64_t* x = src + item * si + s * ss;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(x[t]);
+  const int64_t item = blockIdx.x / a.nsl;
+  const int s = blockIdx.x - (int)(item * a.nsl);
+  const int z = a.zm.z[s];
+  const int64_t off = item * a.si + s * a.ss;
+  const uint64_t* x = a.src + off;
+  if (a.y) {
+    const uint64_t* y = a.y + off;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = mm_d(to_d(x[t]), to_d(y[t]), z, C);
+  } else if (a.has_pre) {
+    const double f = a.pre.v[s];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = mm_d(to_d(x[t]), f, z, C);
+  } else {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(x[t]);
+  }
   __syncthreads();
   ntt_inv_lds_c(lds, C.tab[z]);
-  const int64_t off = item * di + s * ds;
-  if (mode == 1) {
-    int64_t* y = static_cast<int64_t*>(dst) + off;
+  const int64_t doff = item * a.di + s * a.ds;
+  if (a.mode == 1) {
+    int64_t* y = static_cast<int64_t*>(a.dst) + doff;
     for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = centered(to_u(lds[t]), C.mod[z].q);
   } else {
-    uint64_t* y = static_cast<uint64_t*>(dst) + off;
-    const double fz = f.v[s];
-    for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = to_u(mode == 2 ? mm_d(lds[t], fz, z, C) : lds[t]);
+    uint64_t* y = static_cast<uint64_t*>(a.dst) + doff;
+    const double fz = a.f.v[s];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = to_u(a.mode == 2 ? mm_d(lds[t], fz, z, C) : lds[t]);
   }
 }
 
@@ -190,32 +200,49 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
 }
 
 // job = (item * 2 + part) * nsl + s, slot z = zm.z[s]:
-// out = (x - NTT_z(cen mod z)) inv[s] (+ add) mod z, with cen = cen[(item * 2 + part) * N + t].
-__global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, const int64_t* cen, const uint64_t* x,
-                                                         int64_t xi, int64_t xp, const uint64_t* add, int64_t ai,
-                                                         int64_t ap, uint64_t* out, int64_t oi, int64_t op,
-                                                         SlotMap zm, int nsl, SlotFactor inv) {
+// out = (x xmul[s] - NTT_z(cen mod z)) inv[s] + addends mod z, with cen = cen[(item * 2 + part) * N + t].
+// Addends: add (part 0 only when ap = 0), add2 (both parts), the tensor terms of tx and ty (part 0: b_x b_y,
+// part 1: a_x b_y + a_y b_x) and the constant cres on part 0.
+__global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLift a) {
   extern __shared__ double lds[];
   const int n = 1 << C.logn;
-  const int64_t ip = blockIdx.x / nsl;
-  const int s = blockIdx.x - (int)(ip * nsl);
+  const int64_t ip = blockIdx.x / a.nsl;
+  const int s = blockIdx.x - (int)(ip * a.nsl);
   const int64_t item = ip >> 1;
   const int part = (int)(ip & 1);
-  const int z = zm.z[s];
+  const int z = a.zm.z[s];
   const Mod md = C.mod[z];
-  const int64_t* c = cen + ip * n;
+  const int64_t* c = a.cen + ip * n;
   for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(c[t], md.q, md.mu));
   __syncthreads();
   ntt_fwd_lds_c(lds, C.tab[z]);  // signed, below 8.1z
-  const uint64_t* xx = x + item * xi + part * xp + (int64_t)s * n;
-  // ap = 0: the addend belongs to part 0 only (a rotation adds sigma(b) to B)
-  const uint64_t* aa = (add && (part == 0 || ap != 0)) ? add + item * ai + part * ap + (int64_t)s * n : nullptr;
-  uint64_t* o = out + item * oi + part * op + (int64_t)s * n;
-  const double zd = C.zd[z], zi = C.zinv[z], w = inv.v[s];
+  const int64_t so = (int64_t)s * n;
+  const uint64_t* xx = a.x + item * a.xi + part * a.xp + so;
+  const uint64_t* aa = (a.add && (part == 0 || a.ap != 0)) ? a.add + item * a.ai + part * a.ap + so : nullptr;
+  const uint64_t* a2 = a.add2 ? a.add2 + item * a.a2i + part * a.a2p + so : nullptr;
+  const uint64_t* tx = a.tx ? a.tx + item * a.ti + so : nullptr;
+  const uint64_t* ty = a.tx ? a.ty + item * a.ti + so : nullptr;
+  uint64_t* o = a.out + item * a.oi + part * a.op + so;
+  const double zd = C.zd[z], zi = C.zinv[z], w = a.inv.v[s];
+  const double km = a.has_xmul ? a.xmul.v[s] : 0.0, kc = part == 0 ? a.cres.v[s] : 0.0;
   for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    double v = mulmod_c_d(to_d(xx[t]) - lds[t], w, zd, zi);  // |x - NTT| < 9.1z: centered product
-    if (aa) v += to_d(aa[t]);                                 // in (-0.51z, 1.51z)
-    o[t] = to_u(v < 0.0 ? v + zd : (v >= zd ? v - zd : v));
+    double xv = to_d(xx[t]);
+    if (a.has_xmul) xv = mm_d(xv, km, z, C);
+    double v = mulmod_c_d(xv - lds[t], w, zd, zi);  // |x - NTT| < 9.1z: centered product, below 0.51z
+    v = v < 0.0 ? v + zd : v;                        // [0, z)
+    if (aa) v = addmod_d(v, to_d(aa[t]), zd);
+    if (a2) v = addmod_d(v, to_d(a2[t]), zd);
+    if (tx) {
+      const double bx = to_d(tx[t]), by = to_d(ty[t]);
+      if (part == 0) {
+        v = addmod_d(v, mm_d(bx, by, z, C), zd);
+      } else {
+        const double ax = to_d(tx[a.tp + t]), ay = to_d(ty[a.tp + t]);
+        v = addmod_d(v, addmod_d(mm_d(ax, by, z, C), mm_d(ay, bx, z, C), zd), zd);
+      }
+    }
+    v = addmod_d(v, kc, zd);
+    o[t] = to_u(v);
   }
 }
 
@@ -231,57 +258,6 @@ __global__ void k_fold_mul_pt(FoldConsts C, const uint64_t* ct, const uint64_t* 
     const int s = (int)(r % nsl);
     const int64_t item = r / (2 * nsl);
     out[e] = to_u(mm_d(to_d(ct[e]), to_d(pt[(item * nsl + s) * n + t]), s, C));
-  }
-}
-
-// Tensor of x and y at nsl slots: d[item][0 | 1 | 2][s] = b_x b_y, a_x b_y + a_y b_x, a_x a_y.
-__global__ void k_fold_tensor(FoldConsts C, const uint64_t* x, const uint64_t* y, uint64_t* d, int64_t items, int nsl) {
-  const int n = 1 << C.logn;
-  const int64_t per = (int64_t)nsl * n;
-  const int64_t total = items * per;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t item = e / per, w = e - item * per;
-    const int s = (int)(w >> C.logn);
-    const double zd = C.zd[s];
-    const double bx = to_d(x[item * 2 * per + w]), ax = to_d(x[item * 2 * per + per + w]);
-    const double by = to_d(y[item * 2 * per + w]), ay = to_d(y[item * 2 * per + per + w]);
-    uint64_t* o = d + item * 3 * per + w;
-    o[0] = to_u(mm_d(bx, by, s, C));
-    o[per] = to_u(addmod_d(mm_d(ax, by, s, C), mm_d(ay, bx, s, C), zd));
-    o[2 * per] = to_u(mm_d(ax, ay, s, C));
-  }
-}
-
-// out = x k (both parts; kres[s] = k mod q_s), then b += c (cres[s] = c mod q_s; the constant
-// polynomial c is c at every NTT point), at nsl slots.  Either step may be the identity (k = 1, c = 0).
-__global__ void k_fold_affine(FoldConsts C, const uint64_t* x, uint64_t* out, int64_t items, int nsl, SlotFactor kres,
-                              SlotFactor cres) {
-  const int n = 1 << C.logn;
-  const int64_t total = items * 2 * nsl * (int64_t)n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e >> C.logn;
-    const int s = (int)(r % nsl);
-    const bool b = ((r / nsl) & 1) == 0;
-    double v = mm_d(to_d(x[e]), kres.v[s], s, C);
-    if (b) v = addmod_d(v, cres.v[s], C.zd[s]);
-    out[e] = to_u(v);
-  }
-}
-
-// out = x + y at nsl slots; x and y may carry more slots than out (xs, ys: their slot counts), so that
-// dropping primes and adding is one pass.
-__global__ void k_fold_add(FoldConsts C, const uint64_t* x, int xs, const uint64_t* y, int ys, uint64_t* out,
-                           int64_t items, int nsl) {
-  const int n = 1 << C.logn;
-  const int64_t total = items * 2 * nsl * (int64_t)n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int t = (int)(e & (n - 1));
-    const int64_t r = e >> C.logn;
-    const int s = (int)(r % nsl);
-    const int64_t ip = r / nsl;  // item * 2 + part
-    double v = to_d(x[(ip * xs + s) * n + t]);
-    if (y) v = addmod_d(v, to_d(y[(ip * ys + s) * n + t]), C.zd[s]);
-    out[e] = to_u(v);
   }
 }
 
@@ -491,15 +467,12 @@ hipError_t launch_fold_fwd(const FoldConsts& C, const int64_t* src, int64_t si, 
   return hipGetLastError();
 }
 
-hipError_t launch_fold_inv(const FoldConsts& C, const uint64_t* src, int64_t si, int64_t ss, void* dst, int64_t di,
-                           int64_t ds, const SlotMap& zm, int nsl, int mode, const SlotFactor& f, int64_t items,
-                           hipStream_t s) {
+hipError_t launch_fold_inv(const FoldConsts& C, const FoldInv& a, int64_t items, hipStream_t s) {
   if (items <= 0) return hipSuccess;
   const size_t lds = sizeof(double) << C.logn;
   hipError_t e = allow_lds(k_fold_inv, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fold_inv, dim3((unsigned)(items * nsl)), dim3(ntt_block(C.logn)), lds, s, C, src, si, ss, dst,
-                     di, ds, zm, nsl, mode, f);
+  hipLaunchKernelGGL(k_fold_inv, dim3((unsigned)(items * a.nsl)), dim3(ntt_block(C.logn)), lds, s, C, a);
   return hipGetLastError();
 }
 
@@ -517,15 +490,12 @@ hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const uint64_t* di
   });
 }
 
-hipError_t launch_fold_lift(const FoldConsts& C, const int64_t* cen, const uint64_t* x, int64_t xi, int64_t xp,
-                            const uint64_t* add, int64_t ai, int64_t ap, uint64_t* out, int64_t oi, int64_t op,
-                            const SlotMap& zm, int nsl, const SlotFactor& inv, int64_t items, hipStream_t s) {
-  if (items <= 0 || nsl <= 0) return hipSuccess;
+hipError_t launch_fold_lift(const FoldConsts& C, const FoldLift& a, int64_t items, hipStream_t s) {
+  if (items <= 0 || a.nsl <= 0) return hipSuccess;
   const size_t lds = sizeof(double) << C.logn;
   hipError_t e = allow_lds(k_fold_lift, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fold_lift, dim3((unsigned)(items * 2 * nsl)), dim3(ntt_block(C.logn)), lds, s, C, cen, x, xi,
-                     xp, add, ai, ap, out, oi, op, zm, nsl, inv);
+  hipLaunchKernelGGL(k_fold_lift, dim3((unsigned)(items * 2 * a.nsl)), dim3(ntt_block(C.logn)), lds, s, C, a);
   return hipGetLastError();
 }
 
@@ -534,29 +504,6 @@ hipError_t launch_fold_mul_pt(const FoldConsts& C, const uint64_t* ct, const uin
   if (items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fold_mul_pt, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, ct, pt, out, items,
                      nsl);
-  return hipGetLastError();
-}
-
-hipError_t launch_fold_tensor(const FoldConsts& C, const uint64_t* x, const uint64_t* y, uint64_t* d, int64_t items,
-                              int nsl, hipStream_t s) {
-  if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold_tensor, dim3(ew_grid(items * nsl << C.logn)), dim3(256), 0, s, C, x, y, d, items, nsl);
-  return hipGetLastError();
-}
-
-hipError_t launch_fold_affine(const FoldConsts& C, const uint64_t* x, uint64_t* out, int64_t items, int nsl,
-                              const SlotFactor& kres, const SlotFactor& cres, hipStream_t s) {
-  if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold_affine, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, x, out, items, nsl,
-                     kres, cres);
-  return hipGetLastError();
-}
-
-hipError_t launch_fold_add(const FoldConsts& C, const uint64_t* x, int xs, const uint64_t* y, int ys, uint64_t* out,
-                           int64_t items, int nsl, hipStream_t s) {
-  if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold_add, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, x, xs, y, ys, out,
-                     items, nsl);
   return hipGetLastError();
 }
 
