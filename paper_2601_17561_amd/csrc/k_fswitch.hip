@@ -280,52 +280,7 @@ __global__ void k_fs_digits(FsConsts C, const uint64_t* T, int64_t ncols, double
   }
 }
 
-// Forward transforms fused with their load and their use.  With blockDim = n / (8 GPT), the first
-// round (S0 = (log n - 1) mod 3 + 1 stages, t = n / 2: group g holds the coefficients g + k n / 2^S0)
-// reads its coefficients from global memory into registers, the middle rounds of three stages run
-// through LDS, and the last round (t = 4: group g holds the contiguous coefficients 8g .. 8g + 7 of
-// the bit-reversed output) stays in registers, where the caller multiplies by the keys: two LDS
-// passes and two barriers fewer per transform than a load, the transform and a reload.  The
-// butterflies run on signed values without corrections (ct_butterfly_c, hfe_exact.h): inputs below 2q
-// (the digits, below q_i < 2z) leave a transform of degree up to 2^14 below 9.1q, congruent to the
-// exact outputs, which the centered products of the multiply-accumulate take as they are.
-
-// First round: loads every value this thread's groups need (before the barrier that lets it
-// overwrite LDS), then the S0 stages and the store.
-template <int GPT, int S0, class Load>
-__device__ __forceinline__ void fused_first_round(double* lds, const NttTab& T, Load load) {
-  constexpr int G = 1 << S0;
-  constexpr int M = 8 * GPT / G;  // groups per thread
-  const int n = 1 << T.logn, ng = n >> S0;
-  double y[M][G];
-#pragma unroll
-  for (int m = 0; m < M; ++m)
-#pragma unroll
-    for (int k = 0; k < G; ++k) y[m][k] = load(threadIdx.x + m * blockDim.x + k * ng);
-  __syncthreads();  // the previous transform's last round has read LDS
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const int g = threadIdx.x + m * blockDim.x;
-    fwd_stages_c<S0>(y[m], T, 1, 0);
-#pragma unroll
-    for (int k = 0; k < G; ++k) lds[g + k * ng] = y[m][k];
-  }
-  __syncthreads();
-}
-
-template <int GPT, int S0, class Load>
-__device__ __forceinline__ void ntt_fwd_fused(double* lds, const NttTab& T, Load load, double (&x)[GPT][8]) {
-  const int n = 1 << T.logn;
-  fused_first_round<GPT, S0>(lds, T, load);
-  for (int t = (n >> 1) >> S0; t > 4; t >>= 3) fwd_round_c<3>(lds, T, n, t);
-#pragma unroll
-  for (int j = 0; j < GPT; ++j) {
-    const int g = threadIdx.x + j * blockDim.x;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) x[j][k] = lds[8 * g + k];
-    fwd_stages_c<3>(x[j], T, n >> 3, g);
-  }
-}
+// The forward transforms are fused with their load and their use (ntt_fwd_fused, hfe_ntt_lds.h).
 
 // acc + x w with the centered product (|x| <= 16q): acc stays an exact integer, below (1/2 + 2^-11) q
 // times the number of terms (at most 4096 here) in magnitude.
