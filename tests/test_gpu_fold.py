@@ -7,7 +7,8 @@ sum_r' Rot_{r k + r'}(f(IP / count)) within the homomorphic error.
 Workloads: N = 2^7 with k = 4 and blocks of 6 (a full and a partial group, two blocks, a last block of
 empty database slots), N = 2^10 with k = 16 and blocks of 20, and N = 2^14 with the paper's k = 16,
 checked against the oracle's hashes of every residue (tests/golden/fold_paper.json, written by
-tests/golden/make_fold_paper.py from the oracle alone).
+tests/golden/make_fold_paper.py from the oracle alone); and the share workload's full fold (1,024
+ciphertexts) in the benchmark's launch configuration, its first two outputs against the oracle's hashes.
 """
 import hashlib
 import json
@@ -117,6 +118,25 @@ def test_fold_paper_degree_matches_the_oracle():
     _assert_matches("s", H.hfe_export(fk, 0).view(np.int64), g, "secret")
     _assert_matches("ct", _exported(ct, 4, w.count, n), g, "input ciphertexts")
     _assert_matches("out", _exported(out, 0, 1, n), g, "folded ciphertexts")
+    err = float(np.max(np.abs(vals - _plain(w, ip, counts))))
+    assert err < _tol(w, counts), f"decrypted fold off the plain values by {err}"
+
+
+def test_fold_share_workload_at_full_size():
+    """The share workload's fold (1,024 score ciphertexts at 2^14, blocks of 512, k = 16) in the launch
+    configuration the benchmark times: its first two folded ciphertexts (group 0, and group 1 with the
+    rotation by 16 of its sum) equal the oracle's fold of the first 32 score ciphertexts residue by residue
+    (hashes in tests/golden/fold_paper.json); every folded ciphertext decrypts to the plain folded values."""
+    w = S.FOLD_SHARE
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "fold_paper.json")))[w.name + "_head"]
+    _say(f"[gpu-fold] {w.name}: library")
+    fk, ct, out, vals, ip, counts = _run(w)
+    n = 1 << w.log_n
+    groups = w.blocks * -(-w.rho // w.k)
+    assert list(H.hfe_shape(out))[:3] == [0, groups, n]
+    head = H.hfe_export(out, 0, 0, 2 * 2 * n).view(np.int64).reshape(2, 2, 1, n)
+    _assert_matches("out", head, g, "first two folded ciphertexts")
     err = float(np.max(np.abs(vals - _plain(w, ip, counts))))
     assert err < _tol(w, counts), f"decrypted fold off the plain values by {err}"
 
