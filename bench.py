@@ -628,19 +628,21 @@ def fold_modmuls(w: S.FoldWorkload):
     """Modular products of the f stage of one fold (all ciphertexts), counted from its operations: a
     transform of degree N is N/2 log N butterflies of one product (an inverse adds N for its 1/N).
     A product of ciphertexts at level l: the tensor's a_x a_y and the digit factor on l + 1 inverse
-    transforms, (l + 2)(l + 1) forward transforms of the digits with two key products per coefficient,
-    two inverse transforms at p, 2 (l + 1) forward transforms with p^-1 and the tensor terms b_x b_y,
-    a_x b_y + a_y b_x (four products per coefficient over both parts), then a rescale (two inverse and
-    2 l forward transforms with one product per coefficient).  A constant term rescaled from level 3 to
-    `to`: two inverse transforms of the constant times the last slot, 2 (to + 1) forward transforms with two
-    products per coefficient."""
+    transforms, (l + 2)(l + 1) forward transforms of the digits with two key products per coefficient, two
+    inverse transforms at p; rescaled, the sums and p (d0, d1) are divided by p q_l in one rounding: two
+    inverse transforms at q_l with the tensor at q_l, p d and the CRT (7 products per coefficient over both
+    parts), and 2 l forward transforms with (p q_l)^-1, the tensor and q_l^-1 (7 per coefficient and slot over
+    both parts); unrescaled, 2 (l + 1) forward transforms with p^-1 and the tensor (5 per coefficient and
+    slot).  A constant term rescaled from level 3 to `to`: two inverse transforms of the constant times the
+    last slot, 2 (to + 1) forward transforms with two products per coefficient."""
     n, lg = 1 << w.log_n, w.log_n
     fwd, inv = n // 2 * lg, n // 2 * lg + n
 
     def mul(l, rescaled=True):
-        ks = ((l + 1) * (inv + 2 * n) + (l + 2) * (l + 1) * (fwd + 2 * n) + 2 * inv
-              + 2 * (l + 1) * (fwd + n) + (l + 1) * 4 * n)
-        return ks + ((2 * inv + 2 * l * (fwd + n)) if rescaled else 0)
+        sums = (l + 1) * (inv + 2 * n) + (l + 2) * (l + 1) * (fwd + 2 * n) + 2 * inv
+        if rescaled:
+            return sums + 2 * inv + 7 * n + 2 * l * fwd + 7 * l * n
+        return sums + 2 * (l + 1) * fwd + 5 * (l + 1) * n
 
     def const(to):
         return 2 * (inv + n) + 2 * (to + 1) * (fwd + 2 * n)

@@ -29,7 +29,9 @@ Parameters (the paper fixes degree, depth, scale and key weight; the rest are re
   key-switching error is far below the scale), and brings the folded sum to level 0, scale F = 2^24
   Rot_{r k + r'} = Rot_{r k} o Rot_{r'}: the k - 1 rotations inside a group, then one by r k on the sum
   key switching: one digit per prime, d_i = [a (Q_l / q_i)^-1]_{q_i}, keys
-  K_i = (k_i, -k_i s + p (Q_l / q_i) s_from + e_i) mod Q_l p, then RS_p (as for FormatSwitch)
+  K_i = (k_i, -k_i s + p (Q_l / q_i) s_from + e_i) mod Q_l p, then RS_p (as for FormatSwitch); a product
+  that is rescaled divides p (d0, d1) + sum_i d_i K_i by p q_l in one rounding (RS_{p q_l}) instead of
+  RS_p and then RS_{q_l}
 
 Encoding.  Ecd rounds the real polynomial whose slots are the given values, (2/N) sum_j z_j
 cos(pi i g_j / N) with g_j = 5^j mod 2N, to integers.  It is computed as a length-N/2 inverse DFT
@@ -370,8 +372,8 @@ def mul_plain(ct: Ct, m: np.ndarray) -> Ct:
     return (l, {z: negmul_mod(m % z, b[z], z) for z in b}, {z: negmul_mod(m % z, a[z], z) for z in a})
 
 
-def key_switch(P: FoldParams, level: int, x: Dict[int, np.ndarray], key) -> Tuple[Dict, Dict]:
-    """(B, A) with B + A s = x s_from + small: RS_p(sum_i d_i K_i), d_i = [x (Q_l/q_i)^-1]_{q_i}."""
+def key_switch_sums(P: FoldParams, level: int, x: Dict[int, np.ndarray], key) -> Tuple[Dict, Dict]:
+    """sum_i d_i K_i modulo Q_l p, d_i = [x (Q_l/q_i)^-1]_{q_i}: (B, A) before the division by p."""
     primes = P.moduli(level)
     Ql = P.Q(level)
     dig = [mulc(x[qi], pow((Ql // qi) % qi, -1, qi), qi) for qi in primes]
@@ -384,11 +386,38 @@ def key_switch(P: FoldParams, level: int, x: Dict[int, np.ndarray], key) -> Tupl
             acc_a = (acc_a + negmul_mod(dig[i] % z, ka, z)) % z
             acc_b = (acc_b + negmul_mod(dig[i] % z, beta, z)) % z
         A[z], B[z] = acc_a, acc_b
+    return B, A
+
+
+def key_switch(P: FoldParams, level: int, x: Dict[int, np.ndarray], key) -> Tuple[Dict, Dict]:
+    """(B, A) with B + A s = x s_from + small: RS_p(sum_i d_i K_i), d_i = [x (Q_l/q_i)^-1]_{q_i}."""
+    primes = P.moduli(level)
+    B, A = key_switch_sums(P, level, x, key)
     return rescale_by(B, P.p, primes), rescale_by(A, P.p, primes)
 
 
+def rescale_by_two(res: Dict[int, np.ndarray], p: int, ql: int, keep: List[int]) -> Dict[int, np.ndarray]:
+    """RS_{p q_l}: floor(x / (p q_l) + 1/2) on residues over keep + [q_l, p]: the centered value c of x modulo
+    D = p q_l by the CRT of its residues modulo p and q_l, then (x_z - c) D^-1 mod z for z in keep."""
+    D = p * ql
+    pinv = pow(p, -1, ql)
+    c = []
+    for a, b in zip(res[p], res[ql]):
+        v = int(a) + p * ((int(b) - int(a)) * pinv % ql)      # = a mod p, = b mod q_l, in [0, D)
+        c.append(centered(v, D))
+    c = np.array(c, dtype=object)
+    out = {}
+    for z in keep:
+        inv = pow(D % z, -1, z)
+        out[z] = np.array([(int(x) - int(cv)) * inv % z for x, cv in zip(res[z], c)], dtype=np.int64)
+    return out
+
+
 def mul(FK: FoldKeys, ct1: Ct, ct2: Ct, rescaled: bool = True) -> Ct:
-    """Product with relinearisation, then (by default) RS by the level's last prime."""
+    """Product with relinearisation.  Rescaled (the default): the key switch's sums and the tensor's d0, d1
+    times p are divided by p q_l in one rounding, RS_{p q_l}(p (d0, d1) + sum_i d_i K_i), which lands at level
+    l - 1 as RS_{q_l} of the relinearised product does; otherwise the relinearised product at level l,
+    (d0, d1) + RS_p(sum_i d_i K_i)."""
     P = FK.P
     l, b1, a1 = ct1
     l2, b2, a2 = ct2
@@ -398,9 +427,16 @@ def mul(FK: FoldKeys, ct1: Ct, ct2: Ct, rescaled: bool = True) -> Ct:
         d0[z] = negmul_mod(b1[z], b2[z], z)
         d1[z] = (negmul_mod(a1[z], b2[z], z) + negmul_mod(a2[z], b1[z], z)) % z
         d2[z] = negmul_mod(a1[z], a2[z], z)
-    B, A = key_switch(P, l, d2, FK.relin[l])
-    out = (l, {z: (d0[z] + B[z]) % z for z in d0}, {z: (d1[z] + A[z]) % z for z in d1})
-    return rescale(P, out) if rescaled else out
+    if not rescaled:
+        B, A = key_switch(P, l, d2, FK.relin[l])
+        return (l, {z: (d0[z] + B[z]) % z for z in d0}, {z: (d1[z] + A[z]) % z for z in d1})
+    B, A = key_switch_sums(P, l, d2, FK.relin[l])
+    primes = P.moduli(l)
+    XB = {z: (B[z] + mulc(d0[z], P.p, z)) % z for z in primes}
+    XA = {z: (A[z] + mulc(d1[z], P.p, z)) % z for z in primes}
+    XB[P.p], XA[P.p] = B[P.p], A[P.p]
+    keep = primes[:-1]
+    return (l - 1, rescale_by_two(XB, P.p, P.q[l], keep), rescale_by_two(XA, P.p, P.q[l], keep))
 
 
 def rotate(FK: FoldKeys, ct: Ct, r: int) -> Ct:

@@ -380,12 +380,13 @@ hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out, const R
   return HFE_OK;
 }
 
-// Key switch at level l: digits of the polynomial src (item stride si, slots 0 .. l at stride N), or of the
-// product src y (the a parts of a tensor) when y is given; the result RS_p(sum_i d_i K_i) plus the addends
-// that `tail` names goes to tail.out.  keys + kidx[item] * kstride is the item's key.
-hfe_status key_switch(const Ev& e, int l, const uint64_t* src, const uint64_t* y, int64_t si, const double* keys,
-                      int64_t kstride, const int32_t* kidx, FoldLift tail) {
-  DevBuf dig, acc, accp;
+// The sums of a key switch at level l: digits of the polynomial src (item stride si, slots 0 .. l at stride
+// N), or of the product src y (the a parts of a tensor) when y is given; acc [n][2][l+1][N] the sums at
+// q_0 .. q_l (NTT domain), accp [n][2][N] the sums at p, centered (coefficients).  keys + kidx[item] * kstride
+// is the item's key.
+hfe_status ks_sums(const Ev& e, int l, const uint64_t* src, const uint64_t* y, int64_t si, const double* keys,
+                   int64_t kstride, const int32_t* kidx, DevBuf& acc, DevBuf& accp) {
+  DevBuf dig;
   HFE_TRY(dig.alloc((size_t)e.n * (l + 1) * e.N * 8, e.s));
   HFE_TRY(acc.alloc((size_t)e.n * 2 * (l + 1) * e.N * 8, e.s));
   HFE_TRY(accp.alloc((size_t)e.n * 2 * e.N * 8, e.s));
@@ -410,6 +411,14 @@ hfe_status key_switch(const Ev& e, int l, const uint64_t* src, const uint64_t* y
   FD_LAUNCH(launch_fold_inv(e.C, ia, e.n, e.s));
   FD_LAUNCH(launch_fold_ks_mac(e.C, l, dig.as<uint64_t>(), keys, kstride, kidx, acc.as<uint64_t>(),
                                accp.as<int64_t>(), e.n, e.s));
+  return HFE_OK;
+}
+
+// Key switch at level l (see ks_sums): RS_p of the sums plus the addends that `tail` names, to tail.out.
+hfe_status key_switch(const Ev& e, int l, const uint64_t* src, const uint64_t* y, int64_t si, const double* keys,
+                      int64_t kstride, const int32_t* kidx, FoldLift tail) {
+  DevBuf acc, accp;
+  HFE_TRY(ks_sums(e, l, src, y, si, keys, kstride, kidx, acc, accp));
   tail.cen = accp.as<int64_t>();
   tail.x = acc.as<uint64_t>();
   tail.xi = 2 * (l + 1) * e.N;
@@ -422,9 +431,10 @@ hfe_status key_switch(const Ev& e, int l, const uint64_t* src, const uint64_t* y
   return HFE_OK;
 }
 
-// x y with relinearisation at level l (the tensor's d2 formed in the digit pass, d0 and d1 in the key
-// switch's last pass), then RS by q_l: out [n][2][l][N] plus add2 (level l - 1); rescaled = false: the
-// relinearised product itself, [n][2][l + 1][N], plus add2 (level l).
+// x y with relinearisation at level l (the tensor's d2 formed in the digit pass, d0 and d1 in the last
+// pass).  Rescaled (the default): p (d0, d1) plus the key switch's sums divided by p q_l in one rounding,
+// out [n][2][l][N], plus add2 (level l - 1); otherwise the relinearised product (d0, d1) + RS_p(sums),
+// [n][2][l + 1][N], plus add2 (level l).
 hfe_status mul(const Ev& e, const uint64_t* x, const uint64_t* y, int l, uint64_t* out, bool rescaled = true,
                const uint64_t* add2 = nullptr) {
   const int64_t per = (l + 1) * e.N;
@@ -434,10 +444,10 @@ hfe_status mul(const Ev& e, const uint64_t* x, const uint64_t* y, int l, uint64_
   tail.ty = y;
   tail.ti = 2 * per;
   tail.tp = per;
-  tail.oi = 2 * per;
-  tail.op = per;
+  tail.out = out;
   if (!rescaled) {
-    tail.out = out;
+    tail.oi = 2 * per;
+    tail.op = per;
     if (add2) {
       tail.add2 = add2;
       tail.a2i = 2 * per;
@@ -445,13 +455,34 @@ hfe_status mul(const Ev& e, const uint64_t* x, const uint64_t* y, int l, uint64_
     }
     return key_switch(e, l, x + per, y + per, 2 * per, key, 0, nullptr, tail);
   }
-  DevBuf t;
-  HFE_TRY(t.alloc((size_t)ct_words(e, l) * 8, e.s));
-  tail.out = t.as<uint64_t>();
-  HFE_TRY(key_switch(e, l, x + per, y + per, 2 * per, key, 0, nullptr, tail));
-  RsOpts o;
-  o.add2 = add2;
-  return rescale(e, t.as<uint64_t>(), l, out, o);
+  DevBuf acc, accp, cen;
+  HFE_TRY(ks_sums(e, l, x + per, y + per, 2 * per, key, 0, nullptr, acc, accp));
+  HFE_TRY(cen.alloc((size_t)e.n * 2 * e.N * 8, e.s));
+  FD_LAUNCH(launch_fold_relin_center(e.C, l, acc.as<uint64_t>(), accp.as<int64_t>(), x, y, e.n, cen.as<int64_t>(),
+                                     e.s));
+  const int64_t po = l * e.N;  // the output's slots q_0 .. q_{l-1}
+  tail.cen = cen.as<int64_t>();
+  tail.x = acc.as<uint64_t>();
+  tail.xi = 2 * per;
+  tail.xp = per;
+  tail.oi = 2 * po;
+  tail.op = po;
+  if (add2) {
+    tail.add2 = add2;
+    tail.a2i = 2 * po;
+    tail.a2p = po;
+  }
+  tail.zm = slots_upto(l - 1, false);
+  tail.nsl = l;
+  tail.has_tscale = 1;
+  const uint64_t p = e.C.mod[5].q, ql = e.C.mod[l].q;
+  for (int j = 0; j < l; ++j) {
+    const uint64_t qj = e.C.mod[j].q;
+    tail.inv.v[j] = (double)inv_mod(mm(p % qj, ql % qj, qj), qj);  // (p q_l)^-1
+    tail.tscale.v[j] = (double)inv_mod(ql % qj, qj);               // p (d0, d1) (p q_l)^-1 = (d0, d1) q_l^-1
+  }
+  FD_LAUNCH(launch_fold_lift(e.C, tail, e.n, e.s));
+  return HFE_OK;
 }
 
 // RS(k x) at level l -> level l - 1, kept at the slots of level `to` (a mod-drop), then + c.

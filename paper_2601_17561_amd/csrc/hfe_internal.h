@@ -759,6 +759,8 @@ struct FoldLift {
   const uint64_t* tx = nullptr;          // tensor addend of tx, ty (item stride ti, part stride tp)
   const uint64_t* ty = nullptr;
   int64_t ti = 0, tp = 0;
+  int has_tscale = 0;
+  SlotFactor tscale{};                   // tensor addend times tscale[s] (a rescale by p q_l: q_l^-1)
   SlotFactor cres{};                     // constant added to part 0
   uint64_t* out = nullptr;
   int64_t oi = 0, op = 0;
@@ -821,6 +823,8 @@ hipError_t launch_fold_inv(const FoldConsts& C, const FoldInv& a, int64_t items,
 hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const uint64_t* dig, const double* keys, int64_t kstride,
                               const int32_t* kidx, uint64_t* acc, int64_t* accp, int64_t items, hipStream_t s);
 hipError_t launch_fold_lift(const FoldConsts& C, const FoldLift& a, int64_t items, hipStream_t s);
+hipError_t launch_fold_relin_center(const FoldConsts& C, int level, const uint64_t* acc, const int64_t* accp,
+                                   const uint64_t* tx, const uint64_t* ty, int64_t items, int64_t* cen, hipStream_t s);
 hipError_t launch_fold_mul_pt(const FoldConsts& C, const uint64_t* ct, const uint64_t* pt, uint64_t* out,
                               int64_t items, int nsl, hipStream_t s);
 hipError_t launch_fold_perm(const FoldConsts& C, const uint64_t* x, const int32_t* src, const int32_t* amt,

@@ -234,15 +234,62 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLif
     if (a2) v = addmod_d(v, to_d(a2[t]), zd);
     if (tx) {
       const double bx = to_d(tx[t]), by = to_d(ty[t]);
+      double d;
       if (part == 0) {
-        v = addmod_d(v, mm_d(bx, by, z, C), zd);
+        d = mm_d(bx, by, z, C);
       } else {
         const double ax = to_d(tx[a.tp + t]), ay = to_d(ty[a.tp + t]);
-        v = addmod_d(v, addmod_d(mm_d(ax, by, z, C), mm_d(ay, bx, z, C), zd), zd);
+        d = addmod_d(mm_d(ax, by, z, C), mm_d(ay, bx, z, C), zd);
       }
+      if (a.has_tscale) d = mm_d(d, a.tscale.v[s], z, C);
+      v = addmod_d(v, d, zd);
     }
     v = addmod_d(v, kc, zd);
     o[t] = to_u(v);
+  }
+}
+
+// The end of a relinearised product divided by p q_l in one rounding: job = item * 2 + part,
+// X = acc[item][part][l] + (p mod q_l) d (d the tensor's d0 or d1 at slot l, formed from tx, ty), its
+// inverse transform r (mod q_l), and the value c = a + p ((r - a) p^-1 mod q_l) (a = accp, centered mod p),
+// the representative of X modulo D = p q_l, centered: cen[item][part][t].
+__global__ void __launch_bounds__(kNttThreads) k_fold_relin_center(FoldConsts C, int level, const uint64_t* acc,
+                                                                 const int64_t* accp, const uint64_t* tx,
+                                                                 const uint64_t* ty, double p_l, double pinv_l,
+                                                                 int64_t D, int64_t* cen) {
+  extern __shared__ double lds[];
+  const int n = 1 << C.logn;
+  const int64_t ip = blockIdx.x;
+  const int64_t item = ip >> 1;
+  const int part = (int)(ip & 1);
+  const int l = level;
+  const int64_t per = (int64_t)(l + 1) * n;
+  const uint64_t* x = acc + ip * per + (int64_t)l * n;
+  const uint64_t* bx = tx + item * 2 * per + (int64_t)l * n;
+  const uint64_t* by = ty + item * 2 * per + (int64_t)l * n;
+  const double zd = C.zd[l];
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    double d;
+    if (part == 0) {
+      d = mm_d(to_d(bx[t]), to_d(by[t]), l, C);
+    } else {
+      d = addmod_d(mm_d(to_d(bx[per + t]), to_d(by[t]), l, C), mm_d(to_d(by[per + t]), to_d(bx[t]), l, C), zd);
+    }
+    lds[t] = addmod_d(to_d(x[t]), mm_d(d, p_l, l, C), zd);
+  }
+  __syncthreads();
+  ntt_inv_lds_c(lds, C.tab[l]);
+  const Mod ml = C.mod[l];
+  const int64_t p = (int64_t)C.mod[5].q;
+  const int64_t* ap = accp + ip * n;
+  int64_t* o = cen + ip * n;
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const int64_t a = ap[t];
+    const double am = to_d(from_signed(a, ml.q, ml.mu));
+    const double u = mm_d(submod_d(lds[t], am, zd), pinv_l, l, C);  // (r - a) p^-1 mod q_l
+    int64_t v = a + p * (int64_t)u;                                  // in (-p/2, D): |v| < 2^60
+    if (v > D / 2) v -= D;
+    o[t] = v;
   }
 }
 
@@ -496,6 +543,19 @@ hipError_t launch_fold_lift(const FoldConsts& C, const FoldLift& a, int64_t item
   hipError_t e = allow_lds(k_fold_lift, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fold_lift, dim3((unsigned)(items * 2 * a.nsl)), dim3(ntt_block(C.logn)), lds, s, C, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_relin_center(const FoldConsts& C, int level, const uint64_t* acc, const int64_t* accp,
+                                   const uint64_t* tx, const uint64_t* ty, int64_t items, int64_t* cen, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) << C.logn;
+  hipError_t e = allow_lds(k_fold_relin_center, lds);
+  if (e != hipSuccess) return e;
+  const uint64_t ql = C.mod[level].q, p = C.mod[5].q;
+  const double p_l = (double)(p % ql), pinv_l = (double)inv_mod(p % ql, ql);
+  hipLaunchKernelGGL(k_fold_relin_center, dim3((unsigned)(items * 2)), dim3(ntt_block(C.logn)), lds, s, C, level, acc,
+                     accp, tx, ty, p_l, pinv_l, (int64_t)(p * ql), cen);
   return hipGetLastError();
 }
 

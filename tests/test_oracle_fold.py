@@ -9,7 +9,7 @@ Each step is checked against something other than itself:
   * the sparse secret's weight and values;
   * key switching by the decryption equation with numpy.polymul products (not oracle.bigmul), the
     same small error modulo every prime;
-  * RS by Fraction rounding of the CRT value;
+  * RS, and the relinearised product's single RS by p q_l, by Fraction rounding of the CRT value;
   * products, rotations, f and the whole fold by decryption against the plain values (Appendix C.2's
     polynomial evaluated by numpy.polyval), within bounds derived from the noise.
 """
@@ -134,6 +134,33 @@ def test_rescale_rounds_to_nearest(keys):
             x += int(res[z][t]) * Mi * pow(Mi, -1, z)
         x = F.centered(x, Q)
         want = Fraction(x, primes[-1])
+        rounded = int(want + Fraction(1, 2)) if want >= 0 else -int(-want + Fraction(1, 2))
+        if abs(want - int(want)) == Fraction(1, 2):
+            continue
+        for z in primes[:-1]:
+            assert int(out[z][t]) == rounded % z
+
+
+def test_rescale_by_p_q_rounds_to_nearest(keys):
+    """RS_{p q_l} of a relinearised product (one division by the composite p q_3) against Fraction rounding
+    of the CRT value over q_0 .. q_3 and p."""
+    P = keys.P
+    rng = np.random.default_rng(6)
+    primes = P.moduli(3)
+    mods = primes + [P.p]
+    res = {z: rng.integers(0, z, 16) for z in mods}
+    out = F.rescale_by_two(res, P.p, primes[-1], primes[:-1])
+    M = 1
+    for z in mods:
+        M *= z
+    D = P.p * primes[-1]
+    for t in range(16):
+        x = 0
+        for z in mods:
+            Mi = M // z
+            x += int(res[z][t]) * Mi * pow(Mi, -1, z)
+        x = F.centered(x, M)
+        want = Fraction(x, D)
         rounded = int(want + Fraction(1, 2)) if want >= 0 else -int(-want + Fraction(1, 2))
         if abs(want - int(want)) == Fraction(1, 2):
             continue
