@@ -633,8 +633,9 @@ def fold_modmuls(w: S.FoldWorkload):
     inverse transforms at q_l with the tensor at q_l, p d and the CRT (7 products per coefficient over both
     parts), and 2 l forward transforms with (p q_l)^-1, the tensor and q_l^-1 (7 per coefficient and slot over
     both parts); unrescaled, 2 (l + 1) forward transforms with p^-1 and the tensor (5 per coefficient and
-    slot).  A constant term rescaled from level 3 to `to`: two inverse transforms of the constant times the
-    last slot, 2 (to + 1) forward transforms with two products per coefficient."""
+    slot).  The constant terms share two inverse transforms of x's last slot (k x_3 transforms to k u); each,
+    rescaled from level 3 to `to`, takes k u (2 products per coefficient) and 2 (to + 1) forward transforms
+    with two products per coefficient."""
     n, lg = 1 << w.log_n, w.log_n
     fwd, inv = n // 2 * lg, n // 2 * lg + n
 
@@ -645,9 +646,9 @@ def fold_modmuls(w: S.FoldWorkload):
         return sums + 2 * (l + 1) * fwd + 5 * (l + 1) * n
 
     def const(to):
-        return 2 * (inv + n) + 2 * (to + 1) * (fwd + 2 * n)
+        return 2 * n + 2 * (to + 1) * (fwd + 2 * n)
 
-    f = mul(3) + const(2) + const(2) + const(1) + const(1) + 3 * mul(2) + mul(1, rescaled=False)
+    f = mul(3) + 2 * inv + const(2) + const(2) + const(1) + const(1) + 3 * mul(2) + mul(1, rescaled=False)
     return w.count * f
 
 

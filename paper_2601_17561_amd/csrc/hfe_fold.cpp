@@ -314,31 +314,14 @@ struct Ev {
 
 int64_t ct_words(const Ev& e, int l) { return e.n * 2 * (l + 1) * e.N; }
 
-// A ciphertext array at level l in the fold's layout [n][b | a][slot][N].
-struct View {
-  const uint64_t* p = nullptr;
-  int l = 0;
-};
-
 SlotFactor const_res(const FoldConsts& C, int64_t k, int nsl) {
   SlotFactor r{};
   for (int j = 0; j < nsl; ++j) r.v[j] = (double)residue(k, C.mod[j].q);
   return r;
 }
 
-// Options of a rescale: x times k first (a constant), keep only slots 0 .. to (a mod-drop), add c to b and
-// add2 (an array at level `to`) to the result.
-struct RsOpts {
-  bool has_k = false;
-  int64_t k = 1;
-  int to = -1;  // -1: l - 1
-  int64_t c = 0;
-  const uint64_t* add2 = nullptr;
-};
-
-// RS by q_l: x [n][2][l+1][N] -> out [n][2][to+1][N].
-hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out, const RsOpts& o = RsOpts()) {
-  const int to = o.to < 0 ? l - 1 : o.to;
+// RS by q_l: x [n][2][l+1][N] -> out [n][2][l][N].
+hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out) {
   DevBuf cen;
   HFE_TRY(cen.alloc((size_t)e.n * 2 * e.N * 8, e.s));
   FoldInv ia;
@@ -347,10 +330,6 @@ hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out, const R
   ia.zm.z[0] = (int8_t)l;
   ia.nsl = 1;
   ia.mode = 1;
-  if (o.has_k) {
-    ia.has_pre = 1;
-    ia.pre.v[0] = (double)residue(o.k, e.C.mod[l].q);
-  }
   ia.dst = cen.ptr;
   ia.di = e.N;
   FD_LAUNCH(launch_fold_inv(e.C, ia, e.n * 2, e.s));
@@ -359,23 +338,13 @@ hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out, const R
   la.x = x;
   la.xi = 2 * (l + 1) * e.N;
   la.xp = (l + 1) * e.N;
-  if (o.has_k) {
-    la.has_xmul = 1;
-    la.xmul = const_res(e.C, o.k, to + 1);
-  }
-  la.cres = const_res(e.C, o.c, to + 1);
-  if (o.add2) {
-    la.add2 = o.add2;
-    la.a2i = 2 * (to + 1) * e.N;
-    la.a2p = (to + 1) * e.N;
-  }
   la.out = out;
-  la.oi = 2 * (to + 1) * e.N;
-  la.op = (to + 1) * e.N;
-  la.zm = slots_upto(to, false);
-  la.nsl = to + 1;
+  la.oi = 2 * l * e.N;
+  la.op = l * e.N;
+  la.zm = slots_upto(l - 1, false);
+  la.nsl = l;
   const uint64_t ql = e.C.mod[l].q;
-  for (int j = 0; j <= to; ++j) la.inv.v[j] = (double)inv_mod(ql % e.C.mod[j].q, e.C.mod[j].q);
+  for (int j = 0; j < l; ++j) la.inv.v[j] = (double)inv_mod(ql % e.C.mod[j].q, e.C.mod[j].q);
   FD_LAUNCH(launch_fold_lift(e.C, la, e.n, e.s));
   return HFE_OK;
 }
@@ -485,15 +454,31 @@ hfe_status mul(const Ev& e, const uint64_t* x, const uint64_t* y, int l, uint64_
   return HFE_OK;
 }
 
-// RS(k x) at level l -> level l - 1, kept at the slots of level `to` (a mod-drop), then + c.
-hfe_status const_term(const Ev& e, const uint64_t* x, int l, int64_t k, int to, int64_t c, DevBuf& out) {
+// RS(k x) at level l -> level l - 1, kept at the slots of level `to` (a mod-drop), then + c.  u: the
+// residues of x's last slot in coefficients, [n][2][N] (shared by the constants: the transform of k x_l is
+// k times that of x_l).
+hfe_status const_term(const Ev& e, const uint64_t* x, const uint64_t* u, int l, int64_t k, int to, int64_t c,
+                      DevBuf& out) {
   HFE_TRY(out.alloc((size_t)ct_words(e, to) * 8, e.s));
-  RsOpts o;
-  o.has_k = true;
-  o.k = k;
-  o.to = to;
-  o.c = c;
-  return rescale(e, x, l, out.as<uint64_t>(), o);
+  FoldLift la;
+  la.ures = u;
+  la.cl = l;
+  la.ku = (double)residue(k, e.C.mod[l].q);
+  la.x = x;
+  la.xi = 2 * (l + 1) * e.N;
+  la.xp = (l + 1) * e.N;
+  la.has_xmul = 1;
+  la.xmul = const_res(e.C, k, to + 1);
+  la.cres = const_res(e.C, c, to + 1);
+  la.out = out.as<uint64_t>();
+  la.oi = 2 * (to + 1) * e.N;
+  la.op = (to + 1) * e.N;
+  la.zm = slots_upto(to, false);
+  la.nsl = to + 1;
+  const uint64_t ql = e.C.mod[l].q;
+  for (int j = 0; j <= to; ++j) la.inv.v[j] = (double)inv_mod(ql % e.C.mod[j].q, e.C.mod[j].q);
+  FD_LAUNCH(launch_fold_lift(e.C, la, e.n, e.s));
+  return HFE_OK;
 }
 
 // Rotations at level 1 of the items src[u] of x ([.][2][2][N]) by the amounts with key index amt[u]
@@ -558,10 +543,22 @@ hfe_status fold_impl(const hfe_foldkeys* F, const hfe_fct* in, const int32_t* co
   DevBuf x2, x4, L0, L1, L2, L3, inner, t1, f;
   HFE_TRY(x2.alloc((size_t)ct_words(e, 2) * 8, s));
   HFE_TRY(mul(e, x3.as<uint64_t>(), x3.as<uint64_t>(), 3, x2.as<uint64_t>()));
-  HFE_TRY(const_term(e, x3.as<uint64_t>(), 3, k[7], 2, k[6], L3));
-  HFE_TRY(const_term(e, x3.as<uint64_t>(), 3, k[3], 2, k[2], L1));
-  HFE_TRY(const_term(e, x3.as<uint64_t>(), 3, k[5], 1, k[4], L2));
-  HFE_TRY(const_term(e, x3.as<uint64_t>(), 3, k[1], 1, k[0], L0));
+  {
+    DevBuf u3;  // x's slot q_3 in coefficients, for the four constant terms
+    HFE_TRY(u3.alloc((size_t)n * 2 * N * 8, s));
+    FoldInv ia;
+    ia.src = x3.as<uint64_t>() + 3 * N;
+    ia.si = 4 * N;
+    ia.zm.z[0] = 3;
+    ia.nsl = 1;
+    ia.dst = u3.ptr;
+    ia.di = N;
+    FD_LAUNCH(launch_fold_inv(C, ia, n * 2, s));
+    HFE_TRY(const_term(e, x3.as<uint64_t>(), u3.as<uint64_t>(), 3, k[7], 2, k[6], L3));
+    HFE_TRY(const_term(e, x3.as<uint64_t>(), u3.as<uint64_t>(), 3, k[3], 2, k[2], L1));
+    HFE_TRY(const_term(e, x3.as<uint64_t>(), u3.as<uint64_t>(), 3, k[5], 1, k[4], L2));
+    HFE_TRY(const_term(e, x3.as<uint64_t>(), u3.as<uint64_t>(), 3, k[1], 1, k[0], L0));
+  }
   x3.reset();
   HFE_TRY(x4.alloc((size_t)ct_words(e, 1) * 8, s));
   HFE_TRY(mul(e, x2.as<uint64_t>(), x2.as<uint64_t>(), 2, x4.as<uint64_t>()));

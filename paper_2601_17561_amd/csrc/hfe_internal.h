@@ -748,6 +748,9 @@ struct FoldInv {
 // A lift pass of the fold (k_fold_lift), see k_fold.hip.
 struct FoldLift {
   const int64_t* cen = nullptr;          // [item][part][N] centered values of the divided-out modulus
+  const uint64_t* ures = nullptr;        // or residues u mod q_cl, [item][part][N]: cen = centered(ku u mod q_cl)
+  int cl = 0;
+  double ku = 0.0;
   const uint64_t* x = nullptr;           // kept residues, item stride xi, part stride xp, slot stride N
   int64_t xi = 0, xp = 0;
   int has_xmul = 0;

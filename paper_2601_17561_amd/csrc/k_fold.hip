@@ -200,7 +200,8 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
 }
 
 // job = (item * 2 + part) * nsl + s, slot z = zm.z[s]:
-// out = (x xmul[s] - NTT_z(cen mod z)) inv[s] + addends mod z, with cen = cen[(item * 2 + part) * N + t].
+// out = (x xmul[s] - NTT_z(cen mod z)) inv[s] + addends mod z, with cen = cen[(item * 2 + part) * N + t], or
+// cen = the centered k u mod q_cl from the residues u = ures[(item * 2 + part) * N + t] when ures is given.
 // Addends: add (part 0 only when ap = 0), add2 (both parts), the tensor terms of tx and ty (part 0: b_x b_y,
 // part 1: a_x b_y + a_y b_x) and the constant cres on part 0.
 __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLift a) {
@@ -212,8 +213,18 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLif
   const int part = (int)(ip & 1);
   const int z = a.zm.z[s];
   const Mod md = C.mod[z];
-  const int64_t* c = a.cen + ip * n;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(c[t], md.q, md.mu));
+  if (a.ures) {  // the centered value of k u mod q_cl from the residues u (a constant's rescale)
+    const uint64_t* u = a.ures + ip * n;
+    const int cl = a.cl;
+    const uint64_t qc = C.mod[cl].q;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      const int64_t cv = centered(to_u(mm_d(to_d(u[t]), a.ku, cl, C)), qc);
+      lds[t] = to_d(from_signed(cv, md.q, md.mu));
+    }
+  } else {
+    const int64_t* c = a.cen + ip * n;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(c[t], md.q, md.mu));
+  }
   __syncthreads();
   ntt_fwd_lds_c(lds, C.tab[z]);  // signed, below 8.1z
   const int64_t so = (int64_t)s * n;
