@@ -628,8 +628,9 @@ def fold_modmuls(w: S.FoldWorkload):
     """Modular products of the f stage of one fold (all ciphertexts), counted from its operations: a
     transform of degree N is N/2 log N butterflies of one product (an inverse adds N for its 1/N).
     A product of ciphertexts at level l: the tensor's a_x a_y and the digit factor on l + 1 inverse
-    transforms, (l + 2)(l + 1) forward transforms of the digits with two key products per coefficient, two
-    inverse transforms at p; rescaled, the sums and p (d0, d1) are divided by p q_l in one rounding: two
+    transforms, (l + 1)^2 forward transforms of the digits (none at a digit's own prime, where the tensor
+    and the factor are taken again: two products per coefficient), two key products per coefficient for
+    each of the (l + 2)(l + 1) digit and prime pairs, two inverse transforms at p; rescaled, the sums and p (d0, d1) are divided by p q_l in one rounding: two
     inverse transforms at q_l with the tensor at q_l, p d and the CRT (7 products per coefficient over both
     parts), and 2 l forward transforms with (p q_l)^-1, the tensor and q_l^-1 (7 per coefficient and slot over
     both parts); unrescaled, 2 (l + 1) forward transforms with p^-1 and the tensor (5 per coefficient and
@@ -640,7 +641,7 @@ def fold_modmuls(w: S.FoldWorkload):
     fwd, inv = n // 2 * lg, n // 2 * lg + n
 
     def mul(l, rescaled=True):
-        sums = (l + 1) * (inv + 2 * n) + (l + 2) * (l + 1) * (fwd + 2 * n) + 2 * inv
+        sums = (l + 1) * (inv + 2 * n) + (l + 1) ** 2 * fwd + (l + 2) * (l + 1) * 2 * n + (l + 1) * 2 * n + 2 * inv
         if rescaled:
             return sums + 2 * inv + 7 * n + 2 * l * fwd + 7 * l * n
         return sums + 2 * (l + 1) * fwd + 5 * (l + 1) * n

@@ -378,7 +378,7 @@ hfe_status ks_sums(const Ev& e, int l, const uint64_t* src, const uint64_t* y, i
     ia.f.v[i] = (double)inv_mod(qhat, qi);
   }
   FD_LAUNCH(launch_fold_inv(e.C, ia, e.n, e.s));
-  FD_LAUNCH(launch_fold_ks_mac(e.C, l, dig.as<uint64_t>(), keys, kstride, kidx, acc.as<uint64_t>(),
+  FD_LAUNCH(launch_fold_ks_mac(e.C, l, ia, dig.as<uint64_t>(), keys, kstride, kidx, acc.as<uint64_t>(),
                                accp.as<int64_t>(), e.n, e.s));
   return HFE_OK;
 }

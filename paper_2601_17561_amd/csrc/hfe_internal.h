@@ -823,8 +823,9 @@ hipError_t launch_fold_encode(const int64_t* w, int64_t items, int logn, double 
 hipError_t launch_fold_fwd(const FoldConsts& C, const int64_t* src, int64_t si, int64_t ss, uint64_t* dst, int64_t di,
                            int64_t ds, const SlotMap& zm, int nsl, int64_t items, hipStream_t s);
 hipError_t launch_fold_inv(const FoldConsts& C, const FoldInv& a, int64_t items, hipStream_t s);
-hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const uint64_t* dig, const double* keys, int64_t kstride,
-                              const int32_t* kidx, uint64_t* acc, int64_t* accp, int64_t items, hipStream_t s);
+hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const FoldInv& dg, const uint64_t* dig, const double* keys,
+                              int64_t kstride, const int32_t* kidx, uint64_t* acc, int64_t* accp, int64_t items,
+                              hipStream_t s);
 hipError_t launch_fold_lift(const FoldConsts& C, const FoldLift& a, int64_t items, hipStream_t s);
 hipError_t launch_fold_relin_center(const FoldConsts& C, int level, const uint64_t* acc, const int64_t* accp,
                                    const uint64_t* tx, const uint64_t* ty, int64_t items, int64_t* cen, hipStream_t s);

@@ -137,21 +137,25 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, FoldInv 
 }
 
 // ------------------------------------------------------------------ key switching
-// job = item * (level + 2) + s, slot z = s (s <= level) or p (s = level + 1).  For each digit i <= level
+// job = s * items + item (slot-major: the blocks that run together share the slot's keys, (level + 1) pairs of
+// N doubles, which stay in each XCD's L2), slot z = s (s <= level) or p (s = level + 1).  For each digit i <= level
 // (dig[item][i][N], residues mod q_i): reduce mod z, forward NTT in LDS, multiply by the key's two
-// parts for (z, i) and accumulate in registers (R coefficients per thread and part).  The key of the
+// parts for (z, i) and accumulate in registers (R coefficients per thread and part).  At z = q_i the
+// digit's transform is the NTT-domain value it came from times its factor (src [times y] at slot i, times
+// dg.f[i], as the digit pass k_fold_inv with mode 2 describes it), taken directly.  The key of the
 // item is keys + kidx[item] * kstride (kidx NULL: key 0), laid out [s][i][2][N] doubles.  Slots of Q_l
 // store the NTT-domain sums to acc[item][part][s][N]; the special prime's sums are transformed back,
 // centered and stored to accp[item][part][N].
 template <int R>
-__global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int level, const uint64_t* dig,
-                                                           const double* keys, int64_t kstride, const int32_t* kidx,
-                                                           uint64_t* acc, int64_t* accp) {
+__global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int level, FoldInv dg,
+                                                           const uint64_t* dig, const double* keys, int64_t kstride,
+                                                           const int32_t* kidx, uint64_t* acc, int64_t* accp) {
   extern __shared__ double lds[];
   const int n = 1 << C.logn;
   const int nsl = level + 2;
-  const int64_t item = blockIdx.x / nsl;
-  const int s = blockIdx.x - (int)(item * nsl);
+  const int64_t items = gridDim.x / nsl;
+  const int s = (int)(blockIdx.x / items);
+  const int64_t item = blockIdx.x - s * items;
   const bool special = s == level + 1;
   const int z = special ? 5 : s;
   const Mod md = C.mod[z];
@@ -163,17 +167,36 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
 #pragma unroll
   for (int r = 0; r < R; ++r) ab[r] = aa[r] = 0.0;
   for (int i = 0; i <= level; ++i) {
-    const uint64_t* d = dig + (item * (level + 1) + i) * n;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(barrett64(d[t], md.q, md.mu));
-    __syncthreads();
-    ntt_fwd_lds_c(lds, C.tab[z]);
+    if (i == s) {  // the digit's own prime: its transform is the NTT-domain value it came from
+      const int64_t off = item * dg.si + i * dg.ss;
+      const uint64_t* x = dg.src + off;
+      const uint64_t* y = dg.y ? dg.y + off : nullptr;
+      const double f = dg.f.v[i];
+      for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        double v = to_d(x[t]);
+        if (y) v = mm_d(v, to_d(y[t]), z, C);
+        lds[t] = mm_d(v, f, z, C);
+      }
+      __syncthreads();
+    } else {
+      const uint64_t* d = dig + (item * (level + 1) + i) * n;
+      for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(barrett64(d[t], md.q, md.mu));
+      __syncthreads();
+      ntt_fwd_lds_c(lds, C.tab[z]);
+    }
     const double* kb = key + (int64_t)i * 2 * n;   // part 0: mask k_i, part 1: beta_i
+    // four coefficients at a time: the scheduler may not hoist more key loads, which with the 2R live
+    // sums would spill registers
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int t = threadIdx.x + r * blockDim.x;
-      const double v = lds[t];
-      aa[r] += mulmod_c_d(v, kb[t], zd, zi);
-      ab[r] += mulmod_c_d(v, kb[n + t], zd, zi);
+    for (int r0 = 0; r0 < R; r0 += 4) {
+#pragma unroll
+      for (int r = r0; r < r0 + 4 && r < R; ++r) {
+        const int t = threadIdx.x + r * blockDim.x;
+        const double v = lds[t];
+        aa[r] += mulmod_c_d(v, kb[t], zd, zi);
+        ab[r] += mulmod_c_d(v, kb[n + t], zd, zi);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
   }
@@ -534,8 +557,9 @@ hipError_t launch_fold_inv(const FoldConsts& C, const FoldInv& a, int64_t items,
   return hipGetLastError();
 }
 
-hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const uint64_t* dig, const double* keys, int64_t kstride,
-                              const int32_t* kidx, uint64_t* acc, int64_t* accp, int64_t items, hipStream_t s) {
+hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const FoldInv& dg, const uint64_t* dig, const double* keys,
+                              int64_t kstride, const int32_t* kidx, uint64_t* acc, int64_t* accp, int64_t items,
+                              hipStream_t s) {
   if (items <= 0) return hipSuccess;
   const size_t lds = sizeof(double) << C.logn;
   return by_regs(regs_per_thread(C.logn), [&](auto rc) -> hipError_t {
@@ -543,7 +567,7 @@ hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const uint64_t* di
     hipError_t e = allow_lds(k_fold_ks_mac<R>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fold_ks_mac<R>, dim3((unsigned)(items * (level + 2))), dim3(ntt_block(C.logn)), lds, s, C,
-                       level, dig, keys, kstride, kidx, acc, accp);
+                       level, dg, dig, keys, kstride, kidx, acc, accp);
     return hipGetLastError();
   });
 }
