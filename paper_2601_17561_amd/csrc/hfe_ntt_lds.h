@@ -17,6 +17,35 @@ constexpr int kNttThreads = 1024;
 __device__ __forceinline__ double to_d(uint64_t x) { return (double)x; }    // exact below 2^53
 __device__ __forceinline__ uint64_t to_u(double x) { return (uint64_t)x; }  // x an integer in [0, q)
 
+// The transforms address the array through an accessor A: a plain double* (natural layout) or SwLds,
+// the same N values with each aligned row of 32 permuted (index i at i ^ h(i >> 5)).  A round whose stride
+// is below 32 has the 64 lanes of a wavefront read 2^S values each at addresses 2t or 8 apart, which in
+// the natural layout fall into 4 to 8 of the LDS banks; h spreads the rows over the banks so that every
+// round of a transform of degree 2^14 reads and writes whole bank rows (in both halves of a wavefront for
+// 32 banks, and for 64), and no round of smaller degrees meets more than two-way conflicts.  Kernels that
+// use SwLds address the array through it everywhere, so the permutation is invisible to them.
+// h is linear over GF(2), so the place of i ^ j for indices with disjoint bits is the XOR of their places:
+// a round computes the place of its group's base once and reaches the other 2^S - 1 values with one XOR
+// by a constant of the round (lds_place of k stride).
+struct SwLds {
+  double* p;
+  __device__ __forceinline__ static int h(int r) {
+    return (r & 7) | ((((r >> 3) ^ r) & 1) << 3) | (((r >> 1) & 1) << 4);
+  }
+  __device__ __forceinline__ double& operator[](int i) const { return p[i ^ h(i >> 5)]; }
+};
+
+// The byte offset of logical index i in the array (its place times 8) and the value at a byte offset, for
+// both accessors; XORs of places are XORs of their byte offsets.
+__device__ __forceinline__ uint32_t lds_place(const double*, int i) { return (uint32_t)i << 3; }
+__device__ __forceinline__ uint32_t lds_place(const SwLds&, int i) { return (uint32_t)(i ^ SwLds::h(i >> 5)) << 3; }
+__device__ __forceinline__ double& lds_at(double* a, uint32_t b) {
+  return *reinterpret_cast<double*>(reinterpret_cast<char*>(a) + b);
+}
+__device__ __forceinline__ double& lds_at(const SwLds& a, uint32_t b) {
+  return *reinterpret_cast<double*>(reinterpret_cast<char*>(a.p) + b);
+}
+
 // Both transforms run in rounds of up to three butterfly stages: a thread loads a group of 2^S
 // coefficients into registers, applies S stages there and stores them back, so a transform of
 // degree 2^logn takes ceil(logn / 3) LDS passes and barriers instead of logn.
@@ -37,7 +66,7 @@ __device__ __forceinline__ void fwd_stages(double* x, const NttTab& T, int m1, i
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       if (k & h) continue;
-      const int w = (m1 << s) + (B << s) + (k >> (S - s));
+      const uint32_t w = (uint32_t)((m1 << s) + (B << s) + (k >> (S - s)));
       const double U = x[k];
       const double V = mulmod_d(x[k + h], T.psi_d[w], q, qinv);
       x[k] = addmod_d(U, V, q);
@@ -56,42 +85,50 @@ __device__ __forceinline__ void fwd_stages_c(double* x, const NttTab& T, int m1,
 #pragma unroll
     for (int k = 0; k < G; ++k) {
       if (k & h) continue;
-      const int w = (m1 << s) + (B << s) + (k >> (S - s));
+      const uint32_t w = (uint32_t)((m1 << s) + (B << s) + (k >> (S - s)));
       ct_butterfly_c(x[k], x[k + h], T.psi_d[w], T.qd, T.qinv);
     }
   }
 }
 
-template <int S>
-__device__ __forceinline__ void fwd_round_c(double* a, const NttTab& T, int n, int t) {
+template <int S, class A>
+__device__ __forceinline__ void fwd_round_c(A a, const NttTab& T, int n, int t) {
   constexpr int G = 1 << S;
-  const int stride = t >> (S - 1), m1 = n / (2 * t);
+  const int ls = __builtin_ctz((unsigned)t) - (S - 1);  // stride = 2^ls (t, n powers of two)
+  const int stride = 1 << ls, m1 = n / (2 * t);
+  uint32_t off[G];  // byte offsets of k stride (bits disjoint from any base)
+#pragma unroll
+  for (int k = 0; k < G; ++k) off[k] = lds_place(a, k << ls);
   for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
-    const int B = g / stride, r = g - B * stride;
-    const int base = B * 2 * t + r;
+    const int B = g >> ls, r = g & (stride - 1);
+    const uint32_t p0 = lds_place(a, (B << (ls + S)) + r);  // base = B 2t + r
     double x[G];
 #pragma unroll
-    for (int k = 0; k < G; ++k) x[k] = a[base + k * stride];
+    for (int k = 0; k < G; ++k) x[k] = lds_at(a, p0 ^ off[k]);
     fwd_stages_c<S>(x, T, m1, B);
 #pragma unroll
-    for (int k = 0; k < G; ++k) a[base + k * stride] = x[k];
+    for (int k = 0; k < G; ++k) lds_at(a, p0 ^ off[k]) = x[k];
   }
   __syncthreads();
 }
 
-template <int S>
-__device__ __forceinline__ void fwd_round(double* a, const NttTab& T, int n, int t) {
+template <int S, class A>
+__device__ __forceinline__ void fwd_round(A a, const NttTab& T, int n, int t) {
   constexpr int G = 1 << S;
-  const int stride = t >> (S - 1), m1 = n / (2 * t);
+  const int ls = __builtin_ctz((unsigned)t) - (S - 1);  // stride = 2^ls (t, n powers of two)
+  const int stride = 1 << ls, m1 = n / (2 * t);
+  uint32_t off[G];  // byte offsets of k stride (bits disjoint from any base)
+#pragma unroll
+  for (int k = 0; k < G; ++k) off[k] = lds_place(a, k << ls);
   for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
-    const int B = g / stride, r = g - B * stride;
-    const int base = B * 2 * t + r;
+    const int B = g >> ls, r = g & (stride - 1);
+    const uint32_t p0 = lds_place(a, (B << (ls + S)) + r);  // base = B 2t + r
     double x[G];
 #pragma unroll
-    for (int k = 0; k < G; ++k) x[k] = a[base + k * stride];
+    for (int k = 0; k < G; ++k) x[k] = lds_at(a, p0 ^ off[k]);
     fwd_stages<S>(x, T, m1, B);
 #pragma unroll
-    for (int k = 0; k < G; ++k) a[base + k * stride] = x[k];
+    for (int k = 0; k < G; ++k) lds_at(a, p0 ^ off[k]) = x[k];
   }
   __syncthreads();
 }
@@ -100,16 +137,20 @@ __device__ __forceinline__ void fwd_round(double* a, const NttTab& T, int n, int
 // base = B 2^S t + r (B = g / t, r = g mod t).  Stage s (half-size 2^s t, m = n / (2^(s+1) t)
 // blocks) pairs k and k + 2^s; the pair lies in block B 2^(S-1-s) + (k >> (s + 1)), twiddle
 // ipsi[m + block].  With scale, the round ends with the 1/n factor.
-template <int S>
-__device__ __forceinline__ void inv_round(double* a, const NttTab& T, int n, int t, bool scale) {
+template <int S, class A>
+__device__ __forceinline__ void inv_round(A a, const NttTab& T, int n, int t, bool scale) {
   constexpr int G = 1 << S;
   const double q = T.qd, qinv = T.qinv;
+  const int lt = __builtin_ctz((unsigned)t);
+  uint32_t off[G];  // byte offsets of k t (bits disjoint from any base)
+#pragma unroll
+  for (int k = 0; k < G; ++k) off[k] = lds_place(a, k << lt);
   for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
-    const int B = g / t, r = g - B * t;
-    const int base = B * G * t + r;
+    const int B = g >> lt, r = g & (t - 1);
+    const uint32_t p0 = lds_place(a, (B << (lt + S)) + r);  // base = B 2^S t + r
     double x[G];
 #pragma unroll
-    for (int k = 0; k < G; ++k) x[k] = a[base + k * t];
+    for (int k = 0; k < G; ++k) x[k] = lds_at(a, p0 ^ off[k]);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int h = 1 << s;
@@ -117,7 +158,7 @@ __device__ __forceinline__ void inv_round(double* a, const NttTab& T, int n, int
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         if (k & h) continue;
-        const int w = m + (B << (S - 1 - s)) + (k >> (s + 1));
+        const uint32_t w = (uint32_t)(m + (B << (S - 1 - s)) + (k >> (s + 1)));
         const double U = x[k], V = x[k + h];
         x[k] = addmod_d(U, V, q);
         x[k + h] = mulmod_d(submod_d(U, V, q), T.ipsi_d[w], q, qinv);
@@ -128,7 +169,7 @@ __device__ __forceinline__ void inv_round(double* a, const NttTab& T, int n, int
       for (int k = 0; k < G; ++k) x[k] = mulmod_d(x[k], T.n_inv_d, q, qinv);
     }
 #pragma unroll
-    for (int k = 0; k < G; ++k) a[base + k * t] = x[k];
+    for (int k = 0; k < G; ++k) lds_at(a, p0 ^ off[k]) = x[k];
   }
   __syncthreads();
 }
@@ -137,16 +178,20 @@ __device__ __forceinline__ void inv_round(double* a, const NttTab& T, int n, int
 // magnitude) to centered representatives (reduce_c_d, at most (1/2 + 2^-11) q), so that its S <= 3
 // Gentleman-Sande stages (X + Y, and (X - Y) W centered) keep every value below 4.01q and every
 // product operand below 8.02q; the last round scales by 1/n and returns residues in [0, q).
-template <int S>
-__device__ __forceinline__ void inv_round_c(double* a, const NttTab& T, int n, int t, bool last) {
+template <int S, class A>
+__device__ __forceinline__ void inv_round_c(A a, const NttTab& T, int n, int t, bool last) {
   constexpr int G = 1 << S;
   const double q = T.qd, qinv = T.qinv;
+  const int lt = __builtin_ctz((unsigned)t);
+  uint32_t off[G];  // byte offsets of k t (bits disjoint from any base)
+#pragma unroll
+  for (int k = 0; k < G; ++k) off[k] = lds_place(a, k << lt);
   for (int g = threadIdx.x; g < (n >> S); g += blockDim.x) {
-    const int B = g / t, r = g - B * t;
-    const int base = B * G * t + r;
+    const int B = g >> lt, r = g & (t - 1);
+    const uint32_t p0 = lds_place(a, (B << (lt + S)) + r);  // base = B 2^S t + r
     double x[G];
 #pragma unroll
-    for (int k = 0; k < G; ++k) x[k] = reduce_c_d(a[base + k * t], q, qinv);
+    for (int k = 0; k < G; ++k) x[k] = reduce_c_d(lds_at(a, p0 ^ off[k]), q, qinv);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int h = 1 << s;
@@ -154,7 +199,7 @@ __device__ __forceinline__ void inv_round_c(double* a, const NttTab& T, int n, i
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         if (k & h) continue;
-        const int w = m + (B << (S - 1 - s)) + (k >> (s + 1));
+        const uint32_t w = (uint32_t)(m + (B << (S - 1 - s)) + (k >> (s + 1)));
         const double U = x[k], V = x[k + h];
         x[k] = U + V;
         x[k + h] = mulmod_c_d(U - V, T.ipsi_d[w], q, qinv);
@@ -165,13 +210,14 @@ __device__ __forceinline__ void inv_round_c(double* a, const NttTab& T, int n, i
       for (int k = 0; k < G; ++k) x[k] = residue_of_c(mulmod_c_d(x[k], T.n_inv_d, q, qinv), q);
     }
 #pragma unroll
-    for (int k = 0; k < G; ++k) a[base + k * t] = x[k];
+    for (int k = 0; k < G; ++k) lds_at(a, p0 ^ off[k]) = x[k];
   }
   __syncthreads();
 }
 
 // Forward negacyclic NTT in place (output in bit-reversed order).
-__device__ __forceinline__ void ntt_fwd_lds(double* a, const NttTab& T) {
+template <class A>
+__device__ __forceinline__ void ntt_fwd_lds(A a, const NttTab& T) {
   const int n = 1 << T.logn;
   int t = n >> 1, left = T.logn;
   while (left > 0) {
@@ -193,7 +239,8 @@ __device__ __forceinline__ void ntt_fwd_lds(double* a, const NttTab& T) {
 
 // The same transform on signed values without corrections (fwd_round_c): inputs in [0, q) give
 // outputs congruent to the exact ones, below 8.1q in magnitude for degrees up to 2^14.
-__device__ __forceinline__ void ntt_fwd_lds_c(double* a, const NttTab& T) {
+template <class A>
+__device__ __forceinline__ void ntt_fwd_lds_c(A a, const NttTab& T) {
   const int n = 1 << T.logn;
   int t = n >> 1, left = T.logn;
   while (left > 0) {
@@ -215,7 +262,8 @@ __device__ __forceinline__ void ntt_fwd_lds_c(double* a, const NttTab& T) {
 
 // The inverse on signed inputs (any integers below 2^47 in magnitude) through inv_round_c; outputs in
 // [0, q), the same residues as ntt_inv_lds of the inputs' residues.
-__device__ __forceinline__ void ntt_inv_lds_c(double* a, const NttTab& T) {
+template <class A>
+__device__ __forceinline__ void ntt_inv_lds_c(A a, const NttTab& T) {
   const int n = 1 << T.logn;
   int t = 1, left = T.logn;
   while (left > 0) {
@@ -236,7 +284,8 @@ __device__ __forceinline__ void ntt_inv_lds_c(double* a, const NttTab& T) {
 }
 
 // Inverse negacyclic NTT in place (input in bit-reversed order), including the 1/n factor.
-__device__ __forceinline__ void ntt_inv_lds(double* a, const NttTab& T) {
+template <class A>
+__device__ __forceinline__ void ntt_inv_lds(A a, const NttTab& T) {
   const int n = 1 << T.logn;
   int t = 1, left = T.logn;
   while (left > 0) {
@@ -299,6 +348,27 @@ __device__ __forceinline__ void ntt_fwd_fused(double* lds, const NttTab& T, Load
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[j][k] = lds[8 * g + k];
     fwd_stages_c<3>(x[j], T, n >> 3, g);
+  }
+}
+
+// A pass over the n values of a workgroup's polynomial (thread t takes t, t + blockDim, ...) in chunks of
+// CH per thread: the chunk's global loads (ld(i) returns what index i needs) are all issued before the first
+// is used (st(i, loaded)), so that a thread waits for memory once per chunk rather than once per value.
+template <int CH, class Ld, class St>
+__device__ __forceinline__ void staged_pass(int n, Ld ld, St st) {
+  using V = decltype(ld(0));
+  for (int t0 = threadIdx.x; t0 < n; t0 += CH * blockDim.x) {
+    V v[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int t = t0 + j * blockDim.x;
+      if (t < n) v[j] = ld(t);
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int t = t0 + j * blockDim.x;
+      if (t < n) st(t, v[j]);
+    }
   }
 }
 

@@ -88,14 +88,15 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_encode(const int64_t* w, i
 // dst[item * di + s * ds + t].
 __global__ void __launch_bounds__(kNttThreads) k_fold_fwd(FoldConsts C, const int64_t* src, int64_t si, int64_t ss,
                                                         uint64_t* dst, int64_t di, int64_t ds, SlotMap zm, int nsl) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  const SwLds lds{lds_raw};
   const int n = 1 << C.logn;
   const int64_t item = blockIdx.x / nsl;
   const int s = blockIdx.x - (int)(item * nsl);
   const int z = zm.z[s];
   const Mod md = C.mod[z];
   const int64_t* x = src + item * si + s * ss;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(x[t], md.q, md.mu));
+  staged_pass<4>(n, [&](int t) { return x[t]; }, [&](int t, int64_t v) { lds[t] = to_d(from_signed(v, md.q, md.mu)); });
   __syncthreads();
   ntt_fwd_lds_c(lds, C.tab[z]);
   uint64_t* y = dst + item * di + s * ds;
@@ -107,7 +108,8 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_fwd(FoldConsts C, const in
 // y is given, times pre[s] when has_pre); mode 0: residues (uint64), 1: centered (int64), 2: residues times
 // factor[s] mod z_s (the digits of a key switch).
 __global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, FoldInv a) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  const SwLds lds{lds_raw};
   const int n = 1 << C.logn;
   const int64_t item = blockIdx.x / a.nsl;
   const int s = blockIdx.x - (int)(item * a.nsl);
@@ -116,12 +118,16 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, FoldInv 
   const uint64_t* x = a.src + off;
   if (a.y) {
     const uint64_t* y = a.y + off;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = mm_d(to_d(x[t]), to_d(y[t]), z, C);
+    struct Two {
+      uint64_t x, y;
+    };
+    staged_pass<4>(n, [&](int t) { return Two{x[t], y[t]}; },
+                   [&](int t, const Two& v) { lds[t] = mm_d(to_d(v.x), to_d(v.y), z, C); });
   } else if (a.has_pre) {
     const double f = a.pre.v[s];
-    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = mm_d(to_d(x[t]), f, z, C);
+    staged_pass<4>(n, [&](int t) { return x[t]; }, [&](int t, uint64_t v) { lds[t] = mm_d(to_d(v), f, z, C); });
   } else {
-    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(x[t]);
+    staged_pass<4>(n, [&](int t) { return x[t]; }, [&](int t, uint64_t v) { lds[t] = to_d(v); });
   }
   __syncthreads();
   ntt_inv_lds_c(lds, C.tab[z]);
@@ -150,7 +156,8 @@ template <int R>
 __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int level, FoldInv dg,
                                                            const uint64_t* dig, const double* keys, int64_t kstride,
                                                            const int32_t* kidx, uint64_t* acc, int64_t* accp) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  const SwLds lds{lds_raw};
   const int n = 1 << C.logn;
   const int nsl = level + 2;
   const int64_t items = gridDim.x / nsl;
@@ -172,15 +179,18 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
       const uint64_t* x = dg.src + off;
       const uint64_t* y = dg.y ? dg.y + off : nullptr;
       const double f = dg.f.v[i];
-      for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        double v = to_d(x[t]);
-        if (y) v = mm_d(v, to_d(y[t]), z, C);
+      struct Two {
+        uint64_t x, y;
+      };
+      staged_pass<4>(n, [&](int t) { return Two{x[t], y ? y[t] : 0}; }, [&](int t, const Two& u) {
+        double v = to_d(u.x);
+        if (y) v = mm_d(v, to_d(u.y), z, C);
         lds[t] = mm_d(v, f, z, C);
-      }
+      });
       __syncthreads();
     } else {
       const uint64_t* d = dig + (item * (level + 1) + i) * n;
-      for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(barrett64(d[t], md.q, md.mu));
+      staged_pass<4>(n, [&](int t) { return d[t]; }, [&](int t, uint64_t v) { lds[t] = to_d(barrett64(v, md.q, md.mu)); });
       __syncthreads();
       ntt_fwd_lds_c(lds, C.tab[z]);
     }
@@ -228,7 +238,8 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
 // Addends: add (part 0 only when ap = 0), add2 (both parts), the tensor terms of tx and ty (part 0: b_x b_y,
 // part 1: a_x b_y + a_y b_x) and the constant cres on part 0.
 __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLift a) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  const SwLds lds{lds_raw};
   const int n = 1 << C.logn;
   const int64_t ip = blockIdx.x / a.nsl;
   const int s = blockIdx.x - (int)(ip * a.nsl);
@@ -240,13 +251,14 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLif
     const uint64_t* u = a.ures + ip * n;
     const int cl = a.cl;
     const uint64_t qc = C.mod[cl].q;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-      const int64_t cv = centered(to_u(mm_d(to_d(u[t]), a.ku, cl, C)), qc);
+    staged_pass<4>(n, [&](int t) { return u[t]; }, [&](int t, uint64_t v) {
+      const int64_t cv = centered(to_u(mm_d(to_d(v), a.ku, cl, C)), qc);
       lds[t] = to_d(from_signed(cv, md.q, md.mu));
-    }
+    });
   } else {
     const int64_t* c = a.cen + ip * n;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) lds[t] = to_d(from_signed(c[t], md.q, md.mu));
+    staged_pass<4>(n, [&](int t) { return c[t]; },
+                   [&](int t, int64_t v) { lds[t] = to_d(from_signed(v, md.q, md.mu)); });
   }
   __syncthreads();
   ntt_fwd_lds_c(lds, C.tab[z]);  // signed, below 8.1z
@@ -259,28 +271,46 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLif
   uint64_t* o = a.out + item * a.oi + part * a.op + so;
   const double zd = C.zd[z], zi = C.zinv[z], w = a.inv.v[s];
   const double km = a.has_xmul ? a.xmul.v[s] : 0.0, kc = part == 0 ? a.cres.v[s] : 0.0;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    double xv = to_d(xx[t]);
-    if (a.has_xmul) xv = mm_d(xv, km, z, C);
-    double v = mulmod_c_d(xv - lds[t], w, zd, zi);  // |x - NTT| < 9.1z: centered product, below 0.51z
-    v = v < 0.0 ? v + zd : v;                        // [0, z)
-    if (aa) v = addmod_d(v, to_d(aa[t]), zd);
-    if (a2) v = addmod_d(v, to_d(a2[t]), zd);
-    if (tx) {
-      const double bx = to_d(tx[t]), by = to_d(ty[t]);
-      double d;
-      if (part == 0) {
-        d = mm_d(bx, by, z, C);
-      } else {
-        const double ax = to_d(tx[a.tp + t]), ay = to_d(ty[a.tp + t]);
-        d = addmod_d(mm_d(ax, by, z, C), mm_d(ay, bx, z, C), zd);
-      }
-      if (a.has_tscale) d = mm_d(d, a.tscale.v[s], z, C);
-      v = addmod_d(v, d, zd);
-    }
-    v = addmod_d(v, kc, zd);
-    o[t] = to_u(v);
-  }
+  struct In {
+    uint64_t x, ad, ad2, bx, by, ax, ay;
+  };
+  staged_pass<4>(
+      n,
+      [&](int t) {
+        In r{xx[t], 0, 0, 0, 0, 0, 0};
+        if (aa) r.ad = aa[t];
+        if (a2) r.ad2 = a2[t];
+        if (tx) {
+          r.bx = tx[t];
+          r.by = ty[t];
+          if (part != 0) {
+            r.ax = tx[a.tp + t];
+            r.ay = ty[a.tp + t];
+          }
+        }
+        return r;
+      },
+      [&](int t, const In& r) {
+        double xv = to_d(r.x);
+        if (a.has_xmul) xv = mm_d(xv, km, z, C);
+        double v = mulmod_c_d(xv - lds[t], w, zd, zi);  // |x - NTT| < 9.1z: centered product, below 0.51z
+        v = v < 0.0 ? v + zd : v;                        // [0, z)
+        if (aa) v = addmod_d(v, to_d(r.ad), zd);
+        if (a2) v = addmod_d(v, to_d(r.ad2), zd);
+        if (tx) {
+          const double bx = to_d(r.bx), by = to_d(r.by);
+          double d;
+          if (part == 0) {
+            d = mm_d(bx, by, z, C);
+          } else {
+            d = addmod_d(mm_d(to_d(r.ax), by, z, C), mm_d(to_d(r.ay), bx, z, C), zd);
+          }
+          if (a.has_tscale) d = mm_d(d, a.tscale.v[s], z, C);
+          v = addmod_d(v, d, zd);
+        }
+        v = addmod_d(v, kc, zd);
+        o[t] = to_u(v);
+      });
 }
 
 // The end of a relinearised product divided by p q_l in one rounding: job = item * 2 + part,
@@ -291,7 +321,8 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_relin_center(FoldConsts C,
                                                                  const int64_t* accp, const uint64_t* tx,
                                                                  const uint64_t* ty, double p_l, double pinv_l,
                                                                  int64_t D, int64_t* cen) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  const SwLds lds{lds_raw};
   const int n = 1 << C.logn;
   const int64_t ip = blockIdx.x;
   const int64_t item = ip >> 1;
@@ -302,29 +333,41 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_relin_center(FoldConsts C,
   const uint64_t* bx = tx + item * 2 * per + (int64_t)l * n;
   const uint64_t* by = ty + item * 2 * per + (int64_t)l * n;
   const double zd = C.zd[l];
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    double d;
-    if (part == 0) {
-      d = mm_d(to_d(bx[t]), to_d(by[t]), l, C);
-    } else {
-      d = addmod_d(mm_d(to_d(bx[per + t]), to_d(by[t]), l, C), mm_d(to_d(by[per + t]), to_d(bx[t]), l, C), zd);
-    }
-    lds[t] = addmod_d(to_d(x[t]), mm_d(d, p_l, l, C), zd);
-  }
+  struct In {
+    uint64_t x, bx, by, ax, ay;
+  };
+  staged_pass<4>(
+      n,
+      [&](int t) {
+        In r{x[t], bx[t], by[t], 0, 0};
+        if (part != 0) {
+          r.ax = bx[per + t];
+          r.ay = by[per + t];
+        }
+        return r;
+      },
+      [&](int t, const In& r) {
+        double d;
+        if (part == 0) {
+          d = mm_d(to_d(r.bx), to_d(r.by), l, C);
+        } else {
+          d = addmod_d(mm_d(to_d(r.ax), to_d(r.by), l, C), mm_d(to_d(r.ay), to_d(r.bx), l, C), zd);
+        }
+        lds[t] = addmod_d(to_d(r.x), mm_d(d, p_l, l, C), zd);
+      });
   __syncthreads();
   ntt_inv_lds_c(lds, C.tab[l]);
   const Mod ml = C.mod[l];
   const int64_t p = (int64_t)C.mod[5].q;
   const int64_t* ap = accp + ip * n;
   int64_t* o = cen + ip * n;
-  for (int t = threadIdx.x; t < n; t += blockDim.x) {
-    const int64_t a = ap[t];
+  staged_pass<4>(n, [&](int t) { return ap[t]; }, [&](int t, int64_t a) {
     const double am = to_d(from_signed(a, ml.q, ml.mu));
     const double u = mm_d(submod_d(lds[t], am, zd), pinv_l, l, C);  // (r - a) p^-1 mod q_l
     int64_t v = a + p * (int64_t)u;                                  // in (-p/2, D): |v| < 2^60
     if (v > D / 2) v -= D;
     o[t] = v;
-  }
+  });
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -450,7 +493,8 @@ __global__ void k_fold_add_errors(FoldConsts C, uint64_t seed, const uint64_t* c
 // errors are already in ct[c][0][z]).
 __global__ void __launch_bounds__(kNttThreads) k_fold_encrypt(FoldConsts C, uint64_t seed, const uint64_t* s_hat,
                                                             uint64_t* ct) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  const SwLds lds{lds_raw};
   const int n = 1 << C.logn;
   const int64_t c = blockIdx.x / 5;
   const int z = (int)(blockIdx.x - c * 5);
