@@ -351,9 +351,26 @@ __device__ __forceinline__ void ntt_fwd_fused(double* lds, const NttTab& T, Load
   }
 }
 
-// A pass over the n values of a workgroup's polynomial (thread t takes t, t + blockDim, ...) in chunks of
-// CH per thread: the chunk's global loads (ld(i) returns what index i needs) are all issued before the first
+// A pass over the n values of a workgroup's polynomial (thread t takes t, t + blockDim, ...; staged_range:
+// the indices lo .. hi - 1 the same way) in chunks of CH per thread: the chunk's global loads (ld(i) returns what index i needs) are all issued before the first
 // is used (st(i, loaded)), so that a thread waits for memory once per chunk rather than once per value.
+template <int CH, class Ld, class St>
+__device__ __forceinline__ void staged_range(int64_t lo, int64_t hi, Ld ld, St st) {
+  using V = decltype(ld(lo));
+  for (int64_t t0 = lo + threadIdx.x; t0 < hi; t0 += CH * (int64_t)blockDim.x) {
+    V v[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int64_t t = t0 + j * (int64_t)blockDim.x;
+      if (t < hi) v[j] = ld(t);
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int64_t t = t0 + j * (int64_t)blockDim.x;
+      if (t < hi) st(t, v[j]);
+    }
+  }
+}
 template <int CH, class Ld, class St>
 __device__ __forceinline__ void staged_pass(int n, Ld ld, St st) {
   using V = decltype(ld(0));

@@ -346,19 +346,23 @@ k_dec_products(const uint64_t* out, int64_t R_out, int64_t row0, int64_t rows, N
   const int j = j0 + (int)blockIdx.y;
   const uint64_t q = M.q;  // the arithmetic modulus (the table's prime, or n^2 of the chain)
   const uint64_t* ocol = out + c * R_out;
-  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = CHAIN ? to_ntt(ocol[v], q, T.q) : to_d(ocol[v]);
+  // loads staged four per thread (all issued before the first is used)
+  staged_pass<4>(n, [&](int v) { return ocol[v]; },
+                 [&](int v, uint64_t x) { lds[v] = CHAIN ? to_ntt(x, q, T.q) : to_d(x); });
   __syncthreads();
   ntt_fwd_lds_c(lds, T);  // signed, uncorrected: below 8.1q
   const uint64_t* w = sdb_hat + (int64_t)j * 2 * n;
-  for (int v = threadIdx.x; v < n; v += blockDim.x) lds[v] = mulmod_c_d(lds[v], to_d(w[v]), T.qd, T.qinv);
+  staged_pass<4>(n, [&](int v) { return w[v]; },
+                 [&](int v, uint64_t x) { lds[v] = mulmod_c_d(lds[v], to_d(x), T.qd, T.qinv); });
   __syncthreads();
   ntt_inv_lds_c(lds, T);  // residues in [0, q)
   int64_t lo = (int64_t)j * n - row0, hi = lo + n;
   if (lo < 0) lo = 0;
   if (hi > rows) hi = rows;
-  for (int64_t r = lo + threadIdx.x; r < hi; r += blockDim.x)
-    y[c * rows + r] = add_mod(ocol[n + r], CHAIN ? from_ntt(lds[row0 + r - (int64_t)j * n], T.q, M)
-                                                 : to_u(lds[row0 + r - (int64_t)j * n]), q);
+  staged_range<4>(lo, hi, [&](int64_t r) { return ocol[n + r]; }, [&](int64_t r, uint64_t b) {
+    y[c * rows + r] = add_mod(b, CHAIN ? from_ntt(lds[row0 + r - (int64_t)j * n], T.q, M)
+                                       : to_u(lds[row0 + r - (int64_t)j * n]), q);
+  });
 }
 
 hipError_t launch_dec_products(const uint64_t* out_prime, int64_t d3, int64_t R_out, int64_t row0,
