@@ -274,6 +274,19 @@ __global__ void k_fs_digits(FsConsts C, const uint64_t* T, int64_t ncols, double
   const double q = C.zd[i], qinv = C.zinv[i], g = C.ghat[i];
   const uint64_t* a = T + ((size_t)i * ncols + col) * 2 * nt;
   double* o = Dg + ((size_t)col * (C.level + 1) + i) * nt;
+  // thread u takes the rho coefficients u rho .. u rho + rho - 1 (contiguous across the wavefront) and writes
+  // part r at r N_Q + u (consecutive u across the wavefront): both sides coalesced
+  if (C.rho == 8) {
+    for (int u = threadIdx.x; u < nq; u += blockDim.x) {
+      const uint64_t* src = a + (int64_t)u * 8;
+      uint64_t x[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) x[r] = src[r];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) o[(int64_t)r * nq + u] = mulmod_d(to_d(x[r]), g, q, qinv);
+    }
+    return;
+  }
   for (int64_t t = threadIdx.x; t < nt; t += blockDim.x) {
     const int64_t u = t / C.rho, r = t - u * C.rho;
     o[r * nq + u] = mulmod_d(to_d(a[t]), g, q, qinv);
