@@ -352,8 +352,10 @@ __device__ __forceinline__ void ntt_fwd_fused(double* lds, const NttTab& T, Load
 }
 
 // A pass over the n values of a workgroup's polynomial (thread t takes t, t + blockDim, ...; staged_range:
-// the indices lo .. hi - 1 the same way) in chunks of CH per thread: the chunk's global loads (ld(i) returns what index i needs) are all issued before the first
-// is used (st(i, loaded)), so that a thread waits for memory once per chunk rather than once per value.
+// the indices lo .. hi - 1 the same way) in chunks of CH per thread: the chunk's global loads (ld(i) returns
+// what index i needs) are all issued before the first is used (st(i, loaded)), so that a thread waits for
+// memory once per chunk rather than once per value.  With one workgroup per CU (a polynomial of 2^14 doubles
+// fills the LDS) no other workgroup hides those waits.
 template <int CH, class Ld, class St>
 __device__ __forceinline__ void staged_range(int64_t lo, int64_t hi, Ld ld, St st) {
   using V = decltype(ld(lo));
