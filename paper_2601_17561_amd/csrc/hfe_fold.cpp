@@ -320,8 +320,9 @@ SlotFactor const_res(const FoldConsts& C, int64_t k, int nsl) {
   return r;
 }
 
-// RS by q_l: x [n][2][l+1][N] -> out [n][2][l][N].
-hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out) {
+// RS by q_l: x [n][2][l+1][N] -> out [n][2][l][N]; with pm ([n][l+1][N], NTT domain), RS by q_l of the
+// plaintext product x pm, the product formed as the two passes load x.
+hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out, const uint64_t* pm = nullptr) {
   DevBuf cen;
   HFE_TRY(cen.alloc((size_t)e.n * 2 * e.N * 8, e.s));
   FoldInv ia;
@@ -332,9 +333,13 @@ hfe_status rescale(const Ev& e, const uint64_t* x, int l, uint64_t* out) {
   ia.mode = 1;
   ia.dst = cen.ptr;
   ia.di = e.N;
+  ia.pm = pm;
+  ia.pmi = (l + 1) * e.N;
   FD_LAUNCH(launch_fold_inv(e.C, ia, e.n * 2, e.s));
   FoldLift la;
   la.cen = cen.as<int64_t>();
+  la.pm = pm;
+  la.pmi = (l + 1) * e.N;
   la.x = x;
   la.xi = 2 * (l + 1) * e.N;
   la.xp = (l + 1) * e.N;
@@ -528,14 +533,11 @@ hfe_status fold_impl(const hfe_foldkeys* F, const hfe_fct* in, const int32_t* co
   m.reset();
   if (ev) FD_LAUNCH(hipEventRecord(ev[1], s));
 
-  // x = RS_{q_4}(ct mu), level 3
-  DevBuf t4, x3;
-  HFE_TRY(t4.alloc((size_t)ct_words(e, 4) * 8, s));
-  FD_LAUNCH(launch_fold_mul_pt(C, in->ct.as<uint64_t>(), mu.as<uint64_t>(), t4.as<uint64_t>(), n, 5, s));
-  mu.reset();
+  // x = RS_{q_4}(ct mu), level 3 (the product formed where the rescale loads it)
+  DevBuf x3;
   HFE_TRY(x3.alloc((size_t)ct_words(e, 3) * 8, s));
-  HFE_TRY(rescale(e, t4.as<uint64_t>(), 4, x3.as<uint64_t>()));
-  t4.reset();
+  HFE_TRY(rescale(e, in->ct.as<uint64_t>(), 4, x3.as<uint64_t>(), mu.as<uint64_t>()));
+  mu.reset();
   if (ev) FD_LAUNCH(hipEventRecord(ev[2], s));
 
   // f(x) = (c0 + c1 x) + x^2 (c2 + c3 x) + x^4 ((c4 + c5 x) + x^2 (c6 + c7 x)) at level 1, scale G: the

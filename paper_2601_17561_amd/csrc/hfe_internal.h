@@ -744,6 +744,8 @@ struct FoldInv {
   SlotMap zm{};
   int nsl = 0, mode = 0;
   SlotFactor f{};
+  const uint64_t* pm = nullptr;          // or src times the plaintext pm[(item >> 1) pmi + z N + t] (item = 2 c + part)
+  int64_t pmi = 0;
 };
 // A lift pass of the fold (k_fold_lift), see k_fold.hip.
 struct FoldLift {
@@ -770,6 +772,8 @@ struct FoldLift {
   SlotMap zm{};
   int nsl = 0;
   SlotFactor inv{};
+  const uint64_t* pm = nullptr;          // x times the plaintext pm[item pmi + z N + t] first (a plaintext product)
+  int64_t pmi = 0;
 };
 
 struct FoldConsts {
@@ -829,8 +833,6 @@ hipError_t launch_fold_ks_mac(const FoldConsts& C, int level, const FoldInv& dg,
 hipError_t launch_fold_lift(const FoldConsts& C, const FoldLift& a, int64_t items, hipStream_t s);
 hipError_t launch_fold_relin_center(const FoldConsts& C, int level, const uint64_t* acc, const int64_t* accp,
                                    const uint64_t* tx, const uint64_t* ty, int64_t items, int64_t* cen, hipStream_t s);
-hipError_t launch_fold_mul_pt(const FoldConsts& C, const uint64_t* ct, const uint64_t* pt, uint64_t* out,
-                              int64_t items, int nsl, hipStream_t s);
 hipError_t launch_fold_perm(const FoldConsts& C, const uint64_t* x, const int32_t* src, const int32_t* amt,
                             const int32_t* perm, uint64_t* out, int64_t items, int nsl, hipStream_t s);
 hipError_t launch_fold_group_sum(const FoldConsts& C, const uint64_t* f, const uint64_t* rotated, const int32_t* beg,

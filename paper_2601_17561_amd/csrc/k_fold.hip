@@ -6,14 +6,15 @@
 // built from a few passes:
 //   k_fold_encode     the slot encoder (plaintext coefficients from integer slot values, hfe_slots.h)
 //   k_fold_fwd        signed coefficients -> NTT-domain residues, for several slots
-//   k_fold_inv        NTT-domain residues (or the product of two, or times a constant) -> coefficients
-//                     (residues, centered, or the digits of a key switch)
+//   k_fold_inv        NTT-domain residues (or the product of two, or with a plaintext, or times a constant)
+//                     -> coefficients (residues, centered, or the digits of a key switch)
 //   k_fold_ks_mac     sum_i NTT(d_i) K_i for one slot: each digit's transform in LDS, the products
 //                     accumulated in registers; the special prime's sum is transformed back and centered
 //   k_fold_lift       (x k - NTT([y]_div)) div^-1 plus addends on every kept slot: RS_div of a product, of a
 //                     constant times a ciphertext (with a mod-drop and an added constant), and the end of a
-//                     key switch (with the tensor terms d0, d1 of a product, or sigma(b) of a rotation)
-//   elementwise       plaintext products, the automorphism of a rotation as a permutation of the NTT points,
+//                     key switch (with the tensor terms d0, d1 of a product, or sigma(b) of a rotation), and of
+//                     a plaintext product (the normalisation, the product formed on load)
+//   elementwise       the automorphism of a rotation as a permutation of the NTT points,
 //                     group sums, key and input draws
 #include "hfe_ntt_lds.h"
 #include "hfe_slots.h"
@@ -104,8 +105,8 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_fwd(FoldConsts C, const in
   for (int t = threadIdx.x; t < n; t += blockDim.x) y[t] = to_u(residue_of_c(reduce_c_d(lds[t], zd, zi), zd));
 }
 
-// job = item * nsl + s: inverse NTT of src[item * si + s * ss] mod z_s (times y at the same place when
-// y is given, times pre[s] when has_pre); mode 0: residues (uint64), 1: centered (int64), 2: residues times
+// job = item * nsl + s: inverse NTT of src[item * si + s * ss] mod z_s (times the plaintext pm at slot z_s
+// when pm is given, times y at the same place when y is given, times pre[s] when has_pre); mode 0: residues (uint64), 1: centered (int64), 2: residues times
 // factor[s] mod z_s (the digits of a key switch).
 __global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, FoldInv a) {
   extern __shared__ double lds_raw[];
@@ -116,7 +117,14 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, FoldInv 
   const int z = a.zm.z[s];
   const int64_t off = item * a.si + s * a.ss;
   const uint64_t* x = a.src + off;
-  if (a.y) {
+  if (a.pm) {  // the plaintext product formed on load
+    const uint64_t* y = a.pm + (item >> 1) * a.pmi + (int64_t)z * n;
+    struct Two {
+      uint64_t x, y;
+    };
+    staged_pass<4>(n, [&](int t) { return Two{x[t], y[t]}; },
+                   [&](int t, const Two& v) { lds[t] = mm_d(to_d(v.x), to_d(v.y), z, C); });
+  } else if (a.y) {
     const uint64_t* y = a.y + off;
     struct Two {
       uint64_t x, y;
@@ -233,7 +241,8 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_ks_mac(FoldConsts C, int l
 }
 
 // job = (item * 2 + part) * nsl + s, slot z = zm.z[s]:
-// out = (x xmul[s] - NTT_z(cen mod z)) inv[s] + addends mod z, with cen = cen[(item * 2 + part) * N + t], or
+// out = (x pm xmul[s] - NTT_z(cen mod z)) inv[s] + addends mod z (pm the plaintext at slot z when given), with
+// cen = cen[(item * 2 + part) * N + t], or
 // cen = the centered k u mod q_cl from the residues u = ures[(item * 2 + part) * N + t] when ures is given.
 // Addends: add (part 0 only when ap = 0), add2 (both parts), the tensor terms of tx and ty (part 0: b_x b_y,
 // part 1: a_x b_y + a_y b_x) and the constant cres on part 0.
@@ -271,13 +280,15 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLif
   uint64_t* o = a.out + item * a.oi + part * a.op + so;
   const double zd = C.zd[z], zi = C.zinv[z], w = a.inv.v[s];
   const double km = a.has_xmul ? a.xmul.v[s] : 0.0, kc = part == 0 ? a.cres.v[s] : 0.0;
+  const uint64_t* pm = a.pm ? a.pm + item * a.pmi + (int64_t)z * n : nullptr;
   struct In {
-    uint64_t x, ad, ad2, bx, by, ax, ay;
+    uint64_t x, pmv, ad, ad2, bx, by, ax, ay;
   };
   staged_pass<4>(
       n,
       [&](int t) {
-        In r{xx[t], 0, 0, 0, 0, 0, 0};
+        In r{xx[t], 0, 0, 0, 0, 0, 0, 0};
+        if (pm) r.pmv = pm[t];
         if (aa) r.ad = aa[t];
         if (a2) r.ad2 = a2[t];
         if (tx) {
@@ -292,6 +303,7 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_lift(FoldConsts C, FoldLif
       },
       [&](int t, const In& r) {
         double xv = to_d(r.x);
+        if (pm) xv = mm_d(xv, to_d(r.pmv), z, C);
         if (a.has_xmul) xv = mm_d(xv, km, z, C);
         double v = mulmod_c_d(xv - lds[t], w, zd, zi);  // |x - NTT| < 9.1z: centered product, below 0.51z
         v = v < 0.0 ? v + zd : v;                        // [0, z)
@@ -371,20 +383,6 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_relin_center(FoldConsts C,
 }
 
 // ------------------------------------------------------------------ elementwise
-// Plaintext product: out[item][part][s] = ct[item][part][s] pt[item][s] (nsl slots q_0 .. q_{nsl-1}).
-__global__ void k_fold_mul_pt(FoldConsts C, const uint64_t* ct, const uint64_t* pt, uint64_t* out, int64_t items,
-                              int nsl) {
-  const int n = 1 << C.logn;
-  const int64_t total = items * 2 * nsl * (int64_t)n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int t = (int)(e & (n - 1));
-    const int64_t r = e >> C.logn;
-    const int s = (int)(r % nsl);
-    const int64_t item = r / (2 * nsl);
-    out[e] = to_u(mm_d(to_d(ct[e]), to_d(pt[(item * nsl + s) * n + t]), s, C));
-  }
-}
-
 // Rotation's automorphism on gathered items with nsl slots: out[u][part][s][t] =
 // x[src[u]][part][s][perm[amt[u]][t]] (the NTT points of every prime are ordered alike).
 __global__ void k_fold_perm(FoldConsts C, const uint64_t* x, const int32_t* src, const int32_t* amt,
@@ -635,14 +633,6 @@ hipError_t launch_fold_relin_center(const FoldConsts& C, int level, const uint64
   const double p_l = (double)(p % ql), pinv_l = (double)inv_mod(p % ql, ql);
   hipLaunchKernelGGL(k_fold_relin_center, dim3((unsigned)(items * 2)), dim3(ntt_block(C.logn)), lds, s, C, level, acc,
                      accp, tx, ty, p_l, pinv_l, (int64_t)(p * ql), cen);
-  return hipGetLastError();
-}
-
-hipError_t launch_fold_mul_pt(const FoldConsts& C, const uint64_t* ct, const uint64_t* pt, uint64_t* out,
-                              int64_t items, int nsl, hipStream_t s) {
-  if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fold_mul_pt, dim3(ew_grid(items * 2 * nsl << C.logn)), dim3(256), 0, s, C, ct, pt, out, items,
-                     nsl);
   return hipGetLastError();
 }
 
