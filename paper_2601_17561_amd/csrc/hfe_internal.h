@@ -737,8 +737,6 @@ struct FoldInv {
   const uint64_t* src = nullptr;
   int64_t si = 0, ss = 0;
   const uint64_t* y = nullptr;
-  int has_pre = 0;
-  SlotFactor pre{};
   void* dst = nullptr;
   int64_t di = 0, ds = 0;
   SlotMap zm{};

@@ -6,7 +6,7 @@
 // built from a few passes:
 //   k_fold_encode     the slot encoder (plaintext coefficients from integer slot values, hfe_slots.h)
 //   k_fold_fwd        signed coefficients -> NTT-domain residues, for several slots
-//   k_fold_inv        NTT-domain residues (or the product of two, or with a plaintext, or times a constant)
+//   k_fold_inv        NTT-domain residues (or the product of two, or with a plaintext)
 //                     -> coefficients (residues, centered, or the digits of a key switch)
 //   k_fold_ks_mac     sum_i NTT(d_i) K_i for one slot: each digit's transform in LDS, the products
 //                     accumulated in registers; the special prime's sum is transformed back and centered
@@ -106,8 +106,8 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_fwd(FoldConsts C, const in
 }
 
 // job = item * nsl + s: inverse NTT of src[item * si + s * ss] mod z_s (times the plaintext pm at slot z_s
-// when pm is given, times y at the same place when y is given, times pre[s] when has_pre); mode 0: residues (uint64), 1: centered (int64), 2: residues times
-// factor[s] mod z_s (the digits of a key switch).
+// when pm is given, times y at the same place when y is given); mode 0: residues (uint64), 1: centered (int64),
+// 2: residues times factor[s] mod z_s (the digits of a key switch).
 __global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, FoldInv a) {
   extern __shared__ double lds_raw[];
   const SwLds lds{lds_raw};
@@ -131,9 +131,6 @@ __global__ void __launch_bounds__(kNttThreads) k_fold_inv(FoldConsts C, FoldInv 
     };
     staged_pass<4>(n, [&](int t) { return Two{x[t], y[t]}; },
                    [&](int t, const Two& v) { lds[t] = mm_d(to_d(v.x), to_d(v.y), z, C); });
-  } else if (a.has_pre) {
-    const double f = a.pre.v[s];
-    staged_pass<4>(n, [&](int t) { return x[t]; }, [&](int t, uint64_t v) { lds[t] = mm_d(to_d(v), f, z, C); });
   } else {
     staged_pass<4>(n, [&](int t) { return x[t]; }, [&](int t, uint64_t v) { lds[t] = to_d(v); });
   }
